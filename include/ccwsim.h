@@ -1,0 +1,185 @@
+/*
+ * ccwsim.h -- C ABI of the CCWSIM hot path on AMD Instinct MI355X (gfx950).
+ *
+ * CCWSIM (Bavandsavadkoohi et al., arXiv 2404.00441) simulates a categorical
+ * grid patch by patch along a raster path.  For every patch it
+ *   1. takes the overlap with already simulated patches as a data event
+ *      (Sec. 4.1, Fig. 3a-c),
+ *   2. compares the data event's Haar approximation with every candidate
+ *      position of the training image's approximation grid through the CCW
+ *      cross-correlation (Sec. 4.3),
+ *   3. keeps the K best candidates and draws one uniformly (Sec. 4.4,
+ *      Algorithm 1),
+ *   4. rebuilds the chosen pattern by inverse DWT from the stored detail
+ *      coefficients (Sec. 3.1, Algorithm 1) and pastes it behind a
+ *      minimal-error boundary cut (image quilting, Sec. 2 and Sec. 4.1).
+ *
+ * Conventions shared by every entry point
+ *   - Extents and coordinates are (x, y, z) with x fastest in memory; a 2D
+ *     problem has ndim = 2 and extent 1 (template 1, overlap 0) on z.
+ *   - Codes are int8 facies indices 0 .. n_facies-1 (n_facies <= 127).
+ *   - The Haar transform is kept in exact integer form: per axis and level
+ *     the low-pass is e + o and the high-pass e - o (e, o = even and odd
+ *     sample; the wavelet is +1 on its first half, Sec. 4.2).  The level-J
+ *     approximation is therefore the integer block sum over 2^J cells per
+ *     axis; orthonormal coefficients are these integers times 2^(-p/2) after
+ *     p filter passes.  Images whose extent is not a multiple of 2^J are
+ *     extended by edge replication first.
+ *   - Unless stated otherwise every pointer is a DEVICE pointer owned by the
+ *     caller; `stream` is a hipStream_t passed as void* (NULL = default
+ *     stream).  Calls are asynchronous on `stream` and return a status; a
+ *     fault inside a kernel shows up at the caller's next synchronisation.
+ *   - Argument errors are reported before anything is launched.  The text of
+ *     the last error on the calling thread is ccwsim_last_error().
+ *   - Calls never abort or throw.  Calls on different streams must not share
+ *     output buffers or workspaces.
+ */
+#ifndef CCWSIM_H
+#define CCWSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CCWSIM_OK 0
+#define CCWSIM_ERR_INVALID_ARG 1 /* null pointer, bad enum, bad count      */
+#define CCWSIM_ERR_SHAPE 2       /* extents / template / overlap invalid   */
+#define CCWSIM_ERR_WORKSPACE 3   /* workspace missing or too small         */
+#define CCWSIM_ERR_HIP 4         /* a HIP runtime call failed              */
+#define CCWSIM_ERR_UNSUPPORTED 5 /* valid input outside what is built      */
+
+const char* ccwsim_status_string(int status);
+/* Text of the last failure on the calling thread ("" if none). */
+const char* ccwsim_last_error(void);
+
+/* ---- shapes and parameters --------------------------------------------- */
+typedef struct {
+  int32_t ndim; /* 2 or 3                                            */
+  int32_t n[3]; /* extent per axis, n[0] = x; n[2] = 1 when ndim = 2  */
+} ccwsim_shape;
+
+/* Problem statement of Algorithm 1 (TI, template size, overlap size, level
+ * J, K, number of realizations) plus the choices the paper leaves open. */
+typedef struct {
+  ccwsim_shape ti;      /* training image extent                          */
+  ccwsim_shape grid;    /* simulation grid extent (per realization)       */
+  int32_t tmpl[3];      /* template T per axis (T > OV >= 1 on used axes) */
+  int32_t overlap[3];   /* overlap OV per axis                            */
+  int32_t level;        /* wavelet decomposition level J, 0 <= J <= 6     */
+  int32_t top_k;        /* K best candidates kept for the draw, >= 1      */
+  int32_t n_real;       /* realizations simulated together, >= 1          */
+  int32_t n_facies;     /* codes are 0 .. n_facies-1, 1 <= n_facies <= 127*/
+  uint64_t seed;        /* every random draw is a function of
+                           (seed, realization, raster step)              */
+  int32_t path_mode;    /* 0: raster from the low corner, x fastest;
+                           1: per realization a seeded start corner (and,
+                           in 2D, which axis is walked fastest)          */
+  int32_t score_mode;   /* 0: squared difference of approximations
+                           (CCW cross term + energy term, smaller = better);
+                           1: negated raw CCW                             */
+  int32_t nc_margin[3]; /* non-causal margin of the virtual template used
+                           for hard data; < 0 means "= overlap"          */
+  int32_t cut;          /* 1: minimal-error boundary cut; 0: plain paste  */
+  int32_t precision;    /* 0: fp16 inputs, fp32 accumulation (exact for
+                           Haar on integer codes within the limits checked
+                           by ccwsim_simulate)                            */
+  int32_t shortlist;    /* reserved, must be 0                            */
+  int32_t reserved[4];  /* must be 0                                      */
+} ccwsim_params;
+
+/* ---- A1: training-image transform (Sec. 3.1; Algorithm 1, DWT of TI) ---
+ * Level-J Haar DWT of x (int8, extent s).  The image is extended by edge
+ * replication to Np = ceil(n / 2^J) * 2^J per used axis.
+ *   approx:  level-J approximation = integer block sums, G = Np / 2^J cells
+ *            per used axis, int32.
+ *   details: for j = 1..J, for sub-band q = 1 .. 2^ndim - 1 (bit a of q set
+ *            when axis a took the high-pass), Np / 2^j cells per used axis,
+ *            int32; levels concatenated in increasing j.
+ * ccwsim_dwt_sizes returns the element counts of both outputs (host call,
+ * no device work).  Returns CCWSIM_ERR_SHAPE for bad extents or J > 6. */
+int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int64_t* n_approx, int64_t* n_details);
+int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t* approx,
+               int32_t* details, void* stream);
+
+/* ---- A3/A4: CCW scan (Sec. 4.3, CCW equation) ------------------------------
+ * Scores every candidate of the TI approximation grid against n_filters
+ * data events.  Candidates are coarse-aligned: candidate c = (cx, cy, cz)
+ * has its fine window at 2^J * c, fully inside the TI, so there are
+ * C_a = (n_a - T_a) / 2^J + 1 candidates per axis, index cx + C_x*(cy + C_y*cz).
+ * A data event is given per level-J block of the template footprint
+ * (T_c = ceil(T / 2^J) blocks per axis, x fastest): or_n = number of known
+ * overlap cells in the block, or_m = sum of their codes (the level-J
+ * approximation of the zero-filled overlap), int32 [n_filters][T_c cells].
+ *   score_mode 0: S = sum n K^2 - 2 |beta| sum m K   (|beta| = 2^(J*ndim))
+ *   score_mode 1: S = - sum m K
+ * with K = approx[c + beta].  scores: int32 [n_filters][C cells].
+ * The library allocates its temporaries with stream-ordered allocation.
+ * Returns CCWSIM_ERR_UNSUPPORTED if the values could leave the range in
+ * which fp16/fp32 MFMA arithmetic is exact (the bound uses max_code, the
+ * largest code in the TI; 0 < max_code <= 126). */
+int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code, const int32_t* approx,
+                    const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
+                    int32_t n_filters, int32_t score_mode, int32_t* scores, void* stream);
+
+/* ---- A6: top-K and draw (Sec. 4.4; Algorithm 1, K best and random draw) ---
+ * For each filter f, candidates are ordered by the key
+ *   (min(mismatch, 4095), S + 2^31, pi(index))
+ * where pi is a keyed bijection of the 20-bit index (ties between equal
+ * scores are broken by a seeded order, not by position).  The K' = min(K,
+ * n_cand) smallest are kept and the j-th is chosen with
+ * j = floor(u * K' / 2^32), u the high 32 bits of the draw for (seed,
+ * realization[f], step[f]).
+ *   scores:   int32 [n_filters][n_cand]
+ *   mismatch: uint16 [n_filters][n_cand] hard-data mismatch counts, or NULL
+ *   realization, step: int32 / int64 [n_filters] (device)
+ *   chosen:   int32 [n_filters] chosen candidate index
+ *   topk_keys: uint64 [n_filters][K'] ascending keys, or NULL
+ * 1 <= top_k <= 16, 1 <= n_cand <= 2^20. */
+int ccwsim_select(const int32_t* scores, const uint16_t* mismatch, int64_t n_cand,
+                  int32_t n_filters, int32_t top_k, uint64_t seed, const int32_t* realization,
+                  const int64_t* step, int32_t* chosen, uint64_t* topk_keys, void* stream);
+
+/* ---- A7: inverse DWT of chosen patterns (Sec. 3.1; Algorithm 1 Inv-DWT) ---
+ * Rebuilds n patterns of extent `patch` (fine cells, <= 64 x 64 x 64 and
+ * <= 16384 cells) whose level-J block origins are block_origins (int32
+ * [n][3], x y z) from the approx/details layout of ccwsim_dwt of a TI of
+ * extent ti.  patches: int8 [n][patch cells].  The block range
+ * [origin, origin + ceil(patch / 2^J)) must lie inside the approximation
+ * grid; a pattern whose origin does not is filled with -1. */
+int ccwsim_idwt(const int32_t* approx, const int32_t* details, ccwsim_shape ti, int32_t level,
+                const int32_t* block_origins, int32_t n, const int32_t patch[3], int8_t* patches,
+                void* stream);
+
+/* ---- whole hot path (Algorithm 1 and the conditioning of Sec. 4.4) --------
+ * Simulates p->n_real realizations of p->grid from the TI (device int8).
+ * Hard data (may be n_hd = 0 and NULL pointers): hd_real int32 [n_hd]
+ * realization index, hd_pos int32 [n_hd][3] grid coordinates (x, y, z),
+ * hd_val int8 [n_hd] code.  Hard-data cells are never overwritten; entries
+ * outside the grid or with a realization outside [0, n_real) are ignored;
+ * positions must be distinct within a realization.
+ *   out:    int8 [n_real][grid cells]
+ *   chosen: int32 [n_real][lattice patches] chosen candidate per raster
+ *           step, or NULL
+ *   workspace: device memory of at least ccwsim_simulate_workspace_size(p)
+ *           bytes, 256-byte aligned, owned by the caller; its contents on
+ *           entry do not matter.
+ * The result does not depend on how patches are scheduled: patches whose
+ * windows do not overlap run concurrently (anti-diagonal wavefronts when
+ * T >= 2 OV on every axis), and every draw is keyed by the raster step. */
+int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p);
+int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
+                    const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
+                    void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Releases host-side caches (simulation plans).  Not thread-safe with
+ * concurrent ccwsim_simulate calls. */
+void ccwsim_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCWSIM_H */

@@ -455,6 +455,56 @@ int orc_mincut(const int64_t *e, int32_t rows, int32_t cols, int32_t *seam)
 }
 
 /* ------------------------------------------------------------------------ */
+/* K best candidates and the uniform draw among them (Sec. 4.4, Algorithm 1).*/
+/* Candidates are ordered by (hard-data mismatch, score, keyed tie-break);   */
+/* reading for conditioning: the sequential search of Sec. 4.4 over the      */
+/* sorted scores takes the best candidate that honours the data, which is    */
+/* the lexicographic order with the mismatch first.  The mismatch is capped  */
+/* at 4095.  The K' = min(K, n) best are kept and the j-th is drawn with      */
+/* j = floor(u * K' / 2^32), u the high half of the DRAW stream for          */
+/* (seed, r, step).  mis may be NULL (no hard data).  topkeys, if not NULL,  */
+/* receives the K' keys (mismatch << 52 | (S + 2^31) << 20 | tie-break) in   */
+/* ascending order.                                                          */
+/* ------------------------------------------------------------------------ */
+int orc_select(const int64_t *S, const int64_t *mis, int64_t ncand, int32_t k, uint64_t seed,
+               int64_t r, int64_t step, int64_t *chosen, uint64_t *topkeys)
+{
+    if (ncand < 1 || ncand > (1 << 20) || k < 1) return ORC_ERR_ARG;
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * ncand);
+    if (!keys) return ORC_ERR_NOMEM;
+    uint64_t tkey = orc_rng(seed, ORC_STREAM_TIEBREAK, (uint64_t)r, (uint64_t)step);
+    for (int64_t c = 0; c < ncand; c++) {
+        int64_t m = mis ? (mis[c] > 4095 ? 4095 : mis[c]) : 0;
+        int64_t s = S[c] + 2147483648LL;
+        if (s < 0 || s > 0xFFFFFFFFLL) {
+            free(keys);
+            return ORC_ERR_RANGE;
+        }
+        keys[c] = ((uint64_t)m << 52) | ((uint64_t)s << 20) | (uint64_t)orc_perm20((uint32_t)c, tkey);
+    }
+    /* the K' best, by repeated minimum (plain selection) */
+    int64_t kk = k < ncand ? k : ncand;
+    uint64_t u32 = orc_rng(seed, ORC_STREAM_DRAW, (uint64_t)r, (uint64_t)step) >> 32;
+    int64_t j = (int64_t)((u32 * (uint64_t)kk) >> 32);
+    int64_t pick = -1;
+    uint64_t prev = 0;
+    for (int64_t rank = 0; rank < kk; rank++) {
+        int64_t best = -1;
+        for (int64_t c = 0; c < ncand; c++) {
+            if (rank > 0 && keys[c] <= prev) continue;
+            if (best < 0 || keys[c] < keys[best]) best = c;
+        }
+        prev = keys[best];
+        if (topkeys) topkeys[rank] = prev;
+        if (rank == j) pick = best;
+        if (!topkeys && rank == j) break;
+    }
+    *chosen = pick;
+    free(keys);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole simulation (Algorithm 1, with the conditioning of Sec. 4.4).        */
 /* ------------------------------------------------------------------------ */
 
@@ -578,14 +628,13 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
     int64_t *mb = (int64_t *)malloc(sizeof(int64_t) * tcells);
     int64_t *S = (int64_t *)malloc(sizeof(int64_t) * g.ncand);
     int64_t *mis = (int64_t *)malloc(sizeof(int64_t) * g.ncand);
-    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * g.ncand);
     int64_t *rec = (int64_t *)malloc(sizeof(int64_t) * rcells[0] * rcells[1] * rcells[2]);
     int8_t *patch = (int8_t *)malloc(wcells);
     uint8_t *inband = (uint8_t *)malloc(wcells);
     uint8_t *keep_old = (uint8_t *)malloc(wcells);
     int8_t *sg = (int8_t *)malloc(pcells);
     int8_t *hdmap = (int8_t *)malloc(pcells);
-    if (!nb || !mb || !S || !mis || !keys || !rec || !patch || !inband || !keep_old || !sg || !hdmap)
+    if (!nb || !mb || !S || !mis || !rec || !patch || !inband || !keep_old || !sg || !hdmap)
         return ORC_ERR_NOMEM;
 
     for (int r = 0; r < p->n_real; r++) {
@@ -691,30 +740,10 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
                         }
             }
 
-            /* total order: (mismatch, score, keyed tie-break) */
-            uint64_t tkey = orc_rng(p->seed, ORC_STREAM_TIEBREAK, (uint64_t)r, (uint64_t)step);
-            for (int64_t c = 0; c < g.ncand; c++) {
-                int64_t m = mis[c] > 4095 ? 4095 : mis[c];
-                int64_t s = S[c] + 2147483648LL;
-                if (s < 0 || s > 0xFFFFFFFFLL) return ORC_ERR_RANGE;
-                keys[c] = ((uint64_t)m << 52) | ((uint64_t)s << 20) |
-                          (uint64_t)orc_perm20((uint32_t)c, tkey);
-            }
-            /* the K best candidates, by repeated minimum (plain selection) */
-            int64_t kk = p->top_k < g.ncand ? p->top_k : g.ncand;
-            uint64_t u32 = orc_rng(p->seed, ORC_STREAM_DRAW, (uint64_t)r, (uint64_t)step) >> 32;
-            int64_t j = (int64_t)((u32 * (uint64_t)kk) >> 32);
+            /* K best and the draw */
             int64_t pick = -1;
-            uint64_t prev = 0;
-            for (int64_t rank = 0; rank <= j; rank++) {
-                int64_t best = -1;
-                for (int64_t c = 0; c < g.ncand; c++) {
-                    if (rank > 0 && keys[c] <= prev) continue;
-                    if (best < 0 || keys[c] < keys[best]) best = c;
-                }
-                prev = keys[best];
-                pick = best;
-            }
+            st = orc_select(S, mis, g.ncand, p->top_k, p->seed, r, step, &pick, NULL);
+            if (st) return st;
             if (chosen) chosen[(int64_t)r * nsteps + step] = (int32_t)pick;
 
             /* reconstruct the chosen pattern from the coefficient pyramid */
@@ -800,7 +829,6 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
     free(mb);
     free(S);
     free(mis);
-    free(keys);
     free(rec);
     free(patch);
     free(inband);

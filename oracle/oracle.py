@@ -58,6 +58,8 @@ def lib():
         L.orc_idwt_region.argtypes = [p, p, p, i32, i32, p, p, p]
         L.orc_scores.restype = ctypes.c_int
         L.orc_scores.argtypes = [p, p, p, p, i64, p, p, i32, p]
+        L.orc_select.restype = ctypes.c_int
+        L.orc_select.argtypes = [p, p, i64, i32, u64, i64, i64, p, p]
         L.orc_mincut.restype = ctypes.c_int
         L.orc_mincut.argtypes = [p, i32, i32, p]
         L.orc_geometry.restype = ctypes.c_int
@@ -223,6 +225,19 @@ def scores(K: np.ndarray, cand_xyz, nb: np.ndarray, mb: np.ndarray, beta_cells: 
     _check(lib().orc_scores(_ptr(K), _ptr(G), _ptr(cand), _ptr(tc), beta_cells, _ptr(nb), _ptr(mb),
                             mode, _ptr(S)), "scores")
     return S.reshape(tuple(int(c) for c in cand[: K.ndim][::-1]))
+
+
+def select(S: np.ndarray, mis, k: int, seed: int, r: int, step: int):
+    """K best keys and the drawn candidate.  Returns (chosen, keys[K'])."""
+    S = np.ascontiguousarray(S, dtype=np.int64).ravel()
+    m = None if mis is None else np.ascontiguousarray(mis, dtype=np.int64).ravel()
+    n = S.size
+    kk = min(k, n)
+    keys = np.zeros(kk, dtype=np.uint64)
+    chosen = ctypes.c_int64()
+    _check(lib().orc_select(_ptr(S), _ptr(m) if m is not None else None, n, k, seed, r, step,
+                            ctypes.byref(chosen), _ptr(keys)), "select")
+    return int(chosen.value), keys
 
 
 def mincut(e: np.ndarray) -> np.ndarray:

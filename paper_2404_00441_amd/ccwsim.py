@@ -1,0 +1,256 @@
+"""Python binding of the CCWSIM C ABI (``include/ccwsim.h``).
+
+Argument marshalling only: every function takes torch tensors that live on
+the GPU, passes their device pointers and the current HIP stream to
+``libccwsim.so`` and raises if the call reports an error.  All computation
+happens in the library's HIP kernels; there is no fallback of any kind --
+without the built library, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccwsim.so")
+
+CCWSIM_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "workspace", 4: "HIP error",
+          5: "unsupported"}
+
+
+class CcwsimError(RuntimeError):
+    def __init__(self, fn, status, text):
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)}: {text}")
+        self.status = status
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("ti", Shape), ("grid", Shape),
+        ("tmpl", ctypes.c_int32 * 3), ("overlap", ctypes.c_int32 * 3),
+        ("level", ctypes.c_int32), ("top_k", ctypes.c_int32), ("n_real", ctypes.c_int32),
+        ("n_facies", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("path_mode", ctypes.c_int32), ("score_mode", ctypes.c_int32),
+        ("nc_margin", ctypes.c_int32 * 3), ("cut", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("shortlist", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load ``libccwsim.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2404_00441_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    L.ccwsim_status_string.restype = ctypes.c_char_p
+    L.ccwsim_status_string.argtypes = [ctypes.c_int]
+    L.ccwsim_last_error.restype = ctypes.c_char_p
+    L.ccwsim_last_error.argtypes = []
+    L.ccwsim_dwt_sizes.restype = ctypes.c_int
+    L.ccwsim_dwt_sizes.argtypes = [Shape, i32, p, p]
+    L.ccwsim_dwt.restype = ctypes.c_int
+    L.ccwsim_dwt.argtypes = [p, Shape, i32, p, p, p]
+    L.ccwsim_ccf_scan.restype = ctypes.c_int
+    L.ccwsim_ccf_scan.argtypes = [Shape, i32, i32, p, p, p, p, i32, i32, p, p]
+    L.ccwsim_select.restype = ctypes.c_int
+    L.ccwsim_select.argtypes = [p, p, i64, i32, i32, u64, p, p, p, p, p]
+    L.ccwsim_idwt.restype = ctypes.c_int
+    L.ccwsim_idwt.argtypes = [p, p, Shape, i32, p, i32, p, p, p]
+    L.ccwsim_simulate_workspace_size.restype = i64
+    L.ccwsim_simulate_workspace_size.argtypes = [p]
+    L.ccwsim_simulate.restype = ctypes.c_int
+    L.ccwsim_simulate.argtypes = [p, p, i64, p, p, p, p, p, p, i64, p]
+    L.ccwsim_release_caches.restype = None
+    L.ccwsim_release_caches.argtypes = []
+    _lib = L
+    return L
+
+
+EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
+           "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
+           "ccwsim_simulate", "ccwsim_release_caches")
+
+
+def _check(fn, status):
+    if status != CCWSIM_OK:
+        raise CcwsimError(fn, status, load().ccwsim_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def shape_of(extent) -> Shape:
+    """Shape from an (x, y[, z]) extent."""
+    n = list(extent) + [1] * (3 - len(extent))
+    return Shape(len(extent), (ctypes.c_int32 * 3)(*n))
+
+
+def _i3(v, fill):
+    v = list(v) + [fill] * (3 - len(v))
+    return (ctypes.c_int32 * 3)(*v)
+
+
+def params_of(p: dict) -> Params:
+    """Params from a workload dict (extents (x, y[, z]))."""
+    q = Params()
+    q.ti = shape_of(p["ti"])
+    q.grid = shape_of(p["grid"])
+    nd = len(p["ti"])
+    q.tmpl = _i3(p["tmpl"], 1)
+    q.overlap = _i3(p["overlap"], 0)
+    q.level = p["level"]
+    q.top_k = p["top_k"]
+    q.n_real = p.get("n_real", 1)
+    q.n_facies = p.get("n_facies", 2)
+    q.seed = p.get("seed", 1)
+    q.path_mode = p.get("path_mode", 0)
+    q.score_mode = p.get("score_mode", 0)
+    m = list(p.get("nc_margin", (-1, -1, -1)))[:nd] + [-1] * (3 - nd)
+    q.nc_margin = (ctypes.c_int32 * 3)(*m)
+    q.cut = p.get("cut", 1)
+    q.precision = p.get("precision", 0)
+    q.shortlist = 0
+    return q
+
+
+# ---------------------------------------------------------------------------
+def dwt_sizes(extent, level):
+    na, nd = ctypes.c_int64(), ctypes.c_int64()
+    _check("ccwsim_dwt_sizes", load().ccwsim_dwt_sizes(shape_of(extent), level, ctypes.byref(na),
+                                                       ctypes.byref(nd)))
+    return na.value, nd.value
+
+
+def dwt(x: torch.Tensor, level: int):
+    """x: int8 GPU tensor in numpy order ([y][x] or [z][y][x]).
+    Returns (approx int32 [grid], details int32 flat)."""
+    extent = tuple(x.shape[::-1])
+    na, nd = dwt_sizes(extent, level)
+    b = 2 ** level
+    grid = tuple(-(-n // b) for n in x.shape)
+    approx = torch.empty(grid, dtype=torch.int32, device=x.device)
+    details = torch.empty(max(nd, 1), dtype=torch.int32, device=x.device)
+    _check("ccwsim_dwt", load().ccwsim_dwt(_ptr(x), shape_of(extent), level, _ptr(approx), _ptr(details),
+                                           _stream()))
+    return approx, details[:nd]
+
+
+def ccf_scan(ti_extent, level, max_code, approx, tmpl, or_n, or_m, score_mode=0):
+    """or_n, or_m: int32 [n_filters, *T_c numpy order].  Returns int32
+    scores [n_filters, n_cand]."""
+    nf = or_m.shape[0]
+    b = 2 ** level
+    cand = [(ti_extent[a] - tmpl[a]) // b + 1 for a in range(len(ti_extent))]
+    ncand = 1
+    for c in cand:
+        ncand *= c
+    scores = torch.empty((nf, ncand), dtype=torch.int32, device=approx.device)
+    t3 = _i3(tmpl, 1)
+    _check("ccwsim_ccf_scan", load().ccwsim_ccf_scan(shape_of(ti_extent), level, max_code, _ptr(approx), t3,
+                                                     _ptr(or_n) if or_n is not None else None, _ptr(or_m), nf,
+                                                     score_mode, _ptr(scores), _stream()))
+    return scores
+
+
+def select(scores, mismatch, top_k, seed, realization, step, want_keys=False):
+    """scores int32 [F, n]; mismatch uint16-compatible int16 [F, n] or None;
+    realization int32 [F]; step int64 [F].  Returns (chosen int32 [F],
+    keys uint64-as-int64 [F, k'] or None)."""
+    nf, n = scores.shape
+    chosen = torch.empty(nf, dtype=torch.int32, device=scores.device)
+    k = min(top_k, n)
+    keys = torch.empty((nf, k), dtype=torch.int64, device=scores.device) if want_keys else None
+    _check("ccwsim_select", load().ccwsim_select(_ptr(scores), _ptr(mismatch), n, nf, top_k, seed,
+                                                 _ptr(realization), _ptr(step), _ptr(chosen), _ptr(keys),
+                                                 _stream()))
+    return chosen, keys
+
+
+def idwt(approx, details, ti_extent, level, origins, patch):
+    """origins int32 [n, 3] (x, y, z block origins).  Returns int8 patterns
+    [n, *patch numpy order]."""
+    n = origins.shape[0]
+    out = torch.empty((n,) + tuple(patch[::-1]), dtype=torch.int8, device=approx.device)
+    _check("ccwsim_idwt", load().ccwsim_idwt(_ptr(approx), _ptr(details), shape_of(ti_extent), level,
+                                             _ptr(origins), n, _i3(patch, 1), _ptr(out), _stream()))
+    return out
+
+
+def simulate_workspace_size(p: dict) -> int:
+    q = params_of(p)
+    v = load().ccwsim_simulate_workspace_size(ctypes.byref(q))
+    if v < 0:
+        raise CcwsimError("ccwsim_simulate_workspace_size", 1, load().ccwsim_last_error().decode())
+    return int(v)
+
+
+class Simulator:
+    """Holds the workspace for one parameter set and runs ccwsim_simulate."""
+
+    def __init__(self, p: dict, device="cuda"):
+        self.p = dict(p)
+        self.q = params_of(p)
+        self.ws_bytes = simulate_workspace_size(p)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off: off + self.ws_bytes]
+
+    def run(self, ti, hd=None, out=None, chosen=None):
+        """ti: int8 GPU tensor (numpy order).  hd: (real int32 [n], pos int32
+        [n, 3], val int8 [n]) GPU tensors or None.  Returns out int8
+        [n_real, *grid numpy order]."""
+        p = self.p
+        if out is None:
+            out = torch.empty((p["n_real"],) + tuple(p["grid"][::-1]), dtype=torch.int8, device=ti.device)
+        if hd is None:
+            n_hd, hr, hp, hv = 0, None, None, None
+        else:
+            hr, hp, hv = hd
+            n_hd = int(hr.shape[0])
+        _check("ccwsim_simulate", load().ccwsim_simulate(
+            ctypes.byref(self.q), _ptr(ti), n_hd, _ptr(hr) if n_hd else None, _ptr(hp) if n_hd else None,
+            _ptr(hv) if n_hd else None, _ptr(out), _ptr(chosen), ctypes.c_void_p(self.ws_view.data_ptr()),
+            self.ws_bytes, _stream()))
+        return out
+
+
+def hd_to_device(hd, ndim, device="cuda"):
+    """(real, pos (n, ndim), val) numpy -> GPU tensors with pos padded to 3."""
+    if hd is None or len(hd[0]) == 0:
+        return None
+    import numpy as np
+    real, pos, val = hd
+    pos3 = np.zeros((len(real), 3), dtype=np.int32)
+    pos3[:, :ndim] = pos
+    return (torch.from_numpy(np.ascontiguousarray(real, dtype=np.int32)).to(device),
+            torch.from_numpy(pos3).to(device),
+            torch.from_numpy(np.ascontiguousarray(val, dtype=np.int8)).to(device))
+
+
+def release_caches():
+    load().ccwsim_release_caches()

@@ -1,0 +1,1039 @@
+// ccwsim.hip -- CCWSIM hot path on MI355X: C ABI, simulation plan and the
+// per-step kernels (data-event extraction, selection + reconstruction + cut +
+// paste).  The scan itself is in dev_scan.h, the transform and top-K
+// building blocks in dev_kernels.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ccwsim.h"
+#include "dev_scan.h"
+
+using namespace ccw;
+
+// ===========================================================================
+// errors
+// ===========================================================================
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(x)                                                                 \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) return fail(CCWSIM_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CCW_TRY(x)        \
+  do {                    \
+    int s_ = (x);         \
+    if (s_) return s_;    \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline unsigned nblocks(long long n, int per = kThreads) { return (unsigned)((n + per - 1) / per); }
+inline long long align256(long long x) { return (x + 255) & ~255ll; }
+
+// ===========================================================================
+// geometry
+// ===========================================================================
+int geom_ti(Geom& g, const ccwsim_shape& s, int level) {
+  memset(&g, 0, sizeof g);
+  if (s.ndim < 2 || s.ndim > 3) return fail(CCWSIM_ERR_SHAPE, "ndim must be 2 or 3 (got %d)", s.ndim);
+  if (level < 0 || level > kMaxLevel) return fail(CCWSIM_ERR_SHAPE, "level must be in [0, %d]", kMaxLevel);
+  g.ndim = s.ndim;
+  g.level = level;
+  for (int a = 0; a < 3; ++a) {
+    const bool used = a < s.ndim;
+    const int n = s.n[a];
+    if (!used && n != 1) return fail(CCWSIM_ERR_SHAPE, "extent of unused axis %d must be 1", a);
+    if (n < 1) return fail(CCWSIM_ERR_SHAPE, "extent %d on axis %d", n, a);
+    g.ti[a] = n;
+    g.b[a] = used ? (1 << level) : 1;
+    g.np[a] = (n + g.b[a] - 1) / g.b[a] * g.b[a];
+    g.G[a] = g.np[a] / g.b[a];
+  }
+  g.beta = g.b[0] * g.b[1] * g.b[2];
+  g.log2beta = level * s.ndim;
+  for (int j = 0; j <= level; ++j)
+    for (int a = 0; a < 3; ++a) g.Gj[j][a] = a < s.ndim ? (g.np[a] >> j) : 1;
+  g.det_off[1] = 0;
+  for (int j = 1; j <= level; ++j) {
+    const long long cells = (long long)g.Gj[j][0] * g.Gj[j][1] * g.Gj[j][2];
+    g.det_off[j + 1] = g.det_off[j] + (long long)((1 << s.ndim) - 1) * cells;
+  }
+  g.det_total = level > 0 ? g.det_off[level + 1] : 0;
+  return CCWSIM_OK;
+}
+
+int geom_tmpl(Geom& g, const int32_t T[3]) {
+  long long nc = 1;
+  for (int a = 0; a < 3; ++a) {
+    const bool used = a < g.ndim;
+    const int t = used ? T[a] : 1;
+    if (used && (t < 1 || t > g.ti[a]))
+      return fail(CCWSIM_ERR_SHAPE, "template %d on axis %d must be in [1, TI extent %d]", t, a, g.ti[a]);
+    g.T[a] = t;
+    g.tc[a] = (t + g.b[a] - 1) / g.b[a];
+    g.cand[a] = (g.ti[a] - t) / g.b[a] + 1;
+    nc *= g.cand[a];
+  }
+  if (nc > (1 << 20)) return fail(CCWSIM_ERR_UNSUPPORTED, "%lld candidates exceed 2^20", nc);
+  g.ncand = (int)nc;
+  g.tcells = (long long)g.tc[0] * g.tc[1] * g.tc[2];
+  g.wcells = (long long)g.T[0] * g.T[1] * g.T[2];
+  return CCWSIM_OK;
+}
+
+int geom_grid(Geom& g, const ccwsim_shape& grid, const int32_t OV[3], const int32_t margin[3]) {
+  if (grid.ndim != g.ndim) return fail(CCWSIM_ERR_SHAPE, "grid and TI must have the same ndim");
+  for (int a = 0; a < 3; ++a) {
+    const bool used = a < g.ndim;
+    const int n = grid.n[a];
+    if (!used && n != 1) return fail(CCWSIM_ERR_SHAPE, "grid extent of unused axis %d must be 1", a);
+    if (n < 1) return fail(CCWSIM_ERR_SHAPE, "grid extent %d on axis %d", n, a);
+    g.sg[a] = n;
+    g.OV[a] = used ? OV[a] : 0;
+    if (used && !(g.T[a] > g.OV[a] && g.OV[a] >= 1))
+      return fail(CCWSIM_ERR_SHAPE, "need T > OV >= 1 on axis %d (T=%d, OV=%d)", a, g.T[a], g.OV[a]);
+    g.margin[a] = used ? (margin[a] < 0 ? OV[a] : margin[a]) : 0;
+    if (g.margin[a] > 4096) return fail(CCWSIM_ERR_SHAPE, "margin too large");
+    g.stride[a] = used ? g.T[a] - g.OV[a] : 1;
+    const int l = used ? (n - g.OV[a] + g.stride[a] - 1) / g.stride[a] : 1;
+    g.lat[a] = l < 1 ? 1 : l;
+    g.pad[a] = used ? g.lat[a] * g.stride[a] + g.OV[a] : 1;
+  }
+  g.pcells = (long long)g.pad[0] * g.pad[1] * g.pad[2];
+  return CCWSIM_OK;
+}
+
+// Bounds under which fp16 inputs and fp32 accumulation are exact and the
+// int32 score cannot overflow.  maxc = largest code, ovcells = largest number
+// of known overlap cells of a data event.
+int check_exact(const Geom& g, long long maxc, long long ovcells) {
+  const long long kmax = maxc * g.beta;
+  if (kmax > 2048) return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld are not exact in fp16", kmax);
+  const long long cmax = maxc * maxc * g.beta * ovcells;  // bound on any partial cross sum
+  if (cmax >= (1ll << 24))
+    return fail(CCWSIM_ERR_UNSUPPORTED, "cross sums up to %lld are not exact in fp32", cmax);
+  const long long smax = 3ll * ovcells * kmax * kmax;
+  if (smax >= (1ll << 31)) return fail(CCWSIM_ERR_UNSUPPORTED, "scores up to %lld overflow int32", smax);
+  return CCWSIM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// status
+// ===========================================================================
+extern "C" const char* ccwsim_status_string(int status) {
+  switch (status) {
+    case CCWSIM_OK: return "ok";
+    case CCWSIM_ERR_INVALID_ARG: return "invalid argument";
+    case CCWSIM_ERR_SHAPE: return "invalid shape";
+    case CCWSIM_ERR_WORKSPACE: return "workspace missing or too small";
+    case CCWSIM_ERR_HIP: return "HIP runtime error";
+    case CCWSIM_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* ccwsim_last_error(void) { return g_err.c_str(); }
+
+// ===========================================================================
+// A1: DWT
+// ===========================================================================
+namespace {
+
+// Runs the J level kernels.  tmp must hold 2 * |level-1 grid| int32 when J >= 2.
+int launch_dwt(const Geom& g, const int8_t* x, int32_t* approx, _Float16* approx_h, int32_t* det,
+               int32_t* tmp, hipStream_t st) {
+  const int J = g.level;
+  if (J == 0) {
+    const long long cells = (long long)g.ti[0] * g.ti[1] * g.ti[2];
+    k_level0<<<nblocks(cells), kThreads, 0, st>>>(x, approx, approx_h, cells);
+    HIP_TRY(hipGetLastError());
+    return CCWSIM_OK;
+  }
+  const long long c1 = (long long)g.Gj[1][0] * g.Gj[1][1] * g.Gj[1][2];
+  for (int j = 1; j <= J; ++j) {
+    const long long cells = (long long)g.Gj[j][0] * g.Gj[j][1] * g.Gj[j][2];
+    const int32_t* src = j >= 2 ? tmp + ((j - 1) & 1) * c1 : nullptr;
+    int32_t* dst = j == J ? approx : tmp + (j & 1) * c1;
+    _Float16* dh = j == J ? approx_h : nullptr;
+    if (g.ndim == 2)
+      k_dwt_level<2><<<nblocks(cells), kThreads, 0, st>>>(x, src, dst, dh, det, g, j);
+    else
+      k_dwt_level<3><<<nblocks(cells), kThreads, 0, st>>>(x, src, dst, dh, det, g, j);
+    HIP_TRY(hipGetLastError());
+  }
+  return CCWSIM_OK;
+}
+
+}  // namespace
+
+extern "C" int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int64_t* n_approx, int64_t* n_details) {
+  Geom g;
+  CCW_TRY(geom_ti(g, s, level));
+  if (n_approx) *n_approx = (int64_t)g.G[0] * g.G[1] * g.G[2];
+  if (n_details) *n_details = g.det_total;
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t* approx,
+                          int32_t* details, void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, s, level));
+  if (!x || !approx || (level > 0 && !details)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  hipStream_t st = as_stream(stream);
+  int32_t* tmp = nullptr;
+  if (level >= 2) {
+    const long long c1 = (long long)g.Gj[1][0] * g.Gj[1][1] * g.Gj[1][2];
+    HIP_TRY(hipMallocAsync((void**)&tmp, 2 * c1 * sizeof(int32_t), st));
+  }
+  const int rc = launch_dwt(g, x, approx, nullptr, details, tmp, st);
+  if (tmp) HIP_TRY(hipFreeAsync(tmp, st));
+  return rc;
+}
+
+// ===========================================================================
+// A3: standalone scan
+// ===========================================================================
+namespace {
+
+__global__ void k_to_half(const int32_t* __restrict__ src, _Float16* __restrict__ dst, long long n) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) dst[id] = (_Float16)(float)src[id];
+}
+
+// Standalone data events: or_m[f][beta] -> mbuf[f][k = beta] (fp16), zero pad.
+__global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, _Float16* __restrict__ mbuf,
+                                 int n_filters, long long tcells) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)n_filters * kKMax) return;
+  const long long f = id / kKMax, k = id - f * kKMax;
+  mbuf[id] = k < tcells ? (_Float16)(float)or_m[f * tcells + k] : (_Float16)0.0f;
+}
+
+size_t scan_lds_bytes(const Geom& g, int W, int kpad) {
+  const int nrows = g.tc[1] * g.tc[2];
+  const size_t strip = ((size_t)nrows * W * 2 + 15) & ~(size_t)15;
+  return strip + (size_t)kpad * 4 + (size_t)kFiltersPerTile * (kpad + 8) * 2;
+}
+
+int scan_strip_width(const Geom& g) {
+  return ((g.cand[0] + 31) / 32) * 32 + g.tc[0] - 1 + 1;  // +1 keeps an even length
+}
+
+}  // namespace
+
+extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code, const int32_t* approx,
+                               const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
+                               int32_t n_filters, int32_t score_mode, int32_t* scores, void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, ti, level));
+  if (!tmpl) return fail(CCWSIM_ERR_INVALID_ARG, "null template");
+  CCW_TRY(geom_tmpl(g, tmpl));
+  if (!approx || !or_m || !scores || (score_mode == 0 && !or_n))
+    return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_filters < 1) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters must be >= 1");
+  if (score_mode != 0 && score_mode != 1) return fail(CCWSIM_ERR_INVALID_ARG, "score_mode");
+  if (max_code < 1 || max_code > 126) return fail(CCWSIM_ERR_INVALID_ARG, "max_code must be in [1, 126]");
+  const int kpad = (int)((g.tcells + 15) / 16 * 16);
+  if (kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kKMax);
+  CCW_TRY(check_exact(g, max_code, g.wcells));
+  const int W = scan_strip_width(g);
+  const size_t lds = scan_lds_bytes(g, W, kpad);
+  if (lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu bytes of LDS", lds);
+
+  hipStream_t st = as_stream(stream);
+  const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
+  _Float16* Kh = nullptr;
+  _Float16* mbuf = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&Kh, gcells * 2, st));
+  HIP_TRY(hipMallocAsync((void**)&mbuf, (size_t)n_filters * kKMax * 2, st));
+  k_to_half<<<nblocks(gcells), kThreads, 0, st>>>(approx, Kh, gcells);
+  k_events_to_mbuf<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_m, mbuf, n_filters, g.tcells);
+  if (score_mode == 0)
+    k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, scores, g);
+  ScanArgs a = {};
+  a.g = g;
+  a.Kh = Kh;
+  a.mbuf = mbuf;
+  a.scores = scores;
+  a.kpad = kpad;
+  a.W = W;
+  a.score_mode = score_mode;
+  a.standalone = 1;
+  a.n_filters = n_filters;
+  dim3 grid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + kFiltersPerTile - 1) / kFiltersPerTile));
+  k_scan<<<grid, kThreads, lds, st>>>(a);
+  const hipError_t le = hipGetLastError();
+  HIP_TRY(hipFreeAsync(Kh, st));
+  HIP_TRY(hipFreeAsync(mbuf, st));
+  if (le != hipSuccess) return fail(CCWSIM_ERR_HIP, "k_scan launch: %s", hipGetErrorString(le));
+  return CCWSIM_OK;
+}
+
+// ===========================================================================
+// A6: standalone select
+// ===========================================================================
+namespace {
+
+__global__ __launch_bounds__(kThreads) void k_select(const int32_t* __restrict__ scores,
+                                                     const uint16_t* __restrict__ mism, long long n,
+                                                     int k, uint64_t seed, const int32_t* __restrict__ real,
+                                                     const int64_t* __restrict__ steps,
+                                                     int32_t* __restrict__ chosen, uint64_t* __restrict__ topk) {
+  __shared__ TopkShared sh;
+  const int f = blockIdx.x;
+  const uint64_t r = (uint64_t)real[f], s = (uint64_t)steps[f];
+  const uint64_t tkey = draw64(seed, kStreamTiebreak, r, s);
+  const int32_t* sc = scores + (long long)f * n;
+  const uint16_t* mm = mism ? mism + (long long)f * n : nullptr;
+  block_topk(n, k, [&](long long i) {
+    return make_key(mm ? mm[i] : 0u, sc[i], tie_perm((uint32_t)i, tkey));
+  }, sh);
+  if (threadIdx.x == 0) {
+    const uint64_t u = draw64(seed, kStreamDraw, r, s) >> 32;
+    const int jpick = (int)((u * (uint64_t)k) >> 32);
+    chosen[f] = (int32_t)tie_perm_inv((uint32_t)(sh.top[jpick] & kMask20), tkey);
+  }
+  if (topk && threadIdx.x < k) topk[(long long)f * k + threadIdx.x] = sh.top[threadIdx.x];
+}
+
+}  // namespace
+
+extern "C" int ccwsim_select(const int32_t* scores, const uint16_t* mismatch, int64_t n_cand,
+                             int32_t n_filters, int32_t top_k, uint64_t seed, const int32_t* realization,
+                             const int64_t* step, int32_t* chosen, uint64_t* topk_keys, void* stream) {
+  if (!scores || !realization || !step || !chosen) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_cand < 1 || n_cand > (1 << 20)) return fail(CCWSIM_ERR_INVALID_ARG, "n_cand must be in [1, 2^20]");
+  if (n_filters < 1) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters must be >= 1");
+  if (top_k < 1 || top_k > kTopMax) return fail(CCWSIM_ERR_UNSUPPORTED, "top_k must be in [1, %d]", kTopMax);
+  const int k = (int)std::min<int64_t>(top_k, n_cand);
+  hipStream_t st = as_stream(stream);
+  k_select<<<(unsigned)n_filters, kThreads, 0, st>>>(scores, mismatch, n_cand, k, seed, realization, step,
+                                                     chosen, topk_keys);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+// ===========================================================================
+// A7: standalone inverse transform of patterns
+// ===========================================================================
+namespace {
+
+long long idwt_buf_cells(const Geom& g) {
+  if (g.level == 0) return 0;
+  long long c = 1;
+  for (int a = 0; a < 3; ++a) c *= a < g.ndim ? (long long)g.tc[a] << (g.level - 1) : 1;
+  return c;
+}
+
+template <int ND>
+__global__ __launch_bounds__(kThreads) void k_idwt(const int32_t* __restrict__ approx,
+                                                   const int32_t* __restrict__ det, Geom g,
+                                                   const int32_t* __restrict__ origins,
+                                                   int8_t* __restrict__ out, long long buf_cells) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t* bufA = (int32_t*)smem;
+  int32_t* bufB = bufA + buf_cells;
+  int8_t* P = (int8_t*)(bufB + buf_cells);
+  const int p = blockIdx.x;
+  const int c0x = origins[3 * p], c0y = origins[3 * p + 1], c0z = origins[3 * p + 2];
+  const int c0[3] = {c0x, c0y, c0z};
+  bool ok = true;
+  for (int d = 0; d < 3; ++d) ok = ok && c0[d] >= 0 && c0[d] + g.tc[d] <= g.G[d];
+  if (!ok) {  // origin outside the approximation grid: mark the pattern invalid
+    for (long long u = threadIdx.x; u < g.wcells; u += kThreads) out[(long long)p * g.wcells + u] = -1;
+    return;
+  }
+  idwt_window<ND>(approx, det, g, c0x, c0y, c0z, bufA, bufB, P);
+  __syncthreads();
+  for (long long u = threadIdx.x; u < g.wcells; u += kThreads) out[(long long)p * g.wcells + u] = P[u];
+}
+
+}  // namespace
+
+extern "C" int ccwsim_idwt(const int32_t* approx, const int32_t* details, ccwsim_shape ti, int32_t level,
+                           const int32_t* block_origins, int32_t n, const int32_t patch[3], int8_t* patches,
+                           void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, ti, level));
+  if (!approx || !block_origins || !patches || !patch || (level > 0 && !details))
+    return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n < 0) return fail(CCWSIM_ERR_INVALID_ARG, "n must be >= 0");
+  for (int a = 0; a < 3; ++a) {
+    const int t = a < g.ndim ? patch[a] : 1;
+    if (t < 1 || t > 64) return fail(CCWSIM_ERR_UNSUPPORTED, "patch extent %d on axis %d", t, a);
+    g.T[a] = t;
+    g.tc[a] = (t + g.b[a] - 1) / g.b[a];
+    if (g.tc[a] > g.G[a]) return fail(CCWSIM_ERR_SHAPE, "patch larger than the TI on axis %d", a);
+  }
+  g.tcells = (long long)g.tc[0] * g.tc[1] * g.tc[2];
+  g.wcells = (long long)g.T[0] * g.T[1] * g.T[2];
+  if (g.wcells > 16384) return fail(CCWSIM_ERR_UNSUPPORTED, "patch has more than 16384 cells");
+  if (n == 0) return CCWSIM_OK;
+  const long long bc = idwt_buf_cells(g);
+  const size_t lds = (size_t)bc * 8 + (size_t)g.wcells;
+  if (lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "pattern needs %zu bytes of LDS", lds);
+  hipStream_t st = as_stream(stream);
+  if (g.ndim == 2)
+    k_idwt<2><<<(unsigned)n, kThreads, lds, st>>>(approx, details, g, block_origins, patches, bc);
+  else
+    k_idwt<3><<<(unsigned)n, kThreads, lds, st>>>(approx, details, g, block_origins, patches, bc);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+// ===========================================================================
+// whole hot path
+// ===========================================================================
+namespace {
+
+struct StepRange {
+  int fbegin, fcount;  // filters of this wavefront step (consecutive)
+  int tbegin, tcount;  // tiles of this step
+};
+
+struct DpDesc {        // one boundary-cut dynamic programme
+  int axis;            // band axis a
+  int rowaxis;         // axis along which the seam runs
+  int sliceaxis;       // remaining axis (3D) or -1
+  int slice;           // fixed coordinate on sliceaxis
+};
+
+struct Plan {
+  Geom g;
+  int n_orient = 0, n_shapes = 0, kpad = 0, W = 0;
+  int max_slots = 0, nsteps_raster = 0;
+  long long hdmax = 0;
+  std::vector<StepRange> steps;
+  // host tables, uploaded on every call (pinned)
+  size_t tbl_bytes = 0;
+  unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles
+  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0;
+  // workspace carve-up (bytes from the workspace base)
+  long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
+            ws_hdmap = 0, ws_mbuf = 0, ws_hdlist = 0, ws_hdcnt = 0, ws_keys = 0, ws_total = 0;
+  size_t scan_lds = 0, fin_lds = 0;
+  long long buf_cells = 0;
+  int dp_stride = 0, dp_batch = 0;
+  ~Plan() {
+    if (tbl) (void)hipHostFree(tbl);
+  }
+};
+
+std::mutex g_plan_mu;
+std::map<std::string, std::unique_ptr<Plan>> g_plans;
+
+// path of realization r: perm[k] = lattice axis at path depth k (0 fastest),
+// flip[a] = 1 when axis a is walked from its high end
+void path_of(const ccwsim_params& p, int r, int perm[3], int flip[3]) {
+  for (int a = 0; a < 3; ++a) {
+    perm[a] = a;
+    flip[a] = 0;
+  }
+  if (p.path_mode == 1) {
+    const uint64_t u = draw64(p.seed, kStreamPath, (uint64_t)r, 0);
+    for (int a = 0; a < p.ti.ndim; ++a) flip[a] = (int)((u >> a) & 1u);
+    if (p.ti.ndim == 2 && ((u >> 3) & 1u)) {
+      perm[0] = 1;
+      perm[1] = 0;
+    }
+  }
+}
+
+// cell u of the window is in a band of (orient, bandmask)
+bool in_band(const Geom& g, int orient, int bandmask, const int u[3]) {
+  for (int a = 0; a < g.ndim; ++a) {
+    if (!((bandmask >> a) & 1)) continue;
+    const int w = ((orient >> a) & 1) ? g.T[a] - 1 - u[a] : u[a];
+    if (w < g.OV[a]) return true;
+  }
+  return false;
+}
+
+int build_plan(const ccwsim_params& p, Plan& P) {
+  Geom& g = P.g;
+  CCW_TRY(geom_ti(g, p.ti, p.level));
+  CCW_TRY(geom_tmpl(g, p.tmpl));
+  CCW_TRY(geom_grid(g, p.grid, p.overlap, p.nc_margin));
+  if (p.top_k < 1 || p.top_k > kTopMax) return fail(CCWSIM_ERR_UNSUPPORTED, "top_k must be in [1, %d]", kTopMax);
+  if (p.n_real < 1) return fail(CCWSIM_ERR_INVALID_ARG, "n_real must be >= 1");
+  if (p.n_facies < 1 || p.n_facies > 127) return fail(CCWSIM_ERR_INVALID_ARG, "n_facies must be in [1, 127]");
+  if (p.path_mode != 0 && p.path_mode != 1) return fail(CCWSIM_ERR_INVALID_ARG, "path_mode");
+  if (p.score_mode != 0 && p.score_mode != 1) return fail(CCWSIM_ERR_INVALID_ARG, "score_mode");
+  if (p.cut != 0 && p.cut != 1) return fail(CCWSIM_ERR_INVALID_ARG, "cut");
+  if (p.precision != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
+  if (p.shortlist != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist %d", p.shortlist);
+  for (int i = 0; i < 4; ++i)
+    if (p.reserved[i]) return fail(CCWSIM_ERR_INVALID_ARG, "reserved fields must be 0");
+  const int nd = g.ndim;
+  P.n_orient = 1 << nd;
+  P.n_shapes = P.n_orient << nd;
+
+  // overlap blocks per orientation: blocks touching any trailing band
+  std::vector<std::vector<int>> klists(P.n_orient);
+  int kmax_len = 0;
+  long long ov_cells_max = 0;
+  for (int o = 0; o < P.n_orient; ++o) {
+    const int all = (1 << nd) - 1;
+    long long cnt = 0;
+    for (int bz = 0; bz < g.tc[2]; ++bz)
+      for (int by = 0; by < g.tc[1]; ++by)
+        for (int bx = 0; bx < g.tc[0]; ++bx) {
+          bool hit = false;
+          for (int uz = bz * g.b[2]; uz < std::min((bz + 1) * g.b[2], g.T[2]); ++uz)
+            for (int uy = by * g.b[1]; uy < std::min((by + 1) * g.b[1], g.T[1]); ++uy)
+              for (int ux = bx * g.b[0]; ux < std::min((bx + 1) * g.b[0], g.T[0]); ++ux) {
+                const int u[3] = {ux, uy, uz};
+                if (in_band(g, o, all, u)) {
+                  hit = true;
+                  ++cnt;
+                }
+              }
+          if (hit) klists[o].push_back((bz * g.tc[1] + by) * g.tc[0] + bx);
+        }
+    kmax_len = std::max<int>(kmax_len, (int)klists[o].size());
+    ov_cells_max = std::max(ov_cells_max, cnt);
+  }
+  P.kpad = std::max(16, (kmax_len + 15) / 16 * 16);
+  if (P.kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "overlap spans %d blocks (> %d)", kmax_len, kKMax);
+  CCW_TRY(check_exact(g, p.n_facies - 1 > 0 ? p.n_facies - 1 : 1, ov_cells_max));
+  P.W = scan_strip_width(g);
+  P.scan_lds = scan_lds_bytes(g, P.W, P.kpad);
+  if (P.scan_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu B of LDS", P.scan_lds);
+
+  // schedule: anti-diagonal wavefronts when same-step windows are disjoint
+  bool wave_ok = true;
+  for (int a = 0; a < nd; ++a) wave_ok = wave_ok && g.T[a] >= 2 * g.OV[a];
+  const long long nsteps = (long long)g.lat[0] * g.lat[1] * g.lat[2];
+  if (nsteps > (1ll << 30)) return fail(CCWSIM_ERR_UNSUPPORTED, "lattice too large");
+  P.nsteps_raster = (int)nsteps;
+  std::vector<std::vector<FilterDev>> by_t;
+  for (int r = 0; r < p.n_real; ++r) {
+    int perm[3], flip[3];
+    path_of(p, r, perm, flip);
+    const int plen[3] = {g.lat[perm[0]], g.lat[perm[1]], g.lat[perm[2]]};
+    int orient = 0;
+    for (int a = 0; a < nd; ++a) orient |= flip[a] << a;
+    for (long long s = 0; s < nsteps; ++s) {
+      const int q[3] = {(int)(s % plen[0]), (int)((s / plen[0]) % plen[1]), (int)(s / ((long long)plen[0] * plen[1]))};
+      FilterDev f = {};
+      f.r = r;
+      f.step = (int)s;
+      int li[3];
+      int bm = 0;
+      for (int k = 0; k < 3; ++k) {
+        const int a = perm[k];
+        li[a] = flip[a] ? g.lat[a] - 1 - q[k] : q[k];
+        if (a < nd && q[k] > 0) bm |= 1 << a;
+      }
+      for (int a = 0; a < 3; ++a) f.org[a] = li[a] * g.stride[a];
+      f.orient = orient;
+      f.bandmask = bm;
+      f.shape = (orient << nd) | bm;
+      const long long t = wave_ok ? (long long)q[0] + 2ll * q[1] + 4ll * q[2] : s;
+      if ((long long)by_t.size() <= t) by_t.resize(t + 1);
+      by_t[t].push_back(f);
+    }
+  }
+  std::vector<FilterDev> filters;
+  std::vector<TileDev> tiles;
+  for (auto& lst : by_t) {
+    if (lst.empty()) continue;   // e.g. odd t when the fast path axis has one patch
+    std::stable_sort(lst.begin(), lst.end(), [](const FilterDev& x, const FilterDev& y) { return x.orient < y.orient; });
+    StepRange sr;
+    sr.fbegin = (int)filters.size();
+    sr.fcount = (int)lst.size();
+    sr.tbegin = (int)tiles.size();
+    for (size_t i = 0; i < lst.size();) {
+      size_t e = i;
+      while (e < lst.size() && lst[e].orient == lst[i].orient && (int)(e - i) < kFiltersPerTile) ++e;
+      TileDev t = {(int)i, (int)(e - i), lst[i].orient, 0};
+      tiles.push_back(t);
+      i = e;
+    }
+    sr.tcount = (int)tiles.size() - sr.tbegin;
+    filters.insert(filters.end(), lst.begin(), lst.end());
+    P.max_slots = std::max(P.max_slots, sr.fcount);
+    P.steps.push_back(sr);
+  }
+
+  // energy rows: known-cell count per block for each (orient, bandmask)
+  std::vector<int32_t> nbt((size_t)P.n_shapes * g.tcells, 0);
+  for (int sh = 0; sh < P.n_shapes; ++sh) {
+    const int o = sh >> nd, bm = sh & ((1 << nd) - 1);
+    for (int uz = 0; uz < g.T[2]; ++uz)
+      for (int uy = 0; uy < g.T[1]; ++uy)
+        for (int ux = 0; ux < g.T[0]; ++ux) {
+          const int u[3] = {ux, uy, uz};
+          if (!in_band(g, o, bm, u)) continue;
+          const long long bi = ((long long)(uz / g.b[2]) * g.tc[1] + uy / g.b[1]) * g.tc[0] + ux / g.b[0];
+          nbt[(size_t)sh * g.tcells + bi] += 1;
+        }
+  }
+  std::vector<int32_t> kbeta((size_t)P.n_orient * kKMax, -1);
+  for (int o = 0; o < P.n_orient; ++o)
+    for (size_t i = 0; i < klists[o].size(); ++i) kbeta[(size_t)o * kKMax + i] = klists[o][i];
+
+  // pinned table block
+  P.off_kbeta = 0;
+  P.off_nbt = align256(kbeta.size() * 4);
+  P.off_filters = P.off_nbt + align256(nbt.size() * 4);
+  P.off_tiles = P.off_filters + align256(filters.size() * sizeof(FilterDev));
+  P.tbl_bytes = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
+  if (hipHostMalloc((void**)&P.tbl, P.tbl_bytes, hipHostMallocDefault) != hipSuccess)
+    return fail(CCWSIM_ERR_HIP, "hipHostMalloc of %zu bytes failed", P.tbl_bytes);
+  memcpy(P.tbl + P.off_kbeta, kbeta.data(), kbeta.size() * 4);
+  memcpy(P.tbl + P.off_nbt, nbt.data(), nbt.size() * 4);
+  memcpy(P.tbl + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
+  memcpy(P.tbl + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
+
+  // hard data: a virtual template holds at most its own cell count
+  long long vcells = 1;
+  for (int a = 0; a < 3; ++a) vcells *= (long long)g.T[a] + g.margin[a];
+  P.hdmax = vcells;
+
+  // workspace
+  const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
+  const long long c1 = g.level >= 2 ? (long long)g.Gj[1][0] * g.Gj[1][1] * g.Gj[1][2] : 0;
+  long long o = 0;
+  P.ws_kh = o;        o += align256(gcells * 2);
+  P.ws_ki = o;        o += align256(gcells * 4);
+  P.ws_det = o;       o += align256(std::max(1ll, g.det_total) * 4);
+  P.ws_tmp = o;       o += align256(2 * c1 * 4);
+  P.ws_energy = o;    o += align256((long long)P.n_shapes * g.ncand * 4);
+  P.ws_tbl = o;       o += align256((long long)P.tbl_bytes);
+  P.ws_sg = o;        o += align256((long long)p.n_real * g.pcells);
+  P.ws_hdmap = o;     o += align256((long long)p.n_real * g.pcells);
+  P.ws_mbuf = o;      o += align256((long long)P.max_slots * kKMax * 2);
+  P.ws_hdlist = o;    o += align256((long long)P.max_slots * P.hdmax * (long long)sizeof(HdEnt));
+  P.ws_hdcnt = o;     o += align256((long long)P.max_slots * 4);
+  P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
+  P.ws_total = o;
+
+  // finalize LDS: idwt buffers, pattern, keep mask, cut scratch
+  P.buf_cells = idwt_buf_cells(g);
+  int maxrows = 1, maxcols = 1;
+  for (int a = 0; a < nd; ++a) {
+    const int ra = a == 0 ? 1 : 0;
+    maxrows = std::max(maxrows, g.T[ra]);
+    maxcols = std::max(maxcols, g.OV[a]);
+  }
+  P.dp_stride = (int)align256((long long)maxrows * maxcols * 5 + (long long)maxcols * 8 + 16) ;
+  const size_t fixed = (size_t)P.buf_cells * 8 + 2 * (size_t)((g.wcells + 15) & ~15ll);
+  if (fixed + P.dp_stride > 60 * 1024)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs %zu B of LDS", fixed + P.dp_stride);
+  P.dp_batch = (int)std::min<long long>(kThreads, (60 * 1024 - (long long)fixed) / P.dp_stride);
+  P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride;
+  return CCWSIM_OK;
+}
+
+int get_plan(const ccwsim_params& p, Plan** out) {
+  std::string key((const char*)&p, sizeof p);
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return CCWSIM_OK;
+  }
+  std::unique_ptr<Plan> P(new Plan);
+  CCW_TRY(build_plan(p, *P));
+  *out = P.get();
+  g_plans.emplace(key, std::move(P));
+  return CCWSIM_OK;
+}
+
+// ---- simple per-call kernels ---------------------------------------------
+__global__ void k_fill_i8(int8_t* __restrict__ p, long long n, int8_t v) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) p[id] = v;
+}
+
+__global__ void k_scatter_hd(int8_t* __restrict__ sg, int8_t* __restrict__ hdmap, Geom g, int n_real,
+                             long long n_hd, const int32_t* __restrict__ hr, const int32_t* __restrict__ hp,
+                             const int8_t* __restrict__ hv) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_hd) return;
+  const int r = hr[i];
+  const int x = hp[3 * i], y = hp[3 * i + 1], z = hp[3 * i + 2];
+  if (r < 0 || r >= n_real || x < 0 || y < 0 || z < 0 || x >= g.sg[0] || y >= g.sg[1] || z >= g.sg[2]) return;
+  const long long at = (long long)r * g.pcells + idx3(x, y, z, g.pad);
+  sg[at] = hv[i];
+  hdmap[at] = hv[i];
+}
+
+__global__ void k_crop(const int8_t* __restrict__ sg, int8_t* __restrict__ out, Geom g, int n_real) {
+  const long long cells = (long long)g.sg[0] * g.sg[1] * g.sg[2];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= cells * n_real) return;
+  const long long r = id / cells, c = id - r * cells;
+  const int x = (int)(c % g.sg[0]), y = (int)((c / g.sg[0]) % g.sg[1]), z = (int)(c / ((long long)g.sg[0] * g.sg[1]));
+  out[id] = sg[r * g.pcells + idx3(x, y, z, g.pad)];
+}
+
+// ---- data event of each active patch (Algorithm 1: extract OR, DWT of OR) --
+struct PrepArgs {
+  Geom g;
+  const FilterDev* filters;   // of this step
+  const int32_t* kbeta;
+  const int8_t* sg;
+  const int8_t* hdmap;
+  _Float16* mbuf;
+  HdEnt* hdlist;
+  int32_t* hdcnt;
+  long long hdmax;
+  int kpad;
+  int has_hd;
+};
+
+__device__ __forceinline__ bool dev_in_band(const Geom& g, int orient, int bandmask, int ux, int uy, int uz) {
+  const int u[3] = {ux, uy, uz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.ndim || !((bandmask >> a) & 1)) continue;
+    const int w = ((orient >> a) & 1) ? g.T[a] - 1 - u[a] : u[a];
+    if (w < g.OV[a]) return true;
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(kThreads) void k_prepare(PrepArgs a) {
+  const Geom& g = a.g;
+  const int slot = blockIdx.x;
+  const FilterDev f = a.filters[slot];
+  const int8_t* sg = a.sg + (long long)f.r * g.pcells;
+  for (int k = threadIdx.x; k < a.kpad; k += kThreads) {
+    const int beta = a.kbeta[f.orient * kKMax + k];
+    int m = 0;
+    if (beta >= 0 && f.bandmask) {
+      const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
+      for (int uz = bz * g.b[2]; uz < min((bz + 1) * g.b[2], g.T[2]); ++uz)
+        for (int uy = by * g.b[1]; uy < min((by + 1) * g.b[1], g.T[1]); ++uy)
+          for (int ux = bx * g.b[0]; ux < min((bx + 1) * g.b[0], g.T[0]); ++ux)
+            if (dev_in_band(g, f.orient, f.bandmask, ux, uy, uz))
+              m += sg[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)];
+    }
+    a.mbuf[(long long)slot * kKMax + k] = (_Float16)(float)m;
+  }
+  if (!a.has_hd) return;
+  __shared__ unsigned s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int lo[3], ext[3];
+  for (int d = 0; d < 3; ++d) {
+    int l = 0, h = g.T[d];
+    if (d < g.ndim) {
+      if ((f.orient >> d) & 1) l = -g.margin[d];
+      else h = g.T[d] + g.margin[d];
+    }
+    l = max(l, -f.org[d]);
+    h = min(h, g.pad[d] - f.org[d]);
+    lo[d] = l;
+    ext[d] = max(0, h - l);
+  }
+  const long long vc = (long long)ext[0] * ext[1] * ext[2];
+  const int8_t* hm = a.hdmap + (long long)f.r * g.pcells;
+  for (long long i = threadIdx.x; i < vc; i += kThreads) {
+    const int ux = lo[0] + (int)(i % ext[0]);
+    const int uy = lo[1] + (int)((i / ext[0]) % ext[1]);
+    const int uz = lo[2] + (int)(i / ((long long)ext[0] * ext[1]));
+    const int8_t v = hm[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)];
+    if (v >= 0) {
+      const unsigned p = atomicAdd(&s_cnt, 1u);
+      if (p < a.hdmax) {
+        HdEnt e;
+        e.u[0] = (int16_t)ux;
+        e.u[1] = (int16_t)uy;
+        e.u[2] = (int16_t)uz;
+        e.v = v;
+        a.hdlist[(long long)slot * a.hdmax + p] = e;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.hdcnt[slot] = (int32_t)min((long long)s_cnt, a.hdmax);
+}
+
+// ---- choose, rebuild, cut, paste (Algorithm 1 lines K best .. paste) ----
+struct FinArgs {
+  Geom g;
+  const FilterDev* filters;
+  const uint64_t* keys;
+  const int32_t* Ki;
+  const int32_t* det;
+  int8_t* sg;
+  const int8_t* hdmap;
+  int32_t* chosen_log;
+  uint64_t seed;
+  long long buf_cells;
+  int top_k;
+  int cut;
+  int nsteps;
+  int dp_stride, dp_batch;
+};
+
+template <int ND>
+__global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ TopkShared sh;
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+  const int slot = blockIdx.x;
+  const FilterDev f = a.filters[slot];
+  const uint64_t* kf = a.keys + (long long)slot * g.ncand;
+  const int k = min(a.top_k, g.ncand);
+  block_topk(g.ncand, k, [&](long long i) { return kf[i]; }, sh);
+  const uint64_t tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
+  const uint64_t u = draw64(a.seed, kStreamDraw, (uint64_t)f.r, (uint64_t)f.step) >> 32;
+  const int jpick = (int)((u * (uint64_t)k) >> 32);
+  int idx = (int)tie_perm_inv((uint32_t)(sh.top[jpick] & kMask20), tkey);
+  idx = min(max(idx, 0), g.ncand - 1);  // always in range for keys written by the scan
+  if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
+  const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
+
+  int32_t* bufA = (int32_t*)smem;
+  int32_t* bufB = bufA + a.buf_cells;
+  int8_t* P = (int8_t*)(bufB + a.buf_cells);
+  const long long wpad = (g.wcells + 15) & ~15ll;
+  uint8_t* keep = (uint8_t*)(P + wpad);
+  unsigned char* dps = (unsigned char*)(keep + wpad);
+  idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
+  for (long long i = tid; i < g.wcells; i += kThreads) keep[i] = 0;
+  __syncthreads();
+
+  const int8_t* sgr = a.sg + (long long)f.r * g.pcells;
+  if (a.cut && f.bandmask) {
+    // enumerate the seams: one per present band, per slice in 3D
+    int ndp = 0;
+    int dstart[3] = {0, 0, 0};
+    for (int ax = 0; ax < ND; ++ax) {
+      dstart[ax] = ndp;
+      if (!((f.bandmask >> ax) & 1)) continue;
+      const int ra = ax == 0 ? 1 : 0;
+      const int sa = ND == 3 ? 3 - ax - ra : -1;
+      ndp += sa >= 0 ? g.T[sa] : 1;
+    }
+    for (int base = 0; base < ndp; base += a.dp_batch) {
+      const int nb = min(a.dp_batch, ndp - base);
+      // stage the squared differences of every seam of this batch
+      for (int d = 0; d < nb; ++d) {
+        const int dd = base + d;
+        int ax = 0;
+        for (int q = 0; q < ND; ++q)
+          if (((f.bandmask >> q) & 1) && dd >= dstart[q]) ax = q;
+        const int ra = ax == 0 ? 1 : 0;
+        const int sa = ND == 3 ? 3 - ax - ra : -1;
+        const int sl = dd - dstart[ax];
+        const int rows = g.T[ra], cols = g.OV[ax];
+        int32_t* e = (int32_t*)(dps + (long long)d * a.dp_stride);
+        for (int i = tid; i < rows * cols; i += kThreads) {
+          const int y = i / cols, w = i - y * cols;
+          int uu[3] = {0, 0, 0};
+          uu[ax] = ((f.orient >> ax) & 1) ? g.T[ax] - 1 - w : w;
+          uu[ra] = y;
+          if (sa >= 0) uu[sa] = sl;
+          const int sv = sgr[idx3(f.org[0] + uu[0], f.org[1] + uu[1], f.org[2] + uu[2], g.pad)];
+          const int pv = P[idx3(uu[0], uu[1], uu[2], g.T)];
+          e[i] = (sv - pv) * (sv - pv);
+        }
+      }
+      __syncthreads();
+      if (tid < nb) {
+        const int dd = base + tid;
+        int ax = 0;
+        for (int q = 0; q < ND; ++q)
+          if (((f.bandmask >> q) & 1) && dd >= dstart[q]) ax = q;
+        const int ra = ax == 0 ? 1 : 0;
+        const int sa = ND == 3 ? 3 - ax - ra : -1;
+        const int sl = dd - dstart[ax];
+        const int rows = g.T[ra], cols = g.OV[ax];
+        unsigned char* scr = dps + (long long)tid * a.dp_stride;
+        int32_t* e = (int32_t*)scr;
+        int32_t* Ep = e + rows * cols;
+        int32_t* Ec = Ep + cols;
+        uint8_t* from = (uint8_t*)(Ec + cols);
+        for (int w = 0; w < cols; ++w) Ep[w] = e[w];
+        for (int y = 1; y < rows; ++y) {
+          for (int w = 0; w < cols; ++w) {
+            int best = w, bv = Ep[w];
+            if (w > 0 && Ep[w - 1] < bv) { best = w - 1; bv = Ep[w - 1]; }
+            if (w + 1 < cols && Ep[w + 1] < bv) { best = w + 1; bv = Ep[w + 1]; }
+            Ec[w] = e[y * cols + w] + bv;
+            from[y * cols + w] = (uint8_t)best;
+          }
+          int32_t* t = Ep; Ep = Ec; Ec = t;
+        }
+        int seam = 0;
+        for (int w = 1; w < cols; ++w)
+          if (Ep[w] < Ep[seam]) seam = w;
+        for (int y = rows - 1; y >= 0; --y) {
+          for (int w = 0; w < seam; ++w) {
+            int uu[3] = {0, 0, 0};
+            uu[ax] = ((f.orient >> ax) & 1) ? g.T[ax] - 1 - w : w;
+            uu[ra] = y;
+            if (sa >= 0) uu[sa] = sl;
+            keep[idx3(uu[0], uu[1], uu[2], g.T)] = 1;
+          }
+          if (y > 0) seam = from[y * cols + seam];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // paste the new side of every seam, keep hard data
+  int8_t* sgw = a.sg + (long long)f.r * g.pcells;
+  const int8_t* hm = a.hdmap + (long long)f.r * g.pcells;
+  for (long long i = tid; i < g.wcells; i += kThreads) {
+    const int ux = (int)(i % g.T[0]), uy = (int)((i / g.T[0]) % g.T[1]), uz = (int)(i / ((long long)g.T[0] * g.T[1]));
+    const long long at = idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad);
+    if (hm[at] < 0 && !keep[i]) sgw[at] = P[i];
+  }
+}
+
+}  // namespace
+
+extern "C" int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p) {
+  if (!p) {
+    fail(CCWSIM_ERR_INVALID_ARG, "null params");
+    return -1;
+  }
+  Plan* P = nullptr;
+  if (get_plan(*p, &P)) return -1;
+  return P->ws_total;
+}
+
+extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
+                               const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
+                               void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!p || !ti || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_hd < 0 || (n_hd > 0 && (!hd_real || !hd_pos || !hd_val)))
+    return fail(CCWSIM_ERR_INVALID_ARG, "hard data pointers");
+  Plan* P = nullptr;
+  CCW_TRY(get_plan(*p, &P));
+  if (!workspace || workspace_bytes < P->ws_total)
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)P->ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const Geom& g = P->g;
+  hipStream_t st = as_stream(stream);
+  unsigned char* ws = (unsigned char*)workspace;
+  _Float16* Kh = (_Float16*)(ws + P->ws_kh);
+  int32_t* Ki = (int32_t*)(ws + P->ws_ki);
+  int32_t* det = (int32_t*)(ws + P->ws_det);
+  int32_t* tmp = (int32_t*)(ws + P->ws_tmp);
+  int32_t* energy = (int32_t*)(ws + P->ws_energy);
+  unsigned char* tbl = ws + P->ws_tbl;
+  int8_t* sg = (int8_t*)(ws + P->ws_sg);
+  int8_t* hdmap = (int8_t*)(ws + P->ws_hdmap);
+  _Float16* mbuf = (_Float16*)(ws + P->ws_mbuf);
+  HdEnt* hdlist = (HdEnt*)(ws + P->ws_hdlist);
+  int32_t* hdcnt = (int32_t*)(ws + P->ws_hdcnt);
+  uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
+  const int32_t* kbeta = (const int32_t*)(tbl + P->off_kbeta);
+  const int32_t* nbt = (const int32_t*)(tbl + P->off_nbt);
+  const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
+  const TileDev* tiles = (const TileDev*)(tbl + P->off_tiles);
+
+  HIP_TRY(hipMemcpyAsync(tbl, P->tbl, P->tbl_bytes, hipMemcpyHostToDevice, st));
+  // TI transform and energy rows (depend on the TI only)
+  CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));
+  if (p->score_mode == 0) {
+    k_energy<<<nblocks((long long)P->n_shapes * g.ncand), kThreads, 0, st>>>(Ki, nbt, P->n_shapes, energy, g);
+    HIP_TRY(hipGetLastError());
+  }
+  // grids start unknown (-1) except for hard data
+  const long long allp = (long long)p->n_real * g.pcells;
+  k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(sg, allp, (int8_t)-1);
+  k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(hdmap, allp, (int8_t)-1);
+  if (n_hd > 0)
+    k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
+  HIP_TRY(hipGetLastError());
+
+  PrepArgs pa = {};
+  pa.g = g;
+  pa.kbeta = kbeta;
+  pa.sg = sg;
+  pa.hdmap = hdmap;
+  pa.mbuf = mbuf;
+  pa.hdlist = hdlist;
+  pa.hdcnt = hdcnt;
+  pa.hdmax = P->hdmax;
+  pa.kpad = P->kpad;
+  pa.has_hd = n_hd > 0;
+
+  ScanArgs sa = {};
+  sa.g = g;
+  sa.Kh = Kh;
+  sa.kbeta = kbeta;
+  sa.mbuf = mbuf;
+  sa.energy = energy;
+  sa.hdlist = hdlist;
+  sa.hdcnt = hdcnt;
+  sa.ti = ti;
+  sa.keys = keys;
+  sa.seed = p->seed;
+  sa.hdmax = (int)P->hdmax;
+  sa.kpad = P->kpad;
+  sa.W = P->W;
+  sa.score_mode = p->score_mode;
+  sa.standalone = 0;
+  sa.has_hd = n_hd > 0;
+
+  FinArgs fa = {};
+  fa.g = g;
+  fa.keys = keys;
+  fa.Ki = Ki;
+  fa.det = det;
+  fa.sg = sg;
+  fa.hdmap = hdmap;
+  fa.chosen_log = chosen;
+  fa.seed = p->seed;
+  fa.buf_cells = P->buf_cells;
+  fa.top_k = p->top_k;
+  fa.cut = p->cut;
+  fa.nsteps = P->nsteps_raster;
+  fa.dp_stride = P->dp_stride;
+  fa.dp_batch = P->dp_batch;
+
+  const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
+  for (const StepRange& s : P->steps) {
+    pa.filters = filters + s.fbegin;
+    k_prepare<<<(unsigned)s.fcount, kThreads, 0, st>>>(pa);
+    sa.filters = filters + s.fbegin;
+    sa.tiles = tiles + s.tbegin;
+    k_scan<<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
+    fa.filters = filters + s.fbegin;
+    if (g.ndim == 2)
+      k_finalize<2><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
+    else
+      k_finalize<3><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
+  }
+  HIP_TRY(hipGetLastError());
+  k_crop<<<nblocks((long long)p->n_real * g.sg[0] * g.sg[1] * g.sg[2]), kThreads, 0, st>>>(sg, out, g, p->n_real);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" void ccwsim_release_caches(void) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans.clear();
+}

@@ -1,0 +1,190 @@
+// dev_scan.h -- the CCW scan on MFMA (Sec. 4.3): every candidate of the TI
+// approximation grid against a tile of up to 32 data events ("filters").
+//
+// The contraction C[c][f] = sum_k K[c + beta_k] * m[f][k] is a GEMM with
+// M = candidates, N = filters, K = the level-J blocks of the overlap.  One
+// workgroup owns one row of candidates (fixed cy, cz) and one filter tile.
+// It stages the K-grid rows the row touches (T_c,y * T_c,z rows of the fp16
+// grid) in LDS, so the A operand is gathered from LDS without forming the
+// im2col matrix: A[i][k] = strip[off(beta_k) + cx_i].  Each wavefront takes
+// 32-candidate chunks and runs v_mfma_f32_32x32x16_f16 over the K dimension.
+// Inputs are integers <= 2048 and every partial sum stays below 2^24, so the
+// fp16-in / fp32-accumulate contraction is exact; the score is then formed
+// in int32: S = E - 2 |beta| C (squared-difference mode) or S = -C.
+#pragma once
+
+#include "dev_kernels.h"
+
+namespace ccw {
+
+constexpr int kKMax = 256;   // longest padded list of overlap blocks
+constexpr int kFiltersPerTile = 32;
+
+struct FilterDev {     // one (realization, patch) pair active in a step
+  int32_t r;           // realization
+  int32_t step;        // raster step of the patch
+  int32_t org[3];      // patch origin in the padded grid
+  int32_t shape;       // energy row: orient * 2^ndim + bandmask
+  int32_t orient;      // bit a: axis a walked from its high end
+  int32_t bandmask;    // bit a: overlap band present on axis a
+};
+
+struct TileDev {
+  int32_t first;       // first filter (index within the step)
+  int32_t count;       // filters in this tile (<= 32)
+  int32_t orient;      // shared orientation of the tile
+  int32_t pad_;
+};
+
+struct HdEnt {         // one hard datum inside a virtual template
+  int16_t u[3];        // offset from the patch origin
+  int16_t v;           // code
+};
+
+struct ScanArgs {
+  Geom g;
+  const _Float16* Kh;          // fp16 level-J grid
+  const int32_t* kbeta;        // [orient][kKMax] block index or -1 (simulate)
+  const TileDev* tiles;        // simulate: tiles of this step
+  const FilterDev* filters;    // simulate: filters of this step
+  const _Float16* mbuf;        // [slot][kKMax] data-event block sums
+  const int32_t* energy;       // simulate: [shape][ncand]
+  const HdEnt* hdlist;         // [slot][hdmax]
+  const int32_t* hdcnt;        // [slot]
+  const int8_t* ti;
+  uint64_t* keys;              // simulate: [slot][ncand]
+  int32_t* scores;             // standalone: [filter][ncand], holds E on entry
+  uint64_t seed;
+  int hdmax;
+  int kpad;                    // padded K dimension (multiple of 16)
+  int W;                       // LDS strip row length (halves)
+  int score_mode;              // 0 squared difference, 1 raw
+  int standalone;              // 1: filters/tiles/kbeta are implicit
+  int n_filters;               // standalone: number of filters
+  int has_hd;
+};
+
+__global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Geom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = blockIdx.x;
+  const int cy = row % g.cand[1], cz = row / g.cand[1];
+  const int W = a.W, kpad = a.kpad;
+  const int nrows = g.tc[1] * g.tc[2];
+
+  TileDev t;
+  if (a.standalone) {
+    t.first = blockIdx.y * kFiltersPerTile;
+    t.count = min(kFiltersPerTile, a.n_filters - t.first);
+    t.orient = 0;
+  } else {
+    t = a.tiles[blockIdx.y];
+  }
+
+  _Float16* s_strip = (_Float16*)smem;
+  const int strip_bytes = ((nrows * W * 2) + 15) & ~15;
+  int* s_off = (int*)(smem + strip_bytes);
+  _Float16* s_B = (_Float16*)(smem + strip_bytes + kpad * 4);
+  const int bstride = kpad + 8;   // halves per filter row (keeps 16 B alignment)
+
+  for (int i = tid; i < nrows * W; i += kThreads) {
+    const int rr = i / W, x = i - rr * W;
+    const int by = rr % g.tc[1], bz = rr / g.tc[1];
+    s_strip[i] = x < g.G[0] ? a.Kh[idx3(x, cy + by, cz + bz, g.G)] : (_Float16)0.0f;
+  }
+  for (int k = tid; k < kpad; k += kThreads) {
+    int beta;
+    if (a.standalone) beta = k < (int)g.tcells ? k : -1;
+    else beta = a.kbeta[t.orient * kKMax + k];
+    int off = 0;
+    if (beta >= 0) {
+      const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
+      off = (bz * g.tc[1] + by) * W + bx;
+    }
+    s_off[k] = off;
+  }
+  for (int i = tid; i < kFiltersPerTile * kpad; i += kThreads) {
+    const int j = i / kpad, k = i - j * kpad;
+    s_B[j * bstride + k] = j < t.count ? a.mbuf[(long long)(t.first + j) * kKMax + k] : (_Float16)0.0f;
+  }
+  __syncthreads();
+
+  const int j = lane & 31;          // A row (candidate in chunk) and B/D column (filter)
+  const int g8 = (lane >> 5) * 8;   // this lane's 8 entries of each 16-wide K slice
+  const bool fvalid = j < t.count;
+  const int slot = t.first + j;
+  FilterDev f = {};
+  uint64_t tkey = 0;
+  int nhd = 0;
+  if (fvalid && !a.standalone) {
+    f = a.filters[slot];
+    tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
+    if (a.has_hd) nhd = a.hdcnt[slot];
+  }
+  const int shift = g.log2beta + 1;
+  const int nchunks = (g.cand[0] + 31) / 32;
+  const long long rowbase = (long long)g.cand[0] * row;
+
+  for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
+    float16_t acc = {};
+    const int cbase = ch * 32 + j;
+    for (int kc = 0; kc < kpad; kc += 16) {
+      half8_t av, bv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
+      bv = *(const half8_t*)(s_B + j * bstride + kc + g8);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+    }
+    if (!fvalid) continue;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int cx = ch * 32 + i;
+      if (cx >= g.cand[0]) continue;
+      const long long idx = rowbase + cx;
+      const int C = (int)acc[v];
+      if (a.standalone) {
+        int32_t* sp = a.scores + (long long)slot * g.ncand + idx;
+        *sp = (a.score_mode == 0) ? *sp - (C << shift) : -C;
+        continue;
+      }
+      const int S = (a.score_mode == 0) ? a.energy[(long long)f.shape * g.ncand + idx] - (C << shift) : -C;
+      unsigned mis = 0;
+      for (int h = 0; h < nhd; ++h) {
+        const HdEnt e = a.hdlist[(long long)slot * a.hdmax + h];
+        const int fx = g.b[0] * cx + e.u[0], fy = g.b[1] * cy + e.u[1], fz = g.b[2] * cz + e.u[2];
+        if (fx >= 0 && fy >= 0 && fz >= 0 && fx < g.ti[0] && fy < g.ti[1] && fz < g.ti[2])
+          mis += a.ti[idx3(fx, fy, fz, g.ti)] != e.v;
+      }
+      a.keys[(long long)slot * g.ncand + idx] = make_key(mis, S, tie_perm((uint32_t)idx, tkey));
+    }
+  }
+}
+
+// Energy term E(c) = sum_beta n_beta K[c + beta]^2 for each shape (rows of
+// nbt), int32.  One thread per (shape, candidate).
+__global__ __launch_bounds__(kThreads) void k_energy(const int32_t* __restrict__ K,
+                                                     const int32_t* __restrict__ nbt, int n_shapes,
+                                                     int32_t* __restrict__ out, Geom g) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)n_shapes * g.ncand) return;
+  const int shape = (int)(id / g.ncand);
+  const long long c = id - (long long)shape * g.ncand;
+  const int cx = (int)(c % g.cand[0]), cy = (int)((c / g.cand[0]) % g.cand[1]);
+  const int cz = (int)(c / ((long long)g.cand[0] * g.cand[1]));
+  const int32_t* nb = nbt + (long long)shape * g.tcells;
+  int e = 0;
+  for (int bz = 0; bz < g.tc[2]; ++bz)
+    for (int by = 0; by < g.tc[1]; ++by)
+      for (int bx = 0; bx < g.tc[0]; ++bx) {
+        const int n = nb[(bz * g.tc[1] + by) * g.tc[0] + bx];
+        if (n) {
+          const int kv = K[idx3(cx + bx, cy + by, cz + bz, g.G)];
+          e += n * kv * kv;
+        }
+      }
+  out[id] = e;
+}
+
+}  // namespace ccw

@@ -1,0 +1,96 @@
+"""CPU-side checks of the C ABI: the library builds, loads and exports every
+function declared in include/ccwsim.h; host-side argument validation
+returns the documented status codes without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccwsim.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccwsim_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_00441_amd import ccwsim
+    if not os.path.exists(ccwsim.LIB_PATH):
+        from paper_2404_00441_amd import build
+        build.build()
+    return ccwsim.load()
+
+
+def test_header_declares_the_five_entry_points():
+    names = _declared()
+    for n in ("ccwsim_dwt", "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2404_00441_amd import ccwsim
+    names = _declared()
+    assert set(names) == set(ccwsim.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    assert lib.ccwsim_status_string(0) == b"ok"
+    assert lib.ccwsim_status_string(5) == b"unsupported"
+    assert lib.ccwsim_status_string(99) == b"unknown status"
+
+
+def test_dwt_sizes_host_only(lib):
+    from paper_2404_00441_amd import ccwsim
+    na, nd = ccwsim.dwt_sizes((500, 500), 2)
+    assert na == 125 * 125
+    assert nd == 3 * 250 * 250 + 3 * 125 * 125
+    na, nd = ccwsim.dwt_sizes((180, 150, 60), 2)
+    assert na == 45 * 38 * 15
+    assert nd == 7 * (90 * 76 * 30) + 7 * (45 * 38 * 15)
+    with pytest.raises(ccwsim.CcwsimError):
+        ccwsim.dwt_sizes((10, 10), 7)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(overlap=(24, 24)),            # T > OV violated
+    dict(overlap=(0, 6)),              # OV >= 1 violated
+    dict(tmpl=(200, 24)),              # template larger than the TI
+    dict(top_k=0),
+    dict(top_k=17),
+    dict(n_real=0),
+    dict(n_facies=0),
+    dict(path_mode=2),
+    dict(score_mode=3),
+    dict(level=7),
+])
+def test_simulate_validation_errors(lib, bad):
+    from paper_2404_00441_amd import ccwsim
+    from paper_2404_00441_amd import workloads as wl
+    p, _, _ = wl.make("c1_plain2d")
+    p.update(bad)
+    q = ccwsim.params_of(p)
+    assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q)) == -1
+    assert lib.ccwsim_last_error() != b""
+    st = lib.ccwsim_simulate(ctypes.byref(q), ctypes.c_void_p(1), 0, None, None, None, ctypes.c_void_p(1),
+                             None, ctypes.c_void_p(256), 1 << 30, None)
+    assert st in (1, 2, 5)
+
+
+def test_inexact_range_is_rejected(lib):
+    # 3 facies at J = 3 in 2D: block sums up to 2 * 64 = 128 are fine, but a
+    # level-4 grid of |beta| = 256 gives 512 -> still fine; codes up to 126 at
+    # J = 3 give 8064 > 2048 and must be rejected before any launch
+    from paper_2404_00441_amd import ccwsim
+    from paper_2404_00441_amd import workloads as wl
+    p, _, _ = wl.make("c1_plain2d")
+    p.update(level=3, n_facies=127)
+    q = ccwsim.params_of(p)
+    assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q)) == -1
+    assert b"fp16" in lib.ccwsim_last_error()

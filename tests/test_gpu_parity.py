@@ -1,0 +1,328 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle.
+
+All comparisons are bit-exact: every quantity of the method is an integer
+(integer Haar coefficients, integer scores, indices, codes).  Inputs are
+seeded and synthetic (``paper_2404_00441_amd.synthetic``); expected values
+come from ``oracle/`` only.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_00441_amd import synthetic as syn
+from paper_2404_00441_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_00441_amd import ccwsim
+    ccwsim.load()
+    return ccwsim
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a if dtype is None else a.astype(dtype))).cuda()
+
+
+def _sp(p, orc):
+    keys = ("ti", "grid", "tmpl", "overlap", "level", "top_k", "n_real", "n_facies", "seed", "path_mode",
+            "score_mode", "nc_margin", "cut")
+    return orc.SimParams(**{k: p[k] for k in keys})
+
+
+# --------------------------------------------------------------------------
+# A1 DWT
+# --------------------------------------------------------------------------
+DWT_CASES = [((13, 17), 1), ((150, 150), 1), ((500, 500), 2), ((61, 47), 3), ((33, 20), 0),
+             ((20, 18, 9), 2), ((180, 150, 60), 2), ((7, 9, 5), 1)]
+
+
+@pytest.mark.parametrize("shape,J", DWT_CASES, ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in DWT_CASES])
+def test_dwt_parity(cc, orc, shape, J):
+    _say("dwt", shape, J)
+    rng = np.random.default_rng(sum(shape) + J)
+    if len(shape) == 2:
+        x = syn.channel_image_2d(shape[1], shape[0], 5, 3, seed=7) if min(shape) >= 40 else \
+            rng.integers(0, 3, size=shape).astype(np.int8)
+    else:
+        x = rng.integers(0, 2, size=shape).astype(np.int8)
+    a_gpu, d_gpu = cc.dwt(_t(x), J)
+    a_orc, d_orc = orc.dwt(x, J)
+    assert np.array_equal(a_gpu.cpu().numpy().astype(np.int64), a_orc)
+    if J > 0:
+        assert np.array_equal(d_gpu.cpu().numpy().astype(np.int64), orc.details_flat(d_orc))
+
+
+# --------------------------------------------------------------------------
+# A7 inverse DWT of patterns
+# --------------------------------------------------------------------------
+IDWT_CASES = [((150, 150), (24, 24), 1), ((500, 500), (40, 40), 2), ((101, 77), (13, 9), 2),
+              ((180, 150, 60), (30, 30, 10), 2), ((40, 30, 20), (7, 5, 6), 1), ((50, 40), (11, 7), 0)]
+
+
+@pytest.mark.parametrize("ext,patch,J", IDWT_CASES, ids=[f"{'x'.join(map(str, e))}_J{j}" for e, _, j in IDWT_CASES])
+def test_idwt_parity(cc, orc, ext, patch, J):
+    _say("idwt", ext, patch, J)
+    rng = np.random.default_rng(len(ext) * 100 + J)
+    shape = ext[::-1]
+    x = rng.integers(0, 3, size=shape).astype(np.int8)
+    a_gpu, d_gpu = cc.dwt(_t(x), J)
+    b = 2 ** J
+    nd = len(ext)
+    G = [-(-e // b) for e in ext]
+    tc = [-(-t // b) for t in patch]
+    n = 40
+    org = np.zeros((n, 3), dtype=np.int32)
+    for a in range(nd):
+        org[:, a] = rng.integers(0, G[a] - tc[a] + 1, size=n)
+        org[0, a] = 0
+        org[1, a] = G[a] - tc[a]
+    pats = cc.idwt(a_gpu, d_gpu, ext, J, _t(org), patch).cpu().numpy()
+    a_orc, d_orc = orc.dwt(x, J)
+    xp = np.pad(x, [(0, (-s) % b) for s in shape], mode="edge")
+    for i in range(n):
+        sl = tuple(slice(b * org[i, a], b * org[i, a] + patch[a]) for a in range(nd))[::-1]
+        reg = orc.idwt_region(a_orc, d_orc, ext, J, list(org[i, :nd]), tc)
+        want = reg[tuple(slice(0, patch[a]) for a in range(nd))[::-1]]
+        assert np.array_equal(want, xp[sl])
+        assert np.array_equal(pats[i].astype(np.int64), want)
+
+
+def test_idwt_rejects_origin_outside_grid(cc):
+    x = np.random.default_rng(0).integers(0, 2, size=(40, 40)).astype(np.int8)
+    a, d = cc.dwt(_t(x), 1)
+    org = np.array([[19, 0, 0], [-1, 0, 0], [0, 15, 0]], dtype=np.int32)  # tc = 6 -> only [0..14] fit
+    pats = cc.idwt(a, d, (40, 40), 1, _t(org), (12, 12)).cpu().numpy()
+    assert (pats == -1).all()
+
+
+# --------------------------------------------------------------------------
+# A3/A4 scan
+# --------------------------------------------------------------------------
+def _events(rng, T, J, nf, ncode, kind):
+    """nf data events over the T window: random masks, or overlap bands."""
+    b = 2 ** J
+    tc = [-(-t // b) for t in T]
+    nd = len(T)
+    nb = np.zeros((nf,) + tuple(tc[::-1]), dtype=np.int64)
+    mb = np.zeros_like(nb)
+    for f in range(nf):
+        vals = rng.integers(0, ncode, size=T[::-1])
+        if kind == "random":
+            mask = rng.random(T[::-1]) < rng.uniform(0.05, 1.0)
+        else:
+            mask = np.zeros(T[::-1], dtype=bool)
+            ov = [max(1, t // 4) for t in T]
+            for a in range(nd):
+                if rng.random() < 0.6:
+                    sl = [slice(None)] * nd
+                    sl[nd - 1 - a] = slice(0, ov[a]) if rng.random() < 0.5 else slice(T[a] - ov[a], T[a])
+                    mask[tuple(sl)] = True
+        for u in zip(*np.nonzero(mask)):
+            bk = tuple(ui // b for ui in u)
+            nb[(f,) + bk] += 1
+            mb[(f,) + bk] += vals[u]
+    return nb, mb
+
+
+SCAN_CASES = [
+    # ext (x,y[,z]), T, J, n_filters, n_facies, kind, mode
+    ((150, 150), (24, 24), 1, 3, 2, "bands", 0),
+    ((500, 500), (40, 40), 2, 17, 3, "bands", 0),
+    ((400, 400), (32, 32), 2, 70, 3, "random", 0),
+    ((97, 131), (18, 22), 1, 33, 3, "random", 1),
+    ((60, 50), (9, 7), 0, 5, 3, "random", 0),
+    ((180, 150, 60), (30, 30, 10), 2, 46, 2, "bands", 0),
+    ((45, 40, 21), (9, 11, 6), 1, 9, 3, "random", 1),
+]
+
+
+@pytest.mark.parametrize("case", SCAN_CASES, ids=[f"{'x'.join(map(str, c[0]))}_J{c[2]}_F{c[3]}_m{c[6]}"
+                                                  for c in SCAN_CASES])
+def test_scan_parity(cc, orc, case):
+    ext, T, J, nf, nfac, kind, mode = case
+    _say("scan", case)
+    rng = np.random.default_rng(nf + J)
+    shape = ext[::-1]
+    if len(ext) == 2 and min(ext) >= 60:
+        x = syn.channel_image_2d(ext[0], ext[1], 8, nfac, seed=nf)
+    else:
+        x = rng.integers(0, nfac, size=shape).astype(np.int8)
+    a_gpu, _ = cc.dwt(_t(x), J)
+    nb, mb = _events(rng, T, J, nf, nfac, kind)
+    S = cc.ccf_scan(ext, J, nfac - 1, a_gpu, T, _t(nb, np.int32), _t(mb, np.int32), score_mode=mode)
+    S = S.cpu().numpy()
+    a_orc, _ = orc.dwt(x, J)
+    b = 2 ** J
+    cand = [(ext[a] - T[a]) // b + 1 for a in range(len(ext))]
+    for f in range(nf):
+        want = orc.scores(a_orc, cand, nb[f], mb[f], b ** len(ext), mode=mode).ravel()
+        assert np.array_equal(S[f].astype(np.int64), want), f"filter {f}"
+
+
+def test_scan_rejects_inexact_range(cc):
+    x = np.zeros((64, 64), dtype=np.int8)
+    a, _ = cc.dwt(_t(x), 3)   # |beta| = 64: block sums up to 64 * 126 > 2048
+    nb = np.zeros((1, 2, 2), np.int32)
+    with pytest.raises(cc.CcwsimError):
+        cc.ccf_scan((64, 64), 3, 126, a, (16, 16), _t(nb), _t(nb))
+
+
+# --------------------------------------------------------------------------
+# A6 select
+# --------------------------------------------------------------------------
+SELECT_CASES = [(1, 5, False), (7, 10, True), (4096, 5, False), (13456, 10, True), (57121, 16, False),
+                (8649, 1, True), (300, 16, True)]
+
+
+@pytest.mark.parametrize("n,k,with_mis", SELECT_CASES, ids=[f"n{c[0]}_k{c[1]}_{c[2]}" for c in SELECT_CASES])
+def test_select_parity(cc, orc, n, k, with_mis):
+    import torch
+    _say("select", n, k, with_mis)
+    rng = np.random.default_rng(n + k)
+    nf = 12
+    S = (rng.integers(-40, 40, size=(nf, n)) * rng.integers(1, 1000, size=(nf, 1))).astype(np.int32)
+    S[0] = 0                                 # one filter of pure ties (first patch)
+    mis = rng.integers(0, 4, size=(nf, n)).astype(np.int16) if with_mis else None
+    if with_mis:
+        mis[1] = 5000                        # saturates at 4095
+    real = rng.integers(0, 64, size=nf).astype(np.int32)
+    step = rng.integers(0, 4000, size=nf).astype(np.int64)
+    seed = 12345
+    chosen, keys = cc.select(_t(S), _t(mis) if with_mis else None, k, seed, _t(real), _t(step), want_keys=True)
+    chosen = chosen.cpu().numpy()
+    keys = keys.cpu().numpy().view(np.uint64)
+    for f in range(nf):
+        c, kk = orc.select(S[f], None if mis is None else mis[f], k, seed, int(real[f]), int(step[f]))
+        assert chosen[f] == c, f"filter {f}"
+        assert np.array_equal(keys[f], kk), f"filter {f}"
+
+
+# --------------------------------------------------------------------------
+# whole path
+# --------------------------------------------------------------------------
+def _run(cc, p, ti, hd):
+    import torch
+    sim = cc.Simulator(p)
+    nd = len(p["ti"])
+    geo_steps = 1
+    for a in range(nd):
+        s = p["tmpl"][a] - p["overlap"][a]
+        geo_steps *= max(1, -(-(p["grid"][a] - p["overlap"][a]) // s))
+    chosen = torch.full((p["n_real"], geo_steps), -7, dtype=torch.int32, device="cuda")
+    out = sim.run(_t(ti), cc.hd_to_device(hd, nd), chosen=chosen)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), chosen.cpu().numpy()
+
+
+def _compare(cc, orc, p, ti, hd):
+    out, chosen = _run(cc, p, ti, hd)
+    oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(chosen, ochosen), f"first differing step {np.argwhere(chosen != ochosen)[:3]}"
+    assert np.array_equal(out, oout)
+    return out
+
+
+def _tiny(over, nhd, seed=11):
+    p = dict(nc_margin=(-1, -1, -1), n_facies=3, seed=seed, score_mode=0, name="tiny")
+    p.update(over)
+    nd = len(p["ti"])
+    if nd == 2:
+        ti = syn.channel_image_2d(p["ti"][0], p["ti"][1], 4, 3, seed=21)
+        ref = syn.channel_image_2d(p["grid"][0], p["grid"][1], 4, 3, seed=22)
+    else:
+        ti = syn.tube_image_3d(*p["ti"], 4, seed=21)
+        ref = syn.tube_image_3d(*p["grid"], 4, seed=22)
+        p["n_facies"] = 2
+    hd = syn.sample_hard_data(ref, [nhd] * p["n_real"], seed=23) if nhd else None
+    return p, ti, hd
+
+
+SIM_TINY = [
+    ("fixed_2d_j1", dict(ti=(40, 36), grid=(50, 47), tmpl=(10, 10), overlap=(3, 3), level=1, top_k=3,
+                         path_mode=0, n_real=1, cut=1), 0),
+    ("seeded_2d_j1_hd_batch", dict(ti=(48, 40), grid=(45, 52), tmpl=(12, 10), overlap=(3, 2), level=1,
+                                   top_k=4, path_mode=1, n_real=6, cut=1), 30),
+    ("partial_blocks_j2", dict(ti=(70, 66), grid=(61, 58), tmpl=(14, 11), overlap=(5, 3), level=2, top_k=5,
+                               path_mode=1, n_real=3, cut=1), 20),
+    ("level0_nocut", dict(ti=(30, 28), grid=(40, 33), tmpl=(7, 6), overlap=(2, 2), level=0, top_k=3,
+                          path_mode=1, n_real=2, cut=0), 10),
+    ("raw_score", dict(ti=(60, 60), grid=(64, 64), tmpl=(16, 16), overlap=(4, 4), level=1, top_k=6,
+                       path_mode=0, n_real=2, cut=1, score_mode=1), 0),
+    ("sequential_schedule", dict(ti=(50, 50), grid=(40, 44), tmpl=(10, 10), overlap=(6, 6), level=1,
+                                 top_k=3, path_mode=1, n_real=3, cut=1), 8),
+    ("one_column_lattice", dict(ti=(60, 60), grid=(20, 90), tmpl=(24, 24), overlap=(6, 6), level=1,
+                                top_k=5, path_mode=1, n_real=4, cut=1), 5),
+    ("single_patch", dict(ti=(40, 40), grid=(16, 16), tmpl=(16, 16), overlap=(4, 4), level=2, top_k=16,
+                          path_mode=0, n_real=2, cut=1), 3),
+    ("k_exceeds_candidates", dict(ti=(24, 24), grid=(40, 40), tmpl=(20, 20), overlap=(5, 5), level=1,
+                                  top_k=16, path_mode=1, n_real=2, cut=1), 0),
+    ("seeded_3d_j1", dict(ti=(24, 22, 16), grid=(30, 26, 18), tmpl=(8, 8, 6), overlap=(2, 2, 2), level=1,
+                          top_k=4, path_mode=1, n_real=3, cut=1), 12),
+    ("fixed_3d_j2", dict(ti=(40, 36, 20), grid=(44, 40, 22), tmpl=(12, 12, 8), overlap=(3, 3, 2), level=2,
+                         top_k=6, path_mode=0, n_real=2, cut=1), 0),
+]
+
+
+@pytest.mark.parametrize("case", SIM_TINY, ids=[c[0] for c in SIM_TINY])
+def test_simulate_small_cases(cc, orc, case):
+    name, over, nhd = case
+    _say("simulate", name)
+    p, ti, hd = _tiny(over, nhd)
+    out = _compare(cc, orc, p, ti, hd)
+    assert out.min() >= 0
+
+
+WORKLOAD_CASES = [("c1_plain2d", 1.0, None), ("c2_scale2d", 0.3, None), ("c4_batched", 0.5, 8),
+                  ("c3_split3d", 0.4, None), ("c5_learned", 0.12, 2)]
+
+
+@pytest.mark.parametrize("name,scale,nr", WORKLOAD_CASES, ids=[f"{c[0]}_s{c[1]}" for c in WORKLOAD_CASES])
+def test_simulate_workloads_scaled(cc, orc, name, scale, nr):
+    _say("workload", name, scale, nr)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    out = _compare(cc, orc, p, ti, hd)
+    if hd is not None:
+        for r, pos, v in zip(*hd):
+            assert out[(r,) + tuple(pos[::-1])] == v
+
+
+@pytest.mark.parametrize("name,nr", [("c2_scale2d", None), ("c1_plain2d", None), ("c4_batched", 16)])
+def test_simulate_full_size(cc, orc, name, nr):
+    # the full workload sizes, in the launch configuration the benchmark times
+    _say("full", name, nr)
+    p, ti, hd = wl.make(name, n_real=nr)
+    out = _compare(cc, orc, p, ti, hd)
+    assert out.min() >= 0
+    if hd is not None:
+        for r, pos, v in zip(*hd):
+            assert out[(r,) + tuple(pos[::-1])] == v
+
+
+def test_simulate_is_deterministic(cc):
+    p, ti, hd = wl.make("c2_scale2d", scale=0.3)
+    a, ca = _run(cc, p, ti, hd)
+    b, cb = _run(cc, p, ti, hd)
+    assert np.array_equal(a, b) and np.array_equal(ca, cb)
+
+
+def test_simulate_rejects_bad_workspace(cc):
+    import torch
+    p, ti, hd = wl.make("c1_plain2d")
+    q = cc.params_of(p)
+    import ctypes
+    out = torch.empty((1, 100, 100), dtype=torch.int8, device="cuda")
+    st = cc.load().ccwsim_simulate(ctypes.byref(q), ctypes.c_void_p(_t(ti).data_ptr()), 0, None, None, None,
+                                   ctypes.c_void_p(out.data_ptr()), None, None, 0, None)
+    assert st == 3

@@ -250,6 +250,30 @@ def test_raw_ccw_is_coarse_cross_correlation(orc):
 
 
 # --------------------------------------------------------------------------
+# K best and the draw
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,k,with_mis", [(1, 5, False), (7, 10, True), (500, 10, False), (3000, 16, True)])
+def test_select_matches_plain_sort(orc, n, k, with_mis):
+    # Sec. 4.4: sort, keep the K best, draw one uniformly; checked against a
+    # plain tuple sort of (mismatch, score, tie-break)
+    rng = np.random.default_rng(n + k)
+    for trial in range(5):
+        S = rng.integers(-50, 50, size=n) * (trial + 1)          # many ties
+        mis = rng.integers(0, 3, size=n) if with_mis else None
+        seed, r, step = 77 + trial, trial, 3 * trial + 1
+        chosen, keys = orc.select(S, mis, k, seed, r, step)
+        tkey = orc.rng(seed, 2, r, step)
+        order = sorted(range(n), key=lambda c: (0 if mis is None else int(mis[c]), int(S[c]),
+                                                orc.perm20(c, tkey)))
+        kk = min(k, n)
+        j = ((orc.rng(seed, 3, r, step) >> 32) * kk) >> 32
+        assert chosen == order[j]
+        want = [((0 if mis is None else int(mis[c])) << 52) | ((int(S[c]) + 2 ** 31) << 20)
+                | orc.perm20(c, tkey) for c in order[:kk]]
+        assert [int(x) for x in keys] == want
+
+
+# --------------------------------------------------------------------------
 # minimal-error boundary cut
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("rows,cols", [(1, 1), (1, 4), (4, 1), (5, 3), (6, 4), (4, 6)])
