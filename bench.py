@@ -1,0 +1,165 @@
+"""Throughput of the CCWSIM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One step is one ccwsim_simulate call: every patch of every realization of
+the workload goes through data-event extraction, the CCW scan over all
+candidates, top-K + draw, inverse DWT, boundary cut and paste.  Inputs (TI,
+hard data) are resident in HBM before the timed region.  Prints one JSON line.
+
+The roofline object is measured live: after the timed region, the same K
+steps run again with the library's event profiler on (events bracket every
+kernel launch on the launch stream); the dominant kernel's algorithmic work
+per launch divided by its average launch time gives `achieved`.
+The CPU baseline is the oracle, as it stands, on a bounded sample of the same
+workload (whole realizations, single thread).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_FP16_TFLOPS = 2500.0      # MI355X dense fp16 MFMA
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+
+METRIC = "simulated cells/s + CCF candidates/s (fraction of MFMA/HBM peak), plain vs learned"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2_scale2d")
+    ap.add_argument("--n-real", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
+                    help="HBM bytes per launch measured with rocprofv3 counters (optional)")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, ti, hd, budget_s=10.0, max_reps=8):
+    """Oracle on whole realizations of the workload, single-threaded."""
+    from oracle import oracle as orc
+    orc.build_oracle(force=False)
+    keys = ("ti", "grid", "tmpl", "overlap", "level", "top_k", "n_real", "n_facies", "seed", "path_mode",
+            "score_mode", "nc_margin", "cut")
+    q = dict(p)
+    sample_real = 1
+    q["n_real"] = sample_real
+    if hd is not None:
+        sel = hd[0] == 0
+        hd = (hd[0][sel], hd[1][sel], hd[2][sel])
+    sp = orc.SimParams(**{k: q[k] for k in keys})
+    cells = 1
+    for n in p["grid"]:
+        cells *= n
+    reps, t_total = 0, 0.0
+    while reps < max_reps and (reps == 0 or t_total < budget_s):
+        t0 = time.perf_counter()
+        orc.simulate(sp, ti, hd)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return {"value": cells * sample_real * reps / t_total, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} x realization 0 of the workload ({cells} cells each), {t_total:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2404_00441_amd import ccwsim as cc
+    from paper_2404_00441_amd import workloads as wl
+
+    p, ti, hd = wl.make(a.workload, n_real=a.n_real)
+    nd = len(p["ti"])
+    dev = torch.device("cuda:0")
+    ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+    hd_d = cc.hd_to_device(hd, nd, device=dev)
+    sim = cc.Simulator(p, device=dev)
+    out = torch.empty((p["n_real"],) + tuple(p["grid"][::-1]), dtype=torch.int8, device=dev)
+    stats = cc.simulate_stats(p)
+
+    for _ in range(a.warmup):
+        sim.run(ti_d, hd_d, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        sim.run(ti_d, hd_d, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    print(f"timed {a.steps} steps: {dt * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    cells = stats["cells"]
+    scanned = stats["patches"]          # every patch scans all candidates (the first scores 0)
+    res = {
+        "metric": METRIC,
+        "value": cells / dt,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp16",
+        "data": "synthetic",
+        "config": {"workload": wl.describe(p), "hard_data": 0 if hd is None else int(len(hd[0])),
+                   "path": "seeded" if p["path_mode"] else "raster", "form": "plain"},
+        "ccf_candidates_per_s": scanned * stats["candidates"] / dt,
+        "scan_tflops_algorithmic": stats["scan_flops"] / dt / 1e12,
+    }
+
+    if not a.no_roofline:
+        cc.profile_enable(True)
+        cc.profile_read()
+        for _ in range(a.steps):
+            sim.run(ti_d, hd_d, out=out)
+        torch.cuda.synchronize()
+        prof = cc.profile_read()
+        cc.profile_enable(False)
+        kern = {k: {"ms_per_step": v[0] / a.steps, "launches_per_step": v[1] / a.steps,
+                    "us_per_launch": (1e3 * v[0] / v[1]) if v[1] else 0.0} for k, v in prof.items()}
+        res["kernels"] = kern
+        dom = max(prof, key=lambda k: prof[k][0])
+        # algorithmic work of each kind per step
+        per_step_work = {
+            "scan": ("mfma", stats["scan_flops"], "TFLOP/s", PEAK_FP16_TFLOPS, 1e12),
+            "finalize": ("hbm", stats["key_bytes"] / 2, "GB/s", PEAK_HBM_GBS, 1e9),
+        }
+        kind = dom if dom in per_step_work else "scan"
+        bound, work, unit, peak, scale = per_step_work[kind]
+        launches = prof[kind][1] / a.steps
+        us = kern[kind]["us_per_launch"]
+        achieved = (work / launches) / (us * 1e-6) / scale if us > 0 else 0.0
+        traffic = None
+        if os.path.exists(a.traffic_json):
+            try:
+                tj = json.load(open(a.traffic_json))
+                if tj.get("kernel") == kind and tj.get("workload") == a.workload:
+                    traffic = tj.get("bytes_per_launch")
+            except (OSError, ValueError):
+                traffic = None
+        res["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                           "frac": achieved / peak, "traffic": traffic, "kernel": kind,
+                           "dominant_by_time": dom, "us_per_launch": us}
+
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(p, ti, hd)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,40 @@ int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, cons
  * concurrent ccwsim_simulate calls. */
 void ccwsim_release_caches(void);
 
+/* ---- measurement --------------------------------------------------------
+ * Work of one ccwsim_simulate call as the method defines it (not counting
+ * padding the kernels add): patches = (realization, patch) pairs, or_blocks =
+ * sum over patches of the level-J blocks holding known overlap cells,
+ * scan_flops = 2 * or_blocks * candidates (one multiply-add per block and
+ * candidate, Sec. 4.3).  Host call, no device work. */
+typedef struct {
+  int64_t patches;
+  int64_t wavefront_steps;
+  int64_t candidates;      /* per patch */
+  int64_t or_blocks;
+  double scan_flops;
+  double key_bytes;        /* candidate keys written by the scan and read by the selection */
+  double cells;            /* simulated grid cells, all realizations */
+} ccwsim_plan_stats;
+int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out);
+
+/* Kernel kinds timed by the profiler. */
+#define CCWSIM_KIND_DWT 0
+#define CCWSIM_KIND_ENERGY 1
+#define CCWSIM_KIND_INIT 2
+#define CCWSIM_KIND_PREPARE 3
+#define CCWSIM_KIND_SCAN 4
+#define CCWSIM_KIND_FINALIZE 5
+#define CCWSIM_KIND_CROP 6
+#define CCWSIM_NUM_KINDS 7
+/* When enabled, ccwsim_simulate brackets each kernel launch with a pair of
+ * hipEvents on the caller's stream.  ccwsim_profile_read synchronises those
+ * events, writes per-kind total milliseconds and launch counts (arrays of
+ * CCWSIM_NUM_KINDS) and clears the record.  Host calls; the events add a
+ * little launch overhead, so time throughput with profiling disabled. */
+int ccwsim_profile_enable(int on);
+int ccwsim_profile_read(double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,13 +76,28 @@ def load():
     L.ccwsim_simulate.argtypes = [p, p, i64, p, p, p, p, p, p, i64, p]
     L.ccwsim_release_caches.restype = None
     L.ccwsim_release_caches.argtypes = []
+    L.ccwsim_simulate_stats.restype = ctypes.c_int
+    L.ccwsim_simulate_stats.argtypes = [p, p]
+    L.ccwsim_profile_enable.restype = ctypes.c_int
+    L.ccwsim_profile_enable.argtypes = [ctypes.c_int]
+    L.ccwsim_profile_read.restype = ctypes.c_int
+    L.ccwsim_profile_read.argtypes = [p, p]
     _lib = L
     return L
 
 
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
-           "ccwsim_simulate", "ccwsim_release_caches")
+           "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
+           "ccwsim_profile_read")
+
+KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop")
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("patches", ctypes.c_int64), ("wavefront_steps", ctypes.c_int64),
+                ("candidates", ctypes.c_int64), ("or_blocks", ctypes.c_int64),
+                ("scan_flops", ctypes.c_double), ("key_bytes", ctypes.c_double), ("cells", ctypes.c_double)]
 
 
 def _check(fn, status):
@@ -254,3 +269,21 @@ def hd_to_device(hd, ndim, device="cuda"):
 
 def release_caches():
     load().ccwsim_release_caches()
+
+
+def simulate_stats(p: dict) -> dict:
+    s = PlanStats()
+    _check("ccwsim_simulate_stats", load().ccwsim_simulate_stats(ctypes.byref(params_of(p)), ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in PlanStats._fields_}
+
+
+def profile_enable(on: bool):
+    _check("ccwsim_profile_enable", load().ccwsim_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """Per kernel kind: (total ms, launches) since the last read."""
+    ms = (ctypes.c_double * len(KINDS))()
+    n = (ctypes.c_int64 * len(KINDS))()
+    _check("ccwsim_profile_read", load().ccwsim_profile_read(ms, n))
+    return {k: (ms[i], n[i]) for i, k in enumerate(KINDS)}

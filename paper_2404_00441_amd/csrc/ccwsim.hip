@@ -137,6 +137,47 @@ int check_exact(const Geom& g, long long maxc, long long ovcells) {
   return CCWSIM_OK;
 }
 
+// ---- launch profiler (events around each kernel launch) -------------------
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Scope object: records an event before and after the launches in its scope.
+struct ProfScope {
+  hipStream_t st;
+  int kind;
+  hipEvent_t a = nullptr;
+  ProfScope(int k, hipStream_t s) : st(s), kind(k) {
+    if (!g_prof_on) return;
+    a = prof_event();
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_recs.push_back({kind, a, b});
+  }
+};
+
 }  // namespace
 
 // ===========================================================================
@@ -424,6 +465,7 @@ struct Plan {
   Geom g;
   int n_orient = 0, n_shapes = 0, kpad = 0, W = 0;
   int max_slots = 0, nsteps_raster = 0;
+  long long patches = 0, or_blocks = 0;
   long long hdmax = 0;
   std::vector<StepRange> steps;
   // host tables, uploaded on every call (pinned)
@@ -556,9 +598,30 @@ int build_plan(const ccwsim_params& p, Plan& P) {
       by_t[t].push_back(f);
     }
   }
+  // overlap blocks holding known cells, per shape (the method's K dimension)
+  std::vector<int> shape_blocks(P.n_shapes, 0);
+  for (int sh = 0; sh < P.n_shapes; ++sh) {
+    const int o = sh >> nd, bm = sh & ((1 << nd) - 1);
+    for (int bz = 0; bz < g.tc[2]; ++bz)
+      for (int by = 0; by < g.tc[1]; ++by)
+        for (int bx = 0; bx < g.tc[0]; ++bx) {
+          bool hit = false;
+          for (int uz = bz * g.b[2]; uz < std::min((bz + 1) * g.b[2], g.T[2]) && !hit; ++uz)
+            for (int uy = by * g.b[1]; uy < std::min((by + 1) * g.b[1], g.T[1]) && !hit; ++uy)
+              for (int ux = bx * g.b[0]; ux < std::min((bx + 1) * g.b[0], g.T[0]) && !hit; ++ux) {
+                const int u[3] = {ux, uy, uz};
+                hit = in_band(g, o, bm, u);
+              }
+          shape_blocks[sh] += hit;
+        }
+  }
   std::vector<FilterDev> filters;
   std::vector<TileDev> tiles;
   for (auto& lst : by_t) {
+    for (const FilterDev& f : lst) {
+      P.patches += 1;
+      P.or_blocks += shape_blocks[f.shape];
+    }
     if (lst.empty()) continue;   // e.g. odd t when the fast path axis has one patch
     std::stable_sort(lst.begin(), lst.end(), [](const FilterDev& x, const FilterDev& y) { return x.orient < y.orient; });
     StepRange sr;
@@ -955,18 +1018,25 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
 
   HIP_TRY(hipMemcpyAsync(tbl, P->tbl, P->tbl_bytes, hipMemcpyHostToDevice, st));
   // TI transform and energy rows (depend on the TI only)
-  CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));
+  {
+    ProfScope ps(CCWSIM_KIND_DWT, st);
+    CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));
+  }
   if (p->score_mode == 0) {
+    ProfScope ps(CCWSIM_KIND_ENERGY, st);
     k_energy<<<nblocks((long long)P->n_shapes * g.ncand), kThreads, 0, st>>>(Ki, nbt, P->n_shapes, energy, g);
     HIP_TRY(hipGetLastError());
   }
   // grids start unknown (-1) except for hard data
   const long long allp = (long long)p->n_real * g.pcells;
-  k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(sg, allp, (int8_t)-1);
-  k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(hdmap, allp, (int8_t)-1);
-  if (n_hd > 0)
-    k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
-  HIP_TRY(hipGetLastError());
+  {
+    ProfScope ps(CCWSIM_KIND_INIT, st);
+    k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(sg, allp, (int8_t)-1);
+    k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(hdmap, allp, (int8_t)-1);
+    if (n_hd > 0)
+      k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
+    HIP_TRY(hipGetLastError());
+  }
 
   PrepArgs pa = {};
   pa.g = g;
@@ -1017,18 +1087,30 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
   for (const StepRange& s : P->steps) {
     pa.filters = filters + s.fbegin;
-    k_prepare<<<(unsigned)s.fcount, kThreads, 0, st>>>(pa);
+    {
+      ProfScope ps(CCWSIM_KIND_PREPARE, st);
+      k_prepare<<<(unsigned)s.fcount, kThreads, 0, st>>>(pa);
+    }
     sa.filters = filters + s.fbegin;
     sa.tiles = tiles + s.tbegin;
-    k_scan<<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
+    {
+      ProfScope ps(CCWSIM_KIND_SCAN, st);
+      k_scan<<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
+    }
     fa.filters = filters + s.fbegin;
-    if (g.ndim == 2)
-      k_finalize<2><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
-    else
-      k_finalize<3><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
+    {
+      ProfScope ps(CCWSIM_KIND_FINALIZE, st);
+      if (g.ndim == 2)
+        k_finalize<2><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
+      else
+        k_finalize<3><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
+    }
   }
   HIP_TRY(hipGetLastError());
-  k_crop<<<nblocks((long long)p->n_real * g.sg[0] * g.sg[1] * g.sg[2]), kThreads, 0, st>>>(sg, out, g, p->n_real);
+  {
+    ProfScope ps(CCWSIM_KIND_CROP, st);
+    k_crop<<<nblocks((long long)p->n_real * g.sg[0] * g.sg[1] * g.sg[2]), kThreads, 0, st>>>(sg, out, g, p->n_real);
+  }
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }
@@ -1036,4 +1118,46 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
 extern "C" void ccwsim_release_caches(void) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plans.clear();
+}
+
+extern "C" int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out) {
+  if (!p || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  Plan* P = nullptr;
+  CCW_TRY(get_plan(*p, &P));
+  const Geom& g = P->g;
+  out->patches = P->patches;
+  out->wavefront_steps = (int64_t)P->steps.size();
+  out->candidates = g.ncand;
+  out->or_blocks = P->or_blocks;
+  out->scan_flops = 2.0 * (double)P->or_blocks * (double)g.ncand;
+  out->key_bytes = 2.0 * 8.0 * (double)P->patches * (double)g.ncand;
+  out->cells = (double)p->n_real * g.sg[0] * g.sg[1] * g.sg[2];
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_profile_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int k = 0; k < CCWSIM_NUM_KINDS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  int rc = CCWSIM_OK;
+  for (const ProfRec& r : g_prof_recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      rc = fail(CCWSIM_ERR_HIP, "profiling events could not be read");
+    ms[r.kind] += t;
+    launches[r.kind] += 1;
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  return rc;
 }
