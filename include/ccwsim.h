@@ -175,8 +175,8 @@ int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, cons
                     const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
                     void* workspace, int64_t workspace_bytes, void* stream);
 
-/* Releases host-side caches (simulation plans).  Not thread-safe with
- * concurrent ccwsim_simulate calls. */
+/* Releases host-side caches (simulation plans and captured graphs).  Not
+ * thread-safe with concurrent ccwsim_simulate calls. */
 void ccwsim_release_caches(void);
 
 /* ---- measurement --------------------------------------------------------
@@ -212,6 +212,12 @@ int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out);
  * little launch overhead, so time throughput with profiling disabled. */
 int ccwsim_profile_enable(int on);
 int ccwsim_profile_read(double* ms, int64_t* launches);
+
+/* ccwsim_simulate captures its launch sequence into a HIP graph the first
+ * time it sees a (parameters, buffers) combination and replays the graph on
+ * later calls (up to 8 graphs are kept; the profiler bypasses them).
+ * ccwsim_set_graphs(0) switches to plain launches and drops the graphs. */
+int ccwsim_set_graphs(int on);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,8 @@ def load():
     L.ccwsim_profile_enable.argtypes = [ctypes.c_int]
     L.ccwsim_profile_read.restype = ctypes.c_int
     L.ccwsim_profile_read.argtypes = [p, p]
+    L.ccwsim_set_graphs.restype = ctypes.c_int
+    L.ccwsim_set_graphs.argtypes = [ctypes.c_int]
     _lib = L
     return L
 
@@ -89,7 +91,7 @@ def load():
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
-           "ccwsim_profile_read")
+           "ccwsim_profile_read", "ccwsim_set_graphs")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop")
 
@@ -275,6 +277,10 @@ def simulate_stats(p: dict) -> dict:
     s = PlanStats()
     _check("ccwsim_simulate_stats", load().ccwsim_simulate_stats(ctypes.byref(params_of(p)), ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in PlanStats._fields_}
+
+
+def set_graphs(on: bool):
+    _check("ccwsim_set_graphs", load().ccwsim_set_graphs(1 if on else 0))
 
 
 def profile_enable(on: bool):

@@ -403,12 +403,12 @@ __global__ __launch_bounds__(kThreads) void k_idwt(const int32_t* __restrict__ a
   bool ok = true;
   for (int d = 0; d < 3; ++d) ok = ok && c0[d] >= 0 && c0[d] + g.tc[d] <= g.G[d];
   if (!ok) {  // origin outside the approximation grid: mark the pattern invalid
-    for (long long u = threadIdx.x; u < g.wcells; u += kThreads) out[(long long)p * g.wcells + u] = -1;
+    for (int u = threadIdx.x; u < (int)g.wcells; u += kThreads) out[(long long)p * g.wcells + u] = -1;
     return;
   }
   idwt_window<ND>(approx, det, g, c0x, c0y, c0z, bufA, bufB, P);
   __syncthreads();
-  for (long long u = threadIdx.x; u < g.wcells; u += kThreads) out[(long long)p * g.wcells + u] = P[u];
+  for (int u = threadIdx.x; u < (int)g.wcells; u += kThreads) out[(long long)p * g.wcells + u] = P[u];
 }
 
 }  // namespace
@@ -474,10 +474,12 @@ struct Plan {
   size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0;
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
-            ws_hdmap = 0, ws_mbuf = 0, ws_hdlist = 0, ws_hdcnt = 0, ws_keys = 0, ws_total = 0;
+            ws_hdmap = 0, ws_mbuf = 0, ws_hdlist = 0, ws_hdcnt = 0, ws_keys = 0, ws_rowmin = 0, ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
-  long long buf_cells = 0;
-  int dp_stride = 0, dp_batch = 0;
+  long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
+  int tree_level = 0;   // 1 or 2: block-subtree coefficients; 0: planar details
+  int dp_stride = 0, dp_batch = 0, rows_max = 0, dp_wave = 0;
+  size_t prep_lds = 0;
   ~Plan() {
     if (tbl) (void)hipHostFree(tbl);
   }
@@ -682,7 +684,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   long long o = 0;
   P.ws_kh = o;        o += align256(gcells * 2);
   P.ws_ki = o;        o += align256(gcells * 4);
-  P.ws_det = o;       o += align256(std::max(1ll, g.det_total) * 4);
+  P.tree_level = (g.level == 1 || g.level == 2) ? g.level : 0;
+  P.ws_det = o;       o += align256(std::max(1ll, P.tree_level ? (long long)g.np[0] * g.np[1] * g.np[2] : g.det_total) * 4);
   P.ws_tmp = o;       o += align256(2 * c1 * 4);
   P.ws_energy = o;    o += align256((long long)P.n_shapes * g.ncand * 4);
   P.ws_tbl = o;       o += align256((long long)P.tbl_bytes);
@@ -692,22 +695,39 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_hdlist = o;    o += align256((long long)P.max_slots * P.hdmax * (long long)sizeof(HdEnt));
   P.ws_hdcnt = o;     o += align256((long long)P.max_slots * 4);
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
+  P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
   P.ws_total = o;
 
-  // finalize LDS: idwt buffers, pattern, keep mask, cut scratch
+  // finalize LDS: idwt buffers, pattern, keep mask, grid and hard-data
+  // windows, keys of the best rows, cut scratch
   P.buf_cells = idwt_buf_cells(g);
-  int maxrows = 1, maxcols = 1;
+  const long long wpad = (g.wcells + 15) & ~15ll;
+  int maxcols = 1;
+  P.rows_max = 1;
   for (int a = 0; a < nd; ++a) {
     const int ra = a == 0 ? 1 : 0;
-    maxrows = std::max(maxrows, g.T[ra]);
+    P.rows_max = std::max(P.rows_max, g.T[ra]);
     maxcols = std::max(maxcols, g.OV[a]);
   }
-  P.dp_stride = (int)align256((long long)maxrows * maxcols * 5 + (long long)maxcols * 8 + 16) ;
-  const size_t fixed = (size_t)P.buf_cells * 8 + 2 * (size_t)((g.wcells + 15) & ~15ll);
-  if (fixed + P.dp_stride > 60 * 1024)
-    return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs %zu B of LDS", fixed + P.dp_stride);
-  P.dp_batch = (int)std::min<long long>(kThreads, (60 * 1024 - (long long)fixed) / P.dp_stride);
+  P.dp_wave = maxcols <= 16 && P.rows_max <= 64;
+  const long long cand_bytes = (long long)std::min(p.top_k, g.ncand) * g.cand[0] * 8;
+  P.cand_cap = cand_bytes <= 24 * 1024 ? (long long)std::min(p.top_k, g.ncand) * g.cand[0] : 0;
+  const size_t fixed = (size_t)P.buf_cells * 8 + 4 * (size_t)wpad + (size_t)P.cand_cap * 8;
+  const long long budget = 60 * 1024;
+  if (P.dp_wave) {
+    P.dp_stride = 256;   // no scratch: the seams live in registers
+    P.dp_batch = 1;
+  } else {
+    P.dp_stride = (int)align256((long long)P.rows_max * maxcols + (long long)maxcols * 8 + 16);
+    P.dp_batch = (int)std::min<long long>(kThreads, (budget - (long long)fixed) / P.dp_stride);
+  }
+  if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
   P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride;
+  // the coefficient staging area aliases the key list and the cut scratch
+  const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
+  P.coef_lds = !P.tree_level && g.level > 0 && P.cand_cap > 0 && idwt_coef_count(g) * 4 <= alias_bytes;
+  P.prep_lds = (size_t)wpad;
   return CCWSIM_OK;
 }
 
@@ -780,11 +800,72 @@ __device__ __forceinline__ bool dev_in_band(const Geom& g, int orient, int bandm
   return false;
 }
 
+// Copy the T-window of a padded grid at `org` into LDS (every load of a
+// thread is issued before its stores).
+__device__ __forceinline__ void load_window(int8_t* dst, const int8_t* __restrict__ grid, const int org[3],
+                                            const Geom& g) {
+  constexpr int U = 8;
+  const int n = (int)g.wcells;
+  for (int base = threadIdx.x; base < n; base += kThreads * U) {
+    int8_t v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * kThreads;
+      v[q] = 0;
+      if (i < n) {
+        int ux, uy, uz;
+        split3(i, g.T[0], g.T[1], ux, uy, uz);
+        v[q] = grid[idx3(org[0] + ux, org[1] + uy, org[2] + uz, g.pad)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * kThreads;
+      if (i < n) dst[i] = v[q];
+    }
+  }
+}
+
+// Both windows (grid and hard-data map) in one pass; without hard data the
+// second window is filled with -1.
+__device__ __forceinline__ void load_windows(int8_t* d0, const int8_t* __restrict__ g0, int8_t* d1,
+                                             const int8_t* __restrict__ g1, const int org[3], const Geom& g) {
+  constexpr int U = 8;
+  const int n = (int)g.wcells;
+  for (int base = threadIdx.x; base < n; base += kThreads * U) {
+    int8_t v0[U], v1[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * kThreads;
+      v0[q] = 0;
+      v1[q] = -1;
+      if (i < n) {
+        int ux, uy, uz;
+        split3(i, g.T[0], g.T[1], ux, uy, uz);
+        const long long at = idx3(org[0] + ux, org[1] + uy, org[2] + uz, g.pad);
+        v0[q] = g0[at];
+        if (g1) v1[q] = g1[at];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * kThreads;
+      if (i < n) {
+        d0[i] = v0[q];
+        d1[i] = v1[q];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_prepare(PrepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const Geom& g = a.g;
   const int slot = blockIdx.x;
   const FilterDev f = a.filters[slot];
-  const int8_t* sg = a.sg + (long long)f.r * g.pcells;
+  int8_t* s_win = (int8_t*)smem;
+  load_window(s_win, a.sg + (long long)f.r * g.pcells, f.org, g);
+  __syncthreads();
   for (int k = threadIdx.x; k < a.kpad; k += kThreads) {
     const int beta = a.kbeta[f.orient * kKMax + k];
     int m = 0;
@@ -793,8 +874,7 @@ __global__ __launch_bounds__(kThreads) void k_prepare(PrepArgs a) {
       for (int uz = bz * g.b[2]; uz < min((bz + 1) * g.b[2], g.T[2]); ++uz)
         for (int uy = by * g.b[1]; uy < min((by + 1) * g.b[1], g.T[1]); ++uy)
           for (int ux = bx * g.b[0]; ux < min((bx + 1) * g.b[0], g.T[0]); ++ux)
-            if (dev_in_band(g, f.orient, f.bandmask, ux, uy, uz))
-              m += sg[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)];
+            if (dev_in_band(g, f.orient, f.bandmask, ux, uy, uz)) m += s_win[idx3(ux, uy, uz, g.T)];
     }
     a.mbuf[(long long)slot * kKMax + k] = (_Float16)(float)m;
   }
@@ -814,22 +894,35 @@ __global__ __launch_bounds__(kThreads) void k_prepare(PrepArgs a) {
     lo[d] = l;
     ext[d] = max(0, h - l);
   }
-  const long long vc = (long long)ext[0] * ext[1] * ext[2];
+  const int vc = ext[0] * ext[1] * ext[2];
   const int8_t* hm = a.hdmap + (long long)f.r * g.pcells;
-  for (long long i = threadIdx.x; i < vc; i += kThreads) {
-    const int ux = lo[0] + (int)(i % ext[0]);
-    const int uy = lo[1] + (int)((i / ext[0]) % ext[1]);
-    const int uz = lo[2] + (int)(i / ((long long)ext[0] * ext[1]));
-    const int8_t v = hm[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)];
-    if (v >= 0) {
-      const unsigned p = atomicAdd(&s_cnt, 1u);
-      if (p < a.hdmax) {
-        HdEnt e;
-        e.u[0] = (int16_t)ux;
-        e.u[1] = (int16_t)uy;
-        e.u[2] = (int16_t)uz;
-        e.v = v;
-        a.hdlist[(long long)slot * a.hdmax + p] = e;
+  constexpr int U = 8;
+  for (int base = threadIdx.x; base < vc; base += kThreads * U) {
+    int8_t v[U];
+    int uu[U][3];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = base + q * kThreads;
+      v[q] = -1;
+      uu[q][0] = uu[q][1] = uu[q][2] = 0;
+      if (i < vc) {
+        split3(i, ext[0], ext[1], uu[q][0], uu[q][1], uu[q][2]);
+        for (int d = 0; d < 3; ++d) uu[q][d] += lo[d];
+        v[q] = hm[idx3(f.org[0] + uu[q][0], f.org[1] + uu[q][1], f.org[2] + uu[q][2], g.pad)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (v[q] >= 0) {
+        const unsigned p = atomicAdd(&s_cnt, 1u);
+        if (p < a.hdmax) {
+          HdEnt e;
+          e.u[0] = (int16_t)uu[q][0];
+          e.u[1] = (int16_t)uu[q][1];
+          e.u[2] = (int16_t)uu[q][2];
+          e.v = v[q];
+          a.hdlist[(long long)slot * a.hdmax + p] = e;
+        }
       }
     }
   }
@@ -842,31 +935,213 @@ struct FinArgs {
   Geom g;
   const FilterDev* filters;
   const uint64_t* keys;
+  const uint64_t* rowmin;
   const int32_t* Ki;
   const int32_t* det;
+  const int32_t* tree;  // block-subtree coefficients (tree path)
   int8_t* sg;
   const int8_t* hdmap;
   int32_t* chosen_log;
   uint64_t seed;
   long long buf_cells;
+  long long cand_cap;   // keys of the best rows staged in LDS (0: read all keys from memory)
+  long long coef_lds;   // 1: stage the window's coefficients in LDS (aliases the key/cut area)
   int top_k;
   int cut;
   int nsteps;
+  int rows_max;         // longest seam (cells)
+  int has_hd;
+  int dp_wave;          // 1: every overlap <= 16 cells, one 16-lane group per seam
   int dp_stride, dp_batch;
 };
 
-template <int ND>
+// Window cell of a seam: w along the band axis ax (counted from the side
+// that faces the already simulated neighbour), y along the seam axis ra, sl
+// on the slice axis sa (or none).  Built with selects, not array indexing,
+// so everything stays in registers.
+__device__ __forceinline__ int seam_cell(const Geom& g, int orient, int ax, int ra, int sa, int sl, int y, int w) {
+  const int wc = ((orient >> ax) & 1) ? (ax == 0 ? g.T[0] : ax == 1 ? g.T[1] : g.T[2]) - 1 - w : w;
+  const int ux = ax == 0 ? wc : ra == 0 ? y : sa == 0 ? sl : 0;
+  const int uy = ax == 1 ? wc : ra == 1 ? y : sa == 1 ? sl : 0;
+  const int uz = ax == 2 ? wc : ra == 2 ? y : sa == 2 ? sl : 0;
+  return ux + g.T[0] * (uy + g.T[1] * uz);
+}
+
+// Squared code difference between the grid and the new pattern at that cell.
+__device__ __forceinline__ int seam_err(const Geom& g, const int8_t* s_sg, const int8_t* P, int orient, int ax,
+                                        int ra, int sa, int sl, int y, int w) {
+  const int c = seam_cell(g, orient, ax, ra, sa, sl, y, w);
+  const int d = (int)s_sg[c] - (int)P[c];
+  return d * d;
+}
+
+constexpr int kSeamRowsMax = 64;   // longest seam of the register dynamic programme
+
+// Minimal-error boundary cut of every seam of one patch, one wavefront per
+// seam (overlap <= 16 cells, seam <= ROWS cells).  Lane w holds column w
+// (w = 0 faces the already simulated neighbour).  Row by row the cumulative
+// error is E'[w] = e[w] + min(E[w], E[w-1], E[w+1]) with ties preferring w,
+// then w-1, then w+1; the neighbours come from row shifts, and the choice is
+// kept as a 2-bit field per row in registers.  The trace back then walks the
+// choices with a wave-uniform column (register reads only), collecting the
+// seam column of row y in lane y, and the cells before the seam are marked
+// in parallel afterwards.
+template <int ND, int ROWS>
+__device__ void seam_dp_wave(const Geom& g, const FilterDev& f, const int8_t* s_sg, const int8_t* P,
+                             uint8_t* keep, int n0, int n1, int n2) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ndp = n0 + n1 + n2;
+  for (int dd = wave; dd < ndp; dd += kThreads / 64) {
+    const int ax = dd < n0 ? 0 : dd < n0 + n1 ? 1 : 2;
+    const int sl = dd - (ax == 0 ? 0 : ax == 1 ? n0 : n0 + n1);
+    const int ra = ax == 0 ? 1 : 0;
+    const int sa = ND == 3 ? 3 - ax - ra : -1;
+    const int rows = ra == 0 ? g.T[0] : g.T[1];
+    const int cols = ax == 0 ? g.OV[0] : ax == 1 ? g.OV[1] : g.OV[2];
+    const int w = lane;
+    const bool on = w < cols;
+    int ev[ROWS];
+#pragma unroll
+    for (int y = 0; y < ROWS; ++y)
+      ev[y] = (on && y < rows) ? seam_err(g, s_sg, P, f.orient, ax, ra, sa, sl, y, w) : 0;
+    uint32_t choice[ROWS / 16];
+#pragma unroll
+    for (int q = 0; q < ROWS / 16; ++q) choice[q] = 0;
+    int E = on ? ev[0] : INT_MAX;
+#pragma unroll
+    for (int y = 1; y < ROWS; ++y) {
+      if (y < rows) {   // wave-uniform
+        const int left = __builtin_amdgcn_update_dpp(INT_MAX, E, 0x111, 0xF, 0xF, false);   // lane w-1
+        const int right = __builtin_amdgcn_update_dpp(INT_MAX, E, 0x101, 0xF, 0xF, false);  // lane w+1
+        const int lr = min(left, right);
+        const int m = min(E, lr);
+        const uint32_t c = E <= lr ? 0u : (left <= right ? 1u : 2u);
+        choice[y >> 4] |= c << (2 * (y & 15));
+        E = on ? ev[y] + m : INT_MAX;
+      }
+    }
+    // end of the seam: smallest cumulative error, smallest column on ties
+    int bE = on ? E : INT_MAX, bw = w;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) {
+      const int oE = __shfl_xor(bE, m, 16), ow = __shfl_xor(bw, m, 16);
+      if (oE < bE || (oE == bE && ow < bw)) { bE = oE; bw = ow; }
+    }
+    int sc = __builtin_amdgcn_readfirstlane(bw);
+    int my_seam = 0;   // lane y: seam column of row y
+#pragma unroll
+    for (int q = ROWS / 16 - 1; q >= 0; --q) {
+#pragma unroll
+      for (int yy = 15; yy >= 0; --yy) {
+        const int y = q * 16 + yy;
+        if (y < rows) {
+          my_seam = lane == y ? sc : my_seam;
+          if (y > 0) {
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)choice[q], sc);
+            const uint32_t c = (word >> (2 * yy)) & 3u;
+            sc += c == 1u ? -1 : (c == 2u ? 1 : 0);
+          }
+        }
+      }
+    }
+    if (lane < rows)
+      for (int ww = 0; ww < my_seam; ++ww) keep[seam_cell(g, f.orient, ax, ra, sa, sl, lane, ww)] = 1;
+  }
+}
+
+
+template <int ND, int ROWS, int TJ>
 __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ TopkShared sh;
+  __shared__ int s_rows[kTopMax];
   const Geom& g = a.g;
   const int tid = threadIdx.x;
   const int slot = blockIdx.x;
   const FilterDev f = a.filters[slot];
-  const uint64_t* kf = a.keys + (long long)slot * g.ncand;
-  const int k = min(a.top_k, g.ncand);
-  block_topk(g.ncand, k, [&](long long i) { return kf[i]; }, sh);
+  const long long wpad = (g.wcells + 15) & ~15ll;
+  int32_t* bufA = (int32_t*)smem;
+  int32_t* bufB = bufA + a.buf_cells;
+  int8_t* P = (int8_t*)(bufB + a.buf_cells);
+  uint8_t* keep = (uint8_t*)(P + wpad);
+  int8_t* s_sg = (int8_t*)(keep + wpad);
+  int8_t* s_hd = s_sg + wpad;
+  uint64_t* s_cand = (uint64_t*)(s_hd + wpad);
+  unsigned char* dps = (unsigned char*)(s_cand + a.cand_cap);
+
+  // windows of the grid and of the hard-data map
+  load_windows(s_sg, a.sg + (long long)f.r * g.pcells, s_hd, a.has_hd ? a.hdmap + (long long)f.r * g.pcells : nullptr,
+               f.org, g);
+  for (int i = tid; i < (int)g.wcells; i += kThreads) keep[i] = 0;
+
+  // K best keys.  The smallest key of every candidate row is known from the
+  // scan; the K best keys lie in the K rows with the smallest minima, so only
+  // those rows are read.
   const uint64_t tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
+  const int k = min(a.top_k, g.ncand);
+  const uint64_t* kf = a.keys + (long long)slot * g.ncand;
+  __shared__ uint64_t s_rowtop[kTopMax];
+  __shared__ unsigned s_cnt;
+  __shared__ int s_over;
+  bool done = false;
+  if (a.cand_cap > 0) {
+    // 1. the kr smallest row minima, by rank (rows are few)
+    const int nrows = g.cand[1] * g.cand[2];
+    const uint64_t* rm = a.rowmin + (long long)slot * nrows;
+    const int kr = min(k, nrows);
+    uint64_t* s_rm = s_cand;   // staging; the candidate list reuses it afterwards
+    if (nrows <= a.cand_cap) {
+      for (int i = tid; i < nrows; i += kThreads) s_rm[i] = rm[i];
+      if (tid == 0) { s_cnt = 0; s_over = 0; }
+      __syncthreads();
+      block_rank_select(s_rm, nrows, kr, s_rowtop);
+    } else {
+      block_topk(nrows, kr, [&](long long i) { return rm[i]; }, sh);
+      if (tid < kr) s_rowtop[tid] = sh.top[tid];
+      if (tid == 0) { s_cnt = 0; s_over = 0; }
+      __syncthreads();
+    }
+    if (tid < kr) {
+      const int id = (int)tie_perm_inv((uint32_t)(s_rowtop[tid] & kMask20), tkey);
+      s_rows[tid] = min(max(id / g.cand[0], 0), nrows - 1);
+    }
+    __syncthreads();
+    // 2. every key of those rows at or below the kr-th row minimum (when
+    //    there are fewer rows than k, every key of every row)
+    const uint64_t thr = kr == k ? s_rowtop[kr - 1] : ~0ull;
+    const int cx = g.cand[0];
+    const int nc = kr * cx;
+    const int cap = (int)min(a.cand_cap, 256ll);
+    constexpr int U = 8;
+    for (int base = tid; base < nc; base += kThreads * U) {
+      uint64_t v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        v[q] = ~0ull;
+        if (i < nc) {
+          const int rr = i / cx;
+          v[q] = kf[(long long)s_rows[rr] * cx + (i - rr * cx)];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (v[q] <= thr && v[q] != ~0ull) {
+          const unsigned p = atomicAdd(&s_cnt, 1u);
+          if (p < (unsigned)cap) s_cand[p] = v[q];
+          else s_over = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (!s_over) {
+      // 3. the k smallest of the short list, by rank
+      block_rank_select(s_cand, (int)s_cnt, k, sh.top);
+      done = true;
+    }
+    // a long list falls through to the full selection below
+  }
+  if (!done) block_topk(g.ncand, k, [&](long long i) { return kf[i]; }, sh);
   const uint64_t u = draw64(a.seed, kStreamDraw, (uint64_t)f.r, (uint64_t)f.step) >> 32;
   const int jpick = (int)((u * (uint64_t)k) >> 32);
   int idx = (int)tie_perm_inv((uint32_t)(sh.top[jpick] & kMask20), tkey);
@@ -874,105 +1149,101 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
   const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
 
-  int32_t* bufA = (int32_t*)smem;
-  int32_t* bufB = bufA + a.buf_cells;
-  int8_t* P = (int8_t*)(bufB + a.buf_cells);
-  const long long wpad = (g.wcells + 15) & ~15ll;
-  uint8_t* keep = (uint8_t*)(P + wpad);
-  unsigned char* dps = (unsigned char*)(keep + wpad);
-  idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
-  for (long long i = tid; i < g.wcells; i += kThreads) keep[i] = 0;
-  __syncthreads();
+  // rebuild the pattern from the coefficient pyramid
+  if constexpr (TJ > 0) idwt_window_tree<ND, TJ>(a.tree, g, cx, cy, cz, P);
+  else if (a.coef_lds) idwt_window_lds<ND>(a.Ki, a.det, g, cx, cy, cz, (int32_t*)s_cand, bufA, bufB, P);
+  else idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
 
-  const int8_t* sgr = a.sg + (long long)f.r * g.pcells;
   if (a.cut && f.bandmask) {
-    // enumerate the seams: one per present band, per slice in 3D
-    int ndp = 0;
-    int dstart[3] = {0, 0, 0};
-    for (int ax = 0; ax < ND; ++ax) {
-      dstart[ax] = ndp;
-      if (!((f.bandmask >> ax) & 1)) continue;
-      const int ra = ax == 0 ? 1 : 0;
-      const int sa = ND == 3 ? 3 - ax - ra : -1;
-      ndp += sa >= 0 ? g.T[sa] : 1;
-    }
-    for (int base = 0; base < ndp; base += a.dp_batch) {
-      const int nb = min(a.dp_batch, ndp - base);
-      // stage the squared differences of every seam of this batch
-      for (int d = 0; d < nb; ++d) {
-        const int dd = base + d;
-        int ax = 0;
-        for (int q = 0; q < ND; ++q)
-          if (((f.bandmask >> q) & 1) && dd >= dstart[q]) ax = q;
-        const int ra = ax == 0 ? 1 : 0;
-        const int sa = ND == 3 ? 3 - ax - ra : -1;
-        const int sl = dd - dstart[ax];
-        const int rows = g.T[ra], cols = g.OV[ax];
-        int32_t* e = (int32_t*)(dps + (long long)d * a.dp_stride);
-        for (int i = tid; i < rows * cols; i += kThreads) {
-          const int y = i / cols, w = i - y * cols;
-          int uu[3] = {0, 0, 0};
-          uu[ax] = ((f.orient >> ax) & 1) ? g.T[ax] - 1 - w : w;
-          uu[ra] = y;
-          if (sa >= 0) uu[sa] = sl;
-          const int sv = sgr[idx3(f.org[0] + uu[0], f.org[1] + uu[1], f.org[2] + uu[2], g.pad)];
-          const int pv = P[idx3(uu[0], uu[1], uu[2], g.T)];
-          e[i] = (sv - pv) * (sv - pv);
-        }
-      }
+    // seams: one per present band, per slice in 3D
+    // seams of band 0 first, then band 1, then band 2; n_a seams per band
+    const int n0 = (f.bandmask & 1) ? (ND == 3 ? g.T[2] : 1) : 0;
+    const int n1 = (f.bandmask & 2) ? (ND == 3 ? g.T[2] : 1) : 0;
+    const int n2 = (ND == 3 && (f.bandmask & 4)) ? g.T[1] : 0;
+    const int ndp = n0 + n1 + n2;
+    auto dp_of = [&](int dd, int& ax, int& ra, int& sa, int& sl) {
+      ax = dd < n0 ? 0 : dd < n0 + n1 ? 1 : 2;
+      sl = dd - (ax == 0 ? 0 : ax == 1 ? n0 : n0 + n1);
+      ra = ax == 0 ? 1 : 0;
+      sa = ND == 3 ? 3 - ax - ra : -1;
+    };
+    if (a.dp_wave) {
+      seam_dp_wave<ND, ROWS>(g, f, s_sg, P, keep, n0, n1, n2);
       __syncthreads();
-      if (tid < nb) {
-        const int dd = base + tid;
-        int ax = 0;
-        for (int q = 0; q < ND; ++q)
-          if (((f.bandmask >> q) & 1) && dd >= dstart[q]) ax = q;
-        const int ra = ax == 0 ? 1 : 0;
-        const int sa = ND == 3 ? 3 - ax - ra : -1;
-        const int sl = dd - dstart[ax];
-        const int rows = g.T[ra], cols = g.OV[ax];
-        unsigned char* scr = dps + (long long)tid * a.dp_stride;
-        int32_t* e = (int32_t*)scr;
-        int32_t* Ep = e + rows * cols;
-        int32_t* Ec = Ep + cols;
-        uint8_t* from = (uint8_t*)(Ec + cols);
-        for (int w = 0; w < cols; ++w) Ep[w] = e[w];
-        for (int y = 1; y < rows; ++y) {
-          for (int w = 0; w < cols; ++w) {
-            int best = w, bv = Ep[w];
-            if (w > 0 && Ep[w - 1] < bv) { best = w - 1; bv = Ep[w - 1]; }
-            if (w + 1 < cols && Ep[w + 1] < bv) { best = w + 1; bv = Ep[w + 1]; }
-            Ec[w] = e[y * cols + w] + bv;
-            from[y * cols + w] = (uint8_t)best;
+    } else {
+      // wide overlaps: one thread per seam
+      for (int base = 0; base < ndp; base += a.dp_batch) {
+        const int nb = min(a.dp_batch, ndp - base);
+        if (tid < nb) {
+          int ax, ra, sa, sl;
+          dp_of(base + tid, ax, ra, sa, sl);
+          const int rows = g.T[ra], cols = g.OV[ax];
+          unsigned char* scr = dps + (long long)tid * a.dp_stride;
+          int32_t* Ep = (int32_t*)scr;
+          int32_t* Ec = Ep + cols;
+          uint8_t* from = (uint8_t*)(Ec + cols);
+          for (int w = 0; w < cols; ++w) Ep[w] = seam_err(g, s_sg, P, f.orient, ax, ra, sa, sl, 0, w);
+          for (int y = 1; y < rows; ++y) {
+            for (int w = 0; w < cols; ++w) {
+              int best = w, bv = Ep[w];
+              if (w > 0 && Ep[w - 1] < bv) { best = w - 1; bv = Ep[w - 1]; }
+              if (w + 1 < cols && Ep[w + 1] < bv) { best = w + 1; bv = Ep[w + 1]; }
+              Ec[w] = seam_err(g, s_sg, P, f.orient, ax, ra, sa, sl, y, w) + bv;
+              from[y * cols + w] = (uint8_t)best;
+            }
+            int32_t* t = Ep; Ep = Ec; Ec = t;
           }
-          int32_t* t = Ep; Ep = Ec; Ec = t;
-        }
-        int seam = 0;
-        for (int w = 1; w < cols; ++w)
-          if (Ep[w] < Ep[seam]) seam = w;
-        for (int y = rows - 1; y >= 0; --y) {
-          for (int w = 0; w < seam; ++w) {
-            int uu[3] = {0, 0, 0};
-            uu[ax] = ((f.orient >> ax) & 1) ? g.T[ax] - 1 - w : w;
-            uu[ra] = y;
-            if (sa >= 0) uu[sa] = sl;
-            keep[idx3(uu[0], uu[1], uu[2], g.T)] = 1;
+          int sc = 0;
+          for (int w = 1; w < cols; ++w)
+            if (Ep[w] < Ep[sc]) sc = w;
+          for (int y = rows - 1; y >= 0; --y) {
+            for (int w = 0; w < sc; ++w) keep[seam_cell(g, f.orient, ax, ra, sa, sl, y, w)] = 1;
+            if (y > 0) sc = from[y * cols + sc];
           }
-          if (y > 0) seam = from[y * cols + seam];
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
   // paste the new side of every seam, keep hard data
   int8_t* sgw = a.sg + (long long)f.r * g.pcells;
-  const int8_t* hm = a.hdmap + (long long)f.r * g.pcells;
-  for (long long i = tid; i < g.wcells; i += kThreads) {
-    const int ux = (int)(i % g.T[0]), uy = (int)((i / g.T[0]) % g.T[1]), uz = (int)(i / ((long long)g.T[0] * g.T[1]));
-    const long long at = idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad);
-    if (hm[at] < 0 && !keep[i]) sgw[at] = P[i];
+  for (int i = tid; i < (int)g.wcells; i += kThreads) {
+    if (s_hd[i] >= 0 || keep[i]) continue;
+    int ux, uy, uz;
+    split3(i, g.T[0], g.T[1], ux, uy, uz);
+    sgw[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)] = P[i];
   }
 }
 
+}  // namespace
+
+namespace {
+// One kernel per (dimension, seam length rounded up to 16) keeps the register
+// dynamic programme at its real trip count.
+void launch_finalize(int ndim, int rows_max, int tree_level, unsigned blocks, size_t lds, hipStream_t st,
+                     const FinArgs& fa) {
+  const int r = rows_max <= 16 ? 16 : rows_max <= 32 ? 32 : rows_max <= 48 ? 48 : 64;
+#define CCW_FIN(ND, R, TJ) k_finalize<ND, R, TJ><<<blocks, kThreads, lds, st>>>(fa)
+#define CCW_FIN_R(ND, TJ)                 \
+  do {                                    \
+    if (r == 16) CCW_FIN(ND, 16, TJ);     \
+    else if (r == 32) CCW_FIN(ND, 32, TJ); \
+    else if (r == 48) CCW_FIN(ND, 48, TJ); \
+    else CCW_FIN(ND, 64, TJ);             \
+  } while (0)
+  if (ndim == 2) {
+    if (tree_level == 1) CCW_FIN_R(2, 1);
+    else if (tree_level == 2) CCW_FIN_R(2, 2);
+    else CCW_FIN_R(2, 0);
+  } else {
+    if (tree_level == 1) CCW_FIN_R(3, 1);
+    else if (tree_level == 2) CCW_FIN_R(3, 2);
+    else CCW_FIN_R(3, 0);
+  }
+#undef CCW_FIN_R
+#undef CCW_FIN
+}
 }  // namespace
 
 extern "C" int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p) {
@@ -985,19 +1256,11 @@ extern "C" int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p) {
   return P->ws_total;
 }
 
-extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
-                               const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
-                               void* workspace, int64_t workspace_bytes, void* stream) {
-  if (!p || !ti || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
-  if (n_hd < 0 || (n_hd > 0 && (!hd_real || !hd_pos || !hd_val)))
-    return fail(CCWSIM_ERR_INVALID_ARG, "hard data pointers");
-  Plan* P = nullptr;
-  CCW_TRY(get_plan(*p, &P));
-  if (!workspace || workspace_bytes < P->ws_total)
-    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)P->ws_total);
-  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+namespace {
+int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
+                     const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen, void* workspace,
+                     hipStream_t st) {
   const Geom& g = P->g;
-  hipStream_t st = as_stream(stream);
   unsigned char* ws = (unsigned char*)workspace;
   _Float16* Kh = (_Float16*)(ws + P->ws_kh);
   int32_t* Ki = (int32_t*)(ws + P->ws_ki);
@@ -1011,6 +1274,7 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   HdEnt* hdlist = (HdEnt*)(ws + P->ws_hdlist);
   int32_t* hdcnt = (int32_t*)(ws + P->ws_hdcnt);
   uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
+  uint64_t* rowmin = (uint64_t*)(ws + P->ws_rowmin);
   const int32_t* kbeta = (const int32_t*)(tbl + P->off_kbeta);
   const int32_t* nbt = (const int32_t*)(tbl + P->off_nbt);
   const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
@@ -1020,7 +1284,16 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   // TI transform and energy rows (depend on the TI only)
   {
     ProfScope ps(CCWSIM_KIND_DWT, st);
-    CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));
+    if (P->tree_level) {
+      const long long gc = (long long)g.G[0] * g.G[1] * g.G[2];
+      if (g.ndim == 2 && g.level == 1) k_dwt_tree<2, 1><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
+      else if (g.ndim == 2) k_dwt_tree<2, 2><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
+      else if (g.level == 1) k_dwt_tree<3, 1><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
+      else k_dwt_tree<3, 2><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
+      HIP_TRY(hipGetLastError());
+    } else {
+      CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));
+    }
   }
   if (p->score_mode == 0) {
     ProfScope ps(CCWSIM_KIND_ENERGY, st);
@@ -1060,6 +1333,7 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   sa.hdcnt = hdcnt;
   sa.ti = ti;
   sa.keys = keys;
+  sa.rowmin = rowmin;
   sa.seed = p->seed;
   sa.hdmax = (int)P->hdmax;
   sa.kpad = P->kpad;
@@ -1071,8 +1345,15 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   FinArgs fa = {};
   fa.g = g;
   fa.keys = keys;
+  fa.rowmin = rowmin;
+  fa.cand_cap = P->cand_cap;
+  fa.coef_lds = P->coef_lds;
+  fa.rows_max = P->rows_max;
+  fa.has_hd = n_hd > 0;
+  fa.dp_wave = P->dp_wave;
   fa.Ki = Ki;
   fa.det = det;
+  fa.tree = det;
   fa.sg = sg;
   fa.hdmap = hdmap;
   fa.chosen_log = chosen;
@@ -1089,7 +1370,7 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
     pa.filters = filters + s.fbegin;
     {
       ProfScope ps(CCWSIM_KIND_PREPARE, st);
-      k_prepare<<<(unsigned)s.fcount, kThreads, 0, st>>>(pa);
+      k_prepare<<<(unsigned)s.fcount, kThreads, P->prep_lds, st>>>(pa);
     }
     sa.filters = filters + s.fbegin;
     sa.tiles = tiles + s.tbegin;
@@ -1100,10 +1381,7 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
     fa.filters = filters + s.fbegin;
     {
       ProfScope ps(CCWSIM_KIND_FINALIZE, st);
-      if (g.ndim == 2)
-        k_finalize<2><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
-      else
-        k_finalize<3><<<(unsigned)s.fcount, kThreads, P->fin_lds, st>>>(fa);
+      launch_finalize(g.ndim, P->rows_max, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -1114,8 +1392,103 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }
+}  // namespace
+
+namespace {
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;   // most recent last
+bool g_graphs_on = true;
+constexpr size_t kMaxGraphs = 8;
+
+void drop_graphs() {
+  for (GraphEntry& e : g_graphs) (void)hipGraphExecDestroy(e.exec);
+  g_graphs.clear();
+}
+}  // namespace
+
+extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
+                               const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
+                               void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!p || !ti || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_hd < 0 || (n_hd > 0 && (!hd_real || !hd_pos || !hd_val)))
+    return fail(CCWSIM_ERR_INVALID_ARG, "hard data pointers");
+  Plan* P = nullptr;
+  CCW_TRY(get_plan(*p, &P));
+  if (!workspace || workspace_bytes < P->ws_total)
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)P->ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  bool prof;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof = g_prof_on;
+  }
+  if (prof || !g_graphs_on)
+    return enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, st);
+
+  // The launch sequence depends only on the parameters and the buffers, so it
+  // is captured once into a HIP graph and replayed on the caller's stream.
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::string key((const char*)p, sizeof *p);
+  const void* ptrs[8] = {ti, hd_real, hd_pos, hd_val, out, chosen, workspace, (const void*)(intptr_t)n_hd};
+  key.append((const char*)ptrs, sizeof ptrs);
+  key.append((const char*)&dev, sizeof dev);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size(); ++i) {
+    if (g_graphs[i].key == key) {
+      GraphEntry e = g_graphs[i];
+      g_graphs.erase(g_graphs.begin() + i);
+      g_graphs.push_back(e);
+      HIP_TRY(hipGraphLaunch(e.exec, st));
+      return CCWSIM_OK;
+    }
+  }
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(CCWSIM_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  const int rc = enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, cs);
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (rc != CCWSIM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(CCWSIM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(CCWSIM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  if (g_graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(g_graphs.front().exec);
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back({key, exec});
+  HIP_TRY(hipGraphLaunch(exec, st));
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_set_graphs(int on) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  g_graphs_on = on != 0;
+  if (!g_graphs_on) drop_graphs();
+  return CCWSIM_OK;
+}
 
 extern "C" void ccwsim_release_caches(void) {
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    drop_graphs();
+  }
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plans.clear();
 }

@@ -111,6 +111,16 @@ struct Geom {
   long long tcells, wcells, pcells;
 };
 
+// Split a linear index of an e0 x e1 x (..) box into (x, y, z) with 32-bit
+// divisions only.
+CCW_HD void split3(int i, int e0, int e1, int& x, int& y, int& z) {
+  const int e01 = e0 * e1;
+  z = i / e01;
+  const int r = i - z * e01;
+  y = r / e0;
+  x = r - y * e0;
+}
+
 CCW_HD long long idx3(int x, int y, int z, const int d[3]) {
   return (long long)x + (long long)d[0] * ((long long)y + (long long)d[1] * z);
 }

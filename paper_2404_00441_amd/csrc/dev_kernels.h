@@ -93,10 +93,9 @@ __device__ void idwt_window(const int32_t* __restrict__ approx, const int32_t* _
   const int tid = threadIdx.x, nth = blockDim.x;
   const int J = g.level;
   if (J == 0) {
-    for (long long u = tid; u < g.wcells; u += nth) {
-      const int ux = (int)(u % g.T[0]);
-      const int uy = (int)((u / g.T[0]) % g.T[1]);
-      const int uz = (int)(u / ((long long)g.T[0] * g.T[1]));
+    for (int u = tid; u < (int)g.wcells; u += nth) {
+      int ux, uy, uz;
+      split3(u, g.T[0], g.T[1], ux, uy, uz);
       P[u] = (int8_t)approx[idx3(c0x + ux, c0y + uy, c0z + uz, g.G)];
     }
     __syncthreads();
@@ -105,9 +104,10 @@ __device__ void idwt_window(const int32_t* __restrict__ approx, const int32_t* _
   int e[3] = {g.tc[0], g.tc[1], g.tc[2]};
   int o[3] = {c0x, c0y, c0z};
   {
-    const long long n = (long long)e[0] * e[1] * e[2];
-    for (long long i = tid; i < n; i += nth) {
-      const int x = (int)(i % e[0]), y = (int)((i / e[0]) % e[1]), z = (int)(i / ((long long)e[0] * e[1]));
+    const int n = e[0] * e[1] * e[2];
+    for (int i = tid; i < n; i += nth) {
+      int x, y, z;
+      split3(i, e[0], e[1], x, y, z);
       bufA[i] = approx[idx3(o[0] + x, o[1] + y, o[2] + z, g.G)];
     }
   }
@@ -118,10 +118,11 @@ __device__ void idwt_window(const int32_t* __restrict__ approx, const int32_t* _
   for (int j = J; j >= 1; --j) {
     const int* Gd = g.Gj[j];
     const long long gcells = (long long)Gd[0] * Gd[1] * Gd[2];
-    const long long rc = (long long)e[0] * e[1] * e[2];
+    const int rc = e[0] * e[1] * e[2];
     const int en[3] = {e[0] * 2, e[1] * 2, ND == 3 ? e[2] * 2 : 1};
-    for (long long i = tid; i < rc; i += nth) {
-      const int x = (int)(i % e[0]), y = (int)((i / e[0]) % e[1]), z = (int)(i / ((long long)e[0] * e[1]));
+    for (int i = tid; i < rc; i += nth) {
+      int x, y, z;
+      split3(i, e[0], e[1], x, y, z);
       int c[NC];
       c[0] = cur[i];
       const long long gi = idx3(o[0] + x, o[1] + y, o[2] + z, Gd);
@@ -151,6 +152,173 @@ __device__ void idwt_window(const int32_t* __restrict__ approx, const int32_t* _
       o[a] *= 2;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Block-subtree layout of the Haar pyramid.  The transform of one level-J
+// block touches nothing outside it, so its 2^(ND*J) coefficients can be
+// stored together: [approximation][level-J details][level-(J-1) details of
+// the 2^ND children] ... [level-1 details], each level's nodes x-fastest,
+// 2^ND - 1 sub-bands per node.  It is a permutation of the planar layout
+// (the transform is orthogonal), and rebuilding a block needs one
+// contiguous read and no cooperation between threads.
+// ---------------------------------------------------------------------------
+template <int ND, int J>
+struct HaarTree {
+  static constexpr int NC = 1 << ND;
+  static constexpr int B = 1 << (ND * J);
+  // offset of the level-j details (1 <= j <= J)
+  static constexpr int off(int j) {
+    int o = 1, n = 1;
+    for (int jj = J; jj > j; --jj) {
+      o += (NC - 1) * n;
+      n *= NC;
+    }
+    return o;
+  }
+  // node index of child delta of node (x, y, z) on a grid of nj nodes per axis
+  static constexpr int child(int x, int y, int z, int delta, int nj) {
+    const int cx = 2 * x + (delta & 1), cy = 2 * y + ((delta >> 1) & 1);
+    const int cz = ND == 3 ? 2 * z + ((delta >> 2) & 1) : 0;
+    return cx + 2 * nj * (cy + 2 * nj * cz);
+  }
+};
+
+// Forward transform of one level-J block: v holds the B fine cells (x
+// fastest), out receives the block-subtree layout.
+template <int ND, int J, int BB = (1 << (ND * J))>
+__device__ __forceinline__ void haar_tree_forward(const int (&v)[BB], int (&out)[BB]) {
+  using T = HaarTree<ND, J>;
+  constexpr int NC = T::NC;
+  int cur[T::B];
+#pragma unroll
+  for (int i = 0; i < T::B; ++i) cur[i] = v[i];
+#pragma unroll
+  for (int j = 1; j <= J; ++j) {
+    const int nj = 1 << (J - j);                 // nodes per axis at level j
+    const int nn = ND == 3 ? nj * nj * nj : nj * nj;
+    int nxt[T::B];
+#pragma unroll
+    for (int n = 0; n < nn; ++n) {
+      const int x = n % nj, y = (n / nj) % nj, z = ND == 3 ? n / (nj * nj) : 0;
+      int c[NC];
+#pragma unroll
+      for (int d = 0; d < NC; ++d) c[d] = cur[T::child(x, y, z, d, nj)];
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+#pragma unroll
+        for (int d = 0; d < NC; ++d) {
+          if (!(d & (1 << a))) {
+            const int e = c[d], o = c[d | (1 << a)];
+            c[d] = e + o;
+            c[d | (1 << a)] = e - o;
+          }
+        }
+      }
+      nxt[n] = c[0];
+#pragma unroll
+      for (int q = 1; q < NC; ++q) out[T::off(j) + n * (NC - 1) + q - 1] = c[q];
+    }
+#pragma unroll
+    for (int n = 0; n < nn; ++n) cur[n] = nxt[n];
+  }
+  out[0] = cur[0];
+}
+
+// Inverse of haar_tree_forward: rebuilds the B fine cells of one block.
+template <int ND, int J, int BB = (1 << (ND * J))>
+__device__ __forceinline__ void haar_tree_inverse(const int (&t)[BB], int (&v)[BB]) {
+  using T = HaarTree<ND, J>;
+  constexpr int NC = T::NC;
+  int cur[T::B];
+  cur[0] = t[0];
+#pragma unroll
+  for (int j = J; j >= 1; --j) {
+    const int nj = 1 << (J - j);
+    const int nn = ND == 3 ? nj * nj * nj : nj * nj;
+    int nxt[T::B];
+#pragma unroll
+    for (int n = 0; n < nn; ++n) {
+      const int x = n % nj, y = (n / nj) % nj, z = ND == 3 ? n / (nj * nj) : 0;
+      int c[NC];
+      c[0] = cur[n];
+#pragma unroll
+      for (int q = 1; q < NC; ++q) c[q] = t[T::off(j) + n * (NC - 1) + q - 1];
+#pragma unroll
+      for (int d = 0; d < NC; ++d) {
+        int acc = 0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc += (__popc(q & d) & 1) ? -c[q] : c[q];
+        nxt[T::child(x, y, z, d, nj)] = acc >> ND;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < nn * NC; ++i) cur[i] = nxt[i];
+  }
+#pragma unroll
+  for (int i = 0; i < T::B; ++i) v[i] = cur[i];
+}
+
+// One thread per level-J block: fine cells (edge-replicated) -> subtree
+// layout, plus the approximation in int32 and fp16.
+template <int ND, int J>
+__global__ __launch_bounds__(kThreads) void k_dwt_tree(const int8_t* __restrict__ ti, int32_t* __restrict__ tree,
+                                                       int32_t* __restrict__ approx, _Float16* __restrict__ approx_h,
+                                                       Geom g) {
+  using T = HaarTree<ND, J>;
+  const long long cells = (long long)g.G[0] * g.G[1] * g.G[2];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= cells) return;
+  int bx, by, bz;
+  split3((int)id, g.G[0], g.G[1], bx, by, bz);
+  constexpr int b = 1 << J;
+  int v[T::B], out[T::B];
+#pragma unroll
+  for (int i = 0; i < T::B; ++i) {
+    const int lx = i % b, ly = (i / b) % b, lz = ND == 3 ? i / (b * b) : 0;
+    const int x = min(b * bx + lx, g.ti[0] - 1), y = min(b * by + ly, g.ti[1] - 1);
+    const int z = ND == 3 ? min(b * bz + lz, g.ti[2] - 1) : 0;
+    v[i] = ti[idx3(x, y, z, g.ti)];
+  }
+  haar_tree_forward<ND, J>(v, out);
+  int4* dst = (int4*)(tree + id * T::B);
+#pragma unroll
+  for (int i = 0; i < T::B / 4; ++i) dst[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+  approx[id] = out[0];
+  approx_h[id] = (_Float16)(float)out[0];
+}
+
+// Rebuild the template window at block origin c0 from the subtree layout:
+// one thread per level-J block of the window.
+template <int ND, int J>
+__device__ __forceinline__ void idwt_window_tree(const int32_t* __restrict__ tree, const Geom& g, int c0x, int c0y,
+                                                 int c0z, int8_t* P) {
+  using T = HaarTree<ND, J>;
+  constexpr int b = 1 << J;
+  const int nblk = g.tc[0] * g.tc[1] * g.tc[2];
+  for (int t = threadIdx.x; t < nblk; t += kThreads) {
+    int bx, by, bz;
+    split3(t, g.tc[0], g.tc[1], bx, by, bz);
+    const long long gb = idx3(c0x + bx, c0y + by, c0z + bz, g.G);
+    const int4* src = (const int4*)(tree + gb * T::B);
+    int tv[T::B], v[T::B];
+#pragma unroll
+    for (int i = 0; i < T::B / 4; ++i) {
+      const int4 q = src[i];
+      tv[4 * i] = q.x;
+      tv[4 * i + 1] = q.y;
+      tv[4 * i + 2] = q.z;
+      tv[4 * i + 3] = q.w;
+    }
+    haar_tree_inverse<ND, J>(tv, v);
+#pragma unroll
+    for (int i = 0; i < T::B; ++i) {
+      const int lx = i % b, ly = (i / b) % b, lz = ND == 3 ? i / (b * b) : 0;
+      const int ux = b * bx + lx, uy = b * by + ly, uz = ND == 3 ? b * bz + lz : 0;
+      if (ux < g.T[0] && uy < g.T[1] && uz < g.T[2]) P[idx3(ux, uy, uz, g.T)] = (int8_t)v[i];
+    }
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -189,6 +357,128 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
     v = o < v ? o : v;
   }
   return v;
+}
+
+// k smallest of n distinct keys held in LDS, by rank: each key counts the
+// keys below it and, if its rank is under k, writes itself to out[rank].
+// Cost n^2 / 256 comparisons per thread, so only for short lists.
+__device__ __forceinline__ void block_rank_select(const uint64_t* v, int n, int k, uint64_t* out) {
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const uint64_t x = v[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += v[j] < x ? 1 : 0;
+    if (rank < k) out[rank] = x;
+  }
+  __syncthreads();
+}
+
+// Number of coefficients idwt_window_lds stages: the level-J block range and
+// the detail sub-bands of every level over the same window.
+__host__ __device__ inline long long idwt_coef_count(const Geom& g) {
+  long long e = 1;
+  for (int a = 0; a < g.ndim; ++a) e *= g.tc[a];
+  const long long nsub = (1 << g.ndim) - 1;
+  long long total = e;  // level-J approximation
+  for (int j = g.level; j >= 1; --j) {
+    total += nsub * e;
+    e <<= g.ndim;
+  }
+  return total;
+}
+
+// Same reconstruction as idwt_window, but every coefficient the window needs
+// is first loaded into `coef` (LDS) with all loads in flight at once, so the
+// whole pyramid costs one memory round trip.
+template <int ND>
+__device__ void idwt_window_lds(const int32_t* __restrict__ approx, const int32_t* __restrict__ det,
+                                const Geom& g, int c0x, int c0y, int c0z, int32_t* coef, int32_t* bufA,
+                                int32_t* bufB, int8_t* P) {
+  const int tid = threadIdx.x;
+  const int J = g.level;
+  constexpr int NC = 1 << ND;
+  // segment table: level-J approximation, then details of level J, J-1, .., 1
+  {
+    constexpr int U = 8;
+    const int total = (int)idwt_coef_count(g);
+    for (int base = tid; base < total; base += kThreads * U) {
+      int32_t v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        int i = base + q * kThreads;
+        v[q] = 0;
+        if (i >= total) continue;
+        int e[3] = {g.tc[0], g.tc[1], g.tc[2]};
+        int o[3] = {c0x, c0y, c0z};
+        int cells = e[0] * e[1] * e[2];
+        if (i < cells) {
+          int x, y, z;
+          split3(i, e[0], e[1], x, y, z);
+          v[q] = approx[idx3(o[0] + x, o[1] + y, o[2] + z, g.G)];
+          continue;
+        }
+        i -= cells;
+        for (int j = J; j >= 1; --j) {
+          if (i < (NC - 1) * cells) {
+            const int s = i / cells + 1;
+            const int r = i - (s - 1) * cells;
+            int x, y, z;
+            split3(r, e[0], e[1], x, y, z);
+            const int* Gd = g.Gj[j];
+            const long long gcells = (long long)Gd[0] * Gd[1] * Gd[2];
+            v[q] = det[g.det_off[j] + (long long)(s - 1) * gcells + idx3(o[0] + x, o[1] + y, o[2] + z, Gd)];
+            break;
+          }
+          i -= (NC - 1) * cells;
+          for (int a = 0; a < ND; ++a) {
+            e[a] *= 2;
+            o[a] *= 2;
+          }
+          cells <<= ND;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        if (i < total) coef[i] = v[q];
+      }
+    }
+  }
+  __syncthreads();
+  int e[3] = {g.tc[0], g.tc[1], g.tc[2]};
+  const int32_t* cur = coef;
+  int doff = e[0] * e[1] * e[2];   // details of level J start here
+  int32_t* nxt = bufA;
+  for (int j = J; j >= 1; --j) {
+    const int rc = e[0] * e[1] * e[2];
+    const int en[3] = {e[0] * 2, e[1] * 2, ND == 3 ? e[2] * 2 : 1};
+    for (int i = tid; i < rc; i += kThreads) {
+      int x, y, z;
+      split3(i, e[0], e[1], x, y, z);
+      int c[NC];
+      c[0] = cur[i];
+#pragma unroll
+      for (int s = 1; s < NC; ++s) c[s] = coef[doff + (s - 1) * rc + i];
+#pragma unroll
+      for (int d = 0; d < NC; ++d) {
+        int acc = 0;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) acc += (__popc(s & d) & 1) ? -c[s] : c[s];
+        const int val = acc >> ND;
+        const int fx = 2 * x + (d & 1), fy = 2 * y + ((d >> 1) & 1);
+        const int fz = ND == 3 ? 2 * z + ((d >> 2) & 1) : 0;
+        if (j > 1) {
+          nxt[idx3(fx, fy, fz, en)] = val;
+        } else if (fx < g.T[0] && fy < g.T[1] && fz < g.T[2]) {
+          P[idx3(fx, fy, fz, g.T)] = (int8_t)val;
+        }
+      }
+    }
+    __syncthreads();
+    doff += (NC - 1) * rc;
+    cur = nxt;
+    nxt = (nxt == bufA) ? bufB : bufA;
+    for (int a = 0; a < ND; ++a) e[a] *= 2;
+  }
 }
 
 struct TopkShared {

@@ -53,6 +53,7 @@ struct ScanArgs {
   const int32_t* hdcnt;        // [slot]
   const int8_t* ti;
   uint64_t* keys;              // simulate: [slot][ncand]
+  uint64_t* rowmin;            // simulate: [slot][candidate rows] smallest key of each row
   int32_t* scores;             // standalone: [filter][ncand], holds E on entry
   uint64_t seed;
   int hdmax;
@@ -87,11 +88,31 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   int* s_off = (int*)(smem + strip_bytes);
   _Float16* s_B = (_Float16*)(smem + strip_bytes + kpad * 4);
   const int bstride = kpad + 8;   // halves per filter row (keeps 16 B alignment)
+  __shared__ unsigned long long s_rowmin[kFiltersPerTile];
+  if (tid < kFiltersPerTile) s_rowmin[tid] = ~0ull;
 
-  for (int i = tid; i < nrows * W; i += kThreads) {
-    const int rr = i / W, x = i - rr * W;
-    const int by = rr % g.tc[1], bz = rr / g.tc[1];
-    s_strip[i] = x < g.G[0] ? a.Kh[idx3(x, cy + by, cz + bz, g.G)] : (_Float16)0.0f;
+  // K-grid strip: issue every load of a thread before storing any of them
+  {
+    constexpr int U = 8;
+    const int n = nrows * W;
+    for (int base = tid; base < n; base += kThreads * U) {
+      _Float16 v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        v[q] = (_Float16)0.0f;
+        if (i < n) {
+          const int rr = i / W, x = i - rr * W;
+          const int by = rr % g.tc[1], bz = rr / g.tc[1];
+          if (x < g.G[0]) v[q] = a.Kh[idx3(x, cy + by, cz + bz, g.G)];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        if (i < n) s_strip[i] = v[q];
+      }
+    }
   }
   for (int k = tid; k < kpad; k += kThreads) {
     int beta;
@@ -104,9 +125,12 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     }
     s_off[k] = off;
   }
-  for (int i = tid; i < kFiltersPerTile * kpad; i += kThreads) {
-    const int j = i / kpad, k = i - j * kpad;
-    s_B[j * bstride + k] = j < t.count ? a.mbuf[(long long)(t.first + j) * kKMax + k] : (_Float16)0.0f;
+  // data events, 8 halves (16 B) per load
+  for (int i = tid; i < kFiltersPerTile * (kpad / 8); i += kThreads) {
+    const int jj = i / (kpad / 8), k8 = (i - jj * (kpad / 8)) * 8;
+    half8_t v = {};
+    if (jj < t.count) v = *(const half8_t*)(a.mbuf + (long long)(t.first + jj) * kKMax + k8);
+    *(half8_t*)(s_B + jj * bstride + k8) = v;
   }
   __syncthreads();
 
@@ -126,6 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   const int nchunks = (g.cand[0] + 31) / 32;
   const long long rowbase = (long long)g.cand[0] * row;
 
+  uint64_t lane_min = ~0ull;
   for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
     float16_t acc = {};
     const int cbase = ch * 32 + j;
@@ -137,6 +162,26 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
       acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
     }
     if (!fvalid) continue;
+    // hard-data mismatch of the 16 candidates of this lane: per datum, one
+    // entry load and 16 independent TI gathers
+    unsigned mis[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) mis[v] = 0;
+    for (int h = 0; h < nhd; ++h) {
+      const HdEnt e = a.hdlist[(long long)slot * a.hdmax + h];
+      const int fy = g.b[1] * cy + e.u[1], fz = g.b[2] * cz + e.u[2];
+      if (fy < 0 || fz < 0 || fy >= g.ti[1] || fz >= g.ti[2]) continue;
+      const int8_t* trow = a.ti + ((long long)fz * g.ti[1] + fy) * g.ti[0];
+      int8_t tv[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int fx = g.b[0] * cx + e.u[0];
+        tv[v] = (fx >= 0 && fx < g.ti[0] && cx < g.cand[0]) ? trow[fx] : (int8_t)e.v;
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mis[v] += tv[v] != e.v;
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -150,16 +195,21 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         continue;
       }
       const int S = (a.score_mode == 0) ? a.energy[(long long)f.shape * g.ncand + idx] - (C << shift) : -C;
-      unsigned mis = 0;
-      for (int h = 0; h < nhd; ++h) {
-        const HdEnt e = a.hdlist[(long long)slot * a.hdmax + h];
-        const int fx = g.b[0] * cx + e.u[0], fy = g.b[1] * cy + e.u[1], fz = g.b[2] * cz + e.u[2];
-        if (fx >= 0 && fy >= 0 && fz >= 0 && fx < g.ti[0] && fy < g.ti[1] && fz < g.ti[2])
-          mis += a.ti[idx3(fx, fy, fz, g.ti)] != e.v;
-      }
-      a.keys[(long long)slot * g.ncand + idx] = make_key(mis, S, tie_perm((uint32_t)idx, tkey));
+      const uint64_t key = make_key(mis[v], S, tie_perm((uint32_t)idx, tkey));
+      a.keys[(long long)slot * g.ncand + idx] = key;
+      lane_min = key < lane_min ? key : lane_min;
     }
   }
+  if (a.standalone) return;
+  // smallest key of this candidate row, per filter (lanes j and j + 32 hold
+  // the same filter; the four wavefronts meet in LDS)
+  {
+    const uint64_t other = shfl_xor64(lane_min, 32);
+    lane_min = other < lane_min ? other : lane_min;
+    if (lane < 32 && fvalid) atomicMin(&s_rowmin[j], (unsigned long long)lane_min);
+  }
+  __syncthreads();
+  if (tid < t.count) a.rowmin[(long long)(t.first + tid) * (g.cand[1] * g.cand[2]) + row] = s_rowmin[tid];
 }
 
 // Energy term E(c) = sum_beta n_beta K[c + beta]^2 for each shape (rows of

@@ -326,3 +326,28 @@ def test_simulate_rejects_bad_workspace(cc):
     st = cc.load().ccwsim_simulate(ctypes.byref(q), ctypes.c_void_p(_t(ti).data_ptr()), 0, None, None, None,
                                    ctypes.c_void_p(out.data_ptr()), None, None, 0, None)
     assert st == 3
+
+
+def test_graph_replays_match_eager(cc, orc):
+    # the captured launch sequence, replayed several times with unrelated
+    # eager work and synchronisations in between, must give the eager result
+    import torch
+    p, ti, hd = wl.make("c4_batched", scale=0.4, n_real=4)
+    nd = len(p["ti"])
+    sim = cc.Simulator(p)
+    ti_d = _t(ti)
+    hd_d = cc.hd_to_device(hd, nd)
+    cc.set_graphs(False)
+    eager = sim.run(ti_d, hd_d).cpu().numpy()
+    cc.set_graphs(True)
+    out = torch.empty((p["n_real"],) + tuple(p["grid"][::-1]), dtype=torch.int8, device="cuda")
+    for rep in range(4):
+        out.fill_(-5)
+        junk = torch.randn(256, 256, device="cuda") @ torch.randn(256, 256, device="cuda")
+        torch.cuda.synchronize()
+        sim.run(ti_d, hd_d, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), f"replay {rep}"
+        del junk
+    oout, _ = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(eager, oout)
