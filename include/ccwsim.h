@@ -88,7 +88,9 @@ typedef struct {
                            Haar on integer codes within the limits checked
                            by ccwsim_simulate)                            */
   int32_t shortlist;    /* reserved, must be 0                            */
-  int32_t reserved[4];  /* must be 0                                      */
+  int32_t max_hard_data;/* most hard data a call passes (sizes the
+                           workspace); 0 = unconditional only            */
+  int32_t reserved[3];  /* must be 0                                      */
 } ccwsim_params;
 
 /* ---- A1: training-image transform (Sec. 3.1; Algorithm 1, DWT of TI) ---

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("path_mode", ctypes.c_int32), ("score_mode", ctypes.c_int32),
         ("nc_margin", ctypes.c_int32 * 3), ("cut", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("shortlist", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("max_hard_data", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -152,6 +152,7 @@ def params_of(p: dict) -> Params:
     q.cut = p.get("cut", 1)
     q.precision = p.get("precision", 0)
     q.shortlist = 0
+    q.max_hard_data = int(p.get("max_hard_data", 0))
     return q
 
 

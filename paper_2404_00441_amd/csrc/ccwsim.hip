@@ -466,20 +466,21 @@ struct Plan {
   int n_orient = 0, n_shapes = 0, kpad = 0, W = 0;
   int max_slots = 0, nsteps_raster = 0;
   long long patches = 0, or_blocks = 0;
-  long long hdmax = 0;
+  long long hd_cap = 0;               // hard-data entries of all virtual templates
+  int nfilters = 0;
   std::vector<StepRange> steps;
   // host tables, uploaded on every call (pinned)
   size_t tbl_bytes = 0;
-  unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles
-  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0;
+  unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles | npred | succ_off | succ
+  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_npred = 0, off_succoff = 0, off_succ = 0;
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
-            ws_hdmap = 0, ws_mbuf = 0, ws_hdlist = 0, ws_hdcnt = 0, ws_keys = 0, ws_rowmin = 0, ws_total = 0;
+            ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
+            ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
   int tree_level = 0;   // 1 or 2: block-subtree coefficients; 0: planar details
   int dp_stride = 0, dp_batch = 0, rows_max = 0, dp_wave = 0;
-  size_t prep_lds = 0;
   ~Plan() {
     if (tbl) (void)hipHostFree(tbl);
   }
@@ -528,8 +529,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (p.cut != 0 && p.cut != 1) return fail(CCWSIM_ERR_INVALID_ARG, "cut");
   if (p.precision != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
   if (p.shortlist != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist %d", p.shortlist);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (p.reserved[i]) return fail(CCWSIM_ERR_INVALID_ARG, "reserved fields must be 0");
+  if (p.max_hard_data < 0) return fail(CCWSIM_ERR_INVALID_ARG, "max_hard_data must be >= 0");
   const int nd = g.ndim;
   P.n_orient = 1 << nd;
   P.n_shapes = P.n_orient << nd;
@@ -633,7 +635,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     for (size_t i = 0; i < lst.size();) {
       size_t e = i;
       while (e < lst.size() && lst[e].orient == lst[i].orient && (int)(e - i) < kFiltersPerTile) ++e;
-      TileDev t = {(int)i, (int)(e - i), lst[i].orient, 0};
+      uint32_t zm = 0;
+      for (size_t q = i; q < e; ++q) zm |= (lst[q].bandmask == 0 ? 1u : 0u) << (q - i);
+      TileDev t = {(int)i, (int)(e - i), lst[i].orient, zm};
       tiles.push_back(t);
       i = e;
     }
@@ -641,6 +645,60 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     filters.insert(filters.end(), lst.begin(), lst.end());
     P.max_slots = std::max(P.max_slots, sr.fcount);
     P.steps.push_back(sr);
+  }
+
+  // Overlapping predecessors / successors of every patch.  A patch's overlap
+  // cells are final once every earlier patch whose window overlaps it has
+  // pasted; the last of them computes the patch's data event.
+  P.nfilters = (int)filters.size();
+  std::vector<int32_t> npred(filters.size(), 0), succ_off(filters.size() + 1, 0), succ;
+  {
+    const long long latc = (long long)g.lat[0] * g.lat[1] * g.lat[2];
+    std::vector<int32_t> at((size_t)p.n_real * latc, -1);
+    auto lat_of = [&](const FilterDev& f, int li[3]) {
+      for (int a = 0; a < 3; ++a) li[a] = f.org[a] / g.stride[a];
+    };
+    for (size_t i = 0; i < filters.size(); ++i) {
+      int li[3];
+      lat_of(filters[i], li);
+      at[(size_t)filters[i].r * latc + ((long long)li[2] * g.lat[1] + li[1]) * g.lat[0] + li[0]] = (int32_t)i;
+    }
+    int reach[3];
+    for (int a = 0; a < 3; ++a) reach[a] = a < nd ? (g.T[a] - 1) / g.stride[a] : 0;  // |d| * s < T
+    std::vector<std::vector<int32_t>> sl(filters.size());
+    for (size_t i = 0; i < filters.size(); ++i) {
+      int li[3];
+      lat_of(filters[i], li);
+      for (int dz = -reach[2]; dz <= reach[2]; ++dz)
+        for (int dy = -reach[1]; dy <= reach[1]; ++dy)
+          for (int dx = -reach[0]; dx <= reach[0]; ++dx) {
+            if (!dx && !dy && !dz) continue;
+            const int n[3] = {li[0] + dx, li[1] + dy, li[2] + dz};
+            bool in = true;
+            for (int a = 0; a < 3; ++a) in = in && n[a] >= 0 && n[a] < g.lat[a];
+            if (!in) continue;
+            const int32_t j = at[(size_t)filters[i].r * latc + ((long long)n[2] * g.lat[1] + n[1]) * g.lat[0] + n[0]];
+            if (filters[j].step < filters[i].step) {
+              npred[i] += 1;
+              sl[j].push_back((int32_t)i);
+            }
+          }
+    }
+    for (size_t i = 0; i < filters.size(); ++i) {
+      if (sl[i].size() > 64) return fail(CCWSIM_ERR_UNSUPPORTED, "a patch overlaps more than 64 later patches");
+      succ_off[i + 1] = succ_off[i] + (int32_t)sl[i].size();
+      filters[i].succ0 = succ_off[i];
+      filters[i].nsucc = (int32_t)sl[i].size();
+    }
+    for (size_t i = 0; i < filters.size(); ++i)
+      for (int32_t q : sl[i]) {
+        succ.push_back(q);
+        succ.push_back(npred[q]);
+      }
+    if (succ.empty()) {
+      succ.push_back(-1);
+      succ.push_back(0);
+    }
   }
 
   // energy rows: known-cell count per block for each (orient, bandmask)
@@ -665,18 +723,25 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.off_nbt = align256(kbeta.size() * 4);
   P.off_filters = P.off_nbt + align256(nbt.size() * 4);
   P.off_tiles = P.off_filters + align256(filters.size() * sizeof(FilterDev));
-  P.tbl_bytes = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
+  P.off_npred = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
+  P.off_succoff = P.off_npred + align256(npred.size() * 4);
+  P.off_succ = P.off_succoff + align256(succ_off.size() * 4);
+  P.tbl_bytes = P.off_succ + align256(succ.size() * 4);
   if (hipHostMalloc((void**)&P.tbl, P.tbl_bytes, hipHostMallocDefault) != hipSuccess)
     return fail(CCWSIM_ERR_HIP, "hipHostMalloc of %zu bytes failed", P.tbl_bytes);
   memcpy(P.tbl + P.off_kbeta, kbeta.data(), kbeta.size() * 4);
   memcpy(P.tbl + P.off_nbt, nbt.data(), nbt.size() * 4);
   memcpy(P.tbl + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
   memcpy(P.tbl + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
+  memcpy(P.tbl + P.off_npred, npred.data(), npred.size() * 4);
+  memcpy(P.tbl + P.off_succoff, succ_off.data(), succ_off.size() * 4);
+  memcpy(P.tbl + P.off_succ, succ.data(), succ.size() * 4);
 
-  // hard data: a virtual template holds at most its own cell count
-  long long vcells = 1;
-  for (int a = 0; a < 3; ++a) vcells *= (long long)g.T[a] + g.margin[a];
-  P.hdmax = vcells;
+  // hard data: a grid cell lies in the virtual templates of at most
+  // prod ceil((T + margin) / stride) patches of its realization
+  long long per_cell = 1;
+  for (int a = 0; a < nd; ++a) per_cell *= (g.T[a] + g.margin[a] + g.stride[a] - 1) / g.stride[a];
+  P.hd_cap = (long long)p.max_hard_data * per_cell;
 
   // workspace
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
@@ -691,9 +756,10 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_tbl = o;       o += align256((long long)P.tbl_bytes);
   P.ws_sg = o;        o += align256((long long)p.n_real * g.pcells);
   P.ws_hdmap = o;     o += align256((long long)p.n_real * g.pcells);
-  P.ws_mbuf = o;      o += align256((long long)P.max_slots * kKMax * 2);
-  P.ws_hdlist = o;    o += align256((long long)P.max_slots * P.hdmax * (long long)sizeof(HdEnt));
-  P.ws_hdcnt = o;     o += align256((long long)P.max_slots * 4);
+  P.ws_mbuf = o;      o += align256((long long)P.nfilters * kKMax * 2);
+  P.ws_predcnt = o;   o += align256((long long)P.nfilters * 4);
+  P.ws_hdoff = o;     o += align256((long long)(P.nfilters + 1) * 4);
+  P.ws_hdent = o;     o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdEnt));
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
   P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
   P.ws_total = o;
@@ -723,11 +789,11 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   }
   if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
     return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
-  P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride;
+  P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride + (size_t)((g.tcells * 4 + 15) & ~15ll);
+  if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
   // the coefficient staging area aliases the key list and the cut scratch
   const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
   P.coef_lds = !P.tree_level && g.level > 0 && P.cand_cap > 0 && idwt_coef_count(g) * 4 <= alias_bytes;
-  P.prep_lds = (size_t)wpad;
   return CCWSIM_OK;
 }
 
@@ -774,21 +840,7 @@ __global__ void k_crop(const int8_t* __restrict__ sg, int8_t* __restrict__ out, 
   out[id] = sg[r * g.pcells + idx3(x, y, z, g.pad)];
 }
 
-// ---- data event of each active patch (Algorithm 1: extract OR, DWT of OR) --
-struct PrepArgs {
-  Geom g;
-  const FilterDev* filters;   // of this step
-  const int32_t* kbeta;
-  const int8_t* sg;
-  const int8_t* hdmap;
-  _Float16* mbuf;
-  HdEnt* hdlist;
-  int32_t* hdcnt;
-  long long hdmax;
-  int kpad;
-  int has_hd;
-};
-
+// ---- data events (Algorithm 1: extract the overlap, its level-J DWT) ------
 __device__ __forceinline__ bool dev_in_band(const Geom& g, int orient, int bandmask, int ux, int uy, int uz) {
   const int u[3] = {ux, uy, uz};
 #pragma unroll
@@ -858,31 +910,9 @@ __device__ __forceinline__ void load_windows(int8_t* d0, const int8_t* __restric
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_prepare(PrepArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const Geom& g = a.g;
-  const int slot = blockIdx.x;
-  const FilterDev f = a.filters[slot];
-  int8_t* s_win = (int8_t*)smem;
-  load_window(s_win, a.sg + (long long)f.r * g.pcells, f.org, g);
-  __syncthreads();
-  for (int k = threadIdx.x; k < a.kpad; k += kThreads) {
-    const int beta = a.kbeta[f.orient * kKMax + k];
-    int m = 0;
-    if (beta >= 0 && f.bandmask) {
-      const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
-      for (int uz = bz * g.b[2]; uz < min((bz + 1) * g.b[2], g.T[2]); ++uz)
-        for (int uy = by * g.b[1]; uy < min((by + 1) * g.b[1], g.T[1]); ++uy)
-          for (int ux = bx * g.b[0]; ux < min((bx + 1) * g.b[0], g.T[0]); ++ux)
-            if (dev_in_band(g, f.orient, f.bandmask, ux, uy, uz)) m += s_win[idx3(ux, uy, uz, g.T)];
-    }
-    a.mbuf[(long long)slot * kKMax + k] = (_Float16)(float)m;
-  }
-  if (!a.has_hd) return;
-  __shared__ unsigned s_cnt;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  int lo[3], ext[3];
+// Virtual template of patch f (template extended by the margin on the
+// sides not yet simulated), clipped to the padded grid: origin lo, extent ext.
+__device__ __forceinline__ int vbox(const Geom& g, const FilterDev& f, int lo[3], int ext[3]) {
   for (int d = 0; d < 3; ++d) {
     int l = 0, h = g.T[d];
     if (d < g.ndim) {
@@ -894,46 +924,91 @@ __global__ __launch_bounds__(kThreads) void k_prepare(PrepArgs a) {
     lo[d] = l;
     ext[d] = max(0, h - l);
   }
-  const int vc = ext[0] * ext[1] * ext[2];
-  const int8_t* hm = a.hdmap + (long long)f.r * g.pcells;
-  constexpr int U = 8;
-  for (int base = threadIdx.x; base < vc; base += kThreads * U) {
-    int8_t v[U];
-    int uu[U][3];
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int i = base + q * kThreads;
-      v[q] = -1;
-      uu[q][0] = uu[q][1] = uu[q][2] = 0;
-      if (i < vc) {
-        split3(i, ext[0], ext[1], uu[q][0], uu[q][1], uu[q][2]);
-        for (int d = 0; d < 3; ++d) uu[q][d] += lo[d];
-        v[q] = hm[idx3(f.org[0] + uu[q][0], f.org[1] + uu[q][1], f.org[2] + uu[q][2], g.pad)];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      if (v[q] >= 0) {
-        const unsigned p = atomicAdd(&s_cnt, 1u);
-        if (p < a.hdmax) {
-          HdEnt e;
-          e.u[0] = (int16_t)uu[q][0];
-          e.u[1] = (int16_t)uu[q][1];
-          e.u[2] = (int16_t)uu[q][2];
-          e.v = v[q];
-          a.hdlist[(long long)slot * a.hdmax + p] = e;
-        }
+  return ext[0] * ext[1] * ext[2];
+}
+
+// Hard data inside each patch's virtual template, binned once per call
+// (they do not change during the simulation).  Pass 1 counts, an exclusive
+// scan turns counts into offsets, pass 2 writes the entries.
+template <bool FILL>
+__global__ __launch_bounds__(kThreads) void k_hd_bin(Geom g, const FilterDev* __restrict__ filters,
+                                                     const int8_t* __restrict__ hdmap, int32_t* __restrict__ hd_off,
+                                                     HdEnt* __restrict__ hd_ent, long long cap) {
+  __shared__ unsigned s_cnt;
+  const int fg = blockIdx.x;
+  const FilterDev f = filters[fg];
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int lo[3], ext[3];
+  const int vc = vbox(g, f, lo, ext);
+  const int8_t* hm = hdmap + (long long)f.r * g.pcells;
+  const long long base_off = FILL ? hd_off[fg] : 0;
+  for (int i = threadIdx.x; i < vc; i += kThreads) {
+    int ux, uy, uz;
+    split3(i, ext[0], ext[1], ux, uy, uz);
+    ux += lo[0];
+    uy += lo[1];
+    uz += lo[2];
+    const int8_t v = hm[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)];
+    if (v >= 0) {
+      const unsigned p = atomicAdd(&s_cnt, 1u);
+      if (FILL && base_off + p < cap) {
+        HdEnt e;
+        e.u[0] = (int16_t)ux;
+        e.u[1] = (int16_t)uy;
+        e.u[2] = (int16_t)uz;
+        e.v = v;
+        hd_ent[base_off + p] = e;
       }
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) a.hdcnt[slot] = (int32_t)min((long long)s_cnt, a.hdmax);
+  if (!FILL && threadIdx.x == 0) hd_off[fg] = (int32_t)s_cnt;
+}
+
+// In-place exclusive scan of n counts (one workgroup); x[n] receives the total.
+__global__ __launch_bounds__(kThreads) void k_exclusive_scan(int32_t* __restrict__ x, int n) {
+  __shared__ int s_part[kThreads];
+  const int tid = threadIdx.x;
+  const int per = (n + kThreads - 1) / kThreads;
+  const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+  int sum = 0;
+  for (int i = b0; i < b1; ++i) sum += x[i];
+  s_part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    const int v = tid >= off ? s_part[tid - off] : 0;
+    __syncthreads();
+    s_part[tid] += v;
+    __syncthreads();
+  }
+  int run = s_part[tid] - sum;
+  for (int i = b0; i < b1; ++i) {
+    const int c = x[i];
+    x[i] = run;
+    run += c;
+  }
+  if (tid == kThreads - 1) x[n] = s_part[tid];
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, long long n, int32_t v) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) p[id] = v;
 }
 
 // ---- choose, rebuild, cut, paste (Algorithm 1 lines K best .. paste) ----
 struct FinArgs {
   Geom g;
-  const FilterDev* filters;
+  const FilterDev* filters;       // of this step
+  const FilterDev* filters_all;   // every patch of the call
+  int fbegin;                     // global index of this step's first patch
+  const int32_t* npred;
+  const int32_t* succ_off;
+  const int32_t* succ;
+  int32_t* predcnt;
+  const int32_t* kbeta;
+  _Float16* mbuf;                 // [patch][kKMax] data events
+  int kpad;
   const uint64_t* keys;
   const uint64_t* rowmin;
   const int32_t* Ki;
@@ -976,6 +1051,7 @@ __device__ __forceinline__ int seam_err(const Geom& g, const int8_t* s_sg, const
 }
 
 constexpr int kSeamRowsMax = 64;   // longest seam of the register dynamic programme
+constexpr int kMaxSucc = 64;       // overlapping successors of one patch
 
 // Minimal-error boundary cut of every seam of one patch, one wavefront per
 // seam (overlap <= 16 cells, seam <= ROWS cells).  Lane w holds column w
@@ -1068,6 +1144,19 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   int8_t* s_hd = s_sg + wpad;
   uint64_t* s_cand = (uint64_t*)(s_hd + wpad);
   unsigned char* dps = (unsigned char*)(s_cand + a.cand_cap);
+
+  // successor list of this patch (used at the very end), fetched early
+  __shared__ int s_mine[kMaxSucc];
+  __shared__ int s_nmine;
+  const int my_nsucc = min(f.nsucc, kMaxSucc);
+  int my_succ = 0, my_npred = 0;
+  if (tid < my_nsucc) {
+    const int2 e = ((const int2*)a.succ)[f.succ0 + tid];
+    my_succ = e.x;
+    my_npred = e.y;
+  }
+  // the block list of this realization's orientation (shared by successors)
+  const int my_beta = tid < a.kpad ? a.kbeta[f.orient * kKMax + tid] : -1;
 
   // windows of the grid and of the hard-data map
   load_windows(s_sg, a.sg + (long long)f.r * g.pcells, s_hd, a.has_hd ? a.hdmap + (long long)f.r * g.pcells : nullptr,
@@ -1214,6 +1303,55 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     split3(i, g.T[0], g.T[1], ux, uy, uz);
     sgw[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)] = P[i];
   }
+  // Successors whose last overlapping predecessor is this patch get their
+  // data event here.  Every wavefront first waits for its own stores of the
+  // paste; then one lane per successor counts this patch in with an
+  // acquire-release atomic at device scope (its release publishes the paste,
+  // its acquire makes the other predecessors' cells visible), and the patch
+  // that completes a successor's count computes that successor's block sums.
+  __builtin_amdgcn_s_waitcnt(0);
+  if (tid == 0) s_nmine = 0;
+  __syncthreads();
+  if (tid < my_nsucc) {
+    if (__hip_atomic_fetch_add(&a.predcnt[my_succ], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1 == my_npred)
+      s_mine[atomicAdd(&s_nmine, 1)] = my_succ;
+  }
+  __syncthreads();
+  const int nmine = min(s_nmine, kMaxSucc);
+  int* s_msum = (int*)(dps + (long long)a.dp_batch * a.dp_stride);
+  for (int m = 0; m < nmine; ++m) {
+    const FilterDev fq = a.filters_all[s_mine[m]];
+    for (int i = tid; i < (int)g.tcells; i += kThreads) s_msum[i] = 0;
+    __syncthreads();
+    // overlap cells of the successor, summed per level-J block
+    const int8_t* sgq = a.sg + (long long)fq.r * g.pcells;
+    constexpr int U = 8;
+    const int n = (int)g.wcells;
+    for (int base = tid; base < n; base += kThreads * U) {
+      int v[U], bi[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        v[q] = 0;
+        bi[q] = -1;
+        if (i < n) {
+          int ux, uy, uz;
+          split3(i, g.T[0], g.T[1], ux, uy, uz);
+          if (dev_in_band(g, fq.orient, fq.bandmask, ux, uy, uz)) {
+            v[q] = sgq[idx3(fq.org[0] + ux, fq.org[1] + uy, fq.org[2] + uz, g.pad)];
+            bi[q] = (uz / g.b[2] * g.tc[1] + uy / g.b[1]) * g.tc[0] + ux / g.b[0];
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (bi[q] >= 0) atomicAdd(&s_msum[bi[q]], v[q]);
+    }
+    __syncthreads();
+    if (tid < a.kpad)
+      a.mbuf[(long long)s_mine[m] * kKMax + tid] = (_Float16)(float)(my_beta >= 0 ? s_msum[my_beta] : 0);
+    __syncthreads();
+  }
 }
 
 }  // namespace
@@ -1271,14 +1409,18 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   int8_t* sg = (int8_t*)(ws + P->ws_sg);
   int8_t* hdmap = (int8_t*)(ws + P->ws_hdmap);
   _Float16* mbuf = (_Float16*)(ws + P->ws_mbuf);
-  HdEnt* hdlist = (HdEnt*)(ws + P->ws_hdlist);
-  int32_t* hdcnt = (int32_t*)(ws + P->ws_hdcnt);
+  int32_t* predcnt = (int32_t*)(ws + P->ws_predcnt);
+  int32_t* hd_off = (int32_t*)(ws + P->ws_hdoff);
+  HdEnt* hd_ent = (HdEnt*)(ws + P->ws_hdent);
   uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
   uint64_t* rowmin = (uint64_t*)(ws + P->ws_rowmin);
   const int32_t* kbeta = (const int32_t*)(tbl + P->off_kbeta);
   const int32_t* nbt = (const int32_t*)(tbl + P->off_nbt);
   const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
   const TileDev* tiles = (const TileDev*)(tbl + P->off_tiles);
+  const int32_t* npred = (const int32_t*)(tbl + P->off_npred);
+  const int32_t* succ_off = (const int32_t*)(tbl + P->off_succoff);
+  const int32_t* succ = (const int32_t*)(tbl + P->off_succ);
 
   HIP_TRY(hipMemcpyAsync(tbl, P->tbl, P->tbl_bytes, hipMemcpyHostToDevice, st));
   // TI transform and energy rows (depend on the TI only)
@@ -1308,34 +1450,27 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     k_fill_i8<<<nblocks(allp), kThreads, 0, st>>>(hdmap, allp, (int8_t)-1);
     if (n_hd > 0)
       k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
+    k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
+    if (n_hd > 0) {
+      k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
+      k_exclusive_scan<<<1, kThreads, 0, st>>>(hd_off, P->nfilters);
+      k_hd_bin<true><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
+    }
     HIP_TRY(hipGetLastError());
   }
-
-  PrepArgs pa = {};
-  pa.g = g;
-  pa.kbeta = kbeta;
-  pa.sg = sg;
-  pa.hdmap = hdmap;
-  pa.mbuf = mbuf;
-  pa.hdlist = hdlist;
-  pa.hdcnt = hdcnt;
-  pa.hdmax = P->hdmax;
-  pa.kpad = P->kpad;
-  pa.has_hd = n_hd > 0;
 
   ScanArgs sa = {};
   sa.g = g;
   sa.Kh = Kh;
   sa.kbeta = kbeta;
   sa.mbuf = mbuf;
+  sa.hd_off = hd_off;
+  sa.hd_ent = hd_ent;
   sa.energy = energy;
-  sa.hdlist = hdlist;
-  sa.hdcnt = hdcnt;
   sa.ti = ti;
   sa.keys = keys;
   sa.rowmin = rowmin;
   sa.seed = p->seed;
-  sa.hdmax = (int)P->hdmax;
   sa.kpad = P->kpad;
   sa.W = P->W;
   sa.score_mode = p->score_mode;
@@ -1346,6 +1481,14 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.g = g;
   fa.keys = keys;
   fa.rowmin = rowmin;
+  fa.filters_all = filters;
+  fa.npred = npred;
+  fa.succ_off = succ_off;
+  fa.succ = succ;
+  fa.predcnt = predcnt;
+  fa.kbeta = kbeta;
+  fa.mbuf = mbuf;
+  fa.kpad = P->kpad;
   fa.cand_cap = P->cand_cap;
   fa.coef_lds = P->coef_lds;
   fa.rows_max = P->rows_max;
@@ -1367,18 +1510,15 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
 
   const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
   for (const StepRange& s : P->steps) {
-    pa.filters = filters + s.fbegin;
-    {
-      ProfScope ps(CCWSIM_KIND_PREPARE, st);
-      k_prepare<<<(unsigned)s.fcount, kThreads, P->prep_lds, st>>>(pa);
-    }
     sa.filters = filters + s.fbegin;
+    sa.fbegin = s.fbegin;
     sa.tiles = tiles + s.tbegin;
     {
       ProfScope ps(CCWSIM_KIND_SCAN, st);
       k_scan<<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
     }
     fa.filters = filters + s.fbegin;
+    fa.fbegin = s.fbegin;
     {
       ProfScope ps(CCWSIM_KIND_FINALIZE, st);
       launch_finalize(g.ndim, P->rows_max, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa);
@@ -1421,6 +1561,8 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   if (!workspace || workspace_bytes < P->ws_total)
     return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)P->ws_total);
   if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (n_hd > p->max_hard_data)
+    return fail(CCWSIM_ERR_INVALID_ARG, "%lld hard data exceed max_hard_data = %d", (long long)n_hd, p->max_hard_data);
   hipStream_t st = as_stream(stream);
   bool prof;
   {

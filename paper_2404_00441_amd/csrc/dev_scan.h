@@ -27,13 +27,15 @@ struct FilterDev {     // one (realization, patch) pair active in a step
   int32_t shape;       // energy row: orient * 2^ndim + bandmask
   int32_t orient;      // bit a: axis a walked from its high end
   int32_t bandmask;    // bit a: overlap band present on axis a
+  int32_t succ0;       // first entry of this patch's successor list
+  int32_t nsucc;       // later patches whose windows overlap this one
 };
 
 struct TileDev {
   int32_t first;       // first filter (index within the step)
   int32_t count;       // filters in this tile (<= 32)
   int32_t orient;      // shared orientation of the tile
-  int32_t pad_;
+  uint32_t zmask;      // bit j: filter j has no overlap yet (first patch)
 };
 
 struct HdEnt {         // one hard datum inside a virtual template
@@ -47,16 +49,16 @@ struct ScanArgs {
   const int32_t* kbeta;        // [orient][kKMax] block index or -1 (simulate)
   const TileDev* tiles;        // simulate: tiles of this step
   const FilterDev* filters;    // simulate: filters of this step
-  const _Float16* mbuf;        // [slot][kKMax] data-event block sums
+  const _Float16* mbuf;        // [patch][kKMax] data-event block sums (standalone: [filter])
   const int32_t* energy;       // simulate: [shape][ncand]
-  const HdEnt* hdlist;         // [slot][hdmax]
-  const int32_t* hdcnt;        // [slot]
+  const int32_t* hd_off;       // simulate: [patch + 1] offsets of each patch's hard data
+  const HdEnt* hd_ent;
   const int8_t* ti;
   uint64_t* keys;              // simulate: [slot][ncand]
   uint64_t* rowmin;            // simulate: [slot][candidate rows] smallest key of each row
   int32_t* scores;             // standalone: [filter][ncand], holds E on entry
   uint64_t seed;
-  int hdmax;
+  int fbegin;                  // simulate: global index of this step's first patch
   int kpad;                    // padded K dimension (multiple of 16)
   int W;                       // LDS strip row length (halves)
   int score_mode;              // 0 squared difference, 1 raw
@@ -79,6 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     t.first = blockIdx.y * kFiltersPerTile;
     t.count = min(kFiltersPerTile, a.n_filters - t.first);
     t.orient = 0;
+    t.zmask = 0;
   } else {
     t = a.tiles[blockIdx.y];
   }
@@ -129,7 +132,8 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   for (int i = tid; i < kFiltersPerTile * (kpad / 8); i += kThreads) {
     const int jj = i / (kpad / 8), k8 = (i - jj * (kpad / 8)) * 8;
     half8_t v = {};
-    if (jj < t.count) v = *(const half8_t*)(a.mbuf + (long long)(t.first + jj) * kKMax + k8);
+    if (jj < t.count && !((t.zmask >> jj) & 1u))
+      v = *(const half8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
     *(half8_t*)(s_B + jj * bstride + k8) = v;
   }
   __syncthreads();
@@ -140,35 +144,36 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   const int slot = t.first + j;
   FilterDev f = {};
   uint64_t tkey = 0;
-  int nhd = 0;
+  int nhd = 0, hd0 = 0;
   if (fvalid && !a.standalone) {
     f = a.filters[slot];
     tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
-    if (a.has_hd) nhd = a.hdcnt[slot];
+    if (a.has_hd) {
+      hd0 = a.hd_off[a.fbegin + slot];
+      nhd = a.hd_off[a.fbegin + slot + 1] - hd0;
+    }
   }
   const int shift = g.log2beta + 1;
   const int nchunks = (g.cand[0] + 31) / 32;
   const long long rowbase = (long long)g.cand[0] * row;
 
   uint64_t lane_min = ~0ull;
+  const int32_t* erow = a.standalone ? a.scores + (long long)slot * g.ncand
+                                     : a.energy + (long long)f.shape * g.ncand;
   for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
-    float16_t acc = {};
-    const int cbase = ch * 32 + j;
-    for (int kc = 0; kc < kpad; kc += 16) {
-      half8_t av, bv;
+    // the epilogue's memory reads (energy, hard-data gathers) do not depend
+    // on the contraction: issue them first so they overlap the MFMA work
+    int ev[16];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
-      bv = *(const half8_t*)(s_B + j * bstride + kc + g8);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+    for (int v = 0; v < 16; ++v) {
+      const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      ev[v] = (fvalid && a.score_mode == 0 && cx < g.cand[0]) ? erow[rowbase + cx] : 0;
     }
-    if (!fvalid) continue;
-    // hard-data mismatch of the 16 candidates of this lane: per datum, one
-    // entry load and 16 independent TI gathers
     unsigned mis[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) mis[v] = 0;
     for (int h = 0; h < nhd; ++h) {
-      const HdEnt e = a.hdlist[(long long)slot * a.hdmax + h];
+      const HdEnt e = a.hd_ent[hd0 + h];
       const int fy = g.b[1] * cy + e.u[1], fz = g.b[2] * cz + e.u[2];
       if (fy < 0 || fz < 0 || fy >= g.ti[1] || fz >= g.ti[2]) continue;
       const int8_t* trow = a.ti + ((long long)fz * g.ti[1] + fy) * g.ti[0];
@@ -182,6 +187,16 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) mis[v] += tv[v] != e.v;
     }
+    float16_t acc = {};
+    const int cbase = ch * 32 + j;
+    for (int kc = 0; kc < kpad; kc += 16) {
+      half8_t av, bv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
+      bv = *(const half8_t*)(s_B + j * bstride + kc + g8);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+    }
+    if (!fvalid) continue;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -189,12 +204,11 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
       if (cx >= g.cand[0]) continue;
       const long long idx = rowbase + cx;
       const int C = (int)acc[v];
+      const int S = (a.score_mode == 0) ? ev[v] - (C << shift) : -C;
       if (a.standalone) {
-        int32_t* sp = a.scores + (long long)slot * g.ncand + idx;
-        *sp = (a.score_mode == 0) ? *sp - (C << shift) : -C;
+        a.scores[(long long)slot * g.ncand + idx] = S;
         continue;
       }
-      const int S = (a.score_mode == 0) ? a.energy[(long long)f.shape * g.ncand + idx] - (C << shift) : -C;
       const uint64_t key = make_key(mis[v], S, tie_perm((uint32_t)idx, tkey));
       a.keys[(long long)slot * g.ncand + idx] = key;
       lane_min = key < lane_min ? key : lane_min;

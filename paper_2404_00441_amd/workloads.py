@@ -78,6 +78,7 @@ def make(name: str, scale: float = 1.0, n_real: int | None = None):
     if n_real is not None:
         p["n_real"] = n_real
     p["name"] = name
+    p["max_hard_data"] = 0 if hd is None else int(len(hd[0]))
     return p, ti, hd
 
 

@@ -246,6 +246,7 @@ def _tiny(over, nhd, seed=11):
         ref = syn.tube_image_3d(*p["grid"], 4, seed=22)
         p["n_facies"] = 2
     hd = syn.sample_hard_data(ref, [nhd] * p["n_real"], seed=23) if nhd else None
+    p["max_hard_data"] = 0 if hd is None else int(len(hd[0]))
     return p, ti, hd
 
 
