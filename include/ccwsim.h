@@ -84,10 +84,13 @@ typedef struct {
   int32_t nc_margin[3]; /* non-causal margin of the virtual template used
                            for hard data; < 0 means "= overlap"          */
   int32_t cut;          /* 1: minimal-error boundary cut; 0: plain paste  */
-  int32_t precision;    /* 0: fp16 inputs, fp32 accumulation (exact for
-                           Haar on integer codes within the limits checked
-                           by ccwsim_simulate)                            */
-  int32_t shortlist;    /* reserved, must be 0                            */
+  int32_t precision;    /* bulk scan operands, fp32 accumulation:
+                           0 fp16 (exact for block sums <= 2048),
+                           1 bf16 (exact for block sums <= 256);
+                           ccwsim_simulate refuses inexact combinations  */
+  int32_t shortlist;    /* 0, or S in [top_k, 32]: the S best candidates by
+                           the bulk score are rescored exactly in integers
+                           and the K best of those are drawn from        */
   int32_t max_hard_data;/* most hard data a call passes (sizes the
                            workspace); 0 = unconditional only            */
   int32_t reserved[3];  /* must be 0                                      */
@@ -197,6 +200,14 @@ typedef struct {
   double cells;            /* simulated grid cells, all realizations */
 } ccwsim_plan_stats;
 int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out);
+
+/* Report of the exact shortlist rescoring of the last ccwsim_simulate call
+ * on this workspace (synchronises `stream`): out[0] largest |bulk score -
+ * exact score|, out[1] candidates rescored, out[2] patches whose K best
+ * changed after rescoring, out[3] patches rescored.  All zero without a
+ * shortlist. */
+int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
+                           int64_t* out, void* stream);
 
 /* Kernel kinds timed by the profiler. */
 #define CCWSIM_KIND_DWT 0

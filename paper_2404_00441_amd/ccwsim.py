@@ -84,6 +84,8 @@ def load():
     L.ccwsim_profile_read.argtypes = [p, p]
     L.ccwsim_set_graphs.restype = ctypes.c_int
     L.ccwsim_set_graphs.argtypes = [ctypes.c_int]
+    L.ccwsim_simulate_report.restype = ctypes.c_int
+    L.ccwsim_simulate_report.argtypes = [p, p, i64, p, p]
     _lib = L
     return L
 
@@ -91,7 +93,7 @@ def load():
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
-           "ccwsim_profile_read", "ccwsim_set_graphs")
+           "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop")
 
@@ -151,7 +153,7 @@ def params_of(p: dict) -> Params:
     q.nc_margin = (ctypes.c_int32 * 3)(*m)
     q.cut = p.get("cut", 1)
     q.precision = p.get("precision", 0)
-    q.shortlist = 0
+    q.shortlist = int(p.get("shortlist", 0))
     q.max_hard_data = int(p.get("max_hard_data", 0))
     return q
 
@@ -255,6 +257,14 @@ class Simulator:
             _ptr(hv) if n_hd else None, _ptr(out), _ptr(chosen), ctypes.c_void_p(self.ws_view.data_ptr()),
             self.ws_bytes, _stream()))
         return out
+
+
+    def report(self) -> dict:
+        """Shortlist rescoring report of the last run (synchronises)."""
+        out = (ctypes.c_int64 * 4)()
+        _check("ccwsim_simulate_report", load().ccwsim_simulate_report(
+            ctypes.byref(self.q), ctypes.c_void_p(self.ws_view.data_ptr()), self.ws_bytes, out, _stream()))
+        return {"max_abs_error": out[0], "rescored": out[1], "topk_changed": out[2], "patches": out[3]}
 
 
 def hd_to_device(hd, ndim, device="cuda"):

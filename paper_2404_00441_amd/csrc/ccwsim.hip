@@ -263,13 +263,18 @@ __global__ void k_to_half(const int32_t* __restrict__ src, _Float16* __restrict_
   if (id < n) dst[id] = (_Float16)(float)src[id];
 }
 
+__global__ void k_to_bf16(const int32_t* __restrict__ src, __bf16* __restrict__ dst, long long n) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) dst[id] = (__bf16)(float)src[id];
+}
+
 // Standalone data events: or_m[f][beta] -> mbuf[f][k = beta] (fp16), zero pad.
-__global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, _Float16* __restrict__ mbuf,
+__global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int16_t* __restrict__ mbuf,
                                  int n_filters, long long tcells) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long long)n_filters * kKMax) return;
   const long long f = id / kKMax, k = id - f * kKMax;
-  mbuf[id] = k < tcells ? (_Float16)(float)or_m[f * tcells + k] : (_Float16)0.0f;
+  mbuf[id] = k < tcells ? (int16_t)or_m[f * tcells + k] : (int16_t)0;
 }
 
 size_t scan_lds_bytes(const Geom& g, int W, int kpad) {
@@ -306,7 +311,7 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   hipStream_t st = as_stream(stream);
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
   _Float16* Kh = nullptr;
-  _Float16* mbuf = nullptr;
+  int16_t* mbuf = nullptr;
   HIP_TRY(hipMallocAsync((void**)&Kh, gcells * 2, st));
   HIP_TRY(hipMallocAsync((void**)&mbuf, (size_t)n_filters * kKMax * 2, st));
   k_to_half<<<nblocks(gcells), kThreads, 0, st>>>(approx, Kh, gcells);
@@ -315,7 +320,7 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
     k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, scores, g);
   ScanArgs a = {};
   a.g = g;
-  a.Kh = Kh;
+  a.Kop = Kh;
   a.mbuf = mbuf;
   a.scores = scores;
   a.kpad = kpad;
@@ -324,7 +329,7 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   a.standalone = 1;
   a.n_filters = n_filters;
   dim3 grid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + kFiltersPerTile - 1) / kFiltersPerTile));
-  k_scan<<<grid, kThreads, lds, st>>>(a);
+  k_scan<_Float16><<<grid, kThreads, lds, st>>>(a);
   const hipError_t le = hipGetLastError();
   HIP_TRY(hipFreeAsync(Kh, st));
   HIP_TRY(hipFreeAsync(mbuf, st));
@@ -475,7 +480,7 @@ struct Plan {
   size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_npred = 0, off_succoff = 0, off_succ = 0;
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
-            ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
+            ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_report = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
             ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
@@ -527,8 +532,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (p.path_mode != 0 && p.path_mode != 1) return fail(CCWSIM_ERR_INVALID_ARG, "path_mode");
   if (p.score_mode != 0 && p.score_mode != 1) return fail(CCWSIM_ERR_INVALID_ARG, "score_mode");
   if (p.cut != 0 && p.cut != 1) return fail(CCWSIM_ERR_INVALID_ARG, "cut");
-  if (p.precision != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
-  if (p.shortlist != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist %d", p.shortlist);
+  if (p.precision != 0 && p.precision != 1) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
+  if (p.shortlist != 0 && (p.shortlist < p.top_k || p.shortlist > kShortMax))
+    return fail(CCWSIM_ERR_INVALID_ARG, "shortlist must be 0 or in [top_k, %d]", kShortMax);
   for (int i = 0; i < 3; ++i)
     if (p.reserved[i]) return fail(CCWSIM_ERR_INVALID_ARG, "reserved fields must be 0");
   if (p.max_hard_data < 0) return fail(CCWSIM_ERR_INVALID_ARG, "max_hard_data must be >= 0");
@@ -564,6 +570,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.kpad = std::max(16, (kmax_len + 15) / 16 * 16);
   if (P.kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "overlap spans %d blocks (> %d)", kmax_len, kKMax);
   CCW_TRY(check_exact(g, p.n_facies - 1 > 0 ? p.n_facies - 1 : 1, ov_cells_max));
+  if (p.precision == 1 && (long long)(p.n_facies > 1 ? p.n_facies - 1 : 1) * g.beta > 256)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld are not exact in bf16",
+                (long long)(p.n_facies - 1) * g.beta);
   P.W = scan_strip_width(g);
   P.scan_lds = scan_lds_bytes(g, P.W, P.kpad);
   if (P.scan_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu B of LDS", P.scan_lds);
@@ -758,6 +767,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_hdmap = o;     o += align256((long long)p.n_real * g.pcells);
   P.ws_mbuf = o;      o += align256((long long)P.nfilters * kKMax * 2);
   P.ws_predcnt = o;   o += align256((long long)P.nfilters * 4);
+  P.ws_report = o;    o += 256;
   P.ws_hdoff = o;     o += align256((long long)(P.nfilters + 1) * 4);
   P.ws_hdent = o;     o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdEnt));
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
@@ -776,8 +786,11 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     maxcols = std::max(maxcols, g.OV[a]);
   }
   P.dp_wave = maxcols <= 16 && P.rows_max <= 64;
-  const long long cand_bytes = (long long)std::min(p.top_k, g.ncand) * g.cand[0] * 8;
-  P.cand_cap = cand_bytes <= 24 * 1024 ? (long long)std::min(p.top_k, g.ncand) * g.cand[0] : 0;
+  const int ksel = std::min(p.shortlist > 0 ? p.shortlist : p.top_k, g.ncand);
+  const long long cand_bytes = (long long)ksel * g.cand[0] * 8;
+  P.cand_cap = cand_bytes <= 24 * 1024 ? (long long)ksel * g.cand[0] : 0;
+  if (ksel > kTopMax && (P.cand_cap == 0 || (long long)g.cand[1] * g.cand[2] > P.cand_cap))
+    return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist of %d needs %lld B of keys in LDS", ksel, cand_bytes);
   const size_t fixed = (size_t)P.buf_cells * 8 + 4 * (size_t)wpad + (size_t)P.cand_cap * 8;
   const long long budget = 60 * 1024;
   if (P.dp_wave) {
@@ -1007,8 +1020,12 @@ struct FinArgs {
   const int32_t* succ;
   int32_t* predcnt;
   const int32_t* kbeta;
-  _Float16* mbuf;                 // [patch][kKMax] data events
+  const int32_t* nbt;             // [shape][window block] known-cell counts
+  int16_t* mbuf;                  // [patch][kKMax] data events
+  unsigned long long* report;     // shortlist report: max |bulk - exact|, rescored, changed, patches
   int kpad;
+  int shortlist;
+  int score_mode;
   const uint64_t* keys;
   const uint64_t* rowmin;
   const int32_t* Ki;
@@ -1130,7 +1147,7 @@ template <int ND, int ROWS, int TJ>
 __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ TopkShared sh;
-  __shared__ int s_rows[kTopMax];
+  __shared__ int s_rows[kShortMax];
   const Geom& g = a.g;
   const int tid = threadIdx.x;
   const int slot = blockIdx.x;
@@ -1169,25 +1186,28 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   const uint64_t tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
   const int k = min(a.top_k, g.ncand);
   const uint64_t* kf = a.keys + (long long)slot * g.ncand;
-  __shared__ uint64_t s_rowtop[kTopMax];
+  // ksel best bulk keys: k, or the shortlist that is rescored exactly below
+  __shared__ uint64_t s_rowtop[kShortMax];
+  __shared__ uint64_t s_sel[kShortMax];
+  __shared__ uint64_t s_fin[kShortMax];
   __shared__ unsigned s_cnt;
-  __shared__ int s_over;
+  const int ksel = a.shortlist > 0 ? min(a.shortlist, g.ncand) : k;
   bool done = false;
   if (a.cand_cap > 0) {
     // 1. the kr smallest row minima, by rank (rows are few)
     const int nrows = g.cand[1] * g.cand[2];
     const uint64_t* rm = a.rowmin + (long long)slot * nrows;
-    const int kr = min(k, nrows);
+    const int kr = min(ksel, nrows);
     uint64_t* s_rm = s_cand;   // staging; the candidate list reuses it afterwards
     if (nrows <= a.cand_cap) {
       for (int i = tid; i < nrows; i += kThreads) s_rm[i] = rm[i];
-      if (tid == 0) { s_cnt = 0; s_over = 0; }
+      if (tid == 0) s_cnt = 0;
       __syncthreads();
       block_rank_select(s_rm, nrows, kr, s_rowtop);
-    } else {
+    } else {   // only reached with kr <= 16 (checked when the plan is built)
       block_topk(nrows, kr, [&](long long i) { return rm[i]; }, sh);
       if (tid < kr) s_rowtop[tid] = sh.top[tid];
-      if (tid == 0) { s_cnt = 0; s_over = 0; }
+      if (tid == 0) s_cnt = 0;
       __syncthreads();
     }
     if (tid < kr) {
@@ -1196,11 +1216,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     }
     __syncthreads();
     // 2. every key of those rows at or below the kr-th row minimum (when
-    //    there are fewer rows than k, every key of every row)
-    const uint64_t thr = kr == k ? s_rowtop[kr - 1] : ~0ull;
+    //    there are fewer rows than ksel, every key of every row); the list
+    //    holds at most kr * C_x <= cand_cap keys
+    const uint64_t thr = kr == ksel ? s_rowtop[kr - 1] : ~0ull;
     const int cx = g.cand[0];
     const int nc = kr * cx;
-    const int cap = (int)min(a.cand_cap, 256ll);
     constexpr int U = 8;
     for (int base = tid; base < nc; base += kThreads * U) {
       uint64_t v[U];
@@ -1214,26 +1234,100 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (v[q] <= thr && v[q] != ~0ull) {
-          const unsigned p = atomicAdd(&s_cnt, 1u);
-          if (p < (unsigned)cap) s_cand[p] = v[q];
-          else s_over = 1;
-        }
-      }
+      for (int q = 0; q < U; ++q)
+        if (v[q] <= thr && v[q] != ~0ull) s_cand[atomicAdd(&s_cnt, 1u)] = v[q];
     }
     __syncthreads();
-    if (!s_over) {
-      // 3. the k smallest of the short list, by rank
-      block_rank_select(s_cand, (int)s_cnt, k, sh.top);
-      done = true;
+    const int n = (int)s_cnt;
+    if (n <= 512) {
+      // 3. the ksel smallest of the short list, by rank
+      block_rank_select(s_cand, n, ksel, s_sel);
+    } else {
+      // long list: ksel rounds of "smallest key above the previous one"
+      uint64_t prev = 0;
+      for (int r = 0; r < ksel; ++r) {
+        uint64_t mm = ~0ull;
+        for (int i = tid; i < n; i += kThreads) {
+          const uint64_t key = s_cand[i];
+          if ((r == 0 || key > prev) && key < mm) mm = key;
+        }
+        mm = wave_min64(mm);
+        __syncthreads();
+        if ((tid & 63) == 0) sh.small[tid >> 6] = mm;
+        __syncthreads();
+        uint64_t best = sh.small[0];
+        for (int w = 1; w < kThreads / 64; ++w) best = sh.small[w] < best ? sh.small[w] : best;
+        prev = best;
+        if (tid == 0) s_sel[r] = best;
+      }
+      __syncthreads();
     }
-    // a long list falls through to the full selection below
+    done = true;
   }
-  if (!done) block_topk(g.ncand, k, [&](long long i) { return kf[i]; }, sh);
+  if (!done) {   // only reached with ksel <= 16 (checked when the plan is built)
+    block_topk(g.ncand, ksel, [&](long long i) { return kf[i]; }, sh);
+    if (tid < ksel) s_sel[tid] = sh.top[tid];
+    __syncthreads();
+  }
+
+  if (a.shortlist > 0) {
+    // Exact rescoring of the shortlist in integers from the int32 grid and
+    // the exact data event; the K best of the rescored keys are drawn from.
+    __shared__ int s_bk[kKMax], s_mk[kKMax], s_nk[kKMax];
+    __shared__ uint64_t s_resc[kShortMax];
+    const int fgi = a.fbegin + slot;
+    if (tid < a.kpad) {
+      s_bk[tid] = my_beta;
+      s_mk[tid] = (my_beta >= 0 && f.bandmask) ? (int)a.mbuf[(long long)fgi * kKMax + tid] : 0;
+      s_nk[tid] = my_beta >= 0 ? a.nbt[(long long)f.shape * g.tcells + my_beta] : 0;
+    }
+    __syncthreads();
+    const int ci = tid >> 3, sub = tid & 7;   // 8 lanes per shortlisted candidate
+    long long C = 0, E = 0;
+    uint64_t key = 0;
+    int c0[3] = {0, 0, 0};
+    if (ci < ksel) {
+      key = s_sel[ci];
+      const int id = min(max((int)tie_perm_inv((uint32_t)(key & kMask20), tkey), 0), g.ncand - 1);
+      split3(id, g.cand[0], g.cand[1], c0[0], c0[1], c0[2]);
+      for (int kk = sub; kk < a.kpad; kk += 8) {
+        const int beta = s_bk[kk];
+        if (beta < 0) continue;
+        int bx, by, bz;
+        split3(beta, g.tc[0], g.tc[1], bx, by, bz);
+        const long long kv = a.Ki[idx3(c0[0] + bx, c0[1] + by, c0[2] + bz, g.G)];
+        C += (long long)s_mk[kk] * kv;
+        E += (long long)s_nk[kk] * kv * kv;
+      }
+    }
+#pragma unroll
+    for (int m = 4; m >= 1; m >>= 1) {
+      C += __shfl_xor(C, m, 8);
+      E += __shfl_xor(E, m, 8);
+    }
+    if (ci < ksel && sub == 0) {
+      const long long sx = a.score_mode == 0 ? E - 2ll * g.beta * C : -C;
+      const long long sb = (long long)((key >> 20) & 0xFFFFFFFFull) - 2147483648ll;
+      const unsigned long long err = (unsigned long long)(sx > sb ? sx - sb : sb - sx);
+      s_resc[ci] = make_key((uint32_t)(key >> 52), (int32_t)sx, (uint32_t)(key & kMask20));
+      if (err) atomicMax(&a.report[0], err);
+    }
+    __syncthreads();
+    block_rank_select(s_resc, ksel, k, s_fin);
+    if (tid == 0) {
+      atomicAdd(&a.report[1], (unsigned long long)ksel);
+      atomicAdd(&a.report[3], 1ull);
+      bool changed = false;
+      for (int i = 0; i < k; ++i) changed = changed || ((s_fin[i] ^ s_sel[i]) & kMask20) != 0;
+      if (changed) atomicAdd(&a.report[2], 1ull);
+    }
+  } else if (tid < k) {
+    s_fin[tid] = s_sel[tid];
+  }
+  __syncthreads();
   const uint64_t u = draw64(a.seed, kStreamDraw, (uint64_t)f.r, (uint64_t)f.step) >> 32;
   const int jpick = (int)((u * (uint64_t)k) >> 32);
-  int idx = (int)tie_perm_inv((uint32_t)(sh.top[jpick] & kMask20), tkey);
+  int idx = (int)tie_perm_inv((uint32_t)(s_fin[jpick] & kMask20), tkey);
   idx = min(max(idx, 0), g.ncand - 1);  // always in range for keys written by the scan
   if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
   const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
@@ -1349,7 +1443,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     }
     __syncthreads();
     if (tid < a.kpad)
-      a.mbuf[(long long)s_mine[m] * kKMax + tid] = (_Float16)(float)(my_beta >= 0 ? s_msum[my_beta] : 0);
+      a.mbuf[(long long)s_mine[m] * kKMax + tid] = (int16_t)(my_beta >= 0 ? s_msum[my_beta] : 0);
     __syncthreads();
   }
 }
@@ -1408,7 +1502,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   unsigned char* tbl = ws + P->ws_tbl;
   int8_t* sg = (int8_t*)(ws + P->ws_sg);
   int8_t* hdmap = (int8_t*)(ws + P->ws_hdmap);
-  _Float16* mbuf = (_Float16*)(ws + P->ws_mbuf);
+  int16_t* mbuf = (int16_t*)(ws + P->ws_mbuf);
+  unsigned long long* report = (unsigned long long*)(ws + P->ws_report);
   int32_t* predcnt = (int32_t*)(ws + P->ws_predcnt);
   int32_t* hd_off = (int32_t*)(ws + P->ws_hdoff);
   HdEnt* hd_ent = (HdEnt*)(ws + P->ws_hdent);
@@ -1436,6 +1531,11 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     } else {
       CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));
     }
+    if (p->precision == 1) {
+      const long long gc = (long long)g.G[0] * g.G[1] * g.G[2];
+      k_to_bf16<<<nblocks(gc), kThreads, 0, st>>>(Ki, (__bf16*)Kh, gc);
+      HIP_TRY(hipGetLastError());
+    }
   }
   if (p->score_mode == 0) {
     ProfScope ps(CCWSIM_KIND_ENERGY, st);
@@ -1451,6 +1551,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     if (n_hd > 0)
       k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
     k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
+    k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 8, 0);
     if (n_hd > 0) {
       k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
       k_exclusive_scan<<<1, kThreads, 0, st>>>(hd_off, P->nfilters);
@@ -1461,7 +1562,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
 
   ScanArgs sa = {};
   sa.g = g;
-  sa.Kh = Kh;
+  sa.Kop = Kh;
   sa.kbeta = kbeta;
   sa.mbuf = mbuf;
   sa.hd_off = hd_off;
@@ -1487,8 +1588,12 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.succ = succ;
   fa.predcnt = predcnt;
   fa.kbeta = kbeta;
+  fa.nbt = nbt;
   fa.mbuf = mbuf;
+  fa.report = report;
   fa.kpad = P->kpad;
+  fa.shortlist = p->shortlist;
+  fa.score_mode = p->score_mode;
   fa.cand_cap = P->cand_cap;
   fa.coef_lds = P->coef_lds;
   fa.rows_max = P->rows_max;
@@ -1515,7 +1620,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     sa.tiles = tiles + s.tbegin;
     {
       ProfScope ps(CCWSIM_KIND_SCAN, st);
-      k_scan<<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
+      if (p->precision == 1) k_scan<__bf16><<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
+      else k_scan<_Float16><<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
     }
     fa.filters = filters + s.fbegin;
     fa.fbegin = s.fbegin;
@@ -1675,4 +1781,18 @@ extern "C" int ccwsim_profile_read(double* ms, int64_t* launches) {
   }
   g_prof_recs.clear();
   return rc;
+}
+
+extern "C" int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
+                                      int64_t* out, void* stream) {
+  if (!p || !workspace || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  Plan* P = nullptr;
+  CCW_TRY(get_plan(*p, &P));
+  if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
+  unsigned long long v[4] = {0, 0, 0, 0};
+  hipStream_t st = as_stream(stream);
+  HIP_TRY(hipMemcpyAsync(v, (const unsigned char*)workspace + P->ws_report, sizeof v, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < 4; ++i) out[i] = (int64_t)v[i];
+  return CCWSIM_OK;
 }

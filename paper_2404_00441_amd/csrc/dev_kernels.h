@@ -12,6 +12,7 @@ typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;   // every kernel here runs 4 wavefronts of 64
 constexpr int kTopMax = 16;     // largest K handled by block_topk
+constexpr int kShortMax = 32;   // longest shortlist rescored exactly
 
 // ---------------------------------------------------------------------------
 // Forward Haar DWT, one level (Sec. 3.1 filter-and-decimate steps done as a

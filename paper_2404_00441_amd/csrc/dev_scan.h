@@ -45,11 +45,11 @@ struct HdEnt {         // one hard datum inside a virtual template
 
 struct ScanArgs {
   Geom g;
-  const _Float16* Kh;          // fp16 level-J grid
+  const void* Kop;             // level-J grid in the operand type (fp16 or bf16)
   const int32_t* kbeta;        // [orient][kKMax] block index or -1 (simulate)
   const TileDev* tiles;        // simulate: tiles of this step
   const FilterDev* filters;    // simulate: filters of this step
-  const _Float16* mbuf;        // [patch][kKMax] data-event block sums (standalone: [filter])
+  const int16_t* mbuf;         // [patch][kKMax] data-event block sums (standalone: [filter])
   const int32_t* energy;       // simulate: [shape][ncand]
   const int32_t* hd_off;       // simulate: [patch + 1] offsets of each patch's hard data
   const HdEnt* hd_ent;
@@ -67,7 +67,29 @@ struct ScanArgs {
   int has_hd;
 };
 
+template <typename OT>
+struct MfmaOp;
+template <>
+struct MfmaOp<_Float16> {
+  typedef _Float16 vec8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ float16_t mma(vec8 a, vec8 b, float16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfmaOp<__bf16> {
+  typedef __bf16 vec8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ float16_t mma(vec8 a, vec8 b, float16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Operand type OT: _Float16 (exact for integers <= 2048) or __bf16 (exact for
+// integers <= 256); accumulation is fp32 either way.
+template <typename OT>
 __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+  typedef typename MfmaOp<OT>::vec8 vec8;
+  const OT* Kop = (const OT*)a.Kop;
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -86,10 +108,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     t = a.tiles[blockIdx.y];
   }
 
-  _Float16* s_strip = (_Float16*)smem;
+  OT* s_strip = (OT*)smem;
   const int strip_bytes = ((nrows * W * 2) + 15) & ~15;
   int* s_off = (int*)(smem + strip_bytes);
-  _Float16* s_B = (_Float16*)(smem + strip_bytes + kpad * 4);
+  OT* s_B = (OT*)(smem + strip_bytes + kpad * 4);
   const int bstride = kpad + 8;   // halves per filter row (keeps 16 B alignment)
   __shared__ unsigned long long s_rowmin[kFiltersPerTile];
   if (tid < kFiltersPerTile) s_rowmin[tid] = ~0ull;
@@ -99,15 +121,15 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     constexpr int U = 8;
     const int n = nrows * W;
     for (int base = tid; base < n; base += kThreads * U) {
-      _Float16 v[U];
+      OT v[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         const int i = base + q * kThreads;
-        v[q] = (_Float16)0.0f;
+        v[q] = (OT)0.0f;
         if (i < n) {
           const int rr = i / W, x = i - rr * W;
           const int by = rr % g.tc[1], bz = rr / g.tc[1];
-          if (x < g.G[0]) v[q] = a.Kh[idx3(x, cy + by, cz + bz, g.G)];
+          if (x < g.G[0]) v[q] = Kop[idx3(x, cy + by, cz + bz, g.G)];
         }
       }
 #pragma unroll
@@ -128,13 +150,17 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     }
     s_off[k] = off;
   }
-  // data events, 8 halves (16 B) per load
+  // data events: 8 int16 (16 B) per load, converted to the operand type
+  typedef int16_t short8_t __attribute__((ext_vector_type(8)));
   for (int i = tid; i < kFiltersPerTile * (kpad / 8); i += kThreads) {
     const int jj = i / (kpad / 8), k8 = (i - jj * (kpad / 8)) * 8;
-    half8_t v = {};
+    short8_t m = {};
     if (jj < t.count && !((t.zmask >> jj) & 1u))
-      v = *(const half8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
-    *(half8_t*)(s_B + jj * bstride + k8) = v;
+      m = *(const short8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
+    vec8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
+    *(vec8*)(s_B + jj * bstride + k8) = v;
   }
   __syncthreads();
 
@@ -190,11 +216,11 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     float16_t acc = {};
     const int cbase = ch * 32 + j;
     for (int kc = 0; kc < kpad; kc += 16) {
-      half8_t av, bv;
+      vec8 av, bv;
 #pragma unroll
       for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
-      bv = *(const half8_t*)(s_B + j * bstride + kc + g8);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+      bv = *(const vec8*)(s_B + j * bstride + kc + g8);
+      acc = MfmaOp<OT>::mma(av, bv, acc);
     }
     if (!fvalid) continue;
 #pragma unroll

@@ -70,7 +70,7 @@ def make(name: str, scale: float = 1.0, n_real: int | None = None):
         ti_n = (_scaled(1000, scale, 80),) * 2
         g = (_scaled(2000, scale, 80),) * 2
         p = _base(ti=ti_n, grid=g, tmpl=(48, 48), overlap=(12, 12), level=2, top_k=10,
-                  n_facies=3, seed=1, path_mode=1, n_real=nr, shortlist=256)
+                  n_facies=3, seed=1, path_mode=1, n_real=nr)
         ti = syn.channel_image_2d(ti_n[0], ti_n[1], max(3, int(round(50 * scale))), 3, seed=105)
         hd = None
     else:

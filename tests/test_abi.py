@@ -69,6 +69,9 @@ def test_dwt_sizes_host_only(lib):
     dict(path_mode=2),
     dict(score_mode=3),
     dict(level=7),
+    dict(shortlist=3),                 # below top_k
+    dict(shortlist=33),                # above the longest shortlist
+    dict(precision=5),
 ])
 def test_simulate_validation_errors(lib, bad):
     from paper_2404_00441_amd import ccwsim
@@ -94,3 +97,15 @@ def test_inexact_range_is_rejected(lib):
     q = ccwsim.params_of(p)
     assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q)) == -1
     assert b"fp16" in lib.ccwsim_last_error()
+
+
+def test_bf16_range_is_rejected(lib):
+    # 3 facies at J = 3 in 2D: block sums up to 2 * 64 = 128 fit bf16, at
+    # J = 4 (256 cells) they reach 512 and must be refused for bf16
+    from paper_2404_00441_amd import ccwsim
+    from paper_2404_00441_amd import workloads as wl
+    p, _, _ = wl.make("c1_plain2d")
+    p.update(level=4, n_facies=3, precision=1, tmpl=(48, 48), overlap=(12, 12))
+    q = ccwsim.params_of(p)
+    assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q)) == -1
+    assert b"bf16" in lib.ccwsim_last_error()

@@ -352,3 +352,36 @@ def test_graph_replays_match_eager(cc, orc):
         del junk
     oout, _ = orc.simulate(_sp(p, orc), ti, hd)
     assert np.array_equal(eager, oout)
+
+
+PRECISION_CASES = [
+    # name, scale, n_real, overrides
+    ("c3_split3d", 0.4, None, dict(shortlist=32, precision=0)),
+    ("c3_split3d", 0.4, None, dict(shortlist=32, precision=1)),
+    ("c2_scale2d", 0.3, None, dict(shortlist=16, precision=1)),
+    ("c4_batched", 0.4, 4, dict(shortlist=10, precision=0)),
+]
+
+
+@pytest.mark.parametrize("case", PRECISION_CASES,
+                         ids=[f"{c[0]}_S{c[3]['shortlist']}_p{c[3]['precision']}" for c in PRECISION_CASES])
+def test_precision_split(cc, orc, case):
+    # bulk scan in fp16 or bf16, exact integer rescoring of the shortlist:
+    # for Haar on integer codes the bulk is exact, so the rescoring changes
+    # nothing and the realization equals the oracle's exact-score one
+    import torch
+    name, scale, nr, over = case
+    _say("precision", case)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    p.update(over)
+    sim = cc.Simulator(p)
+    out = sim.run(_t(ti), cc.hd_to_device(hd, len(p["ti"])))
+    torch.cuda.synchronize()
+    rep = sim.report()
+    oout, _ = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(out.cpu().numpy(), oout)
+    geo = orc.geometry(_sp(p, orc))
+    npatch = p["n_real"] * geo["nsteps"]
+    assert rep["max_abs_error"] == 0 and rep["topk_changed"] == 0
+    assert rep["patches"] == npatch
+    assert rep["rescored"] == npatch * min(p["shortlist"], geo["ncand"])
