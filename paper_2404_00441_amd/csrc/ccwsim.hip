@@ -1082,42 +1082,63 @@ constexpr int kMaxSucc = 64;       // overlapping successors of one patch
 template <int ND, int ROWS>
 __device__ void seam_dp_wave(const Geom& g, const FilterDev& f, const int8_t* s_sg, const int8_t* P,
                              uint8_t* keep, int n0, int n1, int n2) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int ndp = n0 + n1 + n2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ndp = __builtin_amdgcn_readfirstlane(n0 + n1 + n2);
   for (int dd = wave; dd < ndp; dd += kThreads / 64) {
-    const int ax = dd < n0 ? 0 : dd < n0 + n1 ? 1 : 2;
-    const int sl = dd - (ax == 0 ? 0 : ax == 1 ? n0 : n0 + n1);
+    // seam parameters are the same for the whole wavefront: keep them scalar
+    const int ax = __builtin_amdgcn_readfirstlane(dd < n0 ? 0 : dd < n0 + n1 ? 1 : 2);
+    const int sl = __builtin_amdgcn_readfirstlane(dd - (ax == 0 ? 0 : ax == 1 ? n0 : n0 + n1));
     const int ra = ax == 0 ? 1 : 0;
     const int sa = ND == 3 ? 3 - ax - ra : -1;
-    const int rows = ra == 0 ? g.T[0] : g.T[1];
-    const int cols = ax == 0 ? g.OV[0] : ax == 1 ? g.OV[1] : g.OV[2];
+    const int rows = __builtin_amdgcn_readfirstlane(ra == 0 ? g.T[0] : g.T[1]);
+    const int cols = __builtin_amdgcn_readfirstlane(ax == 0 ? g.OV[0] : ax == 1 ? g.OV[1] : g.OV[2]);
+    const int flip = (f.orient >> ax) & 1;
+    // window strides: cell(y, w) = y * rs + wc(w) * as + sl * ss
+    const int st[3] = {1, g.T[0], g.T[0] * g.T[1]};
+    const int rs = ra == 0 ? st[0] : st[1];
+    const int as = ax == 0 ? st[0] : ax == 1 ? st[1] : st[2];
+    const int ss = sa < 0 ? 0 : sa == 0 ? st[0] : sa == 1 ? st[1] : st[2];
+    const int tax = ax == 0 ? g.T[0] : ax == 1 ? g.T[1] : g.T[2];
     const int w = lane;
     const bool on = w < cols;
-    int ev[ROWS];
+    const int base = (flip ? tax - 1 - w : w) * as + sl * ss;   // cell of (0, w)
+    // squared differences, read up front; columns outside the overlap hold
+    // the largest value and stay there (saturating add)
+    constexpr uint32_t kBig = 0xFFFFFFFFu;
+    uint32_t ev[ROWS];
 #pragma unroll
-    for (int y = 0; y < ROWS; ++y)
-      ev[y] = (on && y < rows) ? seam_err(g, s_sg, P, f.orient, ax, ra, sa, sl, y, w) : 0;
+    for (int y = 0; y < ROWS; ++y) {
+      ev[y] = kBig;
+      if (on && y < rows) {
+        const int c = base + y * rs;
+        const int d = (int)s_sg[c] - (int)P[c];
+        ev[y] = (uint32_t)(d * d);
+      }
+    }
     uint32_t choice[ROWS / 16];
 #pragma unroll
     for (int q = 0; q < ROWS / 16; ++q) choice[q] = 0;
-    int E = on ? ev[0] : INT_MAX;
+    uint32_t E = ev[0];
 #pragma unroll
     for (int y = 1; y < ROWS; ++y) {
-      if (y < rows) {   // wave-uniform
-        const int left = __builtin_amdgcn_update_dpp(INT_MAX, E, 0x111, 0xF, 0xF, false);   // lane w-1
-        const int right = __builtin_amdgcn_update_dpp(INT_MAX, E, 0x101, 0xF, 0xF, false);  // lane w+1
-        const int lr = min(left, right);
-        const int m = min(E, lr);
-        const uint32_t c = E <= lr ? 0u : (left <= right ? 1u : 2u);
+      if (y < rows) {   // scalar branch
+        const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp((int)kBig, (int)E, 0x111, 0xF, 0xF, false);
+        const uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp((int)kBig, (int)E, 0x101, 0xF, 0xF, false);
+        const uint32_t lr = min(left, right);
+        const uint32_t m = min(E, lr);
+        const uint32_t c = E <= lr ? 0u : (left <= right ? 1u : 2u);   // off the dependency chain
         choice[y >> 4] |= c << (2 * (y & 15));
-        E = on ? ev[y] + m : INT_MAX;
+        E = __builtin_elementwise_add_sat(ev[y], m);
       }
     }
     // end of the seam: smallest cumulative error, smallest column on ties
-    int bE = on ? E : INT_MAX, bw = w;
+    uint32_t bE = on ? E : kBig;
+    int bw = w;
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) {
-      const int oE = __shfl_xor(bE, m, 16), ow = __shfl_xor(bw, m, 16);
+      const uint32_t oE = (uint32_t)__shfl_xor((int)bE, m, 16);
+      const int ow = __shfl_xor(bw, m, 16);
       if (oE < bE || (oE == bE && ow < bw)) { bE = oE; bw = ow; }
     }
     int sc = __builtin_amdgcn_readfirstlane(bw);
@@ -1137,11 +1158,12 @@ __device__ void seam_dp_wave(const Geom& g, const FilterDev& f, const int8_t* s_
         }
       }
     }
-    if (lane < rows)
-      for (int ww = 0; ww < my_seam; ++ww) keep[seam_cell(g, f.orient, ax, ra, sa, sl, lane, ww)] = 1;
+    if (lane < rows) {
+      const int rb = lane * rs + sl * ss;
+      for (int ww = 0; ww < my_seam; ++ww) keep[rb + (flip ? tax - 1 - ww : ww) * as] = 1;
+    }
   }
 }
-
 
 template <int ND, int ROWS, int TJ>
 __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
