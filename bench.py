@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--n-real", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and precision-split side measurements")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     return ap.parse_args()
@@ -69,6 +71,68 @@ def cpu_baseline(p, ti, hd, budget_s=10.0, max_reps=8):
         reps += 1
     return {"value": cells * sample_real * reps / t_total, "unit": "cells/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} x realization 0 of the workload ({cells} cells each), {t_total:.1f} s"}
+
+
+def _time_runs(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def measure_forms(cc, wl, dev):
+    """Side measurements of the batched and precision-split forms.
+
+    batched: the 64-realization workload in one call against the same 64
+    realizations simulated one call at a time (same kernels, same results).
+    precision_split: the 3D workload with an fp16 bulk scan and exact
+    rescoring of a 32-shortlist; the report gives the largest bulk-vs-exact
+    score difference over every rescored candidate."""
+    import numpy as np
+    import torch
+    out = {}
+    p, ti, hd = wl.make("c4_batched")
+    nd = len(p["ti"])
+    ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+    sim = cc.Simulator(p, device=dev)
+    hd_d = cc.hd_to_device(hd, nd, device=dev)
+    t_batch = _time_runs(lambda: sim.run(ti_d, hd_d), 3)
+    cells = p["n_real"] * int(np.prod(p["grid"]))
+    # one realization per call: realization r keeps its own hard data
+    p1 = dict(p, n_real=1)
+    sims, hds = [], []
+    for r in range(p["n_real"]):
+        q = dict(p1, seed=p["seed"])
+        sel = hd[0] == r
+        hr = (np.zeros(int(sel.sum()), np.int32), hd[1][sel], hd[2][sel])
+        q["max_hard_data"] = int(sel.sum())
+        sims.append(cc.Simulator(q, device=dev))
+        hds.append(cc.hd_to_device(hr, nd, device=dev))
+    def one_at_a_time():
+        for s_, h_ in zip(sims, hds):
+            s_.run(ti_d, h_)
+    t_single = _time_runs(one_at_a_time, 2)
+    out["batched"] = {"workload": wl.describe(p), "ms_batched": t_batch * 1e3,
+                      "ms_one_at_a_time": t_single * 1e3, "cells_per_s_batched": cells / t_batch,
+                      "cells_per_s_one_at_a_time": cells / t_single, "speedup": t_single / t_batch}
+    p3, ti3, hd3 = wl.make("c3_split3d")
+    sim3 = cc.Simulator(p3, device=dev)
+    ti3_d = torch.from_numpy(np.ascontiguousarray(ti3)).to(dev)
+    t3 = _time_runs(lambda: sim3.run(ti3_d, None), 3)
+    rep = sim3.report()
+    p3b = dict(p3, shortlist=0)
+    sim3b = cc.Simulator(p3b, device=dev)
+    t3b = _time_runs(lambda: sim3b.run(ti3_d, None), 3)
+    out["precision_split"] = {"workload": wl.describe(p3), "bulk": "fp16 in / fp32 accumulate",
+                              "shortlist": p3["shortlist"], "cells_per_s": int(np.prod(p3["grid"])) / t3,
+                              "cells_per_s_without_rescoring": int(np.prod(p3["grid"])) / t3b,
+                              "max_abs_score_error_vs_exact": rep["max_abs_error"],
+                              "candidates_rescored": rep["rescored"], "topk_changed": rep["topk_changed"]}
+    return out
 
 
 def main():
@@ -155,6 +219,9 @@ def main():
         res["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                            "frac": achieved / peak, "traffic": traffic, "kernel": kind,
                            "dominant_by_time": dom, "us_per_launch": us}
+
+    if not a.no_forms:
+        res["forms"] = measure_forms(cc, wl, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, ti, hd)

@@ -228,7 +228,8 @@ int ccwsim_profile_read(double* ms, int64_t* launches);
 
 /* ccwsim_simulate captures its launch sequence into a HIP graph the first
  * time it sees a (parameters, buffers) combination and replays the graph on
- * later calls (up to 8 graphs are kept; the profiler bypasses them).
+ * later calls (up to 64 graphs are kept, least recently used dropped first; the profiler
+ * bypasses them).
  * ccwsim_set_graphs(0) switches to plain launches and drops the graphs. */
 int ccwsim_set_graphs(int on);
 

@@ -18,6 +18,9 @@
 
 using namespace ccw;
 
+constexpr int kSeamRowsMax = 64;   // longest seam of the register dynamic programme
+constexpr int kMaxSucc = 64;       // overlapping successors of one patch
+
 // ===========================================================================
 // errors
 // ===========================================================================
@@ -120,6 +123,8 @@ int geom_grid(Geom& g, const ccwsim_shape& grid, const int32_t OV[3], const int3
     g.pad[a] = used ? g.lat[a] * g.stride[a] + g.OV[a] : 1;
   }
   g.pcells = (long long)g.pad[0] * g.pad[1] * g.pad[2];
+  // kernels address a realization's padded grid with 32-bit offsets
+  if (g.pcells > 0x7FFFFFFFll) return fail(CCWSIM_ERR_SHAPE, "padded grid of %lld cells exceeds 2^31 - 1", g.pcells);
   return CCWSIM_OK;
 }
 
@@ -485,7 +490,7 @@ struct Plan {
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
   int tree_level = 0;   // 1 or 2: block-subtree coefficients; 0: planar details
-  int dp_stride = 0, dp_batch = 0, rows_max = 0, dp_wave = 0;
+  int dp_stride = 0, dp_batch = 0, rows_max = 0, dp_wave = 0, dp_evs = 0;
   ~Plan() {
     if (tbl) (void)hipHostFree(tbl);
   }
@@ -727,6 +732,47 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   for (int o = 0; o < P.n_orient; ++o)
     for (size_t i = 0; i < klists[o].size(); ++i) kbeta[(size_t)o * kKMax + i] = klists[o][i];
 
+  // the coefficient tree layout serves J = 1 and 2
+  P.tree_level = (g.level == 1 || g.level == 2) ? g.level : 0;
+
+  // finalize LDS: idwt buffers, pattern, keep mask, grid and hard-data
+  // windows, keys of the best rows, cut scratch
+  P.buf_cells = idwt_buf_cells(g);
+  const long long wpad = (g.wcells + 15) & ~15ll;
+  int maxcols = 1;
+  P.rows_max = 1;
+  for (int a = 0; a < nd; ++a) {
+    const int ra = a == 0 ? 1 : 0;
+    P.rows_max = std::max(P.rows_max, g.T[ra]);
+    maxcols = std::max(maxcols, g.OV[a]);
+  }
+  P.dp_wave = maxcols <= 16 && P.rows_max <= kSeamRowsMax;
+  const int ksel = std::min(p.shortlist > 0 ? p.shortlist : p.top_k, g.ncand);
+  const long long cand_bytes = (long long)ksel * g.cand[0] * 8;
+  P.cand_cap = cand_bytes <= 24 * 1024 ? (long long)ksel * g.cand[0] : 0;
+  if (ksel > kTopMax && (P.cand_cap == 0 || (long long)g.cand[1] * g.cand[2] > P.cand_cap))
+    return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist of %d needs %lld B of keys in LDS", ksel, cand_bytes);
+  const size_t fixed = (size_t)P.buf_cells * 8 + 4 * (size_t)wpad + (size_t)P.cand_cap * 8;
+  const long long budget = 60 * 1024;
+  if (P.dp_wave) {
+    // squared differences of the seams, [wave][column][step] with a padded
+    // step stride; the area begins at the key list, which is free by then
+    P.dp_evs = (int)(((P.rows_max + 7) & ~7) + 4);
+    const long long ev_bytes = 4ll * 16 * P.dp_evs * 4 + 16;
+    P.dp_stride = (int)align256(std::max<long long>(256, ev_bytes - P.cand_cap * 8));
+    P.dp_batch = 1;
+  } else {
+    P.dp_stride = (int)align256((long long)P.rows_max * maxcols + (long long)maxcols * 8 + 16);
+    P.dp_batch = (int)std::min<long long>(kThreads, (budget - (long long)fixed) / P.dp_stride);
+  }
+  if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
+  P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride + (size_t)((2 * g.tcells * 4 + 15) & ~15ll);
+  if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
+  // the coefficient staging area aliases the key list and the cut scratch
+  const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
+  P.coef_lds = !P.tree_level && g.level > 0 && P.cand_cap > 0 && idwt_coef_count(g) * 4 <= alias_bytes;
+
   // pinned table block
   P.off_kbeta = 0;
   P.off_nbt = align256(kbeta.size() * 4);
@@ -758,7 +804,6 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   long long o = 0;
   P.ws_kh = o;        o += align256(gcells * 2);
   P.ws_ki = o;        o += align256(gcells * 4);
-  P.tree_level = (g.level == 1 || g.level == 2) ? g.level : 0;
   P.ws_det = o;       o += align256(std::max(1ll, P.tree_level ? (long long)g.np[0] * g.np[1] * g.np[2] : g.det_total) * 4);
   P.ws_tmp = o;       o += align256(2 * c1 * 4);
   P.ws_energy = o;    o += align256((long long)P.n_shapes * g.ncand * 4);
@@ -774,39 +819,6 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
   P.ws_total = o;
 
-  // finalize LDS: idwt buffers, pattern, keep mask, grid and hard-data
-  // windows, keys of the best rows, cut scratch
-  P.buf_cells = idwt_buf_cells(g);
-  const long long wpad = (g.wcells + 15) & ~15ll;
-  int maxcols = 1;
-  P.rows_max = 1;
-  for (int a = 0; a < nd; ++a) {
-    const int ra = a == 0 ? 1 : 0;
-    P.rows_max = std::max(P.rows_max, g.T[ra]);
-    maxcols = std::max(maxcols, g.OV[a]);
-  }
-  P.dp_wave = maxcols <= 16 && P.rows_max <= 64;
-  const int ksel = std::min(p.shortlist > 0 ? p.shortlist : p.top_k, g.ncand);
-  const long long cand_bytes = (long long)ksel * g.cand[0] * 8;
-  P.cand_cap = cand_bytes <= 24 * 1024 ? (long long)ksel * g.cand[0] : 0;
-  if (ksel > kTopMax && (P.cand_cap == 0 || (long long)g.cand[1] * g.cand[2] > P.cand_cap))
-    return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist of %d needs %lld B of keys in LDS", ksel, cand_bytes);
-  const size_t fixed = (size_t)P.buf_cells * 8 + 4 * (size_t)wpad + (size_t)P.cand_cap * 8;
-  const long long budget = 60 * 1024;
-  if (P.dp_wave) {
-    P.dp_stride = 256;   // no scratch: the seams live in registers
-    P.dp_batch = 1;
-  } else {
-    P.dp_stride = (int)align256((long long)P.rows_max * maxcols + (long long)maxcols * 8 + 16);
-    P.dp_batch = (int)std::min<long long>(kThreads, (budget - (long long)fixed) / P.dp_stride);
-  }
-  if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
-    return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
-  P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride + (size_t)((g.tcells * 4 + 15) & ~15ll);
-  if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
-  // the coefficient staging area aliases the key list and the cut scratch
-  const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
-  P.coef_lds = !P.tree_level && g.level > 0 && P.cand_cap > 0 && idwt_coef_count(g) * 4 <= alias_bytes;
   return CCWSIM_OK;
 }
 
@@ -871,17 +883,15 @@ __device__ __forceinline__ void load_window(int8_t* dst, const int8_t* __restric
                                             const Geom& g) {
   constexpr int U = 8;
   const int n = (int)g.wcells;
+  BoxWalk w(threadIdx.x, kThreads, g.T[0], g.T[1]);
   for (int base = threadIdx.x; base < n; base += kThreads * U) {
     int8_t v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int i = base + q * kThreads;
       v[q] = 0;
-      if (i < n) {
-        int ux, uy, uz;
-        split3(i, g.T[0], g.T[1], ux, uy, uz);
-        v[q] = grid[idx3(org[0] + ux, org[1] + uy, org[2] + uz, g.pad)];
-      }
+      if (i < n) v[q] = grid[idx3(org[0] + w.x, org[1] + w.y, org[2] + w.z, g.pad)];
+      w.next();
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -897,6 +907,7 @@ __device__ __forceinline__ void load_windows(int8_t* d0, const int8_t* __restric
                                              const int8_t* __restrict__ g1, const int org[3], const Geom& g) {
   constexpr int U = 8;
   const int n = (int)g.wcells;
+  BoxWalk w(threadIdx.x, kThreads, g.T[0], g.T[1]);
   for (int base = threadIdx.x; base < n; base += kThreads * U) {
     int8_t v0[U], v1[U];
 #pragma unroll
@@ -905,12 +916,11 @@ __device__ __forceinline__ void load_windows(int8_t* d0, const int8_t* __restric
       v0[q] = 0;
       v1[q] = -1;
       if (i < n) {
-        int ux, uy, uz;
-        split3(i, g.T[0], g.T[1], ux, uy, uz);
-        const long long at = idx3(org[0] + ux, org[1] + uy, org[2] + uz, g.pad);
+        const long long at = idx3(org[0] + w.x, org[1] + w.y, org[2] + w.z, g.pad);
         v0[q] = g0[at];
         if (g1) v1[q] = g1[at];
       }
+      w.next();
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -1044,6 +1054,7 @@ struct FinArgs {
   int rows_max;         // longest seam (cells)
   int has_hd;
   int dp_wave;          // 1: every overlap <= 16 cells, one 16-lane group per seam
+  int dp_evs;           // step stride of the seam error buffer (wavefront DP)
   int dp_stride, dp_batch;
 };
 
@@ -1067,24 +1078,34 @@ __device__ __forceinline__ int seam_err(const Geom& g, const int8_t* s_sg, const
   return d * d;
 }
 
-constexpr int kSeamRowsMax = 64;   // longest seam of the register dynamic programme
-constexpr int kMaxSucc = 64;       // overlapping successors of one patch
 
 // Minimal-error boundary cut of every seam of one patch, one wavefront per
-// seam (overlap <= 16 cells, seam <= ROWS cells).  Lane w holds column w
+// seam (overlap <= 16 cells, seam <= 64 cells).  Lane w holds column w
 // (w = 0 faces the already simulated neighbour).  Row by row the cumulative
-// error is E'[w] = e[w] + min(E[w], E[w-1], E[w+1]) with ties preferring w,
-// then w-1, then w+1; the neighbours come from row shifts, and the choice is
-// kept as a 2-bit field per row in registers.  The trace back then walks the
-// choices with a wave-uniform column (register reads only), collecting the
-// seam column of row y in lane y, and the cells before the seam are marked
-// in parallel afterwards.
-template <int ND, int ROWS>
+// error is E'[w] = e[w] + min(E[w], E[w-1], E[w+1]); the wavefront keeps its
+// complement F = ~E instead, for which the recurrence reads
+// F'[w] = max(F[w], F[w-1], F[w+1]) - e[w] (saturating at 0), and a column
+// outside the overlap, or outside the 16-lane row of a row shift, reads as
+// F = 0, i.e. E = infinity.  The seam is padded at the top to a multiple of
+// 8 rows with rows of zero error, which leave F unchanged, so the row loop
+// needs no per-row bound checks.  The errors e of the whole seam are first
+// written to LDS by all 64 lanes (lane = step), so the row loop reads four
+// rows per load.  Each row also records, per column, the step to the row
+// above (0, -1 or +1; ties prefer the same column, then w - 1, then w + 1),
+// off the dependency chain of F.  The trace back starts at the smallest end
+// value (smallest column on ties) and costs one register read per row; the
+// seam column of step s is kept in lane s, and the cells before the seam are
+// marked in parallel afterwards.  Lanes 16..63 run the row loop on copies
+// that never reach lanes 0..15.
+template <int ND>
 __device__ void seam_dp_wave(const Geom& g, const FilterDev& f, const int8_t* s_sg, const int8_t* P,
-                             uint8_t* keep, int n0, int n1, int n2) {
+                             uint8_t* keep, int n0, int n1, int n2, uint32_t* s_ev, int evs) {
+  constexpr int NS = kSeamRowsMax;
+  constexpr uint32_t kBig = 0xFFFFFFFFu;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ndp = __builtin_amdgcn_readfirstlane(n0 + n1 + n2);
+  uint32_t* my_ev = s_ev + wave * 16 * evs;   // [column][step]
   for (int dd = wave; dd < ndp; dd += kThreads / 64) {
     // seam parameters are the same for the whole wavefront: keep them scalar
     const int ax = __builtin_amdgcn_readfirstlane(dd < n0 ? 0 : dd < n0 + n1 ? 1 : 2);
@@ -1100,72 +1121,78 @@ __device__ void seam_dp_wave(const Geom& g, const FilterDev& f, const int8_t* s_
     const int as = ax == 0 ? st[0] : ax == 1 ? st[1] : st[2];
     const int ss = sa < 0 ? 0 : sa == 0 ? st[0] : sa == 1 ? st[1] : st[2];
     const int tax = ax == 0 ? g.T[0] : ax == 1 ? g.T[1] : g.T[2];
-    const int w = lane;
-    const bool on = w < cols;
-    const int base = (flip ? tax - 1 - w : w) * as + sl * ss;   // cell of (0, w)
-    // squared differences, read up front; columns outside the overlap hold
-    // the largest value and stay there (saturating add)
-    constexpr uint32_t kBig = 0xFFFFFFFFu;
-    uint32_t ev[ROWS];
+    const int steps = (rows + 7) & ~7;   // rows padded at the top
+    const int pad = steps - rows;        // step s holds row s - pad
+    // errors of the seam: lane s fills step s of every column
+    {
+      const bool real = lane >= pad && lane < steps;
+      const int rowc = min(max(lane - pad, 0), rows - 1) * rs + sl * ss;
+      int d[16];
 #pragma unroll
-    for (int y = 0; y < ROWS; ++y) {
-      ev[y] = kBig;
-      if (on && y < rows) {
-        const int c = base + y * rs;
-        const int d = (int)s_sg[c] - (int)P[c];
-        ev[y] = (uint32_t)(d * d);
+      for (int w = 0; w < 16; ++w) {
+        const int c = rowc + (flip ? tax - 1 - min(w, tax - 1) : min(w, tax - 1)) * as;
+        d[w] = (int)s_sg[c] - (int)P[c];
+      }
+      asm volatile("" : "+v"(d[0]), "+v"(d[1]), "+v"(d[2]), "+v"(d[3]), "+v"(d[4]), "+v"(d[5]), "+v"(d[6]),
+                   "+v"(d[7]), "+v"(d[8]), "+v"(d[9]), "+v"(d[10]), "+v"(d[11]), "+v"(d[12]), "+v"(d[13]),
+                   "+v"(d[14]), "+v"(d[15]));
+      if (lane < steps) {
+#pragma unroll
+        for (int w = 0; w < 16; ++w)
+          my_ev[w * evs + lane] = w >= cols ? kBig : real ? (uint32_t)__mul24(d[w], d[w]) : 0u;
       }
     }
-    uint32_t choice[ROWS / 16];
+    const uint32_t* ev_row = my_ev + (lane & 15) * evs;
+    int D[NS];   // step to the row above, per step and column
+    uint32_t Fc = lane < cols ? kBig : 0u;
 #pragma unroll
-    for (int q = 0; q < ROWS / 16; ++q) choice[q] = 0;
-    uint32_t E = ev[0];
+    for (int s0 = 0; s0 < NS; s0 += 8) {
+      if (s0 < steps) {   // one scalar branch per 8 rows
+        const uint4 e0 = *(const uint4*)(ev_row + s0);
+        const uint4 e1 = *(const uint4*)(ev_row + s0 + 4);
+        const uint32_t ev[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
 #pragma unroll
-    for (int y = 1; y < ROWS; ++y) {
-      if (y < rows) {   // scalar branch
-        const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp((int)kBig, (int)E, 0x111, 0xF, 0xF, false);
-        const uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp((int)kBig, (int)E, 0x101, 0xF, 0xF, false);
-        const uint32_t lr = min(left, right);
-        const uint32_t m = min(E, lr);
-        const uint32_t c = E <= lr ? 0u : (left <= right ? 1u : 2u);   // off the dependency chain
-        choice[y >> 4] |= c << (2 * (y & 15));
-        E = __builtin_elementwise_add_sat(ev[y], m);
-      }
-    }
-    // end of the seam: smallest cumulative error, smallest column on ties
-    uint32_t bE = on ? E : kBig;
-    int bw = w;
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) {
-      const uint32_t oE = (uint32_t)__shfl_xor((int)bE, m, 16);
-      const int ow = __shfl_xor(bw, m, 16);
-      if (oE < bE || (oE == bE && ow < bw)) { bE = oE; bw = ow; }
-    }
-    int sc = __builtin_amdgcn_readfirstlane(bw);
-    int my_seam = 0;   // lane y: seam column of row y
-#pragma unroll
-    for (int q = ROWS / 16 - 1; q >= 0; --q) {
-#pragma unroll
-      for (int yy = 15; yy >= 0; --yy) {
-        const int y = q * 16 + yy;
-        if (y < rows) {
-          my_seam = lane == y ? sc : my_seam;
-          if (y > 0) {
-            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)choice[q], sc);
-            const uint32_t c = (word >> (2 * yy)) & 3u;
-            sc += c == 1u ? -1 : (c == 2u ? 1 : 0);
-          }
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Fc, 0x111, 0xF, 0xF, true);
+          const uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Fc, 0x101, 0xF, 0xF, true);
+          const uint32_t lr = max(l, r);
+          D[s0 + e] = Fc >= lr ? 0 : (l >= r ? -1 : 1);
+          const uint32_t m = max(Fc, lr);
+          Fc = m > ev[e] ? m - ev[e] : 0u;
         }
       }
     }
-    if (lane < rows) {
-      const int rb = lane * rs + sl * ss;
-      for (int ww = 0; ww < my_seam; ++ww) keep[rb + (flip ? tax - 1 - ww : ww) * as] = 1;
+    // end of the seam: largest F (smallest error), smallest column on ties;
+    // lane 15 ends with the largest F of lanes 0..15
+    uint32_t mx = Fc;
+    mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x111, 0xF, 0xF, true));
+    mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x112, 0xF, 0xF, true));
+    mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x114, 0xF, 0xF, true));
+    mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x118, 0xF, 0xF, true));
+    const uint32_t fmax = (uint32_t)__builtin_amdgcn_readlane((int)mx, 15);
+    const unsigned long long hit = __ballot(Fc == fmax) & 0xFFFFull;
+    int sc = __builtin_amdgcn_readfirstlane(__builtin_ctzll(hit | (1ull << 15)));
+    int seam_of_step = 0;   // lane s: seam column at step s
+#pragma unroll
+    for (int s0 = NS - 8; s0 >= 0; s0 -= 8) {
+      if (s0 < steps) {
+#pragma unroll
+        for (int e = 7; e >= 0; --e) {
+          seam_of_step = lane == s0 + e ? sc : seam_of_step;
+          sc += __builtin_amdgcn_readlane(D[s0 + e], sc);
+        }
+      }
+    }
+    const int y = lane - pad;
+    if (y >= 0 && lane < steps) {
+      const int rb = y * rs + sl * ss;
+      const int sc_y = min(seam_of_step, cols);
+      for (int ww = 0; ww < sc_y; ++ww) keep[rb + (flip ? tax - 1 - ww : ww) * as] = 1;
     }
   }
 }
 
-template <int ND, int ROWS, int TJ>
+template <int ND, int TJ>
 __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ TopkShared sh;
@@ -1174,6 +1201,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   const int tid = threadIdx.x;
   const int slot = blockIdx.x;
   const FilterDev f = a.filters[slot];
+  // the row minima depend on the slot only: fetch them with the record
+  const int nrows_c = g.cand[1] * g.cand[2];
+  uint64_t rm_pre = ~0ull;
+  if (a.cand_cap > 0 && tid < nrows_c) rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
   const long long wpad = (g.wcells + 15) & ~15ll;
   int32_t* bufA = (int32_t*)smem;
   int32_t* bufB = bufA + a.buf_cells;
@@ -1186,13 +1217,19 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
 
   // successor list of this patch (used at the very end), fetched early
   __shared__ int s_mine[kMaxSucc];
+  __shared__ FilterDev s_fq[kMaxSucc];
   __shared__ int s_nmine;
   const int my_nsucc = min(f.nsucc, kMaxSucc);
   int my_succ = 0, my_npred = 0;
+  static_assert(sizeof(FilterDev) == 40, "successor record is moved as five int2");
+  int2 my_fq[5] = {};   // the successor's record, kept in registers until the end
   if (tid < my_nsucc) {
     const int2 e = ((const int2*)a.succ)[f.succ0 + tid];
     my_succ = e.x;
     my_npred = e.y;
+    const int2* src = (const int2*)(a.filters_all + my_succ);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) my_fq[q] = src[q];
   }
   // the block list of this realization's orientation (shared by successors)
   const int my_beta = tid < a.kpad ? a.kbeta[f.orient * kKMax + tid] : -1;
@@ -1222,7 +1259,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     const int kr = min(ksel, nrows);
     uint64_t* s_rm = s_cand;   // staging; the candidate list reuses it afterwards
     if (nrows <= a.cand_cap) {
-      for (int i = tid; i < nrows; i += kThreads) s_rm[i] = rm[i];
+      if (tid < nrows) s_rm[tid] = rm_pre;
+      for (int i = tid + kThreads; i < nrows; i += kThreads) s_rm[i] = rm[i];
       if (tid == 0) s_cnt = 0;
       __syncthreads();
       block_rank_select(s_rm, nrows, kr, s_rowtop);
@@ -1244,16 +1282,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     const int cx = g.cand[0];
     const int nc = kr * cx;
     constexpr int U = 8;
+    BoxWalk w(tid, kThreads, cx, 1 << 30);   // (x, y) = (column, list row)
     for (int base = tid; base < nc; base += kThreads * U) {
       uint64_t v[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         const int i = base + q * kThreads;
         v[q] = ~0ull;
-        if (i < nc) {
-          const int rr = i / cx;
-          v[q] = kf[(long long)s_rows[rr] * cx + (i - rr * cx)];
-        }
+        if (i < nc) v[q] = kf[(long long)s_rows[w.y] * cx + w.x];
+        w.next();
       }
 #pragma unroll
       for (int q = 0; q < U; ++q)
@@ -1359,6 +1396,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   else if (a.coef_lds) idwt_window_lds<ND>(a.Ki, a.det, g, cx, cy, cz, (int32_t*)s_cand, bufA, bufB, P);
   else idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
 
+  int8_t* sgw = a.sg + (long long)f.r * g.pcells;
+  bool interior_done = false;   // cells outside every band already pasted
   if (a.cut && f.bandmask) {
     // seams: one per present band, per slice in 3D
     // seams of band 0 first, then band 1, then band 2; n_a seams per band
@@ -1373,7 +1412,20 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       sa = ND == 3 ? 3 - ax - ra : -1;
     };
     if (a.dp_wave) {
-      seam_dp_wave<ND, ROWS>(g, f, s_sg, P, keep, n0, n1, n2);
+      uint32_t* s_ev = (uint32_t*)(((uintptr_t)s_cand + 15) & ~(uintptr_t)15);
+      seam_dp_wave<ND>(g, f, s_sg, P, keep, n0, n1, n2, s_ev, a.dp_evs);
+      // wavefronts without a seam paste the cells outside every band meanwhile
+      const int busy = min(ndp, kThreads / 64);
+      if (busy < kThreads / 64) {
+        interior_done = true;
+        const int t0 = tid - busy * 64, nt = kThreads - busy * 64;
+        if (t0 >= 0) {
+          BoxWalk w(t0, nt, g.T[0], g.T[1]);
+          for (int i = t0; i < (int)g.wcells; i += nt, w.next())
+            if (s_hd[i] < 0 && !dev_in_band(g, f.orient, f.bandmask, w.x, w.y, w.z))
+              sgw[idx3(f.org[0] + w.x, f.org[1] + w.y, f.org[2] + w.z, g.pad)] = P[i];
+        }
+      }
       __syncthreads();
     } else {
       // wide overlaps: one thread per seam
@@ -1411,13 +1463,30 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     }
   }
   __syncthreads();
-  // paste the new side of every seam, keep hard data
-  int8_t* sgw = a.sg + (long long)f.r * g.pcells;
-  for (int i = tid; i < (int)g.wcells; i += kThreads) {
-    if (s_hd[i] >= 0 || keep[i]) continue;
-    int ux, uy, uz;
-    split3(i, g.T[0], g.T[1], ux, uy, uz);
-    sgw[idx3(f.org[0] + ux, f.org[1] + uy, f.org[2] + uz, g.pad)] = P[i];
+  // paste the new side of every seam, keep hard data (the LDS reads of
+  // eight cells are issued before the first test)
+  {
+    constexpr int U = 8;
+    const int n = (int)g.wcells;
+    BoxWalk w(tid, kThreads, g.T[0], g.T[1]);
+    for (int base = tid; base < n; base += kThreads * U) {
+      int8_t pv[U], hv[U];
+      uint8_t kv[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = min(base + q * kThreads, n - 1);
+        pv[q] = P[i];
+        hv[q] = s_hd[i];
+        kv[q] = keep[i];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (base + q * kThreads < n && hv[q] < 0 && !kv[q] &&
+            !(interior_done && !dev_in_band(g, f.orient, f.bandmask, w.x, w.y, w.z)))
+          sgw[((f.org[2] + w.z) * g.pad[1] + f.org[1] + w.y) * g.pad[0] + f.org[0] + w.x] = pv[q];
+        w.next();
+      }
+    }
   }
   // Successors whose last overlapping predecessor is this patch get their
   // data event here.  Every wavefront first waits for its own stores of the
@@ -1429,73 +1498,75 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   if (tid == 0) s_nmine = 0;
   __syncthreads();
   if (tid < my_nsucc) {
-    if (__hip_atomic_fetch_add(&a.predcnt[my_succ], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1 == my_npred)
-      s_mine[atomicAdd(&s_nmine, 1)] = my_succ;
+    if (__hip_atomic_fetch_add(&a.predcnt[my_succ], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+        my_npred) {
+      const int m = atomicAdd(&s_nmine, 1);
+      s_mine[m] = my_succ;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) ((int2*)&s_fq[m])[q] = my_fq[q];
+    }
   }
   __syncthreads();
   const int nmine = min(s_nmine, kMaxSucc);
-  int* s_msum = (int*)(dps + (long long)a.dp_batch * a.dp_stride);
-  for (int m = 0; m < nmine; ++m) {
-    const FilterDev fq = a.filters_all[s_mine[m]];
-    for (int i = tid; i < (int)g.tcells; i += kThreads) s_msum[i] = 0;
+  int* s_msum = (int*)(dps + (long long)a.dp_batch * a.dp_stride);   // [2][tcells]
+  // overlap cells of the successors, summed per level-J block; with two or
+  // more left, each half of the block takes one, so both sets of reads are
+  // in flight together
+  constexpr int U = 16;
+  const int n = (int)g.wcells;
+  const int lb = g.level;   // block of a cell: coordinates shifted by J on the used axes
+  const int lbz = g.ndim == 3 ? lb : 0;
+  for (int m0 = 0; m0 < nmine;) {
+    const int gm = nmine - m0 >= 2 ? 2 : 1;
+    for (int i = tid; i < gm * (int)g.tcells; i += kThreads) s_msum[i] = 0;
     __syncthreads();
-    // overlap cells of the successor, summed per level-J block
+    const int half = gm == 2 ? tid / (kThreads / 2) : 0;
+    const int t0 = gm == 2 ? tid - half * (kThreads / 2) : tid, nt = kThreads / gm;
+    const FilterDev& fq = s_fq[m0 + half];
+    int* msum = s_msum + half * (int)g.tcells;
     const int8_t* sgq = a.sg + (long long)fq.r * g.pcells;
-    constexpr int U = 8;
-    const int n = (int)g.wcells;
-    for (int base = tid; base < n; base += kThreads * U) {
+    BoxWalk w(t0, nt, g.T[0], g.T[1]);
+    for (int base = t0; base < n; base += nt * U) {
       int v[U], bi[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int i = base + q * kThreads;
         v[q] = 0;
         bi[q] = -1;
-        if (i < n) {
-          int ux, uy, uz;
-          split3(i, g.T[0], g.T[1], ux, uy, uz);
-          if (dev_in_band(g, fq.orient, fq.bandmask, ux, uy, uz)) {
-            v[q] = sgq[idx3(fq.org[0] + ux, fq.org[1] + uy, fq.org[2] + uz, g.pad)];
-            bi[q] = (uz / g.b[2] * g.tc[1] + uy / g.b[1]) * g.tc[0] + ux / g.b[0];
-          }
+        if (base + q * nt < n && dev_in_band(g, fq.orient, fq.bandmask, w.x, w.y, w.z)) {
+          v[q] = sgq[((fq.org[2] + w.z) * g.pad[1] + fq.org[1] + w.y) * g.pad[0] + fq.org[0] + w.x];
+          bi[q] = ((w.z >> lbz) * g.tc[1] + (w.y >> lb)) * g.tc[0] + (w.x >> lb);
         }
+        w.next();
       }
 #pragma unroll
       for (int q = 0; q < U; ++q)
-        if (bi[q] >= 0) atomicAdd(&s_msum[bi[q]], v[q]);
+        if (bi[q] >= 0) atomicAdd(&msum[bi[q]], v[q]);
     }
     __syncthreads();
     if (tid < a.kpad)
-      a.mbuf[(long long)s_mine[m] * kKMax + tid] = (int16_t)(my_beta >= 0 ? s_msum[my_beta] : 0);
+      for (int mm = 0; mm < gm; ++mm)
+        a.mbuf[(long long)s_mine[m0 + mm] * kKMax + tid] =
+            (int16_t)(my_beta >= 0 ? s_msum[mm * (int)g.tcells + my_beta] : 0);
     __syncthreads();
+    m0 += gm;
   }
 }
 
 }  // namespace
 
 namespace {
-// One kernel per (dimension, seam length rounded up to 16) keeps the register
-// dynamic programme at its real trip count.
-void launch_finalize(int ndim, int rows_max, int tree_level, unsigned blocks, size_t lds, hipStream_t st,
-                     const FinArgs& fa) {
-  const int r = rows_max <= 16 ? 16 : rows_max <= 32 ? 32 : rows_max <= 48 ? 48 : 64;
-#define CCW_FIN(ND, R, TJ) k_finalize<ND, R, TJ><<<blocks, kThreads, lds, st>>>(fa)
-#define CCW_FIN_R(ND, TJ)                 \
-  do {                                    \
-    if (r == 16) CCW_FIN(ND, 16, TJ);     \
-    else if (r == 32) CCW_FIN(ND, 32, TJ); \
-    else if (r == 48) CCW_FIN(ND, 48, TJ); \
-    else CCW_FIN(ND, 64, TJ);             \
-  } while (0)
+// One kernel per (dimension, depth of the coefficient tree).
+void launch_finalize(int ndim, int tree_level, unsigned blocks, size_t lds, hipStream_t st, const FinArgs& fa) {
+#define CCW_FIN(ND, TJ) k_finalize<ND, TJ><<<blocks, kThreads, lds, st>>>(fa)
   if (ndim == 2) {
-    if (tree_level == 1) CCW_FIN_R(2, 1);
-    else if (tree_level == 2) CCW_FIN_R(2, 2);
-    else CCW_FIN_R(2, 0);
+    if (tree_level == 1) CCW_FIN(2, 1);
+    else if (tree_level == 2) CCW_FIN(2, 2);
+    else CCW_FIN(2, 0);
   } else {
-    if (tree_level == 1) CCW_FIN_R(3, 1);
-    else if (tree_level == 2) CCW_FIN_R(3, 2);
-    else CCW_FIN_R(3, 0);
+    if (tree_level == 1) CCW_FIN(3, 1);
+    else if (tree_level == 2) CCW_FIN(3, 2);
+    else CCW_FIN(3, 0);
   }
-#undef CCW_FIN_R
 #undef CCW_FIN
 }
 }  // namespace
@@ -1621,6 +1692,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.rows_max = P->rows_max;
   fa.has_hd = n_hd > 0;
   fa.dp_wave = P->dp_wave;
+  fa.dp_evs = P->dp_evs;
   fa.Ki = Ki;
   fa.det = det;
   fa.tree = det;
@@ -1649,7 +1721,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     fa.fbegin = s.fbegin;
     {
       ProfScope ps(CCWSIM_KIND_FINALIZE, st);
-      launch_finalize(g.ndim, P->rows_max, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa);
+      launch_finalize(g.ndim, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -1670,7 +1742,7 @@ struct GraphEntry {
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;   // most recent last
 bool g_graphs_on = true;
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxGraphs = 64;
 
 void drop_graphs() {
   for (GraphEntry& e : g_graphs) (void)hipGraphExecDestroy(e.exec);

@@ -14,6 +14,24 @@ constexpr int kThreads = 256;   // every kernel here runs 4 wavefronts of 64
 constexpr int kTopMax = 16;     // largest K handled by block_topk
 constexpr int kShortMax = 32;   // longest shortlist rescored exactly
 
+// Coordinates of the cells start, start + step, start + 2 step, ... of an
+// e0 x e1 x (..) box in x-fastest order, advanced with adds and compares
+// instead of a division per cell (the step is split once).
+struct BoxWalk {
+  int x, y, z, dx, dy, dz, e0, e1;
+  __device__ __forceinline__ BoxWalk(int start, int step, int e0_, int e1_) : e0(e0_), e1(e1_) {
+    split3(start, e0, e1, x, y, z);
+    split3(step, e0, e1, dx, dy, dz);
+  }
+  __device__ __forceinline__ void next() {
+    x += dx;
+    y += dy;
+    z += dz;
+    if (x >= e0) { x -= e0; ++y; }
+    if (y >= e1) { y -= e1; ++z; }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Forward Haar DWT, one level (Sec. 3.1 filter-and-decimate steps done as a
 // separable two-point lifting per axis).  One thread per level-j cell: it
@@ -367,7 +385,15 @@ __device__ __forceinline__ void block_rank_select(const uint64_t* v, int n, int 
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const uint64_t x = v[i];
     int rank = 0;
-    for (int j = 0; j < n; ++j) rank += v[j] < x ? 1 : 0;
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {   // eight reads in flight per wait
+      uint64_t y[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y[e] = v[j + e];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rank += y[e] < x ? 1 : 0;
+    }
+    for (; j < n; ++j) rank += v[j] < x ? 1 : 0;
     if (rank < k) out[rank] = x;
   }
   __syncthreads();

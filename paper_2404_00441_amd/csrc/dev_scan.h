@@ -120,17 +120,15 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   {
     constexpr int U = 8;
     const int n = nrows * W;
+    BoxWalk w(tid, kThreads, W, g.tc[1]);   // (x, by, bz) of strip entry i
     for (int base = tid; base < n; base += kThreads * U) {
       OT v[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         const int i = base + q * kThreads;
         v[q] = (OT)0.0f;
-        if (i < n) {
-          const int rr = i / W, x = i - rr * W;
-          const int by = rr % g.tc[1], bz = rr / g.tc[1];
-          if (x < g.G[0]) v[q] = Kop[idx3(x, cy + by, cz + bz, g.G)];
-        }
+        if (i < n && w.x < g.G[0]) v[q] = Kop[idx3(w.x, cy + w.y, cz + w.z, g.G)];
+        w.next();
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {

@@ -109,3 +109,17 @@ def test_bf16_range_is_rejected(lib):
     q = ccwsim.params_of(p)
     assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q)) == -1
     assert b"bf16" in lib.ccwsim_last_error()
+
+
+@pytest.mark.parametrize("name", ["c1_plain2d", "c2_scale2d", "c3_split3d", "c4_batched", "c5_learned"])
+def test_every_workload_fits_the_kernel_limits(lib, name):
+    # the plan checks LDS budgets and operand ranges before it allocates
+    # anything; without a GPU it stops at the first host allocation instead
+    from paper_2404_00441_amd import ccwsim
+    from paper_2404_00441_amd import workloads as wl
+    p, _, _ = wl.make(name)
+    q = ccwsim.params_of(p)
+    v = lib.ccwsim_simulate_workspace_size(ctypes.byref(q))
+    if v < 0:
+        err = lib.ccwsim_last_error().decode()
+        assert "hipHostMalloc" in err, err
