@@ -72,6 +72,9 @@ int geom_ti(Geom& g, const ccwsim_shape& s, int level) {
     g.np[a] = (n + g.b[a] - 1) / g.b[a] * g.b[a];
     g.G[a] = g.np[a] / g.b[a];
   }
+  // kernels index the (padded) TI and its grids with 32-bit offsets
+  if ((long long)g.np[0] * g.np[1] * g.np[2] > 0x7FFFFFFFll)
+    return fail(CCWSIM_ERR_SHAPE, "padded TI exceeds 2^31 - 1 cells");
   g.beta = g.b[0] * g.b[1] * g.b[2];
   g.log2beta = level * s.ndim;
   for (int j = 0; j <= level; ++j)
@@ -481,8 +484,10 @@ struct Plan {
   std::vector<StepRange> steps;
   // host tables, uploaded on every call (pinned)
   size_t tbl_bytes = 0;
-  unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles | npred | succ_off | succ
-  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_npred = 0, off_succoff = 0, off_succ = 0;
+  unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles | recs | npred | succ_off | succ
+  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_recs = 0, off_npred = 0, off_succoff = 0,
+         off_succ = 0;
+  long long nrecs = 0;
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
             ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_report = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
@@ -635,6 +640,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   }
   std::vector<FilterDev> filters;
   std::vector<TileDev> tiles;
+  std::vector<ScanRec> recs;
   for (auto& lst : by_t) {
     for (const FilterDev& f : lst) {
       P.patches += 1;
@@ -656,6 +662,17 @@ int build_plan(const ccwsim_params& p, Plan& P) {
       i = e;
     }
     sr.tcount = (int)tiles.size() - sr.tbegin;
+    for (int k = sr.tbegin; k < sr.tbegin + sr.tcount; ++k)
+      for (int jj = 0; jj < kFiltersPerTile; ++jj) {
+        ScanRec r = {-1, 0, 0, 0, 0};
+        if (jj < tiles[k].count) {
+          const FilterDev& f = lst[tiles[k].first + jj];
+          r.gidx = sr.fbegin + tiles[k].first + jj;
+          r.shape = f.shape;
+          r.tkey = draw64(p.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
+        }
+        recs.push_back(r);
+      }
     filters.insert(filters.end(), lst.begin(), lst.end());
     P.max_slots = std::max(P.max_slots, sr.fcount);
     P.steps.push_back(sr);
@@ -778,7 +795,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.off_nbt = align256(kbeta.size() * 4);
   P.off_filters = P.off_nbt + align256(nbt.size() * 4);
   P.off_tiles = P.off_filters + align256(filters.size() * sizeof(FilterDev));
-  P.off_npred = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
+  P.off_recs = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
+  P.off_npred = P.off_recs + align256(recs.size() * sizeof(ScanRec));
+  P.nrecs = (long long)recs.size();
   P.off_succoff = P.off_npred + align256(npred.size() * 4);
   P.off_succ = P.off_succoff + align256(succ_off.size() * 4);
   P.tbl_bytes = P.off_succ + align256(succ.size() * 4);
@@ -788,6 +807,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   memcpy(P.tbl + P.off_nbt, nbt.data(), nbt.size() * 4);
   memcpy(P.tbl + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
   memcpy(P.tbl + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
+  memcpy(P.tbl + P.off_recs, recs.data(), recs.size() * sizeof(ScanRec));
   memcpy(P.tbl + P.off_npred, npred.data(), npred.size() * 4);
   memcpy(P.tbl + P.off_succoff, succ_off.data(), succ_off.size() * 4);
   memcpy(P.tbl + P.off_succ, succ.data(), succ.size() * 4);
@@ -987,6 +1007,16 @@ __global__ __launch_bounds__(kThreads) void k_hd_bin(Geom g, const FilterDev* __
   }
   __syncthreads();
   if (!FILL && threadIdx.x == 0) hd_off[fg] = (int32_t)s_cnt;
+}
+
+// Hard-data ranges of the scan records, from the binned offsets.
+__global__ void k_recs_hd(ScanRec* __restrict__ recs, long long n, const int32_t* __restrict__ hd_off) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int gi = recs[i].gidx;
+  if (gi < 0) return;
+  recs[i].hd0 = hd_off[gi];
+  recs[i].nhd = hd_off[gi + 1] - hd_off[gi];
 }
 
 // In-place exclusive scan of n counts (one workgroup); x[n] receives the total.
@@ -1606,6 +1636,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   const int32_t* nbt = (const int32_t*)(tbl + P->off_nbt);
   const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
   const TileDev* tiles = (const TileDev*)(tbl + P->off_tiles);
+  ScanRec* recs = (ScanRec*)(tbl + P->off_recs);
   const int32_t* npred = (const int32_t*)(tbl + P->off_npred);
   const int32_t* succ_off = (const int32_t*)(tbl + P->off_succoff);
   const int32_t* succ = (const int32_t*)(tbl + P->off_succ);
@@ -1649,6 +1680,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
       k_exclusive_scan<<<1, kThreads, 0, st>>>(hd_off, P->nfilters);
       k_hd_bin<true><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
+      k_recs_hd<<<nblocks(P->nrecs), kThreads, 0, st>>>(recs, P->nrecs, hd_off);
     }
     HIP_TRY(hipGetLastError());
   }
@@ -1658,7 +1690,6 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   sa.Kop = Kh;
   sa.kbeta = kbeta;
   sa.mbuf = mbuf;
-  sa.hd_off = hd_off;
   sa.hd_ent = hd_ent;
   sa.energy = energy;
   sa.ti = ti;
@@ -1709,9 +1740,9 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
 
   const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
   for (const StepRange& s : P->steps) {
-    sa.filters = filters + s.fbegin;
     sa.fbegin = s.fbegin;
     sa.tiles = tiles + s.tbegin;
+    sa.recs = recs + (long long)s.tbegin * kFiltersPerTile;
     {
       ProfScope ps(CCWSIM_KIND_SCAN, st);
       if (p->precision == 1) k_scan<__bf16><<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);

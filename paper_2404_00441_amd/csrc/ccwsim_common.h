@@ -52,15 +52,26 @@ constexpr uint32_t kInvA = inv_odd20(kMulA), kInvB = inv_odd20(kMulB);
 static_assert(((kMulA * kInvA) & kMask20) == 1u, "inverse of A");
 static_assert(((kMulB * kInvB) & kMask20) == 1u, "inverse of B");
 
+// Low 32 bits of a product of two values below 2^24 (both operands here
+// are below 2^20, so the low 20 bits are those of the full product); on the
+// GPU this is the full-rate 24-bit multiply.
+CCW_HD uint32_t mul_lo24(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul24(a, b);
+#else
+  return a * b;
+#endif
+}
+
 CCW_HD uint32_t tie_perm(uint32_t x, uint64_t key) {
   const uint32_t k1 = (uint32_t)(key & kMask20);
   const uint32_t k2 = (uint32_t)((key >> 20) & kMask20);
   const uint32_t k3 = (uint32_t)((key >> 40) & kMask20);
   x = (x & kMask20) ^ k1;
-  x = (x * kMulA) & kMask20;
+  x = mul_lo24(x, kMulA) & kMask20;
   x ^= x >> 10;
   x ^= k2;
-  x = (x * kMulB) & kMask20;
+  x = mul_lo24(x, kMulB) & kMask20;
   x ^= x >> 9;
   return (x ^ k3) & kMask20;
 }
@@ -71,10 +82,10 @@ CCW_HD uint32_t tie_perm_inv(uint32_t y, uint64_t key) {
   const uint32_t k3 = (uint32_t)((key >> 40) & kMask20);
   uint32_t x = (y & kMask20) ^ k3;
   x = x ^ (x >> 9) ^ (x >> 18);  // undo x ^= x >> 9 on 20 bits
-  x = (x * kInvB) & kMask20;
+  x = mul_lo24(x, kInvB) & kMask20;
   x ^= k2;
   x = x ^ (x >> 10);             // undo x ^= x >> 10 on 20 bits
-  x = (x * kInvA) & kMask20;
+  x = mul_lo24(x, kInvA) & kMask20;
   return (x ^ k1) & kMask20;
 }
 
@@ -124,5 +135,8 @@ CCW_HD void split3(int i, int e0, int e1, int& x, int& y, int& z) {
 CCW_HD long long idx3(int x, int y, int z, const int d[3]) {
   return (long long)x + (long long)d[0] * ((long long)y + (long long)d[1] * z);
 }
+
+// The same for boxes of fewer than 2^31 cells.
+CCW_HD int idx3i(int x, int y, int z, const int d[3]) { return x + d[0] * (y + d[1] * z); }
 
 }  // namespace ccw

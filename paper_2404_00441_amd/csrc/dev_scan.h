@@ -38,6 +38,13 @@ struct TileDev {
   uint32_t zmask;      // bit j: filter j has no overlap yet (first patch)
 };
 
+struct ScanRec {       // one filter lane of one scan tile (simulate)
+  int32_t gidx;        // patch index over the whole plan, -1 for an empty lane
+  int32_t shape;       // energy row
+  uint64_t tkey;       // tie-break key of the patch
+  int32_t hd0, nhd;    // hard data of the patch's virtual template (set per call)
+};
+
 struct HdEnt {         // one hard datum inside a virtual template
   int16_t u[3];        // offset from the patch origin
   int16_t v;           // code
@@ -48,10 +55,9 @@ struct ScanArgs {
   const void* Kop;             // level-J grid in the operand type (fp16 or bf16)
   const int32_t* kbeta;        // [orient][kKMax] block index or -1 (simulate)
   const TileDev* tiles;        // simulate: tiles of this step
-  const FilterDev* filters;    // simulate: filters of this step
+  const ScanRec* recs;         // simulate: [tile][kFiltersPerTile] records of this step
   const int16_t* mbuf;         // [patch][kKMax] data-event block sums (standalone: [filter])
   const int32_t* energy;       // simulate: [shape][ncand]
-  const int32_t* hd_off;       // simulate: [patch + 1] offsets of each patch's hard data
   const HdEnt* hd_ent;
   const int8_t* ti;
   uint64_t* keys;              // simulate: [slot][ncand]
@@ -97,15 +103,22 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   const int cy = row % g.cand[1], cz = row / g.cand[1];
   const int W = a.W, kpad = a.kpad;
   const int nrows = g.tc[1] * g.tc[2];
+  const int j = lane & 31;          // A row (candidate in chunk) and B/D column (filter)
+  const int g8 = (lane >> 5) * 8;   // this lane's 8 entries of each 16-wide K slice
 
+  // everything this lane's filter needs is in one record, read with the
+  // tile before anything else
   TileDev t;
+  ScanRec rec = {};
   if (a.standalone) {
     t.first = blockIdx.y * kFiltersPerTile;
     t.count = min(kFiltersPerTile, a.n_filters - t.first);
     t.orient = 0;
     t.zmask = 0;
+    rec.gidx = j < t.count ? 0 : -1;
   } else {
     t = a.tiles[blockIdx.y];
+    rec = a.recs[blockIdx.y * kFiltersPerTile + j];
   }
 
   OT* s_strip = (OT*)smem;
@@ -115,6 +128,42 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   const int bstride = kpad + 8;   // halves per filter row (keeps 16 B alignment)
   __shared__ unsigned long long s_rowmin[kFiltersPerTile];
   if (tid < kFiltersPerTile) s_rowmin[tid] = ~0ull;
+
+  const bool fvalid = rec.gidx >= 0;
+  const int slot = t.first + j;
+  const int shift = g.log2beta + 1;
+  const int nchunks = (g.cand[0] + 31) / 32;
+  const long long rowbase = (long long)g.cand[0] * row;
+  const int32_t* erow = a.standalone ? a.scores + (long long)slot * g.ncand
+                                     : a.energy + (long long)rec.shape * g.ncand;
+  // epilogue inputs of a 32-candidate chunk that do not depend on the
+  // contraction: energy and hard-data mismatch counts
+  auto epilogue_inputs = [&](int ch, int (&ev)[16], unsigned (&mis)[16]) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      ev[v] = (fvalid && a.score_mode == 0 && cx < g.cand[0]) ? erow[rowbase + cx] : 0;
+      mis[v] = 0;
+    }
+    const int nhd = fvalid ? rec.nhd : 0;
+    const int J = g.level;   // block factor 2^J on every used axis
+    const int Jz = g.ndim == 3 ? J : 0;
+    for (int h = 0; h < nhd; ++h) {
+      const HdEnt e = a.hd_ent[rec.hd0 + h];
+      const int fy = (cy << J) + e.u[1], fz = (cz << Jz) + e.u[2];
+      if (fy < 0 || fz < 0 || fy >= g.ti[1] || fz >= g.ti[2]) continue;
+      const int8_t* trow = a.ti + (fz * g.ti[1] + fy) * g.ti[0];
+      int8_t tv[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int fx = (cx << J) + e.u[0];
+        tv[v] = (fx >= 0 && fx < g.ti[0] && cx < g.cand[0]) ? trow[fx] : (int8_t)e.v;
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mis[v] += tv[v] != e.v;
+    }
+  };
 
   // K-grid strip: issue every load of a thread before storing any of them
   {
@@ -127,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
       for (int q = 0; q < U; ++q) {
         const int i = base + q * kThreads;
         v[q] = (OT)0.0f;
-        if (i < n && w.x < g.G[0]) v[q] = Kop[idx3(w.x, cy + w.y, cz + w.z, g.G)];
+        if (i < n && w.x < g.G[0]) v[q] = Kop[idx3i(w.x, cy + w.y, cz + w.z, g.G)];
         w.next();
       }
 #pragma unroll
@@ -160,57 +209,16 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
     *(vec8*)(s_B + jj * bstride + k8) = v;
   }
+  // the first chunk's epilogue reads go out before the barrier
+  int ev[16];
+  unsigned mis[16];
+  if (wave < nchunks) epilogue_inputs(wave, ev, mis);
   __syncthreads();
 
-  const int j = lane & 31;          // A row (candidate in chunk) and B/D column (filter)
-  const int g8 = (lane >> 5) * 8;   // this lane's 8 entries of each 16-wide K slice
-  const bool fvalid = j < t.count;
-  const int slot = t.first + j;
-  FilterDev f = {};
-  uint64_t tkey = 0;
-  int nhd = 0, hd0 = 0;
-  if (fvalid && !a.standalone) {
-    f = a.filters[slot];
-    tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
-    if (a.has_hd) {
-      hd0 = a.hd_off[a.fbegin + slot];
-      nhd = a.hd_off[a.fbegin + slot + 1] - hd0;
-    }
-  }
-  const int shift = g.log2beta + 1;
-  const int nchunks = (g.cand[0] + 31) / 32;
-  const long long rowbase = (long long)g.cand[0] * row;
-
+  const uint64_t tkey = rec.tkey;
   uint64_t lane_min = ~0ull;
-  const int32_t* erow = a.standalone ? a.scores + (long long)slot * g.ncand
-                                     : a.energy + (long long)f.shape * g.ncand;
   for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
-    // the epilogue's memory reads (energy, hard-data gathers) do not depend
-    // on the contraction: issue them first so they overlap the MFMA work
-    int ev[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      ev[v] = (fvalid && a.score_mode == 0 && cx < g.cand[0]) ? erow[rowbase + cx] : 0;
-    }
-    unsigned mis[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) mis[v] = 0;
-    for (int h = 0; h < nhd; ++h) {
-      const HdEnt e = a.hd_ent[hd0 + h];
-      const int fy = g.b[1] * cy + e.u[1], fz = g.b[2] * cz + e.u[2];
-      if (fy < 0 || fz < 0 || fy >= g.ti[1] || fz >= g.ti[2]) continue;
-      const int8_t* trow = a.ti + ((long long)fz * g.ti[1] + fy) * g.ti[0];
-      int8_t tv[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int fx = g.b[0] * cx + e.u[0];
-        tv[v] = (fx >= 0 && fx < g.ti[0] && cx < g.cand[0]) ? trow[fx] : (int8_t)e.v;
-      }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) mis[v] += tv[v] != e.v;
-    }
+    if (ch != wave) epilogue_inputs(ch, ev, mis);
     float16_t acc = {};
     const int cbase = ch * 32 + j;
     for (int kc = 0; kc < kpad; kc += 16) {
