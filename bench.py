@@ -44,7 +44,33 @@ def parse():
                     help="skip the batched and precision-split side measurements")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain copy kernel of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: counter readings taken on other sources are stale."""
+    import hashlib
+    d = os.path.join(HERE, "paper_2404_00441_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(p, ti, hd, budget_s=10.0, max_reps=8):
@@ -137,6 +163,9 @@ def measure_forms(cc, wl, dev):
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}).",
               file=sys.stderr)
@@ -201,7 +230,7 @@ def main():
         # algorithmic work of each kind per step
         per_step_work = {
             "scan": ("mfma", stats["scan_flops"], "TFLOP/s", PEAK_FP16_TFLOPS, 1e12),
-            "finalize": ("hbm", stats["key_bytes"] / 2, "GB/s", PEAK_HBM_GBS, 1e9),
+            "finalize": ("hbm", stats["fin_bytes"], "GB/s", PEAK_HBM_GBS, 1e9),
         }
         kind = dom if dom in per_step_work else "scan"
         bound, work, unit, peak, scale = per_step_work[kind]
@@ -212,7 +241,8 @@ def main():
         if os.path.exists(a.traffic_json):
             try:
                 tj = json.load(open(a.traffic_json))
-                if tj.get("kernel") == kind and tj.get("workload") == a.workload:
+                if (tj.get("kernel") == kind and tj.get("workload") == a.workload
+                        and tj.get("source_hash") == kernel_source_hash()):
                     traffic = tj.get("bytes_per_launch")
             except (OSError, ValueError):
                 traffic = None

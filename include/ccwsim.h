@@ -198,6 +198,11 @@ typedef struct {
   double scan_flops;
   double key_bytes;        /* candidate keys written by the scan and read by the selection */
   double cells;            /* simulated grid cells, all realizations */
+  double fin_bytes;        /* bytes the per-patch finalize step must move, summed over patches:
+                              grid and hard-data windows (2 T^d), the row minima (8 per candidate
+                              row), the keys of the k best rows, the pattern's coefficients
+                              (4 T^d), the pasted window (T^d) and the successor data event it
+                              completes (its overlap cells plus 2 bytes per block) */
 } ccwsim_plan_stats;
 int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out);
 

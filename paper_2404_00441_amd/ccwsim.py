@@ -101,7 +101,8 @@ KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop")
 class PlanStats(ctypes.Structure):
     _fields_ = [("patches", ctypes.c_int64), ("wavefront_steps", ctypes.c_int64),
                 ("candidates", ctypes.c_int64), ("or_blocks", ctypes.c_int64),
-                ("scan_flops", ctypes.c_double), ("key_bytes", ctypes.c_double), ("cells", ctypes.c_double)]
+                ("scan_flops", ctypes.c_double), ("key_bytes", ctypes.c_double), ("cells", ctypes.c_double),
+                ("fin_bytes", ctypes.c_double)]
 
 
 def _check(fn, status):

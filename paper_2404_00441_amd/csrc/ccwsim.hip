@@ -478,7 +478,7 @@ struct Plan {
   Geom g;
   int n_orient = 0, n_shapes = 0, kpad = 0, W = 0;
   int max_slots = 0, nsteps_raster = 0;
-  long long patches = 0, or_blocks = 0;
+  long long patches = 0, or_blocks = 0, band_cells = 0;
   long long hd_cap = 0;               // hard-data entries of all virtual templates
   int nfilters = 0;
   std::vector<StepRange> steps;
@@ -638,6 +638,17 @@ int build_plan(const ccwsim_params& p, Plan& P) {
           shape_blocks[sh] += hit;
         }
   }
+  // overlap cells per shape
+  std::vector<int> shape_cells(P.n_shapes, 0);
+  for (int sh = 0; sh < P.n_shapes; ++sh) {
+    const int o = sh >> nd, bm = sh & ((1 << nd) - 1);
+    for (int uz = 0; uz < g.T[2]; ++uz)
+      for (int uy = 0; uy < g.T[1]; ++uy)
+        for (int ux = 0; ux < g.T[0]; ++ux) {
+          const int u[3] = {ux, uy, uz};
+          shape_cells[sh] += in_band(g, o, bm, u);
+        }
+  }
   std::vector<FilterDev> filters;
   std::vector<TileDev> tiles;
   std::vector<ScanRec> recs;
@@ -645,6 +656,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     for (const FilterDev& f : lst) {
       P.patches += 1;
       P.or_blocks += shape_blocks[f.shape];
+      P.band_cells += shape_cells[f.shape];
     }
     if (lst.empty()) continue;   // e.g. odd t when the fast path axis has one patch
     std::stable_sort(lst.begin(), lst.end(), [](const FilterDev& x, const FilterDev& y) { return x.orient < y.orient; });
@@ -1878,6 +1890,11 @@ extern "C" int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* 
   out->scan_flops = 2.0 * (double)P->or_blocks * (double)g.ncand;
   out->key_bytes = 2.0 * 8.0 * (double)P->patches * (double)g.ncand;
   out->cells = (double)p->n_real * g.sg[0] * g.sg[1] * g.sg[2];
+  const double rows = (double)g.cand[1] * g.cand[2];
+  const double krows = std::min<double>(std::min(p->shortlist > 0 ? p->shortlist : p->top_k, g.ncand), rows);
+  const double per_patch = 2.0 * g.wcells + 8.0 * rows + 8.0 * krows * g.cand[0] + 4.0 * g.wcells + g.wcells +
+                           2.0 * P->kpad;
+  out->fin_bytes = per_patch * (double)P->patches + (double)P->band_cells;
   return CCWSIM_OK;
 }
 
