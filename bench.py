@@ -110,6 +110,60 @@ def _time_runs(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
+def measure_scan_kernel(cc, wl, dev, reps=20):
+    """The scan kernel alone at the largest filter counts of the batched
+    workloads: M = candidates, K = overlap blocks of an L-shaped overlap,
+    N = filters in flight (realizations x wavefront concurrency).  Data events
+    are synthetic block sums on that overlap; timing comes from events around
+    the scan launch (the energy term is timed separately and excluded)."""
+    import numpy as np
+    import torch
+    out = []
+    for name, n_filters in (("c4_batched", 384), ("c5_learned", 448)):
+        p, ti, _ = wl.make(name, n_real=1)
+        level, T, OV = p["level"], p["tmpl"], p["overlap"]
+        b = 2 ** level
+        tc = [-(-t // b) for t in T]
+        ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+        approx, _ = cc.dwt(ti_d, level)
+        # block counts of the L-shaped overlap (bands on both axes)
+        u = np.zeros((T[1], T[0]), bool)
+        u[:OV[1], :] = True
+        u[:, :OV[0]] = True
+        pad = np.zeros((tc[1] * b, tc[0] * b), int)
+        pad[:T[1], :T[0]] = u
+        n_beta = pad.reshape(tc[1], b, tc[0], b).sum(axis=(1, 3))
+        rng = np.random.default_rng(7)
+        or_n = np.broadcast_to(n_beta, (n_filters,) + n_beta.shape).astype(np.int32).copy()
+        or_m = (rng.integers(0, p["n_facies"], size=or_n.shape) * or_n).astype(np.int32)
+        or_n_d = torch.from_numpy(or_n).to(dev)
+        or_m_d = torch.from_numpy(or_m).to(dev)
+        cand = [(p["ti"][a] - T[a]) // b + 1 for a in range(2)]
+        ncand = cand[0] * cand[1]
+        cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, approx, T, or_n_d, or_m_d)
+        torch.cuda.synchronize()
+        cc.profile_enable(True)
+        cc.profile_read()
+        for _ in range(reps):
+            cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, approx, T, or_n_d, or_m_d)
+        torch.cuda.synchronize()
+        prof = cc.profile_read()
+        cc.profile_enable(False)
+        us = 1e3 * prof["scan"][0] / max(prof["scan"][1], 1)
+        blocks = int((n_beta > 0).sum())
+        flops = 2.0 * blocks * ncand * n_filters
+        nbytes = 8.0 * ncand * n_filters + 2.0 * approx.numel() + 512.0 * n_filters
+        tf = flops / (us * 1e-6) / 1e12
+        gb = nbytes / (us * 1e-6) / 1e9
+        out.append({"shape": f"{name}: M={ncand} candidates, K={blocks} overlap blocks (padded to "
+                             f"{-(-blocks // 16) * 16}), N={n_filters} filters",
+                    "us_per_launch": us, "tflops_algorithmic": tf, "frac_mfma_fp16": tf / PEAK_FP16_TFLOPS,
+                    "gbs_algorithmic": gb, "frac_hbm": gb / PEAK_HBM_GBS,
+                    "bound": "hbm" if nbytes / PEAK_HBM_GBS > flops / PEAK_FP16_TFLOPS / 1e3 else "mfma",
+                    "bytes_per_launch": nbytes, "flops_per_launch": flops})
+    return out
+
+
 def measure_forms(cc, wl, dev):
     """Side measurements of the batched and precision-split forms.
 
@@ -252,6 +306,7 @@ def main():
 
     if not a.no_forms:
         res["forms"] = measure_forms(cc, wl, dev)
+        res["scan_kernel"] = measure_scan_kernel(cc, wl, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, ti, hd)

@@ -324,8 +324,10 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   HIP_TRY(hipMallocAsync((void**)&mbuf, (size_t)n_filters * kKMax * 2, st));
   k_to_half<<<nblocks(gcells), kThreads, 0, st>>>(approx, Kh, gcells);
   k_events_to_mbuf<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_m, mbuf, n_filters, g.tcells);
-  if (score_mode == 0)
+  if (score_mode == 0) {
+    ProfScope ps(CCWSIM_KIND_ENERGY, st);
     k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, scores, g);
+  }
   ScanArgs a = {};
   a.g = g;
   a.Kop = Kh;
@@ -337,7 +339,10 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   a.standalone = 1;
   a.n_filters = n_filters;
   dim3 grid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + kFiltersPerTile - 1) / kFiltersPerTile));
-  k_scan<_Float16><<<grid, kThreads, lds, st>>>(a);
+  {
+    ProfScope ps(CCWSIM_KIND_SCAN, st);
+    k_scan<_Float16><<<grid, kThreads, lds, st>>>(a);
+  }
   const hipError_t le = hipGetLastError();
   HIP_TRY(hipFreeAsync(Kh, st));
   HIP_TRY(hipFreeAsync(mbuf, st));
