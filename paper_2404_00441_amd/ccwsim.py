@@ -86,6 +86,8 @@ def load():
     L.ccwsim_set_graphs.argtypes = [ctypes.c_int]
     L.ccwsim_simulate_report.restype = ctypes.c_int
     L.ccwsim_simulate_report.argtypes = [p, p, i64, p, p]
+    L.ccwsim_set_scan_group.restype = ctypes.c_int
+    L.ccwsim_set_scan_group.argtypes = [ctypes.c_int]
     _lib = L
     return L
 
@@ -93,7 +95,7 @@ def load():
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
-           "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report")
+           "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop")
 
@@ -289,6 +291,11 @@ def simulate_stats(p: dict) -> dict:
     s = PlanStats()
     _check("ccwsim_simulate_stats", load().ccwsim_simulate_stats(ctypes.byref(params_of(p)), ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in PlanStats._fields_}
+
+
+def set_scan_group(g: int):
+    """0: tuned tiles per scan workgroup; 1, 2, 4 or 8: forced."""
+    _check("ccwsim_set_scan_group", load().ccwsim_set_scan_group(int(g)))
 
 
 def set_graphs(on: bool):

@@ -152,6 +152,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_scan_g_force = 0;   // 0: tuned choice; else tiles per scan workgroup (testing)
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
 
@@ -285,10 +286,20 @@ __global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int16_t* __re
   mbuf[id] = k < tcells ? (int16_t)or_m[f * tcells + k] : (int16_t)0;
 }
 
-size_t scan_lds_bytes(const Geom& g, int W, int kpad) {
-  const int nrows = g.tc[1] * g.tc[2];
-  const size_t strip = ((size_t)nrows * W * 2 + 15) & ~(size_t)15;
-  return strip + (size_t)kpad * 4 + (size_t)kFiltersPerTile * (kpad + 8) * 2;
+// Launch the scan with up to G tiles per workgroup (G in {1, 2, 4, 8}) over
+// `ngroups` workgroup columns.
+void launch_scan(int precision, int G, unsigned rows, int ngroups, size_t lds, hipStream_t st, const ScanArgs& sa) {
+  const dim3 grid(rows, (unsigned)ngroups);
+#define CCW_SCAN(OT)                                                \
+  do {                                                              \
+    if (G == 8) k_scan<OT, 8><<<grid, kThreads, lds, st>>>(sa);     \
+    else if (G == 4) k_scan<OT, 4><<<grid, kThreads, lds, st>>>(sa); \
+    else if (G == 2) k_scan<OT, 2><<<grid, kThreads, lds, st>>>(sa); \
+    else k_scan<OT, 1><<<grid, kThreads, lds, st>>>(sa);            \
+  } while (0)
+  if (precision == 1) CCW_SCAN(__bf16);
+  else CCW_SCAN(_Float16);
+#undef CCW_SCAN
 }
 
 int scan_strip_width(const Geom& g) {
@@ -313,8 +324,22 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   if (kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kKMax);
   CCW_TRY(check_exact(g, max_code, g.wcells));
   const int W = scan_strip_width(g);
-  const size_t lds = scan_lds_bytes(g, W, kpad);
-  if (lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu bytes of LDS", lds);
+  const int nrows = g.tc[1] * g.tc[2];
+  if (scan_group_lds(nrows, W, kpad, 1) > 64 * 1024)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu bytes of LDS", scan_group_lds(nrows, W, kpad, 1));
+  // tiles per workgroup: the largest that keeps two workgroups per CU in
+  // flight and fits the LDS (every filter here shares the full window)
+  const int ntiles = (n_filters + kFiltersPerTile - 1) / kFiltersPerTile;
+  const long long crow = (long long)g.cand[1] * g.cand[2];
+  int G = 1;
+  auto group_ok = [&](int c) { return kpad <= kScanGroupKMax && scan_group_lds(nrows, W, kpad, c) <= 64 * 1024; };
+  for (int c : {2, 4, 8})
+    if (c <= ntiles && crow * ((ntiles + c - 1) / c) >= 512 && group_ok(c)) G = c;
+  if (g_scan_g_force > 0) {
+    G = 1;
+    for (int c : {2, 4, 8})
+      if (c <= g_scan_g_force && group_ok(c)) G = c;
+  }
 
   hipStream_t st = as_stream(stream);
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
@@ -338,10 +363,10 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   a.score_mode = score_mode;
   a.standalone = 1;
   a.n_filters = n_filters;
-  dim3 grid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + kFiltersPerTile - 1) / kFiltersPerTile));
+  a.ntiles = ntiles;
   {
     ProfScope ps(CCWSIM_KIND_SCAN, st);
-    k_scan<_Float16><<<grid, kThreads, lds, st>>>(a);
+    launch_scan(0, G, (unsigned)crow, (ntiles + G - 1) / G, scan_group_lds(nrows, W, kpad, G), st, a);
   }
   const hipError_t le = hipGetLastError();
   HIP_TRY(hipFreeAsync(Kh, st));
@@ -470,6 +495,7 @@ namespace {
 struct StepRange {
   int fbegin, fcount;  // filters of this wavefront step (consecutive)
   int tbegin, tcount;  // tiles of this step
+  int gbegin[4], gcount[4];   // scan workgroups of 1, 2, 4, 8 tiles of one orientation
 };
 
 struct DpDesc {        // one boundary-cut dynamic programme
@@ -482,6 +508,9 @@ struct DpDesc {        // one boundary-cut dynamic programme
 struct Plan {
   Geom g;
   int n_orient = 0, n_shapes = 0, kpad = 0, W = 0;
+  int scan_g_max = 1;                 // most tiles one scan workgroup may take (LDS)
+  int scan_g = 1;                     // tiles per scan workgroup (tuned)
+  bool tuned = false;
   int max_slots = 0, nsteps_raster = 0;
   long long patches = 0, or_blocks = 0, band_cells = 0;
   long long hd_cap = 0;               // hard-data entries of all virtual templates
@@ -490,8 +519,8 @@ struct Plan {
   // host tables, uploaded on every call (pinned)
   size_t tbl_bytes = 0;
   unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles | recs | npred | succ_off | succ
-  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_recs = 0, off_npred = 0, off_succoff = 0,
-         off_succ = 0;
+  size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_recs = 0, off_groups = 0, off_npred = 0,
+         off_succoff = 0, off_succ = 0;
   long long nrecs = 0;
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
@@ -589,8 +618,6 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld are not exact in bf16",
                 (long long)(p.n_facies - 1) * g.beta);
   P.W = scan_strip_width(g);
-  P.scan_lds = scan_lds_bytes(g, P.W, P.kpad);
-  if (P.scan_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu B of LDS", P.scan_lds);
 
   // schedule: anti-diagonal wavefronts when same-step windows are disjoint
   bool wave_ok = true;
@@ -626,6 +653,20 @@ int build_plan(const ccwsim_params& p, Plan& P) {
       by_t[t].push_back(f);
     }
   }
+  // Scan LDS for one tile per workgroup; up to 8 tiles of one orientation
+  // may share a workgroup (and its A gather) when the LDS allows.
+  {
+    int kl = 0;
+    for (int o = 0; o < P.n_orient; ++o) kl = std::max<int>(kl, (int)klists[o].size());
+    P.kpad = std::max(16, (kl + 15) / 16 * 16);
+    const int nrows = g.tc[1] * g.tc[2];
+    P.scan_g_max = 1;
+    for (int G : {2, 4, 8})
+      if (P.kpad <= kScanGroupKMax && scan_group_lds(nrows, P.W, P.kpad, G) <= 64 * 1024) P.scan_g_max = G;
+    P.scan_lds = scan_group_lds(nrows, P.W, P.kpad, 1);
+    if (P.scan_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu B of LDS", P.scan_lds);
+  }
+
   // overlap blocks holding known cells, per shape (the method's K dimension)
   std::vector<int> shape_blocks(P.n_shapes, 0);
   for (int sh = 0; sh < P.n_shapes; ++sh) {
@@ -657,6 +698,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   std::vector<FilterDev> filters;
   std::vector<TileDev> tiles;
   std::vector<ScanRec> recs;
+  std::vector<int2> groups;   // (first tile within the step, tiles)
   for (auto& lst : by_t) {
     for (const FilterDev& f : lst) {
       P.patches += 1;
@@ -679,6 +721,17 @@ int build_plan(const ccwsim_params& p, Plan& P) {
       i = e;
     }
     sr.tcount = (int)tiles.size() - sr.tbegin;
+    for (int gi = 0; gi < 4; ++gi) {
+      const int G = 1 << gi;
+      sr.gbegin[gi] = (int)groups.size();
+      for (int k = sr.tbegin; k < sr.tbegin + sr.tcount;) {
+        int e = k + 1;
+        while (e < sr.tbegin + sr.tcount && e - k < G && tiles[e].orient == tiles[k].orient) ++e;
+        groups.push_back({k - sr.tbegin, e - k});
+        k = e;
+      }
+      sr.gcount[gi] = (int)groups.size() - sr.gbegin[gi];
+    }
     for (int k = sr.tbegin; k < sr.tbegin + sr.tcount; ++k)
       for (int jj = 0; jj < kFiltersPerTile; ++jj) {
         ScanRec r = {-1, 0, 0, 0, 0};
@@ -813,7 +866,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.off_filters = P.off_nbt + align256(nbt.size() * 4);
   P.off_tiles = P.off_filters + align256(filters.size() * sizeof(FilterDev));
   P.off_recs = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
-  P.off_npred = P.off_recs + align256(recs.size() * sizeof(ScanRec));
+  P.off_groups = P.off_recs + align256(recs.size() * sizeof(ScanRec));
+  P.off_npred = P.off_groups + align256(groups.size() * sizeof(int2));
   P.nrecs = (long long)recs.size();
   P.off_succoff = P.off_npred + align256(npred.size() * 4);
   P.off_succ = P.off_succoff + align256(succ_off.size() * 4);
@@ -825,6 +879,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   memcpy(P.tbl + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
   memcpy(P.tbl + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
   memcpy(P.tbl + P.off_recs, recs.data(), recs.size() * sizeof(ScanRec));
+  memcpy(P.tbl + P.off_groups, groups.data(), groups.size() * sizeof(int2));
   memcpy(P.tbl + P.off_npred, npred.data(), npred.size() * 4);
   memcpy(P.tbl + P.off_succoff, succ_off.data(), succ_off.size() * 4);
   memcpy(P.tbl + P.off_succ, succ.data(), succ.size() * 4);
@@ -1629,9 +1684,17 @@ extern "C" int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p) {
 }
 
 namespace {
+// Tiles per scan workgroup for this plan: the forced value (tests), else
+// the tuned one, within what the LDS allows.
+int scan_group_of(const Plan* P) {
+  int G = g_scan_g_force > 0 ? g_scan_g_force : P->scan_g;
+  if (G > P->scan_g_max) G = P->scan_g_max;
+  return G >= 8 ? 8 : G >= 4 ? 4 : G >= 2 ? 2 : 1;
+}
+
 int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
                      const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen, void* workspace,
-                     hipStream_t st) {
+                     hipStream_t st, int* tune_best = nullptr) {
   const Geom& g = P->g;
   unsigned char* ws = (unsigned char*)workspace;
   _Float16* Kh = (_Float16*)(ws + P->ws_kh);
@@ -1654,6 +1717,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
   const TileDev* tiles = (const TileDev*)(tbl + P->off_tiles);
   ScanRec* recs = (ScanRec*)(tbl + P->off_recs);
+  const int2* groups = (const int2*)(tbl + P->off_groups);
   const int32_t* npred = (const int32_t*)(tbl + P->off_npred);
   const int32_t* succ_off = (const int32_t*)(tbl + P->off_succoff);
   const int32_t* succ = (const int32_t*)(tbl + P->off_succ);
@@ -1756,14 +1820,18 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.dp_batch = P->dp_batch;
 
   const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
+  const int G = scan_group_of(P);
+  const int gix = G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
+  const size_t scan_lds = scan_group_lds(g.tc[1] * g.tc[2], P->W, P->kpad, G);
   for (const StepRange& s : P->steps) {
     sa.fbegin = s.fbegin;
     sa.tiles = tiles + s.tbegin;
     sa.recs = recs + (long long)s.tbegin * kFiltersPerTile;
+    sa.ntiles = s.tcount;
+    sa.groups = groups + s.gbegin[gix];
     {
       ProfScope ps(CCWSIM_KIND_SCAN, st);
-      if (p->precision == 1) k_scan<__bf16><<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
-      else k_scan<_Float16><<<dim3(rows, (unsigned)s.tcount), kThreads, P->scan_lds, st>>>(sa);
+      launch_scan(p->precision, G, rows, s.gcount[gix], scan_lds, st, sa);
     }
     fa.filters = filters + s.fbegin;
     fa.fbegin = s.fbegin;
@@ -1778,6 +1846,46 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     k_crop<<<nblocks((long long)p->n_real * g.sg[0] * g.sg[1] * g.sg[2]), kThreads, 0, st>>>(sg, out, g, p->n_real);
   }
   HIP_TRY(hipGetLastError());
+  if (tune_best) {
+    // time the widest step's scan for every admissible tile count per
+    // workgroup (the run above is complete; the keys written here are scratch)
+    const StepRange* w = &P->steps[0];
+    for (const StepRange& s : P->steps)
+      if (s.tcount > w->tcount) w = &s;
+    sa.fbegin = w->fbegin;
+    sa.tiles = tiles + w->tbegin;
+    sa.recs = recs + (long long)w->tbegin * kFiltersPerTile;
+    sa.ntiles = w->tcount;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 3.4e38f;
+    int best = 1, prev_groups = -1;
+    for (int ci = 0; ci < 4; ++ci) {
+      const int c = 1 << ci;
+      if (c > P->scan_g_max) break;
+      const int ngr = w->gcount[ci];
+      if (ngr == prev_groups) break;   // larger groups would change nothing
+      prev_groups = ngr;
+      sa.groups = groups + w->gbegin[ci];
+      const size_t l = scan_group_lds(g.tc[1] * g.tc[2], P->W, P->kpad, c);
+      launch_scan(p->precision, c, rows, ngr, l, st, sa);
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) launch_scan(p->precision, c, rows, ngr, l, st, sa);
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms * 0.97f) {   // a larger group must be clearly faster
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipGetLastError());
+    *tune_best = best;
+  }
   return CCWSIM_OK;
 }
 }  // namespace
@@ -1798,6 +1906,73 @@ void drop_graphs() {
 }
 }  // namespace
 
+namespace {
+// Tuned tile counts per scan workgroup, keyed by the scan's shape; kept in
+// memory and, when CCWSIM_TUNE_FILE names a file, in that JSON object.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Plan* P, const ccwsim_params* p) {
+  const Geom& g = P->g;
+  int maxt = 0;
+  for (const StepRange& s : P->steps) maxt = std::max(maxt, s.tcount);
+  char buf[256];
+  snprintf(buf, sizeof buf, "d%d_cand%dx%dx%d_tc%dx%dx%d_k%d_tiles%d_prec%d_hd%d", g.ndim, g.cand[0], g.cand[1],
+           g.cand[2], g.tc[0], g.tc[1], g.tc[2], P->kpad, maxt, p->precision, p->max_hard_data > 0 ? 1 : 0);
+  return buf;
+}
+
+void tune_load_once() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* f = getenv("CCWSIM_TUNE_FILE");
+  if (!f) return;
+  FILE* fp = fopen(f, "r");
+  if (!fp) return;
+  char line[512], key[400];
+  int v = 0;
+  while (fgets(line, sizeof line, fp))
+    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2 && (v == 1 || v == 2 || v == 4 || v == 8)) g_tune[key] = v;
+  fclose(fp);
+}
+
+void tune_save() {
+  const char* f = getenv("CCWSIM_TUNE_FILE");
+  if (!f) return;
+  FILE* fp = fopen(f, "w");
+  if (!fp) return;
+  fprintf(fp, "{\n");
+  size_t i = 0;
+  for (const auto& kv : g_tune) fprintf(fp, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < g_tune.size() ? "," : "");
+  fprintf(fp, "}\n");
+  fclose(fp);
+}
+
+// Before tuning: the largest tile count that still gives two workgroups per
+// CU on the widest step.
+int scan_group_guess(const Plan* P) {
+  int maxt = 0;
+  for (const StepRange& s : P->steps) maxt = std::max(maxt, s.tcount);
+  const long long rows = (long long)P->g.cand[1] * P->g.cand[2];
+  int G = 1;
+  for (int c : {2, 4, 8})
+    if (c <= P->scan_g_max && c <= maxt && rows * ((maxt + c - 1) / c) >= 512) G = c;
+  return G;
+}
+}  // namespace
+
+extern "C" int ccwsim_set_scan_group(int g) {
+  if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8)
+    return fail(CCWSIM_ERR_INVALID_ARG, "tiles per scan workgroup must be 0 (tuned), 1, 2, 4 or 8");
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    drop_graphs();   // captured graphs hold the previous choice
+  }
+  g_scan_g_force = g;
+  return CCWSIM_OK;
+}
+
 extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
                                const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
                                void* workspace, int64_t workspace_bytes, void* stream) {
@@ -1816,6 +1991,34 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof = g_prof_on;
+  }
+  // First call of a plan whose scan may take several tiles per workgroup:
+  // look the shape up in the tuning table, else run eagerly once (a full,
+  // valid call) and time the widest step's scan for each tile count.
+  if (!P->tuned && g_scan_g_force == 0 && P->scan_g_max > 1) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_once();
+    const std::string tk = tune_key(P, p);
+    const auto it = g_tune.find(tk);
+    if (it != g_tune.end()) {
+      P->scan_g = it->second;
+      P->tuned = true;
+    } else {
+      hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+      HIP_TRY(hipStreamIsCapturing(st, &cst));
+      P->scan_g = scan_group_guess(P);
+      if (cst == hipStreamCaptureStatusNone) {
+        int best = P->scan_g;
+        const int rc = enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, st, &best);
+        if (rc == CCWSIM_OK) {
+          P->scan_g = best;
+          P->tuned = true;
+          g_tune[tk] = best;
+          tune_save();
+        }
+        return rc;
+      }
+    }
   }
   if (prof || !g_graphs_on)
     return enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, st);
@@ -1878,6 +2081,11 @@ extern "C" void ccwsim_release_caches(void) {
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     drop_graphs();
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = false;
   }
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plans.clear();

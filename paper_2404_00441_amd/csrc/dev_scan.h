@@ -18,6 +18,7 @@
 namespace ccw {
 
 constexpr int kKMax = 256;   // longest padded list of overlap blocks
+constexpr int kScanGroupKMax = 128;   // longest list for workgroups of several tiles
 constexpr int kFiltersPerTile = 32;
 
 struct FilterDev {     // one (realization, patch) pair active in a step
@@ -71,6 +72,8 @@ struct ScanArgs {
   int standalone;              // 1: filters/tiles/kbeta are implicit
   int n_filters;               // standalone: number of filters
   int has_hd;
+  int ntiles;                  // tiles of this launch
+  const int2* groups;          // simulate: per workgroup column (first tile, tiles), one orientation
 };
 
 template <typename OT>
@@ -90,11 +93,24 @@ struct MfmaOp<__bf16> {
   }
 };
 
+// LDS bytes of a scan workgroup taking G tiles.
+inline size_t scan_group_lds(int nrows, int W, int kpad, int G) {
+  const size_t strip = ((size_t)nrows * W * 2 + 15) & ~(size_t)15;
+  return strip + (size_t)kpad * 4 + (size_t)G * kFiltersPerTile * (kpad + 8) * 2 +
+         (size_t)G * kFiltersPerTile * (sizeof(ScanRec) + 8);
+}
+
 // Operand type OT: _Float16 (exact for integers <= 2048) or __bf16 (exact for
-// integers <= 256); accumulation is fp32 either way.
-template <typename OT>
-__global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+// integers <= 256); accumulation is fp32 either way.  Up to G tiles of one
+// orientation per workgroup: the candidate row's A fragments are gathered
+// once per 32-candidate chunk and serve all of them (they share one block
+// list), so the strip staging, the gather and the prologue's memory round
+// trips are paid once per group.
+template <typename OT, int G>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(G == 1 ? 4 : 2)))
+void k_scan(ScanArgs a) {
   typedef typename MfmaOp<OT>::vec8 vec8;
+  constexpr int KS = kScanGroupKMax / 16;   // K slices kept for a group (G > 1)
   const OT* Kop = (const OT*)a.Kop;
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom& g = a.g;
@@ -105,20 +121,14 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   const int nrows = g.tc[1] * g.tc[2];
   const int j = lane & 31;          // A row (candidate in chunk) and B/D column (filter)
   const int g8 = (lane >> 5) * 8;   // this lane's 8 entries of each 16-wide K slice
-
-  // everything this lane's filter needs is in one record, read with the
-  // tile before anything else
-  TileDev t;
-  ScanRec rec = {};
+  int tile0, nt;
   if (a.standalone) {
-    t.first = blockIdx.y * kFiltersPerTile;
-    t.count = min(kFiltersPerTile, a.n_filters - t.first);
-    t.orient = 0;
-    t.zmask = 0;
-    rec.gidx = j < t.count ? 0 : -1;
+    tile0 = blockIdx.y * G;
+    nt = min(G, a.ntiles - tile0);
   } else {
-    t = a.tiles[blockIdx.y];
-    rec = a.recs[blockIdx.y * kFiltersPerTile + j];
+    const int2 grp = a.groups[blockIdx.y];
+    tile0 = grp.x;
+    nt = grp.y;
   }
 
   OT* s_strip = (OT*)smem;
@@ -126,42 +136,82 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   int* s_off = (int*)(smem + strip_bytes);
   OT* s_B = (OT*)(smem + strip_bytes + kpad * 4);
   const int bstride = kpad + 8;   // halves per filter row (keeps 16 B alignment)
-  __shared__ unsigned long long s_rowmin[kFiltersPerTile];
-  if (tid < kFiltersPerTile) s_rowmin[tid] = ~0ull;
+  ScanRec* s_rec = (ScanRec*)(smem + strip_bytes + kpad * 4 + G * kFiltersPerTile * bstride * 2);
+  unsigned long long* s_rowmin = (unsigned long long*)(s_rec + G * kFiltersPerTile);
+  __shared__ TileDev s_tile[G];
 
-  const bool fvalid = rec.gidx >= 0;
-  const int slot = t.first + j;
+  // tiles and per-lane filter records first (one round trip reaches every
+  // epilogue input); the first tile's record also goes to registers
+  auto tile_of = [&](int gi) {
+    TileDev t;
+    if (a.standalone) {
+      t.first = (tile0 + gi) * kFiltersPerTile;
+      t.count = min(kFiltersPerTile, a.n_filters - t.first);
+      t.orient = 0;
+      t.zmask = 0;
+    } else {
+      t = a.tiles[tile0 + gi];
+    }
+    return t;
+  };
+  auto rec_of = [&](int gi, int jj, const TileDev& t) {
+    ScanRec r = {};
+    if (a.standalone) r.gidx = jj < t.count ? 0 : -1;
+    else r = a.recs[(tile0 + gi) * kFiltersPerTile + jj];
+    return r;
+  };
+  const TileDev t0 = tile_of(0);
+  const ScanRec rec0 = rec_of(0, j, t0);
+  if (tid < nt) s_tile[tid] = tile_of(tid);
+  if (tid < nt * kFiltersPerTile) {
+    const int gi = tid / kFiltersPerTile;
+    s_rec[tid] = rec_of(gi, tid - gi * kFiltersPerTile, tile_of(gi));
+    s_rowmin[tid] = ~0ull;
+  }
+
   const int shift = g.log2beta + 1;
   const int nchunks = (g.cand[0] + 31) / 32;
   const long long rowbase = (long long)g.cand[0] * row;
-  const int32_t* erow = a.standalone ? a.scores + (long long)slot * g.ncand
-                                     : a.energy + (long long)rec.shape * g.ncand;
   // epilogue inputs of a 32-candidate chunk that do not depend on the
   // contraction: energy and hard-data mismatch counts
-  auto epilogue_inputs = [&](int ch, int (&ev)[16], unsigned (&mis)[16]) {
+  auto epilogue_inputs = [&](int ch, const ScanRec& rec, int slot, int (&ev)[16], unsigned (&mis)[16]) {
+    const bool fvalid = rec.gidx >= 0;
+    const int32_t* erow = a.standalone ? a.scores + (long long)slot * g.ncand
+                                       : a.energy + (long long)rec.shape * g.ncand;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       ev[v] = (fvalid && a.score_mode == 0 && cx < g.cand[0]) ? erow[rowbase + cx] : 0;
       mis[v] = 0;
     }
+    // hard data: the next entry is read while the current one's 16 TI
+    // reads (at clamped, always valid cells) are in flight; a datum counts
+    // where it lies inside the TI and the TI differs
     const int nhd = fvalid ? rec.nhd : 0;
     const int J = g.level;   // block factor 2^J on every used axis
     const int Jz = g.ndim == 3 ? J : 0;
+    HdEnt e = {};
+    if (nhd > 0) e = a.hd_ent[rec.hd0];
     for (int h = 0; h < nhd; ++h) {
-      const HdEnt e = a.hd_ent[rec.hd0 + h];
+      const HdEnt en = a.hd_ent[rec.hd0 + min(h + 1, nhd - 1)];
       const int fy = (cy << J) + e.u[1], fz = (cz << Jz) + e.u[2];
-      if (fy < 0 || fz < 0 || fy >= g.ti[1] || fz >= g.ti[2]) continue;
-      const int8_t* trow = a.ti + (fz * g.ti[1] + fy) * g.ti[0];
+      const unsigned ok = (fy >= 0 && fz >= 0 && fy < g.ti[1] && fz < g.ti[2]) ? 1u : 0u;
+      const int8_t* trow =
+          a.ti + (min(max(fz, 0), g.ti[2] - 1) * g.ti[1] + min(max(fy, 0), g.ti[1] - 1)) * g.ti[0];
       int8_t tv[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int fx = (cx << J) + e.u[0];
-        tv[v] = (fx >= 0 && fx < g.ti[0] && cx < g.cand[0]) ? trow[fx] : (int8_t)e.v;
+        tv[v] = trow[min(max((cx << J) + e.u[0], 0), g.ti[0] - 1)];
       }
 #pragma unroll
-      for (int v = 0; v < 16; ++v) mis[v] += tv[v] != e.v;
+      for (int v = 0; v < 16; ++v) {
+        const int cx = ch * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int fx = (cx << J) + e.u[0];
+        const unsigned inb = (fx >= 0 && fx < g.ti[0] && cx < g.cand[0]) ? ok : 0u;
+        mis[v] += inb & (tv[v] != e.v ? 1u : 0u);
+      }
+      e = en;
     }
   };
 
@@ -189,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   for (int k = tid; k < kpad; k += kThreads) {
     int beta;
     if (a.standalone) beta = k < (int)g.tcells ? k : -1;
-    else beta = a.kbeta[t.orient * kKMax + k];
+    else beta = a.kbeta[t0.orient * kKMax + k];
     int off = 0;
     if (beta >= 0) {
       const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
@@ -197,65 +247,97 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     }
     s_off[k] = off;
   }
-  // data events: 8 int16 (16 B) per load, converted to the operand type
+  // data events of every tile: 8 int16 (16 B) per load, converted to the
+  // operand type
   typedef int16_t short8_t __attribute__((ext_vector_type(8)));
-  for (int i = tid; i < kFiltersPerTile * (kpad / 8); i += kThreads) {
-    const int jj = i / (kpad / 8), k8 = (i - jj * (kpad / 8)) * 8;
+  const int k8n = kpad / 8;
+  for (int i = tid; i < nt * kFiltersPerTile * k8n; i += kThreads) {
+    const int row_f = i / k8n, k8 = (i - row_f * k8n) * 8;
+    const int gi = row_f / kFiltersPerTile, jj = row_f - gi * kFiltersPerTile;
+    const TileDev t = tile_of(gi);
     short8_t m = {};
     if (jj < t.count && !((t.zmask >> jj) & 1u))
       m = *(const short8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
     vec8 v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
-    *(vec8*)(s_B + jj * bstride + k8) = v;
+    *(vec8*)(s_B + row_f * bstride + k8) = v;
   }
   // the first chunk's epilogue reads go out before the barrier
   int ev[16];
   unsigned mis[16];
-  if (wave < nchunks) epilogue_inputs(wave, ev, mis);
+  if (wave < nchunks) epilogue_inputs(wave, rec0, t0.first + j, ev, mis);
   __syncthreads();
 
-  const uint64_t tkey = rec.tkey;
-  uint64_t lane_min = ~0ull;
-  for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
-    if (ch != wave) epilogue_inputs(ch, ev, mis);
-    float16_t acc = {};
+  // (chunk, tile) pairs of this wavefront; a pair's epilogue reads go out
+  // before its contraction
+  const int my_chunks = wave < nchunks ? (nchunks - 1 - wave) / (kThreads / 64) + 1 : 0;
+  const int npairs = my_chunks * nt;
+  vec8 afr[KS];
+  for (int p = 0; p < npairs; ++p) {
+    const int ch = wave + (kThreads / 64) * (p / nt), gi = p - (p / nt) * nt;
+    const TileDev t = s_tile[gi];
+    const ScanRec rec = s_rec[gi * kFiltersPerTile + j];
+    if (p > 0) epilogue_inputs(ch, rec, t.first + j, ev, mis);
     const int cbase = ch * 32 + j;
-    for (int kc = 0; kc < kpad; kc += 16) {
-      vec8 av, bv;
+    float16_t acc = {};
+    const OT* brow = s_B + (gi * kFiltersPerTile + j) * bstride + g8;
+    if constexpr (G == 1) {
+      for (int kc = 0; kc < kpad; kc += 16) {
+        vec8 av;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
-      bv = *(const vec8*)(s_B + j * bstride + kc + g8);
-      acc = MfmaOp<OT>::mma(av, bv, acc);
-    }
-    if (!fvalid) continue;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      const int cx = ch * 32 + i;
-      if (cx >= g.cand[0]) continue;
-      const long long idx = rowbase + cx;
-      const int C = (int)acc[v];
-      const int S = (a.score_mode == 0) ? ev[v] - (C << shift) : -C;
-      if (a.standalone) {
-        a.scores[(long long)slot * g.ncand + idx] = S;
-        continue;
+        for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
+        acc = MfmaOp<OT>::mma(av, *(const vec8*)(brow + kc), acc);
       }
-      const uint64_t key = make_key(mis[v], S, tie_perm((uint32_t)idx, tkey));
-      a.keys[(long long)slot * g.ncand + idx] = key;
-      lane_min = key < lane_min ? key : lane_min;
+    } else {
+      if (gi == 0) {   // gather this chunk's A fragments once for the group
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+          if (q * 16 < kpad) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) afr[q][e] = s_strip[s_off[q * 16 + g8 + e] + cbase];
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < KS; ++q)
+        if (q * 16 < kpad) acc = MfmaOp<OT>::mma(afr[q], *(const vec8*)(brow + q * 16), acc);
+    }
+    const bool fvalid = rec.gidx >= 0;
+    const int slot = t.first + j;
+    uint64_t lane_min = ~0ull;
+    if (fvalid) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int cx = ch * 32 + i;
+        if (cx >= g.cand[0]) continue;
+        const long long idx = rowbase + cx;
+        const int C = (int)acc[v];
+        const int S = (a.score_mode == 0) ? ev[v] - (C << shift) : -C;
+        if (a.standalone) {
+          a.scores[(long long)slot * g.ncand + idx] = S;
+          continue;
+        }
+        const uint64_t key = make_key(mis[v], S, tie_perm((uint32_t)idx, rec.tkey));
+        a.keys[(long long)slot * g.ncand + idx] = key;
+        lane_min = key < lane_min ? key : lane_min;
+      }
+    }
+    if (!a.standalone) {
+      // lanes j and j + 32 hold the same filter; the wavefronts meet in LDS
+      const uint64_t other = shfl_xor64(lane_min, 32);
+      lane_min = other < lane_min ? other : lane_min;
+      if (lane < 32 && fvalid) atomicMin(&s_rowmin[gi * kFiltersPerTile + j], (unsigned long long)lane_min);
     }
   }
   if (a.standalone) return;
-  // smallest key of this candidate row, per filter (lanes j and j + 32 hold
-  // the same filter; the four wavefronts meet in LDS)
-  {
-    const uint64_t other = shfl_xor64(lane_min, 32);
-    lane_min = other < lane_min ? other : lane_min;
-    if (lane < 32 && fvalid) atomicMin(&s_rowmin[j], (unsigned long long)lane_min);
-  }
   __syncthreads();
-  if (tid < t.count) a.rowmin[(long long)(t.first + tid) * (g.cand[1] * g.cand[2]) + row] = s_rowmin[tid];
+  if (tid < nt * kFiltersPerTile) {
+    const int gi = tid / kFiltersPerTile, jj = tid - gi * kFiltersPerTile;
+    const TileDev t = s_tile[gi];
+    if (jj < t.count) a.rowmin[(long long)(t.first + jj) * (g.cand[1] * g.cand[2]) + row] = s_rowmin[tid];
+  }
 }
 
 // Energy term E(c) = sum_beta n_beta K[c + beta]^2 for each shape (rows of

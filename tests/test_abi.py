@@ -123,3 +123,9 @@ def test_every_workload_fits_the_kernel_limits(lib, name):
     if v < 0:
         err = lib.ccwsim_last_error().decode()
         assert "hipHostMalloc" in err, err
+
+
+def test_scan_group_validation(lib):
+    assert lib.ccwsim_set_scan_group(3) == 1
+    assert b"tiles per scan workgroup" in lib.ccwsim_last_error()
+    assert lib.ccwsim_set_scan_group(0) == 0

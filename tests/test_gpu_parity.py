@@ -171,6 +171,28 @@ def test_scan_parity(cc, orc, case):
         assert np.array_equal(S[f].astype(np.int64), want), f"filter {f}"
 
 
+@pytest.mark.parametrize("G", [1, 2, 4, 8])
+def test_scan_tile_groups(cc, orc, G):
+    # several 32-filter tiles per workgroup share one A gather; results must
+    # not depend on how many (the last group is ragged for G = 2, 4, 8)
+    ext, T, J, nf, nfac = (400, 400), (32, 32), 2, 70, 3
+    _say("scan groups", G)
+    rng = np.random.default_rng(5)
+    x = syn.channel_image_2d(ext[0], ext[1], 8, nfac, seed=9)
+    a_gpu, _ = cc.dwt(_t(x), J)
+    nb, mb = _events(rng, T, J, nf, nfac, "bands")
+    cc.set_scan_group(G)
+    try:
+        S = cc.ccf_scan(ext, J, nfac - 1, a_gpu, T, _t(nb, np.int32), _t(mb, np.int32)).cpu().numpy()
+    finally:
+        cc.set_scan_group(0)
+    a_orc, _ = orc.dwt(x, J)
+    cand = [(ext[a] - T[a]) // 4 + 1 for a in range(2)]
+    for f in range(nf):
+        want = orc.scores(a_orc, cand, nb[f], mb[f], 16).ravel()
+        assert np.array_equal(S[f].astype(np.int64), want), f"filter {f}"
+
+
 def test_scan_rejects_inexact_range(cc):
     x = np.zeros((64, 64), dtype=np.int8)
     a, _ = cc.dwt(_t(x), 3)   # |beta| = 64: block sums up to 64 * 126 > 2048
@@ -309,6 +331,23 @@ def test_simulate_full_size(cc, orc, name, nr):
     if hd is not None:
         for r, pos, v in zip(*hd):
             assert out[(r,) + tuple(pos[::-1])] == v
+
+
+def test_simulate_tile_groups(cc, orc):
+    # steps wider than one tile: the scan's A operand spans the whole
+    # template window and a workgroup takes 1, 2, 4 or 8 tiles, or the tuned
+    # count; every choice must give the oracle's realizations
+    p, ti, hd = wl.make("c4_batched", scale=0.5, n_real=40)
+    _say("simulate groups", p["n_real"])
+    oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
+    for G in (1, 2, 4, 8, 0):
+        cc.set_scan_group(G)
+        try:
+            out, chosen = _run(cc, p, ti, hd)
+        finally:
+            cc.set_scan_group(0)
+        assert np.array_equal(chosen, ochosen), f"G={G}: first differing step {np.argwhere(chosen != ochosen)[:3]}"
+        assert np.array_equal(out, oout), f"G={G}"
 
 
 def test_simulate_is_deterministic(cc):
