@@ -164,6 +164,44 @@ def measure_scan_kernel(cc, wl, dev, reps=20):
     return out
 
 
+def measure_learned(cc, wl, dev, dims=(16,)):
+    """C5 with the learned proposer against the plain scan: same realizations
+    (checked), cells/s, and how many candidate rows were rescored exactly
+    per patch before the K best were certified."""
+    import numpy as np
+    import torch
+    p, ti, _ = wl.make("c5_learned")
+    ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+    cells = p["n_real"] * int(np.prod(p["grid"]))
+    rows = (p["ti"][1] - p["tmpl"][1]) // 2 ** p["level"] + 1
+    sim0 = cc.Simulator(p, device=dev)
+    ref = sim0.run(ti_d)
+    t_plain = _time_runs(lambda: sim0.run(ti_d), 2)
+    res = {"workload": wl.describe(p), "ms_plain": t_plain * 1e3, "cells_per_s_plain": cells / t_plain,
+           "candidate_rows": rows, "by_dim": []}
+    del sim0
+    for D in dims:
+        simL = cc.Simulator(dict(p, proposer_dim=D), device=dev)
+        got = simL.run(ti_d)
+        torch.cuda.synchronize()
+        rep = simL.report()
+        same = bool(torch.equal(got, ref))
+        t = _time_runs(lambda: simL.run(ti_d), 2)
+        cc.profile_enable(True)
+        cc.profile_read()
+        simL.run(ti_d)
+        torch.cuda.synchronize()
+        prof = cc.profile_read()
+        cc.profile_enable(False)
+        res["by_dim"].append({"proposer_dim": D, "ms": t * 1e3, "cells_per_s": cells / t, "speedup": t_plain / t,
+                              "identical_to_plain": same,
+                              "rows_rescored_per_patch": rep["proposer_rows"] / max(rep["proposer_patches"], 1),
+                              "fit_ms": prof["learn"][0], "proxy_scan_us": 1e3 * prof["scan"][0] / max(prof["scan"][1], 1),
+                              "finalize_us": 1e3 * prof["finalize"][0] / max(prof["finalize"][1], 1)})
+        del simL
+    return res
+
+
 def measure_forms(cc, wl, dev):
     """Side measurements of the batched and precision-split forms.
 
@@ -199,6 +237,7 @@ def measure_forms(cc, wl, dev):
     out["batched"] = {"workload": wl.describe(p), "ms_batched": t_batch * 1e3,
                       "ms_one_at_a_time": t_single * 1e3, "cells_per_s_batched": cells / t_batch,
                       "cells_per_s_one_at_a_time": cells / t_single, "speedup": t_single / t_batch}
+    out["learned"] = measure_learned(cc, wl, dev)
     p3, ti3, hd3 = wl.make("c3_split3d")
     sim3 = cc.Simulator(p3, device=dev)
     ti3_d = torch.from_numpy(np.ascontiguousarray(ti3)).to(dev)

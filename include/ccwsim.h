@@ -93,7 +93,18 @@ typedef struct {
                            and the K best of those are drawn from        */
   int32_t max_hard_data;/* most hard data a call passes (sizes the
                            workspace); 0 = unconditional only            */
-  int32_t reserved[3];  /* must be 0                                      */
+  int32_t proposer_dim; /* 0, or D in {8, 16, 32}: learned proposer.  A
+                           D-dimensional principal-component basis of the
+                           candidates' level-J windows is fitted on the
+                           device from the TI (every call); each patch's
+                           data event is encoded against it, the scan then
+                           bounds every candidate's score from below, and
+                           the exact scores of whole candidate rows are
+                           computed in order of their bound until the K
+                           best are certified.  Results are identical to
+                           proposer_dim = 0.  Needs score_mode 0 and
+                           shortlist 0.                                   */
+  int32_t reserved[2];  /* must be 0                                      */
 } ccwsim_params;
 
 /* ---- A1: training-image transform (Sec. 3.1; Algorithm 1, DWT of TI) ---
@@ -206,11 +217,13 @@ typedef struct {
 } ccwsim_plan_stats;
 int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out);
 
-/* Report of the exact shortlist rescoring of the last ccwsim_simulate call
- * on this workspace (synchronises `stream`): out[0] largest |bulk score -
+/* Report of the last ccwsim_simulate call on this workspace (synchronises
+ * `stream`), int64 out[6].  Shortlist rescoring: out[0] largest |bulk score -
  * exact score|, out[1] candidates rescored, out[2] patches whose K best
- * changed after rescoring, out[3] patches rescored.  All zero without a
- * shortlist. */
+ * changed after rescoring, out[3] patches rescored (all zero without a
+ * shortlist).  Proposer: out[4] patches selected through it, out[5]
+ * candidate rows whose exact keys were computed for them (zero without a
+ * proposer). */
 int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
                            int64_t* out, void* stream);
 
@@ -222,7 +235,8 @@ int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_
 #define CCWSIM_KIND_SCAN 4
 #define CCWSIM_KIND_FINALIZE 5
 #define CCWSIM_KIND_CROP 6
-#define CCWSIM_NUM_KINDS 7
+#define CCWSIM_KIND_LEARN 7   /* the proposer's fit (principal components, embeddings) */
+#define CCWSIM_NUM_KINDS 8
 /* When enabled, ccwsim_simulate brackets each kernel launch with a pair of
  * hipEvents on the caller's stream.  ccwsim_profile_read synchronises those
  * events, writes per-kind total milliseconds and launch counts (arrays of

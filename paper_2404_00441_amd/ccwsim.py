@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("path_mode", ctypes.c_int32), ("score_mode", ctypes.c_int32),
         ("nc_margin", ctypes.c_int32 * 3), ("cut", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("shortlist", ctypes.c_int32),
-        ("max_hard_data", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("max_hard_data", ctypes.c_int32), ("proposer_dim", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -97,7 +97,7 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group")
 
-KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop")
+KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
 
 class PlanStats(ctypes.Structure):
@@ -158,6 +158,7 @@ def params_of(p: dict) -> Params:
     q.precision = p.get("precision", 0)
     q.shortlist = int(p.get("shortlist", 0))
     q.max_hard_data = int(p.get("max_hard_data", 0))
+    q.proposer_dim = int(p.get("proposer_dim", 0))
     return q
 
 
@@ -264,10 +265,11 @@ class Simulator:
 
     def report(self) -> dict:
         """Shortlist rescoring report of the last run (synchronises)."""
-        out = (ctypes.c_int64 * 4)()
+        out = (ctypes.c_int64 * 6)()
         _check("ccwsim_simulate_report", load().ccwsim_simulate_report(
             ctypes.byref(self.q), ctypes.c_void_p(self.ws_view.data_ptr()), self.ws_bytes, out, _stream()))
-        return {"max_abs_error": out[0], "rescored": out[1], "topk_changed": out[2], "patches": out[3]}
+        return {"max_abs_error": out[0], "rescored": out[1], "topk_changed": out[2], "patches": out[3],
+                "proposer_patches": out[4], "proposer_rows": out[5]}
 
 
 def hd_to_device(hd, ndim, device="cuda"):

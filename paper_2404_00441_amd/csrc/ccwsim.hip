@@ -15,6 +15,7 @@
 
 #include "ccwsim.h"
 #include "dev_scan.h"
+#include "dev_learn.h"
 
 using namespace ccw;
 
@@ -509,6 +510,11 @@ struct Plan {
   Geom g;
   int n_orient = 0, n_shapes = 0, kpad = 0, W = 0;
   int scan_g_max = 1;                 // most tiles one scan workgroup may take (LDS)
+  int learn = 0;                      // proposer dimension (0: plain scan)
+  long long ws_pca_part = 0, ws_pca_cov = 0, ws_pca_mu = 0, ws_pca_P = 0, ws_emb = 0, ws_rn = 0, ws_qbuf = 0;
+  long long learn_off = 0;            // finalize LDS offset of the row-rescoring area
+  int learn_kbr = 0, learn_w = 0;
+  size_t proxy_lds = 0;
   int scan_g = 1;                     // tiles per scan workgroup (tuned)
   bool tuned = false;
   int max_slots = 0, nsteps_raster = 0;
@@ -579,9 +585,20 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (p.precision != 0 && p.precision != 1) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
   if (p.shortlist != 0 && (p.shortlist < p.top_k || p.shortlist > kShortMax))
     return fail(CCWSIM_ERR_INVALID_ARG, "shortlist must be 0 or in [top_k, %d]", kShortMax);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (p.reserved[i]) return fail(CCWSIM_ERR_INVALID_ARG, "reserved fields must be 0");
   if (p.max_hard_data < 0) return fail(CCWSIM_ERR_INVALID_ARG, "max_hard_data must be >= 0");
+  if (p.proposer_dim != 0 && p.proposer_dim != 8 && p.proposer_dim != 16 && p.proposer_dim != 32)
+    return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim must be 0, 8, 16 or 32");
+  if (p.proposer_dim) {
+    if (p.score_mode != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "the proposer bounds squared-difference scores only");
+    if (p.shortlist != 0) return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim and shortlist exclude each other");
+    if (g.tcells > kPcaMaxCells)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "the proposer supports templates of <= %d level-J blocks", kPcaMaxCells);
+    if ((long long)g.cand[1] * g.cand[2] > 512)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "the proposer supports <= 512 candidate rows");
+  }
+  P.learn = p.proposer_dim;
   const int nd = g.ndim;
   P.n_orient = 1 << nd;
   P.n_shapes = P.n_orient << nd;
@@ -662,7 +679,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     const int nrows = g.tc[1] * g.tc[2];
     P.scan_g_max = 1;
     for (int G : {2, 4, 8})
-      if (P.kpad <= kScanGroupKMax && scan_group_lds(nrows, P.W, P.kpad, G) <= 64 * 1024) P.scan_g_max = G;
+      if (!P.learn && P.kpad <= kScanGroupKMax && scan_group_lds(nrows, P.W, P.kpad, G) <= 64 * 1024)
+        P.scan_g_max = G;
     P.scan_lds = scan_group_lds(nrows, P.W, P.kpad, 1);
     if (P.scan_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu B of LDS", P.scan_lds);
   }
@@ -839,6 +857,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.cand_cap = cand_bytes <= 24 * 1024 ? (long long)ksel * g.cand[0] : 0;
   if (ksel > kTopMax && (P.cand_cap == 0 || (long long)g.cand[1] * g.cand[2] > P.cand_cap))
     return fail(CCWSIM_ERR_UNSUPPORTED, "shortlist of %d needs %lld B of keys in LDS", ksel, cand_bytes);
+  if (P.learn) P.cand_cap = 0;   // the proposer's selection has its own area
   const size_t fixed = (size_t)P.buf_cells * 8 + 4 * (size_t)wpad + (size_t)P.cand_cap * 8;
   const long long budget = 60 * 1024;
   if (P.dp_wave) {
@@ -855,6 +874,21 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
     return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
   P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride + (size_t)((2 * g.tcells * 4 + 15) & ~15ll);
+  if (P.learn) {
+    // rows by bound, the keys of a round of rows and their level-J rows (int16)
+    const long long nrows = (long long)g.cand[1] * g.cand[2];
+    P.learn_w = (int)((g.cand[0] + g.tc[0] - 1 + 1) & ~1);
+    P.learn_off = (long long)((P.fin_lds + 15) & ~(size_t)15);
+    for (P.learn_kbr = 4; P.learn_kbr >= 1; --P.learn_kbr) {
+      const long long bytes = nrows * 8 + ((nrows + 1) & ~1ll) * 4 + (long long)P.learn_kbr * g.cand[0] * 8 +
+                              (long long)P.learn_kbr * g.tc[1] * g.tc[2] * P.learn_w * 2;
+      if (P.learn_off + bytes <= 64 * 1024) {
+        P.fin_lds = (size_t)(P.learn_off + bytes);
+        break;
+      }
+    }
+    if (P.learn_kbr < 1) return fail(CCWSIM_ERR_UNSUPPORTED, "proposer row rescoring does not fit the LDS");
+  }
   if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
   // the coefficient staging area aliases the key list and the cut scratch
   const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
@@ -909,6 +943,18 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_hdent = o;     o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdEnt));
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
   P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
+  if (P.learn) {
+    const long long n = g.tcells;
+    P.ws_pca_part = o;  o += align256((long long)kPcaParts * (n * n + n) * 4);
+    P.ws_pca_cov = o;   o += align256(n * n * 4);
+    P.ws_pca_mu = o;    o += align256(n * 4);
+    P.ws_pca_P = o;     o += align256((long long)P.learn * n * 4);
+    P.ws_emb = o;       o += align256(g.ncand * P.learn * 4);
+    P.ws_rn = o;        o += align256(g.ncand * 8);
+    P.ws_qbuf = o;      o += align256((long long)P.nfilters * (P.learn + 4) * 4);
+    P.proxy_lds = (size_t)g.cand[0] * P.learn * 4 + (size_t)g.cand[0] * 8;
+    if (P.proxy_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "proposer scan needs %zu B of LDS", P.proxy_lds);
+  }
   P.ws_total = o;
 
   return CCWSIM_OK;
@@ -1158,6 +1204,18 @@ struct FinArgs {
   int dp_wave;          // 1: every overlap <= 16 cells, one 16-lane group per seam
   int dp_evs;           // step stride of the seam error buffer (wavefront DP)
   int dp_stride, dp_batch;
+  // learned proposer (learn = D > 0)
+  int learn;
+  float* qbuf;                    // [patch][D + 4] queries of the data events
+  const float* pca_P;             // [D][template blocks]
+  const float* pca_mu;            // [template blocks]
+  const int32_t* energy;          // [shape][ncand]
+  const int32_t* hd_off;          // [patch + 1]
+  const HdEnt* hd_ent;
+  const int8_t* ti;
+  long long learn_off;            // LDS offset of the row-rescoring area
+  int learn_kbr;                  // candidate rows rescored per round
+  int learn_w;                    // staged K-row length (int16)
 };
 
 // Window cell of a seam: w along the band axis ax (counted from the side
@@ -1306,7 +1364,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   // the row minima depend on the slot only: fetch them with the record
   const int nrows_c = g.cand[1] * g.cand[2];
   uint64_t rm_pre = ~0ull;
-  if (a.cand_cap > 0 && tid < nrows_c) rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
+  if ((a.cand_cap > 0 || a.learn) && tid < nrows_c) rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
   const long long wpad = (g.wcells + 15) & ~15ll;
   int32_t* bufA = (int32_t*)smem;
   int32_t* bufB = bufA + a.buf_cells;
@@ -1354,7 +1412,111 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   __shared__ unsigned s_cnt;
   const int ksel = a.shortlist > 0 ? min(a.shortlist, g.ncand) : k;
   bool done = false;
-  if (a.cand_cap > 0) {
+  if (a.learn) {
+    // Learned proposer: the scan wrote, per candidate row, the smallest lower
+    // bound of its keys.  Rows are rescored exactly in order of their bound,
+    // a few at a time, until the k best exact keys lie below the bound of
+    // every row left (certified), so the k best equal the full scan's.
+    const int nrows = g.cand[1] * g.cand[2];
+    const int C0 = g.cand[0];
+    const uint64_t* rm = a.rowmin + (long long)slot * nrows;
+    const bool exact_rows = f.bandmask == 0;   // no overlap: the row keys are exact keys
+    unsigned char* lb = smem + a.learn_off;
+    uint64_t* s_rk = (uint64_t*)lb;                                  // [nrows] sort keys
+    int* s_order = (int*)(s_rk + nrows);                             // [nrows] rows by bound
+    uint64_t* s_bkey = (uint64_t*)(s_order + ((nrows + 1) & ~1));    // [kbr * C0] batch keys
+    int16_t* s_stage = (int16_t*)(s_bkey + a.learn_kbr * C0);        // [kbr][K rows][W] int16
+    __shared__ int s_koff[kKMax], s_km[kKMax];
+    __shared__ int s_row_of[8];
+    const int nkr = g.tc[1] * g.tc[2];
+    const int W = a.learn_w;
+    // block list of this orientation with the exact data event
+    if (tid < a.kpad) {
+      int off = -1, m = 0;
+      if (my_beta >= 0) {
+        int bx, by, bz;
+        split3(my_beta, g.tc[0], g.tc[1], bx, by, bz);
+        off = (bz * g.tc[1] + by) * W + bx;
+        m = f.bandmask ? (int)a.mbuf[(long long)(a.fbegin + slot) * kKMax + tid] : 0;
+      }
+      s_koff[tid] = off;
+      s_km[tid] = m;
+    }
+    // sort keys: a bound's tie field carries the row index (distinct keys)
+    for (int i = tid; i < nrows; i += kThreads) {
+      const uint64_t v = i < kThreads ? rm_pre : rm[i];
+      s_rk[i] = exact_rows ? v : ((v & ~(uint64_t)kMask20) | (uint64_t)i);
+      s_order[i] = i;
+    }
+    __syncthreads();
+    for (int i = tid; i < nrows; i += kThreads) {
+      const uint64_t x = s_rk[i];
+      int rank = 0;
+      for (int jj = 0; jj < nrows; ++jj) rank += s_rk[jj] < x ? 1 : 0;
+      s_order[rank] = i;
+    }
+    const int hd0 = a.has_hd ? a.hd_off[a.fbegin + slot] : 0;
+    const int nhd = a.has_hd ? a.hd_off[a.fbegin + slot + 1] - hd0 : 0;
+    const int32_t* erow = a.energy + (long long)f.shape * g.ncand;
+    const int shift = g.log2beta + 1;
+    int nsel = 0, pos = 0;
+    while (pos < nrows) {
+      __syncthreads();
+      if (nsel == k) {
+        const uint64_t nb = s_rk[min(max(s_order[pos], 0), nrows - 1)];
+        const uint64_t bound = exact_rows ? nb : (nb & ~(uint64_t)kMask20);
+        if (s_sel[k - 1] < bound) break;   // certified: no row left can hold a better key
+      }
+      const int nb_rows = min(a.learn_kbr, nrows - pos);
+      if (tid < nb_rows) s_row_of[tid] = min(max(s_order[pos + tid], 0), nrows - 1);
+      __syncthreads();
+      // stage the level-J rows these candidate rows read, as int16
+      for (int i = tid; i < nb_rows * nkr * W; i += kThreads) {
+        const int b = i / (nkr * W), rest = i - b * (nkr * W);
+        const int kr = rest / W, x = rest - kr * W;
+        const int row = s_row_of[b];
+        const int cy = row % g.cand[1], cz = row / g.cand[1];
+        const int by = kr % g.tc[1], bz = kr / g.tc[1];
+        s_stage[i] = x < g.G[0] ? (int16_t)a.Ki[idx3i(x, cy + by, cz + bz, g.G)] : (int16_t)0;
+      }
+      __syncthreads();
+      // exact keys of every candidate of the batch
+      const int J = g.level, Jz = g.ndim == 3 ? J : 0;
+      for (int i = tid; i < nb_rows * C0; i += kThreads) {
+        const int b = i / C0, cx = i - b * C0;
+        const int row = s_row_of[b];
+        const int cy = row % g.cand[1], cz = row / g.cand[1];
+        const int16_t* st = s_stage + b * nkr * W + cx;
+        int C = 0;
+        for (int kk = 0; kk < a.kpad; ++kk)
+          if (s_koff[kk] >= 0) C += s_km[kk] * (int)st[s_koff[kk]];
+        const long long idx = (long long)row * C0 + cx;
+        const int S = erow[idx] - (C << shift);
+        unsigned mis = 0;
+        for (int h = 0; h < nhd; ++h) {
+          const HdEnt e = a.hd_ent[hd0 + h];
+          const int fx = (cx << J) + e.u[0], fy = (cy << J) + e.u[1], fz = (cz << Jz) + e.u[2];
+          if (fx >= 0 && fy >= 0 && fz >= 0 && fx < g.ti[0] && fy < g.ti[1] && fz < g.ti[2])
+            mis += a.ti[(fz * g.ti[1] + fy) * g.ti[0] + fx] != e.v ? 1u : 0u;
+        }
+        s_bkey[i] = make_key(mis, f.bandmask ? S : 0, tie_perm((uint32_t)idx, tkey));
+      }
+      __syncthreads();
+      // the k best of the kept keys and the batch
+      const int nkeep = nsel, nbk = nb_rows * C0;
+      block_topk(nkeep + nbk, min(k, nkeep + nbk),
+                 [&](long long q) { return q < nkeep ? s_sel[q] : s_bkey[q - nkeep]; }, sh);
+      nsel = min(k, nkeep + nbk);
+      if (tid < nsel) s_sel[tid] = sh.top[tid];
+      pos += nb_rows;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      atomicAdd(&a.report[4], 1ull);                       // patches selected through the proposer
+      atomicAdd(&a.report[5], (unsigned long long)pos);    // candidate rows rescored exactly
+    }
+    done = true;
+  } else if (a.cand_cap > 0) {
     // 1. the kr smallest row minima, by rank (rows are few)
     const int nrows = g.cand[1] * g.cand[2];
     const uint64_t* rm = a.rowmin + (long long)slot * nrows;
@@ -1645,6 +1807,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
         if (bi[q] >= 0) atomicAdd(&msum[bi[q]], v[q]);
     }
     __syncthreads();
+    if (a.learn)   // the successors' queries for the proposer
+      for (int mm = 0; mm < gm; ++mm)
+        pca_query(s_msum + mm * (int)g.tcells, (int)g.tcells, a.learn, a.pca_P, a.pca_mu,
+                  a.qbuf + (long long)s_mine[m0 + mm] * (a.learn + 4));
     if (tid < a.kpad)
       for (int mm = 0; mm < gm; ++mm)
         a.mbuf[(long long)s_mine[m0 + mm] * kKMax + tid] =
@@ -1747,6 +1913,27 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     k_energy<<<nblocks((long long)P->n_shapes * g.ncand), kThreads, 0, st>>>(Ki, nbt, P->n_shapes, energy, g);
     HIP_TRY(hipGetLastError());
   }
+  // learned proposer: principal components of the candidates' windows
+  float* qbuf = P->learn ? (float*)(ws + P->ws_qbuf) : nullptr;
+  float* pca_mu = P->learn ? (float*)(ws + P->ws_pca_mu) : nullptr;
+  float* pca_P = P->learn ? (float*)(ws + P->ws_pca_P) : nullptr;
+  float* emb = P->learn ? (float*)(ws + P->ws_emb) : nullptr;
+  float2* rn = P->learn ? (float2*)(ws + P->ws_rn) : nullptr;
+  if (P->learn) {
+    ProfScope ps(CCWSIM_KIND_LEARN, st);
+    float* part = (float*)(ws + P->ws_pca_part);
+    float* cov = (float*)(ws + P->ws_pca_cov);
+    const int n = (int)g.tcells;
+    const int R = (n * n + kThreads - 1) / kThreads;
+    if (R <= 9) k_pca_moments<9><<<kPcaParts, kThreads, 0, st>>>(Ki, g, part);
+    else if (R <= 36) k_pca_moments<36><<<kPcaParts, kThreads, 0, st>>>(Ki, g, part);
+    else if (R <= 81) k_pca_moments<81><<<kPcaParts, kThreads, 0, st>>>(Ki, g, part);
+    else k_pca_moments<144><<<kPcaParts, kThreads, 0, st>>>(Ki, g, part);
+    k_pca_reduce<<<nblocks((long long)n * n + n), kThreads, 0, st>>>(part, kPcaParts, g, cov, pca_mu);
+    k_pca_fit<<<1, kThreads, 0, st>>>(cov, pca_mu, g, P->learn, pca_P);
+    k_pca_embed<<<nblocks(g.ncand), kThreads, 0, st>>>(Ki, g, P->learn, pca_mu, pca_P, emb, rn);
+    HIP_TRY(hipGetLastError());
+  }
   // grids start unknown (-1) except for hard data
   const long long allp = (long long)p->n_real * g.pcells;
   {
@@ -1756,7 +1943,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     if (n_hd > 0)
       k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
     k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
-    k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 8, 0);
+    k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 16, 0);
     if (n_hd > 0) {
       k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
       k_exclusive_scan<<<1, kThreads, 0, st>>>(hd_off, P->nfilters);
@@ -1818,6 +2005,29 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.nsteps = P->nsteps_raster;
   fa.dp_stride = P->dp_stride;
   fa.dp_batch = P->dp_batch;
+  fa.learn = P->learn;
+  fa.qbuf = qbuf;
+  fa.pca_P = pca_P;
+  fa.pca_mu = pca_mu;
+  fa.energy = energy;
+  fa.hd_off = hd_off;
+  fa.hd_ent = hd_ent;
+  fa.ti = ti;
+  fa.learn_off = P->learn_off;
+  fa.learn_kbr = P->learn_kbr;
+  fa.learn_w = P->learn_w;
+
+  ProxyArgs xa = {};
+  xa.g = g;
+  xa.qbuf = qbuf;
+  xa.emb = emb;
+  xa.rn = rn;
+  xa.energy = energy;
+  xa.hd_ent = hd_ent;
+  xa.ti = ti;
+  xa.rowmin = rowmin;
+  xa.D = P->learn;
+  xa.has_hd = n_hd > 0;
 
   const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
   const int G = scan_group_of(P);
@@ -1829,7 +2039,13 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     sa.recs = recs + (long long)s.tbegin * kFiltersPerTile;
     sa.ntiles = s.tcount;
     sa.groups = groups + s.gbegin[gix];
-    {
+    if (P->learn) {
+      xa.tiles = tiles + s.tbegin;
+      xa.recs = recs + (long long)s.tbegin * kFiltersPerTile;
+      xa.fbegin = s.fbegin;
+      ProfScope ps(CCWSIM_KIND_SCAN, st);
+      k_proxy<<<dim3(rows, (unsigned)s.tcount), kThreads, P->proxy_lds, st>>>(xa);
+    } else {
       ProfScope ps(CCWSIM_KIND_SCAN, st);
       launch_scan(p->precision, G, rows, s.gcount[gix], scan_lds, st, sa);
     }
@@ -2144,10 +2360,10 @@ extern "C" int ccwsim_simulate_report(const ccwsim_params* p, const void* worksp
   Plan* P = nullptr;
   CCW_TRY(get_plan(*p, &P));
   if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
-  unsigned long long v[4] = {0, 0, 0, 0};
+  unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
   hipStream_t st = as_stream(stream);
   HIP_TRY(hipMemcpyAsync(v, (const unsigned char*)workspace + P->ws_report, sizeof v, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  for (int i = 0; i < 4; ++i) out[i] = (int64_t)v[i];
+  for (int i = 0; i < 6; ++i) out[i] = (int64_t)v[i];
   return CCWSIM_OK;
 }

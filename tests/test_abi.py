@@ -72,6 +72,9 @@ def test_dwt_sizes_host_only(lib):
     dict(shortlist=3),                 # below top_k
     dict(shortlist=33),                # above the longest shortlist
     dict(precision=5),
+    dict(proposer_dim=7),
+    dict(proposer_dim=16, shortlist=8),
+    dict(proposer_dim=16, score_mode=1),
 ])
 def test_simulate_validation_errors(lib, bad):
     from paper_2404_00441_amd import ccwsim

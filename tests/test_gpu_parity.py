@@ -424,3 +424,45 @@ def test_precision_split(cc, orc, case):
     assert rep["max_abs_error"] == 0 and rep["topk_changed"] == 0
     assert rep["patches"] == npatch
     assert rep["rescored"] == npatch * min(p["shortlist"], geo["ncand"])
+
+
+# --------------------------------------------------------------------------
+# A9 learned proposer: certified bounds, so the realizations are the oracle's
+# --------------------------------------------------------------------------
+LEARN_CASES = [
+    # workload, scale, n_real, proposer dimension
+    ("c1_plain2d", 1.0, None, 8),
+    ("c2_scale2d", 0.3, None, 16),
+    ("c4_batched", 0.4, 6, 8),
+    ("c5_learned", 0.12, 2, 32),
+    ("c3_split3d", 0.3, None, 16),
+]
+
+
+@pytest.mark.parametrize("case", LEARN_CASES, ids=[f"{c[0]}_s{c[1]}_D{c[3]}" for c in LEARN_CASES])
+def test_learned_proposer_matches_oracle(cc, orc, case):
+    import torch
+    name, scale, nr, D = case
+    _say("learned", case)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    p = dict(p, proposer_dim=D, shortlist=0)
+    sim = cc.Simulator(p)
+    nd = len(p["ti"])
+    steps = 1
+    for a in range(nd):
+        st_ = p["tmpl"][a] - p["overlap"][a]
+        steps *= max(1, -(-(p["grid"][a] - p["overlap"][a]) // st_))
+    chosen = torch.full((p["n_real"], steps), -7, dtype=torch.int32, device="cuda")
+    out = sim.run(_t(ti), cc.hd_to_device(hd, nd), chosen=chosen)
+    torch.cuda.synchronize()
+    rep = sim.report()
+    oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
+    got_c = chosen.cpu().numpy()
+    assert np.array_equal(got_c, ochosen), f"first differing step {np.argwhere(got_c != ochosen)[:3]}"
+    assert np.array_equal(out.cpu().numpy(), oout)
+    assert rep["proposer_patches"] == p["n_real"] * steps
+    rows = (p["ti"][1] - p["tmpl"][1]) // 2 ** p["level"] + 1
+    if nd == 3:
+        rows *= (p["ti"][2] - p["tmpl"][2]) // 2 ** p["level"] + 1
+    # every patch rescored at least one row and never more than all of them
+    assert rep["proposer_patches"] <= rep["proposer_rows"] <= rep["proposer_patches"] * rows
