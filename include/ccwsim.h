@@ -252,15 +252,20 @@ int ccwsim_profile_read(double* ms, int64_t* launches);
  * ccwsim_set_graphs(0) switches to plain launches and drops the graphs. */
 int ccwsim_set_graphs(int on);
 
-/* Tiles (of 32 patches) one scan workgroup takes.  0 (the default) lets the
- * library choose: on the first call of a parameter set whose steps span
- * several tiles it runs the call eagerly, times the widest step's scan for
- * 1, 2, 4 and 8 tiles per workgroup and keeps the fastest for that scan
- * shape (in memory, and in the JSON object of the file named by the
- * environment variable CCWSIM_TUNE_FILE if set; ccwsim_release_caches forgets
- * the in-memory table).  1, 2, 4 or 8 force a value, within what the LDS
- * allows (for tests; results do not depend on it).  Drops captured graphs.
- * Returns CCWSIM_ERR_INVALID_ARG for other values. */
+/* Scan variant.  The scan has two output layouts: candidate-major (each
+ * lane holds one patch against 16 candidates; up to 1, 2, 4 or 8 tiles of
+ * 32 patches of one orientation share a workgroup and its gather of the
+ * TI approximation) and filter-major (each lane holds one candidate
+ * against 16 patches, so energy reads and key stores are contiguous; one
+ * tile per workgroup).  0 (the default) lets the library choose: on the
+ * first call of a parameter set it runs the call eagerly, times the widest
+ * step's scan for every variant and keeps the fastest for that scan shape
+ * (in memory, and in the JSON object of the file named by the environment
+ * variable CCWSIM_TUNE_FILE if set; ccwsim_release_caches forgets the
+ * in-memory table).  1, 2, 4 or 8 force the candidate-major layout with
+ * that many tiles (within what the LDS allows), -1 the filter-major one
+ * (for tests; results do not depend on the variant).  Drops captured
+ * graphs.  Returns CCWSIM_ERR_INVALID_ARG for other values. */
 int ccwsim_set_scan_group(int g);
 
 #ifdef __cplusplus

@@ -287,16 +287,20 @@ __global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int16_t* __re
   mbuf[id] = k < tcells ? (int16_t)or_m[f * tcells + k] : (int16_t)0;
 }
 
-// Launch the scan with up to G tiles per workgroup (G in {1, 2, 4, 8}) over
-// `ngroups` workgroup columns.
-void launch_scan(int precision, int G, unsigned rows, int ngroups, size_t lds, hipStream_t st, const ScanArgs& sa) {
+// Scan variants: 1, 2, 4, 8 = candidate-major output with up to that many
+// tiles per workgroup; kScanFilterMajor = filter-major output, one tile.
+constexpr int kScanFilterMajor = -1;
+
+// Launch scan variant V over `ngroups` workgroup columns.
+void launch_scan(int precision, int V, unsigned rows, int ngroups, size_t lds, hipStream_t st, const ScanArgs& sa) {
   const dim3 grid(rows, (unsigned)ngroups);
-#define CCW_SCAN(OT)                                                \
-  do {                                                              \
-    if (G == 8) k_scan<OT, 8><<<grid, kThreads, lds, st>>>(sa);     \
-    else if (G == 4) k_scan<OT, 4><<<grid, kThreads, lds, st>>>(sa); \
-    else if (G == 2) k_scan<OT, 2><<<grid, kThreads, lds, st>>>(sa); \
-    else k_scan<OT, 1><<<grid, kThreads, lds, st>>>(sa);            \
+#define CCW_SCAN(OT)                                                     \
+  do {                                                                   \
+    if (V == kScanFilterMajor) k_scan_fm<OT><<<grid, kThreads, lds, st>>>(sa); \
+    else if (V == 8) k_scan<OT, 8><<<grid, kThreads, lds, st>>>(sa);     \
+    else if (V == 4) k_scan<OT, 4><<<grid, kThreads, lds, st>>>(sa);     \
+    else if (V == 2) k_scan<OT, 2><<<grid, kThreads, lds, st>>>(sa);     \
+    else k_scan<OT, 1><<<grid, kThreads, lds, st>>>(sa);                 \
   } while (0)
   if (precision == 1) CCW_SCAN(__bf16);
   else CCW_SCAN(_Float16);
@@ -340,6 +344,8 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
     G = 1;
     for (int c : {2, 4, 8})
       if (c <= g_scan_g_force && group_ok(c)) G = c;
+  } else if (g_scan_g_force == kScanFilterMajor) {
+    G = kScanFilterMajor;
   }
 
   hipStream_t st = as_stream(stream);
@@ -367,7 +373,8 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   a.ntiles = ntiles;
   {
     ProfScope ps(CCWSIM_KIND_SCAN, st);
-    launch_scan(0, G, (unsigned)crow, (ntiles + G - 1) / G, scan_group_lds(nrows, W, kpad, G), st, a);
+    const int Gt = G == kScanFilterMajor ? 1 : G;
+    launch_scan(0, G, (unsigned)crow, (ntiles + Gt - 1) / Gt, scan_group_lds(nrows, W, kpad, Gt), st, a);
   }
   const hipError_t le = hipGetLastError();
   HIP_TRY(hipFreeAsync(Kh, st));
@@ -1850,13 +1857,15 @@ extern "C" int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p) {
 }
 
 namespace {
-// Tiles per scan workgroup for this plan: the forced value (tests), else
-// the tuned one, within what the LDS allows.
+// Scan variant for this plan: the forced value (tests), else the tuned
+// one, within what the LDS allows.
 int scan_group_of(const Plan* P) {
-  int G = g_scan_g_force > 0 ? g_scan_g_force : P->scan_g;
-  if (G > P->scan_g_max) G = P->scan_g_max;
+  const int V = g_scan_g_force != 0 ? g_scan_g_force : P->scan_g;
+  if (V == kScanFilterMajor) return V;
+  const int G = V > P->scan_g_max ? P->scan_g_max : V;
   return G >= 8 ? 8 : G >= 4 ? 4 : G >= 2 ? 2 : 1;
 }
+int group_index(int V) { return V == 8 ? 3 : V == 4 ? 2 : V == 2 ? 1 : 0; }   // filter-major: single tiles
 
 int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
                      const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen, void* workspace,
@@ -2031,8 +2040,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
 
   const unsigned rows = (unsigned)(g.cand[1] * g.cand[2]);
   const int G = scan_group_of(P);
-  const int gix = G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
-  const size_t scan_lds = scan_group_lds(g.tc[1] * g.tc[2], P->W, P->kpad, G);
+  const int gix = group_index(G);
+  const size_t scan_lds = scan_group_lds(g.tc[1] * g.tc[2], P->W, P->kpad, G == kScanFilterMajor ? 1 : G);
   for (const StepRange& s : P->steps) {
     sa.fbegin = s.fbegin;
     sa.tiles = tiles + s.tbegin;
@@ -2077,14 +2086,14 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 3.4e38f;
     int best = 1, prev_groups = -1;
-    for (int ci = 0; ci < 4; ++ci) {
-      const int c = 1 << ci;
+    for (int c : {1, kScanFilterMajor, 2, 4, 8}) {
       if (c > P->scan_g_max) break;
+      const int ci = group_index(c);
       const int ngr = w->gcount[ci];
-      if (ngr == prev_groups) break;   // larger groups would change nothing
-      prev_groups = ngr;
+      if (c > 1 && ngr == prev_groups) break;   // larger groups would change nothing
+      if (c >= 1) prev_groups = ngr;
       sa.groups = groups + w->gbegin[ci];
-      const size_t l = scan_group_lds(g.tc[1] * g.tc[2], P->W, P->kpad, c);
+      const size_t l = scan_group_lds(g.tc[1] * g.tc[2], P->W, P->kpad, c == kScanFilterMajor ? 1 : c);
       launch_scan(p->precision, c, rows, ngr, l, st, sa);
       HIP_TRY(hipEventRecord(e0, st));
       for (int r = 0; r < 3; ++r) launch_scan(p->precision, c, rows, ngr, l, st, sa);
@@ -2149,7 +2158,8 @@ void tune_load_once() {
   char line[512], key[400];
   int v = 0;
   while (fgets(line, sizeof line, fp))
-    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2 && (v == 1 || v == 2 || v == 4 || v == 8)) g_tune[key] = v;
+    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2 && (v == -1 || v == 1 || v == 2 || v == 4 || v == 8))
+      g_tune[key] = v;
   fclose(fp);
 }
 
@@ -2179,8 +2189,8 @@ int scan_group_guess(const Plan* P) {
 }  // namespace
 
 extern "C" int ccwsim_set_scan_group(int g) {
-  if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8)
-    return fail(CCWSIM_ERR_INVALID_ARG, "tiles per scan workgroup must be 0 (tuned), 1, 2, 4 or 8");
+  if (g != 0 && g != -1 && g != 1 && g != 2 && g != 4 && g != 8)
+    return fail(CCWSIM_ERR_INVALID_ARG, "tiles per scan workgroup must be 0 (tuned), -1 (filter-major), 1, 2, 4 or 8");
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     drop_graphs();   // captured graphs hold the previous choice
@@ -2208,10 +2218,10 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof = g_prof_on;
   }
-  // First call of a plan whose scan may take several tiles per workgroup:
-  // look the shape up in the tuning table, else run eagerly once (a full,
-  // valid call) and time the widest step's scan for each tile count.
-  if (!P->tuned && g_scan_g_force == 0 && P->scan_g_max > 1) {
+  // First call of a plan: look the scan shape up in the tuning table, else
+  // run eagerly once (a full, valid call) and time the widest step's scan
+  // for each variant (output layout, tiles per workgroup).
+  if (!P->tuned && g_scan_g_force == 0 && !P->learn) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_once();
     const std::string tk = tune_key(P, p);

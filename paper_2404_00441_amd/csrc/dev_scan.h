@@ -340,6 +340,186 @@ void k_scan(ScanArgs a) {
   }
 }
 
+// Filter-major variant (one tile per workgroup).  The MFMA takes the data
+// events as its A operand and the gathered K values as its B operand, so
+// lane l ends with one candidate (column l % 32) against 16 patches
+// (rows 8(v/4) + 4(l/32) + v%4).  For a fixed v the 32 lanes of a half
+// wavefront then hold 32 consecutive candidates of one patch: the energy
+// reads and the key stores are contiguous runs instead of 32 scattered
+// lines.  Each lane keeps its 16 row minima across its chunks; they are
+// reduced over the half wavefront once at the end.
+template <typename OT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void k_scan_fm(ScanArgs a) {
+  typedef typename MfmaOp<OT>::vec8 vec8;
+  const OT* Kop = (const OT*)a.Kop;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Geom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = blockIdx.x;
+  const int cy = row % g.cand[1], cz = row / g.cand[1];
+  const int W = a.W, kpad = a.kpad;
+  const int nrows = g.tc[1] * g.tc[2];
+  const int j = lane & 31, half = lane >> 5;
+  const int g8 = half * 8;
+  const int tile = a.standalone ? (int)blockIdx.y : a.groups[blockIdx.y].x;
+
+  OT* s_strip = (OT*)smem;
+  const int strip_bytes = ((nrows * W * 2) + 15) & ~15;
+  int* s_off = (int*)(smem + strip_bytes);
+  OT* s_B = (OT*)(smem + strip_bytes + kpad * 4);
+  const int bstride = kpad + 8;
+  ScanRec* s_rec = (ScanRec*)(smem + strip_bytes + kpad * 4 + kFiltersPerTile * bstride * 2);
+  unsigned long long* s_rowmin = (unsigned long long*)(s_rec + kFiltersPerTile);
+
+  TileDev t;
+  if (a.standalone) {
+    t.first = tile * kFiltersPerTile;
+    t.count = min(kFiltersPerTile, a.n_filters - t.first);
+    t.orient = 0;
+    t.zmask = 0;
+  } else {
+    t = a.tiles[tile];
+  }
+  if (tid < kFiltersPerTile) {
+    ScanRec r = {};
+    if (a.standalone) r.gidx = tid < t.count ? 0 : -1;
+    else r = a.recs[tile * kFiltersPerTile + tid];
+    s_rec[tid] = r;
+    s_rowmin[tid] = ~0ull;
+  }
+  {
+    constexpr int U = 8;
+    const int n = nrows * W;
+    BoxWalk w(tid, kThreads, W, g.tc[1]);
+    for (int base = tid; base < n; base += kThreads * U) {
+      OT v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        v[q] = (OT)0.0f;
+        if (i < n && w.x < g.G[0]) v[q] = Kop[idx3i(w.x, cy + w.y, cz + w.z, g.G)];
+        w.next();
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        if (i < n) s_strip[i] = v[q];
+      }
+    }
+  }
+  for (int k = tid; k < kpad; k += kThreads) {
+    int beta;
+    if (a.standalone) beta = k < (int)g.tcells ? k : -1;
+    else beta = a.kbeta[t.orient * kKMax + k];
+    int off = 0;
+    if (beta >= 0) {
+      const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
+      off = (bz * g.tc[1] + by) * W + bx;
+    }
+    s_off[k] = off;
+  }
+  typedef int16_t short8_t __attribute__((ext_vector_type(8)));
+  const int k8n = kpad / 8;
+  for (int i = tid; i < kFiltersPerTile * k8n; i += kThreads) {
+    const int jj = i / k8n, k8 = (i - jj * k8n) * 8;
+    short8_t m = {};
+    if (jj < t.count && !((t.zmask >> jj) & 1u))
+      m = *(const short8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
+    vec8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
+    *(vec8*)(s_B + jj * bstride + k8) = v;
+  }
+  __syncthreads();
+
+  const int shift = g.log2beta + 1;
+  const int nchunks = (g.cand[0] + 31) / 32;
+  const long long rowbase = (long long)g.cand[0] * row;
+  const int J = g.level, Jz = g.ndim == 3 ? J : 0;
+  const int fy0 = cy << J, fz0 = cz << Jz;
+  uint64_t lmin[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) lmin[v] = ~0ull;
+  const OT* brow = s_B + j * bstride + g8;
+  for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
+    const int cx = ch * 32 + j;
+    const bool cval = cx < g.cand[0];
+    const long long idx = rowbase + min(cx, g.cand[0] - 1);
+    // energy of this candidate for each of the lane's 16 patches (contiguous
+    // over the half wavefront), read before the contraction
+    int ev[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+      const ScanRec& r = s_rec[i];
+      ev[v] = 0;
+      if (r.gidx >= 0 && a.score_mode == 0)
+        ev[v] = a.standalone ? a.scores[(long long)(t.first + i) * g.ncand + idx] : a.energy[(long long)r.shape * g.ncand + idx];
+    }
+    float16_t acc = {};
+    for (int kc = 0; kc < kpad; kc += 16) {
+      vec8 av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + ch * 32 + j];
+      acc = MfmaOp<OT>::mma(*(const vec8*)(brow + kc), av, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+      const ScanRec r = s_rec[i];
+      if (r.gidx < 0 || !cval) continue;
+      const int C = (int)acc[v];
+      const int S = (a.score_mode == 0) ? ev[v] - (C << shift) : -C;
+      const long long o = (long long)(t.first + i) * g.ncand + idx;
+      if (a.standalone) {
+        a.scores[o] = S;
+        continue;
+      }
+      // hard-data mismatch of this candidate for patch i (the next entry is
+      // read while the current one's TI read is in flight)
+      unsigned mis = 0;
+      if (r.nhd > 0) {
+        HdEnt e = a.hd_ent[r.hd0];
+        for (int h = 0; h < r.nhd; ++h) {
+          const HdEnt en = a.hd_ent[r.hd0 + min(h + 1, r.nhd - 1)];
+          const int fx = (cx << J) + e.u[0], fy = fy0 + e.u[1], fz = fz0 + e.u[2];
+          const bool in = fx >= 0 && fy >= 0 && fz >= 0 && fx < g.ti[0] && fy < g.ti[1] && fz < g.ti[2];
+          const int8_t tv = a.ti[(min(max(fz, 0), g.ti[2] - 1) * g.ti[1] + min(max(fy, 0), g.ti[1] - 1)) * g.ti[0] +
+                                 min(max(fx, 0), g.ti[0] - 1)];
+          mis += (in && tv != e.v) ? 1u : 0u;
+          e = en;
+        }
+      }
+      const uint64_t key = make_key(mis, S, tie_perm((uint32_t)idx, r.tkey));
+      a.keys[o] = key;
+      lmin[v] = key < lmin[v] ? key : lmin[v];
+    }
+  }
+  if (a.standalone) return;
+  // row minima: reduce each of the 16 patches over the 32 candidates of the
+  // half wavefront, then across wavefronts in LDS
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    uint64_t m = lmin[v];
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) {
+      const uint64_t o = shfl_xor64(m, off);
+      m = o < m ? o : m;
+    }
+    lmin[v] = m;
+  }
+  if (j == 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+      if (i < t.count) atomicMin(&s_rowmin[i], (unsigned long long)lmin[v]);
+    }
+  }
+  __syncthreads();
+  if (tid < t.count) a.rowmin[(long long)(t.first + tid) * (g.cand[1] * g.cand[2]) + row] = s_rowmin[tid];
+}
+
 // Energy term E(c) = sum_beta n_beta K[c + beta]^2 for each shape (rows of
 // nbt), int32.  One thread per (shape, candidate).
 __global__ __launch_bounds__(kThreads) void k_energy(const int32_t* __restrict__ K,

@@ -171,7 +171,7 @@ def test_scan_parity(cc, orc, case):
         assert np.array_equal(S[f].astype(np.int64), want), f"filter {f}"
 
 
-@pytest.mark.parametrize("G", [1, 2, 4, 8])
+@pytest.mark.parametrize("G", [1, 2, 4, 8, -1])
 def test_scan_tile_groups(cc, orc, G):
     # several 32-filter tiles per workgroup share one A gather; results must
     # not depend on how many (the last group is ragged for G = 2, 4, 8)
@@ -340,7 +340,7 @@ def test_simulate_tile_groups(cc, orc):
     p, ti, hd = wl.make("c4_batched", scale=0.5, n_real=40)
     _say("simulate groups", p["n_real"])
     oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
-    for G in (1, 2, 4, 8, 0):
+    for G in (1, 2, 4, 8, -1, 0):
         cc.set_scan_group(G)
         try:
             out, chosen = _run(cc, p, ti, hd)
@@ -348,6 +348,19 @@ def test_simulate_tile_groups(cc, orc):
             cc.set_scan_group(0)
         assert np.array_equal(chosen, ochosen), f"G={G}: first differing step {np.argwhere(chosen != ochosen)[:3]}"
         assert np.array_equal(out, oout), f"G={G}"
+
+
+@pytest.mark.parametrize("name,scale,nr", [("c2_scale2d", 0.3, None), ("c3_split3d", 0.3, None),
+                                           ("c1_plain2d", 1.0, None)])
+def test_simulate_filter_major_scan(cc, orc, name, scale, nr):
+    # the filter-major scan layout on 2D and 3D workloads with hard data
+    _say("filter-major", name)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    cc.set_scan_group(-1)
+    try:
+        _compare(cc, orc, p, ti, hd)
+    finally:
+        cc.set_scan_group(0)
 
 
 def test_simulate_is_deterministic(cc):
