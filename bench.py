@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and precision-split side measurements")
+    ap.add_argument("--next", action="store_true",
+                    help="also measure dense conditioning and the level x grid-size sweep")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -202,6 +204,45 @@ def measure_learned(cc, wl, dev, dims=(16,)):
     return res
 
 
+def _time_case(cc, p, ti, hd, dev, reps=3):
+    import numpy as np
+    import torch
+    nd = len(p["ti"])
+    ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+    hd_d = cc.hd_to_device(hd, nd, device=dev)
+    sim = cc.Simulator(p, device=dev)
+    sim.run(ti_d, hd_d)                      # first call: tuning runs
+    t = _time_runs(lambda: sim.run(ti_d, hd_d), reps)
+    cc.profile_enable(True)
+    cc.profile_read()
+    sim.run(ti_d, hd_d)
+    torch.cuda.synchronize()
+    prof = cc.profile_read()
+    cc.profile_enable(False)
+    cells = p["n_real"] * int(np.prod(p["grid"]))
+    st = cc.simulate_stats(p)
+    return {"ms": t * 1e3, "cells_per_s": cells / t, "wavefront_steps": st["wavefront_steps"],
+            "hard_data": 0 if hd is None else int(len(hd[0])),
+            "kernel_ms": {k: round(v[0], 4) for k, v in prof.items() if v[1]}}
+
+
+def measure_next(cc, wl, dev):
+    """Dense conditioning (C2 with 300, 4000, 8000 hard data) and the level x
+    grid-size sweep (C2 training image, T 32, OV 8, 1000 hard data per 512^2;
+    512^2 also with 2000)."""
+    out = {"dense_conditioning": [], "level_grid": []}
+    for n_hd in (300, 4000, 8000):
+        p, ti, hd = wl.dense_conditioning(n_hd)
+        out["dense_conditioning"].append(dict(_time_case(cc, p, ti, hd, dev), workload=wl.describe(p)))
+    for level in (1, 2, 3):
+        for n in (128, 256, 512, 1024, 2048):
+            p, ti, hd = wl.level_grid_case(level, n)
+            out["level_grid"].append(dict(_time_case(cc, p, ti, hd, dev), level=level, grid=n))
+        p, ti, hd = wl.level_grid_case(level, 512, hd_per_512=2000)
+        out["level_grid"].append(dict(_time_case(cc, p, ti, hd, dev), level=level, grid=512))
+    return out
+
+
 def measure_forms(cc, wl, dev):
     """Side measurements of the batched and precision-split forms.
 
@@ -346,6 +387,8 @@ def main():
     if not a.no_forms:
         res["forms"] = measure_forms(cc, wl, dev)
         res["scan_kernel"] = measure_scan_kernel(cc, wl, dev)
+    if a.next:
+        res["next"] = measure_next(cc, wl, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, ti, hd)

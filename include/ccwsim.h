@@ -104,7 +104,15 @@ typedef struct {
                            best are certified.  Results are identical to
                            proposer_dim = 0.  Needs score_mode 0 and
                            shortlist 0.                                   */
-  int32_t reserved[2];  /* must be 0                                      */
+  int32_t hd_direct;    /* 0: the scan counts hard-data mismatches from a
+                           bit table built once per call (for every TI
+                           row, x phase below 2^J and code: one bit per
+                           level-J x position, set where the TI cell
+                           lies inside the TI and holds another code),
+                           when that table takes at most 1 GiB, else as
+                           1; 1: it reads the TI codes directly.  Both
+                           give the same results.                         */
+  int32_t reserved[1];  /* must be 0                                      */
 } ccwsim_params;
 
 /* ---- A1: training-image transform (Sec. 3.1; Algorithm 1, DWT of TI) ---

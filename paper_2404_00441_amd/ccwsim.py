@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
         ("path_mode", ctypes.c_int32), ("score_mode", ctypes.c_int32),
         ("nc_margin", ctypes.c_int32 * 3), ("cut", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("shortlist", ctypes.c_int32),
-        ("max_hard_data", ctypes.c_int32), ("proposer_dim", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+        ("max_hard_data", ctypes.c_int32), ("proposer_dim", ctypes.c_int32), ("hd_direct", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -159,6 +160,7 @@ def params_of(p: dict) -> Params:
     q.shortlist = int(p.get("shortlist", 0))
     q.max_hard_data = int(p.get("max_hard_data", 0))
     q.proposer_dim = int(p.get("proposer_dim", 0))
+    q.hd_direct = int(p.get("hd_direct", 0))
     return q
 
 

@@ -527,6 +527,8 @@ struct Plan {
   int max_slots = 0, nsteps_raster = 0;
   long long patches = 0, or_blocks = 0, band_cells = 0;
   long long hd_cap = 0;               // hard-data entries of all virtual templates
+  bool hdm = false;                   // hard-data mismatches from the bit table
+  HdmGeom hm = {};
   int nfilters = 0;
   std::vector<StepRange> steps;
   // host tables, uploaded on every call (pinned)
@@ -538,6 +540,7 @@ struct Plan {
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
             ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_report = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
+            ws_hdmask = 0, ws_hdbits = 0,
             ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
@@ -592,8 +595,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (p.precision != 0 && p.precision != 1) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
   if (p.shortlist != 0 && (p.shortlist < p.top_k || p.shortlist > kShortMax))
     return fail(CCWSIM_ERR_INVALID_ARG, "shortlist must be 0 or in [top_k, %d]", kShortMax);
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 1; ++i)
     if (p.reserved[i]) return fail(CCWSIM_ERR_INVALID_ARG, "reserved fields must be 0");
+  if (p.hd_direct != 0 && p.hd_direct != 1) return fail(CCWSIM_ERR_INVALID_ARG, "hd_direct must be 0 or 1");
   if (p.max_hard_data < 0) return fail(CCWSIM_ERR_INVALID_ARG, "max_hard_data must be >= 0");
   if (p.proposer_dim != 0 && p.proposer_dim != 8 && p.proposer_dim != 16 && p.proposer_dim != 32)
     return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim must be 0, 8, 16 or 32");
@@ -931,6 +935,30 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   for (int a = 0; a < nd; ++a) per_cell *= (g.T[a] + g.margin[a] + g.stride[a] - 1) / g.stride[a];
   P.hd_cap = (long long)p.max_hard_data * per_cell;
 
+  // hard-data bit table: rows padded by the virtual-template margins, x
+  // positions from floor(-margin / 2^J) to the last chunk's reach
+  if (p.max_hard_data > 0 && !p.hd_direct) {
+    HdmGeom& m = P.hm;
+    const int bx = g.b[0];
+    const int mx = g.margin[0], my = g.margin[1], mz = nd == 3 ? g.margin[2] : 0;
+    const int nchunks = (g.cand[0] + 31) / 32;
+    m.pb = (mx + bx - 1) / bx;
+    const int avmax = (g.T[0] + mx - 1) / bx;
+    m.nw = nchunks + ((avmax + m.pb) >> 5) + 2;
+    m.py0 = my;
+    m.ry = m.py0 + std::max(g.ti[1], (g.cand[1] - 1) * g.b[1] + g.T[1] + my);
+    m.pz0 = mz;
+    m.rz = m.pz0 + std::max(g.ti[2], (g.cand[2] - 1) * g.b[2] + g.T[2] + mz);
+    m.nf = p.n_facies;
+    m.ns = p.n_facies + 1;
+    const long long rs = (long long)bx * m.ns * m.nw;
+    const long long bytes = (long long)m.rz * m.ry * rs * 4;
+    if (bytes <= (1ll << 30)) {
+      m.rs = (int)rs;
+      P.hdm = true;
+    }
+  }
+
   // workspace
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
   const long long c1 = g.level >= 2 ? (long long)g.Gj[1][0] * g.Gj[1][1] * g.Gj[1][2] : 0;
@@ -948,6 +976,10 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_report = o;    o += 256;
   P.ws_hdoff = o;     o += align256((long long)(P.nfilters + 1) * 4);
   P.ws_hdent = o;     o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdEnt));
+  if (P.hdm) {
+    P.ws_hdmask = o;  o += align256((long long)P.hm.rz * P.hm.ry * P.hm.rs * 4);
+    P.ws_hdbits = o;  o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdBits));
+  }
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
   P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
   if (P.learn) {
@@ -1101,7 +1133,8 @@ __device__ __forceinline__ int vbox(const Geom& g, const FilterDev& f, int lo[3]
 template <bool FILL>
 __global__ __launch_bounds__(kThreads) void k_hd_bin(Geom g, const FilterDev* __restrict__ filters,
                                                      const int8_t* __restrict__ hdmap, int32_t* __restrict__ hd_off,
-                                                     HdEnt* __restrict__ hd_ent, long long cap) {
+                                                     HdEnt* __restrict__ hd_ent, long long cap,
+                                                     HdBits* __restrict__ hd_bits, HdmGeom m) {
   __shared__ unsigned s_cnt;
   const int fg = blockIdx.x;
   const FilterDev f = filters[fg];
@@ -1127,11 +1160,46 @@ __global__ __launch_bounds__(kThreads) void k_hd_bin(Geom g, const FilterDev* __
         e.u[2] = (int16_t)uz;
         e.v = v;
         hd_ent[base_off + p] = e;
+        if (hd_bits) {   // where the datum's vector starts in the bit table
+          const int bx = g.b[0];
+          const int r = ((ux % bx) + bx) % bx;
+          const int av = (ux - r) / bx;
+          const int slot = v < m.nf ? v : m.nf;
+          HdBits hb;
+          hb.woff = ((((uz + m.pz0) * m.ry + (uy + m.py0)) * bx + r) * m.ns + slot) * m.nw + ((av + m.pb) >> 5);
+          hb.sh = (av + m.pb) & 31;
+          hd_bits[base_off + p] = hb;
+        }
       }
     }
   }
   __syncthreads();
   if (!FILL && threadIdx.x == 0) hd_off[fg] = (int32_t)s_cnt;
+}
+
+// The hard-data bit table (layout with HdmGeom): one thread per word.
+__global__ __launch_bounds__(kThreads) void k_hd_mask(Geom g, HdmGeom m, const int8_t* __restrict__ ti,
+                                                      uint32_t* __restrict__ out, long long nwords) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nwords) return;
+  const int bx = g.b[0];
+  long long t = id;
+  const int w = (int)(t % m.nw);
+  t /= m.nw;
+  const int slot = (int)(t % m.ns);
+  t /= m.ns;
+  const int r = (int)(t % bx);
+  t /= bx;
+  const int y = (int)(t % m.ry) - m.py0, z = (int)(t / m.ry) - m.pz0;
+  uint32_t bits = 0;
+  if (y >= 0 && y < g.ti[1] && z >= 0 && z < g.ti[2]) {
+    const int8_t* trow = ti + ((long long)z * g.ti[1] + y) * g.ti[0];
+    for (int b = 0; b < 32; ++b) {
+      const int x = (w * 32 + b - m.pb) * bx + r;
+      if (x >= 0 && x < g.ti[0] && (slot == m.nf || trow[x] != slot)) bits |= 1u << b;
+    }
+  }
+  out[id] = bits;
 }
 
 // Hard-data ranges of the scan records, from the binned offsets.
@@ -1885,6 +1953,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   int32_t* predcnt = (int32_t*)(ws + P->ws_predcnt);
   int32_t* hd_off = (int32_t*)(ws + P->ws_hdoff);
   HdEnt* hd_ent = (HdEnt*)(ws + P->ws_hdent);
+  uint32_t* hdmask = P->hdm ? (uint32_t*)(ws + P->ws_hdmask) : nullptr;
+  HdBits* hd_bits = P->hdm ? (HdBits*)(ws + P->ws_hdbits) : nullptr;
   uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
   uint64_t* rowmin = (uint64_t*)(ws + P->ws_rowmin);
   const int32_t* kbeta = (const int32_t*)(tbl + P->off_kbeta);
@@ -1954,9 +2024,15 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
     k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 16, 0);
     if (n_hd > 0) {
-      k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
+      k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap,
+                                                                   nullptr, P->hm);
       k_exclusive_scan<<<1, kThreads, 0, st>>>(hd_off, P->nfilters);
-      k_hd_bin<true><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap);
+      k_hd_bin<true><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap,
+                                                                  hd_bits, P->hm);
+      if (hdmask) {
+        const long long nw = (long long)P->hm.rz * P->hm.ry * P->hm.rs;
+        k_hd_mask<<<nblocks(nw), kThreads, 0, st>>>(g, P->hm, ti, hdmask, nw);
+      }
       k_recs_hd<<<nblocks(P->nrecs), kThreads, 0, st>>>(recs, P->nrecs, hd_off);
     }
     HIP_TRY(hipGetLastError());
@@ -1968,6 +2044,9 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   sa.kbeta = kbeta;
   sa.mbuf = mbuf;
   sa.hd_ent = hd_ent;
+  sa.hm = P->hm;
+  sa.hdm = n_hd > 0 ? hdmask : nullptr;
+  sa.hd_bits = hd_bits;
   sa.energy = energy;
   sa.ti = ti;
   sa.keys = keys;

@@ -51,8 +51,35 @@ struct HdEnt {         // one hard datum inside a virtual template
   int16_t v;           // code
 };
 
+// Hard-data bit table (built once per call from the TI).  Rows are the TI's
+// (y, z) rows padded by py0 / pz0 rows before the TI (and enough after it)
+// so that every row a virtual template reaches exists; a padded row holds
+// zeros.  Row (ry, rz) holds, for each x phase r < 2^J and code slot c
+// (0 .. nf-1, and nf for a code that no TI cell holds), a bit vector of nw
+// words over the level-J x positions bx, bit bx + pb set where the cell
+// (2^J bx + r, y, z) lies in the TI and its code differs from c.  A
+// candidate's mismatch with datum (u, v) is then bit cx + floor(u_x / 2^J)
+// + pb of the vector (row of y, z; phase u_x mod 2^J; slot of v), so the
+// 32 candidates of a chunk read two adjacent words per datum.
+struct HdmGeom {
+  int pb;          // bit of bx = 0
+  int py0, pz0;    // padding rows before y = 0 and z = 0
+  int ry, rz;      // padded rows per axis
+  int nw;          // words per (row, phase, slot)
+  int ns, nf;      // slots (n_facies + 1) and n_facies
+  int rs;          // words per padded row: 2^J * ns * nw
+};
+
+struct HdBits {        // one hard datum: where its bit vector starts
+  int32_t woff;        // word of the vector for candidates 0..31 of row (cy, cz) = (0, 0)
+  int32_t sh;          // bit of candidate 0 within that word pair
+};
+
 struct ScanArgs {
   Geom g;
+  HdmGeom hm;
+  const uint32_t* hdm;         // simulate: hard-data bit table, or null (read TI codes)
+  const HdBits* hd_bits;       // simulate: entries parallel to hd_ent (with hdm)
   const void* Kop;             // level-J grid in the operand type (fp16 or bf16)
   const int32_t* kbeta;        // [orient][kKMax] block index or -1 (simulate)
   const TileDev* tiles;        // simulate: tiles of this step
@@ -190,6 +217,42 @@ void k_scan(ScanArgs a) {
     const int nhd = fvalid ? rec.nhd : 0;
     const int J = g.level;   // block factor 2^J on every used axis
     const int Jz = g.ndim == 3 ? J : 0;
+    if (a.hdm) {
+      // bit table: per datum two words cover the chunk; byte counters
+      // (4 candidates per register) take up to 255 data between flushes
+      const uint32_t* mb = a.hdm + ((cz << Jz) * a.hm.ry + (cy << J)) * a.hm.rs + ch;
+      const HdBits* hb = a.hd_bits + rec.hd0;
+      const int hs = 4 * (lane >> 5);
+      for (int h0 = 0; h0 < nhd; h0 += 255) {
+        const int hn = min(nhd, h0 + 255);
+        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (int h = h0; h < hn; h += 4) {
+          HdBits b[4];
+          uint32_t lo[4], hi[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[q] = hb[min(h + q, hn - 1)];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            lo[q] = mb[b[q].woff];
+            hi[q] = mb[b[q].woff + 1];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t w = h + q < hn ? __builtin_amdgcn_alignbit(hi[q], lo[q], (uint32_t)b[q].sh) >> hs : 0u;
+            c0 += w & 0x01010101u;
+            c1 += (w >> 1) & 0x01010101u;
+            c2 += (w >> 2) & 0x01010101u;
+            c3 += (w >> 3) & 0x01010101u;
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const uint32_t c = (v & 3) == 0 ? c0 : (v & 3) == 1 ? c1 : (v & 3) == 2 ? c2 : c3;
+          mis[v] += (c >> (8 * (v >> 2))) & 0xFFu;
+        }
+      }
+      return;
+    }
     HdEnt e = {};
     if (nhd > 0) e = a.hd_ent[rec.hd0];
     for (int h = 0; h < nhd; ++h) {
@@ -479,7 +542,16 @@ void k_scan_fm(ScanArgs a) {
       // hard-data mismatch of this candidate for patch i (the next entry is
       // read while the current one's TI read is in flight)
       unsigned mis = 0;
-      if (r.nhd > 0) {
+      if (r.nhd > 0 && a.hdm) {
+        // bit table: candidate cx of patch i is bit j + sh of the datum's
+        // words from chunk ch on
+        const uint32_t* mb = a.hdm + (fz0 * a.hm.ry + fy0) * a.hm.rs + ch;
+        const HdBits* hb = a.hd_bits + r.hd0;
+        for (int h = 0; h < r.nhd; ++h) {
+          const HdBits b = hb[h];
+          mis += (mb[b.woff + ((j + b.sh) >> 5)] >> ((j + b.sh) & 31)) & 1u;
+        }
+      } else if (r.nhd > 0) {
         HdEnt e = a.hd_ent[r.hd0];
         for (int h = 0; h < r.nhd; ++h) {
           const HdEnt en = a.hd_ent[r.hd0 + min(h + 1, r.nhd - 1)];

@@ -82,6 +82,33 @@ def make(name: str, scale: float = 1.0, n_real: int | None = None):
     return p, ti, hd
 
 
+def dense_conditioning(n_hd: int, scale: float = 1.0):
+    """The C2 workload with n_hd hard data instead of 300 (dense conditioning:
+    4000 or 8000 at full size, the count scaled with the grid area)."""
+    p, ti, _ = make("c2_scale2d", scale=scale)
+    g = p["grid"]
+    ref = syn.channel_image_2d(g[0], g[1], max(3, int(round(50 * scale))), 3, seed=202)
+    hd = syn.sample_hard_data(ref, [max(1, int(round(n_hd * scale * scale)))], seed=303)
+    p["name"] = f"c2_dense{n_hd}"
+    p["max_hard_data"] = int(len(hd[0]))
+    return p, ti, hd
+
+
+def level_grid_case(level: int, grid_n: int, hd_per_512: int = 1000):
+    """Level x grid-size sweep: the C2 training image (500^2, 3 facies),
+    template 32, overlap 8, level J, a grid_n^2 grid conditioned by
+    hd_per_512 * (grid_n / 512)^2 hard data, seeded path."""
+    ti = syn.channel_image_2d(500, 500, 25, 3, seed=102)
+    n_hd = max(1, int(round(hd_per_512 * (grid_n / 512.0) ** 2)))
+    ref = syn.channel_image_2d(grid_n, grid_n, max(3, int(round(25 * grid_n / 500))), 3, seed=206)
+    hd = syn.sample_hard_data(ref, [n_hd], seed=306)
+    p = _base(ti=(500, 500), grid=(grid_n, grid_n), tmpl=(32, 32), overlap=(8, 8), level=level, top_k=10,
+              n_facies=3, seed=1, path_mode=1)
+    p["name"] = f"sweep_J{level}_n{grid_n}"
+    p["max_hard_data"] = int(len(hd[0]))
+    return p, ti, hd
+
+
 def describe(p) -> str:
     return (f"{p['name']}: TI {'x'.join(map(str, p['ti']))}, grid {'x'.join(map(str, p['grid']))}"
             f" x{p['n_real']}, T {'x'.join(map(str, p['tmpl']))}, OV {'x'.join(map(str, p['overlap']))},"

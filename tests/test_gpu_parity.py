@@ -363,6 +363,33 @@ def test_simulate_filter_major_scan(cc, orc, name, scale, nr):
         cc.set_scan_group(0)
 
 
+HD_PATH_CASES = [c for c in SIM_TINY if c[2] > 0] + [
+    ("wide_margin_j2", dict(ti=(70, 66), grid=(61, 58), tmpl=(14, 11), overlap=(5, 3), level=2, top_k=5,
+                            path_mode=1, n_real=3, cut=1, nc_margin=(9, 7, -1)), 60),
+    ("wide_margin_3d", dict(ti=(24, 22, 16), grid=(30, 26, 18), tmpl=(8, 8, 6), overlap=(2, 2, 2), level=1,
+                            top_k=4, path_mode=1, n_real=2, cut=1, nc_margin=(5, 3, 4)), 40),
+]
+
+
+@pytest.mark.parametrize("case", HD_PATH_CASES, ids=[c[0] for c in HD_PATH_CASES])
+def test_hard_data_paths(cc, orc, case):
+    # hard-data mismatches from the bit table and from the TI codes, in the
+    # tile-group and filter-major scans
+    name, over, nhd = case
+    p, ti, hd = _tiny(over, nhd)
+    oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
+    for hd_direct in (0, 1):
+        for G in (1, 2, -1):
+            _say("hard-data paths", name, hd_direct, G)
+            cc.set_scan_group(G)
+            try:
+                out, chosen = _run(cc, dict(p, hd_direct=hd_direct), ti, hd)
+            finally:
+                cc.set_scan_group(0)
+            assert np.array_equal(chosen, ochosen), f"hd_direct={hd_direct} G={G}"
+            assert np.array_equal(out, oout), f"hd_direct={hd_direct} G={G}"
+
+
 def test_simulate_is_deterministic(cc):
     p, ti, hd = wl.make("c2_scale2d", scale=0.3)
     a, ca = _run(cc, p, ti, hd)
@@ -479,3 +506,26 @@ def test_learned_proposer_matches_oracle(cc, orc, case):
         rows *= (p["ti"][2] - p["tmpl"][2]) // 2 ** p["level"] + 1
     # every patch rescored at least one row and never more than all of them
     assert rep["proposer_patches"] <= rep["proposer_rows"] <= rep["proposer_patches"] * rows
+
+
+# --------------------------------------------------------------------------
+# Dense conditioning and the level x grid-size cases
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n_hd", [4000, 8000])
+@pytest.mark.parametrize("hd_direct", [0, 1])
+def test_dense_conditioning(cc, orc, n_hd, hd_direct):
+    p, ti, hd = wl.dense_conditioning(n_hd, scale=0.3)
+    p["hd_direct"] = hd_direct
+    _say("dense", n_hd, len(hd[0]), hd_direct)
+    out = _compare(cc, orc, p, ti, hd)
+    for r, pos, v in zip(*hd):
+        assert out[(r,) + tuple(pos[::-1])] == v
+
+
+@pytest.mark.parametrize("level,grid_n", [(1, 128), (2, 160), (3, 128), (3, 200)])
+def test_level_grid_cases(cc, orc, level, grid_n):
+    p, ti, hd = wl.level_grid_case(level, grid_n)
+    _say("level x grid", level, grid_n)
+    out = _compare(cc, orc, p, ti, hd)
+    for r, pos, v in zip(*hd):
+        assert out[(r,) + tuple(pos[::-1])] == v
