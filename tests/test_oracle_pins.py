@@ -400,3 +400,101 @@ def test_first_patch_is_a_ti_crop(orc):
     s = 24 - 6
     crop = ti[b * cy: b * cy + s, b * cx: b * cx + s]
     assert np.array_equal(out[0, :s, :s], crop)
+
+
+# --------------------------------------------------------------------------
+# realization statistics (Sec. 5.2, 5.3, 5.8)
+# --------------------------------------------------------------------------
+from oracle import stats as ost   # noqa: E402
+
+
+def test_histogram_counts_closed_form():
+    y, x = np.mgrid[0:6, 0:9]
+    img = ((x + y) % 3).astype(np.int8)
+    img[0, 0] = 7                                   # a code outside 0..2 counts nowhere
+    stack = np.stack([img, np.full_like(img, 1)])
+    per_image, per_cell = ost.histogram(stack, 3)
+    assert per_image.tolist() == [[17, 18, 18], [0, 54, 0]]
+    assert per_cell.sum() == 2 * 54 - 1
+    assert per_cell[1].min() >= 1                   # image 1 holds facies 1 everywhere
+    assert per_cell[:, 0, 0].tolist() == [0, 1, 0]
+
+
+def test_variogram_alternating_columns_and_step_edge():
+    ny, nx = 5, 12
+    cols = np.tile((np.arange(nx) % 2).astype(np.int8), (ny, 1))
+    d = ost.variogram(cols[None], 2, 0, nx - 1)[0]
+    for h in range(1, nx):
+        n = ost.pair_count(cols.shape, 0, h)
+        assert n == ny * (nx - h)
+        assert d[1, h - 1] == (n if h % 2 else 0) and d[0, h - 1] == d[1, h - 1]
+    assert not ost.variogram(cols[None], 2, 1, ny - 1).any()   # constant along y
+    a = 6
+    edge = np.zeros((ny, 2 * a), dtype=np.int8)
+    edge[:, :a] = 1
+    d = ost.variogram(edge[None], 2, 0, 2 * a - 1)[0, 1]
+    assert d.tolist() == [ny * min(h, 2 * a - h) for h in range(1, 2 * a)]
+
+
+def test_variogram_3d_layers_and_iid_sill():
+    z = np.arange(7)[:, None, None]
+    layers = np.broadcast_to((z % 2).astype(np.int8), (7, 4, 5)).copy()
+    d = ost.variogram(layers[None], 2, 2, 6)[0, 0]
+    assert d.tolist() == [ost.pair_count(layers.shape, 2, h) * (h % 2) for h in range(1, 7)]
+    # independent cells with P(f) = p: gamma(h) = p (1 - p) at every lag
+    rng = np.random.default_rng(5)
+    p = 0.3
+    img = (rng.random((400, 400)) < p).astype(np.int8)
+    d = ost.variogram(img[None], 2, 0, 5)[0, 1]
+    gam = [d[h - 1] / (2 * ost.pair_count(img.shape, 0, h)) for h in range(1, 6)]
+    assert np.allclose(gam, p * (1 - p), atol=0.005)
+
+
+def _canon(lab):
+    out = np.full(lab.shape, -1, dtype=np.int64)
+    seen = {}
+    for i, v in enumerate(lab.reshape(-1)):
+        if v >= 0:
+            out.reshape(-1)[i] = seen.setdefault(v, len(seen))
+    return out
+
+
+@pytest.mark.parametrize("shape,p", [((23, 31), 0.55), ((9, 10, 11), 0.35), ((1, 40), 0.5)])
+def test_components_equal_library_labelling(shape, p):
+    from scipy import ndimage
+    rng = np.random.default_rng(sum(shape))
+    mask = rng.random(shape) < p
+    ref, _ = ndimage.label(mask)          # face connectivity is the default structure
+    assert np.array_equal(_canon(ost.components(mask)), _canon(ref - 1))
+
+
+def test_connectivity_closed_forms():
+    ny, nx = 6, 10
+    full = np.ones((ny, nx), dtype=np.int8)
+    both, conn = ost.connectivity(full[None], 2, 0, nx - 1)
+    assert np.array_equal(both[0, 1], conn[0, 1])
+    assert both[0, 1].tolist() == [ny * (nx - h) for h in range(1, nx)] and not both[0, 0].any()
+    y, x = np.mgrid[0:ny, 0:nx]
+    checker = ((x + y) % 2).astype(np.int8)          # every cell of a facies is isolated
+    both, conn = ost.connectivity(checker[None], 2, 0, nx - 1)
+    assert not conn.any() and both[0, :, 1].min() > 0
+    stripes = (y % 2).astype(np.int8)                # rows alternate: one component per row
+    both, conn = ost.connectivity(stripes[None], 2, 0, nx - 1)
+    assert conn[0, 1].tolist() == [(ny // 2) * (nx - h) for h in range(1, nx)]
+    both, conn = ost.connectivity(stripes[None], 2, 1, ny - 1)
+    assert not conn.any()
+    assert both[0, 1].tolist() == [nx * len([r for r in range(ny - h) if r % 2 and (r + h) % 2])
+                                   for h in range(1, ny)]
+
+
+def test_connectivity_follows_paths_not_lines():
+    # two vertical bars 5 cells apart: joined by a bottom bar they form one
+    # component, without it two
+    u = np.zeros((8, 9), dtype=np.int8)
+    u[:, 1] = 1
+    u[:, 6] = 1
+    both, conn = ost.connectivity(u[None], 2, 0, 8)
+    assert both[0, 1, 4] == 8 and conn[0, 1, 4] == 0
+    u[7, 1:7] = 1
+    both, conn = ost.connectivity(u[None], 2, 0, 8)
+    assert both[0, 1, 4] == 8 and conn[0, 1, 4] == 8
