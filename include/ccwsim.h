@@ -276,6 +276,52 @@ int ccwsim_set_graphs(int on);
  * graphs.  Returns CCWSIM_ERR_INVALID_ARG for other values. */
 int ccwsim_set_scan_group(int g);
 
+/* ---- A17/A18: realization statistics (Sec. 5.2 Fig. 7b ensemble map;
+ * Sec. 5.3 Fig. 9 variograms and probability of connection; Sec. 5.8
+ * Fig. 16b facies proportions) ----
+ * The paper compares realizations with the TI through these statistics
+ * without writing them out; the entry points return the integer counts of
+ * their textbook forms, from which the ratios follow on the host:
+ *   proportion of f in image i   = per_image[i][f] / cells
+ *   ensemble map of f            = per_cell[f][c] / n_img
+ *   indicator variogram          = diff[i][f][h-1] / (2 N(h)),
+ *       N(h) = cells whose neighbour h cells further along `axis` exists
+ *   probability of connection    = connected[i][f][h-1] / both[i][f][h-1]
+ * codes: int8 DEVICE stack of n_img (<= 65535) images, [image][z][y][x] with x
+ * fastest, extent `shape` (ndim 2 or 3, at most 2^31 - 1 cells per image);
+ * codes outside 0 .. n_facies-1 belong to no facies.  axis: 0 = x (the
+ * paper's east-west), 1 = y (north-south), 2 = z.  Lags h = 1 .. max_lag
+ * cells, 1 <= max_lag <= min(n[axis] - 1, 4096).  Outputs are DEVICE
+ * arrays owned by the caller and fully overwritten.  n_img = 0 returns
+ * CCWSIM_OK without touching anything.  Errors: CCWSIM_ERR_SHAPE,
+ * CCWSIM_ERR_INVALID_ARG (counts, axis, lags, null pointers),
+ * CCWSIM_ERR_WORKSPACE (missing, too small or not 256-byte aligned),
+ * CCWSIM_ERR_UNSUPPORTED (images above 2^31 - 1 cells). */
+
+/* Workspace bytes of ccwsim_stats_variogram / _connectivity for n_img
+ * images of this extent (-1 on a bad shape). */
+int64_t ccwsim_stats_workspace_size(ccwsim_shape shape, int32_t n_img);
+
+/* per_image int64 [n_img][n_facies]: cells of image i holding f.
+ * per_cell int32 [n_facies][cells] (may be NULL): images holding f at each
+ * cell.  No workspace. */
+int ccwsim_stats_histogram(const int8_t* codes, ccwsim_shape shape, int32_t n_img, int32_t n_facies,
+                           int64_t* per_image, int32_t* per_cell, void* stream);
+
+/* diff int64 [n_img][n_facies][max_lag]: pairs of cells (x, x + h e_axis)
+ * inside the image whose indicators [code == f] differ. */
+int ccwsim_stats_variogram(const int8_t* codes, ccwsim_shape shape, int32_t n_img, int32_t n_facies,
+                           int32_t axis, int32_t max_lag, int64_t* diff, void* workspace,
+                           int64_t workspace_bytes, void* stream);
+
+/* both, connected int64 [n_img][n_facies][max_lag]: pairs at lag h along
+ * `axis` whose two cells hold f, and those of them whose cells lie in one
+ * connected component of f, cells being connected through shared faces (4
+ * neighbours in 2D, 6 in 3D). */
+int ccwsim_stats_connectivity(const int8_t* codes, ccwsim_shape shape, int32_t n_img, int32_t n_facies,
+                              int32_t axis, int32_t max_lag, int64_t* both, int64_t* connected,
+                              void* workspace, int64_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

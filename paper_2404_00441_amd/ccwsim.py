@@ -89,6 +89,14 @@ def load():
     L.ccwsim_simulate_report.argtypes = [p, p, i64, p, p]
     L.ccwsim_set_scan_group.restype = ctypes.c_int
     L.ccwsim_set_scan_group.argtypes = [ctypes.c_int]
+    L.ccwsim_stats_workspace_size.restype = i64
+    L.ccwsim_stats_workspace_size.argtypes = [Shape, i32]
+    L.ccwsim_stats_histogram.restype = ctypes.c_int
+    L.ccwsim_stats_histogram.argtypes = [p, Shape, i32, i32, p, p, p]
+    L.ccwsim_stats_variogram.restype = ctypes.c_int
+    L.ccwsim_stats_variogram.argtypes = [p, Shape, i32, i32, i32, i32, p, p, i64, p]
+    L.ccwsim_stats_connectivity.restype = ctypes.c_int
+    L.ccwsim_stats_connectivity.argtypes = [p, Shape, i32, i32, i32, i32, p, p, p, i64, p]
     _lib = L
     return L
 
@@ -96,7 +104,9 @@ def load():
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
-           "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group")
+           "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
+           "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
+           "ccwsim_stats_connectivity")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
@@ -316,3 +326,67 @@ def profile_read() -> dict:
     n = (ctypes.c_int64 * len(KINDS))()
     _check("ccwsim_profile_read", load().ccwsim_profile_read(ms, n))
     return {k: (ms[i], n[i]) for i, k in enumerate(KINDS)}
+
+
+# ---- realization statistics (Sec. 5.2, 5.3, 5.8) ----
+def _stack(imgs: torch.Tensor):
+    """int8 GPU stack [image][y][x] or [image][z][y][x] -> (n_img, Shape)."""
+    if imgs.dtype != torch.int8 or imgs.dim() not in (3, 4):
+        raise ValueError("images must be an int8 [image][y][x] or [image][z][y][x] tensor")
+    return imgs.shape[0], shape_of(tuple(imgs.shape[1:][::-1]))
+
+
+def stats_histogram(imgs: torch.Tensor, n_facies: int, per_cell: bool = True):
+    """(per_image int64 [image][facies], per_cell int32 [facies][..cells] or
+    None): cells holding each facies per image, images holding each facies
+    per cell (the ensemble map times the number of images)."""
+    n, sh = _stack(imgs)
+    pi = torch.empty((n, n_facies), dtype=torch.int64, device=imgs.device)
+    pc = torch.empty((n_facies,) + tuple(imgs.shape[1:]), dtype=torch.int32, device=imgs.device) if per_cell else None
+    _check("ccwsim_stats_histogram", load().ccwsim_stats_histogram(_ptr(imgs), sh, n, n_facies, _ptr(pi), _ptr(pc),
+                                                                   _stream()))
+    return pi, pc
+
+
+def _stats_ws(imgs, sh, n):
+    nb = load().ccwsim_stats_workspace_size(sh, n)
+    if nb < 0:
+        raise CcwsimError("ccwsim_stats_workspace_size", 1, load().ccwsim_last_error().decode())
+    ws = torch.empty(max(nb, 256) + 256, dtype=torch.uint8, device=imgs.device)
+    off = (-ws.data_ptr()) % 256
+    return ws, ctypes.c_void_p(ws.data_ptr() + off), nb
+
+
+def stats_variogram(imgs: torch.Tensor, n_facies: int, axis: int, max_lag: int) -> torch.Tensor:
+    """int64 [image][facies][max_lag]: pairs (x, x + h e_axis), h = 1..max_lag,
+    whose indicators of the facies differ; gamma = diff / (2 N(h))."""
+    n, sh = _stack(imgs)
+    out = torch.empty((n, n_facies, max_lag), dtype=torch.int64, device=imgs.device)
+    ws, wp, nb = _stats_ws(imgs, sh, n)
+    _check("ccwsim_stats_variogram", load().ccwsim_stats_variogram(_ptr(imgs), sh, n, n_facies, axis, max_lag,
+                                                                   _ptr(out), wp, nb, _stream()))
+    return out
+
+
+def stats_connectivity(imgs: torch.Tensor, n_facies: int, axis: int, max_lag: int):
+    """(both, connected) int64 [image][facies][max_lag]: pairs at lag h along
+    the axis whose cells both hold the facies, and those of them whose cells
+    share a face-connected component; the probability of connection is
+    connected / both."""
+    n, sh = _stack(imgs)
+    both = torch.empty((n, n_facies, max_lag), dtype=torch.int64, device=imgs.device)
+    conn = torch.empty_like(both)
+    ws, wp, nb = _stats_ws(imgs, sh, n)
+    _check("ccwsim_stats_connectivity", load().ccwsim_stats_connectivity(_ptr(imgs), sh, n, n_facies, axis, max_lag,
+                                                                         _ptr(both), _ptr(conn), wp, nb, _stream()))
+    return both, conn
+
+
+def pair_count(extent, axis: int, h: int) -> int:
+    """N(h): cell pairs at lag h along `axis` in an image of (x, y[, z]) extent."""
+    n = list(extent)
+    n[axis] = max(0, n[axis] - h)
+    out = 1
+    for v in n:
+        out *= v
+    return out

@@ -16,6 +16,7 @@
 #include "ccwsim.h"
 #include "dev_scan.h"
 #include "dev_learn.h"
+#include "dev_stats.h"
 
 using namespace ccw;
 
@@ -2436,5 +2437,138 @@ extern "C" int ccwsim_simulate_report(const ccwsim_params* p, const void* worksp
   HIP_TRY(hipMemcpyAsync(v, (const unsigned char*)workspace + P->ws_report, sizeof v, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int i = 0; i < 6; ++i) out[i] = (int64_t)v[i];
+  return CCWSIM_OK;
+}
+
+// ---- realization statistics (Sec. 5.2, 5.3, 5.8) ----
+namespace {
+constexpr int kStatMaxLag = 4096;
+
+int stat_shape(const ccwsim_shape& sh, StatShape& s) {
+  if (sh.ndim != 2 && sh.ndim != 3) return fail(CCWSIM_ERR_SHAPE, "ndim must be 2 or 3");
+  long long cells = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int n = sh.n[a];
+    if (n < 1) return fail(CCWSIM_ERR_SHAPE, "extent %d on axis %d", n, a);
+    if (a >= sh.ndim && n != 1) return fail(CCWSIM_ERR_SHAPE, "extent of unused axis %d must be 1", a);
+    s.n[a] = n;
+    cells *= n;
+  }
+  if (cells > 0x7fffffffll) return fail(CCWSIM_ERR_UNSUPPORTED, "images of more than 2^31 - 1 cells");
+  s.cells = cells;
+  s.rows = s.n[1] * s.n[2];
+  s.nwx = (s.n[0] + 31) / 32;
+  s.nwp = s.nwx + 1;
+  return CCWSIM_OK;
+}
+
+long long stat_bits_bytes(const StatShape& s, int n_img) { return align256((long long)n_img * s.rows * s.nwp * 4); }
+
+int stat_common(const int8_t* codes, const ccwsim_shape& shape, int n_img, int n_facies, StatShape& s) {
+  CCW_TRY(stat_shape(shape, s));
+  if (n_img < 0 || n_img > 65535) return fail(CCWSIM_ERR_INVALID_ARG, "n_img must be in [0, 65535]");
+  if (n_facies < 1 || n_facies > 127) return fail(CCWSIM_ERR_INVALID_ARG, "n_facies must be in [1, 127]");
+  if (n_img > 0 && !codes) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  return CCWSIM_OK;
+}
+
+int stat_lags(const ccwsim_shape& shape, int axis, int max_lag) {
+  if (axis < 0 || axis >= shape.ndim) return fail(CCWSIM_ERR_INVALID_ARG, "axis must be in [0, ndim)");
+  if (max_lag < 1 || max_lag > shape.n[axis] - 1 || max_lag > kStatMaxLag)
+    return fail(CCWSIM_ERR_INVALID_ARG, "max_lag must be in [1, min(n[axis] - 1, %d)]", kStatMaxLag);
+  return CCWSIM_OK;
+}
+
+unsigned stat_blocks(long long work, int n_img) {
+  const long long per = std::max(1ll, 2048ll / std::max(1, n_img));
+  return (unsigned)std::max(1ll, std::min(per, (work + kThreads - 1) / kThreads));
+}
+}  // namespace
+
+extern "C" int64_t ccwsim_stats_workspace_size(ccwsim_shape shape, int32_t n_img) {
+  StatShape s;
+  if (stat_shape(shape, s)) return -1;
+  if (n_img < 0) {
+    fail(CCWSIM_ERR_INVALID_ARG, "n_img must be >= 0");
+    return -1;
+  }
+  return stat_bits_bytes(s, n_img) + align256((long long)n_img * s.cells * 4);
+}
+
+extern "C" int ccwsim_stats_histogram(const int8_t* codes, ccwsim_shape shape, int32_t n_img, int32_t n_facies,
+                                      int64_t* per_image, int32_t* per_cell, void* stream) {
+  StatShape s;
+  CCW_TRY(stat_common(codes, shape, n_img, n_facies, s));
+  if (!per_image) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_img == 0) return CCWSIM_OK;
+  hipStream_t st = as_stream(stream);
+  unsigned long long* pi = (unsigned long long*)per_image;
+  k_st_fill_u64<<<nblocks((long long)n_img * n_facies), kThreads, 0, st>>>(pi, (long long)n_img * n_facies);
+  k_st_hist_images<<<dim3(stat_blocks(s.cells, n_img), (unsigned)n_img), kThreads, 0, st>>>(codes, s.cells,
+                                                                                             n_facies, pi);
+  if (per_cell) k_st_hist_cells<<<nblocks(s.cells), kThreads, 0, st>>>(codes, s.cells, n_img, n_facies, per_cell);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_stats_variogram(const int8_t* codes, ccwsim_shape shape, int32_t n_img, int32_t n_facies,
+                                      int32_t axis, int32_t max_lag, int64_t* diff, void* workspace,
+                                      int64_t workspace_bytes, void* stream) {
+  StatShape s;
+  CCW_TRY(stat_common(codes, shape, n_img, n_facies, s));
+  CCW_TRY(stat_lags(shape, axis, max_lag));
+  if (!diff) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_img == 0) return CCWSIM_OK;
+  if (!workspace || workspace_bytes < stat_bits_bytes(s, n_img))
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)stat_bits_bytes(s, n_img));
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  uint32_t* bits = (uint32_t*)workspace;
+  unsigned long long* out = (unsigned long long*)diff;
+  const long long nout = (long long)n_img * n_facies * max_lag;
+  k_st_fill_u64<<<nblocks(nout), kThreads, 0, st>>>(out, nout);
+  const long long words = (long long)n_img * s.rows * s.nwp;
+  // rows per block: a block's count for one lag (at most rb * nx pairs) stays
+  // within its 32-bit counter
+  const int rb = (int)std::max(1ll, std::min(32ll, 0x7fffffffll / s.n[0]));
+  for (int f = 0; f < n_facies; ++f) {
+    k_st_pack<<<nblocks(words), kThreads, 0, st>>>(codes, s, n_img, f, bits);
+    k_st_pairs<<<dim3((unsigned)((s.rows + rb - 1) / rb), (unsigned)n_img), kThreads, (size_t)max_lag * 4, st>>>(
+        bits, s, axis, max_lag, rb, out + (long long)f * max_lag, (long long)n_facies * max_lag);
+  }
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_stats_connectivity(const int8_t* codes, ccwsim_shape shape, int32_t n_img, int32_t n_facies,
+                                         int32_t axis, int32_t max_lag, int64_t* both, int64_t* connected,
+                                         void* workspace, int64_t workspace_bytes, void* stream) {
+  StatShape s;
+  CCW_TRY(stat_common(codes, shape, n_img, n_facies, s));
+  CCW_TRY(stat_lags(shape, axis, max_lag));
+  if (!both || !connected) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (n_img == 0) return CCWSIM_OK;
+  const long long need = ccwsim_stats_workspace_size(shape, n_img);
+  if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  uint32_t* bits = (uint32_t*)workspace;
+  int32_t* L = (int32_t*)((unsigned char*)workspace + stat_bits_bytes(s, n_img));
+  unsigned long long* ob = (unsigned long long*)both;
+  unsigned long long* oc = (unsigned long long*)connected;
+  const long long nout = (long long)n_img * n_facies * max_lag;
+  k_st_fill_u64<<<nblocks(nout), kThreads, 0, st>>>(ob, nout);
+  k_st_fill_u64<<<nblocks(nout), kThreads, 0, st>>>(oc, nout);
+  const long long words = (long long)n_img * s.rows * s.nwp;
+  const long long cells = (long long)n_img * s.cells;
+  for (int f = 0; f < n_facies; ++f) {
+    k_st_pack<<<nblocks(words), kThreads, 0, st>>>(codes, s, n_img, f, bits);
+    k_st_ccl_init<<<nblocks(cells), kThreads, 0, st>>>(bits, s, n_img, L);
+    k_st_ccl_merge<<<nblocks((long long)n_img * s.rows * s.nwx), kThreads, 0, st>>>(bits, s, n_img, L);
+    k_st_ccl_flatten<<<nblocks(cells), kThreads, 0, st>>>(s, n_img, L);
+    k_st_conn<<<dim3(stat_blocks(s.cells, n_img), (unsigned)n_img), kThreads, (size_t)max_lag * 8, st>>>(
+        L, s, axis, max_lag, ob + (long long)f * max_lag, oc + (long long)f * max_lag, (long long)n_facies * max_lag);
+  }
+  HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }

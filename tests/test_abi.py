@@ -133,3 +133,28 @@ def test_scan_group_validation(lib):
     assert lib.ccwsim_set_scan_group(3) == 1
     assert b"tiles per scan workgroup" in lib.ccwsim_last_error()
     assert lib.ccwsim_set_scan_group(0) == 0
+
+
+def test_stats_validation_errors(lib):
+    from paper_2404_00441_amd import ccwsim
+    sh = ccwsim.shape_of((40, 30))
+    assert lib.ccwsim_stats_workspace_size(sh, 3) > 0
+    assert lib.ccwsim_stats_workspace_size(ccwsim.shape_of((40, 0)), 3) == -1
+    assert lib.ccwsim_stats_workspace_size(sh, -1) == -1
+    fake = ctypes.c_void_p(256)
+    # (n_img, n_facies, axis, max_lag): rejected before anything is launched
+    for args in [(2, 0, 0, 5), (2, 128, 0, 5), (-1, 3, 0, 5), (2, 3, 2, 5), (2, 3, -1, 5), (2, 3, 0, 0),
+                 (2, 3, 0, 40), (2, 3, 1, 30)]:
+        n, nf, axis, lag = args
+        st = lib.ccwsim_stats_variogram(fake, sh, n, nf, axis, lag, fake, fake, 1 << 30, None)
+        assert st == 1, args
+        st = lib.ccwsim_stats_connectivity(fake, sh, n, nf, axis, lag, fake, fake, fake, 1 << 30, None)
+        assert st == 1, args
+    assert lib.ccwsim_stats_variogram(fake, sh, 2, 3, 0, 39, fake, None, 0, None) == 3      # no workspace
+    assert lib.ccwsim_stats_variogram(fake, sh, 2, 3, 1, 29, fake, ctypes.c_void_p(257), 1 << 30, None) == 3
+    assert lib.ccwsim_stats_connectivity(fake, sh, 2, 3, 0, 39, fake, fake, fake, 16, None) == 3
+    assert lib.ccwsim_stats_histogram(fake, ccwsim.shape_of((4, 4, 4, )), 1, 0, fake, None, None) == 1
+    assert lib.ccwsim_stats_histogram(fake, sh, 1, 3, None, None, None) == 1
+    # no images: nothing to do
+    assert lib.ccwsim_stats_histogram(None, sh, 0, 3, fake, None, None) == 0
+    assert lib.ccwsim_stats_variogram(None, sh, 0, 3, 0, 5, fake, None, 0, None) == 0
