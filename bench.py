@@ -243,6 +243,81 @@ def measure_next(cc, wl, dev):
     return out
 
 
+def measure_stats(cc, wl, dev, n_real=100, max_lag=200):
+    """An ensemble of C2 realizations in one call (the same 300 hard data for
+    each), then its statistics beside the TI's: facies counts and ensemble
+    map, indicator variograms along x and y, probability of connection
+    along x (each timed with events on the launch stream)."""
+    import numpy as np
+    import torch
+    p, ti, hd = wl.ensemble(n_real)
+    ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+    hd_d = cc.hd_to_device(hd, len(p["ti"]), device=dev)
+    sim = cc.Simulator(p, device=dev)
+    out = sim.run(ti_d, hd_d)
+    t_sim = _time_runs(lambda: sim.run(ti_d, hd_d, out=out), 2)
+    del sim
+    real = out.view(torch.int8)
+    nf = p["n_facies"]
+    res = {"workload": wl.describe(p), "simulate_ms": t_sim * 1e3,
+           "simulate_cells_per_s": n_real * int(np.prod(p["grid"])) / t_sim, "max_lag": max_lag}
+
+    def timed(fn, reps=3):
+        fn()
+        st = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            r = fn()
+        b.record(st)
+        b.synchronize()
+        return a.elapsed_time(b) / reps, r
+
+    ms = {}
+    ms["histogram"], (pi, pc) = timed(lambda: cc.stats_histogram(real, nf))
+    ms["variogram_x"], vx = timed(lambda: cc.stats_variogram(real, nf, 0, max_lag))
+    ms["variogram_y"], vy = timed(lambda: cc.stats_variogram(real, nf, 1, max_lag))
+    ms["connectivity_x"], (bx, cx) = timed(lambda: cc.stats_connectivity(real, nf, 0, max_lag))
+    res["ms"] = ms
+    cells = n_real * int(np.prod(p["grid"]))
+    res["cells_per_s"] = {k: cells / (v * 1e-3) for k, v in ms.items()}
+    # the TI's statistics and the ensemble's, as ratios
+    tid = ti_d.view(1, *ti_d.shape)
+    tpi, _ = cc.stats_histogram(tid, nf, per_cell=False)
+    tvx, tvy = cc.stats_variogram(tid, nf, 0, max_lag), cc.stats_variogram(tid, nf, 1, max_lag)
+    tbx, tcx = cc.stats_connectivity(tid, nf, 0, max_lag)
+    g, t_ext = p["grid"], p["ti"]
+    lags = np.arange(1, max_lag + 1)
+    n_r = {a: np.array([cc.pair_count(g, a, h) for h in lags], dtype=np.float64) for a in (0, 1)}
+    n_t = {a: np.array([cc.pair_count(t_ext, a, h) for h in lags], dtype=np.float64) for a in (0, 1)}
+
+    def gam(v, n):
+        return v.cpu().numpy().sum(axis=0) / (2.0 * n * v.shape[0])
+
+    def tau(b, c):
+        b, c = b.cpu().numpy().sum(axis=0), c.cpu().numpy().sum(axis=0)
+        return np.where(b > 0, c / np.maximum(b, 1), np.nan)
+
+    pick = [h for h in (1, 5, 10, 20, 50, 100, 200) if h <= max_lag]
+    q = {"proportions_ti": (tpi.cpu().numpy()[0] / np.prod(t_ext)).round(4).tolist(),
+         "proportions_realizations": (pi.cpu().numpy().sum(axis=0) / cells).round(4).tolist(),
+         "ensemble_map_hard_data_cells": None, "lags": pick}
+    for name, v_r, v_t, a in (("variogram_x", vx, tvx, 0), ("variogram_y", vy, tvy, 1)):
+        gr, gt = gam(v_r, n_r[a]), gam(v_t, n_t[a])
+        q[name] = {"facies": 1, "ti": [round(float(gt[1, h - 1]), 4) for h in pick],
+                   "realizations": [round(float(gr[1, h - 1]), 4) for h in pick]}
+    tr, tt = tau(bx, cx), tau(tbx, tcx)
+    q["connection_x"] = {"facies": 1, "ti": [round(float(tt[1, h - 1]), 4) for h in pick],
+                         "realizations": [round(float(tr[1, h - 1]), 4) for h in pick]}
+    # the ensemble map at hard-data cells: every realization honours them
+    pos = hd[1][: len(hd[1]) // n_real]
+    val = hd[2][: len(hd[2]) // n_real]
+    pcn = pc.cpu().numpy()
+    q["ensemble_map_hard_data_cells"] = float(np.mean([pcn[v, y, x] / n_real for (x, y), v in zip(pos, val)]))
+    res["quality"] = q
+    return res
+
+
 def measure_forms(cc, wl, dev):
     """Side measurements of the batched and precision-split forms.
 
@@ -389,6 +464,7 @@ def main():
         res["scan_kernel"] = measure_scan_kernel(cc, wl, dev)
     if a.next:
         res["next"] = measure_next(cc, wl, dev)
+        res["stats"] = measure_stats(cc, wl, dev)
 
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, ti, hd)

@@ -2443,6 +2443,7 @@ extern "C" int ccwsim_simulate_report(const ccwsim_params* p, const void* worksp
 // ---- realization statistics (Sec. 5.2, 5.3, 5.8) ----
 namespace {
 constexpr int kStatMaxLag = 4096;
+constexpr int kStatRowLds = 16000;   // widest row k_st_conn_x stages in LDS
 
 int stat_shape(const ccwsim_shape& sh, StatShape& s) {
   if (sh.ndim != 2 && sh.ndim != 3) return fail(CCWSIM_ERR_SHAPE, "ndim must be 2 or 3");
@@ -2561,13 +2562,25 @@ extern "C" int ccwsim_stats_connectivity(const int8_t* codes, ccwsim_shape shape
   k_st_fill_u64<<<nblocks(nout), kThreads, 0, st>>>(oc, nout);
   const long long words = (long long)n_img * s.rows * s.nwp;
   const long long cells = (long long)n_img * s.cells;
+  // x-axis counting: rows per block for about 2048 blocks, and a block's
+  // count for one lag (at most rbx * nx pairs) within 32 bits
+  const int rbx = (int)std::max(1ll, std::min({(long long)s.rows * n_img / 2048 + 1, 0x7fffffffll / s.n[0],
+                                               (long long)s.rows}));
   for (int f = 0; f < n_facies; ++f) {
     k_st_pack<<<nblocks(words), kThreads, 0, st>>>(codes, s, n_img, f, bits);
     k_st_ccl_init<<<nblocks(cells), kThreads, 0, st>>>(bits, s, n_img, L);
     k_st_ccl_merge<<<nblocks((long long)n_img * s.rows * s.nwx), kThreads, 0, st>>>(bits, s, n_img, L);
-    k_st_ccl_flatten<<<nblocks(cells), kThreads, 0, st>>>(s, n_img, L);
-    k_st_conn<<<dim3(stat_blocks(s.cells, n_img), (unsigned)n_img), kThreads, (size_t)max_lag * 8, st>>>(
-        L, s, axis, max_lag, ob + (long long)f * max_lag, oc + (long long)f * max_lag, (long long)n_facies * max_lag);
+    k_st_ccl_flatten<true><<<nblocks(cells), kThreads, 0, st>>>(s, n_img, L);
+    k_st_ccl_flatten<false><<<nblocks(cells), kThreads, 0, st>>>(s, n_img, L);
+    if (axis == 0 && s.n[0] <= kStatRowLds) {
+      k_st_conn_x<<<dim3((unsigned)((s.rows + rbx - 1) / rbx), (unsigned)n_img), kThreads,
+                    (size_t)(s.n[0] + 4) * 4, st>>>(L, s, max_lag, rbx, ob + (long long)f * max_lag,
+                                                    oc + (long long)f * max_lag, (long long)n_facies * max_lag);
+    } else {
+      k_st_conn<<<dim3(stat_blocks(s.cells, n_img), (unsigned)n_img), kThreads, (size_t)max_lag * 8, st>>>(
+          L, s, axis, max_lag, ob + (long long)f * max_lag, oc + (long long)f * max_lag,
+          (long long)n_facies * max_lag);
+    }
   }
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;

@@ -246,14 +246,25 @@ __global__ __launch_bounds__(kThreads) void k_st_ccl_merge(const uint32_t* __res
   }
 }
 
-// Every label replaced by its root.
+// Every label replaced by its root, in two passes.  Only the first cell of
+// a run ever changes its parent during the merge (the others keep pointing
+// at it), so the first pass resolves the run starts and the second copies
+// each start's root to the rest of its run.
+template <bool STARTS>
 __global__ __launch_bounds__(kThreads) void k_st_ccl_flatten(StatShape s, int n_img, int32_t* __restrict__ L) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long long)n_img * s.cells) return;
   const long long img = id / s.cells;
   const int c = (int)(id - img * s.cells);
   int32_t* Li = L + img * s.cells;
-  if (Li[c] >= 0) Li[c] = st_find(Li, c);
+  const int p = Li[c];
+  if (p < 0) return;
+  const bool start = c % s.n[0] == 0 || Li[c - 1] < 0;   // membership of f never changes
+  if (STARTS) {
+    if (start) Li[c] = st_find(Li, c);
+  } else if (!start) {
+    Li[c] = Li[p];   // p is the run's start, resolved by the first pass
+  }
 }
 
 // Pairs at lags 1..H along `axis` whose cells both hold f, and those whose
@@ -307,6 +318,53 @@ __global__ __launch_bounds__(kThreads) void k_st_conn(const int32_t* __restrict_
   for (int h = tid; h < H; h += kThreads) {
     if (s_both[h]) atomicAdd(both + (long long)img * out_stride + h, (unsigned long long)s_both[h]);
     if (s_conn[h]) atomicAdd(conn + (long long)img * out_stride + h, (unsigned long long)s_conn[h]);
+  }
+}
+
+// The same counts along x with one lag per thread: a block stages each of
+// its rows' labels in LDS (padded by -1) and every thread walks the row for
+// its lag, four cells per step (one broadcast 16-byte read of the cells,
+// four reads of their partners, which differ between lanes by one word).
+// Grid (row blocks of rb rows, images); dynamic LDS (nx + 4) labels.
+__global__ __launch_bounds__(kThreads) void k_st_conn_x(const int32_t* __restrict__ L, StatShape s, int H, int rb,
+                                                        unsigned long long* __restrict__ both,
+                                                        unsigned long long* __restrict__ conn, long long out_stride) {
+  extern __shared__ __align__(16) int32_t s_row[];
+  const int tid = threadIdx.x, img = blockIdx.y;
+  const int nx = s.n[0];
+  const int r0 = blockIdx.x * rb, r1 = min(s.rows, r0 + rb);
+  const int32_t* Li = L + (long long)img * s.cells;
+  constexpr int kLagsPerThread = 16;   // H <= 4096 = 16 * 256
+  uint32_t nb[kLagsPerThread], nc[kLagsPerThread];
+#pragma unroll
+  for (int k = 0; k < kLagsPerThread; ++k) nb[k] = nc[k] = 0;
+  if (tid < 4) s_row[nx + tid] = -1;
+  for (int r = r0; r < r1; ++r) {
+    __syncthreads();
+    for (int x = tid; x < nx; x += kThreads) s_row[x] = Li[(long long)r * nx + x];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kLagsPerThread; ++k) {
+      const int h = 1 + tid + k * kThreads;
+      if (k * kThreads >= H) break;
+      if (h > H) continue;
+      uint32_t b = 0, c = 0;
+      for (int x = 0; x < nx - h; x += 4) {
+        const int4 a = *(const int4*)(s_row + x);
+        const int p0 = s_row[x + h], p1 = s_row[x + h + 1], p2 = s_row[x + h + 2], p3 = s_row[x + h + 3];
+        b += (a.x >= 0 && p0 >= 0) + (a.y >= 0 && p1 >= 0) + (a.z >= 0 && p2 >= 0) + (a.w >= 0 && p3 >= 0);
+        c += (a.x >= 0 && a.x == p0) + (a.y >= 0 && a.y == p1) + (a.z >= 0 && a.z == p2) + (a.w >= 0 && a.w == p3);
+      }
+      nb[k] += b;
+      nc[k] += c;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kLagsPerThread; ++k) {
+    const int h = 1 + tid + k * kThreads;
+    if (h > H) break;
+    if (nb[k]) atomicAdd(both + (long long)img * out_stride + h - 1, (unsigned long long)nb[k]);
+    if (nc[k]) atomicAdd(conn + (long long)img * out_stride + h - 1, (unsigned long long)nc[k]);
   }
 }
 

@@ -94,6 +94,20 @@ def dense_conditioning(n_hd: int, scale: float = 1.0):
     return p, ti, hd
 
 
+def ensemble(n_real: int = 100, scale: float = 1.0):
+    """The C2 workload as an ensemble: n_real realizations in one call, all
+    conditioned by the same 300 hard data (the set-up of the ensemble map
+    and of the variogram and connection checks)."""
+    p, ti, hd = make("c2_scale2d", scale=scale)
+    real, pos, val = hd
+    m = len(real)
+    hd = (np.repeat(np.arange(n_real, dtype=np.int32), m), np.tile(pos, (n_real, 1)), np.tile(val, n_real))
+    p["n_real"] = n_real
+    p["name"] = f"c2_ensemble{n_real}"
+    p["max_hard_data"] = int(len(hd[0]))
+    return p, ti, hd
+
+
 def level_grid_case(level: int, grid_n: int, hd_per_512: int = 1000):
     """Level x grid-size sweep: the C2 training image (500^2, 3 facies),
     template 32, overlap 8, level J, a grid_n^2 grid conditioned by
