@@ -276,6 +276,20 @@ int ccwsim_set_graphs(int on);
  * graphs.  Returns CCWSIM_ERR_INVALID_ARG for other values. */
 int ccwsim_set_scan_group(int g);
 
+/* Selection of the K best candidates (Sec. 4.4).  Stored keys: the scan
+ * writes every candidate's key and the row minimum of every candidate row;
+ * the finalize step reads the keys of the K rows with the smallest minima.
+ * Row minima: the scan writes only the row minima and the finalize step
+ * recomputes the exact keys of rows in order of their minima until the K
+ * best are certified (at most K rows); the scan then stores 8 bytes per
+ * candidate row instead of per candidate.  Both give the same results.  The
+ * row minima need score_mode 0, no shortlist and at most 512 candidate rows
+ * (else the stored keys are used).  0 (the default) lets the tuner of
+ * ccwsim_set_scan_group choose on the first call of a parameter set; 1 and 2
+ * force stored keys or row minima (for tests).  Drops captured graphs.
+ * Returns CCWSIM_ERR_INVALID_ARG for other values. */
+int ccwsim_set_selection(int mode);
+
 /* ---- A17/A18: realization statistics (Sec. 5.2 Fig. 7b ensemble map;
  * Sec. 5.3 Fig. 9 variograms and probability of connection; Sec. 5.8
  * Fig. 16b facies proportions) ----

@@ -89,6 +89,8 @@ def load():
     L.ccwsim_simulate_report.argtypes = [p, p, i64, p, p]
     L.ccwsim_set_scan_group.restype = ctypes.c_int
     L.ccwsim_set_scan_group.argtypes = [ctypes.c_int]
+    L.ccwsim_set_selection.restype = ctypes.c_int
+    L.ccwsim_set_selection.argtypes = [ctypes.c_int]
     L.ccwsim_stats_workspace_size.restype = i64
     L.ccwsim_stats_workspace_size.argtypes = [Shape, i32]
     L.ccwsim_stats_histogram.restype = ctypes.c_int
@@ -105,7 +107,7 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
-           "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
+           "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
            "ccwsim_stats_connectivity")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
@@ -310,6 +312,11 @@ def simulate_stats(p: dict) -> dict:
 def set_scan_group(g: int):
     """0: tuned tiles per scan workgroup; 1, 2, 4 or 8: forced."""
     _check("ccwsim_set_scan_group", load().ccwsim_set_scan_group(int(g)))
+
+
+def set_selection(mode: int):
+    """0: tuned; 1: stored keys; 2: row minima with exact rescoring of rows."""
+    _check("ccwsim_set_selection", load().ccwsim_set_selection(mode))
 
 
 def set_graphs(on: bool):

@@ -155,6 +155,7 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 int g_scan_g_force = 0;   // 0: tuned choice; else tiles per scan workgroup (testing)
+int g_sel_force = 0;      // 0: tuned choice; 1: stored keys; 2: row minima + exact rescoring
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
 
@@ -524,6 +525,8 @@ struct Plan {
   int learn_kbr = 0, learn_w = 0;
   size_t proxy_lds = 0;
   int scan_g = 1;                     // tiles per scan workgroup (tuned)
+  bool rows_ok = false;               // the row-minima selection fits this plan
+  bool sel_rows = false;              // row-minima selection chosen (tuned)
   bool tuned = false;
   int max_slots = 0, nsteps_raster = 0;
   long long patches = 0, or_blocks = 0, band_cells = 0;
@@ -886,12 +889,16 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
     return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
   P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride + (size_t)((2 * g.tcells * 4 + 15) & ~15ll);
-  if (P.learn) {
+  const bool rows_try = !P.learn && p.score_mode == 0 && p.shortlist == 0 &&
+                        (long long)g.cand[1] * g.cand[2] <= 512 && P.kpad <= kKMax;
+  if (P.learn || rows_try) {
     // rows by bound, the keys of a round of rows and their level-J rows (int16)
     const long long nrows = (long long)g.cand[1] * g.cand[2];
     P.learn_w = (int)((g.cand[0] + g.tc[0] - 1 + 1) & ~1);
     P.learn_off = (long long)((P.fin_lds + 15) & ~(size_t)15);
-    for (P.learn_kbr = 4; P.learn_kbr >= 1; --P.learn_kbr) {
+    // rows per round: with exact row minima the k best need at most k rows
+    const int kbr_max = P.learn ? 4 : std::min(16, std::max(1, std::min(p.top_k, g.ncand)));
+    for (P.learn_kbr = kbr_max; P.learn_kbr >= 1; --P.learn_kbr) {
       const long long bytes = nrows * 8 + ((nrows + 1) & ~1ll) * 4 + (long long)P.learn_kbr * g.cand[0] * 8 +
                               (long long)P.learn_kbr * g.tc[1] * g.tc[2] * P.learn_w * 2;
       if (P.learn_off + bytes <= 64 * 1024) {
@@ -899,7 +906,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
         break;
       }
     }
-    if (P.learn_kbr < 1) return fail(CCWSIM_ERR_UNSUPPORTED, "proposer row rescoring does not fit the LDS");
+    if (P.learn && P.learn_kbr < 1) return fail(CCWSIM_ERR_UNSUPPORTED, "proposer row rescoring does not fit the LDS");
+    P.rows_ok = rows_try && P.learn_kbr >= 1;
   }
   if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
   // the coefficient staging area aliases the key list and the cut scratch
@@ -1280,8 +1288,13 @@ struct FinArgs {
   int dp_wave;          // 1: every overlap <= 16 cells, one 16-lane group per seam
   int dp_evs;           // step stride of the seam error buffer (wavefront DP)
   int dp_stride, dp_batch;
-  // learned proposer (learn = D > 0)
+  // learned proposer (learn = D > 0), or the row-minima selection
   int learn;
+  int rescore_rows;               // select by exact rescoring of rows in order of their minima / bounds
+  int rows_exact;                 // the row keys are exact keys (row-minima selection)
+  const uint32_t* hdm;            // hard-data bit table, or null
+  const HdBits* hd_bits;
+  HdmGeom hm;
   float* qbuf;                    // [patch][D + 4] queries of the data events
   const float* pca_P;             // [D][template blocks]
   const float* pca_mu;            // [template blocks]
@@ -1440,7 +1453,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   // the row minima depend on the slot only: fetch them with the record
   const int nrows_c = g.cand[1] * g.cand[2];
   uint64_t rm_pre = ~0ull;
-  if ((a.cand_cap > 0 || a.learn) && tid < nrows_c) rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
+  if ((a.cand_cap > 0 || a.rescore_rows) && tid < nrows_c) rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
   const long long wpad = (g.wcells + 15) & ~15ll;
   int32_t* bufA = (int32_t*)smem;
   int32_t* bufB = bufA + a.buf_cells;
@@ -1488,22 +1501,25 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   __shared__ unsigned s_cnt;
   const int ksel = a.shortlist > 0 ? min(a.shortlist, g.ncand) : k;
   bool done = false;
-  if (a.learn) {
-    // Learned proposer: the scan wrote, per candidate row, the smallest lower
-    // bound of its keys.  Rows are rescored exactly in order of their bound,
-    // a few at a time, until the k best exact keys lie below the bound of
-    // every row left (certified), so the k best equal the full scan's.
+  if (a.rescore_rows) {
+    // The scan wrote, per candidate row, the smallest key of the row (the
+    // row-minima selection) or the smallest lower bound of its keys (the
+    // learned proposer).  Rows are rescored exactly in order of their
+    // minimum or bound, a few at a time, until the k best exact keys lie
+    // below the minimum or bound of every row left (certified), so the k
+    // best equal the full scan's.  With exact minima that takes at most k
+    // rows: a row holding one of the k best keys has its minimum among them.
     const int nrows = g.cand[1] * g.cand[2];
     const int C0 = g.cand[0];
     const uint64_t* rm = a.rowmin + (long long)slot * nrows;
-    const bool exact_rows = f.bandmask == 0;   // no overlap: the row keys are exact keys
+    const bool exact_rows = a.rows_exact || f.bandmask == 0;   // no overlap: the row keys are exact keys
     unsigned char* lb = smem + a.learn_off;
     uint64_t* s_rk = (uint64_t*)lb;                                  // [nrows] sort keys
     int* s_order = (int*)(s_rk + nrows);                             // [nrows] rows by bound
     uint64_t* s_bkey = (uint64_t*)(s_order + ((nrows + 1) & ~1));    // [kbr * C0] batch keys
     int16_t* s_stage = (int16_t*)(s_bkey + a.learn_kbr * C0);        // [kbr][K rows][W] int16
     __shared__ int s_koff[kKMax], s_km[kKMax];
-    __shared__ int s_row_of[8];
+    __shared__ int s_row_of[16];
     const int nkr = g.tc[1] * g.tc[2];
     const int W = a.learn_w;
     // block list of this orientation with the exact data event
@@ -1518,6 +1534,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       s_koff[tid] = off;
       s_km[tid] = m;
     }
+    // the orientation's block list ends at its first -1
+    const int nk = __syncthreads_count(tid < a.kpad && my_beta >= 0);
     // sort keys: a bound's tie field carries the row index (distinct keys)
     for (int i = tid; i < nrows; i += kThreads) {
       const uint64_t v = i < kThreads ? rm_pre : rm[i];
@@ -1546,14 +1564,32 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       const int nb_rows = min(a.learn_kbr, nrows - pos);
       if (tid < nb_rows) s_row_of[tid] = min(max(s_order[pos + tid], 0), nrows - 1);
       __syncthreads();
-      // stage the level-J rows these candidate rows read, as int16
-      for (int i = tid; i < nb_rows * nkr * W; i += kThreads) {
-        const int b = i / (nkr * W), rest = i - b * (nkr * W);
-        const int kr = rest / W, x = rest - kr * W;
-        const int row = s_row_of[b];
-        const int cy = row % g.cand[1], cz = row / g.cand[1];
-        const int by = kr % g.tc[1], bz = kr / g.tc[1];
-        s_stage[i] = x < g.G[0] ? (int16_t)a.Ki[idx3i(x, cy + by, cz + bz, g.G)] : (int16_t)0;
+      // stage the level-J rows these candidate rows read, as int16; every
+      // load of a thread's share is issued before any of them is stored
+      {
+        constexpr int U = 16;
+        const int total = nb_rows * nkr * W;
+        for (int base = tid; base < total; base += kThreads * U) {
+          int16_t v[U];
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int i = base + q * kThreads;
+            v[q] = 0;
+            if (i < total) {
+              const int b = i / (nkr * W), rest = i - b * (nkr * W);
+              const int kr = rest / W, x = rest - kr * W;
+              const int row = s_row_of[b];
+              const int cy = row % g.cand[1], cz = row / g.cand[1];
+              const int by = kr % g.tc[1], bz = kr / g.tc[1];
+              if (x < g.G[0]) v[q] = (int16_t)a.Ki[idx3i(x, cy + by, cz + bz, g.G)];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int i = base + q * kThreads;
+            if (i < total) s_stage[i] = v[q];
+          }
+        }
       }
       __syncthreads();
       // exact keys of every candidate of the batch
@@ -1564,16 +1600,24 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
         const int cy = row % g.cand[1], cz = row / g.cand[1];
         const int16_t* st = s_stage + b * nkr * W + cx;
         int C = 0;
-        for (int kk = 0; kk < a.kpad; ++kk)
-          if (s_koff[kk] >= 0) C += s_km[kk] * (int)st[s_koff[kk]];
+#pragma unroll 8
+        for (int kk = 0; kk < nk; ++kk) C += s_km[kk] * (int)st[s_koff[kk]];
         const long long idx = (long long)row * C0 + cx;
         const int S = erow[idx] - (C << shift);
         unsigned mis = 0;
-        for (int h = 0; h < nhd; ++h) {
-          const HdEnt e = a.hd_ent[hd0 + h];
-          const int fx = (cx << J) + e.u[0], fy = (cy << J) + e.u[1], fz = (cz << Jz) + e.u[2];
-          if (fx >= 0 && fy >= 0 && fz >= 0 && fx < g.ti[0] && fy < g.ti[1] && fz < g.ti[2])
-            mis += a.ti[(fz * g.ti[1] + fy) * g.ti[0] + fx] != e.v ? 1u : 0u;
+        if (a.hdm) {   // bit cx + sh of the datum's vector for this row
+          const uint32_t* mb = a.hdm + ((cz << Jz) * a.hm.ry + (cy << J)) * a.hm.rs;
+          for (int h = 0; h < nhd; ++h) {
+            const HdBits hb = a.hd_bits[hd0 + h];
+            mis += (mb[hb.woff + ((cx + hb.sh) >> 5)] >> ((cx + hb.sh) & 31)) & 1u;
+          }
+        } else {
+          for (int h = 0; h < nhd; ++h) {
+            const HdEnt e = a.hd_ent[hd0 + h];
+            const int fx = (cx << J) + e.u[0], fy = (cy << J) + e.u[1], fz = (cz << Jz) + e.u[2];
+            if (fx >= 0 && fy >= 0 && fz >= 0 && fx < g.ti[0] && fy < g.ti[1] && fz < g.ti[2])
+              mis += a.ti[(fz * g.ti[1] + fy) * g.ti[0] + fx] != e.v ? 1u : 0u;
+          }
         }
         s_bkey[i] = make_key(mis, f.bandmask ? S : 0, tie_perm((uint32_t)idx, tkey));
       }
@@ -1587,7 +1631,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       pos += nb_rows;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && a.learn) {
       atomicAdd(&a.report[4], 1ull);                       // patches selected through the proposer
       atomicAdd(&a.report[5], (unsigned long long)pos);    // candidate rows rescored exactly
     }
@@ -1935,6 +1979,10 @@ int scan_group_of(const Plan* P) {
   return G >= 8 ? 8 : G >= 4 ? 4 : G >= 2 ? 2 : 1;
 }
 int group_index(int V) { return V == 8 ? 3 : V == 4 ? 2 : V == 2 ? 1 : 0; }   // filter-major: single tiles
+bool sel_rows_of(const Plan* P) {
+  if (!P->rows_ok) return false;
+  return g_sel_force != 0 ? g_sel_force == 2 : P->sel_rows;
+}
 
 int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
                      const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen, void* workspace,
@@ -2056,6 +2104,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   sa.kpad = P->kpad;
   sa.W = P->W;
   sa.score_mode = p->score_mode;
+  sa.rowmin_only = !P->learn && sel_rows_of(P);
   sa.standalone = 0;
   sa.has_hd = n_hd > 0;
 
@@ -2095,6 +2144,11 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.dp_stride = P->dp_stride;
   fa.dp_batch = P->dp_batch;
   fa.learn = P->learn;
+  fa.rescore_rows = P->learn || sel_rows_of(P);
+  fa.rows_exact = !P->learn;
+  fa.hdm = n_hd > 0 ? hdmask : nullptr;
+  fa.hd_bits = hd_bits;
+  fa.hm = P->hm;
   fa.qbuf = qbuf;
   fa.pca_P = pca_P;
   fa.pca_mu = pca_mu;
@@ -2239,6 +2293,17 @@ extern "C" int ccwsim_set_scan_group(int g) {
   return CCWSIM_OK;
 }
 
+extern "C" int ccwsim_set_selection(int mode) {
+  if (mode < 0 || mode > 2)
+    return fail(CCWSIM_ERR_INVALID_ARG, "selection must be 0 (tuned), 1 (stored keys) or 2 (row minima)");
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    drop_graphs();   // captured graphs hold the previous choice
+  }
+  g_sel_force = mode;
+  return CCWSIM_OK;
+}
+
 extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, const int32_t* hd_real,
                                const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
                                void* workspace, int64_t workspace_bytes, void* stream) {
@@ -2261,13 +2326,15 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   // First call of a plan: look the scan shape up in the tuning table, else
   // run eagerly once (a full, valid call) and time the widest step's scan
   // for each variant (output layout, tiles per workgroup).
-  if (!P->tuned && g_scan_g_force == 0 && !P->learn) {
+  if (!P->tuned && g_scan_g_force == 0 && g_sel_force == 0 && !P->learn) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_once();
     const std::string tk = tune_key(P, p);
     const auto it = g_tune.find(tk);
     if (it != g_tune.end()) {
-      P->scan_g = it->second;
+      // stored as the tiles per workgroup, plus 100 for the row-minima selection
+      P->sel_rows = it->second > 50 && P->rows_ok;
+      P->scan_g = it->second > 50 ? it->second - 100 : it->second;
       P->tuned = true;
     } else {
       hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
@@ -2281,12 +2348,13 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
         HIP_TRY(hipEventCreate(&e1));
         float best_ms = 3.4e38f;
         int best = 1, rc = CCWSIM_OK;
-        for (int c : {1, kScanFilterMajor, 2, 4, 8}) {
-          if (c > P->scan_g_max) break;
+        bool best_rows = false;
+        auto try_variant = [&](int c, bool rows) {
           P->scan_g = c;
+          P->sel_rows = rows;
           HIP_TRY(hipEventRecord(e0, st));
           rc = enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, st);
-          if (rc != CCWSIM_OK) break;
+          if (rc != CCWSIM_OK) return rc;
           HIP_TRY(hipEventRecord(e1, st));
           HIP_TRY(hipEventSynchronize(e1));
           float ms = 0.f;
@@ -2294,14 +2362,28 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
           if (ms < best_ms * 0.95f) {   // another variant must beat the first by 5 %
             best_ms = ms;
             best = c;
+            best_rows = rows;
           }
+          return CCWSIM_OK;
+        };
+        // the scan's layout and tiles with stored keys, then the row-minima
+        // selection (no stored keys, exact rescoring of the best rows) with
+        // the best layout and with single tiles
+        for (int c : {1, kScanFilterMajor, 2, 4, 8}) {
+          if (c > P->scan_g_max) break;
+          if (try_variant(c, false) != CCWSIM_OK) break;
+        }
+        if (rc == CCWSIM_OK && P->rows_ok) {
+          const int kb = best;
+          if (try_variant(kb, true) == CCWSIM_OK && kb != 1) try_variant(1, true);
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         P->scan_g = best;
+        P->sel_rows = best_rows;
         if (rc == CCWSIM_OK) {
           P->tuned = true;
-          g_tune[tk] = best;
+          g_tune[tk] = best + (best_rows ? 100 : 0);
           tune_save();
         }
         return rc;

@@ -95,7 +95,8 @@ struct ScanArgs {
   int fbegin;                  // simulate: global index of this step's first patch
   int kpad;                    // padded K dimension (multiple of 16)
   int W;                       // LDS strip row length (halves)
-  int score_mode;              // 0 squared difference, 1 raw
+  int score_mode;
+  int rowmin_only;             // simulate: write the row minima only (no per-candidate keys)              // 0 squared difference, 1 raw
   int standalone;              // 1: filters/tiles/kbeta are implicit
   int n_filters;               // standalone: number of filters
   int has_hd;
@@ -383,7 +384,7 @@ void k_scan(ScanArgs a) {
           continue;
         }
         const uint64_t key = make_key(mis[v], S, tie_perm((uint32_t)idx, rec.tkey));
-        a.keys[(long long)slot * g.ncand + idx] = key;
+        if (!a.rowmin_only) a.keys[(long long)slot * g.ncand + idx] = key;
         lane_min = key < lane_min ? key : lane_min;
       }
     }
@@ -564,7 +565,7 @@ void k_scan_fm(ScanArgs a) {
         }
       }
       const uint64_t key = make_key(mis, S, tie_perm((uint32_t)idx, r.tkey));
-      a.keys[o] = key;
+      if (!a.rowmin_only) a.keys[o] = key;
       lmin[v] = key < lmin[v] ? key : lmin[v];
     }
   }

@@ -158,3 +158,9 @@ def test_stats_validation_errors(lib):
     # no images: nothing to do
     assert lib.ccwsim_stats_histogram(None, sh, 0, 3, fake, None, None) == 0
     assert lib.ccwsim_stats_variogram(None, sh, 0, 3, 0, 5, fake, None, 0, None) == 0
+
+
+def test_selection_switch_validation(lib):
+    assert lib.ccwsim_set_selection(3) == 1
+    assert lib.ccwsim_set_selection(-1) == 1
+    assert lib.ccwsim_set_selection(0) == 0

@@ -390,6 +390,58 @@ def test_hard_data_paths(cc, orc, case):
             assert np.array_equal(out, oout), f"hd_direct={hd_direct} G={G}"
 
 
+SEL_CASES = [c for c in SIM_TINY if c[1].get("score_mode", 0) == 0]
+
+
+@pytest.mark.parametrize("case", SEL_CASES, ids=[c[0] for c in SEL_CASES])
+def test_row_minima_selection_small(cc, orc, case):
+    # the scan writes row minima only; the K best come from exact rescoring
+    # of rows in order of their minima
+    name, over, nhd = case
+    p, ti, hd = _tiny(over, nhd)
+    oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
+    for G in (1, -1, 2):
+        _say("row minima", name, G)
+        cc.set_selection(2)
+        cc.set_scan_group(G)
+        try:
+            out, chosen = _run(cc, p, ti, hd)
+        finally:
+            cc.set_scan_group(0)
+            cc.set_selection(0)
+        assert np.array_equal(chosen, ochosen), f"G={G}"
+        assert np.array_equal(out, oout), f"G={G}"
+
+
+@pytest.mark.parametrize("name,scale,nr", WORKLOAD_CASES + [("c2_scale2d", 1.0, None)],
+                         ids=[f"{c[0]}_s{c[1]}" for c in WORKLOAD_CASES] + ["c2_full"])
+def test_row_minima_selection_workloads(cc, orc, name, scale, nr):
+    _say("row minima workload", name, scale, nr)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    cc.set_selection(2)
+    try:
+        _compare(cc, orc, p, ti, hd)
+    finally:
+        cc.set_selection(0)
+
+
+@pytest.mark.parametrize("hd_direct", [0, 1])
+def test_row_minima_selection_dense(cc, orc, hd_direct):
+    p, ti, hd = wl.dense_conditioning(8000, scale=0.3)
+    p["hd_direct"] = hd_direct
+    _say("row minima dense", hd_direct)
+    cc.set_selection(2)
+    try:
+        _compare(cc, orc, p, ti, hd)
+    finally:
+        cc.set_selection(0)
+
+
+def test_selection_validation(cc):
+    with pytest.raises(cc.CcwsimError):
+        cc.set_selection(3)
+
+
 def test_simulate_is_deterministic(cc):
     p, ti, hd = wl.make("c2_scale2d", scale=0.3)
     a, ca = _run(cc, p, ti, hd)
