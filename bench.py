@@ -42,8 +42,8 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and precision-split side measurements")
-    ap.add_argument("--next", action="store_true",
-                    help="also measure dense conditioning and the level x grid-size sweep")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip dense conditioning, the level x grid-size sweep and the ensemble statistics")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -462,7 +462,7 @@ def main():
     if not a.no_forms:
         res["forms"] = measure_forms(cc, wl, dev)
         res["scan_kernel"] = measure_scan_kernel(cc, wl, dev)
-    if a.next:
+    if not a.no_next:
         res["next"] = measure_next(cc, wl, dev)
         res["stats"] = measure_stats(cc, wl, dev)
 
