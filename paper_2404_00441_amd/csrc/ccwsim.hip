@@ -548,7 +548,7 @@ struct Plan {
             ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
-  int tree_level = 0;   // 1 or 2: block-subtree coefficients; 0: planar details
+  int tree_level = 0;   // 1, 2 (or 3 in 2D): block-subtree coefficients; 0: planar details
   int dp_stride = 0, dp_batch = 0, rows_max = 0, dp_wave = 0, dp_evs = 0;
   ~Plan() {
     if (tbl) (void)hipHostFree(tbl);
@@ -852,8 +852,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   for (int o = 0; o < P.n_orient; ++o)
     for (size_t i = 0; i < klists[o].size(); ++i) kbeta[(size_t)o * kKMax + i] = klists[o][i];
 
-  // the coefficient tree layout serves J = 1 and 2
-  P.tree_level = (g.level == 1 || g.level == 2) ? g.level : 0;
+  // the coefficient tree layout serves J = 1 and 2, and J = 3 in 2D
+  P.tree_level = (g.level == 1 || g.level == 2 || (g.level == 3 && nd == 2)) ? g.level : 0;
 
   // finalize LDS: idwt buffers, pattern, keep mask, grid and hard-data
   // windows, keys of the best rows, cut scratch
@@ -1949,6 +1949,7 @@ void launch_finalize(int ndim, int tree_level, unsigned blocks, size_t lds, hipS
   if (ndim == 2) {
     if (tree_level == 1) CCW_FIN(2, 1);
     else if (tree_level == 2) CCW_FIN(2, 2);
+    else if (tree_level == 3) CCW_FIN(2, 3);
     else CCW_FIN(2, 0);
   } else {
     if (tree_level == 1) CCW_FIN(3, 1);
@@ -2023,6 +2024,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     if (P->tree_level) {
       const long long gc = (long long)g.G[0] * g.G[1] * g.G[2];
       if (g.ndim == 2 && g.level == 1) k_dwt_tree<2, 1><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
+      else if (g.ndim == 2 && g.level == 3) k_dwt_tree<2, 3><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
       else if (g.ndim == 2) k_dwt_tree<2, 2><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
       else if (g.level == 1) k_dwt_tree<3, 1><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
       else k_dwt_tree<3, 2><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);

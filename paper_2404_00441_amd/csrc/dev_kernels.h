@@ -307,11 +307,68 @@ __global__ __launch_bounds__(kThreads) void k_dwt_tree(const int8_t* __restrict_
   approx_h[id] = (_Float16)(float)out[0];
 }
 
+// Level J >= 3 in 2D: one thread per level-2 node of each level-J block.
+// The thread walks from the block's approximation down to its node (one
+// inverse step per level, three details each), gathers the node's level-2
+// and level-1 details into the level-2 subtree layout and rebuilds its 4 x 4
+// cells with haar_tree_inverse<2, 2>.
+template <int J>
+__device__ __forceinline__ void idwt_window_tree_split(const int32_t* __restrict__ tree, const Geom& g, int c0x,
+                                                       int c0y, int8_t* P) {
+  using T = HaarTree<2, J>;
+  constexpr int b = 1 << J;
+  constexpr int nq = 1 << (J - 2);          // level-2 nodes per axis in a block
+  const int nblk = g.tc[0] * g.tc[1];
+  for (int t = threadIdx.x; t < nblk * nq * nq; t += kThreads) {
+    const int blk = t / (nq * nq), q = t - blk * (nq * nq);
+    const int bx = blk % g.tc[0], by = blk / g.tc[0];
+    const int qx = q % nq, qy = q / nq;      // the level-2 node within the block
+    const int32_t* src = tree + idx3(c0x + bx, c0y + by, 0, g.G) * T::B;
+    // approximation of the node: from the root down, one level at a time
+    int a = src[0];
+    for (int j = J; j > 2; --j) {
+      const int nj = 1 << (J - j);           // nodes per axis at level j
+      const int sh = j - 3;                  // path bit of level j
+      const int x = qx >> (sh + 1), y = qy >> (sh + 1);
+      const int d = ((qx >> sh) & 1) | (((qy >> sh) & 1) << 1);
+      const int* dt = src + T::off(j) + (x + nj * y) * 3;
+      const int c1 = dt[0], c2 = dt[1], c3 = dt[2];
+      // inverse of e + o / e - o on both axes, child d (bit 0: x, bit 1: y)
+      const int s1 = (d & 1) ? -c1 : c1, s2 = (d & 2) ? -c2 : c2, s3 = (d == 1 || d == 2) ? -c3 : c3;
+      a = (a + s1 + s2 + s3) >> 2;
+    }
+    // the node's level-2 details and its children's level-1 details
+    int tv[16], v[16];
+    tv[0] = a;
+    const int n2 = qx + nq * qy;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tv[1 + i] = src[T::off(2) + n2 * 3 + i];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int n1 = (2 * qx + (e & 1)) + 2 * nq * (2 * qy + (e >> 1));
+#pragma unroll
+      for (int i = 0; i < 3; ++i) tv[4 + e * 3 + i] = src[T::off(1) + n1 * 3 + i];
+    }
+    haar_tree_inverse<2, 2>(tv, v);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int ux = b * bx + 4 * qx + (i & 3), uy = b * by + 4 * qy + (i >> 2);
+      if (ux < g.T[0] && uy < g.T[1]) P[idx3(ux, uy, 0, g.T)] = (int8_t)v[i];
+    }
+  }
+  __syncthreads();
+}
+
 // Rebuild the template window at block origin c0 from the subtree layout:
 // one thread per level-J block of the window.
 template <int ND, int J>
 __device__ __forceinline__ void idwt_window_tree(const int32_t* __restrict__ tree, const Geom& g, int c0x, int c0y,
                                                  int c0z, int8_t* P) {
+  if constexpr (J >= 3) {
+    static_assert(ND == 2, "the subtree layout above level 2 is built in 2D only");
+    idwt_window_tree_split<J>(tree, g, c0x, c0y, P);
+    return;
+  }
   using T = HaarTree<ND, J>;
   constexpr int b = 1 << J;
   const int nblk = g.tc[0] * g.tc[1] * g.tc[2];

@@ -295,6 +295,10 @@ SIM_TINY = [
                           top_k=4, path_mode=1, n_real=3, cut=1), 12),
     ("fixed_3d_j2", dict(ti=(40, 36, 20), grid=(44, 40, 22), tmpl=(12, 12, 8), overlap=(3, 3, 2), level=2,
                          top_k=6, path_mode=0, n_real=2, cut=1), 0),
+    ("partial_blocks_j3", dict(ti=(90, 84), grid=(75, 70), tmpl=(21, 18), overlap=(6, 5), level=3, top_k=5,
+                               path_mode=1, n_real=3, cut=1), 25),
+    ("seeded_3d_j3", dict(ti=(40, 36, 34), grid=(36, 34, 30), tmpl=(17, 16, 16), overlap=(4, 4, 4), level=3,
+                          top_k=4, path_mode=1, n_real=2, cut=1), 10),
 ]
 
 
