@@ -245,8 +245,11 @@ int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_
 #define CCWSIM_KIND_CROP 6
 #define CCWSIM_KIND_LEARN 7   /* the proposer's fit (principal components, embeddings) */
 #define CCWSIM_NUM_KINDS 8
-/* When enabled, ccwsim_simulate brackets each kernel launch with a pair of
- * hipEvents on the caller's stream.  ccwsim_profile_read synchronises those
+/* When enabled, ccwsim_simulate times its kernels with pairs of hipEvents on
+ * the caller's stream: the per-step scan and finalize launches carry start
+ * and stop events recorded by their own dispatch (the kernel's run time);
+ * the other launches are bracketed by event records.  ccwsim_profile_read
+ * synchronises those
  * events, writes per-kind total milliseconds and launch counts (arrays of
  * CCWSIM_NUM_KINDS) and clears the record.  Host calls; the events add a
  * little launch overhead, so time throughput with profiling disabled. */

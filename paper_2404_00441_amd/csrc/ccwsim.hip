@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "ccwsim.h"
 #include "dev_scan.h"
 #include "dev_learn.h"
@@ -190,6 +192,28 @@ struct ProfScope {
   }
 };
 
+// Events for one kernel launch, recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so the interval is the kernel's own run and not
+// the gaps around it; both null when profiling is off.
+struct ProfKernel {
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit ProfKernel(int k) : kind(k) {
+    if (!g_prof_on) return;
+    a = prof_event();
+    b = a ? prof_event() : nullptr;
+    if (!b && a) {
+      g_prof_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~ProfKernel() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_recs.push_back({kind, a, b});
+  }
+};
+
 }  // namespace
 
 // ===========================================================================
@@ -294,15 +318,17 @@ __global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int16_t* __re
 constexpr int kScanFilterMajor = -1;
 
 // Launch scan variant V over `ngroups` workgroup columns.
-void launch_scan(int precision, int V, unsigned rows, int ngroups, size_t lds, hipStream_t st, const ScanArgs& sa) {
-  const dim3 grid(rows, (unsigned)ngroups);
-#define CCW_SCAN(OT)                                                     \
-  do {                                                                   \
-    if (V == kScanFilterMajor) k_scan_fm<OT><<<grid, kThreads, lds, st>>>(sa); \
-    else if (V == 8) k_scan<OT, 8><<<grid, kThreads, lds, st>>>(sa);     \
-    else if (V == 4) k_scan<OT, 4><<<grid, kThreads, lds, st>>>(sa);     \
-    else if (V == 2) k_scan<OT, 2><<<grid, kThreads, lds, st>>>(sa);     \
-    else k_scan<OT, 1><<<grid, kThreads, lds, st>>>(sa);                 \
+void launch_scan(int precision, int V, unsigned rows, int ngroups, size_t lds, hipStream_t st, const ScanArgs& sa,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  const dim3 grid(rows, (unsigned)ngroups), block(kThreads);
+  const uint32_t sh = (uint32_t)lds;
+#define CCW_SCAN(OT)                                                                                  \
+  do {                                                                                                \
+    if (V == kScanFilterMajor) hipExtLaunchKernelGGL((k_scan_fm<OT>), grid, block, sh, st, e0, e1, 0, sa); \
+    else if (V == 8) hipExtLaunchKernelGGL((k_scan<OT, 8>), grid, block, sh, st, e0, e1, 0, sa);     \
+    else if (V == 4) hipExtLaunchKernelGGL((k_scan<OT, 4>), grid, block, sh, st, e0, e1, 0, sa);     \
+    else if (V == 2) hipExtLaunchKernelGGL((k_scan<OT, 2>), grid, block, sh, st, e0, e1, 0, sa);     \
+    else hipExtLaunchKernelGGL((k_scan<OT, 1>), grid, block, sh, st, e0, e1, 0, sa);                 \
   } while (0)
   if (precision == 1) CCW_SCAN(__bf16);
   else CCW_SCAN(_Float16);
@@ -1944,8 +1970,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
 
 namespace {
 // One kernel per (dimension, depth of the coefficient tree).
-void launch_finalize(int ndim, int tree_level, unsigned blocks, size_t lds, hipStream_t st, const FinArgs& fa) {
-#define CCW_FIN(ND, TJ) k_finalize<ND, TJ><<<blocks, kThreads, lds, st>>>(fa)
+void launch_finalize(int ndim, int tree_level, unsigned blocks, size_t lds, hipStream_t st, const FinArgs& fa,
+                     hipEvent_t e0, hipEvent_t e1) {
+#define CCW_FIN(ND, TJ) \
+  hipExtLaunchKernelGGL((k_finalize<ND, TJ>), dim3(blocks), dim3(kThreads), (uint32_t)lds, st, e0, e1, 0, fa)
   if (ndim == 2) {
     if (tree_level == 1) CCW_FIN(2, 1);
     else if (tree_level == 2) CCW_FIN(2, 2);
@@ -2191,14 +2219,14 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       ProfScope ps(CCWSIM_KIND_SCAN, st);
       k_proxy<<<dim3(rows, (unsigned)s.tcount), kThreads, P->proxy_lds, st>>>(xa);
     } else {
-      ProfScope ps(CCWSIM_KIND_SCAN, st);
-      launch_scan(p->precision, G, rows, s.gcount[gix], scan_lds, st, sa);
+      ProfKernel pk(CCWSIM_KIND_SCAN);
+      launch_scan(p->precision, G, rows, s.gcount[gix], scan_lds, st, sa, pk.a, pk.b);
     }
     fa.filters = filters + s.fbegin;
     fa.fbegin = s.fbegin;
     {
-      ProfScope ps(CCWSIM_KIND_FINALIZE, st);
-      launch_finalize(g.ndim, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa);
+      ProfKernel pk(CCWSIM_KIND_FINALIZE);
+      launch_finalize(g.ndim, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa, pk.a, pk.b);
     }
   }
   HIP_TRY(hipGetLastError());
