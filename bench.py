@@ -142,16 +142,26 @@ def measure_scan_kernel(cc, wl, dev, reps=20):
         or_m_d = torch.from_numpy(or_m).to(dev)
         cand = [(p["ti"][a] - T[a]) // b + 1 for a in range(2)]
         ncand = cand[0] * cand[1]
-        cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, approx, T, or_n_d, or_m_d)
-        torch.cuda.synchronize()
-        cc.profile_enable(True)
-        cc.profile_read()
-        for _ in range(reps):
-            cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, approx, T, or_n_d, or_m_d)
-        torch.cuda.synchronize()
-        prof = cc.profile_read()
-        cc.profile_enable(False)
-        us = 1e3 * prof["scan"][0] / max(prof["scan"][1], 1)
+        # every layout: candidate-major with 1, 2, 4, 8 tiles per workgroup,
+        # filter-major (-1); 0 is the library's default choice
+        variants = {}
+        for V in (0, 1, 2, 4, 8, -1):
+            cc.set_scan_group(V)
+            try:
+                cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, approx, T, or_n_d, or_m_d)
+                torch.cuda.synchronize()
+                cc.profile_enable(True)
+                cc.profile_read()
+                for _ in range(reps):
+                    cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, approx, T, or_n_d, or_m_d)
+                torch.cuda.synchronize()
+                prof = cc.profile_read()
+                cc.profile_enable(False)
+            finally:
+                cc.set_scan_group(0)
+            variants[V] = 1e3 * prof["scan"][0] / max(prof["scan"][1], 1)
+        best_v = min(variants, key=variants.get)
+        us = variants[best_v]
         blocks = int((n_beta > 0).sum())
         flops = 2.0 * blocks * ncand * n_filters
         nbytes = 8.0 * ncand * n_filters + 2.0 * approx.numel() + 512.0 * n_filters
@@ -162,7 +172,9 @@ def measure_scan_kernel(cc, wl, dev, reps=20):
                     "us_per_launch": us, "tflops_algorithmic": tf, "frac_mfma_fp16": tf / PEAK_FP16_TFLOPS,
                     "gbs_algorithmic": gb, "frac_hbm": gb / PEAK_HBM_GBS,
                     "bound": "hbm" if nbytes / PEAK_HBM_GBS > flops / PEAK_FP16_TFLOPS / 1e3 else "mfma",
-                    "bytes_per_launch": nbytes, "flops_per_launch": flops})
+                    "bytes_per_launch": nbytes, "flops_per_launch": flops,
+                    "layout": {0: "default", -1: "filter-major"}.get(best_v, f"{best_v} tiles per workgroup"),
+                    "us_per_layout": {str(k): round(v, 2) for k, v in variants.items()}})
     return out
 
 
