@@ -24,6 +24,11 @@
  *     sorted scores: end of Sec. 4.4 (defers to MS-CCSIM).
  *   - Minimal-error boundary cut between patches: Sec. 2 (image quilting) and
  *     Sec. 4.1 (the OR resembles image quilting).
+ *   - Another mother wavelet (Sec. 4.2 calls Haar particularly suitable, so a
+ *     choice exists): the LeGall 5/3 biorthogonal wavelet in the integer
+ *     lifting form of Calderbank, Daubechies, Sweldens and Yeo ("Wavelet
+ *     transforms that map integers to integers", 1998), the reversible filter
+ *     of JPEG 2000, with whole-sample symmetric extension.
  *
  * Integer conventions (the paper's normalisation is orthonormal; every
  * ranking below is scale-invariant, so the oracle works on the unnormalised
@@ -63,6 +68,7 @@ typedef struct {
     int32_t score_mode;    /* 0 SSD, 1 raw CCW */
     int32_t nc_margin[3];  /* virtual-template margin; negative -> overlap */
     int32_t cut;           /* 1 min-error boundary cut, 0 plain paste */
+    int32_t wavelet;       /* 0 Haar, 1 LeGall 5/3 integer lifting */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -382,6 +388,116 @@ int orc_idwt_region(const int64_t *approx, const int64_t *details,
 /* K: level-J block sums over the grid of extent G.  Cand: number of         */
 /* candidates per axis.  n_b, m_b: T_c[0]*T_c[1]*T_c[2] values each.         */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* LeGall 5/3 integer lifting, one level along one line of even length n.   */
+/* Samples outside [0, n) are mirrored about the end samples (x[-i] = x[i], */
+/* x[n-1+i] = x[n-1-i]).  Predict: d[k] = x[2k+1] - floor((x[2k] +          */
+/* x[2k+2]) / 2); update: s[k] = x[2k] + floor((d[k-1] + d[k] + 2) / 4),   */
+/* with d[-1] taken from the mirrored signal (it equals d[0]).  The inverse */
+/* undoes the update, then the prediction, so it returns x exactly.         */
+/* ------------------------------------------------------------------------ */
+static int64_t orc_mirror(int64_t i, int64_t n)
+{
+    while (i < 0 || i >= n) {
+        if (i < 0) i = -i;
+        if (i >= n) i = 2 * (n - 1) - i;
+    }
+    return i;
+}
+
+static int64_t orc_floordiv(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
+    return q;
+}
+
+int orc_lift53_forward(const int64_t *x, int64_t n, int64_t *s, int64_t *d)
+{
+    if (n < 2 || n % 2) return ORC_ERR_SHAPE;
+    int64_t h = n / 2;
+    for (int64_t k = -1; k < h; k++) {
+        /* d[k] from the mirrored signal; k = -1 only feeds s[0] */
+        int64_t xo = x[orc_mirror(2 * k + 1, n)];
+        int64_t xl = x[orc_mirror(2 * k, n)], xr = x[orc_mirror(2 * k + 2, n)];
+        int64_t dk = xo - orc_floordiv(xl + xr, 2);
+        if (k >= 0) d[k] = dk;
+    }
+    for (int64_t k = 0; k < h; k++) {
+        int64_t dl;
+        if (k == 0) {
+            int64_t xo = x[orc_mirror(-1, n)];
+            dl = xo - orc_floordiv(x[orc_mirror(-2, n)] + x[0], 2);
+        } else {
+            dl = d[k - 1];
+        }
+        s[k] = x[2 * k] + orc_floordiv(dl + d[k] + 2, 4);
+    }
+    return ORC_OK;
+}
+
+int orc_lift53_inverse(const int64_t *s, const int64_t *d, int64_t n, int64_t *x)
+{
+    if (n < 2 || n % 2) return ORC_ERR_SHAPE;
+    int64_t h = n / 2;
+    /* the mirrored d[-1] equals d[0] (x[-1] = x[1], x[-2] = x[2]) */
+    for (int64_t k = 0; k < h; k++) {
+        int64_t dl = k == 0 ? d[0] : d[k - 1];
+        x[2 * k] = s[k] - orc_floordiv(dl + d[k] + 2, 4);
+    }
+    for (int64_t k = 0; k < h; k++) {
+        int64_t xr = x[orc_mirror(2 * k + 2, n)];
+        x[2 * k + 1] = d[k] + orc_floordiv(x[2 * k] + xr, 2);
+    }
+    return ORC_OK;
+}
+
+/* Level-J approximation of an image of extent e (every used axis a
+ * multiple of 2^J): per level, the lifting along x, then y, then z, keeping
+ * the low-pass half of each line.  out receives e / 2^J cells per used axis. */
+int orc_approx53(const int64_t *img, const int64_t e_in[3], int32_t ndim, int32_t J, int64_t *out)
+{
+    int64_t e[3] = {e_in[0], e_in[1], e_in[2]};
+    int64_t total = e[0] * e[1] * e[2];
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * total);
+    int64_t *nxt = (int64_t *)malloc(sizeof(int64_t) * total);
+    int64_t nmax = e[0] > e[1] ? e[0] : e[1];
+    if (e[2] > nmax) nmax = e[2];
+    int64_t *line = (int64_t *)malloc(sizeof(int64_t) * nmax);
+    int64_t *ls = (int64_t *)malloc(sizeof(int64_t) * nmax);
+    int64_t *ld = (int64_t *)malloc(sizeof(int64_t) * nmax);
+    if (!cur || !nxt || !line || !ls || !ld) return ORC_ERR_NOMEM;
+    memcpy(cur, img, sizeof(int64_t) * total);
+    for (int j = 0; j < J; j++) {
+        for (int a = 0; a < ndim; a++) {
+            if (e[a] % 2) return ORC_ERR_SHAPE;
+            int64_t ne[3] = {e[0], e[1], e[2]};
+            ne[a] = e[a] / 2;
+            int64_t o1 = (a + 1) % 3, o2 = (a + 2) % 3;
+            for (int64_t p = 0; p < e[o1]; p++)
+                for (int64_t q = 0; q < e[o2]; q++) {
+                    for (int64_t i = 0; i < e[a]; i++) {
+                        int64_t u[3];
+                        u[a] = i; u[o1] = p; u[o2] = q;
+                        line[i] = cur[orc_idx3(u[0], u[1], u[2], e)];
+                    }
+                    int st = orc_lift53_forward(line, e[a], ls, ld);
+                    if (st) return st;
+                    for (int64_t i = 0; i < ne[a]; i++) {
+                        int64_t u[3];
+                        u[a] = i; u[o1] = p; u[o2] = q;
+                        nxt[orc_idx3(u[0], u[1], u[2], ne)] = ls[i];
+                    }
+                }
+            for (int c = 0; c < 3; c++) e[c] = ne[c];
+            int64_t *t = cur; cur = nxt; nxt = t;
+        }
+    }
+    memcpy(out, cur, sizeof(int64_t) * e[0] * e[1] * e[2]);
+    free(cur); free(nxt); free(line); free(ls); free(ld);
+    return ORC_OK;
+}
+
 int orc_scores(const int64_t *K, const int32_t G[3], const int32_t cand[3],
                const int32_t tc[3], int64_t beta_cells, const int64_t *nb,
                const int64_t *mb, int32_t mode, int64_t *S_out)
@@ -520,6 +636,7 @@ static int orc_setup(const orc_params *p, orc_geom *g)
     if (p->ndim < 2 || p->ndim > 3) return ORC_ERR_ARG;
     if (p->level < 0 || p->level > 8 || p->top_k < 1 || p->n_real < 1) return ORC_ERR_ARG;
     if (p->n_facies < 1 || p->n_facies > 127) return ORC_ERR_ARG;
+    if (p->wavelet != 0 && p->wavelet != 1) return ORC_ERR_ARG;
     g->ndim = p->ndim;
     orc_block_factor(p->ndim, p->level, g->b);
     g->beta_cells = g->b[0] * g->b[1] * g->b[2];
@@ -616,7 +733,24 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
     int64_t *K = (int64_t *)malloc(sizeof(int64_t) * gcells);
     int64_t *det = (int64_t *)malloc(sizeof(int64_t) * (ndet > 0 ? ndet : 1));
     if (!K || !det) return ORC_ERR_NOMEM;
-    st = orc_dwt(ti, tin, ndim, J, K, det);
+    if (p->wavelet == 1) {
+        /* LeGall 5/3: approximation of the edge-replicated TI; the pattern
+         * comes back by perfect reconstruction, i.e. as the TI crop */
+        int64_t npc = g.np[0] * g.np[1] * g.np[2];
+        int64_t *tip = (int64_t *)malloc(sizeof(int64_t) * npc);
+        if (!tip) return ORC_ERR_NOMEM;
+        for (int64_t z = 0; z < g.np[2]; z++)
+            for (int64_t y = 0; y < g.np[1]; y++)
+                for (int64_t x = 0; x < g.np[0]; x++) {
+                    int64_t sx = x < g.ti[0] ? x : g.ti[0] - 1, sy = y < g.ti[1] ? y : g.ti[1] - 1;
+                    int64_t sz = z < g.ti[2] ? z : g.ti[2] - 1;
+                    tip[orc_idx3(x, y, z, g.np)] = ti[orc_idx3(sx, sy, sz, g.ti)];
+                }
+        st = orc_approx53(tip, g.np, ndim, J, K);
+        free(tip);
+    } else {
+        st = orc_dwt(ti, tin, ndim, J, K, det);
+    }
     if (st) return st;
 
     int64_t tcells = g.tc[0] * g.tc[1] * g.tc[2];
@@ -634,7 +768,9 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
     uint8_t *keep_old = (uint8_t *)malloc(wcells);
     int8_t *sg = (int8_t *)malloc(pcells);
     int8_t *hdmap = (int8_t *)malloc(pcells);
-    if (!nb || !mb || !S || !mis || !rec || !patch || !inband || !keep_old || !sg || !hdmap)
+    int64_t *win = (int64_t *)malloc(sizeof(int64_t) * rcells[0] * rcells[1] * rcells[2]);
+    int64_t *ade = (int64_t *)malloc(sizeof(int64_t) * tcells);
+    if (!nb || !mb || !S || !mis || !rec || !patch || !inband || !keep_old || !sg || !hdmap || !win || !ade)
         return ORC_ERR_NOMEM;
 
     for (int r = 0; r < p->n_real; r++) {
@@ -698,10 +834,31 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
                         mb[bi] += v;
                     }
 
+            int64_t score_beta = g.beta_cells;
+            if (p->wavelet == 1) {
+                /* 5/3: the data event's approximation is the transform of
+                 * the zero-filled overlap window (tc * b cells per axis);
+                 * each block with a known cell compares its coefficient,
+                 * S = sum (K - A)^2 up to a constant, so n = 1 and m = A */
+                for (int64_t i = 0; i < rcells[0] * rcells[1] * rcells[2]; i++) win[i] = 0;
+                for (int64_t z = 0; z < g.T[2]; z++)
+                    for (int64_t y = 0; y < g.T[1]; y++)
+                        for (int64_t x = 0; x < g.T[0]; x++)
+                            if (inband[orc_idx3(x, y, z, g.T)])
+                                win[orc_idx3(x, y, z, rcells)] =
+                                    sg[orc_idx3(org[0] + x, org[1] + y, org[2] + z, g.pad)];
+                st = orc_approx53(win, rcells, ndim, J, ade);
+                if (st) return st;
+                for (int64_t i = 0; i < tcells; i++) {
+                    nb[i] = nb[i] > 0 ? 1 : 0;
+                    mb[i] = nb[i] ? ade[i] : 0;
+                }
+                score_beta = 1;
+            }
             int32_t G32[3] = {(int32_t)g.G[0], (int32_t)g.G[1], (int32_t)g.G[2]};
             int32_t c32[3] = {(int32_t)g.cand[0], (int32_t)g.cand[1], (int32_t)g.cand[2]};
             int32_t t32[3] = {(int32_t)g.tc[0], (int32_t)g.tc[1], (int32_t)g.tc[2]};
-            st = orc_scores(K, G32, c32, t32, g.beta_cells, nb, mb, p->score_mode, S);
+            st = orc_scores(K, G32, c32, t32, score_beta, nb, mb, p->score_mode, S);
             if (st) return st;
             if (scores) memcpy(scores + ((int64_t)r * nsteps + step) * g.ncand, S, sizeof(int64_t) * g.ncand);
 
@@ -750,16 +907,21 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
             int64_t pc[3] = {pick % g.cand[0], (pick / g.cand[0]) % g.cand[1],
                              pick / (g.cand[0] * g.cand[1])};
             int32_t c0[3] = {(int32_t)pc[0], (int32_t)pc[1], (int32_t)pc[2]};
-            st = orc_idwt_region(K, det, tin, ndim, J, c0, t32, rec);
-            if (st) return st;
+            if (p->wavelet == 0) {
+                st = orc_idwt_region(K, det, tin, ndim, J, c0, t32, rec);
+                if (st) return st;
+            }
             for (int64_t z = 0; z < g.T[2]; z++)
                 for (int64_t y = 0; y < g.T[1]; y++)
                     for (int64_t x = 0; x < g.T[0]; x++) {
-                        int64_t v = rec[orc_idx3(x, y, z, rcells)];
-                        /* Haar reconstruction must give back the TI crop */
                         int64_t tv = ti[orc_idx3(g.b[0] * pc[0] + x, g.b[1] * pc[1] + y,
                                                  g.b[2] * pc[2] + z, g.ti)];
-                        if (v != tv) return ORC_ERR_RANGE;
+                        int64_t v = tv;   /* 5/3: perfect reconstruction of the TI's own window */
+                        if (p->wavelet == 0) {
+                            v = rec[orc_idx3(x, y, z, rcells)];
+                            /* Haar reconstruction must give back the TI crop */
+                            if (v != tv) return ORC_ERR_RANGE;
+                        }
                         patch[orc_idx3(x, y, z, g.T)] = (int8_t)v;
                     }
 
@@ -835,5 +997,7 @@ int orc_simulate(const orc_params *p, const int8_t *ti, int64_t n_hd,
     free(keep_old);
     free(sg);
     free(hdmap);
+    free(win);
+    free(ade);
     return ORC_OK;
 }

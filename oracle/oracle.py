@@ -66,6 +66,12 @@ def lib():
         L.orc_geometry.argtypes = [p, p]
         L.orc_simulate.restype = ctypes.c_int
         L.orc_simulate.argtypes = [p, p, i64, p, p, p, p, p, p]
+        L.orc_lift53_forward.restype = ctypes.c_int
+        L.orc_lift53_forward.argtypes = [p, i64, p, p]
+        L.orc_lift53_inverse.restype = ctypes.c_int
+        L.orc_lift53_inverse.argtypes = [p, p, i64, p]
+        L.orc_approx53.restype = ctypes.c_int
+        L.orc_approx53.argtypes = [p, p, i32, i32, p]
         _lib = L
     return _lib
 
@@ -86,6 +92,7 @@ class OracleParams(ctypes.Structure):
         ("score_mode", ctypes.c_int32),
         ("nc_margin", ctypes.c_int32 * 3),
         ("cut", ctypes.c_int32),
+        ("wavelet", ctypes.c_int32),
     ]
 
 
@@ -106,6 +113,7 @@ class SimParams:
     score_mode: int = 0
     nc_margin: tuple = field(default=(-1, -1, -1))
     cut: int = 1
+    wavelet: int = 0
 
     @property
     def ndim(self) -> int:
@@ -132,6 +140,7 @@ class SimParams:
         m = list(self.nc_margin)[: self.ndim] + [-1] * (3 - self.ndim)
         p.nc_margin = (ctypes.c_int32 * 3)(*m)
         p.cut = self.cut
+        p.wavelet = self.wavelet
         return p
 
 
@@ -293,3 +302,33 @@ def simulate(p: SimParams, ti: np.ndarray, hd=None, want_scores: bool = False):
     if want_scores:
         res = res + (sc.reshape(p.n_real, geo["nsteps"], geo["ncand"]),)
     return res
+
+
+def lift53_forward(x: np.ndarray):
+    """One LeGall 5/3 integer lifting level of an even-length line:
+    (approximation, detail), int64."""
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    n = x.shape[0]
+    s = np.zeros(n // 2, dtype=np.int64)
+    d = np.zeros(n // 2, dtype=np.int64)
+    _check(lib().orc_lift53_forward(_ptr(x), n, _ptr(s), _ptr(d)), "orc_lift53_forward")
+    return s, d
+
+
+def lift53_inverse(s: np.ndarray, d: np.ndarray) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.int64)
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    x = np.zeros(2 * s.shape[0], dtype=np.int64)
+    _check(lib().orc_lift53_inverse(_ptr(s), _ptr(d), x.shape[0], _ptr(x)), "orc_lift53_inverse")
+    return x
+
+
+def approx53(img: np.ndarray, level: int) -> np.ndarray:
+    """Level-J 5/3 approximation of an image in numpy order ([y][x] or
+    [z][y][x]); every extent a multiple of 2^J."""
+    img = np.ascontiguousarray(img, dtype=np.int64)
+    ext = _n3(img.shape[::-1])
+    out = np.zeros(tuple(n >> level for n in img.shape), dtype=np.int64)
+    e = (ctypes.c_int64 * 3)(*[int(v) for v in ext])
+    _check(lib().orc_approx53(_ptr(img), e, img.ndim, level, _ptr(out)), "orc_approx53")
+    return out

@@ -14,6 +14,13 @@ something other than itself:
   dynamic programme;
 * candidates are ordered by a plain tuple sort, not by packed keys.
 
+With the LeGall 5/3 wavelet (p["wavelet"] = 1) the score is the sum of
+squared differences between the TI's level-J approximation at the
+candidate's blocks and the approximation of the zero-filled overlap window,
+over the blocks holding a known cell (exact integers), minus the constant
+sum of the window approximation's squares; the lifting is written out here
+with plain integer loops.
+
 Only the random inputs (the counter-based generator and the tie-break
 bijection, pinned on their own by known-answer and bijection tests) are taken
 from the oracle.
@@ -66,6 +73,30 @@ def best_seam(e: np.ndarray):
     return np.array(best[1], dtype=np.int32), best[0][0]
 
 
+def _lift_low(line):
+    """Low-pass half of one 5/3 integer lifting level (mirror extension)."""
+    n = len(line)
+
+    def x(i):
+        while i < 0 or i >= n:
+            i = -i if i < 0 else 2 * (n - 1) - i
+        return line[i]
+
+    def d(k):
+        return x(2 * k + 1) - (x(2 * k) + x(2 * k + 2)) // 2
+
+    return [x(2 * k) + (d(k - 1) + d(k) + 2) // 4 for k in range(n // 2)]
+
+
+def _approx53(arr, J):
+    """Level-J approximation of an integer array indexed [x][y][z]."""
+    a = np.asarray(arr, dtype=object)
+    for _ in range(J):
+        for ax in range(a.ndim):
+            a = np.apply_along_axis(lambda v: np.array(_lift_low(list(v)), dtype=object), ax, a)
+    return a
+
+
 def simulate(p: dict, ti: np.ndarray, hd, rng, perm20):
     """Brute-force realizations; p is a workload dict (extents (x, y[, z]))."""
     ndim = len(p["ti"])
@@ -87,6 +118,15 @@ def simulate(p: dict, ti: np.ndarray, hd, rng, perm20):
 
     def ti_at(pt):
         return int(tiT[tuple(pt)])
+
+    wav = p.get("wavelet", 0)
+    if wav == 1:
+        npad = [-(-Nti[a] // b) * b for a in range(ndim)]
+        rep_ti = np.empty(npad, dtype=object)
+        for pt in itertools.product(*[range(npad[a]) for a in range(ndim)]):
+            rep_ti[pt] = ti_at([min(pt[a], Nti[a] - 1) for a in range(ndim)])
+        K53 = _approx53(rep_ti, J)
+    tcb = [-(-T[a] // b) for a in range(ndim)]
 
     def ti_block_mean(fine_lo):
         # mean of the b^d TI cells of a block, edge-replicated past the border
@@ -143,6 +183,12 @@ def simulate(p: dict, ti: np.ndarray, hd, rng, perm20):
                 blk_n[bk] = blk_n.get(bk, 0) + 1
                 blk_m[bk] = blk_m.get(bk, 0) + v
             const = sum(Fraction(blk_m[k] ** 2, blk_n[k]) for k in blk_n) * beta * beta
+            if wav == 1:
+                win = np.zeros([tcb[a] * b for a in range(ndim)], dtype=object)
+                for u in M:
+                    win[u] = int(sg[tuple(org[a] + u[a] for a in range(ndim))])
+                A = _approx53(win, J)
+                const53 = sum(int(A[k]) ** 2 for k in blk_n)
             # hard data in the virtual template
             vlo = [(-margin[a] if flip[a] else 0) for a in range(ndim)]
             vhi = [(T[a] if flip[a] else T[a] + margin[a]) for a in range(ndim)]
@@ -155,13 +201,17 @@ def simulate(p: dict, ti: np.ndarray, hd, rng, perm20):
                 for a in range(ndim):
                     c.append(rem % cand[a])
                     rem //= cand[a]
-                ssd = Fraction(0)
-                for u in M:
-                    bk = tuple(u[a] // b for a in range(ndim))
-                    pti = ti_block_mean([b * c[a] + b * bk[a] for a in range(ndim)])
-                    por = Fraction(blk_m[bk], blk_n[bk])
-                    ssd += (pti - por) ** 2
-                S = ssd * beta * beta - const
+                if wav == 1:
+                    S = Fraction(sum((int(K53[tuple(c[a] + k[a] for a in range(ndim))]) - int(A[k])) ** 2
+                                     for k in blk_n) - const53)
+                else:
+                    ssd = Fraction(0)
+                    for u in M:
+                        bk = tuple(u[a] // b for a in range(ndim))
+                        pti = ti_block_mean([b * c[a] + b * bk[a] for a in range(ndim)])
+                        por = Fraction(blk_m[bk], blk_n[bk])
+                        ssd += (pti - por) ** 2
+                    S = ssd * beta * beta - const
                 assert S.denominator == 1
                 mis = 0
                 for uu, v in hd_in:

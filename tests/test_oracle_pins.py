@@ -330,6 +330,7 @@ def _sp(p, **over):
     keys = ("ti", "grid", "tmpl", "overlap", "level", "top_k", "n_real", "n_facies", "seed",
             "path_mode", "score_mode", "nc_margin", "cut")
     d = {k: p[k] for k in keys}
+    d["wavelet"] = p.get("wavelet", 0)
     d.update(over)
     return SimParams(**d)
 
@@ -367,6 +368,32 @@ def test_simulate_matches_bruteforce(orc, case):
     bout, bchosen = bf.simulate(p, ti, hd, orc.rng, orc.perm20)
     assert np.array_equal(chosen, bchosen)
     assert np.array_equal(out, bout)
+
+
+@pytest.mark.parametrize("case", TINY_CASES, ids=[c[0] for c in TINY_CASES])
+def test_simulate_53_matches_bruteforce(orc, case):
+    # the LeGall 5/3 path: transform-domain scores against the brute force's
+    # direct sum of squared coefficient differences, patterns by crop
+    name, over, nhd = case
+    p = dict(nc_margin=(-1, -1, -1), n_facies=3, seed=11, score_mode=0, wavelet=1)
+    p.update(over)
+    nd = len(p["ti"])
+    if nd == 2:
+        ti = syn.channel_image_2d(p["ti"][0], p["ti"][1], 3, 3, seed=21)
+        ref = syn.channel_image_2d(p["grid"][0], p["grid"][1], 3, 3, seed=22)
+    else:
+        ti = syn.tube_image_3d(*p["ti"], 3, seed=21)
+        ref = syn.tube_image_3d(*p["grid"], 3, seed=22)
+        p["n_facies"] = 2
+    hd = syn.sample_hard_data(ref, [nhd] * p["n_real"], seed=23) if nhd else None
+    out, chosen = orc.simulate(_sp(p), ti, hd)
+    bout, bchosen = bf.simulate(p, ti, hd, orc.rng, orc.perm20)
+    assert np.array_equal(chosen, bchosen)
+    assert np.array_equal(out, bout)
+    # a different wavelet gives a different search (same inputs)
+    hout, hchosen = orc.simulate(_sp(dict(p, wavelet=0)), ti, hd)
+    if p["level"] > 0:
+        assert not np.array_equal(chosen, hchosen)
 
 
 @pytest.mark.parametrize("name", ["c1_plain2d", "c2_scale2d", "c4_batched", "c3_split3d"])
@@ -498,3 +525,57 @@ def test_connectivity_follows_paths_not_lines():
     u[7, 1:7] = 1
     both, conn = ost.connectivity(u[None], 2, 0, 8)
     assert both[0, 1, 4] == 8 and conn[0, 1, 4] == 8
+
+
+# --------------------------------------------------------------------------
+# LeGall 5/3 integer lifting (another mother wavelet than Haar)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 4, 6, 10, 64, 130])
+def test_lift53_perfect_reconstruction(orc, n):
+    rng = np.random.default_rng(n)
+    for _ in range(20):
+        x = rng.integers(-300, 300, size=n)
+        s, d = orc.lift53_forward(x)
+        assert np.array_equal(orc.lift53_inverse(s, d), x)
+
+
+def test_lift53_constant_and_ramp():
+    from oracle import oracle as o
+    s, d = o.lift53_forward(np.full(16, 7))
+    assert (s == 7).all() and (d == 0).all()
+    # the predictor is linear interpolation: a ramp has no detail except
+    # where the mirror at the right end breaks it (the last odd sample)
+    x = 3 * np.arange(20) + 5
+    s, d = o.lift53_forward(x)
+    assert (d[:-1] == 0).all() and d[-1] != 0
+    assert np.array_equal(s[1:-1], x[2:-2:2])
+
+
+def test_lift53_hand_example():
+    # x = [1, 4, 2, 8, 5, 7]: d0 = 4 - floor((1 + 2) / 2) = 3,
+    # d1 = 8 - floor((2 + 5) / 2) = 5, d2 = 7 - floor((5 + 5) / 2) = 2 (x6 mirrors
+    # to x4); s0 = 1 + floor((d0 + d0 + 2) / 4) = 3, s1 = 2 + floor((3 + 5 + 2) / 4) = 4,
+    # s2 = 5 + floor((5 + 2 + 2) / 4) = 7
+    from oracle import oracle as o
+    s, d = o.lift53_forward(np.array([1, 4, 2, 8, 5, 7]))
+    assert d.tolist() == [3, 5, 2] and s.tolist() == [3, 4, 7]
+
+
+def test_approx53_is_separable_lifting():
+    # the level-J image approximation equals lifting every row, then every
+    # column, level after level (checked against the 1D routine)
+    from oracle import oracle as o
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 3, size=(16, 24))
+    cur = img.astype(np.int64)
+    for _ in range(2):
+        cur = np.stack([o.lift53_forward(r)[0] for r in cur])
+        cur = np.stack([o.lift53_forward(c)[0] for c in cur.T]).T
+    assert np.array_equal(o.approx53(img, 2), cur)
+    img3 = rng.integers(0, 2, size=(4, 8, 8))
+    a3 = o.approx53(img3, 1)
+    ref = img3.astype(np.int64)
+    ref = np.apply_along_axis(lambda v: o.lift53_forward(v)[0], 2, ref)
+    ref = np.apply_along_axis(lambda v: o.lift53_forward(v)[0], 1, ref)
+    ref = np.apply_along_axis(lambda v: o.lift53_forward(v)[0], 0, ref)
+    assert np.array_equal(a3, ref)
