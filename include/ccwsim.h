@@ -112,7 +112,20 @@ typedef struct {
                            when that table takes at most 1 GiB, else as
                            1; 1: it reads the TI codes directly.  Both
                            give the same results.                         */
-  int32_t reserved[1];  /* must be 0                                      */
+  int32_t wavelet;      /* mother wavelet of the search (Sec. 4.2 calls Haar
+                           particularly suitable): 0 Haar (the default);
+                           1 LeGall 5/3 in the integer lifting form of
+                           Calderbank, Daubechies, Sweldens and Yeo (the
+                           reversible filter of JPEG 2000), whole-sample
+                           symmetric extension, x then y then z per level.
+                           With 5/3 a candidate's score is the squared
+                           difference between the TI's level-J
+                           approximation at its blocks and that of the
+                           zero-filled overlap window, over the blocks
+                           holding a known cell (n = 1, m = the window's
+                           coefficient), and the pattern is rebuilt by
+                           perfect reconstruction, i.e. as the TI window.
+                           Needs shortlist 0 and proposer_dim 0.          */
 } ccwsim_params;
 
 /* ---- A1: training-image transform (Sec. 3.1; Algorithm 1, DWT of TI) ---

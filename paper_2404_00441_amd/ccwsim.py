@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
         ("nc_margin", ctypes.c_int32 * 3), ("cut", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("shortlist", ctypes.c_int32),
         ("max_hard_data", ctypes.c_int32), ("proposer_dim", ctypes.c_int32), ("hd_direct", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("wavelet", ctypes.c_int32),
     ]
 
 
@@ -173,6 +173,7 @@ def params_of(p: dict) -> Params:
     q.max_hard_data = int(p.get("max_hard_data", 0))
     q.proposer_dim = int(p.get("proposer_dim", 0))
     q.hd_direct = int(p.get("hd_direct", 0))
+    q.wavelet = int(p.get("wavelet", 0))
     return q
 
 

@@ -81,6 +81,7 @@ int geom_ti(Geom& g, const ccwsim_shape& s, int level) {
     return fail(CCWSIM_ERR_SHAPE, "padded TI exceeds 2^31 - 1 cells");
   g.beta = g.b[0] * g.b[1] * g.b[2];
   g.log2beta = level * s.ndim;
+  g.shift = g.log2beta + 1;
   for (int j = 0; j <= level; ++j)
     for (int a = 0; a < 3; ++a) g.Gj[j][a] = a < s.ndim ? (g.np[a] >> j) : 1;
   g.det_off[1] = 0;
@@ -138,6 +139,12 @@ int geom_grid(Geom& g, const ccwsim_shape& grid, const int32_t OV[3], const int3
 // Bounds under which fp16 inputs and fp32 accumulation are exact and the
 // int32 score cannot overflow.  maxc = largest code, ovcells = largest number
 // of known overlap cells of a data event.
+long long floor_div(long long a, long long b) {
+  long long q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
 int check_exact(const Geom& g, long long maxc, long long ovcells) {
   const long long kmax = maxc * g.beta;
   if (kmax > 2048) return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld are not exact in fp16", kmax);
@@ -570,7 +577,7 @@ struct Plan {
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
             ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_report = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
-            ws_hdmask = 0, ws_hdbits = 0,
+            ws_hdmask = 0, ws_hdbits = 0, ws_lift = 0,
             ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
@@ -625,9 +632,12 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (p.precision != 0 && p.precision != 1) return fail(CCWSIM_ERR_UNSUPPORTED, "precision %d", p.precision);
   if (p.shortlist != 0 && (p.shortlist < p.top_k || p.shortlist > kShortMax))
     return fail(CCWSIM_ERR_INVALID_ARG, "shortlist must be 0 or in [top_k, %d]", kShortMax);
-  for (int i = 0; i < 1; ++i)
-    if (p.reserved[i]) return fail(CCWSIM_ERR_INVALID_ARG, "reserved fields must be 0");
   if (p.hd_direct != 0 && p.hd_direct != 1) return fail(CCWSIM_ERR_INVALID_ARG, "hd_direct must be 0 or 1");
+  if (p.wavelet != 0 && p.wavelet != 1) return fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (5/3)");
+  if (p.wavelet == 1 && (p.shortlist != 0 || p.proposer_dim != 0))
+    return fail(CCWSIM_ERR_INVALID_ARG, "the 5/3 wavelet needs shortlist 0 and proposer_dim 0");
+  g.wavelet = p.wavelet;
+  if (p.wavelet == 1) g.shift = 1;
   if (p.max_hard_data < 0) return fail(CCWSIM_ERR_INVALID_ARG, "max_hard_data must be >= 0");
   if (p.proposer_dim != 0 && p.proposer_dim != 8 && p.proposer_dim != 16 && p.proposer_dim != 32)
     return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim must be 0, 8, 16 or 32");
@@ -671,10 +681,30 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   }
   P.kpad = std::max(16, (kmax_len + 15) / 16 * 16);
   if (P.kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "overlap spans %d blocks (> %d)", kmax_len, kKMax);
-  CCW_TRY(check_exact(g, p.n_facies - 1 > 0 ? p.n_facies - 1 : 1, ov_cells_max));
-  if (p.precision == 1 && (long long)(p.n_facies > 1 ? p.n_facies - 1 : 1) * g.beta > 256)
-    return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld are not exact in bf16",
-                (long long)(p.n_facies - 1) * g.beta);
+  if (p.wavelet == 1) {
+    // 5/3 coefficients of codes in [0, max]: interval bound through the
+    // J * ndim lifting passes (prediction, then update with rounding)
+    long long lo = 0, hi = p.n_facies - 1 > 0 ? p.n_facies - 1 : 1;
+    for (int k = 0; k < g.level * nd; ++k) {
+      const long long dlo = lo - hi, dhi = hi - lo;
+      const long long nlo = lo + floor_div(2 * dlo + 2, 4), nhi = hi + floor_div(2 * dhi + 2, 4);
+      lo = nlo;
+      hi = nhi;
+    }
+    const long long kb = std::max(-lo, hi);
+    const long long lim = p.precision == 1 ? 256 : 2048;
+    if (kb > lim)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "5/3 coefficients up to %lld are not exact in %s", kb,
+                  p.precision == 1 ? "bf16" : "fp16");
+    const long long cmax = (long long)kmax_len * kb * kb;
+    if (cmax >= (1ll << 24)) return fail(CCWSIM_ERR_UNSUPPORTED, "cross sums up to %lld are not exact in fp32", cmax);
+    if (3 * cmax >= (1ll << 31)) return fail(CCWSIM_ERR_UNSUPPORTED, "scores up to %lld overflow int32", 3 * cmax);
+  } else {
+    CCW_TRY(check_exact(g, p.n_facies - 1 > 0 ? p.n_facies - 1 : 1, ov_cells_max));
+    if (p.precision == 1 && (long long)(p.n_facies > 1 ? p.n_facies - 1 : 1) * g.beta > 256)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld are not exact in bf16",
+                  (long long)(p.n_facies - 1) * g.beta);
+  }
   P.W = scan_strip_width(g);
 
   // schedule: anti-diagonal wavefronts when same-step windows are disjoint
@@ -873,17 +903,29 @@ int build_plan(const ccwsim_params& p, Plan& P) {
           const long long bi = ((long long)(uz / g.b[2]) * g.tc[1] + uy / g.b[1]) * g.tc[0] + ux / g.b[0];
           nbt[(size_t)sh * g.tcells + bi] += 1;
         }
+    if (p.wavelet == 1)   // 5/3: every block with a known cell compares one coefficient
+      for (long long i = 0; i < g.tcells; ++i) nbt[(size_t)sh * g.tcells + i] = nbt[(size_t)sh * g.tcells + i] > 0;
   }
   std::vector<int32_t> kbeta((size_t)P.n_orient * kKMax, -1);
   for (int o = 0; o < P.n_orient; ++o)
     for (size_t i = 0; i < klists[o].size(); ++i) kbeta[(size_t)o * kKMax + i] = klists[o][i];
 
   // the coefficient tree layout serves J = 1 and 2, and J = 3 in 2D
-  P.tree_level = (g.level == 1 || g.level == 2 || (g.level == 3 && nd == 2)) ? g.level : 0;
+  P.tree_level = p.wavelet == 0 && (g.level == 1 || g.level == 2 || (g.level == 3 && nd == 2)) ? g.level : 0;
 
   // finalize LDS: idwt buffers, pattern, keep mask, grid and hard-data
   // windows, keys of the best rows, cut scratch
   P.buf_cells = idwt_buf_cells(g);
+  if (p.wavelet == 1) {
+    // the successors' 5/3 windows (tc * b cells per axis) are lifted in
+    // LDS after the first pass: 3 rc / 4 int16 values over the idwt buffers
+    // and the four window-sized byte arrays behind them
+    long long rc = 1;
+    for (int a = 0; a < 3; ++a) rc *= (long long)g.tc[a] * g.b[a];
+    const long long wpad5 = (g.wcells + 15) & ~15ll;
+    const long long need = (3 * rc / 4 + 8) * 2;
+    P.buf_cells = std::max(P.buf_cells, (need - 4 * wpad5 + 7) / 8);
+  }
   const long long wpad = (g.wcells + 15) & ~15ll;
   int maxcols = 1;
   P.rows_max = 1;
@@ -915,7 +957,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (P.dp_batch < 1 || (long long)fixed + (long long)P.dp_stride * P.dp_batch > budget)
     return fail(CCWSIM_ERR_UNSUPPORTED, "pattern reconstruction needs more than %lld B of LDS", budget);
   P.fin_lds = fixed + (size_t)P.dp_batch * P.dp_stride + (size_t)((2 * g.tcells * 4 + 15) & ~15ll);
-  const bool rows_try = !P.learn && p.score_mode == 0 && p.shortlist == 0 &&
+  const bool rows_try = !P.learn && p.score_mode == 0 && p.shortlist == 0 && p.wavelet == 0 &&
                         (long long)g.cand[1] * g.cand[2] <= 512 && P.kpad <= kKMax;
   if (P.learn || rows_try) {
     // rows by bound, the keys of a round of rows and their level-J rows (int16)
@@ -938,7 +980,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
   // the coefficient staging area aliases the key list and the cut scratch
   const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
-  P.coef_lds = !P.tree_level && g.level > 0 && P.cand_cap > 0 && idwt_coef_count(g) * 4 <= alias_bytes;
+  P.coef_lds = p.wavelet == 0 && !P.tree_level && g.level > 0 && P.cand_cap > 0 &&
+               idwt_coef_count(g) * 4 <= alias_bytes;
 
   // pinned table block
   P.off_kbeta = 0;
@@ -1011,6 +1054,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_report = o;    o += 256;
   P.ws_hdoff = o;     o += align256((long long)(P.nfilters + 1) * 4);
   P.ws_hdent = o;     o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdEnt));
+  if (p.wavelet == 1) {   // two lifting buffers of half the padded TI each
+    P.ws_lift = o;      o += 2 * align256(((long long)g.np[0] * g.np[1] * g.np[2] / 2 + 1) * 4);
+  }
   if (P.hdm) {
     P.ws_hdmask = o;  o += align256((long long)P.hm.rz * P.hm.ry * P.hm.rs * 4);
     P.ws_hdbits = o;  o += align256(std::max(1ll, P.hd_cap) * (long long)sizeof(HdBits));
@@ -1235,6 +1281,48 @@ __global__ __launch_bounds__(kThreads) void k_hd_mask(Geom g, HdmGeom m, const i
     }
   }
   out[id] = bits;
+}
+
+// One LeGall 5/3 integer lifting level along `axis` of an image of extent
+// e (even along that axis), keeping the low-pass half: dst has e[axis] / 2
+// samples along it.  Samples outside [0, n) mirror about the end samples.
+// Prediction d[k] = x[2k+1] - floor((x[2k] + x[2k+2]) / 2), update
+// s[k] = x[2k] + floor((d[k-1] + d[k] + 2) / 4).  FROM_TI: the source is the
+// int8 TI, edge-replicated beyond its extent (the padded TI); dst_h, if
+// given, receives the operand-type copy.  One thread per output sample.
+__device__ __forceinline__ int mirror53(int i, int n) {
+  if (i < 0) i = -i;
+  if (i >= n) i = 2 * (n - 1) - i;
+  if (i < 0) i = -i;   // only for n = 2
+  return i;
+}
+
+template <bool FROM_TI>
+__global__ __launch_bounds__(kThreads) void k_lift53(const void* __restrict__ src, int32_t* __restrict__ dst,
+                                                     _Float16* __restrict__ dst_h, int e0, int e1, int e2, int axis,
+                                                     Geom g) {
+  int o[3] = {e0, e1, e2};
+  const int e[3] = {e0, e1, e2};
+  o[axis] >>= 1;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)o[0] * o[1] * o[2]) return;
+  int c[3];
+  split3((int)id, o[0], o[1], c[0], c[1], c[2]);
+  const int n = e[axis], k = c[axis];
+  auto at = [&](int i) -> int {
+    int u[3] = {c[0], c[1], c[2]};
+    u[axis] = mirror53(i, n);
+    if (FROM_TI) {
+      const int x = min(u[0], g.ti[0] - 1), y = min(u[1], g.ti[1] - 1), z = min(u[2], g.ti[2] - 1);
+      return ((const int8_t*)src)[((long long)z * g.ti[1] + y) * g.ti[0] + x];
+    }
+    return ((const int32_t*)src)[idx3i(u[0], u[1], u[2], e)];
+  };
+  const int x0 = at(2 * k - 2), x1 = at(2 * k - 1), x2 = at(2 * k), x3 = at(2 * k + 1), x4 = at(2 * k + 2);
+  const int dl = x1 - ((x0 + x2) >> 1), dr = x3 - ((x2 + x4) >> 1);
+  const int s = x2 + ((dl + dr + 2) >> 2);
+  dst[id] = s;
+  if (dst_h) dst_h[id] = (_Float16)(float)s;
 }
 
 // Hard-data ranges of the scan records, from the binned offsets.
@@ -1578,7 +1666,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     const int hd0 = a.has_hd ? a.hd_off[a.fbegin + slot] : 0;
     const int nhd = a.has_hd ? a.hd_off[a.fbegin + slot + 1] - hd0 : 0;
     const int32_t* erow = a.energy + (long long)f.shape * g.ncand;
-    const int shift = g.log2beta + 1;
+    const int shift = g.shift;
     int nsel = 0, pos = 0;
     while (pos < nrows) {
       __syncthreads();
@@ -1801,9 +1889,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
   const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
 
-  // rebuild the pattern from the coefficient pyramid
-  if constexpr (TJ > 0) idwt_window_tree<ND, TJ>(a.tree, g, cx, cy, cz, P);
-  else if (a.coef_lds) idwt_window_lds<ND>(a.Ki, a.det, g, cx, cy, cz, (int32_t*)s_cand, bufA, bufB, P);
+  // rebuild the pattern from the coefficient pyramid (5/3: by perfect
+  // reconstruction the TI's own window)
+  if constexpr (TJ > 0) {
+    idwt_window_tree<ND, TJ>(a.tree, g, cx, cy, cz, P);
+  } else if (g.wavelet == 1) {
+    for (int i = tid; i < (int)g.wcells; i += kThreads) {
+      int x, y, z;
+      split3(i, g.T[0], g.T[1], x, y, z);
+      P[i] = a.ti[((long long)(g.b[2] * cz + z) * g.ti[1] + g.b[1] * cy + y) * g.ti[0] + g.b[0] * cx + x];
+    }
+    __syncthreads();
+  } else if (a.coef_lds) idwt_window_lds<ND>(a.Ki, a.det, g, cx, cy, cz, (int32_t*)s_cand, bufA, bufB, P);
   else idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
 
   int8_t* sgw = a.sg + (long long)f.r * g.pcells;
@@ -1926,7 +2023,65 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   const int n = (int)g.wcells;
   const int lb = g.level;   // block of a cell: coordinates shifted by J on the used axes
   const int lbz = g.ndim == 3 ? lb : 0;
-  for (int m0 = 0; m0 < nmine;) {
+  if (g.wavelet == 1) {
+    // 5/3: each successor's data event is the level-J approximation of its
+    // zero-filled overlap window (tc * b cells per axis), lifted in LDS;
+    // blocks without a known cell of the successor compare nothing
+    const int r0 = g.tc[0] * g.b[0], r1 = g.tc[1] * g.b[1], r2 = g.tc[2] * g.b[2];
+    for (int mm = 0; mm < nmine; ++mm) {
+      const FilterDev& fq = s_fq[mm];
+      const int8_t* sgq = a.sg + (long long)fq.r * g.pcells;
+      // the zero-filled window, read from the grid by the first pass
+      auto win = [&](int x, int y, int z) {
+        int v = 0;
+        if (x < g.T[0] && y < g.T[1] && z < g.T[2] && dev_in_band(g, fq.orient, fq.bandmask, x, y, z))
+          v = sgq[((fq.org[2] + z) * g.pad[1] + fq.org[1] + y) * g.pad[0] + fq.org[0] + x];
+        return v;
+      };
+      // int16 buffers (every lifted value is bounded by the plan's check,
+      // <= 2048) over the idwt buffers and the pattern / mask / window
+      // area, all free once the paste is done: rc / 2 values, then rc / 4
+      int16_t* const lA = (int16_t*)bufA;
+      int16_t* const lB = lA + (r0 * r1 * r2) / 2;
+      int e[3] = {r0, r1, r2};
+      int16_t* src = nullptr;
+      int16_t* dst = lA;
+      for (int j = 0; j < g.level; ++j)
+        for (int axis = 0; axis < g.ndim; ++axis) {
+          int o[3] = {e[0], e[1], e[2]};
+          o[axis] >>= 1;
+          const int n = e[axis];
+          for (int i = tid; i < o[0] * o[1] * o[2]; i += kThreads) {
+            int c[3];
+            split3(i, o[0], o[1], c[0], c[1], c[2]);
+            const int k2 = 2 * c[axis];
+            auto at = [&](int q) {
+              int u[3] = {c[0], c[1], c[2]};
+              u[axis] = mirror53(q, n);
+              return src ? src[idx3i(u[0], u[1], u[2], e)] : win(u[0], u[1], u[2]);
+            };
+            const int x0 = at(k2 - 2), x1 = at(k2 - 1), x2 = at(k2), x3 = at(k2 + 1), x4 = at(k2 + 2);
+            const int dl = x1 - ((x0 + x2) >> 1), dr = x3 - ((x2 + x4) >> 1);
+            dst[i] = (int16_t)(x2 + ((dl + dr + 2) >> 2));
+          }
+          __syncthreads();
+          e[axis] = o[axis];
+          src = dst;
+          dst = dst == lA ? lB : lA;
+        }
+      if (tid < a.kpad) {
+        int v = 0;
+        if (my_beta >= 0 && a.nbt[(long long)fq.shape * g.tcells + my_beta]) {
+          int bx, by, bz;
+          split3(my_beta, g.tc[0], g.tc[1], bx, by, bz);
+          v = src ? (int)src[my_beta] : win(bx, by, bz);   // J = 0: the cells themselves
+        }
+        a.mbuf[(long long)s_mine[mm] * kKMax + tid] = (int16_t)v;
+      }
+      __syncthreads();
+    }
+  }
+  for (int m0 = 0; m0 < (g.wavelet == 1 ? 0 : nmine);) {
     const int gm = nmine - m0 >= 2 ? 2 : 1;
     for (int i = tid; i < gm * (int)g.tcells; i += kThreads) s_msum[i] = 0;
     __syncthreads();
@@ -2049,7 +2204,31 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   // TI transform and energy rows (depend on the TI only)
   {
     ProfScope ps(CCWSIM_KIND_DWT, st);
-    if (P->tree_level) {
+    if (g.wavelet == 1) {
+      // J levels of x, y (, z) lifting passes, ping-pong through two
+      // buffers; the last pass writes the approximation grid
+      int32_t* lb[2] = {(int32_t*)(ws + P->ws_lift),
+                        (int32_t*)(ws + P->ws_lift + align256(((long long)g.np[0] * g.np[1] * g.np[2] / 2 + 1) * 4))};
+      int e[3] = {g.np[0], g.np[1], g.np[2]};
+      const void* srcp = ti;
+      const int npass = g.level * g.ndim;
+      for (int q = 0; q < npass; ++q) {
+        const int axis = q % g.ndim;
+        const bool last = q == npass - 1;
+        int32_t* dstp = last ? Ki : lb[q & 1];
+        const long long outc = (long long)e[0] * e[1] * e[2] / 2;
+        if (q == 0)
+          k_lift53<true><<<nblocks(outc), kThreads, 0, st>>>(srcp, dstp, last ? Kh : nullptr, e[0], e[1], e[2],
+                                                             axis, g);
+        else
+          k_lift53<false><<<nblocks(outc), kThreads, 0, st>>>(srcp, dstp, last ? Kh : nullptr, e[0], e[1], e[2],
+                                                              axis, g);
+        e[axis] >>= 1;
+        srcp = dstp;
+      }
+      if (npass == 0) CCW_TRY(launch_dwt(g, ti, Ki, Kh, det, tmp, st));   // J = 0: the TI itself
+      HIP_TRY(hipGetLastError());
+    } else if (P->tree_level) {
       const long long gc = (long long)g.G[0] * g.G[1] * g.G[2];
       if (g.ndim == 2 && g.level == 1) k_dwt_tree<2, 1><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);
       else if (g.ndim == 2 && g.level == 3) k_dwt_tree<2, 3><<<nblocks(gc), kThreads, 0, st>>>(ti, det, Ki, Kh, g);

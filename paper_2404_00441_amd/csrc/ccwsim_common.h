@@ -110,6 +110,8 @@ struct Geom {
   int b[3];        // block factor per axis (2^J on used axes, else 1)
   int beta;        // cells per level-J block
   int log2beta;
+  int shift;       // S = E - (C << shift): log2beta + 1 for Haar block sums, 1 for 5/3 coefficients
+  int wavelet;     // 0 Haar, 1 LeGall 5/3
   int T[3], OV[3], tc[3];       // template, overlap, template in blocks
   int cand[3];     // candidates per axis
   int ncand;

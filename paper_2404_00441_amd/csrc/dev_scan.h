@@ -197,7 +197,7 @@ void k_scan(ScanArgs a) {
     s_rowmin[tid] = ~0ull;
   }
 
-  const int shift = g.log2beta + 1;
+  const int shift = g.shift;
   const int nchunks = (g.cand[0] + 31) / 32;
   const long long rowbase = (long long)g.cand[0] * row;
   // epilogue inputs of a 32-candidate chunk that do not depend on the
@@ -497,7 +497,7 @@ void k_scan_fm(ScanArgs a) {
   }
   __syncthreads();
 
-  const int shift = g.log2beta + 1;
+  const int shift = g.shift;
   const int nchunks = (g.cand[0] + 31) / 32;
   const long long rowbase = (long long)g.cand[0] * row;
   const int J = g.level, Jz = g.ndim == 3 ? J : 0;

@@ -76,6 +76,9 @@ def test_dwt_sizes_host_only(lib):
     dict(proposer_dim=16, shortlist=8),
     dict(proposer_dim=16, score_mode=1),
     dict(hd_direct=2),
+    dict(wavelet=2),
+    dict(wavelet=1, shortlist=8),
+    dict(wavelet=1, proposer_dim=16),
 ])
 def test_simulate_validation_errors(lib, bad):
     from paper_2404_00441_amd import ccwsim

@@ -38,7 +38,9 @@ def _t(a, dtype=None):
 def _sp(p, orc):
     keys = ("ti", "grid", "tmpl", "overlap", "level", "top_k", "n_real", "n_facies", "seed", "path_mode",
             "score_mode", "nc_margin", "cut")
-    return orc.SimParams(**{k: p[k] for k in keys})
+    d = {k: p[k] for k in keys}
+    d["wavelet"] = p.get("wavelet", 0)
+    return orc.SimParams(**d)
 
 
 # --------------------------------------------------------------------------
@@ -444,6 +446,47 @@ def test_row_minima_selection_dense(cc, orc, hd_direct):
 def test_selection_validation(cc):
     with pytest.raises(cc.CcwsimError):
         cc.set_selection(3)
+
+
+# --------------------------------------------------------------------------
+# Another mother wavelet: LeGall 5/3 integer lifting
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("case", SIM_TINY, ids=[c[0] for c in SIM_TINY])
+def test_wavelet53_small_cases(cc, orc, case):
+    name, over, nhd = case
+    _say("5/3", name)
+    p, ti, hd = _tiny(dict(over, wavelet=1), nhd)
+    _compare(cc, orc, p, ti, hd)
+
+
+W53_CASES = [("c1_plain2d", 1.0, None, {}), ("c2_scale2d", 0.3, None, {}), ("c4_batched", 0.5, 8, {}),
+             ("c3_split3d", 0.4, None, {"shortlist": 0}), ("c5_learned", 0.12, 2, {}),
+             ("c2_scale2d", 0.3, None, {"precision": 1}), ("c2_scale2d", 1.0, None, {})]
+
+
+@pytest.mark.parametrize("name,scale,nr,over", W53_CASES,
+                         ids=[f"{c[0]}_s{c[1]}_{'_'.join(c[3]) or 'plain'}" for c in W53_CASES])
+def test_wavelet53_workloads(cc, orc, name, scale, nr, over):
+    _say("5/3 workload", name, scale, nr, over)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    p.update(over, wavelet=1)
+    out = _compare(cc, orc, p, ti, hd)
+    if hd is not None:
+        for r, pos, v in zip(*hd):
+            assert out[(r,) + tuple(pos[::-1])] == v
+
+
+def test_wavelet53_scan_layouts(cc, orc):
+    p, ti, hd = wl.make("c4_batched", scale=0.5, n_real=12)
+    p["wavelet"] = 1
+    oout, ochosen = orc.simulate(_sp(p, orc), ti, hd)
+    for G in (1, 2, -1):
+        cc.set_scan_group(G)
+        try:
+            out, chosen = _run(cc, p, ti, hd)
+        finally:
+            cc.set_scan_group(0)
+        assert np.array_equal(chosen, ochosen) and np.array_equal(out, oout), G
 
 
 def test_simulate_is_deterministic(cc):
