@@ -239,10 +239,15 @@ def _time_case(cc, p, ti, hd, dev, reps=3):
 
 
 def measure_next(cc, wl, dev):
-    """Dense conditioning (C2 with 300, 4000, 8000 hard data) and the level x
-    grid-size sweep (C2 training image, T 32, OV 8, 1000 hard data per 512^2;
-    512^2 also with 2000)."""
-    out = {"dense_conditioning": [], "level_grid": []}
+    """C2 with the 5/3 wavelet beside Haar, dense conditioning (C2 with 300,
+    4000, 8000 hard data) and the level x grid-size sweep (C2 training image,
+    T 32, OV 8, 1000 hard data per 512^2; 512^2 also with 2000)."""
+    out = {"dense_conditioning": [], "level_grid": [], "wavelet": []}
+    # another mother wavelet: C2 with the LeGall 5/3 integer lifting beside Haar
+    for wav in (0, 1):
+        p, ti, hd = wl.make("c2_scale2d")
+        p["wavelet"] = wav
+        out["wavelet"].append(dict(_time_case(cc, p, ti, hd, dev), wavelet="haar" if wav == 0 else "legall53"))
     for n_hd in (300, 4000, 8000):
         p, ti, hd = wl.dense_conditioning(n_hd)
         out["dense_conditioning"].append(dict(_time_case(cc, p, ti, hd, dev), workload=wl.describe(p)))
