@@ -1597,9 +1597,31 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   // the block list of this realization's orientation (shared by successors)
   const int my_beta = tid < a.kpad ? a.kbeta[f.orient * kKMax + tid] : -1;
 
-  // windows of the grid and of the hard-data map
-  load_windows(s_sg, a.sg + (long long)f.r * g.pcells, s_hd, a.has_hd ? a.hdmap + (long long)f.r * g.pcells : nullptr,
-               f.org, g);
+  // windows of the grid and of the hard-data map.  They are first read by
+  // the cut: when a thread's share fits one batch, its loads are issued now
+  // and stored to LDS after the selection, so their latency overlaps it.
+  constexpr int WU = 8;
+  const bool win_defer = (int)g.wcells <= WU * kThreads;
+  const int8_t* win_sg = a.sg + (long long)f.r * g.pcells;
+  const int8_t* win_hd = a.has_hd ? a.hdmap + (long long)f.r * g.pcells : nullptr;
+  int8_t wv0[WU], wv1[WU];
+  if (win_defer) {
+    BoxWalk w(tid, kThreads, g.T[0], g.T[1]);
+#pragma unroll
+    for (int q = 0; q < WU; ++q) {
+      const int i = tid + q * kThreads;
+      wv0[q] = 0;
+      wv1[q] = -1;
+      if (i < (int)g.wcells) {
+        const long long at = idx3(f.org[0] + w.x, f.org[1] + w.y, f.org[2] + w.z, g.pad);
+        wv0[q] = win_sg[at];
+        if (win_hd) wv1[q] = win_hd[at];
+      }
+      w.next();
+    }
+  } else {
+    load_windows(s_sg, win_sg, s_hd, win_hd, f.org, g);
+  }
   for (int i = tid; i < (int)g.wcells; i += kThreads) keep[i] = 0;
 
   // K best keys.  The smallest key of every candidate row is known from the
@@ -1889,6 +1911,16 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
   const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
 
+  if (win_defer) {
+#pragma unroll
+    for (int q = 0; q < WU; ++q) {
+      const int i = tid + q * kThreads;
+      if (i < (int)g.wcells) {
+        s_sg[i] = wv0[q];
+        s_hd[i] = wv1[q];
+      }
+    }
+  }
   // rebuild the pattern from the coefficient pyramid (5/3: by perfect
   // reconstruction the TI's own window)
   if constexpr (TJ > 0) {
@@ -1902,6 +1934,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     __syncthreads();
   } else if (a.coef_lds) idwt_window_lds<ND>(a.Ki, a.det, g, cx, cy, cz, (int32_t*)s_cand, bufA, bufB, P);
   else idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
+  if (win_defer) __syncthreads();   // the windows' LDS stores, for the cut
 
   int8_t* sgw = a.sg + (long long)f.r * g.pcells;
   bool interior_done = false;   // cells outside every band already pasted
