@@ -75,7 +75,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(p, ti, hd, budget_s=10.0, max_reps=8):
+def cpu_baseline(p, ti, hd, budget_s=12.0, max_reps=24):
     """Oracle on whole realizations of the workload, single-threaded."""
     from oracle import oracle as orc
     orc.build_oracle(force=False)
@@ -87,7 +87,7 @@ def cpu_baseline(p, ti, hd, budget_s=10.0, max_reps=8):
     if hd is not None:
         sel = hd[0] == 0
         hd = (hd[0][sel], hd[1][sel], hd[2][sel])
-    sp = orc.SimParams(**{k: q[k] for k in keys})
+    sp = orc.SimParams(**{k: q[k] for k in keys}, wavelet=q.get("wavelet", 0))
     cells = 1
     for n in p["grid"]:
         cells *= n
