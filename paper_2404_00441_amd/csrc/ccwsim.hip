@@ -918,12 +918,12 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.buf_cells = idwt_buf_cells(g);
   if (p.wavelet == 1) {
     // the successors' 5/3 windows (tc * b cells per axis) are lifted in
-    // LDS after the first pass: 3 rc / 4 int16 values over the idwt buffers
-    // and the four window-sized byte arrays behind them
+    // LDS: 7 rc / 4 int16 values (the window and two pass buffers) over
+    // the idwt buffers and the four window-sized byte arrays behind them
     long long rc = 1;
     for (int a = 0; a < 3; ++a) rc *= (long long)g.tc[a] * g.b[a];
     const long long wpad5 = (g.wcells + 15) & ~15ll;
-    const long long need = (3 * rc / 4 + 8) * 2;
+    const long long need = (7 * rc / 4 + 16) * 2;
     P.buf_cells = std::max(P.buf_cells, (need - 4 * wpad5 + 7) / 8);
   }
   const long long wpad = (g.wcells + 15) & ~15ll;
@@ -2061,39 +2061,55 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     // zero-filled overlap window (tc * b cells per axis), lifted in LDS;
     // blocks without a known cell of the successor compare nothing
     const int r0 = g.tc[0] * g.b[0], r1 = g.tc[1] * g.b[1], r2 = g.tc[2] * g.b[2];
+    const int rc = r0 * r1 * r2;
+    // int16 buffers (every lifted value is bounded by the plan's check,
+    // <= 2048) over the idwt buffers and the pattern / mask / window area,
+    // all free once the paste is done: the window (rc values), then the
+    // passes' outputs (rc / 2, rc / 4, ...) alternating behind it
+    int16_t* const lW = (int16_t*)bufA;
+    int16_t* const lA = lW + rc;
+    int16_t* const lB = lA + rc / 2;
     for (int mm = 0; mm < nmine; ++mm) {
       const FilterDev& fq = s_fq[mm];
       const int8_t* sgq = a.sg + (long long)fq.r * g.pcells;
-      // the zero-filled window, read from the grid by the first pass
-      auto win = [&](int x, int y, int z) {
-        int v = 0;
-        if (x < g.T[0] && y < g.T[1] && z < g.T[2] && dev_in_band(g, fq.orient, fq.bandmask, x, y, z))
-          v = sgq[((fq.org[2] + z) * g.pad[1] + fq.org[1] + y) * g.pad[0] + fq.org[0] + x];
-        return v;
-      };
-      // int16 buffers (every lifted value is bounded by the plan's check,
-      // <= 2048) over the idwt buffers and the pattern / mask / window
-      // area, all free once the paste is done: rc / 2 values, then rc / 4
-      int16_t* const lA = (int16_t*)bufA;
-      int16_t* const lB = lA + (r0 * r1 * r2) / 2;
+      // the zero-filled window: every load of a thread's share in flight at once
+      {
+        constexpr int U = 8;
+        BoxWalk w(tid, kThreads, r0, r1);
+        for (int base = tid; base < rc; base += kThreads * U) {
+          int16_t v[U];
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            v[q] = 0;
+            if (base + q * kThreads < rc && w.x < g.T[0] && w.y < g.T[1] && w.z < g.T[2] &&
+                dev_in_band(g, fq.orient, fq.bandmask, w.x, w.y, w.z))
+              v[q] = sgq[((fq.org[2] + w.z) * g.pad[1] + fq.org[1] + w.y) * g.pad[0] + fq.org[0] + w.x];
+            w.next();
+          }
+#pragma unroll
+          for (int q = 0; q < U; ++q)
+            if (base + q * kThreads < rc) lW[base + q * kThreads] = v[q];
+        }
+      }
+      __syncthreads();
       int e[3] = {r0, r1, r2};
-      int16_t* src = nullptr;
+      int16_t* src = lW;
       int16_t* dst = lA;
       for (int j = 0; j < g.level; ++j)
         for (int axis = 0; axis < g.ndim; ++axis) {
           int o[3] = {e[0], e[1], e[2]};
           o[axis] >>= 1;
           const int n = e[axis];
-          for (int i = tid; i < o[0] * o[1] * o[2]; i += kThreads) {
-            int c[3];
-            split3(i, o[0], o[1], c[0], c[1], c[2]);
-            const int k2 = 2 * c[axis];
-            auto at = [&](int q) {
-              int u[3] = {c[0], c[1], c[2]};
-              u[axis] = mirror53(q, n);
-              return src ? src[idx3i(u[0], u[1], u[2], e)] : win(u[0], u[1], u[2]);
-            };
-            const int x0 = at(k2 - 2), x1 = at(k2 - 1), x2 = at(k2), x3 = at(k2 + 1), x4 = at(k2 + 2);
+          const int oc = o[0] * o[1] * o[2];
+          const int sa = axis == 0 ? 1 : axis == 1 ? e[0] : e[0] * e[1];   // input stride along the axis
+          BoxWalk w(tid, kThreads, o[0], o[1]);
+          for (int i = tid; i < oc; i += kThreads, w.next()) {
+            const int k2 = 2 * (axis == 0 ? w.x : axis == 1 ? w.y : w.z);
+            // the line through this output: input index of position 0
+            const int line = idx3i(axis == 0 ? 0 : w.x, axis == 1 ? 0 : w.y, axis == 2 ? 0 : w.z, e);
+            const int x0 = src[line + mirror53(k2 - 2, n) * sa], x1 = src[line + mirror53(k2 - 1, n) * sa];
+            const int x2 = src[line + k2 * sa], x3 = src[line + mirror53(k2 + 1, n) * sa];
+            const int x4 = src[line + mirror53(k2 + 2, n) * sa];
             const int dl = x1 - ((x0 + x2) >> 1), dr = x3 - ((x2 + x4) >> 1);
             dst[i] = (int16_t)(x2 + ((dl + dr + 2) >> 2));
           }
@@ -2104,11 +2120,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
         }
       if (tid < a.kpad) {
         int v = 0;
-        if (my_beta >= 0 && a.nbt[(long long)fq.shape * g.tcells + my_beta]) {
-          int bx, by, bz;
-          split3(my_beta, g.tc[0], g.tc[1], bx, by, bz);
-          v = src ? (int)src[my_beta] : win(bx, by, bz);   // J = 0: the cells themselves
-        }
+        if (my_beta >= 0 && a.nbt[(long long)fq.shape * g.tcells + my_beta]) v = src[my_beta];
         a.mbuf[(long long)s_mine[mm] * kKMax + tid] = (int16_t)v;
       }
       __syncthreads();
