@@ -153,6 +153,9 @@ void k_scan(ScanArgs a) {
   if (a.standalone) {
     tile0 = blockIdx.y * G;
     nt = min(G, a.ntiles - tile0);
+  } else if (G == 1) {   // one tile per workgroup: the group table is the identity
+    tile0 = blockIdx.y;
+    nt = 1;
   } else {
     const int2 grp = a.groups[blockIdx.y];
     tile0 = grp.x;
@@ -426,7 +429,7 @@ void k_scan_fm(ScanArgs a) {
   const int nrows = g.tc[1] * g.tc[2];
   const int j = lane & 31, half = lane >> 5;
   const int g8 = half * 8;
-  const int tile = a.standalone ? (int)blockIdx.y : a.groups[blockIdx.y].x;
+  const int tile = (int)blockIdx.y;   // one tile per workgroup: the group table is the identity
 
   OT* s_strip = (OT*)smem;
   const int strip_bytes = ((nrows * W * 2) + 15) & ~15;
