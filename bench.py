@@ -295,6 +295,7 @@ def measure_stats(cc, wl, dev, n_real=100, max_lag=200):
     ms["variogram_x"], vx = timed(lambda: cc.stats_variogram(real, nf, 0, max_lag))
     ms["variogram_y"], vy = timed(lambda: cc.stats_variogram(real, nf, 1, max_lag))
     ms["connectivity_x"], (bx, cx) = timed(lambda: cc.stats_connectivity(real, nf, 0, max_lag))
+    ms["connectivity_y"], _ = timed(lambda: cc.stats_connectivity(real, nf, 1, max_lag))
     res["ms"] = ms
     cells = n_real * int(np.prod(p["grid"]))
     res["cells_per_s"] = {k: cells / (v * 1e-3) for k, v in ms.items()}

@@ -2912,6 +2912,12 @@ extern "C" int ccwsim_stats_connectivity(const int8_t* codes, ccwsim_shape shape
       k_st_conn_x<<<dim3((unsigned)((s.rows + rbx - 1) / rbx), (unsigned)n_img), kThreads,
                     (size_t)(s.n[0] + 4) * 4, st>>>(L, s, max_lag, rbx, ob + (long long)f * max_lag,
                                                     oc + (long long)f * max_lag, (long long)n_facies * max_lag);
+    } else if (axis > 0) {
+      const int nxb = (s.n[0] + kThreads - 1) / kThreads;
+      const int lines = axis == 1 ? s.n[2] : s.n[1];
+      k_st_conn_col<<<dim3((unsigned)(nxb * lines), (unsigned)((max_lag + 7) / 8), (unsigned)n_img), kThreads, 0,
+                      st>>>(L, s, axis, max_lag, ob + (long long)f * max_lag, oc + (long long)f * max_lag,
+                            (long long)n_facies * max_lag);
     } else {
       k_st_conn<<<dim3(stat_blocks(s.cells, n_img), (unsigned)n_img), kThreads, (size_t)max_lag * 8, st>>>(
           L, s, axis, max_lag, ob + (long long)f * max_lag, oc + (long long)f * max_lag,

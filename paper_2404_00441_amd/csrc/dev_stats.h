@@ -368,6 +368,68 @@ __global__ __launch_bounds__(kThreads) void k_st_conn_x(const int32_t* __restric
   }
 }
 
+// The same counts along y or z, eight lags per thread: a thread owns one
+// column x of one line (fixed z for y, fixed y for z) and lags
+// 8 g + 1 .. 8 g + 8 (g = blockIdx.y).  It walks the line once, keeping the
+// labels at the eight partner positions in a sliding window of registers
+// (two loads per position), and its 16 counters are summed over the block
+// at the end.  Grid (x blocks x lines, lag groups, images).
+__global__ __launch_bounds__(kThreads) void k_st_conn_col(const int32_t* __restrict__ L, StatShape s, int axis, int H,
+                                                          unsigned long long* __restrict__ both,
+                                                          unsigned long long* __restrict__ conn, long long out_stride) {
+  __shared__ uint32_t s_red[kThreads / 64][16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, img = blockIdx.z;
+  const int nx = s.n[0], ny = s.n[1];
+  const int nxb = (nx + kThreads - 1) / kThreads;
+  const int line = blockIdx.x / nxb, x = (blockIdx.x - line * nxb) * kThreads + tid;
+  const int na = s.n[axis];
+  const long long step = axis == 1 ? nx : (long long)nx * ny;
+  // cell of position 0 of this thread's line
+  const long long base = axis == 1 ? (long long)line * ny * nx + x : (long long)line * nx + x;
+  const int32_t* Li = L + (long long)img * s.cells;
+  const int h0 = 8 * blockIdx.y + 1;   // lags h0 .. h0 + 7
+  uint32_t nb[8], nc[8];
+  int w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    nb[q] = nc[q] = 0;
+    w[q] = (x < nx && h0 + q < na) ? Li[base + (h0 + q) * step] : -1;
+  }
+  if (x < nx) {
+    for (int p = 0; p + h0 < na; ++p) {
+      const int av = Li[base + p * step];
+      const int nxt = p + 1 + h0 + 7 < na ? Li[base + (p + 1 + h0 + 7) * step] : -1;
+      if (av >= 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          nb[q] += w[q] >= 0 ? 1u : 0u;
+          nc[q] += w[q] == av ? 1u : 0u;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 7; ++q) w[q] = w[q + 1];
+      w[7] = nxt;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int sb = wave_sum((int)nb[q]), sc = wave_sum((int)nc[q]);
+    if (lane == 0) {
+      s_red[wv][q] = (uint32_t)sb;
+      s_red[wv][8 + q] = (uint32_t)sc;
+    }
+  }
+  __syncthreads();
+  if (tid < 16) {
+    const int q = tid & 7;
+    if (h0 + q <= H) {
+      unsigned long long t = 0;
+      for (int k = 0; k < kThreads / 64; ++k) t += s_red[k][tid];
+      if (t) atomicAdd((tid < 8 ? both : conn) + (long long)img * out_stride + h0 + q - 1, t);
+    }
+  }
+}
+
 __global__ void k_st_fill_u64(unsigned long long* __restrict__ p, long long n) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id < n) p[id] = 0ull;
