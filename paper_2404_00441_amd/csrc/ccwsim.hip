@@ -311,13 +311,13 @@ __global__ void k_to_bf16(const int32_t* __restrict__ src, __bf16* __restrict__ 
   if (id < n) dst[id] = (__bf16)(float)src[id];
 }
 
-// Standalone data events: or_m[f][beta] -> mbuf[f][k = beta] (fp16), zero pad.
-__global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int16_t* __restrict__ mbuf,
+// Standalone data events: or_m[f][beta] -> mbuf[f][k = beta], zero pad.
+__global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int32_t* __restrict__ mbuf,
                                  int n_filters, long long tcells) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long long)n_filters * kKMax) return;
   const long long f = id / kKMax, k = id - f * kKMax;
-  mbuf[id] = k < tcells ? (int16_t)or_m[f * tcells + k] : (int16_t)0;
+  mbuf[id] = k < tcells ? or_m[f * tcells + k] : 0;
 }
 
 // Scan variants: 1, 2, 4, 8 = candidate-major output with up to that many
@@ -386,9 +386,9 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code,
   hipStream_t st = as_stream(stream);
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
   _Float16* Kh = nullptr;
-  int16_t* mbuf = nullptr;
+  int32_t* mbuf = nullptr;
   HIP_TRY(hipMallocAsync((void**)&Kh, gcells * 2, st));
-  HIP_TRY(hipMallocAsync((void**)&mbuf, (size_t)n_filters * kKMax * 2, st));
+  HIP_TRY(hipMallocAsync((void**)&mbuf, (size_t)n_filters * kKMax * 4, st));
   k_to_half<<<nblocks(gcells), kThreads, 0, st>>>(approx, Kh, gcells);
   k_events_to_mbuf<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_m, mbuf, n_filters, g.tcells);
   if (score_mode == 0) {
@@ -559,10 +559,11 @@ struct Plan {
   size_t proxy_lds = 0;
   int scan_g = 1;                     // tiles per scan workgroup (tuned)
   bool rows_ok = false;               // the row-minima selection fits this plan
+  bool ev_delta = false;              // additive Haar data events (see k_event_init)
   bool sel_rows = false;              // row-minima selection chosen (tuned)
   bool tuned = false;
   int max_slots = 0, nsteps_raster = 0;
-  long long patches = 0, or_blocks = 0, band_cells = 0;
+  long long patches = 0, or_blocks = 0, band_cells = 0, succ_links = 0;
   long long hd_cap = 0;               // hard-data entries of all virtual templates
   bool hdm = false;                   // hard-data mismatches from the bit table
   HdmGeom hm = {};
@@ -885,6 +886,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
         succ.push_back(q);
         succ.push_back(npred[q]);
       }
+    P.succ_links = (long long)succ.size() / 2;
     if (succ.empty()) {
       succ.push_back(-1);
       succ.push_back(0);
@@ -978,6 +980,10 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     P.rows_ok = rows_try && P.learn_kbr >= 1;
   }
   if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
+  // additive data events: the Haar block sums of a successor's overlap
+  // change by what each predecessor's paste changes there; the sums of one
+  // group of successors live in the inverse-DWT buffers, free by then
+  P.ev_delta = p.wavelet == 0 && !P.learn && g.level > 0 && 2 * P.buf_cells >= g.tcells;
   // the coefficient staging area aliases the key list and the cut scratch
   const long long alias_bytes = P.cand_cap * 8 + (long long)P.dp_batch * P.dp_stride;
   P.coef_lds = p.wavelet == 0 && !P.tree_level && g.level > 0 && P.cand_cap > 0 &&
@@ -1049,7 +1055,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_tbl = o;       o += align256((long long)P.tbl_bytes);
   P.ws_sg = o;        o += align256((long long)p.n_real * g.pcells);
   P.ws_hdmap = o;     o += align256((long long)p.n_real * g.pcells);
-  P.ws_mbuf = o;      o += align256((long long)P.nfilters * kKMax * 2);
+  P.ws_mbuf = o;      o += align256((long long)P.nfilters * kKMax * 4);
   P.ws_predcnt = o;   o += align256((long long)P.nfilters * 4);
   P.ws_report = o;    o += 256;
   P.ws_hdoff = o;     o += align256((long long)(P.nfilters + 1) * 4);
@@ -1133,6 +1139,39 @@ __device__ __forceinline__ bool dev_in_band(const Geom& g, int orient, int bandm
     if (w < g.OV[a]) return true;
   }
   return false;
+}
+
+// Data events of every patch on the grid as it stands before the first
+// step: per level-J block, the sum of the overlap cells (unknown cells hold
+// -1, hard data their code).  The finalize step of each patch then adds,
+// block by block, what its paste changes in its successors' overlaps.  Both
+// are integer sums, so the order of the additions does not matter and a
+// successor's scan reads the block sums of exactly the cells its
+// predecessors left (Sec. 3.2: the data event is the level-J approximation
+// of the overlap, a block sum for the Haar filters).  One workgroup per patch.
+__global__ __launch_bounds__(kThreads) void k_event_init(Geom g, const FilterDev* __restrict__ filters,
+                                                         const int32_t* __restrict__ kbeta,
+                                                         const int8_t* __restrict__ sg, int32_t* __restrict__ mbuf,
+                                                         int kpad) {
+  extern __shared__ int s_bsum[];   // [window block]
+  const FilterDev fq = filters[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (int)g.tcells; i += kThreads) s_bsum[i] = 0;
+  __syncthreads();
+  if (fq.bandmask) {
+    const int8_t* sgq = sg + (long long)fq.r * g.pcells;
+    const int lb = g.level, lbz = g.ndim == 3 ? g.level : 0;
+    BoxWalk w(tid, kThreads, g.T[0], g.T[1]);
+    for (int i = tid; i < (int)g.wcells; i += kThreads, w.next())
+      if (dev_in_band(g, fq.orient, fq.bandmask, w.x, w.y, w.z))
+        atomicAdd(&s_bsum[((w.z >> lbz) * g.tc[1] + (w.y >> lb)) * g.tc[0] + (w.x >> lb)],
+                  (int)sgq[idx3(fq.org[0] + w.x, fq.org[1] + w.y, fq.org[2] + w.z, g.pad)]);
+  }
+  __syncthreads();
+  for (int t = tid; t < kKMax; t += kThreads) {
+    const int beta = t < kpad ? kbeta[fq.orient * kKMax + t] : -1;
+    mbuf[(long long)blockIdx.x * kKMax + t] = beta >= 0 ? s_bsum[beta] : 0;
+  }
 }
 
 // Copy the T-window of a padded grid at `org` into LDS (every load of a
@@ -1377,7 +1416,8 @@ struct FinArgs {
   int32_t* predcnt;
   const int32_t* kbeta;
   const int32_t* nbt;             // [shape][window block] known-cell counts
-  int16_t* mbuf;                  // [patch][kKMax] data events
+  int32_t* mbuf;                  // [patch][kKMax] data events
+  int ev_delta;                   // 1: add the paste's changes to the successors' events
   unsigned long long* report;     // shortlist report: max |bulk - exact|, rescored, changed, patches
   int kpad;
   int shortlist;
@@ -2028,6 +2068,65 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       }
     }
   }
+  if (a.ev_delta) {
+    // Additive data events: add what this paste changed in each
+    // successor's overlap to that successor's block sums.  A cell changes
+    // where the paste wrote it (no hard datum, new side of every seam);
+    // the old value is the window read before the cut.  The sums of a group
+    // of successors are gathered in the inverse-DWT buffers (free by now),
+    // then each listed block goes out as one device-scope atomic add.
+    if (tid < my_nsucc) {
+      s_mine[tid] = my_succ;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) ((int2*)&s_fq[tid])[q] = my_fq[q];
+    }
+    __syncthreads();
+    int* s_dsum = bufA;
+    const int tcl = (int)g.tcells;
+    const int lb = g.level, lbz = g.ndim == 3 ? g.level : 0;
+    const int ng = max(1, min(my_nsucc, (int)(2 * a.buf_cells / tcl)));
+    for (int m0 = 0; m0 < my_nsucc; m0 += ng) {
+      const int gm = min(ng, my_nsucc - m0);
+      for (int i = tid; i < gm * tcl; i += kThreads) s_dsum[i] = 0;
+      __syncthreads();
+      for (int mm = 0; mm < gm; ++mm) {
+        const FilterDev& fq = s_fq[m0 + mm];
+        // the box both windows cover, in this window's coordinates
+        int d[3], lo[3], ex[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          d[ax] = f.org[ax] - fq.org[ax];
+          lo[ax] = max(0, -d[ax]);
+          ex[ax] = max(0, min(g.T[ax], g.T[ax] - d[ax]) - lo[ax]);
+        }
+        const int nbox = ex[0] * ex[1] * ex[2];
+        if (nbox == 0) continue;
+        int* dsum = s_dsum + mm * tcl;
+        BoxWalk w(tid, kThreads, ex[0], ex[1]);
+        for (int i = tid; i < nbox; i += kThreads, w.next()) {
+          const int x = lo[0] + w.x, y = lo[1] + w.y, z = lo[2] + w.z;
+          const int c = idx3i(x, y, z, g.T);
+          const int old = s_sg[c];
+          const int nv = (s_hd[c] < 0 && !keep[c]) ? (int)P[c] : old;
+          if (nv != old) {
+            const int sx = x + d[0], sy = y + d[1], sz = z + d[2];
+            if (dev_in_band(g, fq.orient, fq.bandmask, sx, sy, sz))
+              atomicAdd(&dsum[((sz >> lbz) * g.tc[1] + (sy >> lb)) * g.tc[0] + (sx >> lb)], nv - old);
+          }
+        }
+      }
+      __syncthreads();
+      if (my_beta >= 0)
+        for (int mm = 0; mm < gm; ++mm) {
+          const int v = s_dsum[mm * tcl + my_beta];
+          if (v != 0)
+            __hip_atomic_fetch_add(&a.mbuf[(long long)s_mine[m0 + mm] * kKMax + tid], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+      __syncthreads();
+    }
+    return;
+  }
   // Successors whose last overlapping predecessor is this patch get their
   // data event here.  Every wavefront first waits for its own stores of the
   // paste; then one lane per successor counts this patch in with an
@@ -2121,7 +2220,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       if (tid < a.kpad) {
         int v = 0;
         if (my_beta >= 0 && a.nbt[(long long)fq.shape * g.tcells + my_beta]) v = src[my_beta];
-        a.mbuf[(long long)s_mine[mm] * kKMax + tid] = (int16_t)v;
+        a.mbuf[(long long)s_mine[mm] * kKMax + tid] = v;
       }
       __syncthreads();
     }
@@ -2160,7 +2259,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     if (tid < a.kpad)
       for (int mm = 0; mm < gm; ++mm)
         a.mbuf[(long long)s_mine[m0 + mm] * kKMax + tid] =
-            (int16_t)(my_beta >= 0 ? s_msum[mm * (int)g.tcells + my_beta] : 0);
+            my_beta >= 0 ? s_msum[mm * (int)g.tcells + my_beta] : 0;
     __syncthreads();
     m0 += gm;
   }
@@ -2226,7 +2325,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   unsigned char* tbl = ws + P->ws_tbl;
   int8_t* sg = (int8_t*)(ws + P->ws_sg);
   int8_t* hdmap = (int8_t*)(ws + P->ws_hdmap);
-  int16_t* mbuf = (int16_t*)(ws + P->ws_mbuf);
+  int32_t* mbuf = (int32_t*)(ws + P->ws_mbuf);
   unsigned long long* report = (unsigned long long*)(ws + P->ws_report);
   int32_t* predcnt = (int32_t*)(ws + P->ws_predcnt);
   int32_t* hd_off = (int32_t*)(ws + P->ws_hdoff);
@@ -2326,6 +2425,9 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
     k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
     k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 16, 0);
+    if (P->ev_delta)
+      k_event_init<<<(unsigned)P->nfilters, kThreads, (size_t)g.tcells * 4, st>>>(g, filters, kbeta, sg, mbuf,
+                                                                                   P->kpad);
     if (n_hd > 0) {
       k_hd_bin<false><<<(unsigned)P->nfilters, kThreads, 0, st>>>(g, filters, hdmap, hd_off, hd_ent, P->hd_cap,
                                                                    nullptr, P->hm);
@@ -2374,6 +2476,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.kbeta = kbeta;
   fa.nbt = nbt;
   fa.mbuf = mbuf;
+  fa.ev_delta = P->ev_delta ? 1 : 0;
   fa.report = report;
   fa.kpad = P->kpad;
   fa.shortlist = p->shortlist;
@@ -2729,9 +2832,14 @@ extern "C" int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* 
   out->cells = (double)p->n_real * g.sg[0] * g.sg[1] * g.sg[2];
   const double rows = (double)g.cand[1] * g.cand[2];
   const double krows = std::min<double>(std::min(p->shortlist > 0 ? p->shortlist : p->top_k, g.ncand), rows);
-  const double per_patch = 2.0 * g.wcells + 8.0 * rows + 8.0 * krows * g.cand[0] + 4.0 * g.wcells + g.wcells +
-                           2.0 * P->kpad;
-  out->fin_bytes = per_patch * (double)P->patches + (double)P->band_cells;
+  // windows, row minima, the best rows' keys, coefficients, paste; then the
+  // successors' events: read back from the grid and written once (4 B per
+  // listed block), or added to by every predecessor (4 B per listed block
+  // and successor link)
+  const double per_patch = 2.0 * g.wcells + 8.0 * rows + 8.0 * krows * g.cand[0] + 4.0 * g.wcells + g.wcells;
+  out->fin_bytes = per_patch * (double)P->patches +
+                   (P->ev_delta ? 4.0 * P->kpad * (double)P->succ_links
+                                : (double)P->band_cells + 4.0 * P->kpad * (double)P->patches);
   return CCWSIM_OK;
 }
 

@@ -84,7 +84,7 @@ struct ScanArgs {
   const int32_t* kbeta;        // [orient][kKMax] block index or -1 (simulate)
   const TileDev* tiles;        // simulate: tiles of this step
   const ScanRec* recs;         // simulate: [tile][kFiltersPerTile] records of this step
-  const int16_t* mbuf;         // [patch][kKMax] data-event block sums (standalone: [filter])
+  const int32_t* mbuf;         // [patch][kKMax] data-event block sums (standalone: [filter])
   const int32_t* energy;       // simulate: [shape][ncand]
   const HdEnt* hd_ent;
   const int8_t* ti;
@@ -314,17 +314,17 @@ void k_scan(ScanArgs a) {
     }
     s_off[k] = off;
   }
-  // data events of every tile: 8 int16 (16 B) per load, converted to the
+  // data events of every tile: 8 int32 (32 B) per load, converted to the
   // operand type
-  typedef int16_t short8_t __attribute__((ext_vector_type(8)));
+  typedef int32_t int8v_t __attribute__((ext_vector_type(8)));
   const int k8n = kpad / 8;
   for (int i = tid; i < nt * kFiltersPerTile * k8n; i += kThreads) {
     const int row_f = i / k8n, k8 = (i - row_f * k8n) * 8;
     const int gi = row_f / kFiltersPerTile, jj = row_f - gi * kFiltersPerTile;
     const TileDev t = tile_of(gi);
-    short8_t m = {};
+    int8v_t m = {};
     if (jj < t.count && !((t.zmask >> jj) & 1u))
-      m = *(const short8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
+      m = *(const int8v_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
     vec8 v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
@@ -486,13 +486,13 @@ void k_scan_fm(ScanArgs a) {
     }
     s_off[k] = off;
   }
-  typedef int16_t short8_t __attribute__((ext_vector_type(8)));
+  typedef int32_t int8v_t __attribute__((ext_vector_type(8)));
   const int k8n = kpad / 8;
   for (int i = tid; i < kFiltersPerTile * k8n; i += kThreads) {
     const int jj = i / k8n, k8 = (i - jj * k8n) * 8;
-    short8_t m = {};
+    int8v_t m = {};
     if (jj < t.count && !((t.zmask >> jj) & 1u))
-      m = *(const short8_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
+      m = *(const int8v_t*)(a.mbuf + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
     vec8 v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
