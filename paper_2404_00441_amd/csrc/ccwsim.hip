@@ -1974,7 +1974,26 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     __syncthreads();
   } else if (a.coef_lds) idwt_window_lds<ND>(a.Ki, a.det, g, cx, cy, cz, (int32_t*)s_cand, bufA, bufB, P);
   else idwt_window<ND>(a.Ki, a.det, g, cx, cy, cz, bufA, bufB, P);
-  if (win_defer) __syncthreads();   // the windows' LDS stores, for the cut
+  // additive data events: the successors' records, the block list and the
+  // zeroed sums of the first group of successors go to LDS now (the inverse
+  // DWT is done with its buffers), so the barriers of the cut cover them
+  // additive data events: the successors' records, the block list and the
+  // zeroed sums of the first group of successors go to LDS now (the inverse
+  // DWT is done with its buffers), under the barrier the cut needs anyway
+  __shared__ int s_betas[kKMax];
+  const int ev_tcl = (int)g.tcells;
+  const int ev_ng = a.ev_delta ? max(1, min(my_nsucc, (int)(2 * a.buf_cells / ev_tcl))) : 0;
+  int* s_dsum = bufA;
+  if (a.ev_delta) {
+    for (int i = tid; i < ev_ng * ev_tcl; i += kThreads) s_dsum[i] = 0;
+    if (tid < a.kpad) s_betas[tid] = my_beta;
+    if (tid < my_nsucc) {
+      s_mine[tid] = my_succ;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) ((int2*)&s_fq[tid])[q] = my_fq[q];
+    }
+  }
+  if (win_defer || a.ev_delta) __syncthreads();   // the windows' LDS stores, for the cut
 
   int8_t* sgw = a.sg + (long long)f.r * g.pcells;
   bool interior_done = false;   // cells outside every band already pasted
@@ -2069,61 +2088,66 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     }
   }
   if (a.ev_delta) {
-    // Additive data events: add what this paste changed in each
-    // successor's overlap to that successor's block sums.  A cell changes
-    // where the paste wrote it (no hard datum, new side of every seam);
-    // the old value is the window read before the cut.  The sums of a group
-    // of successors are gathered in the inverse-DWT buffers (free by now),
-    // then each listed block goes out as one device-scope atomic add.
-    if (tid < my_nsucc) {
-      s_mine[tid] = my_succ;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) ((int2*)&s_fq[tid])[q] = my_fq[q];
-    }
-    __syncthreads();
-    int* s_dsum = bufA;
-    const int tcl = (int)g.tcells;
+    // Additive data events: what this paste changed in each successor's
+    // overlap is added to that successor's block sums.  A cell changes where
+    // the paste wrote it (no hard datum, new side of every seam); the old
+    // value is the window read before the cut.  The sums of a group of
+    // successors are gathered in the inverse-DWT buffers, then each listed
+    // block goes out as one device-scope atomic add (fire and forget).  This
+    // runs once per launch on each CU, so the loops are kept compact: their
+    // code is fetched cold.
     const int lb = g.level, lbz = g.ndim == 3 ? g.level : 0;
-    const int ng = max(1, min(my_nsucc, (int)(2 * a.buf_cells / tcl)));
-    for (int m0 = 0; m0 < my_nsucc; m0 += ng) {
-      const int gm = min(ng, my_nsucc - m0);
-      for (int i = tid; i < gm * tcl; i += kThreads) s_dsum[i] = 0;
-      __syncthreads();
+#pragma unroll 1
+    for (int m0 = 0; m0 < my_nsucc; m0 += ev_ng) {
+      const int gm = min(ev_ng, my_nsucc - m0);
+      if (m0 > 0) {
+        for (int i = tid; i < gm * ev_tcl; i += kThreads) s_dsum[i] = 0;
+        __syncthreads();
+      }
+#pragma unroll 1
       for (int mm = 0; mm < gm; ++mm) {
-        const FilterDev& fq = s_fq[m0 + mm];
-        // the box both windows cover, in this window's coordinates
-        int d[3], lo[3], ex[3];
+        const FilterDev q = s_fq[m0 + mm];   // in registers: the atomics below alias LDS
+        int d[3], lo[3], ex[3];   // the box both windows cover, in this window's coordinates
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          d[ax] = f.org[ax] - fq.org[ax];
+          d[ax] = f.org[ax] - q.org[ax];
           lo[ax] = max(0, -d[ax]);
           ex[ax] = max(0, min(g.T[ax], g.T[ax] - d[ax]) - lo[ax]);
         }
-        const int nbox = ex[0] * ex[1] * ex[2];
-        if (nbox == 0) continue;
-        int* dsum = s_dsum + mm * tcl;
-        BoxWalk w(tid, kThreads, ex[0], ex[1]);
-        for (int i = tid; i < nbox; i += kThreads, w.next()) {
-          const int x = lo[0] + w.x, y = lo[1] + w.y, z = lo[2] + w.z;
+        int* dsum = s_dsum + mm * ev_tcl;
+        auto cell = [&](int x, int y, int z) {
           const int c = idx3i(x, y, z, g.T);
-          const int old = s_sg[c];
-          const int nv = (s_hd[c] < 0 && !keep[c]) ? (int)P[c] : old;
-          if (nv != old) {
-            const int sx = x + d[0], sy = y + d[1], sz = z + d[2];
-            if (dev_in_band(g, fq.orient, fq.bandmask, sx, sy, sz))
-              atomicAdd(&dsum[((sz >> lbz) * g.tc[1] + (sy >> lb)) * g.tc[0] + (sx >> lb)], nv - old);
-          }
+          const int o = s_sg[c], h = s_hd[c], k = keep[c], p = P[c];   // one wait for all four
+          const int nv = (h < 0 && !k) ? p : o;
+          const int sx = x + d[0], sy = y + d[1], sz = z + d[2];
+          if (nv != o && dev_in_band(g, q.orient, q.bandmask, sx, sy, sz))
+            atomicAdd(&dsum[((sz >> lbz) * g.tc[1] + (sy >> lb)) * g.tc[0] + (sx >> lb)], nv - o);
+        };
+        if (ND == 2) {   // a 16 x 16 thread tile over the box: no divisions
+          const int tx = tid & 15, ty = tid >> 4;
+#pragma unroll 1
+          for (int y = ty; y < ex[1]; y += 16)
+#pragma unroll 1
+            for (int x = tx; x < ex[0]; x += 16) cell(lo[0] + x, lo[1] + y, 0);
+        } else {
+          const int nbox = ex[0] * ex[1] * ex[2];
+          BoxWalk w(tid, kThreads, max(ex[0], 1), max(ex[1], 1));
+#pragma unroll 1
+          for (int i = tid; i < nbox; i += kThreads, w.next()) cell(lo[0] + w.x, lo[1] + w.y, lo[2] + w.z);
         }
       }
       __syncthreads();
-      if (my_beta >= 0)
-        for (int mm = 0; mm < gm; ++mm) {
-          const int v = s_dsum[mm * tcl + my_beta];
-          if (v != 0)
-            __hip_atomic_fetch_add(&a.mbuf[(long long)s_mine[m0 + mm] * kKMax + tid], v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-      __syncthreads();
+      // one thread per (successor, listed block)
+#pragma unroll 1
+      for (int i = tid; i < gm * a.kpad; i += kThreads) {
+        const int mm = i / a.kpad, t = i - mm * a.kpad;
+        const int beta = s_betas[t];
+        const int v = beta >= 0 ? s_dsum[mm * ev_tcl + beta] : 0;
+        if (v != 0)
+          __hip_atomic_fetch_add(&a.mbuf[(long long)s_mine[m0 + mm] * kKMax + t], v, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (m0 + gm < my_nsucc) __syncthreads();
     }
     return;
   }
