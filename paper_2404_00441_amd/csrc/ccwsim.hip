@@ -24,6 +24,7 @@ using namespace ccw;
 
 constexpr int kSeamRowsMax = 64;   // longest seam of the register dynamic programme
 constexpr int kMaxSucc = 64;       // overlapping successors of one patch
+constexpr int kFinInline = 64;     // patch records passed by value to a finalize launch
 
 // ===========================================================================
 // errors
@@ -1053,8 +1054,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_tmp = o;       o += align256(2 * c1 * 4);
   P.ws_energy = o;    o += align256((long long)P.n_shapes * g.ncand * 4);
   P.ws_tbl = o;       o += align256((long long)P.tbl_bytes);
-  P.ws_sg = o;        o += align256((long long)p.n_real * g.pcells);
-  P.ws_hdmap = o;     o += align256((long long)p.n_real * g.pcells);
+  P.ws_sg = o;        o += align256((long long)p.n_real * g.pcells + 16);   // slack: window rows are read in 8-byte words
+  P.ws_hdmap = o;     o += align256((long long)p.n_real * g.pcells + 16);
   P.ws_mbuf = o;      o += align256((long long)P.nfilters * kKMax * 4);
   P.ws_predcnt = o;   o += align256((long long)P.nfilters * 4);
   P.ws_report = o;    o += 256;
@@ -1459,6 +1460,10 @@ struct FinArgs {
   long long learn_off;            // LDS offset of the row-rescoring area
   int learn_kbr;                  // candidate rows rescored per round
   int learn_w;                    // staged K-row length (int16)
+  // the step's patch records by value when they fit, so that reading a
+  // workgroup's record overlaps the argument load instead of following it
+  int n_inline;
+  FilterDev recs_inline[kFinInline];
 };
 
 // Window cell of a seam: w along the band axis ax (counted from the side
@@ -1603,7 +1608,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   const Geom& g = a.g;
   const int tid = threadIdx.x;
   const int slot = blockIdx.x;
-  const FilterDev f = a.filters[slot];
+  // scalar loads from the arguments, issued together with the count that
+  // decides whether they are used (the empty asm takes both before the branch)
+  const int n_inline = a.n_inline;
+  const FilterDev f_arg = a.recs_inline[min(slot, kFinInline - 1)];
+  __asm__ volatile("" ::"s"(n_inline), "s"(f_arg.r));
+  FilterDev f;
+  if (slot < n_inline) {
+    f = f_arg;
+    __asm__ volatile("" ::: "memory");  // keeps the two loads apart (no generic pointer)
+  } else {
+    f = a.filters[slot];
+  }
   // the row minima depend on the slot only: fetch them with the record
   const int nrows_c = g.cand[1] * g.cand[2];
   uint64_t rm_pre = ~0ull;
@@ -1623,45 +1639,57 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   __shared__ FilterDev s_fq[kMaxSucc];
   __shared__ int s_nmine;
   const int my_nsucc = min(f.nsucc, kMaxSucc);
-  int my_succ = 0, my_npred = 0;
   static_assert(sizeof(FilterDev) == 40, "successor record is moved as five int2");
-  int2 my_fq[5] = {};   // the successor's record, kept in registers until the end
-  if (tid < my_nsucc) {
-    const int2 e = ((const int2*)a.succ)[f.succ0 + tid];
-    my_succ = e.x;
-    my_npred = e.y;
-    const int2* src = (const int2*)(a.filters_all + my_succ);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) my_fq[q] = src[q];
-  }
+  int2 my_fq[5] = {};   // the successor's record (fetched after the selection), kept in registers
+  // (successor, its predecessor count), meaningful for tid < my_nsucc; read
+  // unconditionally (entry 0 always exists) so that nothing waits for it here
+  const int2 succ_e = ((const int2*)a.succ)[tid < my_nsucc ? f.succ0 + tid : 0];
   // the block list of this realization's orientation (shared by successors)
   const int my_beta = tid < a.kpad ? a.kbeta[f.orient * kKMax + tid] : -1;
 
   // windows of the grid and of the hard-data map.  They are first read by
-  // the cut: when a thread's share fits one batch, its loads are issued now
-  // and stored to LDS after the selection, so their latency overlaps it.
-  constexpr int WU = 8;
-  const bool win_defer = (int)g.wcells <= WU * kThreads;
+  // the cut.  When they fit one batch, each thread loads up to kWinWords
+  // aligned 8-byte words of the window rows (a row of T0 cells starts at
+  // any byte, so it spans at most (T0 + 14) / 8 words), keeps them in
+  // registers through the selection and unpacks their bytes into LDS after
+  // it, so the loads' latency overlaps the selection.  The grids carry 16
+  // bytes of slack for the words that reach past a row's end.
+  constexpr int kWinWords = 4;
+  const int win_wpr = (g.T[0] + 14) >> 3;
+  const int win_nw = g.T[1] * g.T[2] * win_wpr;
+  const bool win_defer = win_wpr <= 64 && win_nw <= kWinWords * kThreads;
   const int8_t* win_sg = a.sg + (long long)f.r * g.pcells;
   const int8_t* win_hd = a.has_hd ? a.hdmap + (long long)f.r * g.pcells : nullptr;
-  int8_t wv0[WU], wv1[WU];
-  if (win_defer) {
-    BoxWalk w(tid, kThreads, g.T[0], g.T[1]);
+  uint64_t wv0[kWinWords], wv1[kWinWords];
+  int wrow[kWinWords], wx0[kWinWords];   // window row of each word, window x of its first byte
+  auto issue_windows = [&]() {
+    const unsigned mdiv = (65536u + win_wpr - 1) / win_wpr;   // j / wpr exactly for j < 2^16 / wpr
 #pragma unroll
-    for (int q = 0; q < WU; ++q) {
-      const int i = tid + q * kThreads;
+    for (int q = 0; q < kWinWords; ++q) {
+      const int j = tid + q * kThreads;
       wv0[q] = 0;
-      wv1[q] = -1;
-      if (i < (int)g.wcells) {
-        const long long at = idx3(f.org[0] + w.x, f.org[1] + w.y, f.org[2] + w.z, g.pad);
-        wv0[q] = win_sg[at];
-        if (win_hd) wv1[q] = win_hd[at];
+      wv1[q] = ~0ull;   // no hard data: every byte -1
+      wrow[q] = -1;
+      wx0[q] = 0;
+      if (j < win_nw) {
+        const int row = (int)(((unsigned)j * mdiv) >> 16), w = j - row * win_wpr;
+        const int z = g.T[2] > 1 ? row / g.T[1] : 0, y = row - z * g.T[1];
+        const long long c0 = idx3(f.org[0], f.org[1] + y, f.org[2] + z, g.pad);
+        const int lead = (int)((uintptr_t)(win_sg + c0) & 7);   // the same for both maps (256-aligned bases)
+        const long long wo = c0 - lead + 8ll * w;
+        wv0[q] = *(const uint64_t*)(win_sg + wo);
+        if (win_hd) wv1[q] = *(const uint64_t*)(win_hd + wo);
+        wrow[q] = row;
+        wx0[q] = 8 * w - lead;
       }
-      w.next();
     }
-  } else {
-    load_windows(s_sg, win_sg, s_hd, win_hd, f.org, g);
-  }
+  };
+  // With stored keys the windows' loads go out after the row minima are
+  // ranked, beside the loads of the best rows' keys: the staging of the row
+  // minima would otherwise wait for them too.
+  const bool win_late = win_defer && !a.rescore_rows && a.cand_cap > 0;
+  if (!win_defer) load_windows(s_sg, win_sg, s_hd, win_hd, f.org, g);
+  else if (!win_late) issue_windows();
   for (int i = tid; i < (int)g.wcells; i += kThreads) keep[i] = 0;
 
   // K best keys.  The smallest key of every candidate row is known from the
@@ -1834,6 +1862,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       const int id = (int)tie_perm_inv((uint32_t)(s_rowtop[tid] & kMask20), tkey);
       s_rows[tid] = min(max(id / g.cand[0], 0), nrows - 1);
     }
+    if (win_late) issue_windows();
     __syncthreads();
     // 2. every key of those rows at or below the kr-th row minimum (when
     //    there are fewer rows than ksel, every key of every row); the list
@@ -1944,6 +1973,14 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     s_fin[tid] = s_sel[tid];
   }
   __syncthreads();
+  // the successors' records: their loads go out now, after the selection's
+  // waits, and arrive while the pattern is rebuilt
+  const int my_succ = succ_e.x, my_npred = succ_e.y;
+  if (tid < my_nsucc) {
+    const int2* src = (const int2*)(a.filters_all + my_succ);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) my_fq[q] = src[q];
+  }
   const uint64_t u = draw64(a.seed, kStreamDraw, (uint64_t)f.r, (uint64_t)f.step) >> 32;
   const int jpick = (int)((u * (uint64_t)k) >> 32);
   int idx = (int)tie_perm_inv((uint32_t)(s_fin[jpick] & kMask20), tkey);
@@ -1953,11 +1990,17 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
 
   if (win_defer) {
 #pragma unroll
-    for (int q = 0; q < WU; ++q) {
-      const int i = tid + q * kThreads;
-      if (i < (int)g.wcells) {
-        s_sg[i] = wv0[q];
-        s_hd[i] = wv1[q];
+    for (int q = 0; q < kWinWords; ++q) {
+      if (wrow[q] < 0) continue;
+      int8_t* ds = s_sg + wrow[q] * g.T[0];
+      int8_t* dh = s_hd + wrow[q] * g.T[0];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int x = wx0[q] + b;
+        if (x >= 0 && x < g.T[0]) {
+          ds[x] = (int8_t)(wv0[q] >> (8 * b));
+          dh[x] = (int8_t)(wv1[q] >> (8 * b));
+        }
       }
     }
   }
@@ -2575,6 +2618,10 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     }
     fa.filters = filters + s.fbegin;
     fa.fbegin = s.fbegin;
+    fa.n_inline = s.fcount <= kFinInline ? s.fcount : 0;
+    if (fa.n_inline)
+      memcpy(fa.recs_inline, P->tbl + P->off_filters + (size_t)s.fbegin * sizeof(FilterDev),
+             (size_t)s.fcount * sizeof(FilterDev));
     {
       ProfKernel pk(CCWSIM_KIND_FINALIZE);
       launch_finalize(g.ndim, P->tree_level, (unsigned)s.fcount, P->fin_lds, st, fa, pk.a, pk.b);
