@@ -2054,7 +2054,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       sa = ND == 3 ? 3 - ax - ra : -1;
     };
     if (a.dp_wave) {
-      uint32_t* s_ev = (uint32_t*)(((uintptr_t)s_cand + 15) & ~(uintptr_t)15);
+      // 16-byte aligned, as an offset from the LDS base: an integer round
+      // trip of the pointer would lose its address space (FLAT accesses)
+      uint32_t* s_ev = (uint32_t*)(smem + ((((unsigned char*)s_cand - smem) + 15) & ~15ll));
       seam_dp_wave<ND>(g, f, s_sg, P, keep, n0, n1, n2, s_ev, a.dp_evs);
       // wavefronts without a seam paste the cells outside every band meanwhile
       const int busy = min(ndp, kThreads / 64);
@@ -2105,9 +2107,42 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     }
   }
   __syncthreads();
-  // paste the new side of every seam, keep hard data (the LDS reads of
-  // eight cells are issued before the first test)
-  {
+  // paste the new side of every seam, keep hard data
+  if (interior_done) {
+    // only the band is left: its cells as up to three disjoint boxes, the
+    // slab of each band axis minus the slabs of the axes before it
+#pragma unroll 1
+    for (int ax = 0; ax < ND; ++ax) {
+      if (!((f.bandmask >> ax) & 1)) continue;
+      int lo[3] = {0, 0, 0}, ex[3] = {g.T[0], g.T[1], g.T[2]};
+      lo[ax] = ((f.orient >> ax) & 1) ? g.T[ax] - g.OV[ax] : 0;
+      ex[ax] = g.OV[ax];
+      for (int b = 0; b < ax; ++b)
+        if ((f.bandmask >> b) & 1) {
+          lo[b] = ((f.orient >> b) & 1) ? 0 : g.OV[b];
+          ex[b] = g.T[b] - g.OV[b];
+        }
+      auto put = [&](int x, int y, int z) {
+        const int c = idx3i(x, y, z, g.T);
+        const int8_t pv = P[c], hv = s_hd[c];
+        const uint8_t kv = keep[c];
+        if (hv < 0 && !kv) sgw[idx3(f.org[0] + x, f.org[1] + y, f.org[2] + z, g.pad)] = pv;
+      };
+      if (ND == 2) {   // a 16 x 16 thread tile over the box: no divisions
+        const int tx = tid & 15, ty = tid >> 4;
+#pragma unroll 1
+        for (int y = ty; y < ex[1]; y += 16)
+#pragma unroll 1
+          for (int x = tx; x < ex[0]; x += 16) put(lo[0] + x, lo[1] + y, 0);
+      } else {
+        const int nbox = ex[0] * ex[1] * ex[2];
+        BoxWalk w(tid, kThreads, max(ex[0], 1), max(ex[1], 1));
+#pragma unroll 1
+        for (int i = tid; i < nbox; i += kThreads, w.next()) put(lo[0] + w.x, lo[1] + w.y, lo[2] + w.z);
+      }
+    }
+  } else {
+    // every cell (the LDS reads of eight cells are issued before the first test)
     constexpr int U = 8;
     const int n = (int)g.wcells;
     BoxWalk w(tid, kThreads, g.T[0], g.T[1]);
@@ -2123,8 +2158,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        if (base + q * kThreads < n && hv[q] < 0 && !kv[q] &&
-            !(interior_done && !dev_in_band(g, f.orient, f.bandmask, w.x, w.y, w.z)))
+        if (base + q * kThreads < n && hv[q] < 0 && !kv[q])
           sgw[((f.org[2] + w.z) * g.pad[1] + f.org[1] + w.y) * g.pad[0] + f.org[0] + w.x] = pv[q];
         w.next();
       }
