@@ -437,21 +437,31 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
 
 // k smallest of n distinct keys held in LDS, by rank: each key counts the
 // keys below it and, if its rank is under k, writes itself to out[rank].
-// Cost n^2 / 256 comparisons per thread, so only for short lists.
+// Cost n^2 / 256 comparisons per thread, so only for short lists.  When the
+// list is short enough, P adjacent lanes (P a power of two, P * n <= the
+// workgroup) share one key's comparisons, each taking every P-th key, and
+// add their counts with lane shuffles: a workgroup runs alone on its CU
+// here, so the length of each thread's chain of LDS reads is the cost.
 __device__ __forceinline__ void block_rank_select(const uint64_t* v, int n, int k, uint64_t* out) {
-  for (int i = threadIdx.x; i < n; i += kThreads) {
+  int lp = 0;   // log2 P
+  while (lp < 3 && (n << (lp + 1)) <= kThreads) ++lp;
+  const int P = 1 << lp;
+  for (int t = threadIdx.x; t < (n << lp); t += kThreads) {
+    const int i = t >> lp, part = t & (P - 1);
     const uint64_t x = v[i];
     int rank = 0;
-    int j = 0;
-    for (; j + 8 <= n; j += 8) {   // eight reads in flight per wait
+    int j = part;
+    for (; j + 7 * P < n; j += 8 * P) {   // eight reads in flight per wait
       uint64_t y[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) y[e] = v[j + e];
+      for (int e = 0; e < 8; ++e) y[e] = v[j + e * P];
 #pragma unroll
       for (int e = 0; e < 8; ++e) rank += y[e] < x ? 1 : 0;
     }
-    for (; j < n; ++j) rank += v[j] < x ? 1 : 0;
-    if (rank < k) out[rank] = x;
+    for (; j < n; j += P) rank += v[j] < x ? 1 : 0;
+    // the P lanes of a key are adjacent and active together
+    for (int m = 1; m < P; m <<= 1) rank += __shfl_xor(rank, m, 64);
+    if (part == 0 && rank < k) out[rank] = x;
   }
   __syncthreads();
 }
