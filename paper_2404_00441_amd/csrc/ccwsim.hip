@@ -2640,6 +2640,10 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     sa.recs = recs + (long long)s.tbegin * kFiltersPerTile;
     sa.ntiles = s.tcount;
     sa.groups = groups + s.gbegin[gix];
+    sa.n_ginline = s.gcount[gix] <= kScanGroupsInline ? s.gcount[gix] : 0;
+    if (sa.n_ginline)
+      memcpy(sa.groups_inline, P->tbl + P->off_groups + (size_t)s.gbegin[gix] * sizeof(int2),
+             (size_t)s.gcount[gix] * sizeof(int2));
     if (P->learn) {
       xa.tiles = tiles + s.tbegin;
       xa.recs = recs + (long long)s.tbegin * kFiltersPerTile;

@@ -75,6 +75,8 @@ struct HdBits {        // one hard datum: where its bit vector starts
   int32_t sh;          // bit of candidate 0 within that word pair
 };
 
+constexpr int kScanGroupsInline = 64;   // group-table entries passed by value to a scan launch
+
 struct ScanArgs {
   Geom g;
   HdmGeom hm;
@@ -102,6 +104,10 @@ struct ScanArgs {
   int has_hd;
   int ntiles;                  // tiles of this launch
   const int2* groups;          // simulate: per workgroup column (first tile, tiles), one orientation
+  // the step's group table by value when it fits, so that a workgroup's
+  // entry arrives with the arguments instead of after them
+  int n_ginline;
+  int2 groups_inline[kScanGroupsInline];
 };
 
 template <typename OT>
@@ -157,7 +163,18 @@ void k_scan(ScanArgs a) {
     tile0 = blockIdx.y;
     nt = 1;
   } else {
-    const int2 grp = a.groups[blockIdx.y];
+    // scalar loads of the arguments, issued with the count that decides
+    // whether they are used (the empty asm takes both before the branch)
+    const int n_gi = a.n_ginline;
+    const int2 g_arg = a.groups_inline[min((int)blockIdx.y, kScanGroupsInline - 1)];
+    __asm__ volatile("" ::"s"(n_gi), "s"(g_arg.x));
+    int2 grp;
+    if ((int)blockIdx.y < n_gi) {
+      grp = g_arg;
+      __asm__ volatile("" ::: "memory");   // keeps the two loads apart (no generic pointer)
+    } else {
+      grp = a.groups[blockIdx.y];
+    }
     tile0 = grp.x;
     nt = grp.y;
   }
