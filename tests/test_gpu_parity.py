@@ -356,6 +356,25 @@ def test_simulate_tile_groups(cc, orc):
         assert np.array_equal(out, oout), f"G={G}"
 
 
+def test_simulate_group_table_in_memory(cc):
+    # 4,096 realizations of the batched workload put more than 64 groups of
+    # two tiles into a step, so the scan reads its group table from memory
+    # instead of the launch arguments; the realizations must equal those of
+    # the one-tile layout (no group table), which the test above ties to the
+    # oracle on the same workload
+    p, ti, hd = wl.make("c4_batched", scale=0.5, n_real=4096)
+    _say("group table in memory", p["n_real"])
+    res = {}
+    for G in (1, 2):
+        cc.set_scan_group(G)
+        try:
+            res[G] = _run(cc, p, ti, hd)
+        finally:
+            cc.set_scan_group(0)
+    assert np.array_equal(res[1][1], res[2][1])
+    assert np.array_equal(res[1][0], res[2][0])
+
+
 @pytest.mark.parametrize("name,scale,nr", [("c2_scale2d", 0.3, None), ("c3_split3d", 0.3, None),
                                            ("c1_plain2d", 1.0, None)])
 def test_simulate_filter_major_scan(cc, orc, name, scale, nr):
