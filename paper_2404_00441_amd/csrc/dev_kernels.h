@@ -387,11 +387,25 @@ __device__ __forceinline__ void idwt_window_tree(const int32_t* __restrict__ tre
       tv[4 * i + 3] = q.w;
     }
     haar_tree_inverse<ND, J>(tv, v);
+    // a block inside the window whose rows start on 4-byte boundaries
+    // writes each row of four cells as one 32-bit store; others cell by cell
+    const bool whole = b == 4 && (g.T[0] & 3) == 0 && b * bx + b <= g.T[0] && b * by + b <= g.T[1] &&
+                       (ND < 3 || b * bz + b <= g.T[2]);
+    if (whole) {
 #pragma unroll
-    for (int i = 0; i < T::B; ++i) {
-      const int lx = i % b, ly = (i / b) % b, lz = ND == 3 ? i / (b * b) : 0;
-      const int ux = b * bx + lx, uy = b * by + ly, uz = ND == 3 ? b * bz + lz : 0;
-      if (ux < g.T[0] && uy < g.T[1] && uz < g.T[2]) P[idx3(ux, uy, uz, g.T)] = (int8_t)v[i];
+      for (int r = 0; r < T::B / b; ++r) {   // row r = (ly, lz)
+        const int ly = r % b, lz = ND == 3 ? r / b : 0;
+        const uint32_t w = (uint32_t)(v[b * r] & 0xFF) | ((uint32_t)(v[b * r + 1] & 0xFF) << 8) |
+                           ((uint32_t)(v[b * r + 2] & 0xFF) << 16) | ((uint32_t)(v[b * r + 3] & 0xFF) << 24);
+        *(uint32_t*)(P + idx3i(b * bx, b * by + ly, ND == 3 ? b * bz + lz : 0, g.T)) = w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < T::B; ++i) {
+        const int lx = i % b, ly = (i / b) % b, lz = ND == 3 ? i / (b * b) : 0;
+        const int ux = b * bx + lx, uy = b * by + ly, uz = ND == 3 ? b * bz + lz : 0;
+        if (ux < g.T[0] && uy < g.T[1] && uz < g.T[2]) P[idx3i(ux, uy, uz, g.T)] = (int8_t)v[i];
+      }
     }
   }
   __syncthreads();
