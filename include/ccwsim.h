@@ -212,16 +212,24 @@ int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t n_hd, cons
                     const int32_t* hd_pos, const int8_t* hd_val, int8_t* out, int32_t* chosen,
                     void* workspace, int64_t workspace_bytes, void* stream);
 
-/* Releases host-side caches (simulation plans and captured graphs).  Not
- * thread-safe with concurrent ccwsim_simulate calls. */
+/* Host-side caches.  A plan (the schedule and the tables of one parameter
+ * set, the seed included) is built on the first call that names its
+ * parameters; at most 16 plans are kept, the least recently used dropped
+ * first together with the graphs captured on it.  ccwsim_release_caches
+ * frees every plan, graph and the in-memory tuning table (not thread-safe
+ * with concurrent ccwsim_simulate calls); ccwsim_cache_counts reports how
+ * many plans and graphs are held (host call, no device work). */
 void ccwsim_release_caches(void);
+int ccwsim_cache_counts(int64_t* plans, int64_t* graphs);
 
 /* ---- measurement --------------------------------------------------------
  * Work of one ccwsim_simulate call as the method defines it (not counting
  * padding the kernels add): patches = (realization, patch) pairs, or_blocks =
  * sum over patches of the level-J blocks holding known overlap cells,
  * scan_flops = 2 * or_blocks * candidates (one multiply-add per block and
- * candidate, Sec. 4.3).  Host call, no device work. */
+ * candidate, Sec. 4.3).  Host call, no device work (it builds or reuses the
+ * plan, which needs no device either; so does
+ * ccwsim_simulate_workspace_size). */
 typedef struct {
   int64_t patches;
   int64_t wavefront_steps;

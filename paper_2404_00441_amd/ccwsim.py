@@ -77,6 +77,8 @@ def load():
     L.ccwsim_simulate.argtypes = [p, p, i64, p, p, p, p, p, p, i64, p]
     L.ccwsim_release_caches.restype = None
     L.ccwsim_release_caches.argtypes = []
+    L.ccwsim_cache_counts.restype = ctypes.c_int
+    L.ccwsim_cache_counts.argtypes = [p, p]
     L.ccwsim_simulate_stats.restype = ctypes.c_int
     L.ccwsim_simulate_stats.argtypes = [p, p]
     L.ccwsim_profile_enable.restype = ctypes.c_int
@@ -108,7 +110,7 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
-           "ccwsim_stats_connectivity")
+           "ccwsim_stats_connectivity", "ccwsim_cache_counts")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
@@ -302,6 +304,13 @@ def hd_to_device(hd, ndim, device="cuda"):
 
 def release_caches():
     load().ccwsim_release_caches()
+
+
+def cache_counts() -> tuple:
+    """(plans, graphs) held by the library's host caches."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check("ccwsim_cache_counts", load().ccwsim_cache_counts(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def simulate_stats(p: dict) -> dict:

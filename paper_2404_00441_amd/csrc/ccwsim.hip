@@ -570,9 +570,12 @@ struct Plan {
   HdmGeom hm = {};
   int nfilters = 0;
   std::vector<StepRange> steps;
-  // host tables, uploaded on every call (pinned)
+  // host tables, uploaded on every call: built in pageable memory (so that
+  // sizes and statistics need no device), copied to pinned memory the first
+  // time a call uploads them
   size_t tbl_bytes = 0;
-  unsigned char* tbl = nullptr;       // kbeta | nbt | filters | tiles | recs | npred | succ_off | succ
+  std::vector<unsigned char> tbl_host;   // kbeta | nbt | filters | tiles | recs | npred | succ_off | succ
+  unsigned char* tbl = nullptr;          // pinned copy of tbl_host, or null
   size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_recs = 0, off_groups = 0, off_npred = 0,
          off_succoff = 0, off_succ = 0;
   long long nrecs = 0;
@@ -590,8 +593,18 @@ struct Plan {
   }
 };
 
+// Plans are cached per parameter set (the seed included: it fixes the
+// paths and tie-break keys baked into the tables), least recently used
+// dropped first beyond kMaxPlans together with the graphs captured on them.
+// A call keeps its plan alive through shared ownership.
 std::mutex g_plan_mu;
-std::map<std::string, std::unique_ptr<Plan>> g_plans;
+struct PlanEntry {
+  std::string key;
+  std::shared_ptr<Plan> plan;
+};
+std::vector<PlanEntry> g_plans;   // most recent last
+constexpr size_t kMaxPlans = 16;
+void drop_graphs_of(const std::string& plan_key);   // defined with the graph cache
 
 // path of realization r: perm[k] = lattice axis at path depth k (0 fastest),
 // flip[a] = 1 when axis a is walked from its high end
@@ -1002,17 +1015,17 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.off_succoff = P.off_npred + align256(npred.size() * 4);
   P.off_succ = P.off_succoff + align256(succ_off.size() * 4);
   P.tbl_bytes = P.off_succ + align256(succ.size() * 4);
-  if (hipHostMalloc((void**)&P.tbl, P.tbl_bytes, hipHostMallocDefault) != hipSuccess)
-    return fail(CCWSIM_ERR_HIP, "hipHostMalloc of %zu bytes failed", P.tbl_bytes);
-  memcpy(P.tbl + P.off_kbeta, kbeta.data(), kbeta.size() * 4);
-  memcpy(P.tbl + P.off_nbt, nbt.data(), nbt.size() * 4);
-  memcpy(P.tbl + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
-  memcpy(P.tbl + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
-  memcpy(P.tbl + P.off_recs, recs.data(), recs.size() * sizeof(ScanRec));
-  memcpy(P.tbl + P.off_groups, groups.data(), groups.size() * sizeof(int2));
-  memcpy(P.tbl + P.off_npred, npred.data(), npred.size() * 4);
-  memcpy(P.tbl + P.off_succoff, succ_off.data(), succ_off.size() * 4);
-  memcpy(P.tbl + P.off_succ, succ.data(), succ.size() * 4);
+  P.tbl_host.assign(P.tbl_bytes, 0);
+  unsigned char* tb = P.tbl_host.data();
+  memcpy(tb + P.off_kbeta, kbeta.data(), kbeta.size() * 4);
+  memcpy(tb + P.off_nbt, nbt.data(), nbt.size() * 4);
+  memcpy(tb + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
+  memcpy(tb + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
+  memcpy(tb + P.off_recs, recs.data(), recs.size() * sizeof(ScanRec));
+  memcpy(tb + P.off_groups, groups.data(), groups.size() * sizeof(int2));
+  memcpy(tb + P.off_npred, npred.data(), npred.size() * 4);
+  memcpy(tb + P.off_succoff, succ_off.data(), succ_off.size() * 4);
+  memcpy(tb + P.off_succ, succ.data(), succ.size() * 4);
 
   // hard data: a grid cell lies in the virtual templates of at most
   // prod ceil((T + margin) / stride) patches of its realization
@@ -1087,18 +1100,39 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   return CCWSIM_OK;
 }
 
-int get_plan(const ccwsim_params& p, Plan** out) {
+int get_plan(const ccwsim_params& p, std::shared_ptr<Plan>* out) {
   std::string key((const char*)&p, sizeof p);
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  auto it = g_plans.find(key);
-  if (it != g_plans.end()) {
-    *out = it->second.get();
-    return CCWSIM_OK;
+  for (size_t i = 0; i < g_plans.size(); ++i) {
+    if (g_plans[i].key == key) {
+      PlanEntry e = g_plans[i];
+      g_plans.erase(g_plans.begin() + i);
+      g_plans.push_back(e);
+      *out = e.plan;
+      return CCWSIM_OK;
+    }
   }
-  std::unique_ptr<Plan> P(new Plan);
+  std::shared_ptr<Plan> P(new Plan);
   CCW_TRY(build_plan(p, *P));
-  *out = P.get();
-  g_plans.emplace(key, std::move(P));
+  if (g_plans.size() >= kMaxPlans) {
+    drop_graphs_of(g_plans.front().key);
+    g_plans.erase(g_plans.begin());
+  }
+  g_plans.push_back({key, P});
+  *out = P;
+  return CCWSIM_OK;
+}
+
+// The pinned copy of a plan's tables (made once, on the first call that
+// uploads them).
+int plan_pin(Plan* P) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (P->tbl) return CCWSIM_OK;
+  unsigned char* t = nullptr;
+  if (hipHostMalloc((void**)&t, P->tbl_bytes, hipHostMallocDefault) != hipSuccess)
+    return fail(CCWSIM_ERR_HIP, "hipHostMalloc of %zu bytes failed", P->tbl_bytes);
+  memcpy(t, P->tbl_host.data(), P->tbl_bytes);
+  P->tbl = t;
   return CCWSIM_OK;
 }
 
@@ -2393,8 +2427,9 @@ extern "C" int64_t ccwsim_simulate_workspace_size(const ccwsim_params* p) {
     fail(CCWSIM_ERR_INVALID_ARG, "null params");
     return -1;
   }
-  Plan* P = nullptr;
-  if (get_plan(*p, &P)) return -1;
+  std::shared_ptr<Plan> Ph;
+  if (get_plan(*p, &Ph)) return -1;
+  Plan* P = Ph.get();
   return P->ws_total;
 }
 
@@ -2642,7 +2677,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     sa.groups = groups + s.gbegin[gix];
     sa.n_ginline = s.gcount[gix] <= kScanGroupsInline ? s.gcount[gix] : 0;
     if (sa.n_ginline)
-      memcpy(sa.groups_inline, P->tbl + P->off_groups + (size_t)s.gbegin[gix] * sizeof(int2),
+      memcpy(sa.groups_inline, P->tbl_host.data() + P->off_groups + (size_t)s.gbegin[gix] * sizeof(int2),
              (size_t)s.gcount[gix] * sizeof(int2));
     if (P->learn) {
       xa.tiles = tiles + s.tbegin;
@@ -2658,7 +2693,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     fa.fbegin = s.fbegin;
     fa.n_inline = s.fcount <= kFinInline ? s.fcount : 0;
     if (fa.n_inline)
-      memcpy(fa.recs_inline, P->tbl + P->off_filters + (size_t)s.fbegin * sizeof(FilterDev),
+      memcpy(fa.recs_inline, P->tbl_host.data() + P->off_filters + (size_t)s.fbegin * sizeof(FilterDev),
              (size_t)s.fcount * sizeof(FilterDev));
     {
       ProfKernel pk(CCWSIM_KIND_FINALIZE);
@@ -2688,6 +2723,21 @@ constexpr size_t kMaxGraphs = 64;
 void drop_graphs() {
   for (GraphEntry& e : g_graphs) (void)hipGraphExecDestroy(e.exec);
   g_graphs.clear();
+}
+}  // namespace
+
+namespace {
+// Graph keys begin with the bytes of the parameters, i.e. the plan key.
+void drop_graphs_of(const std::string& plan_key) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    if (g_graphs[i].key.compare(0, plan_key.size(), plan_key) == 0) {
+      (void)hipGraphExecDestroy(g_graphs[i].exec);
+      g_graphs.erase(g_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
 }
 }  // namespace
 
@@ -2776,13 +2826,15 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   if (!p || !ti || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
   if (n_hd < 0 || (n_hd > 0 && (!hd_real || !hd_pos || !hd_val)))
     return fail(CCWSIM_ERR_INVALID_ARG, "hard data pointers");
-  Plan* P = nullptr;
-  CCW_TRY(get_plan(*p, &P));
+  std::shared_ptr<Plan> Ph;
+  CCW_TRY(get_plan(*p, &Ph));
+  Plan* P = Ph.get();
   if (!workspace || workspace_bytes < P->ws_total)
     return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)P->ws_total);
   if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   if (n_hd > p->max_hard_data)
     return fail(CCWSIM_ERR_INVALID_ARG, "%lld hard data exceed max_hard_data = %d", (long long)n_hd, p->max_hard_data);
+  CCW_TRY(plan_pin(P));
   hipStream_t st = as_stream(stream);
   bool prof;
   {
@@ -2927,10 +2979,22 @@ extern "C" void ccwsim_release_caches(void) {
   g_plans.clear();
 }
 
+extern "C" int ccwsim_cache_counts(int64_t* plans, int64_t* graphs) {
+  if (!plans || !graphs) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    *plans = (int64_t)g_plans.size();
+  }
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  *graphs = (int64_t)g_graphs.size();
+  return CCWSIM_OK;
+}
+
 extern "C" int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out) {
   if (!p || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
-  Plan* P = nullptr;
-  CCW_TRY(get_plan(*p, &P));
+  std::shared_ptr<Plan> Ph;
+  CCW_TRY(get_plan(*p, &Ph));
+  Plan* P = Ph.get();
   const Geom& g = P->g;
   out->patches = P->patches;
   out->wavefront_steps = (int64_t)P->steps.size();
@@ -2982,8 +3046,9 @@ extern "C" int ccwsim_profile_read(double* ms, int64_t* launches) {
 extern "C" int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
                                       int64_t* out, void* stream) {
   if (!p || !workspace || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
-  Plan* P = nullptr;
-  CCW_TRY(get_plan(*p, &P));
+  std::shared_ptr<Plan> Ph;
+  CCW_TRY(get_plan(*p, &Ph));
+  Plan* P = Ph.get();
   if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
   unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
   hipStream_t st = as_stream(stream);

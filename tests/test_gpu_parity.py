@@ -339,6 +339,63 @@ def test_simulate_full_size(cc, orc, name, nr):
             assert out[(r,) + tuple(pos[::-1])] == v
 
 
+# The configurations the benchmark reports, at their full sizes and in the
+# launch configuration it times.  The batched calls run every realization on
+# the GPU; realization r depends only on (seed, r), so a shorter oracle run
+# gives realizations 0 .. n_cmp - 1 of the same batch.
+FULL_BENCH_CASES = [("c5_learned", 16, 2), ("c4_batched", 64, 64), ("c3_split3d", None, None)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,nr,n_cmp", FULL_BENCH_CASES, ids=[c[0] for c in FULL_BENCH_CASES])
+def test_simulate_full_size_bench_configs(cc, orc, name, nr, n_cmp):
+    _say("full bench config", name, nr, n_cmp)
+    p, ti, hd = wl.make(name, n_real=nr)
+    out, chosen = _run(cc, p, ti, hd)
+    q = dict(p)
+    if n_cmp is not None:
+        q["n_real"] = n_cmp
+        if hd is not None:
+            sel = hd[0] < n_cmp
+            hd = (hd[0][sel], hd[1][sel], hd[2][sel])
+    oout, ochosen = orc.simulate(_sp(q, orc), ti, hd)
+    m = q["n_real"]
+    assert np.array_equal(chosen[:m], ochosen), f"first differing step {np.argwhere(chosen[:m] != ochosen)[:3]}"
+    assert np.array_equal(out[:m], oout)
+    assert out.min() >= 0
+
+
+@pytest.mark.timeout(600)
+def test_scan_c5_shape_full(cc, orc):
+    # the standalone scan at the largest batched shape (1000^2 TI, T 48,
+    # J 2, an L-shaped overlap of 63 level-J blocks, 448 filters), the
+    # configuration the benchmark times, against the oracle's scores
+    import torch
+    p, ti, _ = wl.make("c5_learned", n_real=1)
+    level, T, OV = p["level"], p["tmpl"], p["overlap"]
+    b = 2 ** level
+    tc = [-(-t // b) for t in T]
+    nf = 448
+    _say("scan c5 shape", nf)
+    u = np.zeros((T[1], T[0]), bool)
+    u[:OV[1], :] = True
+    u[:, :OV[0]] = True
+    pad = np.zeros((tc[1] * b, tc[0] * b), int)
+    pad[:T[1], :T[0]] = u
+    n_beta = pad.reshape(tc[1], b, tc[0], b).sum(axis=(1, 3))
+    rng = np.random.default_rng(7)
+    nb = np.broadcast_to(n_beta, (nf,) + n_beta.shape).astype(np.int32).copy()
+    mb = (rng.integers(0, p["n_facies"], size=nb.shape) * nb).astype(np.int32)
+    a_gpu, _ = cc.dwt(_t(ti), level)
+    S = cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, a_gpu, T, _t(nb), _t(mb)).cpu().numpy()
+    torch.cuda.synchronize()
+    a_orc, _ = orc.dwt(ti, level)
+    cand = [(p["ti"][a] - T[a]) // b + 1 for a in range(2)]
+    for f in range(nf):
+        want = orc.scores(a_orc, cand, nb[f], mb[f], b * b).ravel()
+        assert np.array_equal(S[f].astype(np.int64), want), f"filter {f}"
+
+
 def test_simulate_tile_groups(cc, orc):
     # steps wider than one tile: the scan's A operand spans the whole
     # template window and a workgroup takes 1, 2, 4 or 8 tiles, or the tuned
@@ -506,6 +563,25 @@ def test_wavelet53_scan_layouts(cc, orc):
         finally:
             cc.set_scan_group(0)
         assert np.array_equal(chosen, ochosen) and np.array_equal(out, oout), G
+
+
+def test_caches_stay_bounded_over_seeds(cc, orc):
+    # one plan and one graph per seed: the caches keep at most 16 plans and
+    # the graphs captured on them, and the last call still equals the oracle
+    p, ti, hd = wl.make("c1_plain2d", scale=0.3)
+    _say("cache bound", 40)
+    cc.release_caches()
+    import torch
+    ti_d = _t(ti)
+    for seed in range(40):
+        p["seed"] = 1000 + seed
+        sim = cc.Simulator(p)
+        out = sim.run(ti_d)
+        plans, graphs = cc.cache_counts()
+        assert plans <= 16 and graphs <= 16, (plans, graphs)
+    torch.cuda.synchronize()
+    oout, _ = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(out.cpu().numpy(), oout)
 
 
 def test_simulate_is_deterministic(cc):
