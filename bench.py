@@ -4,15 +4,23 @@
 
 One step is one ccwsim_simulate call: every patch of every realization of
 the workload goes through data-event extraction, the CCW scan over all
-candidates, top-K + draw, inverse DWT, boundary cut and paste.  Inputs (TI,
-hard data) are resident in HBM before the timed region.  Prints one JSON line.
+candidates, top-K + draw, inverse DWT, boundary cut and paste.  The default
+workload is the largest one-GPU configuration: 16 realizations of a 2000^2
+grid from a 1000^2 three-facies TI (T 48, OV 12, J 2, K 10), plain form.
+Inputs (TI, hard data) are resident in HBM before the timed region.  Prints
+one JSON line.
 
 The roofline object is measured live: after the timed region, the same K
-steps run again with the library's event profiler on (events bracket every
-kernel launch on the launch stream); the dominant kernel's algorithmic work
-per launch divided by its average launch time gives `achieved`.
+steps run again with the library's event profiler on (the scan and finalize
+launches carry start/stop events recorded by their own dispatch); the
+dominant kernel's algorithmic work per launch divided by its average launch
+time gives `achieved`.  Algorithmic work: the scan's contraction, 2 flops
+per (overlap block, candidate, patch); the finalize's bytes, 6 T^d per patch
+(the grid and pattern windows read, the coefficients read, the window
+written).
 The CPU baseline is the oracle, as it stands, on a bounded sample of the same
-workload (whole realizations, single thread).
+workload: one realization on one core, and the same realization in one
+process per host core at once.
 """
 from __future__ import annotations
 
@@ -36,7 +44,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2_scale2d")
+    ap.add_argument("--workload", default="c5_learned")
     ap.add_argument("--n-real", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
@@ -46,6 +54,8 @@ def parse():
                     help="skip dense conditioning, the level x grid-size sweep and the ensemble statistics")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
+    ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-procs", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (counter calibration)")
     return ap.parse_args()
@@ -75,30 +85,84 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(p, ti, hd, budget_s=12.0, max_reps=24):
-    """Oracle on whole realizations of the workload, single-threaded."""
+ORACLE_KEYS = ("ti", "grid", "tmpl", "overlap", "level", "top_k", "n_real", "n_facies", "seed", "path_mode",
+               "score_mode", "nc_margin", "cut")
+
+
+def _oracle_sample(workload, scale, n_real):
+    """Realization 0 of the workload through the oracle (one thread); returns
+    (seconds, cells).  Runs in a process that never touches the GPU."""
     from oracle import oracle as orc
-    orc.build_oracle(force=False)
-    keys = ("ti", "grid", "tmpl", "overlap", "level", "top_k", "n_real", "n_facies", "seed", "path_mode",
-            "score_mode", "nc_margin", "cut")
-    q = dict(p)
-    sample_real = 1
-    q["n_real"] = sample_real
+    from paper_2404_00441_amd import workloads as wl
+    p, ti, hd = wl.make(workload, scale=scale, n_real=n_real)
+    q = dict(p, n_real=1)
     if hd is not None:
         sel = hd[0] == 0
         hd = (hd[0][sel], hd[1][sel], hd[2][sel])
-    sp = orc.SimParams(**{k: q[k] for k in keys}, wavelet=q.get("wavelet", 0))
+    sp = orc.SimParams(**{k: q[k] for k in ORACLE_KEYS}, wavelet=q.get("wavelet", 0))
+    t0 = time.perf_counter()
+    orc.simulate(sp, ti, hd)
     cells = 1
     for n in p["grid"]:
         cells *= n
-    reps, t_total = 0, 0.0
-    while reps < max_reps and (reps == 0 or t_total < budget_s):
-        t0 = time.perf_counter()
-        orc.simulate(sp, ti, hd)
-        t_total += time.perf_counter() - t0
-        reps += 1
-    return {"value": cells * sample_real * reps / t_total, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} x realization 0 of the workload ({cells} cells each), {t_total:.1f} s"}
+    return time.perf_counter() - t0, cells
+
+
+def _host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_worker_main(workload, n_proc):
+    """Child process of cpu_baseline: the oracle on realization 0, first alone
+    (one core), then in n_proc processes at once (one per core)."""
+    import multiprocessing as mp
+    from oracle import oracle as orc
+    orc.build_oracle(force=False)
+    t1, cells = _oracle_sample(workload, 1.0, None)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(n_proc) as pool:
+        res = pool.starmap(_oracle_sample, [(workload, 1.0, None)] * n_proc)
+    tw = time.perf_counter() - t0
+    print(json.dumps({"t_single": t1, "cells": cells, "t_all": tw, "n_proc": n_proc,
+                      "t_each": [r[0] for r in res]}), flush=True)
+
+
+def cpu_baseline(workload, n_real):
+    """The oracle on realization 0 of the workload: one core, then one process
+    per host core (each simulating the same realization), in a child process
+    that never initialises the GPU.  cells/s counts the realization's cells
+    per process."""
+    import subprocess
+    n_proc = _host_cores()
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker", workload, "--oracle-procs", str(n_proc)]
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=HERE)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle worker failed: {r.stderr[-2000:]}")
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    cells = d["cells"]
+    single = cells / d["t_single"]
+    allc = cells * d["n_proc"] / d["t_all"]
+    return {"value": allc, "unit": "cells/s", "cores": d["n_proc"], "kind": "oracle",
+            "sample": f"realization 0 of the workload ({cells} cells) in {d['n_proc']} processes at once, "
+                      f"{d['t_all']:.1f} s wall; the workload has {n_real} realizations, each the same work",
+            "single_core": {"value": single, "unit": "cells/s", "cores": 1,
+                            "sample": f"realization 0 alone, {d['t_single']:.1f} s"},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "cores_used": d["n_proc"]}}
 
 
 def _time_runs(fn, reps):
@@ -390,6 +454,9 @@ def measure_forms(cc, wl, dev):
 
 def main():
     a = parse()
+    if a.oracle_worker:
+        oracle_worker_main(a.oracle_worker, a.oracle_procs)
+        return
     if a.calibrate_copy:
         calibrate_copy(a.calibrate_copy)
         return
@@ -455,9 +522,13 @@ def main():
         res["kernels"] = kern
         dom = max(prof, key=lambda k: prof[k][0])
         # algorithmic work of each kind per step
+        tcells = 1
+        for t in p["tmpl"]:
+            tcells *= t
         per_step_work = {
             "scan": ("mfma", stats["scan_flops"], "TFLOP/s", PEAK_FP16_TFLOPS, 1e12),
-            "finalize": ("hbm", stats["fin_bytes"], "GB/s", PEAK_HBM_GBS, 1e9),
+            # 6 T^d bytes per patch: windows read, coefficients read, window written
+            "finalize": ("hbm", 6.0 * tcells * stats["patches"], "GB/s", PEAK_HBM_GBS, 1e9),
         }
         kind = dom if dom in per_step_work else "scan"
         bound, work, unit, peak, scale = per_step_work[kind]
@@ -475,8 +546,21 @@ def main():
                 traffic = None
         res["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                            "frac": achieved / peak, "traffic": traffic, "kernel": kind,
-                           "dominant_by_time": dom, "us_per_launch": us}
+                           "dominant_by_time": dom, "us_per_launch": us,
+                           "work_per_launch": work / launches}
+        # the other per-step kernel against its own roofline
+        other = "finalize" if kind == "scan" else "scan"
+        if prof.get(other, (0, 0))[1]:
+            b2, w2, u2, pk2, sc2 = per_step_work[other]
+            us2 = kern[other]["us_per_launch"]
+            a2 = (w2 / (prof[other][1] / a.steps)) / (us2 * 1e-6) / sc2
+            res["roofline_other"] = {"kernel": other, "bound": b2, "achieved": a2, "peak": pk2, "unit": u2,
+                                     "frac": a2 / pk2, "us_per_launch": us2}
 
+    if a.workload != "c2_scale2d" and not a.no_next:
+        # the one-realization workload (1000^2, 300 hard data) beside the headline
+        p2, ti2, hd2 = wl.make("c2_scale2d")
+        res["c2_scale2d"] = dict(_time_case(cc, p2, ti2, hd2, dev, reps=10), workload=wl.describe(p2))
     if not a.no_forms:
         res["forms"] = measure_forms(cc, wl, dev)
         res["scan_kernel"] = measure_scan_kernel(cc, wl, dev)
@@ -485,7 +569,7 @@ def main():
         res["stats"] = measure_stats(cc, wl, dev)
 
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(p, ti, hd)
+        res["cpu_baseline"] = cpu_baseline(a.workload, p["n_real"])
     print(json.dumps(res), flush=True)
 
 

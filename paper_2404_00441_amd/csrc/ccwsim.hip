@@ -343,6 +343,23 @@ void launch_scan(int precision, int V, unsigned rows, int ngroups, size_t lds, h
 #undef CCW_SCAN
 }
 
+// Launch the fused-selection scan over `ntiles` tiles of 32 filters.
+void launch_scan_sel(int precision, bool hd, int en, unsigned rows, int ntiles, size_t lds, hipStream_t st,
+                     const ScanArgs& sa, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  const dim3 grid(rows, (unsigned)ntiles), block(kThreads);
+  const uint32_t sh = (uint32_t)lds;
+#define CCW_SEL(OT)                                                                                       \
+  do {                                                                                                    \
+    if (hd) hipExtLaunchKernelGGL((k_scan_sel<OT, true, kEnStage>), grid, block, sh, st, e0, e1, 0, sa);    \
+    else if (en == kEnFold) hipExtLaunchKernelGGL((k_scan_sel<OT, false, kEnFold>), grid, block, sh, st, e0, e1, 0, sa); \
+    else if (en == kEnMem) hipExtLaunchKernelGGL((k_scan_sel<OT, false, kEnMem>), grid, block, sh, st, e0, e1, 0, sa);   \
+    else hipExtLaunchKernelGGL((k_scan_sel<OT, false, kEnStage>), grid, block, sh, st, e0, e1, 0, sa);  \
+  } while (0)
+  if (precision == 1) CCW_SEL(__bf16);
+  else CCW_SEL(_Float16);
+#undef CCW_SEL
+}
+
 int scan_strip_width(const Geom& g) {
   return ((g.cand[0] + 31) / 32) * 32 + g.tc[0] - 1 + 1;  // +1 keeps an even length
 }
@@ -562,6 +579,10 @@ struct Plan {
   bool rows_ok = false;               // the row-minima selection fits this plan
   bool ev_delta = false;              // additive Haar data events (see k_event_init)
   bool sel_rows = false;              // row-minima selection chosen (tuned)
+  bool sel_fused_ok = false;          // the scan may select per row itself (k_scan_sel)
+  bool sel_fused = false;             // fused selection chosen (tuned)
+  int sel_ng_shift = 0, sel_n_bm = 1; // k_scan_sel: group size 2^shift of a lane's values; band masks
+  size_t sel_lds_nohd = 0, sel_lds_hd = 0;
   bool tuned = false;
   int max_slots = 0, nsteps_raster = 0;
   long long patches = 0, or_blocks = 0, band_cells = 0, succ_links = 0;
@@ -582,7 +603,7 @@ struct Plan {
   // workspace carve-up (bytes from the workspace base)
   long long ws_kh = 0, ws_ki = 0, ws_det = 0, ws_tmp = 0, ws_energy = 0, ws_tbl = 0, ws_sg = 0,
             ws_hdmap = 0, ws_mbuf = 0, ws_predcnt = 0, ws_report = 0, ws_hdoff = 0, ws_hdent = 0, ws_keys = 0, ws_rowmin = 0,
-            ws_hdmask = 0, ws_hdbits = 0, ws_lift = 0,
+            ws_hdmask = 0, ws_hdbits = 0, ws_lift = 0, ws_rowcnt = 0,
             ws_total = 0;
   size_t scan_lds = 0, fin_lds = 0;
   long long buf_cells = 0, cand_cap = 0, coef_lds = 0;
@@ -994,6 +1015,36 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     P.rows_ok = rows_try && P.learn_kbr >= 1;
   }
   if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
+  // Selection fused into the scan (k_scan_sel): a lane's values fall into
+  // groups of 2^shift; the largest groups that still give every patch at
+  // least ksel groups holding a candidate.
+  {
+    const int nchunks = (g.cand[0] + 31) / 32;
+    const int nwv = std::min(kThreads / 64, nchunks);
+    P.sel_ng_shift = 0;
+    for (int sh = 4; sh >= 0; --sh) {
+      int valid = 0;
+      for (int w = 0; w < nwv; ++w)
+        for (int hh = 0; hh < 2; ++hh)
+          for (int gi = 0; gi < (16 >> sh); ++gi) {
+            bool any = false;
+            for (int ch = w; ch < nchunks && !any; ch += kThreads / 64)
+              for (int v = gi << sh; v < ((gi + 1) << sh) && !any; ++v)
+                any = ch * 32 + 8 * (v >> 2) + 4 * hh + (v & 3) < g.cand[0];
+            valid += any ? 1 : 0;
+          }
+      if (valid >= ksel) {
+        P.sel_ng_shift = sh;
+        break;
+      }
+    }
+    P.sel_n_bm = 1 << nd;
+    const int nr = g.tc[1] * g.tc[2];
+    P.sel_lds_nohd = scan_sel_lds(nr, P.W, P.kpad, kEnStage, P.sel_n_bm, nchunks * 32, P.sel_ng_shift, false);
+    P.sel_lds_hd = scan_sel_lds(nr, P.W, P.kpad, kEnStage, P.sel_n_bm, nchunks * 32, P.sel_ng_shift, true);
+    P.sel_fused_ok = !P.learn && g.cand[0] <= 4096 && P.cand_cap > 0 &&
+                     std::max(P.sel_lds_nohd, P.sel_lds_hd) <= 64 * 1024 && !(p.max_hard_data > 0 && p.hd_direct);
+  }
   // additive data events: the Haar block sums of a successor's overlap
   // change by what each predecessor's paste changes there; the sums of one
   // group of successors live in the inverse-DWT buffers, free by then
@@ -1056,6 +1107,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
       P.hdm = true;
     }
   }
+  if (p.max_hard_data > 0 && !P.hdm) P.sel_fused_ok = false;   // its mismatches come from the bit table
+  P.sel_fused = P.sel_fused_ok;   // before tuning
 
   // workspace
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
@@ -1083,6 +1136,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   }
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
   P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
+  P.ws_rowcnt = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 4);
   if (P.learn) {
     const long long n = g.tcells;
     P.ws_pca_part = o;  o += align256((long long)kPcaParts * (n * n + n) * 4);
@@ -1459,6 +1513,7 @@ struct FinArgs {
   int score_mode;
   const uint64_t* keys;
   const uint64_t* rowmin;
+  const int32_t* rowcnt;          // fused selection: keys at the start of each row's segment, else null
   const int32_t* Ki;
   const int32_t* det;
   const int32_t* tree;  // block-subtree coefficients (tree path)
@@ -1657,7 +1712,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   // the row minima depend on the slot only: fetch them with the record
   const int nrows_c = g.cand[1] * g.cand[2];
   uint64_t rm_pre = ~0ull;
-  if ((a.cand_cap > 0 || a.rescore_rows) && tid < nrows_c) rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
+  int rc_pre = 0;
+  if ((a.cand_cap > 0 || a.rescore_rows) && tid < nrows_c) {
+    rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
+    if (a.rowcnt) rc_pre = a.rowcnt[(long long)slot * nrows_c + tid];
+  }
+  // keys per candidate row (fused selection: the row's survivors)
+  constexpr int kRcLds = 512;
+  __shared__ int s_rc[kRcLds];
+  if (a.rowcnt && tid < nrows_c && tid < kRcLds) s_rc[tid] = rc_pre;
   const long long wpad = (g.wcells + 15) & ~15ll;
   int32_t* bufA = (int32_t*)smem;
   int32_t* bufB = bufA + a.buf_cells;
@@ -1912,7 +1975,12 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
       for (int q = 0; q < U; ++q) {
         const int i = base + q * kThreads;
         v[q] = ~0ull;
-        if (i < nc) v[q] = kf[(long long)s_rows[w.y] * cx + w.x];
+        if (i < nc) {
+          const int rr = s_rows[w.y];
+          const int n_in_row =
+              !a.rowcnt ? cx : rr < kRcLds ? s_rc[rr] : a.rowcnt[(long long)slot * nrows + rr];
+          if (w.x < n_in_row) v[q] = kf[(long long)rr * cx + w.x];
+        }
         w.next();
       }
 #pragma unroll
@@ -2443,8 +2511,14 @@ int scan_group_of(const Plan* P) {
   return G >= 8 ? 8 : G >= 4 ? 4 : G >= 2 ? 2 : 1;
 }
 int group_index(int V) { return V == 8 ? 3 : V == 4 ? 2 : V == 2 ? 1 : 0; }   // filter-major: single tiles
+bool sel_fused_of(const Plan* P) {
+  if (!P->sel_fused_ok) return false;
+  if (g_sel_force != 0) return g_sel_force == 3;
+  if (g_scan_g_force != 0) return false;   // a forced scan layout runs with stored keys
+  return P->sel_fused;
+}
 bool sel_rows_of(const Plan* P) {
-  if (!P->rows_ok) return false;
+  if (!P->rows_ok || sel_fused_of(P)) return false;
   return g_sel_force != 0 ? g_sel_force == 2 : P->sel_rows;
 }
 
@@ -2470,6 +2544,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   HdBits* hd_bits = P->hdm ? (HdBits*)(ws + P->ws_hdbits) : nullptr;
   uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
   uint64_t* rowmin = (uint64_t*)(ws + P->ws_rowmin);
+  int32_t* rowcnt = (int32_t*)(ws + P->ws_rowcnt);
+  const bool fused = sel_fused_of(P);
   const int32_t* kbeta = (const int32_t*)(tbl + P->off_kbeta);
   const int32_t* nbt = (const int32_t*)(tbl + P->off_nbt);
   const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
@@ -2599,11 +2675,16 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   sa.rowmin_only = !P->learn && sel_rows_of(P);
   sa.standalone = 0;
   sa.has_hd = n_hd > 0;
+  sa.rowcnt = rowcnt;
+  sa.ksel = std::min(p->shortlist > 0 ? p->shortlist : p->top_k, g.ncand);
+  sa.ng_shift = P->sel_ng_shift;
+  sa.n_bm = P->sel_n_bm;
 
   FinArgs fa = {};
   fa.g = g;
   fa.keys = keys;
   fa.rowmin = rowmin;
+  fa.rowcnt = fused ? rowcnt : nullptr;
   fa.filters_all = filters;
   fa.npred = npred;
   fa.succ_off = succ_off;
@@ -2685,6 +2766,10 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       xa.fbegin = s.fbegin;
       ProfScope ps(CCWSIM_KIND_SCAN, st);
       k_proxy<<<dim3(rows, (unsigned)s.tcount), kThreads, P->proxy_lds, st>>>(xa);
+    } else if (fused) {
+      ProfKernel pk(CCWSIM_KIND_SCAN);
+      launch_scan_sel(p->precision, n_hd > 0, kEnStage, rows, s.tcount, n_hd > 0 ? P->sel_lds_hd : P->sel_lds_nohd,
+                      st, sa, pk.a, pk.b);
     } else {
       ProfKernel pk(CCWSIM_KIND_SCAN);
       launch_scan(p->precision, G, rows, s.gcount[gix], scan_lds, st, sa, pk.a, pk.b);
@@ -2768,8 +2853,10 @@ void tune_load_once() {
   char line[512], key[400];
   int v = 0;
   while (fgets(line, sizeof line, fp))
-    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2 && (v == -1 || v == 1 || v == 2 || v == 4 || v == 8))
-      g_tune[key] = v;
+    if (sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2) {
+      const int b = v > 150 ? v - 200 : v > 50 ? v - 100 : v;
+      if (b == -1 || b == 1 || b == 2 || b == 4 || b == 8) g_tune[key] = v;
+    }
   fclose(fp);
 }
 
@@ -2810,8 +2897,9 @@ extern "C" int ccwsim_set_scan_group(int g) {
 }
 
 extern "C" int ccwsim_set_selection(int mode) {
-  if (mode < 0 || mode > 2)
-    return fail(CCWSIM_ERR_INVALID_ARG, "selection must be 0 (tuned), 1 (stored keys) or 2 (row minima)");
+  if (mode < 0 || mode > 3)
+    return fail(CCWSIM_ERR_INVALID_ARG,
+                "selection must be 0 (tuned), 1 (stored keys), 2 (row minima) or 3 (fused into the scan)");
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     drop_graphs();   // captured graphs hold the previous choice
@@ -2850,9 +2938,12 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
     const std::string tk = tune_key(P, p);
     const auto it = g_tune.find(tk);
     if (it != g_tune.end()) {
-      // stored as the tiles per workgroup, plus 100 for the row-minima selection
-      P->sel_rows = it->second > 50 && P->rows_ok;
-      P->scan_g = it->second > 50 ? it->second - 100 : it->second;
+      // stored as the tiles per workgroup, plus 100 for the row-minima
+      // selection, plus 200 for the selection fused into the scan
+      const int v = it->second;
+      P->sel_fused = v > 150 && P->sel_fused_ok;
+      P->sel_rows = v > 50 && v < 150 && P->rows_ok;
+      P->scan_g = v > 150 ? v - 200 : v > 50 ? v - 100 : v;
       P->tuned = true;
     } else {
       hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
@@ -2866,10 +2957,11 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
         HIP_TRY(hipEventCreate(&e1));
         float best_ms = 3.4e38f;
         int best = 1, rc = CCWSIM_OK;
-        bool best_rows = false;
-        auto try_variant = [&](int c, bool rows) {
+        bool best_rows = false, best_fused = false;
+        auto try_variant = [&](int c, bool rows, bool fusedv = false) {
           P->scan_g = c;
           P->sel_rows = rows;
+          P->sel_fused = fusedv;
           HIP_TRY(hipEventRecord(e0, st));
           rc = enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, st);
           if (rc != CCWSIM_OK) return rc;
@@ -2881,27 +2973,31 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
             best_ms = ms;
             best = c;
             best_rows = rows;
+            best_fused = fusedv;
           }
           return CCWSIM_OK;
         };
+        // the selection fused into the scan first (it writes the fewest keys)
+        if (P->sel_fused_ok) try_variant(1, false, true);
         // the scan's layout and tiles with stored keys, then the row-minima
         // selection (no stored keys, exact rescoring of the best rows) with
         // the best layout and with single tiles
         for (int c : {1, kScanFilterMajor, 2, 4, 8}) {
-          if (c > P->scan_g_max) break;
+          if (rc != CCWSIM_OK || c > P->scan_g_max) break;
           if (try_variant(c, false) != CCWSIM_OK) break;
         }
         if (rc == CCWSIM_OK && P->rows_ok) {
-          const int kb = best;
+          const int kb = best_fused ? 1 : best;
           if (try_variant(kb, true) == CCWSIM_OK && kb != 1) try_variant(1, true);
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         P->scan_g = best;
         P->sel_rows = best_rows;
+        P->sel_fused = best_fused;
         if (rc == CCWSIM_OK) {
           P->tuned = true;
-          g_tune[tk] = best + (best_rows ? 100 : 0);
+          g_tune[tk] = best + (best_fused ? 200 : best_rows ? 100 : 0);
           tune_save();
         }
         return rc;

@@ -108,6 +108,15 @@ struct ScanArgs {
   // entry arrives with the arguments instead of after them
   int n_ginline;
   int2 groups_inline[kScanGroupsInline];
+  // fused selection (k_scan_sel): per (patch, candidate row) only the
+  // candidates that can be among the row's ksel best keys are written
+  int32_t* rowcnt;             // [slot][candidate rows] keys written at the start of the row's segment
+  const int32_t* nbuf;         // standalone with the energy in the contraction: [filter][kKMax] known cells
+  const int32_t* fil_real;     // standalone: realization of each filter (tie-break key), or null
+  const int64_t* fil_step;     // standalone: raster step of each filter (tie-break key), or null
+  int ksel;                    // keys the selection keeps per row (K, or the shortlist)
+  int ng_shift;                // value v of a lane joins group v >> ng_shift of its lane
+  int n_bm;                    // band masks per orientation (energy rows per tile)
 };
 
 template <typename OT>
@@ -611,6 +620,413 @@ void k_scan_fm(ScanArgs a) {
   }
   __syncthreads();
   if (tid < t.count) a.rowmin[(long long)(t.first + tid) * (g.cand[1] * g.cand[2]) + row] = s_rowmin[tid];
+}
+
+// ---------------------------------------------------------------------------
+// Scan with the selection of the K best fused into it (Sec. 4.4: the K best
+// candidates of the score map; the map itself is never written).
+//
+// One workgroup takes one candidate row and one tile of 32 patches
+// (candidate-major MFMA layout: lane l holds patch l % 32 against 16
+// candidates of a 32-candidate chunk).  For every patch it writes only the
+// candidates that can be among the row's ksel best keys, at the start of the
+// row's key segment, with their count and the row's smallest key:
+//   1. Every score is formed and reduced to a selection value q, a
+//      non-decreasing function of the key without its tie-break field
+//      (q = S, or (mismatch, S) with hard data).  Each lane keeps the
+//      minima of q over groups of its values (disjoint sets of candidates);
+//      the ksel-th smallest of a patch's group minima, tau, bounds the q of
+//      its ksel-th best candidate from above: ksel candidates have q <= tau,
+//      and a candidate with q > tau has ksel keys below its own.
+//   2. Candidates with q <= tau (the survivors) get their full key (with the
+//      keyed tie-break) and are written out.  Survivors are collected per
+//      wavefront into an LDS queue with ballots, so the keys of a sparse
+//      set of survivors are built densely, 64 at a time.
+// A row's best keys are therefore among its survivors, and the K best keys
+// of a patch are among the survivors of the K rows with the smallest minima.
+//
+// Energy source EN: kEnStage -- the energy rows of the tile's orientation
+// (one per band mask) are staged in LDS; kEnFold -- the MFMA also contracts
+// K^2 against the known-cell counts n (a second accumulator, exact when
+// K^2 <= 2048 and sum n K^2 < 2^24); kEnMem -- per filter energy rows read
+// from memory (standalone).  HD: hard-data mismatch counts from the bit
+// table enter the key.
+// ---------------------------------------------------------------------------
+constexpr int kSelQueue = 512;   // survivor queue entries per wavefront
+enum { kEnStage = 0, kEnFold = 1, kEnMem = 2 };
+
+// LDS bytes of k_scan_sel.
+inline size_t scan_sel_lds(int nrows, int W, int kpad, int en, int n_bm, int cpad, int ng_shift, bool hd) {
+  size_t o = ((size_t)nrows * W * 2 * (en == kEnFold ? 2 : 1) + 15) & ~(size_t)15;
+  const int kk = en == kEnFold ? 2 * kpad : kpad;
+  o += (size_t)kpad * 4;
+  o += (size_t)kFiltersPerTile * (kk + 8) * 2;
+  o += (size_t)kFiltersPerTile * sizeof(ScanRec);
+  if (en == kEnStage) o += (size_t)n_bm * cpad * 4;
+  const int nwv = std::min(kThreads / 64, cpad / 32);
+  o += (size_t)kFiltersPerTile * (nwv * 2 * (16 >> ng_shift)) * (hd ? 8 : 4);
+  o += (size_t)(kThreads / 64) * kSelQueue * 8;
+  return o;
+}
+
+template <bool HD> struct SelVal;
+template <> struct SelVal<false> {
+  typedef int32_t T;
+  static __device__ __forceinline__ T inf() { return 0x7FFFFFFF; }
+  static __device__ __forceinline__ T make(uint32_t, int32_t S) { return S; }
+  static __device__ __forceinline__ int32_t score(T q) { return q; }
+  static __device__ __forceinline__ uint32_t mis(T) { return 0u; }
+};
+template <> struct SelVal<true> {
+  typedef uint64_t T;
+  static __device__ __forceinline__ T inf() { return ~0ull; }
+  static __device__ __forceinline__ T make(uint32_t m, int32_t S) {
+    return ((uint64_t)(m > 4095u ? 4095u : m) << 32) | (uint64_t)((uint32_t)S ^ 0x80000000u);
+  }
+  static __device__ __forceinline__ int32_t score(T q) { return (int32_t)((uint32_t)q ^ 0x80000000u); }
+  static __device__ __forceinline__ uint32_t mis(T q) { return (uint32_t)(q >> 32); }
+};
+
+template <typename OT, bool HD, int EN>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HD ? 2 : 4)))
+void k_scan_sel(ScanArgs a) {
+  typedef typename MfmaOp<OT>::vec8 vec8;
+  typedef SelVal<HD> SV;
+  typedef typename SV::T qt;
+  const OT* Kop = (const OT*)a.Kop;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Geom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = blockIdx.x;
+  const int cy = row % g.cand[1], cz = row / g.cand[1];
+  const int W = a.W, kpad = a.kpad;
+  const int nrows = g.tc[1] * g.tc[2];
+  const int j = lane & 31, h = lane >> 5;
+  const int g8 = h * 8;
+  const int C0 = g.cand[0];
+  const int nchunks = (C0 + 31) / 32;
+  const int cpad = nchunks * 32;
+  const int kk = EN == kEnFold ? 2 * kpad : kpad;
+  const int bstride = kk + 8;
+  const int ng_shift = a.ng_shift;
+  const int NG = 16 >> ng_shift;
+  const int nwv = min(kThreads / 64, nchunks);   // wavefronts holding chunks
+  const int G8 = nwv * 2 * NG;                   // groups per patch
+
+  const int strip_n = nrows * W;
+  OT* s_strip = (OT*)smem;
+  size_t o = ((size_t)strip_n * 2 * (EN == kEnFold ? 2 : 1) + 15) & ~(size_t)15;
+  int* s_off = (int*)(smem + o);
+  o += (size_t)kpad * 4;
+  OT* s_B = (OT*)(smem + o);
+  o += (size_t)kFiltersPerTile * bstride * 2;
+  ScanRec* s_rec = (ScanRec*)(smem + o);
+  o += (size_t)kFiltersPerTile * sizeof(ScanRec);
+  int32_t* s_E = (int32_t*)(smem + o);
+  if (EN == kEnStage) o += (size_t)a.n_bm * cpad * 4;
+  qt* s_gm = (qt*)(smem + o);
+  o += (size_t)kFiltersPerTile * G8 * sizeof(qt);
+  uint2* s_q = (uint2*)(smem + o) + wave * kSelQueue;
+  __shared__ unsigned s_cnt[kFiltersPerTile];
+  __shared__ unsigned long long s_rmin[kFiltersPerTile];
+  __shared__ qt s_tau[kFiltersPerTile];
+
+  TileDev t;
+  if (a.standalone) {
+    t.first = blockIdx.y * kFiltersPerTile;
+    t.count = min(kFiltersPerTile, a.n_filters - t.first);
+    t.orient = 0;
+    t.zmask = 0;
+  } else {
+    t = a.tiles[blockIdx.y];
+  }
+  ScanRec rec = {};
+  if (a.standalone) {
+    rec.gidx = j < t.count ? 0 : -1;
+    if (j < t.count && a.fil_real)
+      rec.tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)a.fil_real[t.first + j], (uint64_t)a.fil_step[t.first + j]);
+  } else {
+    rec = a.recs[blockIdx.y * kFiltersPerTile + j];
+  }
+  if (tid < kFiltersPerTile) {
+    s_rec[tid] = rec;
+    s_cnt[tid] = 0;
+    s_rmin[tid] = ~0ull;
+  }
+  const long long rowbase = (long long)C0 * row;
+  // K-grid strip (and its squares): every load of a thread before any store
+  {
+    constexpr int U = 8;
+    BoxWalk w(tid, kThreads, W, g.tc[1]);
+    for (int base = tid; base < strip_n; base += kThreads * U) {
+      OT v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        v[q] = (OT)0.0f;
+        if (i < strip_n && w.x < g.G[0]) v[q] = Kop[idx3i(w.x, cy + w.y, cz + w.z, g.G)];
+        w.next();
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = base + q * kThreads;
+        if (i < strip_n) {
+          s_strip[i] = v[q];
+          if (EN == kEnFold) {
+            const float f = (float)v[q];
+            s_strip[strip_n + i] = (OT)(f * f);
+          }
+        }
+      }
+    }
+  }
+  for (int k = tid; k < kpad; k += kThreads) {
+    int beta;
+    if (a.standalone) beta = k < (int)g.tcells ? k : -1;
+    else beta = a.kbeta[t.orient * kKMax + k];
+    int off = 0;
+    if (beta >= 0) {
+      const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
+      off = (bz * g.tc[1] + by) * W + bx;
+    }
+    s_off[k] = off;
+  }
+  // data events (and, folded, the known-cell counts) as the B operand
+  typedef int32_t int8v_t __attribute__((ext_vector_type(8)));
+  const int k8n = kk / 8, k8m = kpad / 8;
+  for (int i = tid; i < kFiltersPerTile * k8n; i += kThreads) {
+    const int jj = i / k8n, k8i = i - jj * k8n;
+    const bool second = k8i >= k8m;
+    const int k8 = (second ? k8i - k8m : k8i) * 8;
+    int8v_t m = {};
+    if (jj < t.count && !((t.zmask >> jj) & 1u)) {
+      const int32_t* src = second ? a.nbuf : a.mbuf;
+      m = *(const int8v_t*)(src + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
+    }
+    vec8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
+    *(vec8*)(s_B + jj * bstride + k8i * 8) = v;
+  }
+  // energy rows of the tile's orientation, one per band mask
+  if (EN == kEnStage && a.score_mode == 0) {
+    const int nb = a.n_bm;
+    for (int i = tid; i < nb * cpad; i += kThreads) {
+      const int bm = i / cpad, cx = i - bm * cpad;
+      s_E[i] = cx < C0 ? a.energy[(long long)((t.orient * nb) | bm) * g.ncand + rowbase + cx] : 0;
+    }
+  }
+  __syncthreads();
+
+  const bool fvalid = rec.gidx >= 0;
+  const int shift = g.shift;
+  const int J = g.level, Jz = g.ndim == 3 ? J : 0;
+  const int bm_j = EN == kEnStage ? (rec.shape & (a.n_bm - 1)) : 0;
+  const int32_t* erow = EN == kEnMem ? a.energy + (long long)(t.first + j) * g.ncand + rowbase : nullptr;
+  const OT* brow = s_B + j * bstride + g8;
+
+  // selection values of one 32-candidate chunk (invalid entries: infinity)
+  auto chunk_values = [&](int ch, qt (&q)[16]) {
+    int ev[16];
+    unsigned mis[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      ev[v] = 0;
+      mis[v] = 0;
+    }
+    if (a.score_mode == 0 && EN != kEnFold) {
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        const int cx0 = ch * 32 + 8 * qd + 4 * h;
+        int4 e4;
+        if (EN == kEnStage) {
+          e4 = *(const int4*)(s_E + bm_j * cpad + cx0);
+        } else {
+          e4.x = cx0 < C0 ? erow[cx0] : 0;
+          e4.y = cx0 + 1 < C0 ? erow[cx0 + 1] : 0;
+          e4.z = cx0 + 2 < C0 ? erow[cx0 + 2] : 0;
+          e4.w = cx0 + 3 < C0 ? erow[cx0 + 3] : 0;
+        }
+        ev[4 * qd] = e4.x;
+        ev[4 * qd + 1] = e4.y;
+        ev[4 * qd + 2] = e4.z;
+        ev[4 * qd + 3] = e4.w;
+      }
+    }
+    if (HD && fvalid && rec.nhd > 0) {
+      // bit table: per datum two words cover the chunk; byte counters (four
+      // candidates per register) take up to 255 data between flushes
+      const uint32_t* mb = a.hdm + ((cz << Jz) * a.hm.ry + (cy << J)) * a.hm.rs + ch;
+      const HdBits* hb = a.hd_bits + rec.hd0;
+      const int hs = 4 * h;
+      const int nhd = rec.nhd;
+      for (int h0 = 0; h0 < nhd; h0 += 255) {
+        const int hn = min(nhd, h0 + 255);
+        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (int hh = h0; hh < hn; hh += 4) {
+          HdBits b[4];
+          uint32_t lo[4], hi[4];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) b[qq] = hb[min(hh + qq, hn - 1)];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            lo[qq] = mb[b[qq].woff];
+            hi[qq] = mb[b[qq].woff + 1];
+          }
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const uint32_t w = hh + qq < hn ? __builtin_amdgcn_alignbit(hi[qq], lo[qq], (uint32_t)b[qq].sh) >> hs : 0u;
+            c0 += w & 0x01010101u;
+            c1 += (w >> 1) & 0x01010101u;
+            c2 += (w >> 2) & 0x01010101u;
+            c3 += (w >> 3) & 0x01010101u;
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const uint32_t c = (v & 3) == 0 ? c0 : (v & 3) == 1 ? c1 : (v & 3) == 2 ? c2 : c3;
+          mis[v] += (c >> (8 * (v >> 2))) & 0xFFu;
+        }
+      }
+    }
+    const int cbase = ch * 32 + j;
+    float16_t acc = {}, acc2 = {};
+    for (int kc = 0; kc < kpad; kc += 16) {
+      vec8 av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
+      acc = MfmaOp<OT>::mma(av, *(const vec8*)(brow + kc), acc);
+      if (EN == kEnFold) {
+        vec8 a2;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a2[e] = s_strip[strip_n + s_off[kc + g8 + e] + cbase];
+        acc2 = MfmaOp<OT>::mma(a2, *(const vec8*)(brow + kpad + kc), acc2);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int cx = ch * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+      const int C = (int)acc[v];
+      const int E = EN == kEnFold ? (int)acc2[v] : ev[v];
+      const int S = a.score_mode == 0 ? E - (C << shift) : -C;
+      q[v] = (fvalid && cx < C0) ? SV::make(mis[v], S) : SV::inf();
+    }
+  };
+
+  // pass 1: selection values, their group minima; the first two chunks of
+  // a wavefront stay in registers for pass 2
+  const int my_chunks = wave < nchunks ? (nchunks - 1 - wave) / (kThreads / 64) + 1 : 0;
+  qt qv0[16], qv1[16], vmin[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    vmin[v] = SV::inf();
+    qv0[v] = SV::inf();
+    qv1[v] = SV::inf();
+  }
+  for (int p = 0; p < my_chunks; ++p) {
+    qt q[16];
+    chunk_values(wave + (kThreads / 64) * p, q);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      vmin[v] = q[v] < vmin[v] ? q[v] : vmin[v];
+      if (p == 0) qv0[v] = q[v];
+      if (p == 1) qv1[v] = q[v];
+    }
+  }
+  // minima of groups of 2^ng_shift adjacent values
+  if (ng_shift >= 1) {
+#pragma unroll
+    for (int v = 0; v < 16; v += 2) vmin[v] = vmin[v + 1] < vmin[v] ? vmin[v + 1] : vmin[v];
+  }
+  if (ng_shift >= 2) {
+#pragma unroll
+    for (int v = 0; v < 16; v += 4) vmin[v] = vmin[v + 2] < vmin[v] ? vmin[v + 2] : vmin[v];
+  }
+  if (ng_shift >= 3) {
+#pragma unroll
+    for (int v = 0; v < 16; v += 8) vmin[v] = vmin[v + 4] < vmin[v] ? vmin[v + 4] : vmin[v];
+  }
+  if (ng_shift >= 4) vmin[0] = vmin[8] < vmin[0] ? vmin[8] : vmin[0];
+  if (wave < nwv) {
+    qt* gm = s_gm + j * G8 + (wave * 2 + h) * NG;
+    const int gmask = (1 << ng_shift) - 1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      if ((v & gmask) == 0) gm[v >> ng_shift] = vmin[v];
+  }
+  __syncthreads();
+  // tau of each patch: the ksel-th smallest of its group minima (ties by
+  // position)
+  for (int pi = tid; pi < kFiltersPerTile * G8; pi += kThreads) {
+    const int jj = pi / G8, i = pi - jj * G8;
+    const qt* gm = s_gm + jj * G8;
+    const qt x = gm[i];
+    int rank = 0;
+    for (int i2 = 0; i2 < G8; ++i2) {
+      const qt y = gm[i2];
+      rank += (y < x || (y == x && i2 < i)) ? 1 : 0;
+    }
+    if (rank == a.ksel - 1) s_tau[jj] = x;
+  }
+  __syncthreads();
+
+  // pass 2: survivors, their keys
+  const qt tau = s_tau[j];
+  int qn = 0;   // entries in this wavefront's queue (uniform)
+  auto flush = [&]() {
+    __builtin_amdgcn_wave_barrier();   // the queue entries other lanes wrote come first
+    for (int i = lane; i < qn; i += 64) {
+      const uint2 e = s_q[i];
+      const int jj = (int)((e.y >> 12) & 31u), cx = (int)(e.y & 4095u);
+      const uint32_t mm = e.y >> 20;
+      const long long idx = rowbase + cx;
+      const uint64_t key = make_key(mm, (int32_t)e.x, tie_perm((uint32_t)idx, s_rec[jj].tkey));
+      const unsigned pos = atomicAdd(&s_cnt[jj], 1u);
+      a.keys[(long long)(t.first + jj) * g.ncand + rowbase + pos] = key;
+      atomicMin(&s_rmin[jj], (unsigned long long)key);
+    }
+    __builtin_amdgcn_wave_barrier();
+    qn = 0;
+  };
+  const unsigned jbits = (unsigned)j << 12;
+  for (int p = 0; p < my_chunks; ++p) {
+    const int ch = wave + (kThreads / 64) * p;
+    qt q[16];
+    if (p == 0) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) q[v] = qv0[v];
+    } else if (p == 1) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) q[v] = qv1[v];
+    } else {
+      chunk_values(ch, q);
+    }
+#pragma unroll
+    for (int v4 = 0; v4 < 16; v4 += 4) {
+      if (qn > kSelQueue - 256) flush();
+#pragma unroll
+      for (int v = v4; v < v4 + 4; ++v) {
+        const bool sv = q[v] != SV::inf() && q[v] <= tau;
+        const uint64_t m = __ballot(sv);
+        if (m) {
+          if (sv) {
+            const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const int cx = ch * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            s_q[pos] = make_uint2((uint32_t)SV::score(q[v]), (uint32_t)cx | jbits | (SV::mis(q[v]) << 20));
+          }
+          qn += __builtin_popcountll(m);
+        }
+      }
+    }
+  }
+  flush();
+  __syncthreads();
+  if (tid < t.count && s_rec[tid].gidx >= 0) {
+    const long long o2 = (long long)(t.first + tid) * (g.cand[1] * g.cand[2]) + row;
+    a.rowcnt[o2] = (int32_t)s_cnt[tid];
+    a.rowmin[o2] = s_rmin[tid];
+  }
 }
 
 // Energy term E(c) = sum_beta n_beta K[c + beta]^2 for each shape (rows of

@@ -521,7 +521,97 @@ def test_row_minima_selection_dense(cc, orc, hd_direct):
 
 def test_selection_validation(cc):
     with pytest.raises(cc.CcwsimError):
-        cc.set_selection(3)
+        cc.set_selection(4)
+
+
+# --------------------------------------------------------------------------
+# Selection fused into the scan: per candidate row only the candidates that
+# can be among the row's K best keys are written
+# --------------------------------------------------------------------------
+def _compare_fused(cc, orc, p, ti, hd, n_cmp=None):
+    cc.set_selection(3)
+    try:
+        out, chosen = _run(cc, p, ti, hd)
+    finally:
+        cc.set_selection(0)
+    q = dict(p)
+    if n_cmp is not None:
+        q["n_real"] = n_cmp
+        if hd is not None:
+            sel = hd[0] < n_cmp
+            hd = (hd[0][sel], hd[1][sel], hd[2][sel])
+    oout, ochosen = orc.simulate(_sp(q, orc), ti, hd)
+    m = q["n_real"]
+    assert np.array_equal(chosen[:m], ochosen), f"first differing step {np.argwhere(chosen[:m] != ochosen)[:3]}"
+    assert np.array_equal(out[:m], oout)
+    return out
+
+
+@pytest.mark.parametrize("case", SIM_TINY, ids=[c[0] for c in SIM_TINY])
+def test_fused_selection_small(cc, orc, case):
+    name, over, nhd = case
+    _say("fused selection", name)
+    p, ti, hd = _tiny(over, nhd)
+    _compare_fused(cc, orc, p, ti, hd)
+
+
+@pytest.mark.parametrize("name,scale,nr", WORKLOAD_CASES + [("c2_scale2d", 1.0, None)],
+                         ids=[f"{c[0]}_s{c[1]}" for c in WORKLOAD_CASES] + ["c2_full"])
+def test_fused_selection_workloads(cc, orc, name, scale, nr):
+    _say("fused selection workload", name, scale, nr)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    _compare_fused(cc, orc, p, ti, hd)
+
+
+@pytest.mark.timeout(900)
+def test_fused_selection_c5_full(cc, orc):
+    # the headline configuration: 16 realizations of 2000^2 in one call,
+    # realizations 0 and 1 against the oracle
+    _say("fused selection c5 full")
+    p, ti, hd = wl.make("c5_learned")
+    _compare_fused(cc, orc, p, ti, hd, n_cmp=2)
+
+
+@pytest.mark.parametrize("n_hd", [4000, 8000])
+def test_fused_selection_dense(cc, orc, n_hd):
+    p, ti, hd = wl.dense_conditioning(n_hd, scale=0.3)
+    _say("fused selection dense", n_hd)
+    out = _compare_fused(cc, orc, p, ti, hd)
+    for r, pos, v in zip(*hd):
+        assert out[(r,) + tuple(pos[::-1])] == v
+
+
+@pytest.mark.parametrize("case", [("c3_split3d", 0.4, None, 32, 0), ("c3_split3d", 0.4, None, 32, 1),
+                                  ("c2_scale2d", 0.3, None, 16, 1), ("c4_batched", 0.5, 8, 10, 0)],
+                         ids=["c3_S32_fp16", "c3_S32_bf16", "c2_S16_bf16", "c4_S10_fp16"])
+def test_fused_selection_precision_split(cc, orc, case):
+    import torch
+    name, scale, nr, S, prec = case
+    _say("fused precision", case)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    p.update(shortlist=S, precision=prec)
+    cc.set_selection(3)
+    try:
+        sim = cc.Simulator(p)
+        out = sim.run(_t(ti), cc.hd_to_device(hd, len(p["ti"])))
+        torch.cuda.synchronize()
+        rep = sim.report()
+    finally:
+        cc.set_selection(0)
+    oout, _ = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(out.cpu().numpy(), oout)
+    assert rep["max_abs_error"] == 0 and rep["topk_changed"] == 0
+
+
+@pytest.mark.parametrize("case", [c for c in SIM_TINY if c[0] in ("partial_blocks_j2", "seeded_3d_j1",
+                                                                   "seeded_2d_j1_hd_batch")],
+                         ids=lambda c: c[0])
+def test_fused_selection_wavelet53(cc, orc, case):
+    name, over, nhd = case
+    _say("fused selection 5/3", name)
+    p, ti, hd = _tiny(over, nhd)
+    p["wavelet"] = 1
+    _compare_fused(cc, orc, p, ti, hd)
 
 
 # --------------------------------------------------------------------------
