@@ -191,6 +191,6 @@ def test_stats_validation_errors(lib):
 
 
 def test_selection_switch_validation(lib):
-    assert lib.ccwsim_set_selection(3) == 1
+    assert lib.ccwsim_set_selection(4) == 1
     assert lib.ccwsim_set_selection(-1) == 1
     assert lib.ccwsim_set_selection(0) == 0
