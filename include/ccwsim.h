@@ -142,7 +142,7 @@ int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int64_t* n_approx, int64_t* 
 int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t* approx,
                int32_t* details, void* stream);
 
-/* ---- A3/A4: CCW scan (Sec. 4.3, CCW equation) ------------------------------
+/* ---- A3/A4 (+A6): CCW scan (Sec. 4.3, CCW equation; Sec. 4.4 K best) ----
  * Scores every candidate of the TI approximation grid against n_filters
  * data events.  Candidates are coarse-aligned: candidate c = (cx, cy, cz)
  * has its fine window at 2^J * c, fully inside the TI, so there are
@@ -151,16 +151,37 @@ int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t* approx,
  * (T_c = ceil(T / 2^J) blocks per axis, x fastest): or_n = number of known
  * overlap cells in the block, or_m = sum of their codes (the level-J
  * approximation of the zero-filled overlap), int32 [n_filters][T_c cells].
- *   score_mode 0: S = sum n K^2 - 2 |beta| sum m K   (|beta| = 2^(J*ndim))
+ *   score_mode 0: S = sum n K^2 - 2^s sum m K   (s = 1 + J * ndim for Haar,
+ *                 s = 1 for LeGall 5/3, whose n is 0 or 1)
  *   score_mode 1: S = - sum m K
- * with K = approx[c + beta].  scores: int32 [n_filters][C cells].
- * The library allocates its temporaries with stream-ordered allocation.
- * Returns CCWSIM_ERR_UNSUPPORTED if the values could leave the range in
- * which fp16/fp32 MFMA arithmetic is exact (the bound uses max_code, the
- * largest code in the TI; 0 < max_code <= 126). */
-int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code, const int32_t* approx,
-                    const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
-                    int32_t n_filters, int32_t score_mode, int32_t* scores, void* stream);
+ * with K = approx[c + beta], the level-J approximation from ccwsim_dwt with
+ * the same wavelet (0 Haar, 1 LeGall 5/3).  Two outputs, either or both:
+ *   scores:    int32 [n_filters][C cells], the whole score map, or NULL;
+ *   topk_keys: uint64 [n_filters][K'] ascending, K' = min(top_k, C cells),
+ *              or NULL: the K best candidates of each filter under the key
+ *              (S + 2^31, pi(index)) of ccwsim_select (pi keyed by seed,
+ *              realization[f], step[f]; int32 / int64 [n_filters] device
+ *              arrays).  The selection is fused into the scan: per candidate
+ *              row only the candidates that can be among the row's K best
+ *              keys are kept, and the score map is never written.
+ *              1 <= top_k <= 16.
+ * precision: 0 fp16, 1 bf16 MFMA operands (fp32 accumulation).  The call
+ * returns CCWSIM_ERR_UNSUPPORTED if the values could leave the range in
+ * which that arithmetic is exact (the bound uses max_code, the largest code
+ * in the TI; 0 < max_code <= 126).
+ * workspace: device memory of at least ccwsim_ccf_scan_workspace_size(...)
+ * bytes (the same arguments; want_scores / want_keys say which outputs will
+ * be non-NULL), 256-byte aligned, owned by the caller; nothing is allocated.
+ * ccwsim_ccf_scan_workspace_size is a host call and returns -1 on invalid
+ * arguments (text in ccwsim_last_error). */
+int64_t ccwsim_ccf_scan_workspace_size(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code,
+                                       int32_t precision, const int32_t tmpl[3], int32_t n_filters,
+                                       int32_t score_mode, int32_t top_k, int32_t want_scores, int32_t want_keys);
+int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code, int32_t precision,
+                    const int32_t* approx, const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
+                    int32_t n_filters, int32_t score_mode, int32_t* scores, int32_t top_k, uint64_t seed,
+                    const int32_t* realization, const int64_t* step, uint64_t* topk_keys, void* workspace,
+                    int64_t workspace_bytes, void* stream);
 
 /* ---- A6: top-K and draw (Sec. 4.4; Algorithm 1, K best and random draw) ---
  * For each filter f, candidates are ordered by the key
@@ -308,9 +329,17 @@ int ccwsim_set_scan_group(int g);
  * best are certified (at most K rows); the scan then stores 8 bytes per
  * candidate row instead of per candidate.  Both give the same results.  The
  * row minima need score_mode 0, no shortlist and at most 512 candidate rows
- * (else the stored keys are used).  0 (the default) lets the tuner of
- * ccwsim_set_scan_group choose on the first call of a parameter set; 1 and 2
- * force stored keys or row minima (for tests).  Drops captured graphs.
+ * (else the stored keys are used).  Fused (3): the scan keeps, per
+ * candidate row, only the candidates that can be among the row's K best
+ * keys (a threshold from minima over disjoint groups of the row's
+ * candidates bounds the K-th best from above) and writes their keys, their
+ * count and the row minimum; the finalize step reads the survivors of the K
+ * rows with the smallest minima.  It needs at most 4096 candidates per row,
+ * the hard-data bit table when there are hard data, and no proposer.
+ * 0 (the default) lets the tuner of ccwsim_set_scan_group choose on the
+ * first call of a parameter set (the fused selection is tried first and is
+ * used before tuning); 1, 2 and 3 force stored keys, row minima or the fused
+ * selection (for tests).  Drops captured graphs.
  * Returns CCWSIM_ERR_INVALID_ARG for other values. */
 int ccwsim_set_selection(int mode);
 

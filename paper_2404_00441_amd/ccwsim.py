@@ -65,8 +65,10 @@ def load():
     L.ccwsim_dwt_sizes.argtypes = [Shape, i32, p, p]
     L.ccwsim_dwt.restype = ctypes.c_int
     L.ccwsim_dwt.argtypes = [p, Shape, i32, p, p, p]
+    L.ccwsim_ccf_scan_workspace_size.restype = i64
+    L.ccwsim_ccf_scan_workspace_size.argtypes = [Shape, i32, i32, i32, i32, p, i32, i32, i32, i32, i32]
     L.ccwsim_ccf_scan.restype = ctypes.c_int
-    L.ccwsim_ccf_scan.argtypes = [Shape, i32, i32, p, p, p, p, i32, i32, p, p]
+    L.ccwsim_ccf_scan.argtypes = [Shape, i32, i32, i32, i32, p, p, p, p, i32, i32, p, i32, u64, p, p, p, p, i64, p]
     L.ccwsim_select.restype = ctypes.c_int
     L.ccwsim_select.argtypes = [p, p, i64, i32, i32, u64, p, p, p, p, p]
     L.ccwsim_idwt.restype = ctypes.c_int
@@ -106,7 +108,7 @@ def load():
 
 
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
-           "ccwsim_ccf_scan", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
+           "ccwsim_ccf_scan", "ccwsim_ccf_scan_workspace_size", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
@@ -201,21 +203,54 @@ def dwt(x: torch.Tensor, level: int):
     return approx, details[:nd]
 
 
-def ccf_scan(ti_extent, level, max_code, approx, tmpl, or_n, or_m, score_mode=0):
-    """or_n, or_m: int32 [n_filters, *T_c numpy order].  Returns int32
-    scores [n_filters, n_cand]."""
+def _aligned_workspace(nbytes, device):
+    """Caller-owned workspace, 256-byte aligned."""
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf[off:]
+
+
+def ccf_scan_workspace_size(ti_extent, level, max_code, tmpl, n_filters, score_mode=0, precision=0, wavelet=0,
+                            top_k=0, want_scores=True, want_keys=False):
+    v = load().ccwsim_ccf_scan_workspace_size(shape_of(ti_extent), level, wavelet, max_code, precision,
+                                              _i3(tmpl, 1), n_filters, score_mode, top_k, int(want_scores),
+                                              int(want_keys))
+    if v < 0:
+        raise CcwsimError("ccwsim_ccf_scan_workspace_size", 1, load().ccwsim_last_error().decode())
+    return int(v)
+
+
+def ccf_scan(ti_extent, level, max_code, approx, tmpl, or_n, or_m, score_mode=0, precision=0, wavelet=0,
+             top_k=None, seed=0, realization=None, step=None, want_scores=None):
+    """or_n, or_m: int32 [n_filters, *T_c numpy order].  Without top_k:
+    returns int32 scores [n_filters, n_cand].  With top_k: the selection is
+    fused into the scan and (scores or None, keys uint64-as-int64
+    [n_filters, min(top_k, n_cand)]) is returned; realization int32 [F] and
+    step int64 [F] key the tie-break; the score map is written only when
+    want_scores is true."""
     nf = or_m.shape[0]
     b = 2 ** level
     cand = [(ti_extent[a] - tmpl[a]) // b + 1 for a in range(len(ti_extent))]
     ncand = 1
     for c in cand:
         ncand *= c
-    scores = torch.empty((nf, ncand), dtype=torch.int32, device=approx.device)
+    fused = top_k is not None
+    if want_scores is None:
+        want_scores = not fused
+    scores = torch.empty((nf, ncand), dtype=torch.int32, device=approx.device) if want_scores else None
+    keys = torch.empty((nf, min(top_k, ncand)), dtype=torch.int64, device=approx.device) if fused else None
+    ws_bytes = ccf_scan_workspace_size(ti_extent, level, max_code, tmpl, nf, score_mode, precision, wavelet,
+                                       top_k or 0, want_scores, fused)
+    _, ws = _aligned_workspace(ws_bytes, approx.device)
     t3 = _i3(tmpl, 1)
-    _check("ccwsim_ccf_scan", load().ccwsim_ccf_scan(shape_of(ti_extent), level, max_code, _ptr(approx), t3,
-                                                     _ptr(or_n) if or_n is not None else None, _ptr(or_m), nf,
-                                                     score_mode, _ptr(scores), _stream()))
-    return scores
+    _check("ccwsim_ccf_scan", load().ccwsim_ccf_scan(shape_of(ti_extent), level, wavelet, max_code, precision,
+                                                     _ptr(approx), t3, _ptr(or_n) if or_n is not None else None,
+                                                     _ptr(or_m), nf, score_mode, _ptr(scores), top_k or 0, seed,
+                                                     _ptr(realization), _ptr(step), _ptr(keys), _ptr(ws),
+                                                     ws_bytes, _stream()))
+    if not fused:
+        return scores
+    return scores, keys
 
 
 def select(scores, mismatch, top_k, seed, realization, step, want_keys=False):

@@ -157,6 +157,29 @@ int check_exact(const Geom& g, long long maxc, long long ovcells) {
   return CCWSIM_OK;
 }
 
+// Groups per lane of the fused-selection scan: the fewest (2^gbits) that give
+// every patch at least ksel groups holding a candidate (each such group's
+// minimum is a distinct candidate, so the ksel-th smallest bounds the
+// ksel-th best).  Lane (wave w, half h) holds, for value v of chunk ch (ch = w
+// mod 4), candidate 32 ch + 8 (v / 4) + 4 h + v % 4; its group is v mod 2^gbits.
+int sel_group_bits(int C0, int nchunks, int ksel) {
+  const int nwv = std::min(kThreads / 64, nchunks);
+  for (int gb = 0; gb <= 4; ++gb) {
+    const int NG = 1 << gb;
+    int valid = 0;
+    for (int w = 0; w < nwv; ++w)
+      for (int hh = 0; hh < 2; ++hh)
+        for (int gi = 0; gi < NG; ++gi) {
+          bool any = false;
+          for (int ch = w; ch < nchunks && !any; ch += kThreads / 64)
+            for (int v = gi; v < 16 && !any; v += NG) any = ch * 32 + 8 * (v >> 2) + 4 * hh + (v & 3) < C0;
+          valid += any ? 1 : 0;
+        }
+    if (valid >= ksel) return gb;
+  }
+  return 4;   // fewer candidates than ksel in a row: every candidate survives
+}
+
 // ---- launch profiler (events around each kernel launch) -------------------
 struct ProfRec {
   int kind;
@@ -321,6 +344,21 @@ __global__ void k_events_to_mbuf(const int32_t* __restrict__ or_m, int32_t* __re
   mbuf[id] = k < tcells ? or_m[f * tcells + k] : 0;
 }
 
+// Standalone data events in the fused scan's tap order: tap t of a filter
+// is block (row t / (8 spr), x t % (8 spr)) of the template window, spr =
+// ceil(T_c,x / 8) segments of 8 blocks per block row; taps past the row are 0.
+__global__ void k_events_to_taps(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n_filters, Geom g,
+                                 int kk) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)n_filters * kKMax) return;
+  const long long f = id / kKMax;
+  const int t = (int)(id - f * kKMax);
+  const int wr = ((g.tc[0] + 7) / 8) * 8;
+  const int r = t / wr, bx = t - r * wr;
+  const int nrows = g.tc[1] * g.tc[2];
+  dst[id] = (t < kk && r < nrows && bx < g.tc[0]) ? src[f * g.tcells + (long long)r * g.tc[0] + bx] : 0;
+}
+
 // Scan variants: 1, 2, 4, 8 = candidate-major output with up to that many
 // tiles per workgroup; kScanFilterMajor = filter-major output, one tile.
 constexpr int kScanFilterMajor = -1;
@@ -366,74 +404,267 @@ int scan_strip_width(const Geom& g) {
 
 }  // namespace
 
-extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t max_code, const int32_t* approx,
-                               const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
-                               int32_t n_filters, int32_t score_mode, int32_t* scores, void* stream) {
+namespace {
+// K best keys of each filter from the fused scan's per-row survivors: the
+// K rows with the smallest minima hold them (a row holding one of the K
+// best keys has its minimum among them), and within each such row they are
+// among its survivors.  One workgroup per filter.
+__global__ __launch_bounds__(kThreads) void k_topk_rows(const uint64_t* __restrict__ keys,
+                                                        const uint64_t* __restrict__ rowmin,
+                                                        const int32_t* __restrict__ rowcnt, Geom g, int k,
+                                                        uint64_t seed, const int32_t* __restrict__ real,
+                                                        const int64_t* __restrict__ steps,
+                                                        uint64_t* __restrict__ out) {
+  __shared__ TopkShared sh;
+  __shared__ int s_row[kTopMax], s_pre[kTopMax + 1];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int nrows = g.cand[1] * g.cand[2], C0 = g.cand[0];
+  const uint64_t tkey = draw64(seed, kStreamTiebreak, (uint64_t)real[f], (uint64_t)steps[f]);
+  const uint64_t* rm = rowmin + (long long)f * nrows;
+  const int kr = min(k, nrows);
+  block_topk(nrows, kr, [&](long long i) { return rm[i]; }, sh);
+  if (tid == 0) {
+    int pre = 0;
+    for (int b = 0; b < kr; ++b) {
+      const int id = (int)tie_perm_inv((uint32_t)(sh.top[b] & kMask20), tkey);
+      const int row = min(max(id / C0, 0), nrows - 1);
+      s_row[b] = row;
+      s_pre[b] = pre;
+      pre += rowcnt[(long long)f * nrows + row];
+    }
+    s_pre[kr] = pre;
+  }
+  __syncthreads();
+  const uint64_t* kf = keys + (long long)f * g.ncand;
+  const int total = s_pre[kr];
+  block_topk(total, k, [&](long long i) {
+    int b = 0;
+    while (b + 1 < kr && s_pre[b + 1] <= i) ++b;
+    return kf[(long long)s_row[b] * C0 + (i - s_pre[b])];
+  }, sh);
+  if (tid < k) out[(long long)f * k + tid] = sh.top[tid];
+}
+
+// Coefficient bound of the level-J LeGall 5/3 approximation of codes in
+// [0, max_code]: an interval carried through the J * ndim lifting passes
+// (prediction, then the rounded update).
+long long lift53_bound(int max_code, int passes) {
+  long long lo = 0, hi = max_code > 0 ? max_code : 1;
+  for (int k = 0; k < passes; ++k) {
+    const long long dlo = lo - hi, dhi = hi - lo;
+    const long long nlo = lo + floor_div(2 * dlo + 2, 4), nhi = hi + floor_div(2 * dhi + 2, 4);
+    lo = nlo;
+    hi = nhi;
+  }
+  return std::max(-lo, hi);
+}
+
+// Everything the standalone scan needs besides its inputs and outputs.
+struct ScanPlan {
   Geom g;
+  int kpad = 0, W = 0, en = kEnStage, gbits = 0, sel_kk = 0, sel_W = 0;
+  bool fused = false, full = false;
+  long long ws_kh = 0, ws_mbuf = 0, ws_nbuf = 0, ws_tbuf = 0, ws_energy = 0, ws_keys = 0, ws_rowmin = 0, ws_rowcnt = 0,
+            ws_total = 0;
+  size_t sel_lds = 0;
+};
+
+int scan_plan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code, int32_t precision,
+              const int32_t tmpl[3], int32_t n_filters, int32_t score_mode, int32_t top_k, bool want_scores,
+              bool want_keys, ScanPlan& sp) {
+  Geom& g = sp.g;
   CCW_TRY(geom_ti(g, ti, level));
   if (!tmpl) return fail(CCWSIM_ERR_INVALID_ARG, "null template");
   CCW_TRY(geom_tmpl(g, tmpl));
-  if (!approx || !or_m || !scores || (score_mode == 0 && !or_n))
-    return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
   if (n_filters < 1) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters must be >= 1");
   if (score_mode != 0 && score_mode != 1) return fail(CCWSIM_ERR_INVALID_ARG, "score_mode");
+  if (wavelet != 0 && wavelet != 1) return fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (LeGall 5/3)");
+  if (precision != 0 && precision != 1) return fail(CCWSIM_ERR_INVALID_ARG, "precision must be 0 (fp16) or 1 (bf16)");
   if (max_code < 1 || max_code > 126) return fail(CCWSIM_ERR_INVALID_ARG, "max_code must be in [1, 126]");
-  const int kpad = (int)((g.tcells + 15) / 16 * 16);
-  if (kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kKMax);
-  CCW_TRY(check_exact(g, max_code, g.wcells));
-  const int W = scan_strip_width(g);
+  if (!want_scores && !want_keys) return fail(CCWSIM_ERR_INVALID_ARG, "neither scores nor top-K keys requested");
+  if (want_keys && (top_k < 1 || top_k > kTopMax))
+    return fail(CCWSIM_ERR_UNSUPPORTED, "top_k must be in [1, %d]", kTopMax);
+  sp.kpad = (int)((g.tcells + 15) / 16 * 16);
+  if (sp.kpad > kKMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kKMax);
+  // operand range: block sums (Haar) or 5/3 coefficients
+  long long kmax;
+  if (wavelet == 0) {
+    CCW_TRY(check_exact(g, max_code, g.wcells));
+    kmax = (long long)max_code * g.beta;
+  } else {
+    g.wavelet = 1;
+    g.shift = 1;
+    kmax = lift53_bound(max_code, g.level * g.ndim);
+    const long long cmax = g.tcells * kmax * kmax;
+    if (kmax > 2048) return fail(CCWSIM_ERR_UNSUPPORTED, "5/3 coefficients up to %lld are not exact in fp16", kmax);
+    if (cmax >= (1ll << 24)) return fail(CCWSIM_ERR_UNSUPPORTED, "cross sums up to %lld are not exact in fp32", cmax);
+    if (3 * cmax >= (1ll << 31)) return fail(CCWSIM_ERR_UNSUPPORTED, "scores up to %lld overflow int32", 3 * cmax);
+  }
+  if (precision == 1 && kmax > 256)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "approximation values up to %lld are not exact in bf16", kmax);
+  sp.W = scan_strip_width(g);
   const int nrows = g.tc[1] * g.tc[2];
-  if (scan_group_lds(nrows, W, kpad, 1) > 64 * 1024)
-    return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu bytes of LDS", scan_group_lds(nrows, W, kpad, 1));
-  // tiles per workgroup: the largest that keeps two workgroups per CU in
-  // flight and fits the LDS (every filter here shares the full window)
+  if (scan_group_lds(nrows, sp.W, sp.kpad, 1) > 64 * 1024)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "scan strip needs %zu bytes of LDS", scan_group_lds(nrows, sp.W, sp.kpad, 1));
+  sp.full = want_scores;
+  sp.fused = want_keys;
+  const int ksel = std::min<long long>(top_k, g.ncand);
+  if (sp.fused) {
+    if (g.cand[0] > 4096) return fail(CCWSIM_ERR_UNSUPPORTED, "fused selection supports <= 4096 candidates per row");
+    // the energy in the contraction when K^2 and the sums stay exact
+    const long long klim = precision == 1 ? 256 : 2048;
+    sp.en = (score_mode == 0 && kmax * kmax <= klim && g.tcells * g.beta * kmax * kmax < (1ll << 24))
+                ? kEnFold : kEnMem;
+    const int nchunks = (g.cand[0] + 31) / 32;
+    sp.gbits = sel_group_bits(g.cand[0], nchunks, ksel);
+    // segments of 8 blocks over every block row of the template
+    const int nseg = nrows * ((g.tc[0] + 7) / 8);
+    if (nseg > kSegMax)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "fused selection supports templates of <= %d 8-block row segments", kSegMax);
+    const int ks = ((nseg + 1) / 2 + 3) / 4 * 4;   // K-slices, a multiple of 4
+    sp.sel_kk = 16 * ks;
+    sp.sel_W = scan_sel_width(nchunks * 32, g.tc[0]);
+    sp.sel_lds = scan_sel_lds(nrows, sp.sel_W, sp.sel_kk, 16, sp.en, 1, nchunks * 32, sp.gbits, false);
+    if (sp.sel_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "fused scan needs %zu bytes of LDS", sp.sel_lds);
+  }
+  const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
+  const long long rows = (long long)g.cand[1] * g.cand[2];
+  long long o = 0;
+  sp.ws_kh = o;      o += align256(gcells * 2);
+  sp.ws_mbuf = o;    o += align256((long long)n_filters * kKMax * 4);
+  if (sp.fused) {
+    sp.ws_tbuf = o;    o += align256((long long)n_filters * kKMax * 4);
+    if (sp.en == kEnFold) {
+      sp.ws_nbuf = o;  o += align256((long long)n_filters * kKMax * 4);
+    } else if (score_mode == 0) {
+      sp.ws_energy = o; o += align256((long long)n_filters * g.ncand * 4);
+    }
+    sp.ws_keys = o;    o += align256((long long)n_filters * g.ncand * 8);
+    sp.ws_rowmin = o;  o += align256((long long)n_filters * rows * 8);
+    sp.ws_rowcnt = o;  o += align256((long long)n_filters * rows * 4);
+  }
+  sp.ws_total = o;
+  return CCWSIM_OK;
+}
+
+int enqueue_scan(const ScanPlan& sp, int32_t precision, int32_t score_mode, const int32_t* approx,
+                 const int32_t* or_n, const int32_t* or_m, int32_t n_filters, int32_t* scores, int32_t top_k,
+                 uint64_t seed, const int32_t* realization, const int64_t* step, uint64_t* topk_keys,
+                 unsigned char* ws, hipStream_t st) {
+  const Geom& g = sp.g;
+  const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
+  void* Kh = ws + sp.ws_kh;
+  int32_t* mbuf = (int32_t*)(ws + sp.ws_mbuf);
+  if (precision == 1) k_to_bf16<<<nblocks(gcells), kThreads, 0, st>>>(approx, (__bf16*)Kh, gcells);
+  else k_to_half<<<nblocks(gcells), kThreads, 0, st>>>(approx, (_Float16*)Kh, gcells);
+  k_events_to_mbuf<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_m, mbuf, n_filters, g.tcells);
   const int ntiles = (n_filters + kFiltersPerTile - 1) / kFiltersPerTile;
   const long long crow = (long long)g.cand[1] * g.cand[2];
-  int G = 1;
-  auto group_ok = [&](int c) { return kpad <= kScanGroupKMax && scan_group_lds(nrows, W, kpad, c) <= 64 * 1024; };
-  for (int c : {2, 4, 8})
-    if (c <= ntiles && crow * ((ntiles + c - 1) / c) >= 512 && group_ok(c)) G = c;
-  if (g_scan_g_force > 0) {
-    G = 1;
-    for (int c : {2, 4, 8})
-      if (c <= g_scan_g_force && group_ok(c)) G = c;
-  } else if (g_scan_g_force == kScanFilterMajor) {
-    G = kScanFilterMajor;
-  }
-
-  hipStream_t st = as_stream(stream);
-  const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
-  _Float16* Kh = nullptr;
-  int32_t* mbuf = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&Kh, gcells * 2, st));
-  HIP_TRY(hipMallocAsync((void**)&mbuf, (size_t)n_filters * kKMax * 4, st));
-  k_to_half<<<nblocks(gcells), kThreads, 0, st>>>(approx, Kh, gcells);
-  k_events_to_mbuf<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_m, mbuf, n_filters, g.tcells);
-  if (score_mode == 0) {
-    ProfScope ps(CCWSIM_KIND_ENERGY, st);
-    k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, scores, g);
-  }
+  const int nrows = g.tc[1] * g.tc[2];
   ScanArgs a = {};
   a.g = g;
   a.Kop = Kh;
   a.mbuf = mbuf;
-  a.scores = scores;
-  a.kpad = kpad;
-  a.W = W;
+  a.kpad = sp.kpad;
+  a.W = sp.W;
   a.score_mode = score_mode;
   a.standalone = 1;
   a.n_filters = n_filters;
   a.ntiles = ntiles;
-  {
-    ProfScope ps(CCWSIM_KIND_SCAN, st);
+  if (sp.full) {
+    // the whole score map: energies written first, the scan completes them
+    if (score_mode == 0) {
+      ProfScope ps(CCWSIM_KIND_ENERGY, st);
+      k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, scores, g);
+    }
+    int G = 1;
+    auto group_ok = [&](int c) {
+      return sp.kpad <= kScanGroupKMax && scan_group_lds(nrows, sp.W, sp.kpad, c) <= 64 * 1024;
+    };
+    for (int c : {2, 4, 8})
+      if (c <= ntiles && crow * ((ntiles + c - 1) / c) >= 512 && group_ok(c)) G = c;
+    if (g_scan_g_force > 0) {
+      G = 1;
+      for (int c : {2, 4, 8})
+        if (c <= g_scan_g_force && group_ok(c)) G = c;
+    } else if (g_scan_g_force == kScanFilterMajor) {
+      G = kScanFilterMajor;
+    }
+    a.scores = scores;
+    ProfKernel pk(CCWSIM_KIND_SCAN);
     const int Gt = G == kScanFilterMajor ? 1 : G;
-    launch_scan(0, G, (unsigned)crow, (ntiles + Gt - 1) / Gt, scan_group_lds(nrows, W, kpad, Gt), st, a);
+    launch_scan(precision, G, (unsigned)crow, (ntiles + Gt - 1) / Gt, scan_group_lds(nrows, sp.W, sp.kpad, Gt), st,
+                a, pk.a, pk.b);
   }
-  const hipError_t le = hipGetLastError();
-  HIP_TRY(hipFreeAsync(Kh, st));
-  HIP_TRY(hipFreeAsync(mbuf, st));
-  if (le != hipSuccess) return fail(CCWSIM_ERR_HIP, "k_scan launch: %s", hipGetErrorString(le));
+  if (sp.fused) {
+    int32_t* energy = nullptr;
+    int32_t* tbuf = (int32_t*)(ws + sp.ws_tbuf);
+    k_events_to_taps<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_m, tbuf, n_filters, g, sp.sel_kk);
+    a.mbuf = tbuf;
+    if (sp.en == kEnFold) {
+      int32_t* nbuf = (int32_t*)(ws + sp.ws_nbuf);
+      k_events_to_taps<<<nblocks((long long)n_filters * kKMax), kThreads, 0, st>>>(or_n, nbuf, n_filters, g, sp.sel_kk);
+      a.nbuf = nbuf;
+    } else if (score_mode == 0) {
+      energy = (int32_t*)(ws + sp.ws_energy);
+      ProfScope ps(CCWSIM_KIND_ENERGY, st);
+      k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, energy, g);
+    }
+    uint64_t* keys = (uint64_t*)(ws + sp.ws_keys);
+    uint64_t* rowmin = (uint64_t*)(ws + sp.ws_rowmin);
+    int32_t* rowcnt = (int32_t*)(ws + sp.ws_rowcnt);
+    const int k = (int)std::min<long long>(top_k, g.ncand);
+    a.scores = nullptr;
+    a.energy = energy;
+    a.keys = keys;
+    a.rowmin = rowmin;
+    a.rowcnt = rowcnt;
+    a.seed = seed;
+    a.fil_real = realization;
+    a.fil_step = step;
+    a.ksel = k;
+    a.gbits = sp.gbits;
+    a.n_bm = 1;
+    a.kpad = sp.sel_kk;
+    a.W = sp.sel_W;
+    {
+      ProfKernel pk(CCWSIM_KIND_SCAN);
+      launch_scan_sel(precision, false, sp.en, (unsigned)crow, ntiles, sp.sel_lds, st, a, pk.a, pk.b);
+    }
+    k_topk_rows<<<(unsigned)n_filters, kThreads, 0, st>>>(keys, rowmin, rowcnt, g, k, seed, realization, step,
+                                                          topk_keys);
+  }
+  HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
+}
+}  // namespace
+
+extern "C" int64_t ccwsim_ccf_scan_workspace_size(ccwsim_shape ti, int32_t level, int32_t wavelet,
+                                                  int32_t max_code, int32_t precision, const int32_t tmpl[3],
+                                                  int32_t n_filters, int32_t score_mode, int32_t top_k,
+                                                  int32_t want_scores, int32_t want_keys) {
+  ScanPlan sp;
+  if (scan_plan(ti, level, wavelet, max_code, precision, tmpl, n_filters, score_mode, top_k, want_scores != 0,
+                want_keys != 0, sp))
+    return -1;
+  return sp.ws_total;
+}
+
+extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code, int32_t precision,
+                               const int32_t* approx, const int32_t tmpl[3], const int32_t* or_n,
+                               const int32_t* or_m, int32_t n_filters, int32_t score_mode, int32_t* scores,
+                               int32_t top_k, uint64_t seed, const int32_t* realization, const int64_t* step,
+                               uint64_t* topk_keys, void* workspace, int64_t workspace_bytes, void* stream) {
+  ScanPlan sp;
+  CCW_TRY(scan_plan(ti, level, wavelet, max_code, precision, tmpl, n_filters, score_mode, top_k, scores != nullptr,
+                    topk_keys != nullptr, sp));
+  if (!approx || !or_m || (score_mode == 0 && !or_n)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (topk_keys && (!realization || !step)) return fail(CCWSIM_ERR_INVALID_ARG, "top-K keys need realization and step");
+  if (!workspace || workspace_bytes < sp.ws_total)
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", sp.ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return enqueue_scan(sp, precision, score_mode, approx, or_n, or_m, n_filters, scores, top_k, seed, realization,
+                      step, topk_keys, (unsigned char*)workspace, as_stream(stream));
 }
 
 // ===========================================================================
@@ -581,7 +812,8 @@ struct Plan {
   bool sel_rows = false;              // row-minima selection chosen (tuned)
   bool sel_fused_ok = false;          // the scan may select per row itself (k_scan_sel)
   bool sel_fused = false;             // fused selection chosen (tuned)
-  int sel_ng_shift = 0, sel_n_bm = 1; // k_scan_sel: group size 2^shift of a lane's values; band masks
+  int sel_gbits = 0, sel_n_bm = 1;    // k_scan_sel: 2^gbits groups of a lane's values; band masks
+  int sel_kk = 0, sel_W = 0;          // k_scan_sel: taps (16 per K-slice) and strip row length
   size_t sel_lds_nohd = 0, sel_lds_hd = 0;
   bool tuned = false;
   int max_slots = 0, nsteps_raster = 0;
@@ -597,6 +829,7 @@ struct Plan {
   size_t tbl_bytes = 0;
   std::vector<unsigned char> tbl_host;   // kbeta | nbt | filters | tiles | recs | npred | succ_off | succ
   unsigned char* tbl = nullptr;          // pinned copy of tbl_host, or null
+  size_t off_segoff = 0, off_taps = 0;   // k_scan_sel segment tables, [orient][kSegMax] / [orient][kSegMax * 8]
   size_t off_kbeta = 0, off_nbt = 0, off_filters = 0, off_tiles = 0, off_recs = 0, off_groups = 0, off_npred = 0,
          off_succoff = 0, off_succ = 0;
   long long nrecs = 0;
@@ -946,6 +1179,41 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   std::vector<int32_t> kbeta((size_t)P.n_orient * kKMax, -1);
   for (int o = 0; o < P.n_orient; ++o)
     for (size_t i = 0; i < klists[o].size(); ++i) kbeta[(size_t)o * kKMax + i] = klists[o][i];
+  // fused scan: the overlap blocks of each orientation covered by segments
+  // of 8 consecutive blocks of one block row (greedy from the row's first
+  // uncovered block); each tap names its entry of the block list, or -1
+  std::vector<int32_t> segoff((size_t)P.n_orient * kSegMax, 0), taps((size_t)P.n_orient * kSegMax * 8, -1);
+  {
+    const int cpad = ((g.cand[0] + 31) / 32) * 32;
+    P.sel_W = scan_sel_width(cpad, g.tc[0]);
+    int nseg_max = 0;
+    bool fits = true;
+    for (int o = 0; o < P.n_orient; ++o) {
+      std::map<int, std::vector<std::pair<int, int>>> rows;   // block row -> (bx, list entry)
+      for (size_t i = 0; i < klists[o].size(); ++i) {
+        const int beta = klists[o][i];
+        const int bx = beta % g.tc[0], rr = beta / g.tc[0];
+        rows[rr].push_back({bx, (int)i});
+      }
+      int ns = 0;
+      for (auto& kv : rows) {
+        std::vector<std::pair<int, int>>& v = kv.second;
+        std::sort(v.begin(), v.end());
+        size_t i = 0;
+        while (i < v.size()) {
+          const int bx0 = v[i].first;
+          if (ns < kSegMax) segoff[(size_t)o * kSegMax + ns] = kv.first * P.sel_W + bx0;
+          for (; i < v.size() && v[i].first < bx0 + 8; ++i)
+            if (ns < kSegMax) taps[((size_t)o * kSegMax + ns) * 8 + (v[i].first - bx0)] = v[i].second;
+          ++ns;
+        }
+      }
+      nseg_max = std::max(nseg_max, ns);
+      fits = fits && ns <= kSegMax;
+    }
+    const int ks = std::max(4, ((nseg_max + 1) / 2 + 3) / 4 * 4);   // K-slices, a multiple of 4
+    P.sel_kk = fits && ks <= kSegMax / 2 ? 16 * ks : 0;
+  }
 
   // the coefficient tree layout serves J = 1 and 2, and J = 3 in 2D
   P.tree_level = p.wavelet == 0 && (g.level == 1 || g.level == 2 || (g.level == 3 && nd == 2)) ? g.level : 0;
@@ -1016,33 +1284,16 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   }
   if (P.fin_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "finalize needs %zu B of LDS", P.fin_lds);
   // Selection fused into the scan (k_scan_sel): a lane's values fall into
-  // groups of 2^shift; the largest groups that still give every patch at
-  // least ksel groups holding a candidate.
+  // 2^gbits groups; the fewest groups that still give every patch at least
+  // ksel groups holding a candidate.
   {
     const int nchunks = (g.cand[0] + 31) / 32;
-    const int nwv = std::min(kThreads / 64, nchunks);
-    P.sel_ng_shift = 0;
-    for (int sh = 4; sh >= 0; --sh) {
-      int valid = 0;
-      for (int w = 0; w < nwv; ++w)
-        for (int hh = 0; hh < 2; ++hh)
-          for (int gi = 0; gi < (16 >> sh); ++gi) {
-            bool any = false;
-            for (int ch = w; ch < nchunks && !any; ch += kThreads / 64)
-              for (int v = gi << sh; v < ((gi + 1) << sh) && !any; ++v)
-                any = ch * 32 + 8 * (v >> 2) + 4 * hh + (v & 3) < g.cand[0];
-            valid += any ? 1 : 0;
-          }
-      if (valid >= ksel) {
-        P.sel_ng_shift = sh;
-        break;
-      }
-    }
+    P.sel_gbits = sel_group_bits(g.cand[0], nchunks, ksel);
     P.sel_n_bm = 1 << nd;
     const int nr = g.tc[1] * g.tc[2];
-    P.sel_lds_nohd = scan_sel_lds(nr, P.W, P.kpad, kEnStage, P.sel_n_bm, nchunks * 32, P.sel_ng_shift, false);
-    P.sel_lds_hd = scan_sel_lds(nr, P.W, P.kpad, kEnStage, P.sel_n_bm, nchunks * 32, P.sel_ng_shift, true);
-    P.sel_fused_ok = !P.learn && g.cand[0] <= 4096 && P.cand_cap > 0 &&
+    P.sel_lds_nohd = scan_sel_lds(nr, P.sel_W, P.sel_kk, P.kpad, kEnStage, P.sel_n_bm, nchunks * 32, P.sel_gbits, false);
+    P.sel_lds_hd = scan_sel_lds(nr, P.sel_W, P.sel_kk, P.kpad, kEnStage, P.sel_n_bm, nchunks * 32, P.sel_gbits, true);
+    P.sel_fused_ok = !P.learn && g.cand[0] <= 4096 && P.cand_cap > 0 && P.sel_kk > 0 &&
                      std::max(P.sel_lds_nohd, P.sel_lds_hd) <= 64 * 1024 && !(p.max_hard_data > 0 && p.hd_direct);
   }
   // additive data events: the Haar block sums of a successor's overlap
@@ -1056,7 +1307,9 @@ int build_plan(const ccwsim_params& p, Plan& P) {
 
   // pinned table block
   P.off_kbeta = 0;
-  P.off_nbt = align256(kbeta.size() * 4);
+  P.off_segoff = align256(kbeta.size() * 4);
+  P.off_taps = P.off_segoff + align256(segoff.size() * 4);
+  P.off_nbt = P.off_taps + align256(taps.size() * 4);
   P.off_filters = P.off_nbt + align256(nbt.size() * 4);
   P.off_tiles = P.off_filters + align256(filters.size() * sizeof(FilterDev));
   P.off_recs = P.off_tiles + align256(tiles.size() * sizeof(TileDev));
@@ -1069,6 +1322,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.tbl_host.assign(P.tbl_bytes, 0);
   unsigned char* tb = P.tbl_host.data();
   memcpy(tb + P.off_kbeta, kbeta.data(), kbeta.size() * 4);
+  memcpy(tb + P.off_segoff, segoff.data(), segoff.size() * 4);
+  memcpy(tb + P.off_taps, taps.data(), taps.size() * 4);
   memcpy(tb + P.off_nbt, nbt.data(), nbt.size() * 4);
   memcpy(tb + P.off_filters, filters.data(), filters.size() * sizeof(FilterDev));
   memcpy(tb + P.off_tiles, tiles.data(), tiles.size() * sizeof(TileDev));
@@ -2677,7 +2932,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   sa.has_hd = n_hd > 0;
   sa.rowcnt = rowcnt;
   sa.ksel = std::min(p->shortlist > 0 ? p->shortlist : p->top_k, g.ncand);
-  sa.ng_shift = P->sel_ng_shift;
+  sa.gbits = P->sel_gbits;
   sa.n_bm = P->sel_n_bm;
 
   FinArgs fa = {};
@@ -2767,9 +3022,19 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       ProfScope ps(CCWSIM_KIND_SCAN, st);
       k_proxy<<<dim3(rows, (unsigned)s.tcount), kThreads, P->proxy_lds, st>>>(xa);
     } else if (fused) {
+      ScanArgs sf = sa;
+      sf.kpad = P->sel_kk;
+      sf.klist = P->kpad;
+      sf.W = P->sel_W;
+      sf.segoff = (const int32_t*)(tbl + P->off_segoff);
+      sf.taps = (const int32_t*)(tbl + P->off_taps);
+      sf.n_tinline = s.tcount <= 32 ? s.tcount : 0;
+      if (sf.n_tinline)
+        memcpy(sf.tiles_inline, P->tbl_host.data() + P->off_tiles + (size_t)s.tbegin * sizeof(TileDev),
+               (size_t)s.tcount * sizeof(TileDev));
       ProfKernel pk(CCWSIM_KIND_SCAN);
       launch_scan_sel(p->precision, n_hd > 0, kEnStage, rows, s.tcount, n_hd > 0 ? P->sel_lds_hd : P->sel_lds_nohd,
-                      st, sa, pk.a, pk.b);
+                      st, sf, pk.a, pk.b);
     } else {
       ProfKernel pk(CCWSIM_KIND_SCAN);
       launch_scan(p->precision, G, rows, s.gcount[gix], scan_lds, st, sa, pk.a, pk.b);

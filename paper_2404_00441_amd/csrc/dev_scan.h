@@ -114,8 +114,13 @@ struct ScanArgs {
   const int32_t* nbuf;         // standalone with the energy in the contraction: [filter][kKMax] known cells
   const int32_t* fil_real;     // standalone: realization of each filter (tie-break key), or null
   const int64_t* fil_step;     // standalone: raster step of each filter (tie-break key), or null
+  const int32_t* segoff;       // fused: [orient][kSegMax] strip offset of each 8-tap segment's first block
+  const int32_t* taps;         // fused: [orient][kSegMax * 8] data-event entry of each tap, or -1
+  int klist;                   // fused, simulation: entries of the orientation block lists (a multiple of 16)
+  int n_tinline;               // fused, simulation: tiles passed by value (the step's first ones)
+  TileDev tiles_inline[32];
   int ksel;                    // keys the selection keeps per row (K, or the shortlist)
-  int ng_shift;                // value v of a lane joins group v >> ng_shift of its lane
+  int gbits;                   // value v of a lane joins group v & (2^gbits - 1) of its lane
   int n_bm;                    // band masks per orientation (energy rows per tile)
 };
 
@@ -634,16 +639,26 @@ void k_scan_fm(ScanArgs a) {
 //   1. Every score is formed and reduced to a selection value q, a
 //      non-decreasing function of the key without its tie-break field
 //      (q = S, or (mismatch, S) with hard data).  Each lane keeps the
-//      minima of q over groups of its values (disjoint sets of candidates);
-//      the ksel-th smallest of a patch's group minima, tau, bounds the q of
-//      its ksel-th best candidate from above: ksel candidates have q <= tau,
-//      and a candidate with q > tau has ksel keys below its own.
+//      minima of q over groups of its values (disjoint sets of candidates,
+//      spread along the row); the ksel-th smallest of a patch's group
+//      minima, tau, bounds the q of its ksel-th best candidate from above:
+//      ksel candidates have q <= tau, and a candidate with q > tau has ksel
+//      keys below its own.
 //   2. Candidates with q <= tau (the survivors) get their full key (with the
 //      keyed tie-break) and are written out.  Survivors are collected per
 //      wavefront into an LDS queue with ballots, so the keys of a sparse
 //      set of survivors are built densely, 64 at a time.
 // A row's best keys are therefore among its survivors, and the K best keys
 // of a patch are among the survivors of the K rows with the smallest minima.
+//
+// The contraction uses the Toeplitz structure of the correlation: along a
+// row of template blocks, block bx of candidate cx reads K[cx + bx].  The
+// overlap's blocks are covered by segments of 8 consecutive blocks of one
+// block row (a block outside the overlap inside a segment gets weight 0),
+// and one MFMA K-slice of 16 taps is two segments.  Lane (candidate c,
+// half h) then needs the 8 consecutive values K[c + bx0 .. c + bx0 + 7] of
+// its segment: four aligned 32-bit LDS reads from one of two copies of the
+// strip, the second shifted by one value, picked by the parity of c + bx0.
 //
 // Energy source EN: kEnStage -- the energy rows of the tile's orientation
 // (one per band mask) are staged in LDS; kEnFold -- the MFMA also contracts
@@ -652,20 +667,25 @@ void k_scan_fm(ScanArgs a) {
 // from memory (standalone).  HD: hard-data mismatch counts from the bit
 // table enter the key.
 // ---------------------------------------------------------------------------
-constexpr int kSelQueue = 512;   // survivor queue entries per wavefront
+constexpr int kSelQueue = 256;   // survivor queue entries per wavefront
+constexpr int kSegMax = 32;      // segments of 8 taps (16 MFMA K-slices)
 enum { kEnStage = 0, kEnFold = 1, kEnMem = 2 };
 
+// Strip row length (values) of the fused scan: the candidate chunks, the
+// template row and one segment of slack.
+inline int scan_sel_width(int cpad, int tc0) { return (cpad + ((tc0 + 7) / 8) * 8 + 8 + 3) & ~3; }
+
 // LDS bytes of k_scan_sel.
-inline size_t scan_sel_lds(int nrows, int W, int kpad, int en, int n_bm, int cpad, int ng_shift, bool hd) {
-  size_t o = ((size_t)nrows * W * 2 * (en == kEnFold ? 2 : 1) + 15) & ~(size_t)15;
-  const int kk = en == kEnFold ? 2 * kpad : kpad;
-  o += (size_t)kpad * 4;
-  o += (size_t)kFiltersPerTile * (kk + 8) * 2;
+inline size_t scan_sel_lds(int nrows, int W, int kk, int klist, int en, int n_bm, int cpad, int gbits, bool hd) {
+  const size_t cs = ((size_t)nrows * W * 2 + 15) & ~(size_t)15;
+  size_t o = cs * 2;
+  o += 4 * kSegMax / 2 * 4;                                   // segment addresses
+  o += (size_t)kFiltersPerTile * (kk * (en == kEnFold ? 2 : 1) + 8) * 2;   // B operand
   o += (size_t)kFiltersPerTile * sizeof(ScanRec);
-  if (en == kEnStage) o += (size_t)n_bm * cpad * 4;
+  if (en == kEnStage) o += (size_t)(n_bm + 2) * cpad * 4;
   const int nwv = std::min(kThreads / 64, cpad / 32);
-  o += (size_t)kFiltersPerTile * (nwv * 2 * (16 >> ng_shift)) * (hd ? 8 : 4);
-  o += (size_t)(kThreads / 64) * kSelQueue * 8;
+  o += (size_t)kFiltersPerTile * (nwv * 2 * (1 << gbits)) * (hd ? 8 : 4);
+  o += std::max((size_t)(kThreads / 64) * kSelQueue * 8, (size_t)kFiltersPerTile * klist * 2);
   return o;
 }
 
@@ -693,40 +713,43 @@ void k_scan_sel(ScanArgs a) {
   typedef typename MfmaOp<OT>::vec8 vec8;
   typedef SelVal<HD> SV;
   typedef typename SV::T qt;
+  constexpr bool FOLD = EN == kEnFold;
   const OT* Kop = (const OT*)a.Kop;
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row = blockIdx.x;
   const int cy = row % g.cand[1], cz = row / g.cand[1];
-  const int W = a.W, kpad = a.kpad;
+  const int W = a.W, kk = a.kpad;          // kk: taps (16 per K-slice, a multiple of 64)
+  const int KS = kk / 16;
   const int nrows = g.tc[1] * g.tc[2];
   const int j = lane & 31, h = lane >> 5;
-  const int g8 = h * 8;
   const int C0 = g.cand[0];
   const int nchunks = (C0 + 31) / 32;
   const int cpad = nchunks * 32;
-  const int kk = EN == kEnFold ? 2 * kpad : kpad;
-  const int bstride = kk + 8;
-  const int ng_shift = a.ng_shift;
-  const int NG = 16 >> ng_shift;
+  const int kb = FOLD ? 2 * kk : kk;       // B operand length (taps, then known-cell counts)
+  const int bstride = kb + 8;
+  const int gbits = a.gbits;
+  const int NG = 1 << gbits;
   const int nwv = min(kThreads / 64, nchunks);   // wavefronts holding chunks
   const int G8 = nwv * 2 * NG;                   // groups per patch
 
   const int strip_n = nrows * W;
-  OT* s_strip = (OT*)smem;
-  size_t o = ((size_t)strip_n * 2 * (EN == kEnFold ? 2 : 1) + 15) & ~(size_t)15;
-  int* s_off = (int*)(smem + o);
-  o += (size_t)kpad * 4;
+  const int cs = (strip_n * 2 + 15) & ~15;       // bytes per strip copy
+  unsigned char* s_strip = smem;                 // copies: K, K shifted by one
+  size_t o = (size_t)cs * 2;
+  int* s_seg = (int*)(smem + o);                 // [h][parity of c][slice] byte address of the segment
+  o += 4 * kSegMax / 2 * 4;
   OT* s_B = (OT*)(smem + o);
   o += (size_t)kFiltersPerTile * bstride * 2;
   ScanRec* s_rec = (ScanRec*)(smem + o);
   o += (size_t)kFiltersPerTile * sizeof(ScanRec);
-  int32_t* s_E = (int32_t*)(smem + o);
-  if (EN == kEnStage) o += (size_t)a.n_bm * cpad * 4;
+  int32_t* s_E = (int32_t*)(smem + o);           // [band mask][cpad], then a zero row and an infinite row
+  if (EN == kEnStage) o += (size_t)(a.n_bm + 2) * cpad * 4;
   qt* s_gm = (qt*)(smem + o);
   o += (size_t)kFiltersPerTile * G8 * sizeof(qt);
-  uint2* s_q = (uint2*)(smem + o) + wave * kSelQueue;
+  unsigned char* s_qbase = smem + o;   // survivor queues; before pass 1 the event staging
+  uint2* s_q = (uint2*)s_qbase + wave * kSelQueue;
   __shared__ unsigned s_cnt[kFiltersPerTile];
   __shared__ unsigned long long s_rmin[kFiltersPerTile];
   __shared__ qt s_tau[kFiltersPerTile];
@@ -738,7 +761,17 @@ void k_scan_sel(ScanArgs a) {
     t.orient = 0;
     t.zmask = 0;
   } else {
-    t = a.tiles[blockIdx.y];
+    // the tile record by value when the step's tiles fit the arguments, so
+    // it arrives with them (the empty asm takes both loads before the branch)
+    const int n_ti = a.n_tinline;
+    const TileDev t_arg = a.tiles_inline[min((int)blockIdx.y, 31)];
+    __asm__ volatile("" ::"s"(n_ti), "s"(t_arg.first));
+    if ((int)blockIdx.y < n_ti) {
+      t = t_arg;
+      __asm__ volatile("" ::: "memory");
+    } else {
+      t = a.tiles[blockIdx.y];
+    }
   }
   ScanRec rec = {};
   if (a.standalone) {
@@ -754,103 +787,185 @@ void k_scan_sel(ScanArgs a) {
     s_rmin[tid] = ~0ull;
   }
   const long long rowbase = (long long)C0 * row;
-  // K-grid strip (and its squares): every load of a thread before any store
+  // strip copies: copy 0 holds K[x], copy 1 K[x + 1].  Lane l of a
+  // wavefront loads 4 values of a block row with one 8-byte load and
+  // stores them to copy 0; copy 1 takes values 1..3 of the lane and value 0
+  // of the next lane (a lane shuffle), so each value is loaded once.  The
+  // wavefronts take the rows in turn; near the grid's edge a lane loads
+  // value by value.
   {
-    constexpr int U = 8;
-    BoxWalk w(tid, kThreads, W, g.tc[1]);
-    for (int base = tid; base < strip_n; base += kThreads * U) {
-      OT v[U];
+    const int nq = W / 4;   // 4-value groups per row (W is a multiple of 4)
+    for (int rr = wave; rr < nrows; rr += kThreads / 64) {
+      const int by = rr % g.tc[1], bz = rr / g.tc[1];
+      const OT* krow = Kop + (long long)g.G[0] * ((cy + by) + (long long)g.G[1] * (cz + bz));
+      for (int xq0 = 0; xq0 < nq + 1; xq0 += 64) {
+        const int xq = xq0 + lane;
+        const int x = 4 * xq;
+        uint64_t w0 = 0;
+        if (x + 4 <= g.G[0]) {
+          __builtin_memcpy(&w0, krow + x, 8);
+        } else if (x < g.G[0]) {
+          OT v[4];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int i = base + q * kThreads;
-        v[q] = (OT)0.0f;
-        if (i < strip_n && w.x < g.G[0]) v[q] = Kop[idx3i(w.x, cy + w.y, cz + w.z, g.G)];
-        w.next();
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int i = base + q * kThreads;
-        if (i < strip_n) {
-          s_strip[i] = v[q];
-          if (EN == kEnFold) {
-            const float f = (float)v[q];
-            s_strip[strip_n + i] = (OT)(f * f);
-          }
+          for (int e = 0; e < 4; ++e) v[e] = x + e < g.G[0] ? krow[x + e] : (OT)0.0f;
+          __builtin_memcpy(&w0, v, 8);
+        }
+        // value 0 of the next lane; the last lane of a pass loads its own
+        uint32_t nxt = (uint32_t)__shfl_down((int)(uint32_t)w0, 1, 64);
+        if (lane == 63) {
+          OT v0 = (OT)0.0f;
+          if (x + 4 < g.G[0]) v0 = krow[x + 4];
+          uint16_t b16;
+          __builtin_memcpy(&b16, &v0, 2);
+          nxt = b16;
+        }
+        const uint64_t w1 = (w0 >> 16) | ((uint64_t)(nxt & 0xFFFFu) << 48);
+        if (xq < nq) {
+          *(uint64_t*)(s_strip + 2 * (rr * W + x)) = w0;
+          *(uint64_t*)(s_strip + cs + 2 * (rr * W + x)) = w1;
         }
       }
     }
   }
-  for (int k = tid; k < kpad; k += kThreads) {
-    int beta;
-    if (a.standalone) beta = k < (int)g.tcells ? k : -1;
-    else beta = a.kbeta[t.orient * kKMax + k];
-    int off = 0;
-    if (beta >= 0) {
-      const int bx = beta % g.tc[0], by = (beta / g.tc[0]) % g.tc[1], bz = beta / (g.tc[0] * g.tc[1]);
-      off = (bz * g.tc[1] + by) * W + bx;
-    }
-    s_off[k] = off;
-  }
-  // data events (and, folded, the known-cell counts) as the B operand
+  // data events (and, folded, the known-cell counts) as the B operand:
+  // standalone events arrive in tap order and are copied with 32-byte
+  // loads; a simulation's arrive in the order of the orientation's block
+  // list and are staged in LDS with 32-byte loads, then moved to their taps
+  // after the barrier.  Thread tid takes filter tid % 32 and every eighth
+  // group of 8 entries from tid / 32 on.
   typedef int32_t int8v_t __attribute__((ext_vector_type(8)));
-  const int k8n = kk / 8, k8m = kpad / 8;
-  for (int i = tid; i < kFiltersPerTile * k8n; i += kThreads) {
-    const int jj = i / k8n, k8i = i - jj * k8n;
-    const bool second = k8i >= k8m;
-    const int k8 = (second ? k8i - k8m : k8i) * 8;
-    int8v_t m = {};
-    if (jj < t.count && !((t.zmask >> jj) & 1u)) {
-      const int32_t* src = second ? a.nbuf : a.mbuf;
-      m = *(const int8v_t*)(src + (long long)(a.fbegin + t.first + jj) * kKMax + k8);
-    }
-    vec8 v;
+  const int kl = a.standalone ? kk : a.klist;   // entries per event row
+  OT* s_mst = (OT*)s_qbase;                     // staging (simulation), aliases the survivor queues
+  {
+    const int jj = tid & (kFiltersPerTile - 1);
+    const bool on = jj < t.count && !((t.zmask >> jj) & 1u);
+    const long long fo = (long long)(a.fbegin + t.first + jj) * kKMax;
+    for (int k8 = (tid >> 5) * 8; k8 < kl; k8 += 64) {
+      int8v_t m = {}, n = {};
+      if (on) {
+        m = *(const int8v_t*)(a.mbuf + fo + k8);
+        if (FOLD) n = *(const int8v_t*)(a.nbuf + fo + k8);
+      }
+      vec8 v, w;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (OT)(float)m[e];
-    *(vec8*)(s_B + jj * bstride + k8i * 8) = v;
+      for (int e = 0; e < 8; ++e) {
+        v[e] = (OT)(float)m[e];
+        if (FOLD) w[e] = (OT)(float)n[e];
+      }
+      if (a.standalone) {
+        *(vec8*)(s_B + jj * bstride + k8) = v;
+        if (FOLD) *(vec8*)(s_B + jj * bstride + kk + k8) = w;
+      } else {
+        *(vec8*)(s_mst + jj * kl + k8) = v;
+      }
+    }
   }
-  // energy rows of the tile's orientation, one per band mask
-  if (EN == kEnStage && a.score_mode == 0) {
+  // energy rows of the tile's orientation (one per band mask), a zero row
+  // and an infinite row; 4 candidates per thread and load
+  if (EN == kEnStage) {
     const int nb = a.n_bm;
-    for (int i = tid; i < nb * cpad; i += kThreads) {
-      const int bm = i / cpad, cx = i - bm * cpad;
-      s_E[i] = cx < C0 ? a.energy[(long long)((t.orient * nb) | bm) * g.ncand + rowbase + cx] : 0;
+    const int c4 = cpad / 4;
+    for (int i = tid; i < (nb + 2) * c4; i += kThreads) {
+      const int bm = i / c4, cx = (i - bm * c4) * 4;
+      int4 e4 = make_int4(0, 0, 0, 0);
+      if (bm == nb + 1) {
+        e4 = make_int4(0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF);
+      } else if (bm < nb && a.score_mode == 0) {
+        const int32_t* er = a.energy + (long long)((t.orient * nb) | bm) * g.ncand + rowbase + cx;
+        if (cx + 4 <= C0 && ((uintptr_t)er & 15) == 0) {
+          e4 = *(const int4*)er;
+        } else {
+          e4.x = cx < C0 ? er[0] : 0;
+          e4.y = cx + 1 < C0 ? er[1] : 0;
+          e4.z = cx + 2 < C0 ? er[2] : 0;
+          e4.w = cx + 3 < C0 ? er[3] : 0;
+        }
+      }
+      *(int4*)(s_E + bm * cpad + cx) = e4;
+    }
+  }
+  // the first tap entries of this thread's scatter (after the barrier)
+  int4 tq0[2] = {make_int4(-1, -1, -1, -1), make_int4(-1, -1, -1, -1)};
+  if (!a.standalone && tid < kFiltersPerTile * (kk / 8)) {
+    const int tp = (tid >> 5) * 8;
+    tq0[0] = *(const int4*)(a.taps + t.orient * (kSegMax * 8) + tp);
+    tq0[1] = *(const int4*)(a.taps + t.orient * (kSegMax * 8) + tp + 4);
+  }
+  // segments of this orientation: byte address, per lane parity, of the
+  // four aligned words holding taps bx0 .. bx0 + 7 for candidate c = parity
+  if (tid < kSegMax) {
+    const int sg = tid;
+    int so = 0;
+    if (sg < 2 * KS) {
+      if (a.standalone) {
+        const int spr = (g.tc[0] + 7) / 8;   // segments per block row
+        const int r = sg / spr, bx0 = (sg - r * spr) * 8;
+        so = r < nrows ? r * W + bx0 : 0;
+      } else {
+        so = a.segoff[t.orient * kSegMax + sg];
+      }
+    }
+#pragma unroll
+    for (int jp = 0; jp < 2; ++jp) {
+      const int p = (so + jp) & 1;
+      s_seg[((sg & 1) * 2 + jp) * (kSegMax / 2) + (sg >> 1)] = p * cs + 2 * (so + jp - p);
     }
   }
   __syncthreads();
+  if (!a.standalone) {
+    // events to their taps, 8 taps of one filter per thread and step (the
+    // tap entries were loaded before the barrier)
+    const int tg = kk / 8;
+    for (int i = tid, it = 0; i < kFiltersPerTile * tg; i += kThreads, ++it) {
+      const int jj = i & (kFiltersPerTile - 1), tp = (i >> 5) * 8;
+      const int4 k0 = it == 0 ? tq0[0] : *(const int4*)(a.taps + t.orient * (kSegMax * 8) + tp);
+      const int4 k1 = it == 0 ? tq0[1] : *(const int4*)(a.taps + t.orient * (kSegMax * 8) + tp + 4);
+      const int kq[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+      vec8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = kq[e] >= 0 ? s_mst[jj * kl + kq[e]] : (OT)0.0f;
+      *(vec8*)(s_B + jj * bstride + tp) = v;
+    }
+    __syncthreads();
+  }
 
   const bool fvalid = rec.gidx >= 0;
   const int shift = g.shift;
   const int J = g.level, Jz = g.ndim == 3 ? J : 0;
-  const int bm_j = EN == kEnStage ? (rec.shape & (a.n_bm - 1)) : 0;
-  const int32_t* erow = EN == kEnMem ? a.energy + (long long)(t.first + j) * g.ncand + rowbase : nullptr;
-  const OT* brow = s_B + j * bstride + g8;
+  // S = E - mul * C: mul = 2^shift (squared difference) or 1 (raw, E = 0);
+  // an invalid lane reads the infinite row with mul = 0
+  const int mul = !fvalid ? 0 : a.score_mode == 0 ? (1 << shift) : 1;
+  const int32_t* erow_s = EN == kEnStage
+                              ? s_E + (!fvalid ? a.n_bm + 1 : a.score_mode == 0 ? (rec.shape & (a.n_bm - 1)) : a.n_bm) * cpad
+                              : nullptr;
+  const int32_t* erow_m = EN == kEnMem ? a.energy + (long long)(fvalid ? t.first + j : t.first) * g.ncand + rowbase : nullptr;
+  const int einf = fvalid ? 0 : 0x7FFFFFFF;   // fold / memory energy of an invalid lane
+  const int lane_b = 2 * (j & ~1);            // bytes of the even part of c within a chunk
+  const int jp = j & 1;
+  const int* segp = s_seg + (h * 2 + jp) * (kSegMax / 2);
+  const OT* brow = s_B + j * bstride + 8 * h;
 
   // selection values of one 32-candidate chunk (invalid entries: infinity)
   auto chunk_values = [&](int ch, qt (&q)[16]) {
     int ev[16];
     unsigned mis[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      ev[v] = 0;
-      mis[v] = 0;
-    }
-    if (a.score_mode == 0 && EN != kEnFold) {
+    for (int v = 0; v < 16; ++v) mis[v] = 0;
+    if (EN == kEnStage) {
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
-        const int cx0 = ch * 32 + 8 * qd + 4 * h;
-        int4 e4;
-        if (EN == kEnStage) {
-          e4 = *(const int4*)(s_E + bm_j * cpad + cx0);
-        } else {
-          e4.x = cx0 < C0 ? erow[cx0] : 0;
-          e4.y = cx0 + 1 < C0 ? erow[cx0 + 1] : 0;
-          e4.z = cx0 + 2 < C0 ? erow[cx0 + 2] : 0;
-          e4.w = cx0 + 3 < C0 ? erow[cx0 + 3] : 0;
-        }
+        const int4 e4 = *(const int4*)(erow_s + ch * 32 + 8 * qd + 4 * h);
         ev[4 * qd] = e4.x;
         ev[4 * qd + 1] = e4.y;
         ev[4 * qd + 2] = e4.z;
         ev[4 * qd + 3] = e4.w;
+      }
+    } else if (EN == kEnMem) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int cx = ch * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        ev[v] = (a.score_mode == 0 && cx < C0) ? erow_m[cx] : 0;
+        if (!fvalid) ev[v] = 0x7FFFFFFF;
       }
     }
     if (HD && fvalid && rec.nhd > 0) {
@@ -889,27 +1004,47 @@ void k_scan_sel(ScanArgs a) {
         }
       }
     }
-    const int cbase = ch * 32 + j;
+    // contraction: four K-slices at a time, every read of a group issued
+    // before its MFMAs
     float16_t acc = {}, acc2 = {};
-    for (int kc = 0; kc < kpad; kc += 16) {
-      vec8 av;
+    const int cb = lane_b + ch * 64;
+    for (int q0 = 0; q0 < KS; q0 += 4) {
+      const int4 sa4 = *(const int4*)(segp + q0);
+      const int sa[4] = {sa4.x, sa4.y, sa4.z, sa4.w};
+      vec8 av[4], bv[4], a2[4], b2[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = s_strip[s_off[kc + g8 + e] + cbase];
-      acc = MfmaOp<OT>::mma(av, *(const vec8*)(brow + kc), acc);
-      if (EN == kEnFold) {
-        vec8 a2;
+      for (int qq = 0; qq < 4; ++qq) {
+        const unsigned char* p = s_strip + sa[qq] + cb;
+        uint32_t w4[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) a2[e] = s_strip[strip_n + s_off[kc + g8 + e] + cbase];
-        acc2 = MfmaOp<OT>::mma(a2, *(const vec8*)(brow + kpad + kc), acc2);
+        for (int e = 0; e < 4; ++e) w4[e] = *(const uint32_t*)(p + 4 * e);
+        av[qq] = __builtin_bit_cast(vec8, w4);
+        bv[qq] = *(const vec8*)(brow + (q0 + qq) * 16);
+        if (FOLD) {   // K^2 from the same values: exact, K^2 stays below the operand's integer range
+          a2[qq] = av[qq] * av[qq];
+          b2[qq] = *(const vec8*)(brow + kk + (q0 + qq) * 16);
+        }
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        acc = MfmaOp<OT>::mma(av[qq], bv[qq], acc);
+        if (FOLD) acc2 = MfmaOp<OT>::mma(a2[qq], b2[qq], acc2);
       }
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int cx = ch * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
       const int C = (int)acc[v];
-      const int E = EN == kEnFold ? (int)acc2[v] : ev[v];
-      const int S = a.score_mode == 0 ? E - (C << shift) : -C;
-      q[v] = (fvalid && cx < C0) ? SV::make(mis[v], S) : SV::inf();
+      const int E = FOLD ? (int)acc2[v] + einf : ev[v];
+      q[v] = SV::make(mis[v], E - __mul24(mul, C));
+    }
+    if (ch * 32 + 32 > C0) {   // the row's last chunk: candidates past the row
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        if (ch * 32 + 8 * (v >> 2) + 4 * h + (v & 3) >= C0) q[v] = SV::inf();
+    }
+    if (HD && !fvalid) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) q[v] = SV::inf();
     }
   };
 
@@ -933,26 +1068,28 @@ void k_scan_sel(ScanArgs a) {
       if (p == 1) qv1[v] = q[v];
     }
   }
-  // minima of groups of 2^ng_shift adjacent values
-  if (ng_shift >= 1) {
+  // group g of a lane: its values v with v mod NG = g.  Value v holds
+  // candidate 8 (v / 4) + 4 h + v % 4 of a chunk, so the candidates of one
+  // group are spread along the row and a run of good neighbouring
+  // candidates lands in different groups (a tighter tau).
+  if (gbits <= 3) {
 #pragma unroll
-    for (int v = 0; v < 16; v += 2) vmin[v] = vmin[v + 1] < vmin[v] ? vmin[v + 1] : vmin[v];
+    for (int v = 0; v < 8; ++v) vmin[v] = vmin[v + 8] < vmin[v] ? vmin[v + 8] : vmin[v];
   }
-  if (ng_shift >= 2) {
+  if (gbits <= 2) {
 #pragma unroll
-    for (int v = 0; v < 16; v += 4) vmin[v] = vmin[v + 2] < vmin[v] ? vmin[v + 2] : vmin[v];
+    for (int v = 0; v < 4; ++v) vmin[v] = vmin[v + 4] < vmin[v] ? vmin[v + 4] : vmin[v];
   }
-  if (ng_shift >= 3) {
+  if (gbits <= 1) {
 #pragma unroll
-    for (int v = 0; v < 16; v += 8) vmin[v] = vmin[v + 4] < vmin[v] ? vmin[v + 4] : vmin[v];
+    for (int v = 0; v < 2; ++v) vmin[v] = vmin[v + 2] < vmin[v] ? vmin[v + 2] : vmin[v];
   }
-  if (ng_shift >= 4) vmin[0] = vmin[8] < vmin[0] ? vmin[8] : vmin[0];
+  if (gbits <= 0) vmin[0] = vmin[1] < vmin[0] ? vmin[1] : vmin[0];
   if (wave < nwv) {
     qt* gm = s_gm + j * G8 + (wave * 2 + h) * NG;
-    const int gmask = (1 << ng_shift) - 1;
 #pragma unroll
     for (int v = 0; v < 16; ++v)
-      if ((v & gmask) == 0) gm[v >> ng_shift] = vmin[v];
+      if (v < NG) gm[v] = vmin[v];
   }
   __syncthreads();
   // tau of each patch: the ksel-th smallest of its group minima (ties by
@@ -1001,19 +1138,20 @@ void k_scan_sel(ScanArgs a) {
     } else {
       chunk_values(ch, q);
     }
+    const unsigned cxb = (unsigned)(ch * 32 + 4 * h) | jbits;
 #pragma unroll
-    for (int v4 = 0; v4 < 16; v4 += 4) {
-      if (qn > kSelQueue - 256) flush();
+    for (int v2 = 0; v2 < 16; v2 += 2) {
+      if (qn > kSelQueue - 128) flush();
 #pragma unroll
-      for (int v = v4; v < v4 + 4; ++v) {
-        const bool sv = q[v] != SV::inf() && q[v] <= tau;
+      for (int v = v2; v < v2 + 2; ++v) {
+        const bool sv = q[v] <= tau && q[v] != SV::inf();
         const uint64_t m = __ballot(sv);
         if (m) {
           if (sv) {
             const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const int cx = ch * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-            s_q[pos] = make_uint2((uint32_t)SV::score(q[v]), (uint32_t)cx | jbits | (SV::mis(q[v]) << 20));
+            s_q[pos] = make_uint2((uint32_t)SV::score(q[v]),
+                                  (cxb + (unsigned)(8 * (v >> 2) + (v & 3))) | (SV::mis(q[v]) << 20));
           }
           qn += __builtin_popcountll(m);
         }

@@ -195,6 +195,84 @@ def test_scan_tile_groups(cc, orc, G):
         assert np.array_equal(S[f].astype(np.int64), want), f"filter {f}"
 
 
+FUSED_SCAN_CASES = [
+    # SCAN_CASES index, top_k, precision
+    (0, 5, 0), (1, 10, 0), (2, 16, 0), (3, 7, 0), (4, 3, 0), (5, 10, 0), (6, 4, 0), (1, 10, 1), (2, 1, 0),
+]
+
+
+@pytest.mark.parametrize("case", FUSED_SCAN_CASES,
+                         ids=[f"{'x'.join(map(str, SCAN_CASES[c[0]][0]))}_k{c[1]}_p{c[2]}" for c in FUSED_SCAN_CASES])
+def test_scan_fused_topk(cc, orc, case):
+    # the selection fused into the scan: each filter's K best keys equal the
+    # oracle's selection over its full score map (same tie-break keys)
+    import torch
+    ci, k, prec = case
+    ext, T, J, nf, nfac, kind, mode = SCAN_CASES[ci]
+    _say("scan fused", case)
+    rng = np.random.default_rng(nf + J + 100)
+    shape = ext[::-1]
+    if len(ext) == 2 and min(ext) >= 60:
+        x = syn.channel_image_2d(ext[0], ext[1], 8, nfac, seed=nf)
+    else:
+        x = rng.integers(0, nfac, size=shape).astype(np.int8)
+    a_gpu, _ = cc.dwt(_t(x), J)
+    nb, mb = _events(rng, T, J, nf, nfac, kind)
+    real = rng.integers(0, 50, size=nf).astype(np.int32)
+    step = rng.integers(0, 5000, size=nf).astype(np.int64)
+    seed = 4242
+    S, keys = cc.ccf_scan(ext, J, nfac - 1, a_gpu, T, _t(nb, np.int32), _t(mb, np.int32), score_mode=mode,
+                          precision=prec, top_k=k, seed=seed, realization=_t(real), step=_t(step),
+                          want_scores=(ci % 2 == 0))
+    torch.cuda.synchronize()
+    keys = keys.cpu().numpy().view(np.uint64)
+    a_orc, _ = orc.dwt(x, J)
+    b = 2 ** J
+    cand = [(ext[a] - T[a]) // b + 1 for a in range(len(ext))]
+    for f in range(nf):
+        Sf = orc.scores(a_orc, cand, nb[f], mb[f], b ** len(ext), mode=mode)
+        _, want = orc.select(Sf, None, k, seed, int(real[f]), int(step[f]))
+        assert np.array_equal(keys[f], want), f"filter {f}"
+        if S is not None:
+            assert np.array_equal(S[f].cpu().numpy().astype(np.int64), Sf.ravel()), f"filter {f}"
+
+
+@pytest.mark.timeout(600)
+def test_scan_fused_c5_shape_full(cc, orc):
+    # the fused scan at the largest batched shape (1000^2 TI, T 48, J 2, an
+    # L-shaped overlap of 63 level-J blocks, 448 filters), as the benchmark
+    # times it: every filter's 10 best keys against the oracle
+    import torch
+    p, ti, _ = wl.make("c5_learned", n_real=1)
+    level, T, OV = p["level"], p["tmpl"], p["overlap"]
+    b = 2 ** level
+    tc = [-(-t // b) for t in T]
+    nf = 448
+    _say("scan fused c5 shape", nf)
+    u = np.zeros((T[1], T[0]), bool)
+    u[:OV[1], :] = True
+    u[:, :OV[0]] = True
+    pad = np.zeros((tc[1] * b, tc[0] * b), int)
+    pad[:T[1], :T[0]] = u
+    n_beta = pad.reshape(tc[1], b, tc[0], b).sum(axis=(1, 3))
+    rng = np.random.default_rng(7)
+    nb = np.broadcast_to(n_beta, (nf,) + n_beta.shape).astype(np.int32).copy()
+    mb = (rng.integers(0, p["n_facies"], size=nb.shape) * nb).astype(np.int32)
+    real = np.arange(nf, dtype=np.int32) % 16
+    step = np.arange(nf, dtype=np.int64) * 7
+    a_gpu, _ = cc.dwt(_t(ti), level)
+    _, keys = cc.ccf_scan(p["ti"], level, p["n_facies"] - 1, a_gpu, T, _t(nb), _t(mb), top_k=10, seed=9,
+                          realization=_t(real), step=_t(step))
+    torch.cuda.synchronize()
+    keys = keys.cpu().numpy().view(np.uint64)
+    a_orc, _ = orc.dwt(ti, level)
+    cand = [(p["ti"][a] - T[a]) // b + 1 for a in range(2)]
+    for f in range(0, nf, 7):
+        Sf = orc.scores(a_orc, cand, nb[f], mb[f], b * b)
+        _, want = orc.select(Sf, None, 10, 9, int(real[f]), int(step[f]))
+        assert np.array_equal(keys[f], want), f"filter {f}"
+
+
 def test_scan_rejects_inexact_range(cc):
     x = np.zeros((64, 64), dtype=np.int8)
     a, _ = cc.dwt(_t(x), 3)   # |beta| = 64: block sums up to 64 * 126 > 2048
