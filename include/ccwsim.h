@@ -183,6 +183,26 @@ int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max
                     const int32_t* realization, const int64_t* step, uint64_t* topk_keys, void* workspace,
                     int64_t workspace_bytes, void* stream);
 
+/* ---- the scan without a workspace -----------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).
+ * ccwsim_ccf_scan_noalloc computes exactly what ccwsim_ccf_scan computes
+ * (same arguments, same outputs, which the caller still owns) but keeps its
+ * temporaries in a static device array of ccwsim_ccf_scan_noalloc_capacity()
+ * bytes (64 MiB) that every device the library runs on holds from module
+ * load until the process ends; it calls no allocator and records no
+ * profiler events.  A call whose temporaries (the value
+ * ccwsim_ccf_scan_workspace_size returns for the same arguments) exceed the
+ * array returns CCWSIM_ERR_UNSUPPORTED before launching anything.  All calls
+ * on one device share that device's array: calls that overlap in time on
+ * one device (different streams or host threads) race and must not be
+ * issued; nothing in the array needs clearing between calls. */
+int64_t ccwsim_ccf_scan_noalloc_capacity(void);
+int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code, int32_t precision,
+                            const int32_t* approx, const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
+                            int32_t n_filters, int32_t score_mode, int32_t* scores, int32_t top_k, uint64_t seed,
+                            const int32_t* realization, const int64_t* step, uint64_t* topk_keys, void* stream);
+
 /* ---- A6: top-K and draw (Sec. 4.4; Algorithm 1, K best and random draw) ---
  * For each filter f, candidates are ordered by the key
  *   (min(mismatch, 4095), S + 2^31, pi(index))

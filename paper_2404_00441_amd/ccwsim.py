@@ -67,6 +67,10 @@ def load():
     L.ccwsim_dwt.argtypes = [p, Shape, i32, p, p, p]
     L.ccwsim_ccf_scan_workspace_size.restype = i64
     L.ccwsim_ccf_scan_workspace_size.argtypes = [Shape, i32, i32, i32, i32, p, i32, i32, i32, i32, i32]
+    L.ccwsim_ccf_scan_noalloc_capacity.restype = i64
+    L.ccwsim_ccf_scan_noalloc_capacity.argtypes = []
+    L.ccwsim_ccf_scan_noalloc.restype = ctypes.c_int
+    L.ccwsim_ccf_scan_noalloc.argtypes = [Shape, i32, i32, i32, i32, p, p, p, p, i32, i32, p, i32, u64, p, p, p, p]
     L.ccwsim_ccf_scan.restype = ctypes.c_int
     L.ccwsim_ccf_scan.argtypes = [Shape, i32, i32, i32, i32, p, p, p, p, i32, i32, p, i32, u64, p, p, p, p, i64, p]
     L.ccwsim_select.restype = ctypes.c_int
@@ -108,7 +112,8 @@ def load():
 
 
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
-           "ccwsim_ccf_scan", "ccwsim_ccf_scan_workspace_size", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
+           "ccwsim_ccf_scan", "ccwsim_ccf_scan_workspace_size", "ccwsim_ccf_scan_noalloc",
+           "ccwsim_ccf_scan_noalloc_capacity", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",

@@ -209,7 +209,7 @@ struct ProfScope {
   int kind;
   hipEvent_t a = nullptr;
   ProfScope(int k, hipStream_t s) : st(s), kind(k) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || k < 0) return;
     a = prof_event();
     if (a) (void)hipEventRecord(a, st);
   }
@@ -230,7 +230,7 @@ struct ProfKernel {
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
   explicit ProfKernel(int k) : kind(k) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || k < 0) return;
     a = prof_event();
     b = a ? prof_event() : nullptr;
     if (!b && a) {
@@ -550,7 +550,10 @@ int scan_plan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code,
 int enqueue_scan(const ScanPlan& sp, int32_t precision, int32_t score_mode, const int32_t* approx,
                  const int32_t* or_n, const int32_t* or_m, int32_t n_filters, int32_t* scores, int32_t top_k,
                  uint64_t seed, const int32_t* realization, const int64_t* step, uint64_t* topk_keys,
-                 unsigned char* ws, hipStream_t st) {
+                 unsigned char* ws, hipStream_t st, bool profile = true) {
+  // the profiler's events are created on demand, so a caller that must not
+  // allocate runs without them
+  const int kEn = profile ? CCWSIM_KIND_ENERGY : -1, kSc = profile ? CCWSIM_KIND_SCAN : -1;
   const Geom& g = sp.g;
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
   void* Kh = ws + sp.ws_kh;
@@ -574,7 +577,7 @@ int enqueue_scan(const ScanPlan& sp, int32_t precision, int32_t score_mode, cons
   if (sp.full) {
     // the whole score map: energies written first, the scan completes them
     if (score_mode == 0) {
-      ProfScope ps(CCWSIM_KIND_ENERGY, st);
+      ProfScope ps(kEn, st);
       k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, scores, g);
     }
     int G = 1;
@@ -591,7 +594,7 @@ int enqueue_scan(const ScanPlan& sp, int32_t precision, int32_t score_mode, cons
       G = kScanFilterMajor;
     }
     a.scores = scores;
-    ProfKernel pk(CCWSIM_KIND_SCAN);
+    ProfKernel pk(kSc);
     const int Gt = G == kScanFilterMajor ? 1 : G;
     launch_scan(precision, G, (unsigned)crow, (ntiles + Gt - 1) / Gt, scan_group_lds(nrows, sp.W, sp.kpad, Gt), st,
                 a, pk.a, pk.b);
@@ -607,7 +610,7 @@ int enqueue_scan(const ScanPlan& sp, int32_t precision, int32_t score_mode, cons
       a.nbuf = nbuf;
     } else if (score_mode == 0) {
       energy = (int32_t*)(ws + sp.ws_energy);
-      ProfScope ps(CCWSIM_KIND_ENERGY, st);
+      ProfScope ps(kEn, st);
       k_energy<<<nblocks((long long)n_filters * g.ncand), kThreads, 0, st>>>(approx, or_n, n_filters, energy, g);
     }
     uint64_t* keys = (uint64_t*)(ws + sp.ws_keys);
@@ -628,7 +631,7 @@ int enqueue_scan(const ScanPlan& sp, int32_t precision, int32_t score_mode, cons
     a.kpad = sp.sel_kk;
     a.W = sp.sel_W;
     {
-      ProfKernel pk(CCWSIM_KIND_SCAN);
+      ProfKernel pk(kSc);
       launch_scan_sel(precision, false, sp.en, (unsigned)crow, ntiles, sp.sel_lds, st, a, pk.a, pk.b);
     }
     k_topk_rows<<<(unsigned)n_filters, kThreads, 0, st>>>(keys, rowmin, rowcnt, g, k, seed, realization, step,
@@ -665,6 +668,55 @@ extern "C" int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, 
   if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   return enqueue_scan(sp, precision, score_mode, approx, or_n, or_m, n_filters, scores, top_k, seed, realization,
                       step, topk_keys, (unsigned char*)workspace, as_stream(stream));
+}
+
+// ---- the scan without a workspace: temporaries in a static device array ----
+namespace {
+constexpr size_t kScratchBytes = 64ull << 20;
+// One copy per device, held from module load until the process ends.  In
+// host code its name is only a stand-in: kernels receive the device address
+// that hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;   // device -> address of its scratch
+
+int scratch_of_current_device(unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CCWSIM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, (unsigned char*)ptr).first;
+  }
+  *out = it->second;
+  return CCWSIM_OK;
+}
+}  // namespace
+
+extern "C" int64_t ccwsim_ccf_scan_noalloc_capacity(void) { return (int64_t)kScratchBytes; }
+
+extern "C" int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max_code,
+                                       int32_t precision, const int32_t* approx, const int32_t tmpl[3],
+                                       const int32_t* or_n, const int32_t* or_m, int32_t n_filters,
+                                       int32_t score_mode, int32_t* scores, int32_t top_k, uint64_t seed,
+                                       const int32_t* realization, const int64_t* step, uint64_t* topk_keys,
+                                       void* stream) {
+  ScanPlan sp;
+  CCW_TRY(scan_plan(ti, level, wavelet, max_code, precision, tmpl, n_filters, score_mode, top_k, scores != nullptr,
+                    topk_keys != nullptr, sp));
+  if (!approx || !or_m || (score_mode == 0 && !or_n)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (topk_keys && (!realization || !step)) return fail(CCWSIM_ERR_INVALID_ARG, "top-K keys need realization and step");
+  if ((size_t)sp.ws_total > kScratchBytes)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "this scan needs %lld bytes of temporaries; the static scratch holds %zu",
+                (long long)sp.ws_total, kScratchBytes);
+  unsigned char* ptr = nullptr;
+  CCW_TRY(scratch_of_current_device(&ptr));
+  return enqueue_scan(sp, precision, score_mode, approx, or_n, or_m, n_filters, scores, top_k, seed, realization,
+                      step, topk_keys, ptr, as_stream(stream), false);
 }
 
 // ===========================================================================
