@@ -332,3 +332,69 @@ def approx53(img: np.ndarray, level: int) -> np.ndarray:
     e = (ctypes.c_int64 * 3)(*[int(v) for v in ext])
     _check(lib().orc_approx53(_ptr(img), e, img.ndim, level, _ptr(out)), "orc_approx53")
     return out
+
+
+def _pad_edge(ti: np.ndarray, level: int) -> np.ndarray:
+    """The image extended by edge replication to a multiple of 2^J per axis."""
+    b = 2 ** level
+    pad = [(0, (-n) % b) for n in ti.shape]
+    return np.pad(np.asarray(ti, dtype=np.int64), pad, mode="edge")
+
+
+def _lines(arr: np.ndarray, axis: int, fn):
+    """Apply a 1D routine to every line of arr along numpy axis `axis`."""
+    a = np.moveaxis(arr, axis, -1)
+    flat = a.reshape(-1, a.shape[-1])
+    outs = [fn(flat[i]) for i in range(flat.shape[0])]
+    return outs, a.shape[:-1]
+
+
+def dwt53(ti: np.ndarray, level: int):
+    """Level-J LeGall 5/3 integer DWT of an image in numpy order, extended by
+    edge replication to a multiple of 2^J per axis (Sec. 4.2 makes the mother
+    wavelet a choice; the lifting steps are those of lift53_forward).  Per
+    level the lifting runs along x, then y, then z; sub-band q of level j has
+    bit a set when axis a took the high-pass.  Returns (approx, details) in
+    the layout of dwt(): details[j-1] is (2^d - 1, *grid_j)."""
+    cur = _pad_edge(ti, level)
+    nd = cur.ndim
+    details = []
+    for _ in range(level):
+        bands = {0: cur}
+        for a in range(nd):            # x, y, z
+            ax = nd - 1 - a            # numpy axis of x is the last
+            nxt = {}
+            for q, arr in bands.items():
+                outs, lead = _lines(arr, ax, lift53_forward)
+                lo = np.stack([o[0] for o in outs]).reshape(lead + (-1,))
+                hi = np.stack([o[1] for o in outs]).reshape(lead + (-1,))
+                nxt[q] = np.moveaxis(lo, -1, ax)
+                nxt[q | (1 << a)] = np.moveaxis(hi, -1, ax)
+            bands = nxt
+        cur = bands[0]
+        details.append(np.stack([bands[q] for q in range(1, 2 ** nd)]))
+    return cur, details
+
+
+def idwt53(approx: np.ndarray, details) -> np.ndarray:
+    """Inverse of dwt53: the padded image, exactly (perfect reconstruction
+    of the integer lifting, lift53_inverse line by line)."""
+    cur = np.asarray(approx, dtype=np.int64)
+    nd = cur.ndim
+    for det in reversed(details):
+        bands = {0: cur}
+        for q in range(1, 2 ** nd):
+            bands[q] = np.asarray(det[q - 1], dtype=np.int64)
+        for a in reversed(range(nd)):  # z, y, x
+            ax = nd - 1 - a
+            nxt = {}
+            for q in [q for q in bands if not (q >> a) & 1]:
+                lo, hi = bands[q], bands[q | (1 << a)]
+                L = np.moveaxis(lo, ax, -1)
+                H = np.moveaxis(hi, ax, -1)
+                fl, fh = L.reshape(-1, L.shape[-1]), H.reshape(-1, H.shape[-1])
+                rec = np.stack([lift53_inverse(fl[i], fh[i]) for i in range(fl.shape[0])])
+                nxt[q] = np.moveaxis(rec.reshape(L.shape[:-1] + (-1,)), -1, ax)
+            bands = nxt
+        cur = bands[0]
+    return cur

@@ -579,3 +579,38 @@ def test_approx53_is_separable_lifting():
     ref = np.apply_along_axis(lambda v: o.lift53_forward(v)[0], 1, ref)
     ref = np.apply_along_axis(lambda v: o.lift53_forward(v)[0], 0, ref)
     assert np.array_equal(a3, ref)
+
+
+# --------------------------------------------------------------------------
+# The full LeGall 5/3 transform (approximation and every detail sub-band)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,J", [((37, 22), 2), ((16, 16), 3), ((9, 12, 10), 1), ((20, 18, 12), 2), ((5, 7), 0)])
+def test_dwt53_perfect_reconstruction(orc, shape, J):
+    # the integer lifting is exactly invertible: the inverse returns the
+    # edge-replicated image
+    x = np.random.default_rng(sum(shape) + J).integers(0, 3, size=shape).astype(np.int8)
+    a, d = orc.dwt53(x, J)
+    assert np.array_equal(orc.idwt53(a, d), orc._pad_edge(x, J))
+    assert len(d) == J
+
+
+@pytest.mark.parametrize("shape,J", [((37, 22), 2), ((20, 18, 12), 2), ((32, 24), 3)])
+def test_dwt53_approximation_equals_approx53(orc, shape, J):
+    # the approximation band agrees with the level-J approximation routine
+    # (written separately in C)
+    x = np.random.default_rng(7 + J).integers(0, 3, size=shape).astype(np.int8)
+    a, _ = orc.dwt53(x, J)
+    assert np.array_equal(a, orc.approx53(orc._pad_edge(x, J), J))
+
+
+def test_dwt53_constant_and_ramp(orc):
+    # a constant has no detail and keeps its value; a ramp along x has zero
+    # detail except where the mirror at the far edge bends it, and nothing in
+    # the sub-bands that took the high-pass along y
+    a, d = orc.dwt53(np.full((8, 12), 2, np.int8), 2)
+    assert (a == 2).all() and all((dd == 0).all() for dd in d)
+    x = np.tile(np.arange(16, dtype=np.int8), (6, 1))   # [y][x], ramp along x
+    a, d = orc.dwt53(x, 1)
+    q1, q2, q3 = d[0]
+    assert (q2 == 0).all() and (q3 == 0).all()
+    assert (q1[:, :-1] == 0).all() and (q1[:, -1] == 1).all()
