@@ -128,19 +128,27 @@ typedef struct {
                            Needs shortlist 0 and proposer_dim 0.          */
 } ccwsim_params;
 
-/* ---- A1: training-image transform (Sec. 3.1; Algorithm 1, DWT of TI) ---
- * Level-J Haar DWT of x (int8, extent s).  The image is extended by edge
- * replication to Np = ceil(n / 2^J) * 2^J per used axis.
- *   approx:  level-J approximation = integer block sums, G = Np / 2^J cells
- *            per used axis, int32.
+/* ---- A1: training-image transform (Sec. 3.1 DWT; Sec. 4.2 the mother
+ * wavelet; Algorithm 1, DWT of TI) ---
+ * Level-J DWT of x (int8, extent s) with wavelet 0 (Haar, in the integer
+ * form above) or 1 (LeGall 5/3 integer lifting: per line d[k] = x[2k+1] -
+ * floor((x[2k] + x[2k+2]) / 2), s[k] = x[2k] + floor((d[k-1] + d[k] + 2) / 4),
+ * whole-sample symmetric extension, x then y then z per level).  The image
+ * is extended by edge replication to Np = ceil(n / 2^J) * 2^J per used axis.
+ *   approx:  level-J approximation, G = Np / 2^J cells per used axis, int32
+ *            (for Haar the integer block sums).
  *   details: for j = 1..J, for sub-band q = 1 .. 2^ndim - 1 (bit a of q set
  *            when axis a took the high-pass), Np / 2^j cells per used axis,
  *            int32; levels concatenated in increasing j.
- * ccwsim_dwt_sizes returns the element counts of both outputs (host call,
- * no device work).  Returns CCWSIM_ERR_SHAPE for bad extents or J > 6. */
-int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int64_t* n_approx, int64_t* n_details);
-int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t* approx,
-               int32_t* details, void* stream);
+ *   workspace: device memory of workspace_bytes (ccwsim_dwt_sizes), 256-byte
+ *            aligned, owned by the caller (may be NULL when 0 bytes).
+ * ccwsim_dwt_sizes returns the element counts of both outputs and the
+ * workspace bytes (host call, no device work).  Returns CCWSIM_ERR_SHAPE for
+ * bad extents or J > 6, CCWSIM_ERR_INVALID_ARG for another wavelet. */
+int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int32_t wavelet, int64_t* n_approx, int64_t* n_details,
+                     int64_t* workspace_bytes);
+int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t wavelet, int32_t* approx, int32_t* details,
+               void* workspace, int64_t workspace_bytes, void* stream);
 
 /* ---- A3/A4 (+A6): CCW scan (Sec. 4.3, CCW equation; Sec. 4.4 K best) ----
  * Scores every candidate of the TI approximation grid against n_filters
@@ -224,13 +232,18 @@ int ccwsim_select(const int32_t* scores, const uint16_t* mismatch, int64_t n_can
 /* ---- A7: inverse DWT of chosen patterns (Sec. 3.1; Algorithm 1 Inv-DWT) ---
  * Rebuilds n patterns of extent `patch` (fine cells, <= 64 x 64 x 64 and
  * <= 16384 cells) whose level-J block origins are block_origins (int32
- * [n][3], x y z) from the approx/details layout of ccwsim_dwt of a TI of
- * extent ti.  patches: int8 [n][patch cells].  The block range
- * [origin, origin + ceil(patch / 2^J)) must lie inside the approximation
- * grid; a pattern whose origin does not is filled with -1. */
-int ccwsim_idwt(const int32_t* approx, const int32_t* details, ccwsim_shape ti, int32_t level,
-                const int32_t* block_origins, int32_t n, const int32_t patch[3], int8_t* patches,
-                void* stream);
+ * [n][3], x y z) from the approx/details layout of ccwsim_dwt (same
+ * wavelet) of a TI of extent ti.  patches: int8 [n][patch cells].  The block
+ * range [origin, origin + ceil(patch / 2^J)) must lie inside the
+ * approximation grid; a pattern whose origin does not is filled with -1.
+ * Haar rebuilds each pattern from its own blocks' coefficients and needs no
+ * workspace; LeGall 5/3 (whose synthesis filters reach across blocks)
+ * inverts the whole image into the workspace (ccwsim_idwt_workspace_size
+ * bytes, 256-byte aligned, caller-owned) and crops the patterns from it. */
+int64_t ccwsim_idwt_workspace_size(ccwsim_shape ti, int32_t level, int32_t wavelet);
+int ccwsim_idwt(const int32_t* approx, const int32_t* details, ccwsim_shape ti, int32_t level, int32_t wavelet,
+                const int32_t* block_origins, int32_t n, const int32_t patch[3], int8_t* patches, void* workspace,
+                int64_t workspace_bytes, void* stream);
 
 /* ---- whole hot path (Algorithm 1 and the conditioning of Sec. 4.4) --------
  * Simulates p->n_real realizations of p->grid from the TI (device int8).

@@ -62,9 +62,9 @@ def load():
     L.ccwsim_last_error.restype = ctypes.c_char_p
     L.ccwsim_last_error.argtypes = []
     L.ccwsim_dwt_sizes.restype = ctypes.c_int
-    L.ccwsim_dwt_sizes.argtypes = [Shape, i32, p, p]
+    L.ccwsim_dwt_sizes.argtypes = [Shape, i32, i32, p, p, p]
     L.ccwsim_dwt.restype = ctypes.c_int
-    L.ccwsim_dwt.argtypes = [p, Shape, i32, p, p, p]
+    L.ccwsim_dwt.argtypes = [p, Shape, i32, i32, p, p, p, i64, p]
     L.ccwsim_ccf_scan_workspace_size.restype = i64
     L.ccwsim_ccf_scan_workspace_size.argtypes = [Shape, i32, i32, i32, i32, p, i32, i32, i32, i32, i32]
     L.ccwsim_ccf_scan_noalloc_capacity.restype = i64
@@ -75,8 +75,10 @@ def load():
     L.ccwsim_ccf_scan.argtypes = [Shape, i32, i32, i32, i32, p, p, p, p, i32, i32, p, i32, u64, p, p, p, p, i64, p]
     L.ccwsim_select.restype = ctypes.c_int
     L.ccwsim_select.argtypes = [p, p, i64, i32, i32, u64, p, p, p, p, p]
+    L.ccwsim_idwt_workspace_size.restype = i64
+    L.ccwsim_idwt_workspace_size.argtypes = [Shape, i32, i32]
     L.ccwsim_idwt.restype = ctypes.c_int
-    L.ccwsim_idwt.argtypes = [p, p, Shape, i32, p, i32, p, p, p]
+    L.ccwsim_idwt.argtypes = [p, p, Shape, i32, i32, p, i32, p, p, p, i64, p]
     L.ccwsim_simulate_workspace_size.restype = i64
     L.ccwsim_simulate_workspace_size.argtypes = [p]
     L.ccwsim_simulate.restype = ctypes.c_int
@@ -113,7 +115,7 @@ def load():
 
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_ccf_scan_workspace_size", "ccwsim_ccf_scan_noalloc",
-           "ccwsim_ccf_scan_noalloc_capacity", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
+           "ccwsim_ccf_scan_noalloc_capacity", "ccwsim_idwt_workspace_size", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
@@ -187,24 +189,25 @@ def params_of(p: dict) -> Params:
 
 
 # ---------------------------------------------------------------------------
-def dwt_sizes(extent, level):
-    na, nd = ctypes.c_int64(), ctypes.c_int64()
-    _check("ccwsim_dwt_sizes", load().ccwsim_dwt_sizes(shape_of(extent), level, ctypes.byref(na),
-                                                       ctypes.byref(nd)))
-    return na.value, nd.value
+def dwt_sizes(extent, level, wavelet=0):
+    na, nd, nw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check("ccwsim_dwt_sizes", load().ccwsim_dwt_sizes(shape_of(extent), level, wavelet, ctypes.byref(na),
+                                                       ctypes.byref(nd), ctypes.byref(nw)))
+    return na.value, nd.value, nw.value
 
 
-def dwt(x: torch.Tensor, level: int):
+def dwt(x: torch.Tensor, level: int, wavelet: int = 0):
     """x: int8 GPU tensor in numpy order ([y][x] or [z][y][x]).
     Returns (approx int32 [grid], details int32 flat)."""
     extent = tuple(x.shape[::-1])
-    na, nd = dwt_sizes(extent, level)
+    na, nd, nw = dwt_sizes(extent, level, wavelet)
     b = 2 ** level
     grid = tuple(-(-n // b) for n in x.shape)
     approx = torch.empty(grid, dtype=torch.int32, device=x.device)
     details = torch.empty(max(nd, 1), dtype=torch.int32, device=x.device)
-    _check("ccwsim_dwt", load().ccwsim_dwt(_ptr(x), shape_of(extent), level, _ptr(approx), _ptr(details),
-                                           _stream()))
+    _, ws = _aligned_workspace(nw, x.device)
+    _check("ccwsim_dwt", load().ccwsim_dwt(_ptr(x), shape_of(extent), level, wavelet, _ptr(approx), _ptr(details),
+                                           _ptr(ws), nw, _stream()))
     return approx, details[:nd]
 
 
@@ -272,13 +275,17 @@ def select(scores, mismatch, top_k, seed, realization, step, want_keys=False):
     return chosen, keys
 
 
-def idwt(approx, details, ti_extent, level, origins, patch):
+def idwt(approx, details, ti_extent, level, origins, patch, wavelet=0):
     """origins int32 [n, 3] (x, y, z block origins).  Returns int8 patterns
     [n, *patch numpy order]."""
     n = origins.shape[0]
     out = torch.empty((n,) + tuple(patch[::-1]), dtype=torch.int8, device=approx.device)
-    _check("ccwsim_idwt", load().ccwsim_idwt(_ptr(approx), _ptr(details), shape_of(ti_extent), level,
-                                             _ptr(origins), n, _i3(patch, 1), _ptr(out), _stream()))
+    nw = load().ccwsim_idwt_workspace_size(shape_of(ti_extent), level, wavelet)
+    if nw < 0:
+        raise CcwsimError("ccwsim_idwt_workspace_size", 1, load().ccwsim_last_error().decode())
+    _, ws = _aligned_workspace(nw, approx.device)
+    _check("ccwsim_idwt", load().ccwsim_idwt(_ptr(approx), _ptr(details), shape_of(ti_extent), level, wavelet,
+                                             _ptr(origins), n, _i3(patch, 1), _ptr(out), _ptr(ws), nw, _stream()))
     return out
 
 

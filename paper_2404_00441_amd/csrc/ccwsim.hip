@@ -296,28 +296,210 @@ int launch_dwt(const Geom& g, const int8_t* x, int32_t* approx, _Float16* approx
 
 }  // namespace
 
-extern "C" int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int64_t* n_approx, int64_t* n_details) {
-  Geom g;
-  CCW_TRY(geom_ti(g, s, level));
-  if (n_approx) *n_approx = (int64_t)g.G[0] * g.G[1] * g.G[2];
-  if (n_details) *n_details = g.det_total;
+// ---- LeGall 5/3 transform with every sub-band (Sec. 4.2: the mother
+// wavelet is a choice).  Integer lifting on even-length lines with
+// whole-sample symmetric extension: d[k] = x[2k+1] - floor((x[2k] +
+// x[2k+2]) / 2), s[k] = x[2k] + floor((d[k-1] + d[k] + 2) / 4), with the
+// mirrored x[n] = x[n-2] and d[-1] = d[0].  Per level the lines run along
+// x, then y, then z.  Bands live stacked in one buffer ([band][z][y][x]); a
+// pass along axis a turns bands q < 2^a into q (low half) and q + 2^a (high
+// half), so after the level's last pass band q has bit a set when axis a
+// took the high-pass, the layout of the detail sub-bands.
+namespace {
+
+// The TI edge-replicated to the padded extent, int32.
+__global__ void k_pad_ti(const int8_t* __restrict__ ti, int32_t* __restrict__ out, Geom g) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)g.np[0] * g.np[1] * g.np[2];
+  if (id >= n) return;
+  const int x = (int)(id % g.np[0]), y = (int)((id / g.np[0]) % g.np[1]), z = (int)(id / ((long long)g.np[0] * g.np[1]));
+  out[id] = ti[idx3(min(x, g.ti[0] - 1), min(y, g.ti[1] - 1), min(z, g.ti[2] - 1), g.ti)];
+}
+
+// One forward pass along `axis` over nb stacked bands of extent e; one
+// thread per output position (k, and the other coordinates) of one band.
+__global__ void k_lift53_fwd(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int e0, int e1, int e2,
+                             int axis, int nb) {
+  const int e[3] = {e0, e1, e2};
+  int eo[3] = {e0, e1, e2};
+  eo[axis] >>= 1;
+  const long long half = (long long)eo[0] * eo[1] * eo[2];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= half * nb) return;
+  const int q = (int)(id / half);
+  const long long r = id - q * half;
+  int u[3] = {(int)(r % eo[0]), (int)((r / eo[0]) % eo[1]), (int)(r / ((long long)eo[0] * eo[1]))};
+  const int k = u[axis], n = e[axis];
+  const long long full = (long long)e0 * e1 * e2;
+  const int32_t* line = src + q * full;
+  const long long st = axis == 0 ? 1 : axis == 1 ? e0 : (long long)e0 * e1;
+  u[axis] = 0;
+  const long long base = u[0] + (long long)e0 * (u[1] + (long long)e1 * u[2]);
+  auto X = [&](int i) {   // mirrored sample
+    i = i < 0 ? -i : i;
+    i = i >= n ? 2 * (n - 1) - i : i;
+    return line[base + st * i];
+  };
+  const int x0 = X(2 * k), x1 = X(2 * k + 1), x2 = X(2 * k + 2);
+  const int dk = x1 - ((x0 + x2) >> 1);
+  const int dl = k == 0 ? dk : X(2 * k - 1) - ((X(2 * k - 2) + x0) >> 1);
+  const int sk = x0 + ((dl + dk + 2) >> 2);
+  u[axis] = k;
+  const long long o = u[0] + (long long)eo[0] * (u[1] + (long long)eo[1] * u[2]);
+  dst[q * half + o] = sk;
+  dst[(q + nb) * half + o] = dk;
+}
+
+// One inverse pass along `axis`: bands q and q + nb (extent with axis
+// halved) of src become band q of dst (extent eo); one thread per output
+// pair x[2k], x[2k+1].
+__global__ void k_lift53_inv(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int eo0, int eo1, int eo2,
+                             int axis, int nb) {
+  int ei[3] = {eo0, eo1, eo2};
+  ei[axis] >>= 1;
+  const long long half = (long long)ei[0] * ei[1] * ei[2];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= half * nb) return;
+  const int q = (int)(id / half);
+  const long long r = id - q * half;
+  int u[3] = {(int)(r % ei[0]), (int)((r / ei[0]) % ei[1]), (int)(r / ((long long)ei[0] * ei[1]))};
+  const int k = u[axis], h = ei[axis];
+  const long long st = axis == 0 ? 1 : axis == 1 ? ei[0] : (long long)ei[0] * ei[1];
+  u[axis] = 0;
+  const long long base = u[0] + (long long)ei[0] * (u[1] + (long long)ei[1] * u[2]);
+  const int32_t* S = src + q * half + base;
+  const int32_t* D = src + (q + nb) * half + base;
+  const int dk = D[st * k];
+  const int dl = k == 0 ? dk : D[st * (k - 1)];
+  const int xe = S[st * k] - ((dl + dk + 2) >> 2);
+  int xn = xe;   // x[2k + 2], mirrored to x[2k] past the end
+  if (k + 1 < h) xn = S[st * (k + 1)] - ((dk + D[st * (k + 1)] + 2) >> 2);
+  const int xo = dk + ((xe + xn) >> 1);
+  const long long so = axis == 0 ? 1 : axis == 1 ? eo0 : (long long)eo0 * eo1;
+  u[axis] = 2 * k;
+  const long long o = u[0] + (long long)eo0 * (u[1] + (long long)eo1 * u[2]);
+  dst[q * (half * 2) + o] = xe;
+  dst[q * (half * 2) + o + so] = xo;
+}
+
+// Workspace of the 5/3 transforms: three buffers of the padded TI (int32).
+long long lift53_ws_bytes(const Geom& g) { return 3 * align256((long long)g.np[0] * g.np[1] * g.np[2] * 4); }
+
+// Level-J 5/3 DWT of the TI into approx and the detail layout of the Haar
+// path.
+int launch_dwt53(const Geom& g, const int8_t* x, int32_t* approx, int32_t* details, unsigned char* ws, hipStream_t st) {
+  const long long npc = (long long)g.np[0] * g.np[1] * g.np[2];
+  int32_t* C = (int32_t*)ws;
+  int32_t* A = (int32_t*)(ws + align256(npc * 4));
+  int32_t* B = (int32_t*)(ws + 2 * align256(npc * 4));
+  k_pad_ti<<<nblocks(npc), kThreads, 0, st>>>(x, C, g);
+  int e[3] = {g.np[0], g.np[1], g.np[2]};
+  const int nd = g.ndim;
+  if (g.level == 0) {
+    HIP_TRY(hipMemcpyAsync(approx, C, npc * 4, hipMemcpyDeviceToDevice, st));
+    return CCWSIM_OK;
+  }
+  for (int j = 1; j <= g.level; ++j) {
+    const int32_t* src = C;
+    int32_t* bufs[2] = {A, B};
+    int32_t* dst = nullptr;
+    for (int a = 0; a < nd; ++a) {
+      dst = bufs[a & 1];
+      const long long outc = (long long)e[0] * e[1] * e[2] / 2 * (1 << a);
+      k_lift53_fwd<<<nblocks(outc), kThreads, 0, st>>>(src, dst, e[0], e[1], e[2], a, 1 << a);
+      e[a] >>= 1;
+      src = dst;
+    }
+    const long long band = (long long)e[0] * e[1] * e[2];
+    HIP_TRY(hipMemcpyAsync(details + g.det_off[j], dst + band, band * ((1 << nd) - 1) * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(j == g.level ? approx : C, dst, band * 4, hipMemcpyDeviceToDevice, st));
+  }
+  HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }
 
-extern "C" int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t* approx,
-                          int32_t* details, void* stream) {
+// Full-image 5/3 inverse from approx and details into the workspace's first
+// buffer (the padded TI), then the patterns as crops of it.
+__global__ void k_crop_patterns(const int32_t* __restrict__ img, Geom g, const int32_t* __restrict__ origins,
+                                int n, int8_t* __restrict__ out) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)n * g.wcells) return;
+  const int p = (int)(id / g.wcells);
+  const int u = (int)(id - (long long)p * g.wcells);
+  const int c0[3] = {origins[3 * p], origins[3 * p + 1], origins[3 * p + 2]};
+  bool ok = true;
+  for (int d = 0; d < 3; ++d) ok = ok && c0[d] >= 0 && c0[d] + g.tc[d] <= g.G[d];
+  if (!ok) {
+    out[id] = -1;
+    return;
+  }
+  const int ux = u % g.T[0], uy = (u / g.T[0]) % g.T[1], uz = u / (g.T[0] * g.T[1]);
+  out[id] = (int8_t)img[idx3(c0[0] * g.b[0] + ux, c0[1] * g.b[1] + uy, c0[2] * g.b[2] + uz, g.np)];
+}
+
+int launch_idwt53(const Geom& g, const int32_t* approx, const int32_t* details, unsigned char* ws, hipStream_t st) {
+  const long long npc = (long long)g.np[0] * g.np[1] * g.np[2];
+  int32_t* C = (int32_t*)ws;
+  int32_t* A = (int32_t*)(ws + align256(npc * 4));
+  int32_t* B = (int32_t*)(ws + 2 * align256(npc * 4));
+  const int nd = g.ndim;
+  int e[3] = {g.G[0], g.G[1], g.G[2]};
+  if (g.level == 0) {
+    HIP_TRY(hipMemcpyAsync(C, approx, npc * 4, hipMemcpyDeviceToDevice, st));
+    return CCWSIM_OK;
+  }
+  const int32_t* cur = approx;
+  for (int j = g.level; j >= 1; --j) {
+    const long long band = (long long)e[0] * e[1] * e[2];
+    int32_t* bufs[2] = {A, B};
+    // stack the bands: the approximation of level j, then the details
+    HIP_TRY(hipMemcpyAsync(A, cur, band * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(A + band, details + g.det_off[j], band * ((1 << nd) - 1) * 4, hipMemcpyDeviceToDevice, st));
+    const int32_t* src = A;
+    int32_t* dst = nullptr;
+    for (int a = nd - 1, i = 1; a >= 0; --a, ++i) {
+      dst = (a == 0) ? C : bufs[i & 1];
+      e[a] <<= 1;
+      const long long pairs = (long long)e[0] * e[1] * e[2] / 2 * (1 << a);
+      k_lift53_inv<<<nblocks(pairs), kThreads, 0, st>>>(src, dst, e[0], e[1], e[2], a, 1 << a);
+      src = dst;
+    }
+    cur = C;
+  }
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+}  // namespace
+
+extern "C" int ccwsim_dwt_sizes(ccwsim_shape s, int32_t level, int32_t wavelet, int64_t* n_approx, int64_t* n_details,
+                                int64_t* workspace_bytes) {
   Geom g;
   CCW_TRY(geom_ti(g, s, level));
-  if (!x || !approx || (level > 0 && !details)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
-  hipStream_t st = as_stream(stream);
-  int32_t* tmp = nullptr;
-  if (level >= 2) {
-    const long long c1 = (long long)g.Gj[1][0] * g.Gj[1][1] * g.Gj[1][2];
-    HIP_TRY(hipMallocAsync((void**)&tmp, 2 * c1 * sizeof(int32_t), st));
+  if (wavelet != 0 && wavelet != 1) return fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (LeGall 5/3)");
+  if (n_approx) *n_approx = (int64_t)g.G[0] * g.G[1] * g.G[2];
+  if (n_details) *n_details = g.det_total;
+  if (workspace_bytes) {
+    const long long c1 = level >= 2 ? (long long)g.Gj[1][0] * g.Gj[1][1] * g.Gj[1][2] : 0;
+    *workspace_bytes = wavelet == 1 ? lift53_ws_bytes(g) : align256(2 * c1 * 4);
   }
-  const int rc = launch_dwt(g, x, approx, nullptr, details, tmp, st);
-  if (tmp) HIP_TRY(hipFreeAsync(tmp, st));
-  return rc;
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_dwt(const int8_t* x, ccwsim_shape s, int32_t level, int32_t wavelet, int32_t* approx,
+                          int32_t* details, void* workspace, int64_t workspace_bytes, void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, s, level));
+  if (wavelet != 0 && wavelet != 1) return fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (LeGall 5/3)");
+  if (!x || !approx || (level > 0 && !details)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  int64_t need = 0;
+  CCW_TRY(ccwsim_dwt_sizes(s, level, wavelet, nullptr, nullptr, &need));
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", (long long)need);
+  if (need > 0 && ((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  if (wavelet == 1) return launch_dwt53(g, x, approx, details, (unsigned char*)workspace, st);
+  return launch_dwt(g, x, approx, nullptr, details, level >= 2 ? (int32_t*)workspace : nullptr, st);
 }
 
 // ===========================================================================
@@ -800,11 +982,22 @@ __global__ __launch_bounds__(kThreads) void k_idwt(const int32_t* __restrict__ a
 
 }  // namespace
 
+extern "C" int64_t ccwsim_idwt_workspace_size(ccwsim_shape ti, int32_t level, int32_t wavelet) {
+  Geom g;
+  if (geom_ti(g, ti, level)) return -1;
+  if (wavelet != 0 && wavelet != 1) {
+    fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (LeGall 5/3)");
+    return -1;
+  }
+  return wavelet == 1 ? lift53_ws_bytes(g) : 0;
+}
+
 extern "C" int ccwsim_idwt(const int32_t* approx, const int32_t* details, ccwsim_shape ti, int32_t level,
-                           const int32_t* block_origins, int32_t n, const int32_t patch[3], int8_t* patches,
-                           void* stream) {
+                           int32_t wavelet, const int32_t* block_origins, int32_t n, const int32_t patch[3],
+                           int8_t* patches, void* workspace, int64_t workspace_bytes, void* stream) {
   Geom g;
   CCW_TRY(geom_ti(g, ti, level));
+  if (wavelet != 0 && wavelet != 1) return fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (LeGall 5/3)");
   if (!approx || !block_origins || !patches || !patch || (level > 0 && !details))
     return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
   if (n < 0) return fail(CCWSIM_ERR_INVALID_ARG, "n must be >= 0");
@@ -818,7 +1011,21 @@ extern "C" int ccwsim_idwt(const int32_t* approx, const int32_t* details, ccwsim
   g.tcells = (long long)g.tc[0] * g.tc[1] * g.tc[2];
   g.wcells = (long long)g.T[0] * g.T[1] * g.T[2];
   if (g.wcells > 16384) return fail(CCWSIM_ERR_UNSUPPORTED, "patch has more than 16384 cells");
+  if (wavelet == 1) {
+    const long long need = lift53_ws_bytes(g);
+    if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
+    if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  }
   if (n == 0) return CCWSIM_OK;
+  hipStream_t st53 = as_stream(stream);
+  if (wavelet == 1) {
+    // the whole padded image by the inverse lifting, then crops of it
+    CCW_TRY(launch_idwt53(g, approx, details, (unsigned char*)workspace, st53));
+    k_crop_patterns<<<nblocks((long long)n * g.wcells), kThreads, 0, st53>>>((const int32_t*)workspace, g, block_origins,
+                                                                            n, patches);
+    HIP_TRY(hipGetLastError());
+    return CCWSIM_OK;
+  }
   const long long bc = idwt_buf_cells(g);
   const size_t lds = (size_t)bc * 8 + (size_t)g.wcells;
   if (lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "pattern needs %zu bytes of LDS", lds);
@@ -3294,6 +3501,17 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
           }
           return CCWSIM_OK;
         };
+        // one untimed call first: the first call of a process pays one-time
+        // costs (kernel loading, cold caches) that would bias the first variant
+        P->scan_g = 1;
+        P->sel_rows = false;
+        P->sel_fused = P->sel_fused_ok;
+        rc = enqueue_simulate(P, p, ti, n_hd, hd_real, hd_pos, hd_val, out, chosen, workspace, st);
+        if (rc != CCWSIM_OK) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return rc;
+        }
         // the selection fused into the scan first (it writes the fewest keys)
         if (P->sel_fused_ok) try_variant(1, false, true);
         // the scan's layout and tiles with stored keys, then the row-minima

@@ -48,10 +48,10 @@ def test_status_strings(lib):
 
 def test_dwt_sizes_host_only(lib):
     from paper_2404_00441_amd import ccwsim
-    na, nd = ccwsim.dwt_sizes((500, 500), 2)
+    na, nd, _ = ccwsim.dwt_sizes((500, 500), 2)
     assert na == 125 * 125
     assert nd == 3 * 250 * 250 + 3 * 125 * 125
-    na, nd = ccwsim.dwt_sizes((180, 150, 60), 2)
+    na, nd, _ = ccwsim.dwt_sizes((180, 150, 60), 2)
     assert na == 45 * 38 * 15
     assert nd == 7 * (90 * 76 * 30) + 7 * (45 * 38 * 15)
     with pytest.raises(ccwsim.CcwsimError):

@@ -101,6 +101,50 @@ def test_idwt_parity(cc, orc, ext, patch, J):
         assert np.array_equal(pats[i].astype(np.int64), want)
 
 
+DWT53_CASES = [((13, 17), 1), ((150, 150), 1), ((500, 500), 2), ((61, 47), 3), ((33, 20), 0),
+               ((20, 18, 9), 2), ((180, 150, 60), 2), ((7, 9, 5), 1)]
+
+
+@pytest.mark.parametrize("shape,J", DWT53_CASES, ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in DWT53_CASES])
+def test_dwt53_parity(cc, orc, shape, J):
+    # the LeGall 5/3 transform with every sub-band, and its inverse: the
+    # approximation and details equal the oracle's, and the patterns rebuilt
+    # from them equal the edge-replicated image's windows
+    _say("dwt53", shape, J)
+    rng = np.random.default_rng(sum(shape) + J + 53)
+    if len(shape) == 2:
+        x = syn.channel_image_2d(shape[1], shape[0], 5, 3, seed=7) if min(shape) >= 40 else \
+            rng.integers(0, 3, size=shape).astype(np.int8)
+    else:
+        x = rng.integers(0, 2, size=shape).astype(np.int8)
+    a_gpu, d_gpu = cc.dwt(_t(x), J, wavelet=1)
+    a_orc, d_orc = orc.dwt53(x, J)
+    assert np.array_equal(a_gpu.cpu().numpy().astype(np.int64), a_orc)
+    if J > 0:
+        assert np.array_equal(d_gpu.cpu().numpy().astype(np.int64), orc.details_flat(d_orc))
+    # patterns from the coefficients
+    nd = len(shape)
+    ext = shape[::-1]
+    b = 2 ** J
+    G = [-(-e // b) for e in ext]
+    patch = [max(1, min(e, 11)) for e in ext]
+    tc = [-(-t // b) for t in patch]
+    n = 12
+    org = np.zeros((n, 3), dtype=np.int32)
+    for a in range(nd):
+        org[:, a] = rng.integers(0, G[a] - tc[a] + 1, size=n)
+        org[1, a] = G[a] - tc[a]
+    org[2, 0] = G[0]   # outside the grid: -1
+    pats = cc.idwt(a_gpu, d_gpu, ext, J, _t(org), patch, wavelet=1).cpu().numpy()
+    xp = orc.idwt53(a_orc, d_orc)
+    for i in range(n):
+        if i == 2:
+            assert (pats[i] == -1).all()
+            continue
+        sl = tuple(slice(b * org[i, a], b * org[i, a] + patch[a]) for a in range(nd))[::-1]
+        assert np.array_equal(pats[i].astype(np.int64), xp[sl]), i
+
+
 def test_idwt_rejects_origin_outside_grid(cc):
     x = np.random.default_rng(0).integers(0, 2, size=(40, 40)).astype(np.int8)
     a, d = cc.dwt(_t(x), 1)
