@@ -211,6 +211,50 @@ int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t wavelet, int
                             int32_t n_filters, int32_t score_mode, int32_t* scores, int32_t top_k, uint64_t seed,
                             const int32_t* realization, const int64_t* step, uint64_t* topk_keys, void* stream);
 
+/* ---- A9 learned proposer: encoders and training (Sec. 4.3: the search
+ * runs on the approximation coefficients; Sec. 4.4: the K best are drawn
+ * from) ----
+ * Two convolutional encoders over level-J approximation coefficients rank
+ * candidate positions for a data event; the exact CCW score of a shortlist
+ * then decides.  Key encoder: input K / |beta| (one channel, the TI's
+ * approximation grid); query encoder: input m / |beta| and n / |beta| over
+ * the event's T_c blocks (two channels, zero off the overlap; float32
+ * [batch][2][T_c,y][T_c,x]).  Each: 3x3 convolutions with dilations 1, 2, 4
+ * and 32 channels (ReLU), then a 1x1 convolution to 64 channels.  The key
+ * of candidate c is the key map at c + T_c / 2; the query is the query map
+ * at T_c / 2; the proposer's score is their dot product.  2D TIs only.
+ * Weights: one float32 buffer of n_weights values (key encoder layers 0..3,
+ * then the query encoder's; per layer weights [cout][cin][taps] then
+ * biases).
+ *   ccwsim_lp_sizes:  weights count, workspace bytes for `batch` events and
+ *                     the candidate count (host call, no device work);
+ *   ccwsim_lp_init:   He-uniform weights from the seed (biases zero);
+ *   ccwsim_lp_encode: keys float32 [n_cand][64], queries [batch][64] and
+ *                     scores [batch][n_cand] (each may be NULL);
+ *   ccwsim_lp_train_step: one Adam step (lr, beta 0.9 / 0.999, eps 1e-8,
+ *                     step >= 1 counts the updates) on the mean over the
+ *                     batch of the cross-entropy between the softmax of the
+ *                     scores over every candidate and the label (the
+ *                     candidate index with the best exact score); writes the
+ *                     per-example loss (float32 [batch]) and, when grad_out
+ *                     is not NULL, the gradient before the update;
+ *   ccwsim_lp_shortlist: the k (<= 256) highest scores' candidate indices
+ *                     per row of scores (ties to the smaller index; the
+ *                     order within a row is not significant).
+ * Every pointer is a device pointer owned by the caller; workspaces are
+ * 256-byte aligned. */
+int ccwsim_lp_sizes(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32_t batch, int64_t* n_weights,
+                    int64_t* workspace_bytes, int64_t* n_cand);
+int ccwsim_lp_init(float* weights, uint64_t seed, void* stream);
+int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccwsim_shape ti, int32_t level, const int32_t tmpl[3],
+                     const float* events, int32_t batch, float* keys_out, float* queries_out, float* scores_out,
+                     void* workspace, int64_t workspace_bytes, void* stream);
+int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr, const int32_t* approx,
+                         ccwsim_shape ti, int32_t level, const int32_t tmpl[3], const float* events,
+                         const int32_t* labels, int32_t batch, float* loss, float* grad_out, void* workspace,
+                         int64_t workspace_bytes, void* stream);
+int ccwsim_lp_shortlist(const float* scores, int32_t batch, int64_t n_cand, int32_t k, int32_t* idx_out, void* stream);
+
 /* ---- A6: top-K and draw (Sec. 4.4; Algorithm 1, K best and random draw) ---
  * For each filter f, candidates are ordered by the key
  *   (min(mismatch, 4095), S + 2^31, pi(index))

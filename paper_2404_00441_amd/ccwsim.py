@@ -73,6 +73,16 @@ def load():
     L.ccwsim_ccf_scan_noalloc.argtypes = [Shape, i32, i32, i32, i32, p, p, p, p, i32, i32, p, i32, u64, p, p, p, p]
     L.ccwsim_ccf_scan.restype = ctypes.c_int
     L.ccwsim_ccf_scan.argtypes = [Shape, i32, i32, i32, i32, p, p, p, p, i32, i32, p, i32, u64, p, p, p, p, i64, p]
+    L.ccwsim_lp_sizes.restype = ctypes.c_int
+    L.ccwsim_lp_sizes.argtypes = [Shape, i32, p, i32, p, p, p]
+    L.ccwsim_lp_init.restype = ctypes.c_int
+    L.ccwsim_lp_init.argtypes = [p, u64, p]
+    L.ccwsim_lp_encode.restype = ctypes.c_int
+    L.ccwsim_lp_encode.argtypes = [p, p, Shape, i32, p, p, i32, p, p, p, p, i64, p]
+    L.ccwsim_lp_train_step.restype = ctypes.c_int
+    L.ccwsim_lp_train_step.argtypes = [p, p, p, i32, ctypes.c_float, p, Shape, i32, p, p, p, i32, p, p, p, i64, p]
+    L.ccwsim_lp_shortlist.restype = ctypes.c_int
+    L.ccwsim_lp_shortlist.argtypes = [p, i32, i64, i32, p, p]
     L.ccwsim_select.restype = ctypes.c_int
     L.ccwsim_select.argtypes = [p, p, i64, i32, i32, u64, p, p, p, p, p]
     L.ccwsim_idwt_workspace_size.restype = i64
@@ -115,7 +125,8 @@ def load():
 
 EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccwsim_dwt",
            "ccwsim_ccf_scan", "ccwsim_ccf_scan_workspace_size", "ccwsim_ccf_scan_noalloc",
-           "ccwsim_ccf_scan_noalloc_capacity", "ccwsim_idwt_workspace_size", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
+           "ccwsim_ccf_scan_noalloc_capacity", "ccwsim_idwt_workspace_size", "ccwsim_lp_sizes",
+           "ccwsim_lp_init", "ccwsim_lp_encode", "ccwsim_lp_train_step", "ccwsim_lp_shortlist", "ccwsim_select", "ccwsim_idwt", "ccwsim_simulate_workspace_size",
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
@@ -287,6 +298,70 @@ def idwt(approx, details, ti_extent, level, origins, patch, wavelet=0):
     _check("ccwsim_idwt", load().ccwsim_idwt(_ptr(approx), _ptr(details), shape_of(ti_extent), level, wavelet,
                                              _ptr(origins), n, _i3(patch, 1), _ptr(out), _ptr(ws), nw, _stream()))
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned proposer (training and encoding)
+# ---------------------------------------------------------------------------
+def lp_sizes(ti_extent, level, tmpl, batch):
+    nw, ws, nc = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check("ccwsim_lp_sizes", load().ccwsim_lp_sizes(shape_of(ti_extent), level, _i3(tmpl, 1), batch,
+                                                     ctypes.byref(nw), ctypes.byref(ws), ctypes.byref(nc)))
+    return nw.value, ws.value, nc.value
+
+
+def lp_init(seed: int, device="cuda"):
+    nw, _, _ = lp_sizes((64, 64), 2, (16, 16), 0)
+    w = torch.empty(nw, dtype=torch.float32, device=device)
+    _check("ccwsim_lp_init", load().ccwsim_lp_init(_ptr(w), seed, _stream()))
+    return w
+
+
+class LpWorkspace:
+    """Workspace of the proposer for one TI geometry and batch size."""
+
+    def __init__(self, ti_extent, level, tmpl, batch, device="cuda"):
+        self.args = (tuple(ti_extent), level, tuple(tmpl), batch)
+        self.nw, self.nbytes, self.ncand = lp_sizes(ti_extent, level, tmpl, batch)
+        self._buf, self.ws = _aligned_workspace(self.nbytes, device)
+
+
+def lp_encode(w, approx, ws: LpWorkspace, events=None, want_keys=True, want_queries=False, want_scores=False):
+    """Keys [ncand, 64] of the TI, queries [B, 64] and scores [B, ncand] of
+    the events (float32 [B, 2, Tc_y, Tc_x])."""
+    ext, level, tmpl, batch = ws.args
+    dev = approx.device
+    B = 0 if events is None else events.shape[0]
+    assert B <= batch
+    keys = torch.empty((ws.ncand, 64), dtype=torch.float32, device=dev) if want_keys else None
+    q = torch.empty((max(B, 1), 64), dtype=torch.float32, device=dev) if want_queries else None
+    S = torch.empty((max(B, 1), ws.ncand), dtype=torch.float32, device=dev) if want_scores else None
+    _check("ccwsim_lp_encode", load().ccwsim_lp_encode(_ptr(w), _ptr(approx), shape_of(ext), level, _i3(tmpl, 1),
+                                                       _ptr(events) if B else None, B, _ptr(keys), _ptr(q), _ptr(S),
+                                                       _ptr(ws.ws), ws.nbytes, _stream()))
+    return keys, q, S
+
+
+def lp_train_step(w, m, v, step, lr, approx, ws: LpWorkspace, events, labels, want_grad=False):
+    """One Adam step on a batch; returns the per-example losses (and the
+    gradient before the update when asked)."""
+    ext, level, tmpl, batch = ws.args
+    B = events.shape[0]
+    assert B == batch
+    loss = torch.empty(B, dtype=torch.float32, device=approx.device)
+    g = torch.empty_like(w) if want_grad else None
+    _check("ccwsim_lp_train_step", load().ccwsim_lp_train_step(_ptr(w), _ptr(m), _ptr(v), step, lr, _ptr(approx),
+                                                               shape_of(ext), level, _i3(tmpl, 1), _ptr(events),
+                                                               _ptr(labels), B, _ptr(loss), _ptr(g), _ptr(ws.ws),
+                                                               ws.nbytes, _stream()))
+    return loss, g
+
+
+def lp_shortlist(scores, k):
+    B, n = scores.shape
+    idx = torch.empty((B, k), dtype=torch.int32, device=scores.device)
+    _check("ccwsim_lp_shortlist", load().ccwsim_lp_shortlist(_ptr(scores), B, n, k, _ptr(idx), _stream()))
+    return idx
 
 
 def simulate_workspace_size(p: dict) -> int:

@@ -18,6 +18,7 @@
 #include "ccwsim.h"
 #include "dev_scan.h"
 #include "dev_learn.h"
+#include "dev_lp.h"
 #include "dev_stats.h"
 
 using namespace ccw;
@@ -178,6 +179,11 @@ int sel_group_bits(int C0, int nchunks, int ksel) {
     if (valid >= ksel) return gb;
   }
   return 4;   // fewer candidates than ksel in a row: every candidate survives
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) p[id] = v;
 }
 
 // ---- launch profiler (events around each kernel launch) -------------------
@@ -899,6 +905,221 @@ extern "C" int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t w
   CCW_TRY(scratch_of_current_device(&ptr));
   return enqueue_scan(sp, precision, score_mode, approx, or_n, or_m, n_filters, scores, top_k, seed, realization,
                       step, topk_keys, ptr, as_stream(stream), false);
+}
+
+// ===========================================================================
+// A9 learned proposer: training and encoding (Sec. 4.3-4.4 search on the
+// approximation; the proposer ranks positions, the exact score judges them)
+// ===========================================================================
+namespace {
+
+struct LpPlan {
+  LpGeom q;
+  Geom g;
+  int B = 0;
+  long long gc = 0, wc = 0;
+  long long o_kin = 0, o_ka = 0, o_kmap = 0, o_keys = 0, o_qin = 0, o_qa = 0, o_qmap = 0, o_qv = 0, o_S = 0, o_gW = 0,
+            o_dkmap = 0, o_dk = 0, o_dqmap = 0, o_dq = 0, o_dqa = 0, total = 0;
+};
+
+int lp_plan(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32_t batch, LpPlan& L) {
+  CCW_TRY(geom_ti(L.g, ti, level));
+  if (!tmpl) return fail(CCWSIM_ERR_INVALID_ARG, "null template");
+  CCW_TRY(geom_tmpl(L.g, tmpl));
+  if (L.g.ndim != 2) return fail(CCWSIM_ERR_UNSUPPORTED, "the learned proposer runs on 2D training images");
+  if (batch < 0 || batch > 4096) return fail(CCWSIM_ERR_INVALID_ARG, "batch must be in [0, 4096]");
+  const Geom& g = L.g;
+  for (int a = 0; a < 3; ++a) {
+    L.q.G[a] = g.G[a];
+    L.q.cand[a] = g.cand[a];
+    L.q.tc[a] = g.tc[a];
+    L.q.half[a] = a < g.ndim ? g.tc[a] / 2 : 0;
+  }
+  L.q.ncand = g.ncand;
+  L.B = batch;
+  L.gc = (long long)g.G[0] * g.G[1] * g.G[2];
+  L.wc = g.tcells;
+  const long long B = std::max(batch, 1);
+  long long o = 0;
+  auto take = [&](long long floats) {
+    const long long at = o;
+    o += align256(floats * 4);
+    return at;
+  };
+  L.o_kin = take(L.gc);
+  L.o_ka = take(3 * kLpC * L.gc);
+  L.o_kmap = take(kLpD * L.gc);
+  L.o_keys = take(g.ncand * kLpD);
+  L.o_qin = take(B * 2 * L.wc);
+  L.o_qa = take(3 * B * kLpC * L.wc);
+  L.o_qmap = take(B * kLpD * L.wc);
+  L.o_qv = take(B * kLpD);
+  L.o_S = take(B * g.ncand);
+  L.o_gW = take(lp_weights_total());
+  L.o_dkmap = take(kLpD * L.gc);
+  L.o_dk = take(2 * kLpC * L.gc);
+  L.o_dqmap = take(B * kLpD * L.wc);
+  L.o_dq = take(B * kLpD);
+  L.o_dqa = take(2 * B * kLpC * L.wc);
+  L.total = o;
+  return CCWSIM_OK;
+}
+
+void lp_conv(const float* in, const float* Wb, float* out, int N, int l, int cin0, int H, int Wd, bool relu,
+             hipStream_t st) {
+  const LpLayer Ly = lp_layer(l, cin0);
+  const long long n = (long long)N * Ly.cout * H * Wd;
+  k_lp_conv_fwd<<<nblocks(n), kThreads, 0, st>>>(in, Wb, out, N, Ly.cin, Ly.cout, H, Wd, Ly.taps, Ly.dil, relu ? 1 : 0);
+}
+
+// Forward of one encoder: acts[0..2] (32 channels), out (64 channels).
+void lp_encoder_fwd(const float* W, int e, const float* in, float* acts, float* out, int N, int H, int Wd,
+                    hipStream_t st) {
+  const int cin0 = e == 0 ? 1 : 2;
+  const long long a = (long long)N * kLpC * H * Wd;
+  const float* src = in;
+  for (int l = 0; l < kLpLayers; ++l) {
+    float* dst = l < 3 ? acts + l * a : out;
+    lp_conv(src, W + lp_offset(e, l), dst, N, l, cin0, H, Wd, l < 3, st);
+    src = dst;
+  }
+}
+
+// Backward of one encoder from the gradient of its output (dout, 64
+// channels): weight gradients into gW, input gradient not needed.
+void lp_encoder_bwd(const float* W, float* gW, int e, const float* in, const float* acts, float* dout, float* dbuf,
+                    int N, int H, int Wd, hipStream_t st) {
+  const int cin0 = e == 0 ? 1 : 2;
+  const long long a = (long long)N * kLpC * H * Wd;
+  float* d = dout;   // gradient at the current layer's output (pre-activation once masked)
+  for (int l = kLpLayers - 1; l >= 0; --l) {
+    const LpLayer Ly = lp_layer(l, cin0);
+    const float* lin = l == 0 ? in : acts + (l - 1) * a;
+    k_lp_conv_bwd_w<<<(unsigned)(Ly.cout * Ly.cin), kThreads, 0, st>>>(lin, d, gW + lp_offset(e, l), N, Ly.cin,
+                                                                     Ly.cout, H, Wd, Ly.taps, Ly.dil);
+    if (l == 0) break;
+    float* dn = dbuf + (l & 1) * a;
+    const long long n = (long long)N * Ly.cin * H * Wd;
+    k_lp_conv_bwd_in<<<nblocks(n), kThreads, 0, st>>>(d, W + lp_offset(e, l), dn, N, Ly.cin, Ly.cout, H, Wd, Ly.taps,
+                                                     Ly.dil);
+    k_lp_relu_bwd<<<nblocks(n), kThreads, 0, st>>>(dn, lin, n);   // layer l-1 ends in a ReLU
+    d = dn;
+  }
+}
+
+// Forward through the scores; returns nothing, fills keys, queries, S.
+void lp_forward(const LpPlan& L, const float* W, const int32_t* approx, const float* events, unsigned char* ws,
+                bool want_keys, hipStream_t st) {
+  const Geom& g = L.g;
+  float* kin = (float*)(ws + L.o_kin);
+  float* ka = (float*)(ws + L.o_ka);
+  float* kmap = (float*)(ws + L.o_kmap);
+  float* keys = (float*)(ws + L.o_keys);
+  if (want_keys) {
+    k_lp_kin<<<nblocks(L.gc), kThreads, 0, st>>>(approx, L.gc, 1.f / (float)g.beta, kin);
+    lp_encoder_fwd(W, 0, kin, ka, kmap, 1, g.G[1], g.G[0], st);
+    k_lp_gather_keys<<<nblocks(g.ncand * kLpD), kThreads, 0, st>>>(kmap, L.q, keys);
+  }
+  if (L.B > 0 && events) {
+    float* qa = (float*)(ws + L.o_qa);
+    float* qmap = (float*)(ws + L.o_qmap);
+    float* qv = (float*)(ws + L.o_qv);
+    float* S = (float*)(ws + L.o_S);
+    lp_encoder_fwd(W, 1, events, qa, qmap, L.B, g.tc[1], g.tc[0], st);
+    k_lp_gather_queries<<<nblocks((long long)L.B * kLpD), kThreads, 0, st>>>(qmap, L.q, L.B, qv);
+    k_lp_scores<<<nblocks(g.ncand * L.B), kThreads, 0, st>>>(qv, keys, g.ncand, L.B, S);
+  }
+}
+}  // namespace
+
+extern "C" int ccwsim_lp_sizes(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32_t batch,
+                               int64_t* n_weights, int64_t* workspace_bytes, int64_t* n_cand) {
+  LpPlan L;
+  CCW_TRY(lp_plan(ti, level, tmpl, batch, L));
+  if (n_weights) *n_weights = lp_weights_total();
+  if (workspace_bytes) *workspace_bytes = L.total;
+  if (n_cand) *n_cand = L.g.ncand;
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_lp_init(float* weights, uint64_t seed, void* stream) {
+  if (!weights) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  k_lp_init<<<nblocks(lp_weights_total()), kThreads, 0, as_stream(stream)>>>(weights, seed);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccwsim_shape ti, int32_t level,
+                                const int32_t tmpl[3], const float* events, int32_t batch, float* keys_out,
+                                float* queries_out, float* scores_out, void* workspace, int64_t workspace_bytes,
+                                void* stream) {
+  LpPlan L;
+  CCW_TRY(lp_plan(ti, level, tmpl, batch, L));
+  if (!weights || !approx || (batch > 0 && !events)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (!workspace || workspace_bytes < L.total) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", L.total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  unsigned char* ws = (unsigned char*)workspace;
+  lp_forward(L, weights, approx, events, ws, true, st);
+  const Geom& g = L.g;
+  if (keys_out)
+    HIP_TRY(hipMemcpyAsync(keys_out, ws + L.o_keys, g.ncand * kLpD * 4, hipMemcpyDeviceToDevice, st));
+  if (queries_out && batch > 0)
+    HIP_TRY(hipMemcpyAsync(queries_out, ws + L.o_qv, (size_t)batch * kLpD * 4, hipMemcpyDeviceToDevice, st));
+  if (scores_out && batch > 0)
+    HIP_TRY(hipMemcpyAsync(scores_out, ws + L.o_S, (size_t)batch * g.ncand * 4, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr,
+                                    const int32_t* approx, ccwsim_shape ti, int32_t level, const int32_t tmpl[3],
+                                    const float* events, const int32_t* labels, int32_t batch, float* loss,
+                                    float* grad_out, void* workspace, int64_t workspace_bytes, void* stream) {
+  LpPlan L;
+  CCW_TRY(lp_plan(ti, level, tmpl, batch, L));
+  if (!weights || !adam_m || !adam_v || !approx || !events || !labels || !loss)
+    return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (batch < 1) return fail(CCWSIM_ERR_INVALID_ARG, "batch must be >= 1");
+  if (step < 1) return fail(CCWSIM_ERR_INVALID_ARG, "Adam steps count from 1");
+  if (!workspace || workspace_bytes < L.total) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", L.total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  unsigned char* ws = (unsigned char*)workspace;
+  const Geom& g = L.g;
+  lp_forward(L, weights, approx, events, ws, true, st);
+  float* S = (float*)(ws + L.o_S);
+  k_lp_ce<<<(unsigned)batch, kThreads, 0, st>>>(S, labels, g.ncand, batch, loss);   // S becomes dS
+  float* gW = (float*)(ws + L.o_gW);
+  float* dq = (float*)(ws + L.o_dq);
+  float* dkmap = (float*)(ws + L.o_dkmap);
+  k_lp_grad_q<<<(unsigned)batch, kThreads, 0, st>>>(S, (const float*)(ws + L.o_keys), g.ncand, dq);
+  k_fill_f32<<<nblocks(kLpD * L.gc), kThreads, 0, st>>>(dkmap, kLpD * L.gc, 0.f);
+  k_lp_grad_k<<<nblocks(g.ncand * kLpD), kThreads, 0, st>>>(S, (const float*)(ws + L.o_qv), L.q, batch, dkmap);
+  // query encoder
+  float* dqmap = (float*)(ws + L.o_dqmap);
+  k_lp_scatter_dq<<<nblocks((long long)batch * kLpD * L.wc), kThreads, 0, st>>>(dq, L.q, batch, dqmap);
+  lp_encoder_bwd(weights, gW, 1, events, (const float*)(ws + L.o_qa), dqmap, (float*)(ws + L.o_dqa), batch, g.tc[1],
+                 g.tc[0], st);
+  // key encoder
+  lp_encoder_bwd(weights, gW, 0, (const float*)(ws + L.o_kin), (const float*)(ws + L.o_ka), dkmap,
+                 (float*)(ws + L.o_dk), 1, g.G[1], g.G[0], st);
+  if (grad_out) HIP_TRY(hipMemcpyAsync(grad_out, gW, lp_weights_total() * 4, hipMemcpyDeviceToDevice, st));
+  k_lp_adam<<<nblocks(lp_weights_total()), kThreads, 0, st>>>(weights, gW, adam_m, adam_v, lp_weights_total(), lr,
+                                                              0.9f, 0.999f, 1e-8f, step);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_lp_shortlist(const float* scores, int32_t batch, int64_t n_cand, int32_t k, int32_t* idx_out,
+                                   void* stream) {
+  if (!scores || !idx_out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (batch < 0 || n_cand < 1 || n_cand > (1 << 20)) return fail(CCWSIM_ERR_INVALID_ARG, "sizes");
+  if (k < 1 || k > 256 || k > n_cand) return fail(CCWSIM_ERR_INVALID_ARG, "k must be in [1, min(256, n_cand)]");
+  if (batch == 0) return CCWSIM_OK;
+  k_lp_topk<<<(unsigned)batch, kThreads, 0, as_stream(stream)>>>(scores, n_cand, k, idx_out);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
 }
 
 // ===========================================================================
