@@ -93,7 +93,18 @@ typedef struct {
                            and the K best of those are drawn from        */
   int32_t max_hard_data;/* most hard data a call passes (sizes the
                            workspace); 0 = unconditional only            */
-  int32_t proposer_dim; /* 0, or D in {8, 16, 32}: learned proposer.  A
+  int32_t proposer_dim; /* 64: the learned convolutional proposer (see
+                           ccwsim_lp_*): each patch's data event is encoded
+                           (query encoder), the lp_probe inverted lists of
+                           `proposer` whose centroids score best are
+                           scored exactly (Sec. 4.3, in integers) and the
+                           K best of those are drawn from, unless the gate
+                           sends the patch to the full scan (empty overlap,
+                           hard data in the virtual template, fewer than K
+                           members, or a best match error above lp_gate).
+                           Not identical to proposer_dim = 0 by design;
+                           2D, score_mode 0, Haar, shortlist 0.
+                           D in {8, 16, 32}: a certified proposer.  A
                            D-dimensional principal-component basis of the
                            candidates' level-J windows is fitted on the
                            device from the TI (every call); each patch's
@@ -126,6 +137,14 @@ typedef struct {
                            coefficient), and the pattern is rebuilt by
                            perfect reconstruction, i.e. as the TI window.
                            Needs shortlist 0 and proposer_dim 0.          */
+  int32_t lp_probe;     /* proposer_dim = 64: inverted lists probed per
+                           data event, 1 .. 64                            */
+  float lp_gate;        /* proposer_dim = 64: largest best match error a
+                           proposal may have (below: the full scan
+                           decides); < 0 sends every patch to the scan   */
+  const void* proposer; /* proposer_dim = 64: device index from
+                           ccwsim_lp_build_index for this TI, level and
+                           template (NULL otherwise)                      */
 } ccwsim_params;
 
 /* ---- A1: training-image transform (Sec. 3.1 DWT; Sec. 4.2 the mother
@@ -218,8 +237,8 @@ int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t wavelet, int
  * candidate positions for a data event; the exact CCW score of a shortlist
  * then decides.  Key encoder: input K / |beta| (one channel, the TI's
  * approximation grid); query encoder: input m / |beta| and n / |beta| over
- * the event's T_c blocks (two channels, zero off the overlap; float32
- * [batch][2][T_c,y][T_c,x]).  Each: 3x3 convolutions with dilations 1, 2, 4
+ * the event's T_c blocks (two channels, zero off the overlap).  Events
+ * come as for ccwsim_ccf_scan: or_n / or_m int32 [batch][T_c cells].  Each: 3x3 convolutions with dilations 1, 2, 4
  * and 32 channels (ReLU), then a 1x1 convolution to 64 channels.  The key
  * of candidate c is the key map at c + T_c / 2; the query is the query map
  * at T_c / 2; the proposer's score is their dot product.  2D TIs only.
@@ -247,13 +266,53 @@ int ccwsim_lp_sizes(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32
                     int64_t* workspace_bytes, int64_t* n_cand);
 int ccwsim_lp_init(float* weights, uint64_t seed, void* stream);
 int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccwsim_shape ti, int32_t level, const int32_t tmpl[3],
-                     const float* events, int32_t batch, float* keys_out, float* queries_out, float* scores_out,
-                     void* workspace, int64_t workspace_bytes, void* stream);
+                     const int32_t* or_n, const int32_t* or_m, int32_t batch, float* keys_out, float* queries_out,
+                     float* scores_out, void* workspace, int64_t workspace_bytes, void* stream);
 int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr, const int32_t* approx,
-                         ccwsim_shape ti, int32_t level, const int32_t tmpl[3], const float* events,
-                         const int32_t* labels, int32_t batch, float* loss, float* grad_out, void* workspace,
-                         int64_t workspace_bytes, void* stream);
+                         ccwsim_shape ti, int32_t level, const int32_t tmpl[3], const int32_t* or_n,
+                         const int32_t* or_m, const int32_t* labels, int32_t batch, float* loss, float* grad_out,
+                         void* workspace, int64_t workspace_bytes, void* stream);
 int ccwsim_lp_shortlist(const float* scores, int32_t batch, int64_t n_cand, int32_t k, int32_t* idx_out, void* stream);
+
+/* Inverted lists of the keys and the proposal (Sec. 4.3 exact score of a
+ * shortlist, Sec. 4.4 K best of it).
+ *   ccwsim_lp_index_size: bytes of an index with n_lists lists (1 .. 1024)
+ *     and of the workspace that builds it (host call);
+ *   ccwsim_lp_build_index: keys of every candidate from the key encoder,
+ *     then `iters` rounds of Lloyd's k-means (squared distance; starting
+ *     centroids at evenly spaced candidates; a list's centroid is the mean
+ *     of its members, an empty list keeps its centroid), each candidate in
+ *     the list of its nearest centroid.  The index (device memory of
+ *     index_bytes, 256-byte aligned, owned by the caller) holds a header
+ *     with the geometry, the query encoder's weights, the centroids and the
+ *     lists; ccwsim_simulate takes it as `proposer`;
+ *   ccwsim_lp_propose: for each data event (or_n / or_m as for
+ *     ccwsim_ccf_scan), the query (the query encoder's output at the
+ *     window's centre block), the `probe` lists whose centroids have the
+ *     largest inner product with it (ties to the smaller list), and their
+ *     members in that order, up to 1024 (the first list alone may be cut),
+ *     each scored exactly in integers, S = sum n K^2 - 2 |beta| sum m K.
+ *     Outputs: topk_keys uint64 [n_filters][top_k] the min(top_k, n_cand)
+ *     best keys (S + 2^31, pi(index)) of ccwsim_select (all ones when fewer
+ *     members were scored); members int32 [n_filters][1024] and n_members
+ *     int32 [n_filters], queries float32 [n_filters][64] and best_error
+ *     float32 [n_filters] (the best key's match error, see
+ *     ccwsim_simulate_match_errors; -1 when fewer than top_k members),
+ *     each may be NULL.  The index must match ti, level and tmpl
+ *     (CCWSIM_ERR_INVALID_ARG otherwise; the header is read back, which
+ *     synchronises `stream`).  workspace: ccwsim_lp_propose_workspace_size
+ *     bytes, 256-byte aligned. */
+int ccwsim_lp_index_size(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32_t n_lists, int64_t* index_bytes,
+                         int64_t* workspace_bytes);
+int ccwsim_lp_build_index(const float* weights, const int32_t* approx, ccwsim_shape ti, int32_t level,
+                          const int32_t tmpl[3], int32_t n_lists, int32_t iters, void* index, int64_t index_bytes,
+                          void* workspace, int64_t workspace_bytes, void* stream);
+int64_t ccwsim_lp_propose_workspace_size(ccwsim_shape ti, int32_t level, int32_t max_code, const int32_t tmpl[3]);
+int ccwsim_lp_propose(const void* index, const int32_t* approx, ccwsim_shape ti, int32_t level, int32_t max_code,
+                      const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m, int32_t n_filters,
+                      int32_t probe, int32_t top_k, uint64_t seed, const int32_t* realization, const int64_t* step,
+                      uint64_t* topk_keys, int32_t* members, int32_t* n_members, float* queries, float* best_error,
+                      void* workspace, int64_t workspace_bytes, void* stream);
 
 /* ---- A6: top-K and draw (Sec. 4.4; Algorithm 1, K best and random draw) ---
  * For each filter f, candidates are ordered by the key
@@ -345,14 +404,34 @@ typedef struct {
 int ccwsim_simulate_stats(const ccwsim_params* p, ccwsim_plan_stats* out);
 
 /* Report of the last ccwsim_simulate call on this workspace (synchronises
- * `stream`), int64 out[6].  Shortlist rescoring: out[0] largest |bulk score -
+ * `stream`), int64 out[8].  Shortlist rescoring: out[0] largest |bulk score -
  * exact score|, out[1] candidates rescored, out[2] patches whose K best
  * changed after rescoring, out[3] patches rescored (all zero without a
- * shortlist).  Proposer: out[4] patches selected through it, out[5]
- * candidate rows whose exact keys were computed for them (zero without a
- * proposer). */
+ * shortlist).  Proposer: out[4] patches selected through it; out[5]
+ * candidate rows (dimensions 8 to 32) or candidates (64) whose exact keys
+ * were computed for them; out[6] patches the learned proposer's gate sent
+ * to the full scan; out[7] 0 (zero without a proposer). */
 int ccwsim_simulate_report(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
                            int64_t* out, void* stream);
+
+/* After a ccwsim_simulate call on this workspace, stream-ordered (Sec. 4.3:
+ * the data event of each patch; Sec. 4.4: the choice among the K best):
+ *   ccwsim_simulate_events: every patch's data event in the scan's input
+ *     form, or_n / or_m int32 [patches][T_c cells] (zero on blocks outside
+ *     the overlap; all zero for a first patch), and, where not NULL, its
+ *     realization int32 [patches] and raster step int32 [patches];
+ *   ccwsim_simulate_match_errors: float32 [patches], the match error of the
+ *     drawn candidate, (S + sum |beta|^2 m^2 / n) / (|beta|^2 sum n) for
+ *     score_mode 0: the squared difference between the level-J
+ *     approximations of the TI window and of the overlap, in orthonormal
+ *     coefficients, per known cell (|beta| = 1 for LeGall 5/3); -1 where the
+ *     overlap is empty or score_mode is 1.
+ * Patches are in the order of the plan (ccwsim_simulate_stats counts
+ * them); the buffers are device memory owned by the caller. */
+int ccwsim_simulate_events(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes, int32_t* or_n,
+                           int32_t* or_m, int32_t* realization, int32_t* step, void* stream);
+int ccwsim_simulate_match_errors(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes, float* out,
+                                 void* stream);
 
 /* Kernel kinds timed by the profiler. */
 #define CCWSIM_KIND_DWT 0

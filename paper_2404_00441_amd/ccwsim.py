@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
         ("nc_margin", ctypes.c_int32 * 3), ("cut", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("shortlist", ctypes.c_int32),
         ("max_hard_data", ctypes.c_int32), ("proposer_dim", ctypes.c_int32), ("hd_direct", ctypes.c_int32),
-        ("wavelet", ctypes.c_int32),
+        ("wavelet", ctypes.c_int32), ("lp_probe", ctypes.c_int32), ("lp_gate", ctypes.c_float),
+        ("proposer", ctypes.c_void_p),
     ]
 
 
@@ -78,9 +79,10 @@ def load():
     L.ccwsim_lp_init.restype = ctypes.c_int
     L.ccwsim_lp_init.argtypes = [p, u64, p]
     L.ccwsim_lp_encode.restype = ctypes.c_int
-    L.ccwsim_lp_encode.argtypes = [p, p, Shape, i32, p, p, i32, p, p, p, p, i64, p]
+    L.ccwsim_lp_encode.argtypes = [p, p, Shape, i32, p, p, p, i32, p, p, p, p, i64, p]
     L.ccwsim_lp_train_step.restype = ctypes.c_int
-    L.ccwsim_lp_train_step.argtypes = [p, p, p, i32, ctypes.c_float, p, Shape, i32, p, p, p, i32, p, p, p, i64, p]
+    L.ccwsim_lp_train_step.argtypes = [p, p, p, i32, ctypes.c_float, p, Shape, i32, p, p, p, p, i32, p, p, p, i64,
+                                       p]
     L.ccwsim_lp_shortlist.restype = ctypes.c_int
     L.ccwsim_lp_shortlist.argtypes = [p, i32, i64, i32, p, p]
     L.ccwsim_select.restype = ctypes.c_int
@@ -107,6 +109,19 @@ def load():
     L.ccwsim_set_graphs.argtypes = [ctypes.c_int]
     L.ccwsim_simulate_report.restype = ctypes.c_int
     L.ccwsim_simulate_report.argtypes = [p, p, i64, p, p]
+    L.ccwsim_simulate_events.restype = ctypes.c_int
+    L.ccwsim_simulate_events.argtypes = [p, p, i64, p, p, p, p, p]
+    L.ccwsim_simulate_match_errors.restype = ctypes.c_int
+    L.ccwsim_simulate_match_errors.argtypes = [p, p, i64, p, p]
+    L.ccwsim_lp_index_size.restype = ctypes.c_int
+    L.ccwsim_lp_index_size.argtypes = [Shape, i32, p, i32, p, p]
+    L.ccwsim_lp_build_index.restype = ctypes.c_int
+    L.ccwsim_lp_build_index.argtypes = [p, p, Shape, i32, p, i32, i32, p, i64, p, i64, p]
+    L.ccwsim_lp_propose_workspace_size.restype = i64
+    L.ccwsim_lp_propose_workspace_size.argtypes = [Shape, i32, i32, p]
+    L.ccwsim_lp_propose.restype = ctypes.c_int
+    L.ccwsim_lp_propose.argtypes = [p, p, Shape, i32, i32, p, p, p, i32, i32, i32, u64, p, p, p, p, p, p, p, p, i64,
+                                    p]
     L.ccwsim_set_scan_group.restype = ctypes.c_int
     L.ccwsim_set_scan_group.argtypes = [ctypes.c_int]
     L.ccwsim_set_selection.restype = ctypes.c_int
@@ -130,7 +145,9 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_simulate", "ccwsim_release_caches", "ccwsim_simulate_stats", "ccwsim_profile_enable",
            "ccwsim_profile_read", "ccwsim_set_graphs", "ccwsim_simulate_report", "ccwsim_set_scan_group",
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
-           "ccwsim_stats_connectivity", "ccwsim_cache_counts")
+           "ccwsim_stats_connectivity", "ccwsim_cache_counts",
+           "ccwsim_simulate_events", "ccwsim_simulate_match_errors", "ccwsim_lp_index_size", "ccwsim_lp_build_index",
+           "ccwsim_lp_propose_workspace_size", "ccwsim_lp_propose")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
@@ -196,6 +213,10 @@ def params_of(p: dict) -> Params:
     q.proposer_dim = int(p.get("proposer_dim", 0))
     q.hd_direct = int(p.get("hd_direct", 0))
     q.wavelet = int(p.get("wavelet", 0))
+    q.lp_probe = int(p.get("lp_probe", 0))
+    q.lp_gate = float(p.get("lp_gate", 0.0))
+    ix = p.get("proposer")
+    q.proposer = ctypes.c_void_p(ix.data_ptr() if ix is not None else None)
     return q
 
 
@@ -326,33 +347,36 @@ class LpWorkspace:
         self._buf, self.ws = _aligned_workspace(self.nbytes, device)
 
 
-def lp_encode(w, approx, ws: LpWorkspace, events=None, want_keys=True, want_queries=False, want_scores=False):
+def lp_encode(w, approx, ws: LpWorkspace, or_n=None, or_m=None, want_keys=True, want_queries=False,
+              want_scores=False):
     """Keys [ncand, 64] of the TI, queries [B, 64] and scores [B, ncand] of
-    the events (float32 [B, 2, Tc_y, Tc_x])."""
+    the data events (or_n / or_m int32 [B, T_c cells], as for ccf_scan)."""
     ext, level, tmpl, batch = ws.args
     dev = approx.device
-    B = 0 if events is None else events.shape[0]
+    B = 0 if or_n is None else or_n.shape[0]
     assert B <= batch
     keys = torch.empty((ws.ncand, 64), dtype=torch.float32, device=dev) if want_keys else None
     q = torch.empty((max(B, 1), 64), dtype=torch.float32, device=dev) if want_queries else None
     S = torch.empty((max(B, 1), ws.ncand), dtype=torch.float32, device=dev) if want_scores else None
     _check("ccwsim_lp_encode", load().ccwsim_lp_encode(_ptr(w), _ptr(approx), shape_of(ext), level, _i3(tmpl, 1),
-                                                       _ptr(events) if B else None, B, _ptr(keys), _ptr(q), _ptr(S),
+                                                       _ptr(or_n) if B else None, _ptr(or_m) if B else None, B,
+                                                       _ptr(keys), _ptr(q), _ptr(S),
                                                        _ptr(ws.ws), ws.nbytes, _stream()))
     return keys, q, S
 
 
-def lp_train_step(w, m, v, step, lr, approx, ws: LpWorkspace, events, labels, want_grad=False):
-    """One Adam step on a batch; returns the per-example losses (and the
+def lp_train_step(w, m, v, step, lr, approx, ws: LpWorkspace, or_n, or_m, labels, want_grad=False):
+    """One Adam step on a batch of data events (or_n / or_m int32 [B, T_c
+    cells]) and their labels; returns the per-example losses (and the
     gradient before the update when asked)."""
     ext, level, tmpl, batch = ws.args
-    B = events.shape[0]
+    B = or_n.shape[0]
     assert B == batch
     loss = torch.empty(B, dtype=torch.float32, device=approx.device)
     g = torch.empty_like(w) if want_grad else None
     _check("ccwsim_lp_train_step", load().ccwsim_lp_train_step(_ptr(w), _ptr(m), _ptr(v), step, lr, _ptr(approx),
-                                                               shape_of(ext), level, _i3(tmpl, 1), _ptr(events),
-                                                               _ptr(labels), B, _ptr(loss), _ptr(g), _ptr(ws.ws),
+                                                               shape_of(ext), level, _i3(tmpl, 1), _ptr(or_n),
+                                                               _ptr(or_m), _ptr(labels), B, _ptr(loss), _ptr(g), _ptr(ws.ws),
                                                                ws.nbytes, _stream()))
     return loss, g
 
@@ -362,6 +386,57 @@ def lp_shortlist(scores, k):
     idx = torch.empty((B, k), dtype=torch.int32, device=scores.device)
     _check("ccwsim_lp_shortlist", load().ccwsim_lp_shortlist(_ptr(scores), B, n, k, _ptr(idx), _stream()))
     return idx
+
+
+def lp_index_size(ti_extent, level, tmpl, n_lists):
+    nb, ws = ctypes.c_int64(), ctypes.c_int64()
+    _check("ccwsim_lp_index_size", load().ccwsim_lp_index_size(shape_of(ti_extent), level, _i3(tmpl, 1), n_lists,
+                                                               ctypes.byref(nb), ctypes.byref(ws)))
+    return nb.value, ws.value
+
+
+def lp_build_index(w, approx, ti_extent, level, tmpl, n_lists, iters=10):
+    """Inverted-list index of the keys (uint8 device tensor, 256-byte aligned
+    view) for ccwsim_simulate's `proposer`."""
+    nb, nws = lp_index_size(ti_extent, level, tmpl, n_lists)
+    _, ix = _aligned_workspace(nb, approx.device)
+    _, ws = _aligned_workspace(nws, approx.device)
+    _check("ccwsim_lp_build_index", load().ccwsim_lp_build_index(_ptr(w), _ptr(approx), shape_of(ti_extent), level,
+                                                                 _i3(tmpl, 1), n_lists, iters, _ptr(ix), nb,
+                                                                 _ptr(ws), nws, _stream()))
+    return ix
+
+
+LP_CAND_MAX = 1024
+
+
+def lp_propose(index, approx, ti_extent, level, max_code, tmpl, or_n, or_m, probe, top_k, seed=0, realization=None,
+               step=None):
+    """The proposal for each data event: (keys int64 [F, k], members int32
+    [F, 1024], n_members int32 [F], queries float32 [F, 64], best match
+    error float32 [F])."""
+    F = or_n.shape[0]
+    dev = approx.device
+    nws = load().ccwsim_lp_propose_workspace_size(shape_of(ti_extent), level, max_code, _i3(tmpl, 1))
+    if nws < 0:
+        raise CcwsimError("ccwsim_lp_propose_workspace_size", 1, load().ccwsim_last_error().decode())
+    _, ws = _aligned_workspace(nws, dev)
+    b = 2 ** level
+    ncand = 1
+    for a, t in zip(ti_extent, tmpl):
+        ncand *= (a - t) // b + 1
+    k = min(top_k, ncand)
+    keys = torch.empty((max(F, 1), k), dtype=torch.int64, device=dev)
+    mem = torch.empty((max(F, 1), LP_CAND_MAX), dtype=torch.int32, device=dev)
+    nmem = torch.empty(max(F, 1), dtype=torch.int32, device=dev)
+    q = torch.empty((max(F, 1), 64), dtype=torch.float32, device=dev)
+    err = torch.empty(max(F, 1), dtype=torch.float32, device=dev)
+    _check("ccwsim_lp_propose", load().ccwsim_lp_propose(_ptr(index), _ptr(approx), shape_of(ti_extent), level,
+                                                         max_code, _i3(tmpl, 1), _ptr(or_n), _ptr(or_m), F, probe,
+                                                         top_k, seed, _ptr(realization), _ptr(step), _ptr(keys),
+                                                         _ptr(mem), _ptr(nmem), _ptr(q), _ptr(err), _ptr(ws), nws,
+                                                         _stream()))
+    return keys[:F], mem[:F], nmem[:F], q[:F], err[:F]
 
 
 def simulate_workspace_size(p: dict) -> int:
@@ -403,12 +478,42 @@ class Simulator:
 
 
     def report(self) -> dict:
-        """Shortlist rescoring report of the last run (synchronises)."""
-        out = (ctypes.c_int64 * 6)()
+        """Shortlist rescoring and proposer report of the last run (synchronises)."""
+        out = (ctypes.c_int64 * 8)()
         _check("ccwsim_simulate_report", load().ccwsim_simulate_report(
             ctypes.byref(self.q), ctypes.c_void_p(self.ws_view.data_ptr()), self.ws_bytes, out, _stream()))
         return {"max_abs_error": out[0], "rescored": out[1], "topk_changed": out[2], "patches": out[3],
-                "proposer_patches": out[4], "proposer_rows": out[5]}
+                "proposer_patches": out[4], "proposer_rows": out[5], "proposer_fallbacks": out[6]}
+
+    def n_patches(self) -> int:
+        return int(simulate_stats(self.p)["patches"])
+
+    def events(self):
+        """Every patch's data event of the last run: (or_n, or_m int32
+        [patches, T_c cells], realization int32 [patches], step int32
+        [patches]), in plan order."""
+        n = self.n_patches()
+        b = 2 ** self.p["level"]
+        tc = 1
+        for t in self.p["tmpl"]:
+            tc *= (t + b - 1) // b
+        dev = self.ws.device
+        on = torch.empty((n, tc), dtype=torch.int32, device=dev)
+        om = torch.empty((n, tc), dtype=torch.int32, device=dev)
+        rr = torch.empty(n, dtype=torch.int32, device=dev)
+        ss = torch.empty(n, dtype=torch.int32, device=dev)
+        _check("ccwsim_simulate_events", load().ccwsim_simulate_events(
+            ctypes.byref(self.q), ctypes.c_void_p(self.ws_view.data_ptr()), self.ws_bytes, _ptr(on), _ptr(om),
+            _ptr(rr), _ptr(ss), _stream()))
+        return on, om, rr, ss
+
+    def match_errors(self):
+        """Match error of every patch's drawn candidate (float32 [patches],
+        plan order; -1 where the overlap is empty)."""
+        out = torch.empty(self.n_patches(), dtype=torch.float32, device=self.ws.device)
+        _check("ccwsim_simulate_match_errors", load().ccwsim_simulate_match_errors(
+            ctypes.byref(self.q), ctypes.c_void_p(self.ws_view.data_ptr()), self.ws_bytes, _ptr(out), _stream()))
+        return out
 
 
 def hd_to_device(hd, ndim, device="cuda"):

@@ -1008,8 +1008,8 @@ void lp_encoder_bwd(const float* W, float* gW, int e, const float* in, const flo
 }
 
 // Forward through the scores; returns nothing, fills keys, queries, S.
-void lp_forward(const LpPlan& L, const float* W, const int32_t* approx, const float* events, unsigned char* ws,
-                bool want_keys, hipStream_t st) {
+void lp_forward(const LpPlan& L, const float* W, const int32_t* approx, const int32_t* or_n, const int32_t* or_m,
+                unsigned char* ws, bool want_keys, hipStream_t st) {
   const Geom& g = L.g;
   float* kin = (float*)(ws + L.o_kin);
   float* ka = (float*)(ws + L.o_ka);
@@ -1020,7 +1020,9 @@ void lp_forward(const LpPlan& L, const float* W, const int32_t* approx, const fl
     lp_encoder_fwd(W, 0, kin, ka, kmap, 1, g.G[1], g.G[0], st);
     k_lp_gather_keys<<<nblocks(g.ncand * kLpD), kThreads, 0, st>>>(kmap, L.q, keys);
   }
-  if (L.B > 0 && events) {
+  if (L.B > 0 && or_n && or_m) {
+    float* events = (float*)(ws + L.o_qin);
+    k_lp_events<<<nblocks((long long)L.B * L.wc), kThreads, 0, st>>>(or_n, or_m, L.B, L.wc, 1.f / (float)g.beta, events);
     float* qa = (float*)(ws + L.o_qa);
     float* qmap = (float*)(ws + L.o_qmap);
     float* qv = (float*)(ws + L.o_qv);
@@ -1050,17 +1052,18 @@ extern "C" int ccwsim_lp_init(float* weights, uint64_t seed, void* stream) {
 }
 
 extern "C" int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccwsim_shape ti, int32_t level,
-                                const int32_t tmpl[3], const float* events, int32_t batch, float* keys_out,
+                                const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m, int32_t batch,
+                                float* keys_out,
                                 float* queries_out, float* scores_out, void* workspace, int64_t workspace_bytes,
                                 void* stream) {
   LpPlan L;
   CCW_TRY(lp_plan(ti, level, tmpl, batch, L));
-  if (!weights || !approx || (batch > 0 && !events)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (!weights || !approx || (batch > 0 && (!or_n || !or_m))) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
   if (!workspace || workspace_bytes < L.total) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", L.total);
   if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = as_stream(stream);
   unsigned char* ws = (unsigned char*)workspace;
-  lp_forward(L, weights, approx, events, ws, true, st);
+  lp_forward(L, weights, approx, or_n, or_m, ws, true, st);
   const Geom& g = L.g;
   if (keys_out)
     HIP_TRY(hipMemcpyAsync(keys_out, ws + L.o_keys, g.ncand * kLpD * 4, hipMemcpyDeviceToDevice, st));
@@ -1074,11 +1077,12 @@ extern "C" int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccw
 
 extern "C" int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr,
                                     const int32_t* approx, ccwsim_shape ti, int32_t level, const int32_t tmpl[3],
-                                    const float* events, const int32_t* labels, int32_t batch, float* loss,
+                                    const int32_t* or_n, const int32_t* or_m, const int32_t* labels, int32_t batch,
+                                    float* loss,
                                     float* grad_out, void* workspace, int64_t workspace_bytes, void* stream) {
   LpPlan L;
   CCW_TRY(lp_plan(ti, level, tmpl, batch, L));
-  if (!weights || !adam_m || !adam_v || !approx || !events || !labels || !loss)
+  if (!weights || !adam_m || !adam_v || !approx || !or_n || !or_m || !labels || !loss)
     return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
   if (batch < 1) return fail(CCWSIM_ERR_INVALID_ARG, "batch must be >= 1");
   if (step < 1) return fail(CCWSIM_ERR_INVALID_ARG, "Adam steps count from 1");
@@ -1087,7 +1091,7 @@ extern "C" int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v
   hipStream_t st = as_stream(stream);
   unsigned char* ws = (unsigned char*)workspace;
   const Geom& g = L.g;
-  lp_forward(L, weights, approx, events, ws, true, st);
+  lp_forward(L, weights, approx, or_n, or_m, ws, true, st);
   float* S = (float*)(ws + L.o_S);
   k_lp_ce<<<(unsigned)batch, kThreads, 0, st>>>(S, labels, g.ncand, batch, loss);   // S becomes dS
   float* gW = (float*)(ws + L.o_gW);
@@ -1099,7 +1103,7 @@ extern "C" int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v
   // query encoder
   float* dqmap = (float*)(ws + L.o_dqmap);
   k_lp_scatter_dq<<<nblocks((long long)batch * kLpD * L.wc), kThreads, 0, st>>>(dq, L.q, batch, dqmap);
-  lp_encoder_bwd(weights, gW, 1, events, (const float*)(ws + L.o_qa), dqmap, (float*)(ws + L.o_dqa), batch, g.tc[1],
+  lp_encoder_bwd(weights, gW, 1, (const float*)(ws + L.o_qin), (const float*)(ws + L.o_qa), dqmap, (float*)(ws + L.o_dqa), batch, g.tc[1],
                  g.tc[0], st);
   // key encoder
   lp_encoder_bwd(weights, gW, 0, (const float*)(ws + L.o_kin), (const float*)(ws + L.o_ka), dkmap,
@@ -1118,6 +1122,188 @@ extern "C" int ccwsim_lp_shortlist(const float* scores, int32_t batch, int64_t n
   if (k < 1 || k > 256 || k > n_cand) return fail(CCWSIM_ERR_INVALID_ARG, "k must be in [1, min(256, n_cand)]");
   if (batch == 0) return CCWSIM_OK;
   k_lp_topk<<<(unsigned)batch, kThreads, 0, as_stream(stream)>>>(scores, n_cand, k, idx_out);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+// ---- inverted lists over the keys, and the proposal on its own ----------
+namespace {
+__global__ void k_lp_header(LpIndexHeader h, LpIndexHeader* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = h;
+}
+
+int lp_index_layout(const LpPlan& L, int n_lists, LpIndexHeader& h) {
+  const Geom& g = L.g;
+  if (n_lists < 1 || n_lists > kLpListsMax || n_lists > g.ncand)
+    return fail(CCWSIM_ERR_INVALID_ARG, "n_lists must be in [1, min(%d, candidates)]", kLpListsMax);
+  memset(&h, 0, sizeof h);
+  h.magic = kLpMagic;
+  h.n_lists = n_lists;
+  h.level = g.level;
+  h.ndim = g.ndim;
+  for (int a = 0; a < 3; ++a) {
+    h.G[a] = g.G[a];
+    h.cand[a] = g.cand[a];
+    h.tc[a] = g.tc[a];
+  }
+  h.ncand = g.ncand;
+  long long o = align256(sizeof h);
+  h.off_w = o;
+  o += align256(lp_query_floats() * 4);
+  h.off_cent = o;
+  o += align256((long long)n_lists * kLpD * 4);
+  h.off_list = o;
+  o += align256((long long)(n_lists + 1) * 4);
+  h.off_mem = o;
+  o += align256(g.ncand * 4);
+  h.bytes = o;
+  return CCWSIM_OK;
+}
+
+// Dynamic LDS beyond 64 KiB for the proposal kernel (once per size).
+int lp_lds_allow(int kt, size_t bytes) {
+  if (bytes <= 64 * 1024) return CCWSIM_OK;
+  int dev = 0, lim = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if ((size_t)lim < bytes)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "the proposal needs %zu B of LDS, the device allows %d", bytes, lim);
+  if (kt == 1)
+    HIP_TRY(hipFuncSetAttribute((const void*)k_lp_propose<int8_t>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  else
+    HIP_TRY(hipFuncSetAttribute((const void*)k_lp_propose<int16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return CCWSIM_OK;
+}
+
+// The index header, checked against the geometry (a synchronous read).
+int lp_index_check(const void* index, const Geom& g, hipStream_t st, LpIndexHeader* out) {
+  LpIndexHeader h;
+  HIP_TRY(hipMemcpyAsync(&h, index, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.magic != kLpMagic) return fail(CCWSIM_ERR_INVALID_ARG, "the proposer pointer holds no index");
+  if (h.n_lists < 1 || h.n_lists > kLpListsMax || h.ncand != g.ncand || h.level != g.level || h.G[0] != g.G[0] ||
+      h.G[1] != g.G[1] || h.cand[0] != g.cand[0] || h.cand[1] != g.cand[1] || h.tc[0] != g.tc[0] ||
+      h.tc[1] != g.tc[1])
+    return fail(CCWSIM_ERR_INVALID_ARG, "the proposer index was built for another TI, level or template");
+  if (out) *out = h;
+  return CCWSIM_OK;
+}
+}  // namespace
+
+extern "C" int ccwsim_lp_index_size(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32_t n_lists,
+                                    int64_t* index_bytes, int64_t* workspace_bytes) {
+  LpPlan L;
+  CCW_TRY(lp_plan(ti, level, tmpl, 0, L));
+  LpIndexHeader h;
+  CCW_TRY(lp_index_layout(L, n_lists, h));
+  if (index_bytes) *index_bytes = h.bytes;
+  if (workspace_bytes) *workspace_bytes = L.total + align256(L.g.ncand * 4) + align256((long long)n_lists * 4);
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_lp_build_index(const float* weights, const int32_t* approx, ccwsim_shape ti, int32_t level,
+                                     const int32_t tmpl[3], int32_t n_lists, int32_t iters, void* index,
+                                     int64_t index_bytes, void* workspace, int64_t workspace_bytes, void* stream) {
+  LpPlan L;
+  CCW_TRY(lp_plan(ti, level, tmpl, 0, L));
+  LpIndexHeader h;
+  CCW_TRY(lp_index_layout(L, n_lists, h));
+  if (!weights || !approx || !index) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (iters < 1 || iters > 100) return fail(CCWSIM_ERR_INVALID_ARG, "iters must be in [1, 100]");
+  if (index_bytes < h.bytes) return fail(CCWSIM_ERR_INVALID_ARG, "index of %lld bytes needed", (long long)h.bytes);
+  const long long need = L.total + align256(L.g.ncand * 4) + align256((long long)n_lists * 4);
+  if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
+  if ((((uintptr_t)workspace | (uintptr_t)index) & 255) != 0)
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace and index must be 256-byte aligned");
+  hipStream_t st = as_stream(stream);
+  unsigned char* ws = (unsigned char*)workspace;
+  unsigned char* ix = (unsigned char*)index;
+  const Geom& g = L.g;
+  lp_forward(L, weights, approx, nullptr, nullptr, ws, true, st);
+  const float* keys = (const float*)(ws + L.o_keys);
+  int32_t* assign = (int32_t*)(ws + L.total);
+  int32_t* cnt = (int32_t*)(ws + L.total + align256(g.ncand * 4));
+  float* cent = (float*)(ix + h.off_cent);
+  int32_t* off = (int32_t*)(ix + h.off_list);
+  int32_t* mem = (int32_t*)(ix + h.off_mem);
+  k_lp_header<<<1, 64, 0, st>>>(h, (LpIndexHeader*)ix);
+  HIP_TRY(hipMemcpyAsync(ix + h.off_w, weights + lp_offset(1, 0), lp_query_floats() * 4, hipMemcpyDeviceToDevice, st));
+  k_km_init<<<nblocks((long long)n_lists * kLpD), kThreads, 0, st>>>(keys, g.ncand, n_lists, cent);
+  const unsigned nb = (unsigned)((g.ncand + kThreads - 1) / kThreads);
+  for (int it = 0; it < iters; ++it) {
+    k_km_assign<<<nb, kThreads, 0, st>>>(keys, g.ncand, cent, n_lists, assign);
+    k_km_lists<<<(unsigned)n_lists, kThreads, 0, st>>>(assign, g.ncand, nullptr, cnt);
+    k_km_offsets<<<1, 64, 0, st>>>(cnt, n_lists, off);
+    k_km_lists<<<(unsigned)n_lists, kThreads, 0, st>>>(assign, g.ncand, off, mem);
+    k_km_update<<<(unsigned)n_lists, kThreads, 0, st>>>(keys, off, mem, cent);
+  }
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int64_t ccwsim_lp_propose_workspace_size(ccwsim_shape ti, int32_t level, int32_t max_code,
+                                                    const int32_t tmpl[3]) {
+  Geom g;
+  if (geom_ti(g, ti, level) != CCWSIM_OK || !tmpl || geom_tmpl(g, tmpl) != CCWSIM_OK) return -1;
+  if (max_code < 1 || max_code > 126) {
+    fail(CCWSIM_ERR_INVALID_ARG, "max_code must be in [1, 126]");
+    return -1;
+  }
+  return align256(lp_prop_grid_bytes(g, 2));
+}
+
+extern "C" int ccwsim_lp_propose(const void* index, const int32_t* approx, ccwsim_shape ti, int32_t level,
+                                 int32_t max_code, const int32_t tmpl[3], const int32_t* or_n, const int32_t* or_m,
+                                 int32_t n_filters, int32_t probe, int32_t top_k, uint64_t seed,
+                                 const int32_t* realization, const int64_t* step, uint64_t* topk_keys,
+                                 int32_t* members, int32_t* n_members, float* queries, float* best_error,
+                                 void* workspace, int64_t workspace_bytes, void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, ti, level));
+  if (!tmpl) return fail(CCWSIM_ERR_INVALID_ARG, "null template");
+  CCW_TRY(geom_tmpl(g, tmpl));
+  if (g.ndim != 2) return fail(CCWSIM_ERR_UNSUPPORTED, "the learned proposer runs on 2D training images");
+  if (!index || !approx || !topk_keys || (n_filters > 0 && (!or_n || !or_m)))
+    return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (max_code < 1 || max_code > 126) return fail(CCWSIM_ERR_INVALID_ARG, "max_code must be in [1, 126]");
+  if ((long long)max_code * g.beta > 32767) return fail(CCWSIM_ERR_UNSUPPORTED, "block sums exceed int16");
+  if (probe < 1 || probe > kLpProbeMax) return fail(CCWSIM_ERR_INVALID_ARG, "probe must be in [1, %d]", kLpProbeMax);
+  if (top_k < 1 || top_k > kTopMax) return fail(CCWSIM_ERR_INVALID_ARG, "top_k must be in [1, %d]", kTopMax);
+  if ((realization == nullptr) != (step == nullptr))
+    return fail(CCWSIM_ERR_INVALID_ARG, "realization and step go together");
+  if (n_filters < 0) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters");
+  const long long need = align256(lp_prop_grid_bytes(g, 2));
+  if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const size_t lds = (size_t)lp_prop_lds(g, 2, kLpCandMax, (int)g.tcells);
+  if (lds > 160 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "the proposal needs %zu B of LDS", lds);
+  hipStream_t st = as_stream(stream);
+  CCW_TRY(lp_index_check(index, g, st, nullptr));
+  CCW_TRY(lp_lds_allow(2, lds));
+  if (n_filters == 0) return CCWSIM_OK;
+  const long long gc = (long long)g.G[0] * g.G[1];
+  const long long npad = lp_prop_grid_bytes(g, 2) / 2;
+  k_lp_narrow<int16_t><<<nblocks(npad), kThreads, 0, st>>>(approx, gc, npad, (int16_t*)workspace);
+  LpPropArgs la = {};
+  la.g = g;
+  la.index = (const unsigned char*)index;
+  la.grid = workspace;
+  la.probe = probe;
+  la.cap = kLpCandMax;
+  la.top_k = top_k;
+  la.gate = -1.f;
+  la.seed = seed;
+  la.standalone = 1;
+  la.or_n = or_n;
+  la.or_m = or_m;
+  la.fil_real = realization;
+  la.fil_step = step;
+  la.keys_out = topk_keys;
+  la.list_out = members;
+  la.nlist_out = n_members;
+  la.q_out = queries;
+  la.err_out = best_error;
+  k_lp_propose<int16_t><<<(unsigned)n_filters, kThreads, lds, st>>>(la);
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }
@@ -1286,6 +1472,15 @@ struct Plan {
   long long learn_off = 0;            // finalize LDS offset of the row-rescoring area
   int learn_kbr = 0, learn_w = 0;
   size_t proxy_lds = 0;
+  bool lp = false;                    // learned convolutional proposer (proposer_dim 64)
+  int lp_kt = 1;                      // bytes per value of its LDS copy of the grid
+  int lp_cap = 0;                     // candidates scored exactly per data event
+  int lp_tmax = 0;                    // most scan tiles in one step
+  size_t lp_lds = 0, lp_cmp_lds = 0;
+  const void* lp_checked = nullptr;   // the index whose header was last read back
+  long long ws_lp_grid = 0, ws_lp_sel = 0, ws_lp_ok = 0, ws_lp_map = 0, ws_lp_dtiles = 0, ws_lp_drecs = 0,
+            ws_lp_dmbuf = 0, ws_lp_dcount = 0;
+  long long ws_err = 0;               // match error of every patch's choice
   int scan_g = 1;                     // tiles per scan workgroup (tuned)
   bool rows_ok = false;               // the row-minima selection fits this plan
   bool ev_delta = false;              // additive Haar data events (see k_event_init)
@@ -1385,12 +1580,22 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   if (p.wavelet != 0 && p.wavelet != 1) return fail(CCWSIM_ERR_INVALID_ARG, "wavelet must be 0 (Haar) or 1 (5/3)");
   if (p.wavelet == 1 && (p.shortlist != 0 || p.proposer_dim != 0))
     return fail(CCWSIM_ERR_INVALID_ARG, "the 5/3 wavelet needs shortlist 0 and proposer_dim 0");
+  if (p.proposer_dim == 64) {
+    if (g.ndim != 2) return fail(CCWSIM_ERR_UNSUPPORTED, "the learned proposer runs on 2D training images");
+    if (p.score_mode != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "the learned proposer ranks squared-difference scores");
+    if (p.shortlist != 0) return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim and shortlist exclude each other");
+    if (!p.proposer) return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim 64 needs a proposer index");
+    if (p.lp_probe < 1 || p.lp_probe > kLpProbeMax)
+      return fail(CCWSIM_ERR_INVALID_ARG, "lp_probe must be in [1, %d]", kLpProbeMax);
+    if (!(p.lp_gate == p.lp_gate)) return fail(CCWSIM_ERR_INVALID_ARG, "lp_gate is not a number");
+  }
   g.wavelet = p.wavelet;
   if (p.wavelet == 1) g.shift = 1;
   if (p.max_hard_data < 0) return fail(CCWSIM_ERR_INVALID_ARG, "max_hard_data must be >= 0");
-  if (p.proposer_dim != 0 && p.proposer_dim != 8 && p.proposer_dim != 16 && p.proposer_dim != 32)
-    return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim must be 0, 8, 16 or 32");
-  if (p.proposer_dim) {
+  if (p.proposer_dim != 0 && p.proposer_dim != 8 && p.proposer_dim != 16 && p.proposer_dim != 32 &&
+      p.proposer_dim != 64)
+    return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim must be 0, 8, 16, 32 or 64");
+  if (p.proposer_dim && p.proposer_dim != 64) {
     if (p.score_mode != 0) return fail(CCWSIM_ERR_UNSUPPORTED, "the proposer bounds squared-difference scores only");
     if (p.shortlist != 0) return fail(CCWSIM_ERR_INVALID_ARG, "proposer_dim and shortlist exclude each other");
     if (g.tcells > kPcaMaxCells)
@@ -1398,7 +1603,8 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     if ((long long)g.cand[1] * g.cand[2] > 512)
       return fail(CCWSIM_ERR_UNSUPPORTED, "the proposer supports <= 512 candidate rows");
   }
-  P.learn = p.proposer_dim;
+  P.learn = p.proposer_dim == 64 ? 0 : p.proposer_dim;
+  P.lp = p.proposer_dim == 64;
   const int nd = g.ndim;
   P.n_orient = 1 << nd;
   P.n_shapes = P.n_orient << nd;
@@ -1844,6 +2050,23 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   }
   if (p.max_hard_data > 0 && !P.hdm) P.sel_fused_ok = false;   // its mismatches come from the bit table
   P.sel_fused = P.sel_fused_ok;   // before tuning
+  if (P.lp) {
+    // the patches the gate sends back go through the fused scan; the
+    // proposal keeps the level-J grid in LDS as int8 or int16
+    if (!P.sel_fused_ok)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "the learned proposer needs the selection fused into the scan");
+    const long long kmax = (long long)(p.n_facies - 1) * g.beta;
+    P.lp_kt = kmax <= 127 ? 1 : kmax <= 32767 ? 2 : 0;
+    if (!P.lp_kt) return fail(CCWSIM_ERR_UNSUPPORTED, "block sums up to %lld exceed int16", kmax);
+    P.lp_cap = kLpCandMax;
+    P.lp_lds = (size_t)lp_prop_lds(g, P.lp_kt, P.lp_cap, P.kpad);
+    if (P.lp_lds > 160 * 1024)
+      return fail(CCWSIM_ERR_UNSUPPORTED, "the proposal needs %zu B of LDS (level-J grid too large)", P.lp_lds);
+    for (const StepRange& sr : P.steps) P.lp_tmax = std::max(P.lp_tmax, sr.tcount);
+    if (P.lp_tmax > 256) return fail(CCWSIM_ERR_UNSUPPORTED, "more than 256 scan tiles in one step");
+    P.lp_cmp_lds = (size_t)P.max_slots * 16;
+    if (P.lp_cmp_lds > 60 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "more than 3840 patches in one step");
+  }
 
   // workspace
   const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
@@ -1872,6 +2095,17 @@ int build_plan(const ccwsim_params& p, Plan& P) {
   P.ws_keys = o;      o += align256((long long)P.max_slots * g.ncand * 8);
   P.ws_rowmin = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 8);
   P.ws_rowcnt = o;    o += align256((long long)P.max_slots * g.cand[1] * g.cand[2] * 4);
+  P.ws_err = o;       o += align256((long long)P.nfilters * 4);
+  if (P.lp) {
+    P.ws_lp_grid = o;   o += align256(lp_prop_grid_bytes(g, P.lp_kt));
+    P.ws_lp_sel = o;    o += align256((long long)P.max_slots * p.top_k * 8);
+    P.ws_lp_ok = o;     o += align256((long long)P.max_slots * 4);
+    P.ws_lp_map = o;    o += align256((long long)P.max_slots * 4);
+    P.ws_lp_dtiles = o; o += align256((long long)std::max(1, P.lp_tmax) * sizeof(TileDev));
+    P.ws_lp_drecs = o;  o += align256((long long)std::max(1, P.lp_tmax) * kFiltersPerTile * sizeof(ScanRec));
+    P.ws_lp_dmbuf = o;  o += align256((long long)P.max_slots * kKMax * 4);
+    P.ws_lp_dcount = o; o += 256;
+  }
   if (P.learn) {
     const long long n = g.tcells;
     P.ws_pca_part = o;  o += align256((long long)kPcaParts * (n * n + n) * 4);
@@ -2249,6 +2483,9 @@ struct FinArgs {
   const uint64_t* keys;
   const uint64_t* rowmin;
   const int32_t* rowcnt;          // fused selection: keys at the start of each row's segment, else null
+  const int32_t* lp_map;          // learned proposer: [slot] packed scan slot, or -1 (proposal stands)
+  const uint64_t* lp_sel;         // learned proposer: [slot][top_k] the proposal's K best keys
+  float* err_log;                 // [patch] match error of the chosen candidate (-1: no overlap)
   const int32_t* Ki;
   const int32_t* det;
   const int32_t* tree;  // block-subtree coefficients (tree path)
@@ -2444,13 +2681,17 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   } else {
     f = a.filters[slot];
   }
+  // learned proposer: the patch's slot in the scan's packed output, or -1
+  // where the proposal stands
+  const int kslot = a.lp_map ? a.lp_map[slot] : slot;
+  const bool from_lp = kslot < 0;
   // the row minima depend on the slot only: fetch them with the record
   const int nrows_c = g.cand[1] * g.cand[2];
   uint64_t rm_pre = ~0ull;
   int rc_pre = 0;
-  if ((a.cand_cap > 0 || a.rescore_rows) && tid < nrows_c) {
-    rm_pre = a.rowmin[(long long)slot * nrows_c + tid];
-    if (a.rowcnt) rc_pre = a.rowcnt[(long long)slot * nrows_c + tid];
+  if (!from_lp && (a.cand_cap > 0 || a.rescore_rows) && tid < nrows_c) {
+    rm_pre = a.rowmin[(long long)kslot * nrows_c + tid];
+    if (a.rowcnt) rc_pre = a.rowcnt[(long long)kslot * nrows_c + tid];
   }
   // keys per candidate row (fused selection: the row's survivors)
   constexpr int kRcLds = 512;
@@ -2519,7 +2760,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   // With stored keys the windows' loads go out after the row minima are
   // ranked, beside the loads of the best rows' keys: the staging of the row
   // minima would otherwise wait for them too.
-  const bool win_late = win_defer && !a.rescore_rows && a.cand_cap > 0;
+  const bool win_late = win_defer && !from_lp && !a.rescore_rows && a.cand_cap > 0;
   if (!win_defer) load_windows(s_sg, win_sg, s_hd, win_hd, f.org, g);
   else if (!win_late) issue_windows();
   for (int i = tid; i < (int)g.wcells; i += kThreads) keep[i] = 0;
@@ -2529,7 +2770,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   // those rows are read.
   const uint64_t tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
   const int k = min(a.top_k, g.ncand);
-  const uint64_t* kf = a.keys + (long long)slot * g.ncand;
+  const uint64_t* kf = a.keys + (long long)max(kslot, 0) * g.ncand;
   // ksel best bulk keys: k, or the shortlist that is rescored exactly below
   __shared__ uint64_t s_rowtop[kShortMax];
   __shared__ uint64_t s_sel[kShortMax];
@@ -2537,7 +2778,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   __shared__ unsigned s_cnt;
   const int ksel = a.shortlist > 0 ? min(a.shortlist, g.ncand) : k;
   bool done = false;
-  if (a.rescore_rows) {
+  if (from_lp) {
+    if (tid < k) s_sel[tid] = a.lp_sel[(long long)slot * a.top_k + tid];
+    __syncthreads();
+    done = true;
+  } else if (a.rescore_rows) {
     // The scan wrote, per candidate row, the smallest key of the row (the
     // row-minima selection) or the smallest lower bound of its keys (the
     // learned proposer).  Rows are rescored exactly in order of their
@@ -2547,7 +2792,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
     // rows: a row holding one of the k best keys has its minimum among them.
     const int nrows = g.cand[1] * g.cand[2];
     const int C0 = g.cand[0];
-    const uint64_t* rm = a.rowmin + (long long)slot * nrows;
+    const uint64_t* rm = a.rowmin + (long long)kslot * nrows;
     const bool exact_rows = a.rows_exact || f.bandmask == 0;   // no overlap: the row keys are exact keys
     unsigned char* lb = smem + a.learn_off;
     uint64_t* s_rk = (uint64_t*)lb;                                  // [nrows] sort keys
@@ -2675,7 +2920,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   } else if (a.cand_cap > 0) {
     // 1. the kr smallest row minima, by rank (rows are few)
     const int nrows = g.cand[1] * g.cand[2];
-    const uint64_t* rm = a.rowmin + (long long)slot * nrows;
+    const uint64_t* rm = a.rowmin + (long long)kslot * nrows;
     const int kr = min(ksel, nrows);
     uint64_t* s_rm = s_cand;   // staging; the candidate list reuses it afterwards
     if (nrows <= a.cand_cap) {
@@ -2713,7 +2958,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
         if (i < nc) {
           const int rr = s_rows[w.y];
           const int n_in_row =
-              !a.rowcnt ? cx : rr < kRcLds ? s_rc[rr] : a.rowcnt[(long long)slot * nrows + rr];
+              !a.rowcnt ? cx : rr < kRcLds ? s_rc[rr] : a.rowcnt[(long long)kslot * nrows + rr];
           if (w.x < n_in_row) v[q] = kf[(long long)rr * cx + w.x];
         }
         w.next();
@@ -2823,6 +3068,38 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   int idx = (int)tie_perm_inv((uint32_t)(s_fin[jpick] & kMask20), tkey);
   idx = min(max(idx, 0), g.ncand - 1);  // always in range for keys written by the scan
   if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
+  if (a.err_log) {
+    // match error of the choice: its score completed to the squared
+    // difference, sum n (K - |beta| m / n)^2 = S + sum |beta|^2 m^2 / n,
+    // over |beta|^2 times the known cells (orthonormal coefficients per
+    // known cell)
+    __shared__ double s_et[kThreads / 64], s_en[kThreads / 64];
+    const double B = (double)(1 << (g.shift - 1));
+    double t = 0.0, nn = 0.0;
+    if (tid < a.kpad && my_beta >= 0 && f.bandmask) {
+      const double m = (double)a.mbuf[(long long)(a.fbegin + slot) * kKMax + tid];
+      const int n = a.nbt[(long long)f.shape * g.tcells + my_beta];
+      if (n > 0) {
+        t = B * B * m * m / (double)n;
+        nn = (double)n;
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      t += __shfl_xor(t, m, 64);
+      nn += __shfl_xor(nn, m, 64);
+    }
+    if ((tid & 63) == 0) {
+      s_et[tid >> 6] = t;
+      s_en[tid >> 6] = nn;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double ts = s_et[0] + s_et[1] + s_et[2] + s_et[3], ns = s_en[0] + s_en[1] + s_en[2] + s_en[3];
+      const int32_t S = (int32_t)((uint32_t)((s_fin[jpick] >> 20) & 0xFFFFFFFFull) ^ 0x80000000u);
+      a.err_log[a.fbegin + slot] = ns > 0.0 ? (float)(((double)S + ts) / (B * B * ns)) : -1.f;
+    }
+  }
   const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
 
   if (win_defer) {
@@ -3280,7 +3557,10 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
   uint64_t* rowmin = (uint64_t*)(ws + P->ws_rowmin);
   int32_t* rowcnt = (int32_t*)(ws + P->ws_rowcnt);
-  const bool fused = sel_fused_of(P);
+  float* err_log = (float*)(ws + P->ws_err);
+  // the learned proposer's patches that fall back are scanned with the fused selection
+  const bool fused = P->lp || sel_fused_of(P);
+  const bool sel_rows = !fused && sel_rows_of(P);
   const int32_t* kbeta = (const int32_t*)(tbl + P->off_kbeta);
   const int32_t* nbt = (const int32_t*)(tbl + P->off_nbt);
   const FilterDev* filters = (const FilterDev*)(tbl + P->off_filters);
@@ -3362,6 +3642,16 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     k_pca_embed<<<nblocks(g.ncand), kThreads, 0, st>>>(Ki, g, P->learn, pca_mu, pca_P, emb, rn);
     HIP_TRY(hipGetLastError());
   }
+  // learned proposer: the level-J grid narrowed for the proposal's LDS
+  void* lp_grid = P->lp ? (void*)(ws + P->ws_lp_grid) : nullptr;
+  if (P->lp) {
+    ProfScope ps(CCWSIM_KIND_LEARN, st);
+    const long long gc = (long long)g.G[0] * g.G[1] * g.G[2];
+    const long long npad = lp_prop_grid_bytes(g, P->lp_kt) / P->lp_kt;
+    if (P->lp_kt == 1) k_lp_narrow<int8_t><<<nblocks(npad), kThreads, 0, st>>>(Ki, gc, npad, (int8_t*)lp_grid);
+    else k_lp_narrow<int16_t><<<nblocks(npad), kThreads, 0, st>>>(Ki, gc, npad, (int16_t*)lp_grid);
+    HIP_TRY(hipGetLastError());
+  }
   // grids start unknown (-1) except for hard data
   const long long allp = (long long)p->n_real * g.pcells;
   {
@@ -3371,7 +3661,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     if (n_hd > 0)
       k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
     k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
-    k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 16, 0);
+    k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 32, 0);
+    k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>((int32_t*)err_log, P->nfilters, (int32_t)0xBF800000u);
     if (P->ev_delta)
       k_event_init<<<(unsigned)P->nfilters, kThreads, (size_t)g.tcells * 4, st>>>(g, filters, kbeta, sg, mbuf,
                                                                                    P->kpad);
@@ -3407,7 +3698,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   sa.kpad = P->kpad;
   sa.W = P->W;
   sa.score_mode = p->score_mode;
-  sa.rowmin_only = !P->learn && sel_rows_of(P);
+  sa.rowmin_only = !P->learn && sel_rows;
   sa.standalone = 0;
   sa.has_hd = n_hd > 0;
   sa.rowcnt = rowcnt;
@@ -3453,7 +3744,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.dp_stride = P->dp_stride;
   fa.dp_batch = P->dp_batch;
   fa.learn = P->learn;
-  fa.rescore_rows = P->learn || sel_rows_of(P);
+  fa.rescore_rows = P->learn || sel_rows;
+  fa.err_log = p->score_mode == 0 ? err_log : nullptr;
   fa.rows_exact = !P->learn;
   fa.hdm = n_hd > 0 ? hdmask : nullptr;
   fa.hd_bits = hd_bits;
@@ -3495,7 +3787,68 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     if (sa.n_ginline)
       memcpy(sa.groups_inline, P->tbl_host.data() + P->off_groups + (size_t)s.gbegin[gix] * sizeof(int2),
              (size_t)s.gcount[gix] * sizeof(int2));
-    if (P->learn) {
+    if (P->lp) {
+      // proposals, then the patches the gate sends back packed into scan
+      // tiles, then the scan over those
+      LpPropArgs la = {};
+      la.g = g;
+      la.index = (const unsigned char*)p->proposer;
+      la.grid = lp_grid;
+      la.probe = p->lp_probe;
+      la.cap = P->lp_cap;
+      la.top_k = p->top_k;
+      la.kpad = P->kpad;
+      la.gate = p->lp_gate;
+      la.seed = p->seed;
+      la.filters = filters + s.fbegin;
+      la.fbegin = s.fbegin;
+      la.kbeta = kbeta;
+      la.nbt = nbt;
+      la.mbuf = mbuf;
+      la.hd_off = n_hd > 0 ? hd_off : nullptr;
+      la.sel = (uint64_t*)(ws + P->ws_lp_sel);
+      la.ok = (int32_t*)(ws + P->ws_lp_ok);
+      la.report = report;
+      {
+        ProfKernel pk(CCWSIM_KIND_LEARN);
+        if (P->lp_kt == 1)
+          hipExtLaunchKernelGGL(k_lp_propose<int8_t>, dim3((unsigned)s.fcount), dim3(kThreads), P->lp_lds, st, pk.a,
+                                pk.b, 0, la);
+        else
+          hipExtLaunchKernelGGL(k_lp_propose<int16_t>, dim3((unsigned)s.fcount), dim3(kThreads), P->lp_lds, st, pk.a,
+                                pk.b, 0, la);
+      }
+      LpCompactArgs ca = {};
+      ca.tiles = tiles + s.tbegin;
+      ca.recs = recs + (long long)s.tbegin * kFiltersPerTile;
+      ca.ntiles = s.tcount;
+      ca.nf = s.fcount;
+      ca.n_orient = P->n_orient;
+      ca.fbegin = s.fbegin;
+      ca.ok = la.ok;
+      ca.mbuf = mbuf;
+      ca.dtiles = (TileDev*)(ws + P->ws_lp_dtiles);
+      ca.drecs = (ScanRec*)(ws + P->ws_lp_drecs);
+      ca.dmbuf = (int32_t*)(ws + P->ws_lp_dmbuf);
+      ca.map = (int32_t*)(ws + P->ws_lp_map);
+      ca.dcount = (int32_t*)(ws + P->ws_lp_dcount);
+      k_lp_compact<<<1, kThreads, P->lp_cmp_lds, st>>>(ca);
+      ScanArgs sf = sa;
+      sf.kpad = P->sel_kk;
+      sf.klist = P->kpad;
+      sf.W = P->sel_W;
+      sf.segoff = (const int32_t*)(tbl + P->off_segoff);
+      sf.taps = (const int32_t*)(tbl + P->off_taps);
+      sf.n_tinline = 0;
+      sf.tiles = ca.dtiles;
+      sf.recs = ca.drecs;
+      sf.mbuf = ca.dmbuf;
+      sf.fbegin = 0;
+      sf.ntiles_dyn = ca.dcount;
+      ProfKernel pk(CCWSIM_KIND_SCAN);
+      launch_scan_sel(p->precision, n_hd > 0, kEnStage, rows, s.tcount, n_hd > 0 ? P->sel_lds_hd : P->sel_lds_nohd,
+                      st, sf, pk.a, pk.b);
+    } else if (P->learn) {
       xa.tiles = tiles + s.tbegin;
       xa.recs = recs + (long long)s.tbegin * kFiltersPerTile;
       xa.fbegin = s.fbegin;
@@ -3521,6 +3874,10 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     }
     fa.filters = filters + s.fbegin;
     fa.fbegin = s.fbegin;
+    if (P->lp) {
+      fa.lp_map = (const int32_t*)(ws + P->ws_lp_map);
+      fa.lp_sel = (const uint64_t*)(ws + P->ws_lp_sel);
+    }
     fa.n_inline = s.fcount <= kFinInline ? s.fcount : 0;
     if (fa.n_inline)
       memcpy(fa.recs_inline, P->tbl_host.data() + P->off_filters + (size_t)s.fbegin * sizeof(FilterDev),
@@ -3669,6 +4026,18 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
     return fail(CCWSIM_ERR_INVALID_ARG, "%lld hard data exceed max_hard_data = %d", (long long)n_hd, p->max_hard_data);
   CCW_TRY(plan_pin(P));
   hipStream_t st = as_stream(stream);
+  if (P->lp) {
+    // the index header, read back unless the stream is being captured (the
+    // proposal kernel checks it again and sends every patch to the scan
+    // when it does not match)
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cst));
+    if (cst == hipStreamCaptureStatusNone && P->lp_checked != p->proposer) {
+      CCW_TRY(lp_index_check(p->proposer, P->g, st, nullptr));
+      P->lp_checked = p->proposer;
+    }
+    CCW_TRY(lp_lds_allow(P->lp_kt, P->lp_lds));
+  }
   bool prof;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -3677,7 +4046,7 @@ extern "C" int ccwsim_simulate(const ccwsim_params* p, const int8_t* ti, int64_t
   // First call of a plan: look the scan shape up in the tuning table, else
   // run eagerly once (a full, valid call) and time the widest step's scan
   // for each variant (output layout, tiles per workgroup).
-  if (!P->tuned && g_scan_g_force == 0 && g_sel_force == 0 && !P->learn) {
+  if (!P->tuned && g_scan_g_force == 0 && g_sel_force == 0 && !P->learn && !P->lp) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_once();
     const std::string tk = tune_key(P, p);
@@ -3902,11 +4271,71 @@ extern "C" int ccwsim_simulate_report(const ccwsim_params* p, const void* worksp
   CCW_TRY(get_plan(*p, &Ph));
   Plan* P = Ph.get();
   if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
-  unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipStream_t st = as_stream(stream);
   HIP_TRY(hipMemcpyAsync(v, (const unsigned char*)workspace + P->ws_report, sizeof v, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  for (int i = 0; i < 6; ++i) out[i] = (int64_t)v[i];
+  for (int i = 0; i < 8; ++i) out[i] = (int64_t)v[i];
+  return CCWSIM_OK;
+}
+
+namespace {
+// Every patch's data event as the scan takes it (known cells and code sums
+// per template block), with its realization and raster step.
+__global__ __launch_bounds__(kThreads) void k_export_events(Geom g, const FilterDev* __restrict__ filters,
+                                                            const int32_t* __restrict__ kbeta,
+                                                            const int32_t* __restrict__ nbt,
+                                                            const int32_t* __restrict__ mbuf, int kpad,
+                                                            int32_t* __restrict__ or_n, int32_t* __restrict__ or_m,
+                                                            int32_t* __restrict__ real, int32_t* __restrict__ step) {
+  const int pi = blockIdx.x, tid = threadIdx.x;
+  const FilterDev f = filters[pi];
+  const long long tcl = g.tcells;
+  for (int i = tid; i < (int)tcl; i += kThreads) {
+    or_n[pi * tcl + i] = 0;
+    or_m[pi * tcl + i] = 0;
+  }
+  __syncthreads();
+  if (tid < kpad && f.bandmask) {
+    const int beta = kbeta[f.orient * kKMax + tid];
+    if (beta >= 0) {
+      or_n[pi * tcl + beta] = nbt[(long long)f.shape * tcl + beta];
+      or_m[pi * tcl + beta] = mbuf[(long long)pi * kKMax + tid];
+    }
+  }
+  if (tid == 0) {
+    if (real) real[pi] = f.r;
+    if (step) step[pi] = f.step;
+  }
+}
+}  // namespace
+
+extern "C" int ccwsim_simulate_events(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
+                                      int32_t* or_n, int32_t* or_m, int32_t* realization, int32_t* step,
+                                      void* stream) {
+  if (!p || !workspace || !or_n || !or_m) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  std::shared_ptr<Plan> Ph;
+  CCW_TRY(get_plan(*p, &Ph));
+  Plan* P = Ph.get();
+  if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
+  const unsigned char* ws = (const unsigned char*)workspace;
+  const unsigned char* tbl = ws + P->ws_tbl;
+  k_export_events<<<(unsigned)P->nfilters, kThreads, 0, as_stream(stream)>>>(
+      P->g, (const FilterDev*)(tbl + P->off_filters), (const int32_t*)(tbl + P->off_kbeta),
+      (const int32_t*)(tbl + P->off_nbt), (const int32_t*)(ws + P->ws_mbuf), P->kpad, or_n, or_m, realization, step);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_simulate_match_errors(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
+                                            float* out, void* stream) {
+  if (!p || !workspace || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  std::shared_ptr<Plan> Ph;
+  CCW_TRY(get_plan(*p, &Ph));
+  Plan* P = Ph.get();
+  if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
+  HIP_TRY(hipMemcpyAsync(out, (const unsigned char*)workspace + P->ws_err, (size_t)P->nfilters * 4,
+                         hipMemcpyDeviceToDevice, as_stream(stream)));
   return CCWSIM_OK;
 }
 

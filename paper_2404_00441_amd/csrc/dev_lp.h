@@ -18,6 +18,7 @@
 #pragma once
 
 #include "dev_kernels.h"
+#include "dev_scan.h"
 
 namespace ccw {
 
@@ -321,6 +322,18 @@ __global__ void k_lp_init(float* __restrict__ w, uint64_t seed) {
     }
 }
 
+// Query encoder input from data events given per template block as
+// or_n (known cells) and or_m (sum of their codes): m / |beta| and
+// n / |beta| as two channels.
+__global__ void k_lp_events(const int32_t* __restrict__ or_n, const int32_t* __restrict__ or_m, int B, long long wc,
+                            float inv_beta, float* __restrict__ out) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)B * wc) return;
+  const long long b = id / wc, p = id - b * wc;
+  out[(b * 2) * wc + p] = (float)or_m[id] * inv_beta;
+  out[(b * 2 + 1) * wc + p] = (float)or_n[id] * inv_beta;
+}
+
 // The TI's approximation as the key encoder's input: K / |beta|.
 __global__ void k_lp_kin(const int32_t* __restrict__ K, long long n, float inv_beta, float* __restrict__ out) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,6 +416,640 @@ __global__ __launch_bounds__(kThreads) void k_lp_topk(const float* __restrict__ 
       ++before;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Inverted lists over the keys, built once per TI and weights: Lloyd's
+// k-means in the 64-d key space puts every candidate in the list of its
+// nearest centroid.  A data event's query ranks the centroids by inner
+// product; only the members of the best lists are scored exactly.
+// ---------------------------------------------------------------------------
+constexpr int32_t kLpMagic = 0x4C504958;
+constexpr int kLpListsMax = 1024;   // lists of an index
+constexpr int kLpProbeMax = 64;     // lists probed per data event
+constexpr int kLpCandMax = 1024;    // candidates scored exactly per data event
+
+struct LpIndexHeader {
+  int32_t magic, n_lists, level, ndim;
+  int32_t G[3], cand[3], tc[3], pad0;
+  int64_t ncand;
+  int64_t off_w;      // bytes from the index base: the query encoder's weights (float)
+  int64_t off_cent;   // centroids [n_lists][64] (float)
+  int64_t off_list;   // list offsets [n_lists + 1] (int32)
+  int64_t off_mem;    // members [ncand] (int32), by list, ascending within a list
+  int64_t bytes;
+};
+__host__ __device__ inline long long lp_query_floats() { return lp_weights_total() - lp_offset(1, 0); }
+
+// Starting centroids: keys at evenly spaced candidate indices.
+__global__ void k_km_init(const float* __restrict__ keys, long long ncand, int nl, float* __restrict__ cent) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nl * kLpD) return;
+  const int j = id / kLpD, d = id - j * kLpD;
+  cent[id] = keys[((long long)j * ncand / nl) * kLpD + d];
+}
+
+// Nearest centroid of every key by squared distance (ties to the smaller
+// list); the centroids pass through LDS 64 at a time.
+__global__ __launch_bounds__(kThreads) void k_km_assign(const float* __restrict__ keys, long long ncand,
+                                                        const float* __restrict__ cent, int nl,
+                                                        int32_t* __restrict__ assign) {
+  __shared__ float s_c[64][kLpD + 1];
+  __shared__ float s_nrm[64];
+  const int tid = threadIdx.x;
+  const long long c = (long long)blockIdx.x * kThreads + tid;
+  float k[kLpD];
+#pragma unroll
+  for (int d = 0; d < kLpD; ++d) k[d] = c < ncand ? keys[c * kLpD + d] : 0.f;
+  float best = 3.4e38f;
+  int bj = 0;
+  for (int j0 = 0; j0 < nl; j0 += 64) {
+    __syncthreads();
+    for (int i = tid; i < 64 * kLpD; i += kThreads) {
+      const int jj = i / kLpD, d = i - jj * kLpD;
+      s_c[jj][d] = j0 + jj < nl ? cent[(long long)(j0 + jj) * kLpD + d] : 0.f;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      float n = 0.f;
+      for (int d = 0; d < kLpD; ++d) n += s_c[tid][d] * s_c[tid][d];
+      s_nrm[tid] = n;
+    }
+    __syncthreads();
+    const int nj = min(64, nl - j0);
+    for (int jj = 0; jj < nj; ++jj) {
+      float dot = 0.f;
+#pragma unroll
+      for (int d = 0; d < kLpD; ++d) dot += k[d] * s_c[jj][d];
+      const float dist = s_nrm[jj] - 2.f * dot;
+      if (dist < best) {
+        best = dist;
+        bj = j0 + jj;
+      }
+    }
+  }
+  if (c < ncand) assign[c] = bj;
+}
+
+// Members of list j (one workgroup per list) in ascending candidate order:
+// with off == null only their number goes to cnt[j]; otherwise they are
+// written from off[j] on.
+__global__ __launch_bounds__(kThreads) void k_km_lists(const int32_t* __restrict__ assign, long long ncand,
+                                                       const int32_t* __restrict__ off, int32_t* __restrict__ out) {
+  __shared__ int s_w[kThreads / 64];
+  __shared__ int s_run;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = blockIdx.x;
+  if (tid == 0) s_run = 0;
+  __syncthreads();
+  for (long long b = 0; b < ncand; b += kThreads) {
+    const long long c = b + tid;
+    const bool hit = c < ncand && assign[c] == j;
+    const unsigned long long bal = __ballot(hit);
+    if (lane == 0) s_w[wave] = __popcll(bal);
+    __syncthreads();
+    int before = s_run;
+    for (int w = 0; w < wave; ++w) before += s_w[w];
+    before += __popcll(bal & ((1ull << lane) - 1ull));
+    if (hit && off) out[off[j] + before] = (int32_t)c;
+    __syncthreads();
+    if (tid == 0) s_run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+  }
+  if (!off && tid == 0) out[j] = s_run;
+}
+
+// Exclusive prefix sums of the list sizes, off[0..nl] (one thread: nl <= 1024).
+__global__ void k_km_offsets(const int32_t* __restrict__ cnt, int nl, int32_t* __restrict__ off) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int run = 0;
+  for (int j = 0; j < nl; ++j) {
+    off[j] = run;
+    run += cnt[j];
+  }
+  off[nl] = run;
+}
+
+// Centroid j = mean of its members' keys, summed in a fixed order; an
+// empty list keeps its centroid.
+__global__ __launch_bounds__(kThreads) void k_km_update(const float* __restrict__ keys,
+                                                        const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ mem, float* __restrict__ cent) {
+  __shared__ float s_p[kThreads / kLpD][kLpD];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int d = tid % kLpD, part = tid / kLpD;
+  const int lo = off[j], n = off[j + 1] - lo;
+  float s = 0.f;
+  for (int i = part; i < n; i += kThreads / kLpD) s += keys[(long long)mem[lo + i] * kLpD + d];
+  s_p[part][d] = s;
+  __syncthreads();
+  if (tid < kLpD && n > 0) {
+    float t = 0.f;
+    for (int q = 0; q < kThreads / kLpD; ++q) t += s_p[q][tid];
+    cent[(long long)j * kLpD + tid] = t / (float)n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The query of one data event, evaluated only where the query encoder's
+// output at the window's centre block h depends on it: layer 2 (dilation
+// 4) at h, layer 1 (dilation 2) at h + 4 d, layer 0 at h + 4 d + 2 e for
+// d, e in {-1, 0, 1}^2 (a 7 x 7 lattice of step 2), each position outside
+// the window being zero (the maps' zero padding).  Equal to the full
+// encoder's output at h.  All threads of the workgroup take part.
+//   ev: [2][tc1][tc0] input channels; a0: [49][32]; a1: [9][32]; a2: [32];
+//   q: [64] output.  W: the query encoder's weights.
+// ---------------------------------------------------------------------------
+__device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, int tc0, int tc1, float* a0, float* a1,
+                                float* a2, float* q) {
+  const int tid = threadIdx.x;
+  const int h0 = tc0 / 2, h1 = tc1 / 2;
+  const long long o0 = 0, o1 = lp_layer_size(0, 2), o2 = o1 + lp_layer_size(1, 2), o3 = o2 + lp_layer_size(2, 2);
+  // layer 0: 2 -> 32 channels, dilation 1
+  for (int o = tid; o < 49 * kLpC; o += kThreads) {
+    const int pos = o / kLpC, co = o - pos * kLpC;
+    const int py = h1 + 2 * (pos / 7) - 6, px = h0 + 2 * (pos % 7) - 6;
+    float s = 0.f;
+    if (py >= 0 && py < tc1 && px >= 0 && px < tc0) {
+      s = W[o0 + kLpC * 2 * 9 + co];
+      for (int ci = 0; ci < 2; ++ci)
+        for (int t = 0; t < 9; ++t) {
+          const int yy = py + t / 3 - 1, xx = px + t % 3 - 1;
+          if (yy >= 0 && yy < tc1 && xx >= 0 && xx < tc0)
+            s += W[o0 + (co * 2 + ci) * 9 + t] * ev[(ci * tc1 + yy) * tc0 + xx];
+        }
+      s = fmaxf(s, 0.f);
+    }
+    a0[o] = s;
+  }
+  __syncthreads();
+  // layer 1: 32 -> 32, dilation 2; 8 lanes per output, 4 input channels each
+  for (int it = tid; it < 9 * kLpC * 8; it += kThreads) {
+    const int o = it >> 3, part = it & 7;
+    const int pos = o / kLpC, co = o - pos * kLpC;
+    const int dy = pos / 3 - 1, dx = pos % 3 - 1;
+    const int py = h1 + 4 * dy, px = h0 + 4 * dx;
+    const bool in = py >= 0 && py < tc1 && px >= 0 && px < tc0;
+    float s = 0.f;
+    if (in) {
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const int ci = part * 4 + c4;
+        const float* w = W + o1 + ((long long)co * kLpC + ci) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          // layer-0 lattice point h + 4 d + 2 e with e = tap offset
+          const int ly = 2 * (dy + 1) + (t / 3), lx = 2 * (dx + 1) + (t % 3);
+          s += w[t] * a0[(ly * 7 + lx) * kLpC + ci];
+        }
+      }
+    }
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (part == 0) a1[o] = in ? fmaxf(s + W[o1 + kLpC * kLpC * 9 + co], 0.f) : 0.f;
+  }
+  __syncthreads();
+  // layer 2: 32 -> 32, dilation 4, at h only; 8 lanes per output
+  {
+    const int co = tid >> 3, part = tid & 7;
+    float s = 0.f;
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int ci = part * 4 + c4;
+      const float* w = W + o2 + ((long long)co * kLpC + ci) * 9;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) s += w[t] * a1[t * kLpC + ci];
+    }
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (part == 0) a2[co] = fmaxf(s + W[o2 + kLpC * kLpC * 9 + co], 0.f);
+  }
+  __syncthreads();
+  // layer 3: 1x1, 32 -> 64; 4 lanes per output
+  {
+    const int d = tid >> 2, part = tid & 3;
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s += W[o3 + (long long)d * kLpC + part * 8 + c] * a2[part * 8 + c];
+    s += __shfl_xor(s, 1, 4);
+    s += __shfl_xor(s, 2, 4);
+    if (part == 0) q[d] = s + W[o3 + kLpD * kLpC + d];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Proposal for one data event per workgroup: the query, the probed lists,
+// the exact score of every member (Sec. 4.3 score in integers, from the
+// level-J grid staged in LDS), the K best keys among them and the gate.
+// A patch falls back to the full scan when its overlap is empty, when hard
+// data lie in its virtual template, when fewer than K candidates were
+// scored, or when the best match error exceeds the gate.
+// ---------------------------------------------------------------------------
+struct LpPropArgs {
+  Geom g;
+  const unsigned char* index;   // LpIndexHeader and its arrays
+  const void* grid;             // level-J grid, KT [G1][G0], 16-byte padded
+  int probe, cap, top_k, kpad;
+  float gate;                   // largest accepted match error (< 0: always fall back)
+  uint64_t seed;
+  int standalone;
+  // simulation: the step's patches
+  const FilterDev* filters;
+  int fbegin;
+  const int32_t* kbeta;         // [orient][kKMax] block lists
+  const int32_t* nbt;           // [shape][tcells] known cells per block
+  const int32_t* mbuf;          // [patch][kKMax] data events
+  const int32_t* hd_off;        // [patch + 1] hard data per virtual template, or null
+  uint64_t* sel;                // [slot][top_k] the K best keys
+  int32_t* ok;                  // [slot] 1: the proposal stands, 0: the full scan decides
+  unsigned long long* report;
+  // standalone: events as for the scan
+  const int32_t* or_n;
+  const int32_t* or_m;
+  const int32_t* fil_real;
+  const int64_t* fil_step;
+  uint64_t* keys_out;           // [f][top_k]
+  int32_t* list_out;            // [f][cap] candidates scored, or null
+  int32_t* nlist_out;           // [f], or null
+  float* q_out;                 // [f][64], or null
+  float* err_out;               // [f] best match error, or null
+};
+
+// LDS of k_lp_propose: the grid, the candidate list, then one area shared
+// by the encoder's scratch and the keys; the event's block list after it.
+__host__ __device__ inline long long lp_prop_grid_bytes(const Geom& g, int kt_bytes) {
+  return ((long long)g.G[0] * g.G[1] * kt_bytes + 15) & ~15ll;
+}
+__host__ __device__ inline long long lp_prop_alias_bytes(const Geom& g, int cap) {
+  long long v = (2 * g.tcells + 49 * kLpC + 9 * kLpC + kLpC) * 4;   // encoder scratch
+  if ((long long)cap * 8 > v) v = (long long)cap * 8;                 // keys
+  if (4ll * kLpListsMax > v) v = 4ll * kLpListsMax;                   // list scores
+  return (v + 15) & ~15ll;
+}
+__host__ __device__ inline long long lp_prop_lds(const Geom& g, int kt_bytes, int cap, int list_len) {
+  return lp_prop_grid_bytes(g, kt_bytes) + (((long long)cap * 4 + 15) & ~15ll) + lp_prop_alias_bytes(g, cap) +
+         4ll * 4 * list_len;
+}
+
+template <typename KT>
+__global__ __launch_bounds__(kThreads) void k_lp_propose(LpPropArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ TopkShared sh;
+  __shared__ int s_probe[kLpProbeMax], s_lo[kLpProbeMax], s_len[kLpProbeMax], s_pos[kLpProbeMax];
+  __shared__ int s_nk, s_M, s_np, s_force;
+  __shared__ float s_q[kLpD];
+  __shared__ double s_rt[kThreads / 64], s_rn[kThreads / 64];
+  const Geom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int slot = blockIdx.x;
+  const LpIndexHeader* H = (const LpIndexHeader*)a.index;
+  const int G0 = g.G[0];
+  const int tcells = (int)g.tcells;
+  KT* s_K = (KT*)smem;
+  int* s_cand = (int*)(smem + lp_prop_grid_bytes(g, (int)sizeof(KT)));
+  unsigned char* alias = (unsigned char*)s_cand + (((long long)a.cap * 4 + 15) & ~15ll);
+  uint64_t* s_keys = (uint64_t*)alias;
+  float* s_ev = (float*)alias;
+  float* s_a0 = s_ev + 2 * tcells;
+  float* s_a1 = s_a0 + 49 * kLpC;
+  float* s_a2 = s_a1 + 9 * kLpC;
+  float* s_cs = (float*)alias;   // list scores, after the encoder
+  int* s_beta = (int*)(alias + lp_prop_alias_bytes(g, a.cap));
+  const int L = a.standalone ? tcells : a.kpad;   // block list capacity
+  int* s_koff = s_beta + L;
+  int* s_m = s_koff + L;
+  int* s_n = s_m + L;
+
+  // the grid: every 16-byte word of it, loads issued before the stores
+  {
+    const int nv = (int)(lp_prop_grid_bytes(g, (int)sizeof(KT)) / 16);
+    const uint4* src = (const uint4*)a.grid;
+    uint4* dst = (uint4*)s_K;
+    for (int v0 = tid; v0 < nv; v0 += kThreads * 8) {
+      uint4 r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int v = v0 + u * kThreads;
+        if (v < nv) r[u] = src[v];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int v = v0 + u * kThreads;
+        if (v < nv) dst[v] = r[u];
+      }
+    }
+  }
+  // an index built for another geometry sends every patch to the scan
+  const bool hdr_ok = H->magic == kLpMagic && H->n_lists >= 1 && H->n_lists <= kLpListsMax && H->ncand == g.ncand &&
+                      H->G[0] == g.G[0] && H->G[1] == g.G[1] && H->cand[0] == g.cand[0] &&
+                      H->cand[1] == g.cand[1] && H->tc[0] == g.tc[0] && H->tc[1] == g.tc[1];
+  for (int i = tid; i < 2 * tcells; i += kThreads) s_ev[i] = 0.f;
+  uint64_t tkey = 0;
+  if (tid == 0) {
+    s_nk = 0;
+    s_force = hdr_ok ? 0 : 1;
+  }
+  __syncthreads();
+  // the event's block list: (block, offset in the grid, m, n)
+  if (!a.standalone) {
+    const FilterDev f = a.filters[slot];
+    tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
+    if (tid < a.kpad) {
+      const int beta = a.kbeta[f.orient * kKMax + tid];
+      int m = 0, n = 0, off = 0;
+      if (beta >= 0 && f.bandmask) {
+        m = a.mbuf[(long long)(a.fbegin + slot) * kKMax + tid];
+        n = a.nbt[(long long)f.shape * tcells + beta];
+        int bx, by, bz;
+        split3(beta, g.tc[0], g.tc[1], bx, by, bz);
+        off = by * G0 + bx;
+      }
+      s_beta[tid] = n > 0 ? beta : -1;
+      s_koff[tid] = off;
+      s_m[tid] = m;
+      s_n[tid] = n;
+    }
+    if (tid == 0) {
+      s_nk = a.kpad;
+      const bool hd = a.hd_off && a.hd_off[a.fbegin + slot + 1] > a.hd_off[a.fbegin + slot];
+      if (f.bandmask == 0 || hd) s_force = 1;
+    }
+  } else {
+    if (a.fil_real) tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)a.fil_real[slot], (uint64_t)a.fil_step[slot]);
+    for (int b = tid; b < tcells; b += kThreads) {
+      const int n = a.or_n[(long long)slot * tcells + b];
+      if (n > 0) {
+        const int i = atomicAdd(&s_nk, 1);   // list order does not change integer sums
+        int bx, by, bz;
+        split3(b, g.tc[0], g.tc[1], bx, by, bz);
+        s_beta[i] = b;
+        s_koff[i] = by * G0 + bx;
+        s_m[i] = a.or_m[(long long)slot * tcells + b];
+        s_n[i] = n;
+      }
+    }
+  }
+  __syncthreads();
+  const int nk = s_nk;
+  // the encoder's input, and the match error's constant term
+  // sum |beta|^2 m^2 / n and the known cells sum n
+  const double B = (double)(1 << (g.shift - 1));
+  double ct = 0.0, cn = 0.0;
+  for (int i = tid; i < nk; i += kThreads) {
+    const int n = s_n[i];
+    if (n > 0) {
+      const float inv = 1.f / (float)g.beta;
+      s_ev[s_beta[i]] = (float)s_m[i] * inv;
+      s_ev[tcells + s_beta[i]] = (float)n * inv;
+      ct += B * B * (double)s_m[i] * (double)s_m[i] / (double)n;
+      cn += (double)n;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    ct += __shfl_xor(ct, m, 64);
+    cn += __shfl_xor(cn, m, 64);
+  }
+  if (lane == 0) {
+    s_rt[wave] = ct;
+    s_rn[wave] = cn;
+  }
+  __syncthreads();
+  if (!hdr_ok) {   // nothing of the index is read
+    if (tid == 0) {
+      s_M = 0;
+      s_np = 0;
+    }
+    for (int i = tid; i < kLpD; i += kThreads) s_q[i] = 0.f;
+    __syncthreads();
+  } else {
+  lp_query_sparse((const float*)(a.index + H->off_w), s_ev, g.tc[0], g.tc[1], s_a0, s_a1, s_a2, s_q);
+  if (a.q_out && tid < kLpD) a.q_out[(long long)slot * kLpD + tid] = s_q[tid];
+  // the lists by the inner product of the query with their centroid
+  const float* cent = (const float*)(a.index + H->off_cent);
+  const int nl = hdr_ok ? H->n_lists : 1;
+  for (int j = tid; j < nl; j += kThreads) {
+    const float4* c4 = (const float4*)(cent + (long long)j * kLpD);
+    float s = 0.f;
+#pragma unroll
+    for (int d = 0; d < kLpD / 4; ++d) {
+      const float4 c = c4[d];
+      s += s_q[4 * d] * c.x + s_q[4 * d + 1] * c.y + s_q[4 * d + 2] * c.z + s_q[4 * d + 3] * c.w;
+    }
+    s_cs[j] = s == s ? s : -INFINITY;   // a total order for the ranks below
+  }
+  __syncthreads();
+  const int P = min(a.probe, nl);
+  for (int j = tid; j < nl; j += kThreads) {
+    const float x = s_cs[j];
+    int r = 0;
+    for (int i = 0; i < nl; ++i) {
+      const float y = s_cs[i];
+      r += (y > x || (y == x && i < j)) ? 1 : 0;
+    }
+    if (r < P) s_probe[r] = j;
+  }
+  __syncthreads();
+  const int32_t* loff = (const int32_t*)(a.index + H->off_list);
+  const int32_t* mem = (const int32_t*)(a.index + H->off_mem);
+  if (tid == 0) {
+    int M = 0, np = 0;
+    for (int r = 0; r < P; ++r) {
+      const int j = s_probe[r];
+      const int lo = loff[j];
+      int len = loff[j + 1] - lo;
+      if (M + len > a.cap) {
+        if (r > 0) break;
+        len = a.cap;
+      }
+      s_lo[np] = lo;
+      s_len[np] = len;
+      s_pos[np] = M;
+      M += len;
+      ++np;
+    }
+    s_M = M;
+    s_np = np;
+    if (M < min(a.top_k, (int)g.ncand)) s_force = 1;
+  }
+  __syncthreads();
+  for (int r = 0; r < s_np; ++r)
+    for (int i = tid; i < s_len[r]; i += kThreads) s_cand[s_pos[r] + i] = mem[s_lo[r] + i];
+  __syncthreads();
+  }
+  const int M = s_M;
+  const int k = min(a.top_k, (int)g.ncand);
+  const bool force = s_force != 0;
+  if (!force || a.standalone) {
+    // exact keys of the members (mismatch 0: patches with hard data fall back)
+    const int C0 = g.cand[0];
+    const int shift = g.shift;
+    for (int i = tid; i < M; i += kThreads) {
+      const int c = min(max(s_cand[i], 0), (int)g.ncand - 1);
+      const int cy = c / C0, cx = c - cy * C0;
+      const KT* kb = s_K + cy * G0 + cx;
+      int E = 0, C = 0;
+      for (int q = 0; q < nk; ++q) {
+        const int kv = (int)kb[s_koff[q]];
+        E += s_n[q] * kv * kv;
+        C += s_m[q] * kv;
+      }
+      s_keys[i] = make_key(0u, E - (C << shift), tie_perm((uint32_t)c, tkey));
+    }
+    __syncthreads();
+    if (M >= k) block_topk(M, k, [&](long long i) { return s_keys[i]; }, sh);
+  }
+  if (tid == 0) {
+    double err = -1.0;
+    const double tsum = s_rt[0] + s_rt[1] + s_rt[2] + s_rt[3], nsum = s_rn[0] + s_rn[1] + s_rn[2] + s_rn[3];
+    if (M >= k && nsum > 0.0 && (!force || a.standalone)) {
+      const int32_t S = (int32_t)((uint32_t)((sh.top[0] >> 20) & 0xFFFFFFFFull) ^ 0x80000000u);
+      err = ((double)S + tsum) / (B * B * nsum);
+    }
+    const bool fb = force || a.gate < 0.f || err > (double)a.gate;
+    if (!a.standalone) {
+      a.ok[slot] = fb ? 0 : 1;
+      atomicAdd(&a.report[fb ? 6 : 4], 1ull);
+      if (!force) atomicAdd(&a.report[5], (unsigned long long)M);
+    } else {
+      if (a.nlist_out) a.nlist_out[slot] = M;
+      if (a.err_out) a.err_out[slot] = (float)err;
+    }
+  }
+  if (!a.standalone) {
+    if (tid < k && !force) a.sel[(long long)slot * a.top_k + tid] = sh.top[tid];
+  } else {
+    if (tid < k) a.keys_out[(long long)slot * a.top_k + tid] = M >= k ? sh.top[tid] : ~0ull;
+    if (a.list_out)
+      for (int i = tid; i < M; i += kThreads) a.list_out[(long long)slot * a.cap + i] = s_cand[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The step's patches that fall back, packed into scan tiles of one
+// orientation each (in slot order), with their records and data events;
+// map[slot] = the packed slot, or -1 where the proposal stands.  One
+// workgroup; the packed tiles never outnumber the step's tiles.
+// ---------------------------------------------------------------------------
+struct LpCompactArgs {
+  const TileDev* tiles;   // the step's tiles
+  const ScanRec* recs;    // [tile][kFiltersPerTile]
+  int ntiles, nf, n_orient, fbegin;
+  const int32_t* ok;      // [slot]
+  const int32_t* mbuf;    // [patch][kKMax]
+  TileDev* dtiles;
+  ScanRec* drecs;
+  int32_t* dmbuf;         // [packed slot][kKMax]
+  int32_t* map;           // [slot]
+  int32_t* dcount;        // packed tiles
+};
+
+__global__ __launch_bounds__(kThreads) void k_lp_compact(LpCompactArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* s_or = (int*)smem;          // [nf] orientation, -1: proposal stands
+  int* s_ri = s_or + a.nf;         // [nf] record index
+  int* s_zm = s_ri + a.nf;         // [nf] zmask bit
+  int* s_map = s_zm + a.nf;        // [nf]
+  __shared__ int s_w[kThreads / 64];
+  __shared__ int s_cnt[8], s_bslot[8], s_btile[8];
+  __shared__ uint32_t s_dz[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < a.nf; i += kThreads) s_or[i] = -1;
+  for (int i = tid; i < 256; i += kThreads) s_dz[i] = 0u;
+  __syncthreads();
+  for (int i = tid; i < a.ntiles * kFiltersPerTile; i += kThreads) {
+    const int t = i / kFiltersPerTile, j = i - t * kFiltersPerTile;
+    const TileDev td = a.tiles[t];
+    if (j < td.count) {
+      const int slot = td.first + j;
+      const bool fb = a.recs[i].gidx >= 0 && a.ok[slot] == 0;
+      s_or[slot] = fb ? td.orient : -1;
+      s_ri[slot] = i;
+      s_zm[slot] = (int)((td.zmask >> j) & 1u);
+    }
+  }
+  __syncthreads();
+  // per orientation: the packed position of each of its patches, in slot order
+  for (int o = 0; o < a.n_orient; ++o) {
+    int run = 0;
+    for (int b = 0; b < a.nf; b += kThreads) {
+      const int slot = b + tid;
+      const bool hit = slot < a.nf && s_or[slot] == o;
+      const unsigned long long bal = __ballot(hit);
+      if (lane == 0) s_w[wave] = __popcll(bal);
+      __syncthreads();
+      int before = run;
+      for (int w = 0; w < wave; ++w) before += s_w[w];
+      before += __popcll(bal & ((1ull << lane) - 1ull));
+      if (hit) s_map[slot] = before;   // position within the orientation for now
+      run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+      __syncthreads();
+    }
+    if (tid == 0) s_cnt[o] = run;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int bs = 0, bt = 0;
+    for (int o = 0; o < a.n_orient; ++o) {
+      s_bslot[o] = bs;
+      s_btile[o] = bt;
+      bs += s_cnt[o];
+      bt += (s_cnt[o] + kFiltersPerTile - 1) / kFiltersPerTile;
+    }
+    *a.dcount = bt;
+  }
+  __syncthreads();
+  for (int slot = tid; slot < a.nf; slot += kThreads) {
+    const int o = s_or[slot];
+    int cs = -1;
+    if (o >= 0) {
+      const int pos = s_map[slot];
+      cs = s_bslot[o] + pos;
+      const int t = s_btile[o] + pos / kFiltersPerTile, j = pos % kFiltersPerTile;
+      a.drecs[t * kFiltersPerTile + j] = a.recs[s_ri[slot]];
+      if (s_zm[slot]) atomicOr(&s_dz[t], 1u << j);
+    }
+    s_map[slot] = cs;
+    a.map[slot] = cs;
+  }
+  __syncthreads();
+  for (int o = 0; o < a.n_orient; ++o) {
+    const int nt = (s_cnt[o] + kFiltersPerTile - 1) / kFiltersPerTile;
+    for (int i = tid; i < nt * kFiltersPerTile; i += kThreads) {
+      const int tt = i / kFiltersPerTile, j = i - tt * kFiltersPerTile;
+      const int t = s_btile[o] + tt;
+      const int count = min(kFiltersPerTile, s_cnt[o] - tt * kFiltersPerTile);
+      if (j == 0) {
+        TileDev d;
+        d.first = s_bslot[o] + tt * kFiltersPerTile;
+        d.count = count;
+        d.orient = o;
+        d.zmask = s_dz[t];
+        a.dtiles[t] = d;
+      }
+      if (j >= count) {
+        ScanRec r = {};
+        r.gidx = -1;
+        a.drecs[t * kFiltersPerTile + j] = r;
+      }
+    }
+  }
+  // the packed patches' data events, 16 bytes per thread and step
+  constexpr int V = kKMax / 4;
+  for (int i = tid; i < a.nf * V; i += kThreads) {
+    const int slot = i / V, v = i - slot * V;
+    const int cs = s_map[slot];
+    if (cs >= 0)
+      ((int4*)(a.dmbuf + (long long)cs * kKMax))[v] = ((const int4*)(a.mbuf + (long long)(a.fbegin + slot) * kKMax))[v];
+  }
+}
+
+// The level-J grid narrowed for the proposal's LDS copy (every value fits).
+template <typename KT>
+__global__ void k_lp_narrow(const int32_t* __restrict__ Ki, long long n, long long npad, KT* __restrict__ out) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < npad) out[id] = id < n ? (KT)Ki[id] : (KT)0;
 }
 
 }  // namespace ccw

@@ -122,6 +122,7 @@ struct ScanArgs {
   int ksel;                    // keys the selection keeps per row (K, or the shortlist)
   int gbits;                   // value v of a lane joins group v & (2^gbits - 1) of its lane
   int n_bm;                    // band masks per orientation (energy rows per tile)
+  const int32_t* ntiles_dyn;   // fused, simulation: tiles of this launch counted on the device, or null
 };
 
 template <typename OT>
@@ -754,6 +755,8 @@ void k_scan_sel(ScanArgs a) {
   __shared__ unsigned long long s_rmin[kFiltersPerTile];
   __shared__ qt s_tau[kFiltersPerTile];
 
+  // tiles packed on the device: the grid covers the most there can be
+  if (a.ntiles_dyn && (int)blockIdx.y >= *a.ntiles_dyn) return;
   TileDev t;
   if (a.standalone) {
     t.first = blockIdx.y * kFiltersPerTile;

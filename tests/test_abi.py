@@ -79,6 +79,8 @@ def test_dwt_sizes_host_only(lib):
     dict(wavelet=2),
     dict(wavelet=1, shortlist=8),
     dict(wavelet=1, proposer_dim=16),
+    dict(proposer_dim=64, lp_probe=4),            # no proposer index
+    dict(proposer_dim=65),
 ])
 def test_simulate_validation_errors(lib, bad):
     from paper_2404_00441_amd import ccwsim
@@ -194,3 +196,21 @@ def test_selection_switch_validation(lib):
     assert lib.ccwsim_set_selection(4) == 1
     assert lib.ccwsim_set_selection(-1) == 1
     assert lib.ccwsim_set_selection(0) == 0
+
+
+def test_learned_plan_fits(lib):
+    # the learned proposer's plan (LDS of the proposal, packed scan tiles) is
+    # host work; a stand-in index address is never read when sizing
+    from paper_2404_00441_amd import ccwsim
+    from paper_2404_00441_amd import workloads as wl
+    p, _, _ = wl.make("c5_learned")
+    q = ccwsim.params_of(p)
+    q.proposer_dim, q.lp_probe, q.lp_gate, q.proposer = 64, 8, 0.5, 256
+    v = lib.ccwsim_simulate_workspace_size(ctypes.byref(q))
+    assert v > 0, lib.ccwsim_last_error().decode()
+    for bad in [dict(lp_probe=0), dict(lp_probe=65), dict(lp_gate=float("nan"))]:
+        q2 = ccwsim.params_of(p)
+        q2.proposer_dim, q2.lp_probe, q2.lp_gate, q2.proposer = 64, 8, 0.5, 256
+        for k, v2 in bad.items():
+            setattr(q2, k, v2)
+        assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q2)) == -1

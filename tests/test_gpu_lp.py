@@ -53,30 +53,33 @@ def _inputs(ti, level, tmpl, B, seed):
     G = (-(-ti[0] // b), -(-ti[1] // b))          # the level-J grid covers the TI
     K = rng.integers(0, 2 * b * b + 1, size=(G[1], G[0]))
     tc = ((tmpl[0] + b - 1) // b, (tmpl[1] + b - 1) // b)
-    ev = np.zeros((B, 2, tc[1], tc[0]))
-    # L-shaped overlaps of random width, zero elsewhere, like a data event
+    on = np.zeros((B, tc[1], tc[0]), np.int32)
+    om = np.zeros((B, tc[1], tc[0]), np.int32)
+    # L-shaped overlaps of random width (some blocks partly known), zero
+    # elsewhere, like a data event
     for i in range(B):
         wx, wy = rng.integers(1, tc[0] // 2 + 1), rng.integers(1, tc[1] // 2 + 1)
         mask = np.zeros((tc[1], tc[0]), bool)
         mask[:, :wx] = True
         mask[:wy, :] = True
-        ev[i, 0][mask] = rng.integers(0, 2 * b * b + 1, size=mask.sum()) / (b * b)
-        ev[i, 1][mask] = 1.0
+        on[i][mask] = rng.integers(1, b * b + 1, size=mask.sum())
+        om[i][mask] = rng.integers(0, 2 * on[i][mask] + 1)
+    ev = np.stack([om, on], axis=1) / float(b * b)   # the encoder's input channels
     cand = ((ti[0] - tmpl[0]) // b + 1, (ti[1] - tmpl[1]) // b + 1)
-    return K, ev, cand, tc
+    return K, (on.reshape(B, -1), om.reshape(B, -1)), ev, cand, tc
 
 
 @pytest.mark.parametrize("geom", GEOMS, ids=[f"{g[0][0]}x{g[0][1]}_J{g[1]}_T{g[2][0]}" for g in GEOMS])
 def test_encode_matches_reference(cc, geom):
     ti, level, tmpl, B = geom
     _say("lp encode", geom)
-    K, ev, cand, tc = _inputs(ti, level, tmpl, B, 3)
+    K, (on, om), ev, cand, tc = _inputs(ti, level, tmpl, B, 3)
     w = cc.lp_init(7)
     wn = w.cpu().numpy().astype(np.float64)
     ws = cc.LpWorkspace(ti, level, tmpl, B)
     assert ws.ncand == cand[0] * cand[1]
-    keys, q, S = cc.lp_encode(w, _t(K, np.int32), ws, _t(ev), want_keys=True, want_queries=True,
-                              want_scores=True)
+    keys, q, S = cc.lp_encode(w, _t(K, np.int32), ws, _t(on, np.int32), _t(om, np.int32), want_keys=True,
+                              want_queries=True, want_scores=True)
     k_ref, q_ref, S_ref, _ = lp_ref.forward(wn, K, (2 ** level) ** 2, ev, cand, tc)
     _close(keys.cpu().numpy(), k_ref, what="keys")
     _close(q.cpu().numpy(), q_ref, what="queries")
@@ -104,7 +107,7 @@ def test_train_step_matches_reference(cc, geom):
     import torch
     ti, level, tmpl, B = geom
     _say("lp train step", geom)
-    K, ev, cand, tc = _inputs(ti, level, tmpl, B, 5)
+    K, (on, om), ev, cand, tc = _inputs(ti, level, tmpl, B, 5)
     rng = np.random.default_rng(9)
     labels = rng.integers(0, cand[0] * cand[1], size=B)
     w = cc.lp_init(11)
@@ -112,8 +115,9 @@ def test_train_step_matches_reference(cc, geom):
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
     ws = cc.LpWorkspace(ti, level, tmpl, B)
-    Kt, evt, lt = _t(K, np.int32), _t(ev), _t(labels, np.int32)
-    loss, g = cc.lp_train_step(w, m, v, 1, 1e-3, Kt, ws, evt, lt, want_grad=True)
+    Kt, lt = _t(K, np.int32), _t(labels, np.int32)
+    ont, omt = _t(on, np.int32), _t(om, np.int32)
+    loss, g = cc.lp_train_step(w, m, v, 1, 1e-3, Kt, ws, ont, omt, lt, want_grad=True)
     loss_ref, g_ref = lp_ref.loss_and_grad(w0, K, (2 ** level) ** 2, ev, labels, cand, tc)
     _close(loss.cpu().numpy(), loss_ref, what="loss")
     gn = g.cpu().numpy()
@@ -131,7 +135,7 @@ def test_train_step_matches_reference(cc, geom):
     _close(v.cpu().numpy(), v_ref, rel=1e-4, what="adam v")
     _close(w.cpu().numpy() - w0, w_ref - w0, rel=1e-3, what="adam update")
     # a second step runs on the updated weights and moments
-    loss2, _ = cc.lp_train_step(w, m, v, 2, 1e-3, Kt, ws, evt, lt)
+    loss2, _ = cc.lp_train_step(w, m, v, 2, 1e-3, Kt, ws, ont, omt, lt)
     assert np.isfinite(loss2.cpu().numpy()).all()
 
 
