@@ -1275,15 +1275,17 @@ extern "C" int ccwsim_lp_propose(const void* index, const int32_t* approx, ccwsi
   const long long need = align256(lp_prop_grid_bytes(g, 2));
   if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
   if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-  const size_t lds = (size_t)lp_prop_lds(g, 2, kLpCandMax, (int)g.tcells);
+  const int kt = (long long)max_code * g.beta <= 127 ? 1 : 2;   // the grid's LDS copy as int8 or int16
+  const size_t lds = (size_t)lp_prop_lds(g, kt, kLpCandMax, (int)g.tcells);
   if (lds > 160 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "the proposal needs %zu B of LDS", lds);
   hipStream_t st = as_stream(stream);
   CCW_TRY(lp_index_check(index, g, st, nullptr));
-  CCW_TRY(lp_lds_allow(2, lds));
+  CCW_TRY(lp_lds_allow(kt, lds));
   if (n_filters == 0) return CCWSIM_OK;
   const long long gc = (long long)g.G[0] * g.G[1];
-  const long long npad = lp_prop_grid_bytes(g, 2) / 2;
-  k_lp_narrow<int16_t><<<nblocks(npad), kThreads, 0, st>>>(approx, gc, npad, (int16_t*)workspace);
+  const long long npad = lp_prop_grid_bytes(g, kt) / kt;
+  if (kt == 1) k_lp_narrow<int8_t><<<nblocks(npad), kThreads, 0, st>>>(approx, gc, npad, (int8_t*)workspace);
+  else k_lp_narrow<int16_t><<<nblocks(npad), kThreads, 0, st>>>(approx, gc, npad, (int16_t*)workspace);
   LpPropArgs la = {};
   la.g = g;
   la.index = (const unsigned char*)index;
@@ -1303,7 +1305,8 @@ extern "C" int ccwsim_lp_propose(const void* index, const int32_t* approx, ccwsi
   la.nlist_out = n_members;
   la.q_out = queries;
   la.err_out = best_error;
-  k_lp_propose<int16_t><<<(unsigned)n_filters, kThreads, lds, st>>>(la);
+  if (kt == 1) k_lp_propose<int8_t><<<(unsigned)n_filters, kThreads, lds, st>>>(la);
+  else k_lp_propose<int16_t><<<(unsigned)n_filters, kThreads, lds, st>>>(la);
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }
@@ -1479,7 +1482,7 @@ struct Plan {
   size_t lp_lds = 0, lp_cmp_lds = 0;
   const void* lp_checked = nullptr;   // the index whose header was last read back
   long long ws_lp_grid = 0, ws_lp_sel = 0, ws_lp_ok = 0, ws_lp_map = 0, ws_lp_dtiles = 0, ws_lp_drecs = 0,
-            ws_lp_dmbuf = 0, ws_lp_dcount = 0;
+            ws_lp_dcount = 0;
   long long ws_err = 0;               // match error of every patch's choice
   int scan_g = 1;                     // tiles per scan workgroup (tuned)
   bool rows_ok = false;               // the row-minima selection fits this plan
@@ -2064,8 +2067,10 @@ int build_plan(const ccwsim_params& p, Plan& P) {
       return fail(CCWSIM_ERR_UNSUPPORTED, "the proposal needs %zu B of LDS (level-J grid too large)", P.lp_lds);
     for (const StepRange& sr : P.steps) P.lp_tmax = std::max(P.lp_tmax, sr.tcount);
     if (P.lp_tmax > 256) return fail(CCWSIM_ERR_UNSUPPORTED, "more than 256 scan tiles in one step");
-    P.lp_cmp_lds = (size_t)P.max_slots * 16;
-    if (P.lp_cmp_lds > 60 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "more than 3840 patches in one step");
+    // the step's last proposal packs the gated patches in its LDS
+    P.lp_cmp_lds = (size_t)P.max_slots * 16 + 1024;
+    P.lp_lds = std::max(P.lp_lds, P.lp_cmp_lds);
+    if (P.lp_lds > 160 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "too many patches in one step");
   }
 
   // workspace
@@ -2103,7 +2108,6 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     P.ws_lp_map = o;    o += align256((long long)P.max_slots * 4);
     P.ws_lp_dtiles = o; o += align256((long long)std::max(1, P.lp_tmax) * sizeof(TileDev));
     P.ws_lp_drecs = o;  o += align256((long long)std::max(1, P.lp_tmax) * kFiltersPerTile * sizeof(ScanRec));
-    P.ws_lp_dmbuf = o;  o += align256((long long)P.max_slots * kKMax * 4);
     P.ws_lp_dcount = o; o += 256;
   }
   if (P.learn) {
@@ -3646,6 +3650,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   void* lp_grid = P->lp ? (void*)(ws + P->ws_lp_grid) : nullptr;
   if (P->lp) {
     ProfScope ps(CCWSIM_KIND_LEARN, st);
+    k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)(ws + P->ws_lp_dcount), 64, 0);   // count and ticket
     const long long gc = (long long)g.G[0] * g.G[1] * g.G[2];
     const long long npad = lp_prop_grid_bytes(g, P->lp_kt) / P->lp_kt;
     if (P->lp_kt == 1) k_lp_narrow<int8_t><<<nblocks(npad), kThreads, 0, st>>>(Ki, gc, npad, (int8_t*)lp_grid);
@@ -3809,6 +3814,19 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       la.sel = (uint64_t*)(ws + P->ws_lp_sel);
       la.ok = (int32_t*)(ws + P->ws_lp_ok);
       la.report = report;
+      la.ticket = (int32_t*)(ws + P->ws_lp_dcount) + 16;
+      LpCompactArgs& ca = la.cmp;
+      ca.tiles = tiles + s.tbegin;
+      ca.recs = recs + (long long)s.tbegin * kFiltersPerTile;
+      ca.ntiles = s.tcount;
+      ca.nf = s.fcount;
+      ca.n_orient = P->n_orient;
+      ca.fbegin = s.fbegin;
+      ca.ok = la.ok;
+      ca.dtiles = (TileDev*)(ws + P->ws_lp_dtiles);
+      ca.drecs = (ScanRec*)(ws + P->ws_lp_drecs);
+      ca.map = (int32_t*)(ws + P->ws_lp_map);
+      ca.dcount = (int32_t*)(ws + P->ws_lp_dcount);
       {
         ProfKernel pk(CCWSIM_KIND_LEARN);
         if (P->lp_kt == 1)
@@ -3818,21 +3836,6 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
           hipExtLaunchKernelGGL(k_lp_propose<int16_t>, dim3((unsigned)s.fcount), dim3(kThreads), P->lp_lds, st, pk.a,
                                 pk.b, 0, la);
       }
-      LpCompactArgs ca = {};
-      ca.tiles = tiles + s.tbegin;
-      ca.recs = recs + (long long)s.tbegin * kFiltersPerTile;
-      ca.ntiles = s.tcount;
-      ca.nf = s.fcount;
-      ca.n_orient = P->n_orient;
-      ca.fbegin = s.fbegin;
-      ca.ok = la.ok;
-      ca.mbuf = mbuf;
-      ca.dtiles = (TileDev*)(ws + P->ws_lp_dtiles);
-      ca.drecs = (ScanRec*)(ws + P->ws_lp_drecs);
-      ca.dmbuf = (int32_t*)(ws + P->ws_lp_dmbuf);
-      ca.map = (int32_t*)(ws + P->ws_lp_map);
-      ca.dcount = (int32_t*)(ws + P->ws_lp_dcount);
-      k_lp_compact<<<1, kThreads, P->lp_cmp_lds, st>>>(ca);
       ScanArgs sf = sa;
       sf.kpad = P->sel_kk;
       sf.klist = P->kpad;
@@ -3842,7 +3845,6 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       sf.n_tinline = 0;
       sf.tiles = ca.dtiles;
       sf.recs = ca.drecs;
-      sf.mbuf = ca.dmbuf;
       sf.fbegin = 0;
       sf.ntiles_dyn = ca.dcount;
       ProfKernel pk(CCWSIM_KIND_SCAN);

@@ -426,7 +426,7 @@ __global__ __launch_bounds__(kThreads) void k_lp_topk(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 constexpr int32_t kLpMagic = 0x4C504958;
 constexpr int kLpListsMax = 1024;   // lists of an index
-constexpr int kLpProbeMax = 64;     // lists probed per data event
+constexpr int kLpProbeMax = 16;     // lists probed per data event
 constexpr int kLpCandMax = 1024;    // candidates scored exactly per data event
 
 struct LpIndexHeader {
@@ -557,7 +557,8 @@ __global__ __launch_bounds__(kThreads) void k_km_update(const float* __restrict_
 // d, e in {-1, 0, 1}^2 (a 7 x 7 lattice of step 2), each position outside
 // the window being zero (the maps' zero padding).  Equal to the full
 // encoder's output at h.  All threads of the workgroup take part.
-//   ev: [2][tc1][tc0] input channels; a0: [49][32]; a1: [9][32]; a2: [32];
+//   ev: [2][tc1 + 2][tc0 + 2] input channels with a zero border; a0: [49][32];
+//   a1: [9][32]; a2: [32];
 //   q: [64] output.  W: the query encoder's weights.
 // ---------------------------------------------------------------------------
 __device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, int tc0, int tc1, float* a0, float* a1,
@@ -565,75 +566,105 @@ __device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, in
   const int tid = threadIdx.x;
   const int h0 = tc0 / 2, h1 = tc1 / 2;
   const long long o0 = 0, o1 = lp_layer_size(0, 2), o2 = o1 + lp_layer_size(1, 2), o3 = o2 + lp_layer_size(2, 2);
-  // layer 0: 2 -> 32 channels, dilation 1
-  for (int o = tid; o < 49 * kLpC; o += kThreads) {
-    const int pos = o / kLpC, co = o - pos * kLpC;
-    const int py = h1 + 2 * (pos / 7) - 6, px = h0 + 2 * (pos % 7) - 6;
-    float s = 0.f;
-    if (py >= 0 && py < tc1 && px >= 0 && px < tc0) {
-      s = W[o0 + kLpC * 2 * 9 + co];
-      for (int ci = 0; ci < 2; ++ci)
-        for (int t = 0; t < 9; ++t) {
-          const int yy = py + t / 3 - 1, xx = px + t % 3 - 1;
-          if (yy >= 0 && yy < tc1 && xx >= 0 && xx < tc0)
-            s += W[o0 + (co * 2 + ci) * 9 + t] * ev[(ci * tc1 + yy) * tc0 + xx];
-        }
-      s = fmaxf(s, 0.f);
+  // every weight this thread uses is loaded once, up front, in 16-byte
+  // words (W is 256-byte aligned and every block below starts on a 16-byte
+  // boundary): layer 0 by co = tid % 32 (8-byte words), layers 1 and 2 by
+  // (co = tid / 8, input channels 4 (tid % 8) .. + 3), whose 36 weights are
+  // consecutive, layer 3 by (d = tid / 4, input channels 8 (tid % 4) .. + 7)
+  const int c1 = tid >> 3, p1 = tid & 7;
+  float w1[36], w2[36], w3[8];
+  {
+    const float4* s1 = (const float4*)(W + o1 + (long long)(c1 * kLpC + p1 * 4) * 9);
+    const float4* s2 = (const float4*)(W + o2 + (long long)(c1 * kLpC + p1 * 4) * 9);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      const float4 x = s1[v], y = s2[v];
+      w1[4 * v] = x.x, w1[4 * v + 1] = x.y, w1[4 * v + 2] = x.z, w1[4 * v + 3] = x.w;
+      w2[4 * v] = y.x, w2[4 * v + 1] = y.y, w2[4 * v + 2] = y.z, w2[4 * v + 3] = y.w;
     }
-    a0[o] = s;
+  }
+  const float b1 = W[o1 + kLpC * kLpC * 9 + c1], b2 = W[o2 + kLpC * kLpC * 9 + c1];
+  const int d3 = tid >> 2, p3 = tid & 3;
+  {
+    const float4* s3 = (const float4*)(W + o3 + (long long)d3 * kLpC + p3 * 8);
+    const float4 x = s3[0], y = s3[1];
+    w3[0] = x.x, w3[1] = x.y, w3[2] = x.z, w3[3] = x.w, w3[4] = y.x, w3[5] = y.y, w3[6] = y.z, w3[7] = y.w;
+  }
+  const float b3 = W[o3 + kLpD * kLpC + d3];
+  // layer 0: 2 -> 32 channels, dilation 1.  Thread (co, group) takes every
+  // eighth lattice position.
+  {
+    const int co = tid & (kLpC - 1), grp = tid >> 5;
+    float w0[18];
+    const float2* s0 = (const float2*)(W + o0 + co * 18);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      const float2 x = s0[v];
+      w0[2 * v] = x.x, w0[2 * v + 1] = x.y;
+    }
+    const float b0 = W[o0 + kLpC * 2 * 9 + co];
+    const int ew = tc0 + 2, eh = tc1 + 2;
+    for (int pos = grp; pos < 49; pos += kThreads / kLpC) {
+      const int py = h1 + 2 * (pos / 7) - 6, px = h0 + 2 * (pos % 7) - 6;
+      float s = 0.f;
+      if (py >= 0 && py < tc1 && px >= 0 && px < tc0) {
+        // the 3 x 3 neighbourhood lies in the bordered canvas
+        const float* e0 = ev + py * ew + px;
+        s = b0;
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+          for (int t = 0; t < 9; ++t) s += w0[ci * 9 + t] * e0[ci * eh * ew + (t / 3) * ew + (t % 3)];
+        s = fmaxf(s, 0.f);
+      }
+      a0[pos * kLpC + co] = s;
+    }
   }
   __syncthreads();
-  // layer 1: 32 -> 32, dilation 2; 8 lanes per output, 4 input channels each
-  for (int it = tid; it < 9 * kLpC * 8; it += kThreads) {
-    const int o = it >> 3, part = it & 7;
-    const int pos = o / kLpC, co = o - pos * kLpC;
+  // layer 1: 32 -> 32, dilation 2, at the 9 points h + 4 d.  Thread
+  // (co, part) sums its 4 input channels (one 16-byte LDS read per tap) for
+  // all 9 points; the 8 parts of an output are added with lane shuffles.
+#pragma unroll 1
+  for (int pos = 0; pos < 9; ++pos) {
     const int dy = pos / 3 - 1, dx = pos % 3 - 1;
     const int py = h1 + 4 * dy, px = h0 + 4 * dx;
-    const bool in = py >= 0 && py < tc1 && px >= 0 && px < tc0;
+    const bool in = py >= 0 && py < tc1 && px >= 0 && px < tc0;   // uniform
     float s = 0.f;
-    if (in) {
-      for (int c4 = 0; c4 < 4; ++c4) {
-        const int ci = part * 4 + c4;
-        const float* w = W + o1 + ((long long)co * kLpC + ci) * 9;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          // layer-0 lattice point h + 4 d + 2 e with e = tap offset
-          const int ly = 2 * (dy + 1) + (t / 3), lx = 2 * (dx + 1) + (t % 3);
-          s += w[t] * a0[(ly * 7 + lx) * kLpC + ci];
-        }
-      }
+    for (int t = 0; t < 9; ++t) {
+      // layer-0 lattice point h + 4 d + 2 e with e = tap offset
+      const int ly = 2 * (dy + 1) + (t / 3), lx = 2 * (dx + 1) + (t % 3);
+      const float4 x = *(const float4*)(a0 + (ly * 7 + lx) * kLpC + p1 * 4);
+      s += w1[t] * x.x + w1[9 + t] * x.y + w1[18 + t] * x.z + w1[27 + t] * x.w;
     }
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
-    if (part == 0) a1[o] = in ? fmaxf(s + W[o1 + kLpC * kLpC * 9 + co], 0.f) : 0.f;
+    if (p1 == 0) a1[pos * kLpC + c1] = in ? fmaxf(s + b1, 0.f) : 0.f;
   }
   __syncthreads();
   // layer 2: 32 -> 32, dilation 4, at h only; 8 lanes per output
   {
-    const int co = tid >> 3, part = tid & 7;
     float s = 0.f;
-    for (int c4 = 0; c4 < 4; ++c4) {
-      const int ci = part * 4 + c4;
-      const float* w = W + o2 + ((long long)co * kLpC + ci) * 9;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) s += w[t] * a1[t * kLpC + ci];
+    for (int t = 0; t < 9; ++t) {
+      const float4 x = *(const float4*)(a1 + t * kLpC + p1 * 4);
+      s += w2[t] * x.x + w2[9 + t] * x.y + w2[18 + t] * x.z + w2[27 + t] * x.w;
     }
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
-    if (part == 0) a2[co] = fmaxf(s + W[o2 + kLpC * kLpC * 9 + co], 0.f);
+    if (p1 == 0) a2[c1] = fmaxf(s + b2, 0.f);
   }
   __syncthreads();
   // layer 3: 1x1, 32 -> 64; 4 lanes per output
   {
-    const int d = tid >> 2, part = tid & 3;
-    float s = 0.f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) s += W[o3 + (long long)d * kLpC + part * 8 + c] * a2[part * 8 + c];
+    const float4 x = *(const float4*)(a2 + p3 * 8), y = *(const float4*)(a2 + p3 * 8 + 4);
+    float s = w3[0] * x.x + w3[1] * x.y + w3[2] * x.z + w3[3] * x.w + w3[4] * y.x + w3[5] * y.y + w3[6] * y.z +
+              w3[7] * y.w;
     s += __shfl_xor(s, 1, 4);
     s += __shfl_xor(s, 2, 4);
-    if (part == 0) q[d] = s + W[o3 + kLpD * kLpC + d];
+    if (p3 == 0) q[d3] = s + b3;
   }
   __syncthreads();
 }
@@ -646,314 +677,33 @@ __device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, in
 // data lie in its virtual template, when fewer than K candidates were
 // scored, or when the best match error exceeds the gate.
 // ---------------------------------------------------------------------------
-struct LpPropArgs {
-  Geom g;
-  const unsigned char* index;   // LpIndexHeader and its arrays
-  const void* grid;             // level-J grid, KT [G1][G0], 16-byte padded
-  int probe, cap, top_k, kpad;
-  float gate;                   // largest accepted match error (< 0: always fall back)
-  uint64_t seed;
-  int standalone;
-  // simulation: the step's patches
-  const FilterDev* filters;
-  int fbegin;
-  const int32_t* kbeta;         // [orient][kKMax] block lists
-  const int32_t* nbt;           // [shape][tcells] known cells per block
-  const int32_t* mbuf;          // [patch][kKMax] data events
-  const int32_t* hd_off;        // [patch + 1] hard data per virtual template, or null
-  uint64_t* sel;                // [slot][top_k] the K best keys
-  int32_t* ok;                  // [slot] 1: the proposal stands, 0: the full scan decides
-  unsigned long long* report;
-  // standalone: events as for the scan
-  const int32_t* or_n;
-  const int32_t* or_m;
-  const int32_t* fil_real;
-  const int64_t* fil_step;
-  uint64_t* keys_out;           // [f][top_k]
-  int32_t* list_out;            // [f][cap] candidates scored, or null
-  int32_t* nlist_out;           // [f], or null
-  float* q_out;                 // [f][64], or null
-  float* err_out;               // [f] best match error, or null
-};
-
-// LDS of k_lp_propose: the grid, the candidate list, then one area shared
-// by the encoder's scratch and the keys; the event's block list after it.
-__host__ __device__ inline long long lp_prop_grid_bytes(const Geom& g, int kt_bytes) {
-  return ((long long)g.G[0] * g.G[1] * kt_bytes + 15) & ~15ll;
-}
-__host__ __device__ inline long long lp_prop_alias_bytes(const Geom& g, int cap) {
-  long long v = (2 * g.tcells + 49 * kLpC + 9 * kLpC + kLpC) * 4;   // encoder scratch
-  if ((long long)cap * 8 > v) v = (long long)cap * 8;                 // keys
-  if (4ll * kLpListsMax > v) v = 4ll * kLpListsMax;                   // list scores
-  return (v + 15) & ~15ll;
-}
-__host__ __device__ inline long long lp_prop_lds(const Geom& g, int kt_bytes, int cap, int list_len) {
-  return lp_prop_grid_bytes(g, kt_bytes) + (((long long)cap * 4 + 15) & ~15ll) + lp_prop_alias_bytes(g, cap) +
-         4ll * 4 * list_len;
-}
-
-template <typename KT>
-__global__ __launch_bounds__(kThreads) void k_lp_propose(LpPropArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ TopkShared sh;
-  __shared__ int s_probe[kLpProbeMax], s_lo[kLpProbeMax], s_len[kLpProbeMax], s_pos[kLpProbeMax];
-  __shared__ int s_nk, s_M, s_np, s_force;
-  __shared__ float s_q[kLpD];
-  __shared__ double s_rt[kThreads / 64], s_rn[kThreads / 64];
-  const Geom& g = a.g;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int slot = blockIdx.x;
-  const LpIndexHeader* H = (const LpIndexHeader*)a.index;
-  const int G0 = g.G[0];
-  const int tcells = (int)g.tcells;
-  KT* s_K = (KT*)smem;
-  int* s_cand = (int*)(smem + lp_prop_grid_bytes(g, (int)sizeof(KT)));
-  unsigned char* alias = (unsigned char*)s_cand + (((long long)a.cap * 4 + 15) & ~15ll);
-  uint64_t* s_keys = (uint64_t*)alias;
-  float* s_ev = (float*)alias;
-  float* s_a0 = s_ev + 2 * tcells;
-  float* s_a1 = s_a0 + 49 * kLpC;
-  float* s_a2 = s_a1 + 9 * kLpC;
-  float* s_cs = (float*)alias;   // list scores, after the encoder
-  int* s_beta = (int*)(alias + lp_prop_alias_bytes(g, a.cap));
-  const int L = a.standalone ? tcells : a.kpad;   // block list capacity
-  int* s_koff = s_beta + L;
-  int* s_m = s_koff + L;
-  int* s_n = s_m + L;
-
-  // the grid: every 16-byte word of it, loads issued before the stores
-  {
-    const int nv = (int)(lp_prop_grid_bytes(g, (int)sizeof(KT)) / 16);
-    const uint4* src = (const uint4*)a.grid;
-    uint4* dst = (uint4*)s_K;
-    for (int v0 = tid; v0 < nv; v0 += kThreads * 8) {
-      uint4 r[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int v = v0 + u * kThreads;
-        if (v < nv) r[u] = src[v];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int v = v0 + u * kThreads;
-        if (v < nv) dst[v] = r[u];
-      }
-    }
-  }
-  // an index built for another geometry sends every patch to the scan
-  const bool hdr_ok = H->magic == kLpMagic && H->n_lists >= 1 && H->n_lists <= kLpListsMax && H->ncand == g.ncand &&
-                      H->G[0] == g.G[0] && H->G[1] == g.G[1] && H->cand[0] == g.cand[0] &&
-                      H->cand[1] == g.cand[1] && H->tc[0] == g.tc[0] && H->tc[1] == g.tc[1];
-  for (int i = tid; i < 2 * tcells; i += kThreads) s_ev[i] = 0.f;
-  uint64_t tkey = 0;
-  if (tid == 0) {
-    s_nk = 0;
-    s_force = hdr_ok ? 0 : 1;
-  }
-  __syncthreads();
-  // the event's block list: (block, offset in the grid, m, n)
-  if (!a.standalone) {
-    const FilterDev f = a.filters[slot];
-    tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
-    if (tid < a.kpad) {
-      const int beta = a.kbeta[f.orient * kKMax + tid];
-      int m = 0, n = 0, off = 0;
-      if (beta >= 0 && f.bandmask) {
-        m = a.mbuf[(long long)(a.fbegin + slot) * kKMax + tid];
-        n = a.nbt[(long long)f.shape * tcells + beta];
-        int bx, by, bz;
-        split3(beta, g.tc[0], g.tc[1], bx, by, bz);
-        off = by * G0 + bx;
-      }
-      s_beta[tid] = n > 0 ? beta : -1;
-      s_koff[tid] = off;
-      s_m[tid] = m;
-      s_n[tid] = n;
-    }
-    if (tid == 0) {
-      s_nk = a.kpad;
-      const bool hd = a.hd_off && a.hd_off[a.fbegin + slot + 1] > a.hd_off[a.fbegin + slot];
-      if (f.bandmask == 0 || hd) s_force = 1;
-    }
-  } else {
-    if (a.fil_real) tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)a.fil_real[slot], (uint64_t)a.fil_step[slot]);
-    for (int b = tid; b < tcells; b += kThreads) {
-      const int n = a.or_n[(long long)slot * tcells + b];
-      if (n > 0) {
-        const int i = atomicAdd(&s_nk, 1);   // list order does not change integer sums
-        int bx, by, bz;
-        split3(b, g.tc[0], g.tc[1], bx, by, bz);
-        s_beta[i] = b;
-        s_koff[i] = by * G0 + bx;
-        s_m[i] = a.or_m[(long long)slot * tcells + b];
-        s_n[i] = n;
-      }
-    }
-  }
-  __syncthreads();
-  const int nk = s_nk;
-  // the encoder's input, and the match error's constant term
-  // sum |beta|^2 m^2 / n and the known cells sum n
-  const double B = (double)(1 << (g.shift - 1));
-  double ct = 0.0, cn = 0.0;
-  for (int i = tid; i < nk; i += kThreads) {
-    const int n = s_n[i];
-    if (n > 0) {
-      const float inv = 1.f / (float)g.beta;
-      s_ev[s_beta[i]] = (float)s_m[i] * inv;
-      s_ev[tcells + s_beta[i]] = (float)n * inv;
-      ct += B * B * (double)s_m[i] * (double)s_m[i] / (double)n;
-      cn += (double)n;
-    }
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    ct += __shfl_xor(ct, m, 64);
-    cn += __shfl_xor(cn, m, 64);
-  }
-  if (lane == 0) {
-    s_rt[wave] = ct;
-    s_rn[wave] = cn;
-  }
-  __syncthreads();
-  if (!hdr_ok) {   // nothing of the index is read
-    if (tid == 0) {
-      s_M = 0;
-      s_np = 0;
-    }
-    for (int i = tid; i < kLpD; i += kThreads) s_q[i] = 0.f;
-    __syncthreads();
-  } else {
-  lp_query_sparse((const float*)(a.index + H->off_w), s_ev, g.tc[0], g.tc[1], s_a0, s_a1, s_a2, s_q);
-  if (a.q_out && tid < kLpD) a.q_out[(long long)slot * kLpD + tid] = s_q[tid];
-  // the lists by the inner product of the query with their centroid
-  const float* cent = (const float*)(a.index + H->off_cent);
-  const int nl = hdr_ok ? H->n_lists : 1;
-  for (int j = tid; j < nl; j += kThreads) {
-    const float4* c4 = (const float4*)(cent + (long long)j * kLpD);
-    float s = 0.f;
-#pragma unroll
-    for (int d = 0; d < kLpD / 4; ++d) {
-      const float4 c = c4[d];
-      s += s_q[4 * d] * c.x + s_q[4 * d + 1] * c.y + s_q[4 * d + 2] * c.z + s_q[4 * d + 3] * c.w;
-    }
-    s_cs[j] = s == s ? s : -INFINITY;   // a total order for the ranks below
-  }
-  __syncthreads();
-  const int P = min(a.probe, nl);
-  for (int j = tid; j < nl; j += kThreads) {
-    const float x = s_cs[j];
-    int r = 0;
-    for (int i = 0; i < nl; ++i) {
-      const float y = s_cs[i];
-      r += (y > x || (y == x && i < j)) ? 1 : 0;
-    }
-    if (r < P) s_probe[r] = j;
-  }
-  __syncthreads();
-  const int32_t* loff = (const int32_t*)(a.index + H->off_list);
-  const int32_t* mem = (const int32_t*)(a.index + H->off_mem);
-  if (tid == 0) {
-    int M = 0, np = 0;
-    for (int r = 0; r < P; ++r) {
-      const int j = s_probe[r];
-      const int lo = loff[j];
-      int len = loff[j + 1] - lo;
-      if (M + len > a.cap) {
-        if (r > 0) break;
-        len = a.cap;
-      }
-      s_lo[np] = lo;
-      s_len[np] = len;
-      s_pos[np] = M;
-      M += len;
-      ++np;
-    }
-    s_M = M;
-    s_np = np;
-    if (M < min(a.top_k, (int)g.ncand)) s_force = 1;
-  }
-  __syncthreads();
-  for (int r = 0; r < s_np; ++r)
-    for (int i = tid; i < s_len[r]; i += kThreads) s_cand[s_pos[r] + i] = mem[s_lo[r] + i];
-  __syncthreads();
-  }
-  const int M = s_M;
-  const int k = min(a.top_k, (int)g.ncand);
-  const bool force = s_force != 0;
-  if (!force || a.standalone) {
-    // exact keys of the members (mismatch 0: patches with hard data fall back)
-    const int C0 = g.cand[0];
-    const int shift = g.shift;
-    for (int i = tid; i < M; i += kThreads) {
-      const int c = min(max(s_cand[i], 0), (int)g.ncand - 1);
-      const int cy = c / C0, cx = c - cy * C0;
-      const KT* kb = s_K + cy * G0 + cx;
-      int E = 0, C = 0;
-      for (int q = 0; q < nk; ++q) {
-        const int kv = (int)kb[s_koff[q]];
-        E += s_n[q] * kv * kv;
-        C += s_m[q] * kv;
-      }
-      s_keys[i] = make_key(0u, E - (C << shift), tie_perm((uint32_t)c, tkey));
-    }
-    __syncthreads();
-    if (M >= k) block_topk(M, k, [&](long long i) { return s_keys[i]; }, sh);
-  }
-  if (tid == 0) {
-    double err = -1.0;
-    const double tsum = s_rt[0] + s_rt[1] + s_rt[2] + s_rt[3], nsum = s_rn[0] + s_rn[1] + s_rn[2] + s_rn[3];
-    if (M >= k && nsum > 0.0 && (!force || a.standalone)) {
-      const int32_t S = (int32_t)((uint32_t)((sh.top[0] >> 20) & 0xFFFFFFFFull) ^ 0x80000000u);
-      err = ((double)S + tsum) / (B * B * nsum);
-    }
-    const bool fb = force || a.gate < 0.f || err > (double)a.gate;
-    if (!a.standalone) {
-      a.ok[slot] = fb ? 0 : 1;
-      atomicAdd(&a.report[fb ? 6 : 4], 1ull);
-      if (!force) atomicAdd(&a.report[5], (unsigned long long)M);
-    } else {
-      if (a.nlist_out) a.nlist_out[slot] = M;
-      if (a.err_out) a.err_out[slot] = (float)err;
-    }
-  }
-  if (!a.standalone) {
-    if (tid < k && !force) a.sel[(long long)slot * a.top_k + tid] = sh.top[tid];
-  } else {
-    if (tid < k) a.keys_out[(long long)slot * a.top_k + tid] = M >= k ? sh.top[tid] : ~0ull;
-    if (a.list_out)
-      for (int i = tid; i < M; i += kThreads) a.list_out[(long long)slot * a.cap + i] = s_cand[i];
-  }
-}
-
 // ---------------------------------------------------------------------------
 // The step's patches that fall back, packed into scan tiles of one
 // orientation each (in slot order), with their records and data events;
-// map[slot] = the packed slot, or -1 where the proposal stands.  One
-// workgroup; the packed tiles never outnumber the step's tiles.
+// map[slot] = the packed slot, or -1 where the proposal stands.  Run by one
+// workgroup (the step's last proposal); the packed tiles never outnumber
+// the step's tiles.  A packed tile's records name their patches, whose
+// data events the scan reads in place.
 // ---------------------------------------------------------------------------
 struct LpCompactArgs {
   const TileDev* tiles;   // the step's tiles
   const ScanRec* recs;    // [tile][kFiltersPerTile]
   int ntiles, nf, n_orient, fbegin;
-  const int32_t* ok;      // [slot]
-  const int32_t* mbuf;    // [patch][kKMax]
+  const int32_t* ok;      // [slot], written by the step's other workgroups
   TileDev* dtiles;
   ScanRec* drecs;
-  int32_t* dmbuf;         // [packed slot][kKMax]
   int32_t* map;           // [slot]
   int32_t* dcount;        // packed tiles
 };
 
-__global__ __launch_bounds__(kThreads) void k_lp_compact(LpCompactArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ void lp_compact(const LpCompactArgs& a, unsigned char* smem) {
   int* s_or = (int*)smem;          // [nf] orientation, -1: proposal stands
   int* s_ri = s_or + a.nf;         // [nf] record index
   int* s_zm = s_ri + a.nf;         // [nf] zmask bit
   int* s_map = s_zm + a.nf;        // [nf]
+  uint32_t* s_dz = (uint32_t*)(s_map + a.nf);   // [256] zmask of each packed tile
   __shared__ int s_w[kThreads / 64];
   __shared__ int s_cnt[8], s_bslot[8], s_btile[8];
-  __shared__ uint32_t s_dz[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < a.nf; i += kThreads) s_or[i] = -1;
   for (int i = tid; i < 256; i += kThreads) s_dz[i] = 0u;
@@ -963,7 +713,8 @@ __global__ __launch_bounds__(kThreads) void k_lp_compact(LpCompactArgs a) {
     const TileDev td = a.tiles[t];
     if (j < td.count) {
       const int slot = td.first + j;
-      const bool fb = a.recs[i].gidx >= 0 && a.ok[slot] == 0;
+      const int okv = __hip_atomic_load(&a.ok[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool fb = a.recs[i].gidx >= 0 && okv == 0;
       s_or[slot] = fb ? td.orient : -1;
       s_ri[slot] = i;
       s_zm[slot] = (int)((td.zmask >> j) & 1u);
@@ -1035,13 +786,321 @@ __global__ __launch_bounds__(kThreads) void k_lp_compact(LpCompactArgs a) {
       }
     }
   }
-  // the packed patches' data events, 16 bytes per thread and step
-  constexpr int V = kKMax / 4;
-  for (int i = tid; i < a.nf * V; i += kThreads) {
-    const int slot = i / V, v = i - slot * V;
-    const int cs = s_map[slot];
-    if (cs >= 0)
-      ((int4*)(a.dmbuf + (long long)cs * kKMax))[v] = ((const int4*)(a.mbuf + (long long)(a.fbegin + slot) * kKMax))[v];
+}
+
+struct LpPropArgs {
+  Geom g;
+  const unsigned char* index;   // LpIndexHeader and its arrays
+  const void* grid;             // level-J grid, KT [G1][G0], 16-byte padded
+  int probe, cap, top_k, kpad;
+  float gate;                   // largest accepted match error (< 0: always fall back)
+  uint64_t seed;
+  int standalone;
+  // simulation: the step's patches
+  const FilterDev* filters;
+  int fbegin;
+  const int32_t* kbeta;         // [orient][kKMax] block lists
+  const int32_t* nbt;           // [shape][tcells] known cells per block
+  const int32_t* mbuf;          // [patch][kKMax] data events
+  const int32_t* hd_off;        // [patch + 1] hard data per virtual template, or null
+  uint64_t* sel;                // [slot][top_k] the K best keys
+  int32_t* ok;                  // [slot] 1: the proposal stands, 0: the full scan decides
+  unsigned long long* report;
+  int32_t* ticket;              // proposals of the step done (the last packs; reset to 0 after)
+  LpCompactArgs cmp;
+  // standalone: events as for the scan
+  const int32_t* or_n;
+  const int32_t* or_m;
+  const int32_t* fil_real;
+  const int64_t* fil_step;
+  uint64_t* keys_out;           // [f][top_k]
+  int32_t* list_out;            // [f][cap] candidates scored, or null
+  int32_t* nlist_out;           // [f], or null
+  float* q_out;                 // [f][64], or null
+  float* err_out;               // [f] best match error, or null
+};
+
+// LDS of k_lp_propose: the grid, then one area used in turn by the
+// encoder's scratch, the list scores, and the members with their keys; the
+// event's block list after it.
+__host__ __device__ inline long long lp_prop_grid_bytes(const Geom& g, int kt_bytes) {
+  return ((long long)g.G[0] * g.G[1] * kt_bytes + 15) & ~15ll;
+}
+__host__ __device__ inline long long lp_prop_alias_bytes(const Geom& g, int cap) {
+  long long v = (2ll * (g.tc[0] + 2) * (g.tc[1] + 2) + 49 * kLpC + 9 * kLpC + kLpC) * 4;   // encoder scratch
+  const long long ck = (((long long)cap * 4 + 15) & ~15ll) + (long long)cap * 8;         // members, keys
+  if (ck > v) v = ck;
+  if (4ll * kLpListsMax > v) v = 4ll * kLpListsMax;                                       // list scores
+  return (v + 15) & ~15ll;
+}
+__host__ __device__ inline long long lp_prop_lds(const Geom& g, int kt_bytes, int cap, int list_len) {
+  return lp_prop_grid_bytes(g, kt_bytes) + lp_prop_alias_bytes(g, cap) + 20ll * list_len;
+}
+
+// Two workgroups per CU (LDS for two grid copies; at most 256 registers).
+template <typename KT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_lp_propose(LpPropArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ TopkShared sh;
+  __shared__ int s_probe[kLpProbeMax], s_lo[kLpProbeMax], s_len[kLpProbeMax], s_pos[kLpProbeMax];
+  __shared__ int s_nk, s_M, s_np, s_force;
+  __shared__ float s_q[kLpD];
+  __shared__ double s_rt[kThreads / 64], s_rn[kThreads / 64];
+  const Geom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int slot = blockIdx.x;
+  const LpIndexHeader* H = (const LpIndexHeader*)a.index;
+  const int G0 = g.G[0];
+  const int tcells = (int)g.tcells;
+  KT* s_K = (KT*)smem;
+  unsigned char* alias = smem + lp_prop_grid_bytes(g, (int)sizeof(KT));
+  int* s_cand = (int*)alias;   // members, after the list scores
+  uint64_t* s_keys = (uint64_t*)(alias + (((long long)a.cap * 4 + 15) & ~15ll));
+  float* s_a0 = (float*)alias;
+  float* s_a1 = s_a0 + 49 * kLpC;
+  float* s_a2 = s_a1 + 9 * kLpC;
+  float* s_ev = s_a2 + kLpC;
+  float* s_cs = (float*)alias;   // list scores, after the encoder
+  const int L = a.standalone ? tcells : a.kpad;   // block list capacity
+  int4* s_ent = (int4*)(alias + lp_prop_alias_bytes(g, a.cap));   // (grid offset, m, n, 0) per listed block
+  int* s_beta = (int*)(s_ent + L);
+
+  // the grid goes to LDS by direct loads (global to LDS, no registers),
+  // issued first and waited for only before the exact scores: wavefront w
+  // moves 1 KiB chunks w, w + 4, ..., lane l the chunk's 16 bytes at 16 l
+  {
+    const int nv = (int)(lp_prop_grid_bytes(g, (int)sizeof(KT)) / 16);
+    const unsigned char* src = (const unsigned char*)a.grid;
+    for (int c = wave; c * 64 < nv; c += kThreads / 64) {
+      if (c * 64 + lane < nv)
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1)))*)(src + (long long)(c * 64 + lane) * 16),
+            (void __attribute__((address_space(3)))*)((unsigned char*)s_K + c * 1024), 16, 0, 0);
+    }
+  }
+  // an index built for another geometry sends every patch to the scan
+  const bool hdr_ok = H->magic == kLpMagic && H->n_lists >= 1 && H->n_lists <= kLpListsMax && H->ncand == g.ncand &&
+                      H->G[0] == g.G[0] && H->G[1] == g.G[1] && H->cand[0] == g.cand[0] &&
+                      H->cand[1] == g.cand[1] && H->tc[0] == g.tc[0] && H->tc[1] == g.tc[1];
+  const int ew = g.tc[0] + 2, eh = g.tc[1] + 2;   // the encoder's input with a zero border
+  for (int i = tid; i < 2 * ew * eh; i += kThreads) s_ev[i] = 0.f;
+  uint64_t tkey = 0;
+  if (tid == 0) {
+    s_nk = 0;
+    s_force = hdr_ok ? 0 : 1;
+  }
+  __syncthreads();
+  // the event's block list: (block, offset in the grid, m, n)
+  if (!a.standalone) {
+    const FilterDev f = a.filters[slot];
+    tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)f.r, (uint64_t)f.step);
+    if (tid < a.kpad) {
+      const int beta = a.kbeta[f.orient * kKMax + tid];
+      int m = 0, n = 0, off = 0;
+      if (beta >= 0 && f.bandmask) {
+        m = a.mbuf[(long long)(a.fbegin + slot) * kKMax + tid];
+        n = a.nbt[(long long)f.shape * tcells + beta];
+        int bx, by, bz;
+        split3(beta, g.tc[0], g.tc[1], bx, by, bz);
+        off = by * G0 + bx;
+      }
+      s_beta[tid] = n > 0 ? beta : -1;
+      s_ent[tid] = make_int4(off, m, n, 0);
+    }
+    if (tid == 0) {
+      s_nk = a.kpad;
+      const bool hd = a.hd_off && a.hd_off[a.fbegin + slot + 1] > a.hd_off[a.fbegin + slot];
+      if (f.bandmask == 0 || hd) s_force = 1;
+    }
+  } else {
+    if (a.fil_real) tkey = draw64(a.seed, kStreamTiebreak, (uint64_t)a.fil_real[slot], (uint64_t)a.fil_step[slot]);
+    for (int b = tid; b < tcells; b += kThreads) {
+      const int n = a.or_n[(long long)slot * tcells + b];
+      if (n > 0) {
+        const int i = atomicAdd(&s_nk, 1);   // list order does not change integer sums
+        int bx, by, bz;
+        split3(b, g.tc[0], g.tc[1], bx, by, bz);
+        s_beta[i] = b;
+        s_ent[i] = make_int4(by * G0 + bx, a.or_m[(long long)slot * tcells + b], n, 0);
+      }
+    }
+  }
+  __syncthreads();
+  const int nk = s_nk;
+  // the encoder's input, and the match error's constant term
+  // sum |beta|^2 m^2 / n and the known cells sum n
+  const double B = (double)(1 << (g.shift - 1));
+  double ct = 0.0, cn = 0.0;
+  for (int i = tid; i < nk; i += kThreads) {
+    const int4 e = s_ent[i];
+    if (e.z > 0) {
+      const float inv = 1.f / (float)g.beta;
+      const int by = s_beta[i] / g.tc[0], bx = s_beta[i] - by * g.tc[0];
+      s_ev[(by + 1) * ew + bx + 1] = (float)e.y * inv;
+      s_ev[eh * ew + (by + 1) * ew + bx + 1] = (float)e.z * inv;
+      ct += B * B * (double)e.y * (double)e.y / (double)e.z;
+      cn += (double)e.z;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    ct += __shfl_xor(ct, m, 64);
+    cn += __shfl_xor(cn, m, 64);
+  }
+  if (lane == 0) {
+    s_rt[wave] = ct;
+    s_rn[wave] = cn;
+  }
+  __syncthreads();
+  if (!hdr_ok) {   // nothing of the index is read
+    if (tid == 0) {
+      s_M = 0;
+      s_np = 0;
+    }
+    for (int i = tid; i < kLpD; i += kThreads) s_q[i] = 0.f;
+    __syncthreads();
+  } else {
+  lp_query_sparse((const float*)(a.index + H->off_w), s_ev, g.tc[0], g.tc[1], s_a0, s_a1, s_a2, s_q);
+  if (a.q_out && tid < kLpD) a.q_out[(long long)slot * kLpD + tid] = s_q[tid];
+  // the lists by the inner product of the query with their centroid
+  const float* cent = (const float*)(a.index + H->off_cent);
+  const int nl = hdr_ok ? H->n_lists : 1;
+  for (int j = tid; j < nl; j += kThreads) {
+    const float4* c4 = (const float4*)(cent + (long long)j * kLpD);
+    float s = 0.f;
+#pragma unroll
+    for (int d = 0; d < kLpD / 4; ++d) {
+      const float4 c = c4[d];
+      s += s_q[4 * d] * c.x + s_q[4 * d + 1] * c.y + s_q[4 * d + 2] * c.z + s_q[4 * d + 3] * c.w;
+    }
+    s_cs[j] = s == s ? s : -INFINITY;   // a total order for the ranks below
+  }
+  __syncthreads();
+  // the P best lists: the P smallest keys (descending score, then index)
+  const int P = min(a.probe, nl);
+  block_topk(nl, P, [&](long long j) {
+    const uint32_t u = __float_as_uint(s_cs[j]);
+    const uint32_t up = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending with the score
+    return ((uint64_t)(~up) << 32) | (uint64_t)j;
+  }, sh);
+  if (tid < P) s_probe[tid] = (int)(sh.top[tid] & 0xFFFFFFFFull);
+  __syncthreads();
+  const int32_t* loff = (const int32_t*)(a.index + H->off_list);
+  const int32_t* mem = (const int32_t*)(a.index + H->off_mem);
+  if (tid < P) {   // the probed lists' extents, loaded together
+    const int j = s_probe[tid];
+    const int lo = loff[j];
+    s_lo[tid] = lo;
+    s_len[tid] = loff[j + 1] - lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int M = 0, np = 0;
+    for (int r = 0; r < P; ++r) {
+      int len = s_len[r];
+      if (M + len > a.cap) {
+        if (r > 0) break;
+        len = a.cap;
+        s_len[r] = len;
+      }
+      s_pos[np] = M;
+      M += len;
+      ++np;
+    }
+    s_M = M;
+    s_np = np;
+    if (M < min(a.top_k, (int)g.ncand)) s_force = 1;
+  }
+  __syncthreads();
+  {
+    // every member load of a thread issued at once: list r of entry i by
+    // a search of the (few) list starts
+    const int np = s_np, Mt = s_M;
+    for (int i = tid; i < Mt; i += kThreads) {
+      int r = 0;
+      while (r + 1 < np && s_pos[r + 1] <= i) ++r;
+      s_cand[i] = mem[s_lo[r] + (i - s_pos[r])];
+    }
+  }
+  __syncthreads();
+  }
+  const int M = s_M;
+  const int k = min(a.top_k, (int)g.ncand);
+  const bool force = s_force != 0;
+  // the grid's direct loads of this wavefront, then everyone's
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (!force || a.standalone) {
+    // exact keys of the members (mismatch 0: patches with hard data fall
+    // back), four members per thread so that each list entry read serves four
+    const int C0 = g.cand[0];
+    const int shift = g.shift;
+    for (int i0 = tid; i0 < M; i0 += 4 * kThreads) {
+      const KT* kb[4];
+      int cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = min(i0 + u * kThreads, M - 1);
+        const int c = min(max(s_cand[i], 0), (int)g.ncand - 1);
+        const int cy = c / C0, cx = c - cy * C0;
+        kb[u] = s_K + cy * G0 + cx;
+        cc[u] = c;
+      }
+      int E[4] = {0, 0, 0, 0}, C[4] = {0, 0, 0, 0};
+#pragma unroll 2
+      for (int q = 0; q < nk; ++q) {
+        const int4 e = s_ent[q];   // one broadcast read
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kv = (int)kb[u][e.x];
+          E[u] += e.z * kv * kv;
+          C[u] += e.y * kv;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * kThreads < M) s_keys[i0 + u * kThreads] = make_key(0u, E[u] - (C[u] << shift), tie_perm((uint32_t)cc[u], tkey));
+    }
+    __syncthreads();
+    if (M >= k) block_topk(M, k, [&](long long i) { return s_keys[i]; }, sh);
+  }
+  if (tid == 0) {
+    double err = -1.0;
+    const double tsum = s_rt[0] + s_rt[1] + s_rt[2] + s_rt[3], nsum = s_rn[0] + s_rn[1] + s_rn[2] + s_rn[3];
+    if (M >= k && nsum > 0.0 && (!force || a.standalone)) {
+      const int32_t S = (int32_t)((uint32_t)((sh.top[0] >> 20) & 0xFFFFFFFFull) ^ 0x80000000u);
+      err = ((double)S + tsum) / (B * B * nsum);
+    }
+    const bool fb = force || a.gate < 0.f || err > (double)a.gate;
+    if (!a.standalone) {
+      a.ok[slot] = fb ? 0 : 1;
+      atomicAdd(&a.report[fb ? 6 : 4], 1ull);
+      if (!force) atomicAdd(&a.report[5], (unsigned long long)M);
+    } else {
+      if (a.nlist_out) a.nlist_out[slot] = M;
+      if (a.err_out) a.err_out[slot] = (float)err;
+    }
+  }
+  if (!a.standalone) {
+    if (tid < k && !force) a.sel[(long long)slot * a.top_k + tid] = sh.top[tid];
+    // the step's last proposal packs the patches the gate sends to the scan
+    __shared__ int s_last;
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const int t = __hip_atomic_fetch_add(a.ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = t == (int)gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      lp_compact(a.cmp, smem);
+      if (tid == 0) __hip_atomic_store(a.ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else {
+    if (tid < k) a.keys_out[(long long)slot * a.top_k + tid] = M >= k ? sh.top[tid] : ~0ull;
+    if (a.list_out)
+      for (int i = tid; i < M; i += kThreads) a.list_out[(long long)slot * a.cap + i] = s_cand[i];
   }
 }
 

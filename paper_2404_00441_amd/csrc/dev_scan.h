@@ -842,7 +842,8 @@ void k_scan_sel(ScanArgs a) {
   {
     const int jj = tid & (kFiltersPerTile - 1);
     const bool on = jj < t.count && !((t.zmask >> jj) & 1u);
-    const long long fo = (long long)(a.fbegin + t.first + jj) * kKMax;
+    // packed tiles name their patches in the records (rec is lane jj's)
+    const long long fo = (long long)(a.ntiles_dyn ? rec.gidx : a.fbegin + t.first + jj) * kKMax;
     for (int k8 = (tid >> 5) * 8; k8 < kl; k8 += 64) {
       int8v_t m = {}, n = {};
       if (on) {
