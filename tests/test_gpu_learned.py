@@ -243,3 +243,22 @@ def test_plain_match_errors_are_the_oracles(cc, orc, setup):
         e_ref = (S[c] + (B * B * m[nn > 0] ** 2 / nn[nn > 0]).sum()) / (B * B * nn.sum())
         assert abs(err[i] - e_ref) <= 1e-5 * max(1.0, abs(e_ref)), i
         assert e_ref >= -1e-9   # a sum of squares
+
+
+def test_training_pairs_spot_checked_by_the_oracle(cc, orc, setup):
+    # the proposer's training pairs: 1 % (at least 25) of the labels checked
+    # against the oracle's scores of the same data event
+    from paper_2404_00441_amd import learn
+    p, ti, tig, approx, w, index, K = setup
+    _say("training pairs vs oracle")
+    on, om, lab, sbest, nk = learn.training_pairs(p, tig, [11, 12])
+    geo = orc.geometry(_sp(p, orc))
+    tc = geo["tc"][:2][::-1]
+    b = geo["beta_cells"]
+    onn, omn, labn, sbn = on.cpu().numpy(), om.cpu().numpy(), lab.cpu().numpy(), sbest.cpu().numpy()
+    assert (nk.cpu().numpy() > 0).all()
+    rng = np.random.default_rng(3)
+    n = max(25, len(onn) // 100)
+    for i in rng.choice(len(onn), size=n, replace=False):
+        S = orc.scores(K, geo["cand"][:2], onn[i].reshape(tc), omn[i].reshape(tc), b).ravel()
+        assert S[labn[i]] == S.min() == sbn[i], i
