@@ -54,6 +54,8 @@ def parse():
                     help="skip dense conditioning, the level x grid-size sweep and the ensemble statistics")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the learned proposer's measurement (training, offline metrics, gate sweep)")
     ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--oracle-procs", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -546,6 +548,9 @@ def main():
     from paper_2404_00441_amd import ccwsim as cc
     from paper_2404_00441_amd import workloads as wl
 
+    if a.learned_only:
+        print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"))}), flush=True)
+        return
     p, ti, hd = wl.make(a.workload, n_real=a.n_real)
     nd = len(p["ti"])
     dev = torch.device("cuda:0")
