@@ -499,6 +499,13 @@ int ccwsim_set_scan_group(int g);
  * Returns CCWSIM_ERR_INVALID_ARG for other values. */
 int ccwsim_set_selection(int mode);
 
+/* Test hook of the certified proposer (proposer_dim 8 to 32): s > 0 skews
+ * the fitted basis (row 0 scaled by 1 + s and added s times to every other
+ * row), so that it is neither orthogonal nor normalised; its bounds, and so
+ * the results, must not change.  0 (the default) turns it off; s in [0, 4].
+ * Drops captured graphs. */
+int ccwsim_set_proposer_skew(float s);
+
 /* ---- A17/A18: realization statistics (Sec. 5.2 Fig. 7b ensemble map;
  * Sec. 5.3 Fig. 9 variograms and probability of connection; Sec. 5.8
  * Fig. 16b facies proportions) ----

@@ -126,6 +126,8 @@ def load():
     L.ccwsim_set_scan_group.argtypes = [ctypes.c_int]
     L.ccwsim_set_selection.restype = ctypes.c_int
     L.ccwsim_set_selection.argtypes = [ctypes.c_int]
+    L.ccwsim_set_proposer_skew.restype = ctypes.c_int
+    L.ccwsim_set_proposer_skew.argtypes = [ctypes.c_float]
     L.ccwsim_stats_workspace_size.restype = i64
     L.ccwsim_stats_workspace_size.argtypes = [Shape, i32]
     L.ccwsim_stats_histogram.restype = ctypes.c_int
@@ -147,7 +149,7 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
            "ccwsim_stats_connectivity", "ccwsim_cache_counts",
            "ccwsim_simulate_events", "ccwsim_simulate_match_errors", "ccwsim_lp_index_size", "ccwsim_lp_build_index",
-           "ccwsim_lp_propose_workspace_size", "ccwsim_lp_propose")
+           "ccwsim_lp_propose_workspace_size", "ccwsim_lp_propose", "ccwsim_set_proposer_skew")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
@@ -554,6 +556,10 @@ def set_scan_group(g: int):
 def set_selection(mode: int):
     """0: tuned; 1: stored keys; 2: row minima with exact rescoring of rows."""
     _check("ccwsim_set_selection", load().ccwsim_set_selection(mode))
+
+
+def set_proposer_skew(s: float):
+    _check("ccwsim_set_proposer_skew", load().ccwsim_set_proposer_skew(s))
 
 
 def set_graphs(on: bool):

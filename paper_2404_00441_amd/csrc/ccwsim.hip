@@ -194,6 +194,7 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 int g_scan_g_force = 0;   // 0: tuned choice; else tiles per scan workgroup (testing)
+float g_pca_skew = 0.f;    // test hook: rows of the certified proposer's basis skewed (not orthonormal)
 int g_sel_force = 0;      // 0: tuned choice; 1: stored keys; 2: row minima + exact rescoring
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
@@ -2118,7 +2119,7 @@ int build_plan(const ccwsim_params& p, Plan& P) {
     P.ws_pca_P = o;     o += align256((long long)P.learn * n * 4);
     P.ws_emb = o;       o += align256(g.ncand * P.learn * 4);
     P.ws_rn = o;        o += align256(g.ncand * 8);
-    P.ws_qbuf = o;      o += align256((long long)P.nfilters * (P.learn + 4) * 4);
+    P.ws_qbuf = o;      o += align256((long long)P.nfilters * (P.learn + 4) * 8);
     P.proxy_lds = (size_t)g.cand[0] * P.learn * 4 + (size_t)g.cand[0] * 8;
     if (P.proxy_lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "proposer scan needs %zu B of LDS", P.proxy_lds);
   }
@@ -2515,7 +2516,7 @@ struct FinArgs {
   const uint32_t* hdm;            // hard-data bit table, or null
   const HdBits* hd_bits;
   HdmGeom hm;
-  float* qbuf;                    // [patch][D + 4] queries of the data events
+  double* qbuf;                   // [patch][D + 4] queries of the data events (fp64)
   const float* pca_P;             // [D][template blocks]
   const float* pca_mu;            // [template blocks]
   const int32_t* energy;          // [shape][ncand]
@@ -3626,7 +3627,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     HIP_TRY(hipGetLastError());
   }
   // learned proposer: principal components of the candidates' windows
-  float* qbuf = P->learn ? (float*)(ws + P->ws_qbuf) : nullptr;
+  double* qbuf = P->learn ? (double*)(ws + P->ws_qbuf) : nullptr;
   float* pca_mu = P->learn ? (float*)(ws + P->ws_pca_mu) : nullptr;
   float* pca_P = P->learn ? (float*)(ws + P->ws_pca_P) : nullptr;
   float* emb = P->learn ? (float*)(ws + P->ws_emb) : nullptr;
@@ -3643,6 +3644,8 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
     else k_pca_moments<144><<<kPcaParts, kThreads, 0, st>>>(Ki, g, part);
     k_pca_reduce<<<nblocks((long long)n * n + n), kThreads, 0, st>>>(part, kPcaParts, g, cov, pca_mu);
     k_pca_fit<<<1, kThreads, 0, st>>>(cov, pca_mu, g, P->learn, pca_P);
+    if (g_pca_skew != 0.f)
+      k_pca_skew<<<nblocks((long long)g.tcells), kThreads, 0, st>>>(pca_P, P->learn, (int)g.tcells, g_pca_skew);
     k_pca_embed<<<nblocks(g.ncand), kThreads, 0, st>>>(Ki, g, P->learn, pca_mu, pca_P, emb, rn);
     HIP_TRY(hipGetLastError());
   }
@@ -4009,6 +4012,16 @@ extern "C" int ccwsim_set_selection(int mode) {
     drop_graphs();   // captured graphs hold the previous choice
   }
   g_sel_force = mode;
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_set_proposer_skew(float s) {
+  if (!(s == s) || s < 0.f || s > 4.f) return fail(CCWSIM_ERR_INVALID_ARG, "skew must be in [0, 4]");
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    drop_graphs();
+  }
+  g_pca_skew = s;
   return CCWSIM_OK;
 }
 

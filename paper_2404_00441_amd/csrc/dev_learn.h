@@ -174,6 +174,17 @@ __global__ __launch_bounds__(kThreads) void k_pca_fit(const float* __restrict__ 
   }
 }
 
+// Test hook: row d >= 1 of the basis gets s times row 0 added and row 0 is
+// scaled by 1 + s, so the rows are neither orthogonal nor of unit length
+// (the bound must not depend on either).
+__global__ void k_pca_skew(float* __restrict__ P, int D, int n, float s) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const float p0 = P[b];
+  for (int d = 1; d < D; ++d) P[d * n + b] += s * p0;
+  P[b] = p0 * (1.f + s);
+}
+
 // Embedding e_c = P (x_c - mu), residual bound r_c and |e_c| per candidate.
 __global__ __launch_bounds__(kThreads) void k_pca_embed(const int32_t* __restrict__ K, Geom g, int D,
                                                         const float* __restrict__ mu_g, const float* __restrict__ P_g,
@@ -208,6 +219,22 @@ __global__ __launch_bounds__(kThreads) void k_pca_embed(const int32_t* __restric
         if (d < D) e[d] += s_P[d * n + b0 + q] * xb;
     }
   }
+  (void)xx;
+  // The residual r = x - mu - P^T e of the stored (fp32) e, computed
+  // directly in fp64, so that m . x = mu . m + (P m) . e + m . r holds for
+  // any basis P, orthonormal or not.  Every product below (fp32 by fp32 or
+  // by an integer) is exact in fp64; each sum of at most D + 2 terms is off
+  // by under (D + 2) 2^-53 of its absolute terms (< 1e-14 relative); the
+  // norm is then rounded up to the next fp32 value above it, plus a 1e-9
+  // relative margin that dominates those errors by five orders of magnitude.
+  double rr = 0.0;
+  for (int b = 0; b < n; ++b) {
+    double rb = (double)Kc[s_off[b]] - (double)s_mu[b];
+#pragma unroll
+    for (int d = 0; d < kPcaMaxDim; ++d)
+      if (d < D) rb -= (double)s_P[d * n + b] * (double)e[d];
+    rr += rb * rb;
+  }
   if ((int)(blockIdx.x * kThreads + threadIdx.x) >= (int)g.ncand) return;
   float ee = 0.f;
 #pragma unroll
@@ -216,29 +243,31 @@ __global__ __launch_bounds__(kThreads) void k_pca_embed(const int32_t* __restric
       ee += e[d] * e[d];
       emb[(long long)c * D + d] = e[d];
     }
-  // |x - mu|^2 = |e|^2 + |r|^2 for orthonormal rows of P; the slack covers
-  // fp32 rounding of both sums and of the basis' orthonormality
-  const float r2 = fmaxf(xx - ee, 0.f) + 1e-5f * xx + 1.f;
-  rn[c] = make_float2(sqrtf(r2), sqrtf(ee));
+  const double rd = sqrt(rr) * (1.0 + 1e-9);
+  float rf = (float)rd;
+  if ((double)rf < rd) rf = nextafterf(rf, INFINITY);
+  rn[c] = make_float2(rf, sqrtf(ee));
 }
 
 // Query of one data event (block sums m over the template blocks, in LDS):
-// out = [q (D), a = mu . m, |m|, |q|].  Called by a whole workgroup.
+// out = [q = P m (D), a = mu . m, |m|, unused], in fp64 (products of fp32
+// values and integers are exact; the sums' rounding is covered by the
+// proxy's margin).  Called by a whole workgroup.
 __device__ __forceinline__ void pca_query(const int* s_m, int n, int D, const float* __restrict__ P_g,
-                                          const float* __restrict__ mu_g, float* __restrict__ out) {
+                                          const float* __restrict__ mu_g, double* __restrict__ out) {
   const int tid = threadIdx.x;
   if (tid < D) {
-    float s = 0.f;
-    for (int b = 0; b < n; ++b) s += P_g[tid * n + b] * (float)s_m[b];
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += (double)P_g[tid * n + b] * (double)s_m[b];
     out[tid] = s;
   } else if (tid == D) {
-    float s = 0.f;
-    for (int b = 0; b < n; ++b) s += mu_g[b] * (float)s_m[b];
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += (double)mu_g[b] * (double)s_m[b];
     out[D] = s;
   } else if (tid == D + 1) {
-    float s = 0.f;
-    for (int b = 0; b < n; ++b) s += (float)s_m[b] * (float)s_m[b];
-    out[D + 1] = sqrtf(s);
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += (double)s_m[b] * (double)s_m[b];
+    out[D + 1] = sqrt(s) * (1.0 + 1e-15);
   }
 }
 
@@ -246,7 +275,7 @@ struct ProxyArgs {
   Geom g;
   const TileDev* tiles;        // tiles of this step
   const ScanRec* recs;         // [tile][kFiltersPerTile]
-  const float* qbuf;           // [patch][D + 4]
+  const double* qbuf;          // [patch][D + 4]
   const float* emb;            // [candidate][D]
   const float2* rn;            // [candidate] (residual bound, |e|)
   const int32_t* energy;       // [shape][ncand]
@@ -281,18 +310,14 @@ __global__ __launch_bounds__(kThreads) void k_proxy(ProxyArgs a) {
   for (int i = tid; i < C0; i += kThreads) s_rn[i] = a.rn[rowbase + i];
   const bool fvalid = rec.gidx >= 0;
   const bool exact = fvalid && ((t.zmask >> j) & 1u);   // no overlap: S = 0 for every candidate
-  float q[kPcaMaxDim];
-  float qa = 0.f, qm = 0.f, qn = 0.f;
+  double q[kPcaMaxDim];
+  double qa = 0.0, qm = 0.0;
   if (fvalid) {
-    const float* qb = a.qbuf + (long long)(a.fbegin + t.first + j) * (D + 4);
+    const double* qb = a.qbuf + (long long)(a.fbegin + t.first + j) * (D + 4);
 #pragma unroll
-    for (int d = 0; d < kPcaMaxDim; ++d) q[d] = d < D ? qb[d] : 0.f;
+    for (int d = 0; d < kPcaMaxDim; ++d) q[d] = d < D ? qb[d] : 0.0;
     qa = qb[D];
     qm = qb[D + 1];
-    float s = 0.f;
-#pragma unroll
-    for (int d = 0; d < kPcaMaxDim; ++d) s += q[d] * q[d];
-    qn = sqrtf(s);
   }
   const int32_t* erow = a.energy + (long long)rec.shape * g.ncand + rowbase;
   const int two_beta = 2 * g.beta;
@@ -313,14 +338,21 @@ __global__ __launch_bounds__(kThreads) void k_proxy(ProxyArgs a) {
       if (exact) {
         key = make_key(mis, 0, tie_perm((uint32_t)(rowbase + cx), rec.tkey));
       } else {
-        float dot = 0.f;
+        // m . x = a + q . e + m . r <= a + q . e + |m| |r| (Cauchy-Schwarz),
+        // in fp64 with a 1e-9 margin over the absolute terms (the sums'
+        // rounding is under 1e-14 of them)
+        double dot = 0.0, dabs = 0.0;
 #pragma unroll
         for (int d = 0; d < kPcaMaxDim; ++d)
-          if (d < D) dot += q[d] * s_emb[cx * D + d];
-        const float2 r = s_rn[cx];
-        const float lin = qa + dot + qm * r.x;
-        const float slack = 1e-5f * (fabsf(qa) + qn * r.y + qm * r.x) + 1.f;
-        const double lb = (double)erow[cx] - (double)two_beta * ((double)lin + (double)slack);
+          if (d < D) {
+            const double t = q[d] * (double)s_emb[cx * D + d];
+            dot += t;
+            dabs += fabs(t);
+          }
+        const double mr = qm * (double)s_rn[cx].x;
+        const double lin = qa + dot + mr;
+        const double slack = 1e-9 * (fabs(qa) + dabs + mr) + 1e-9;
+        const double lb = (double)erow[cx] - (double)two_beta * (lin + slack);
         const int lbi = lb <= -2147483648.0 ? (int)0x80000000 : lb >= 2147483647.0 ? 0x7FFFFFFF : (int)floor(lb);
         key = make_key(mis, lbi, 0);
       }

@@ -214,3 +214,9 @@ def test_learned_plan_fits(lib):
         for k, v2 in bad.items():
             setattr(q2, k, v2)
         assert lib.ccwsim_simulate_workspace_size(ctypes.byref(q2)) == -1
+
+
+def test_proposer_skew_validation(lib):
+    assert lib.ccwsim_set_proposer_skew(ctypes.c_float(-1.0)) == 1
+    assert lib.ccwsim_set_proposer_skew(ctypes.c_float(float("nan"))) == 1
+    assert lib.ccwsim_set_proposer_skew(ctypes.c_float(0.0)) == 0

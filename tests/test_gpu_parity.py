@@ -914,6 +914,28 @@ def test_learned_proposer_matches_oracle(cc, orc, case):
     assert rep["proposer_patches"] <= rep["proposer_rows"] <= rep["proposer_patches"] * rows
 
 
+SKEW_CASES = [("c2_scale2d", 0.3, None, 16, 1.0), ("c5_learned", 0.12, 2, 32, 2.0), ("c4_batched", 0.4, 6, 8, 0.5)]
+
+
+@pytest.mark.parametrize("case", SKEW_CASES, ids=[f"{c[0]}_D{c[3]}_skew{c[4]}" for c in SKEW_CASES])
+def test_certified_proposer_with_a_skewed_basis(cc, orc, case):
+    # the bound is a lower bound for any basis: with rows that are neither
+    # orthogonal nor normalised the realizations are still the oracle's
+    name, scale, nr, D, skew = case
+    _say("certified proposer, skewed basis", case)
+    p, ti, hd = wl.make(name, scale=scale, n_real=nr)
+    p = dict(p, proposer_dim=D, shortlist=0)
+    cc.set_proposer_skew(skew)
+    try:
+        sim = cc.Simulator(p)
+        out = sim.run(_t(ti), cc.hd_to_device(hd, len(p["ti"])))
+        out = out.cpu().numpy()
+    finally:
+        cc.set_proposer_skew(0.0)
+    oout, _ = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(out, oout)
+
+
 # --------------------------------------------------------------------------
 # Dense conditioning and the level x grid-size cases
 # --------------------------------------------------------------------------
