@@ -312,15 +312,15 @@ def measure_learned(cc, wl, dev, reps=3):
     cells = p["n_real"] * int(np.prod(p["grid"]))
     approx, _ = cc.dwt(ti_d, p["level"])
     t0 = time.perf_counter()
-    on, om, lab, sb, nk = learn.training_pairs(p, ti_d, LP_TRAIN_SEEDS)
+    on, om, lab, best, sb, nk = learn.training_pairs(p, ti_d, LP_TRAIN_SEEDS)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
-    von, vom, vlab, vsb, vnk = learn.training_pairs(dict(p, n_real=2), ti_d, [LP_HELDOUT_SEED])
+    von, vom, vlab, vbest, vsb, vnk = learn.training_pairs(dict(p, n_real=2), ti_d, [LP_HELDOUT_SEED])
     t0 = time.perf_counter()
     w, hist = learn.train(p, approx, on, om, lab, epochs=LP_EPOCHS, batch=LP_BATCH, lr=LP_LR, seed=7)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    ev = learn.evaluate(p, w, approx, von, vom, vlab, vsb, vnk)
+    ev = learn.evaluate(p, w, approx, von, vom, vlab, vbest, vsb, vnk)
     t0 = time.perf_counter()
     index = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], LP_LISTS, iters=10)
     torch.cuda.synchronize()
@@ -339,6 +339,7 @@ def measure_learned(cc, wl, dev, reps=3):
     t_plain, e_plain, e95_plain, _, n_patches = run(p)
     res = {"workload": wl.describe(p), "training": {
         "pairs": int(on.shape[0]), "pair_seeds": list(LP_TRAIN_SEEDS), "pairs_s": t_pairs,
+        "labels_per_pair": int(lab.shape[1]),
         "epochs": LP_EPOCHS, "batch": LP_BATCH, "lr": LP_LR, "train_s": t_train,
         "loss_per_epoch": hist, "index_lists": LP_LISTS, "index_s": t_index},
         "heldout": dict(ev, seed=LP_HELDOUT_SEED),

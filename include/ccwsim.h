@@ -253,13 +253,17 @@ int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t wavelet, int
  *   ccwsim_lp_train_step: one Adam step (lr, beta 0.9 / 0.999, eps 1e-8,
  *                     step >= 1 counts the updates) on the mean over the
  *                     batch of the cross-entropy between the softmax of the
- *                     scores over every candidate and the label (the
- *                     candidate index with the best exact score); writes the
- *                     per-example loss (float32 [batch]) and, when grad_out
- *                     is not NULL, the gradient before the update;
+ *                     scores over every candidate and the labels, int32
+ *                     [batch][n_pos] distinct candidate indices (1 <= n_pos
+ *                     <= 32; the best exact scores), loss = -log of the
+ *                     softmax mass on them; writes the per-example loss
+ *                     (float32 [batch]) and, when grad_out is not NULL, the
+ *                     gradient before the update;
  *   ccwsim_lp_shortlist: the k (<= 256) highest scores' candidate indices
  *                     per row of scores (ties to the smaller index; the
- *                     order within a row is not significant).
+ *                     order within a row is not significant);
+ *   ccwsim_lp_labels: the same for exact int32 scores (Sec. 4.3 S), the k
+ *                     smallest: the training labels.
  * Every pointer is a device pointer owned by the caller; workspaces are
  * 256-byte aligned. */
 int ccwsim_lp_sizes(ccwsim_shape ti, int32_t level, const int32_t tmpl[3], int32_t batch, int64_t* n_weights,
@@ -270,9 +274,10 @@ int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccwsim_shape t
                      float* scores_out, void* workspace, int64_t workspace_bytes, void* stream);
 int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr, const int32_t* approx,
                          ccwsim_shape ti, int32_t level, const int32_t tmpl[3], const int32_t* or_n,
-                         const int32_t* or_m, const int32_t* labels, int32_t batch, float* loss, float* grad_out,
-                         void* workspace, int64_t workspace_bytes, void* stream);
+                         const int32_t* or_m, const int32_t* labels, int32_t n_pos, int32_t batch, float* loss,
+                         float* grad_out, void* workspace, int64_t workspace_bytes, void* stream);
 int ccwsim_lp_shortlist(const float* scores, int32_t batch, int64_t n_cand, int32_t k, int32_t* idx_out, void* stream);
+int ccwsim_lp_labels(const int32_t* scores, int32_t batch, int64_t n_cand, int32_t k, int32_t* idx_out, void* stream);
 
 /* Inverted lists of the keys and the proposal (Sec. 4.3 exact score of a
  * shortlist, Sec. 4.4 K best of it).

@@ -81,8 +81,10 @@ def load():
     L.ccwsim_lp_encode.restype = ctypes.c_int
     L.ccwsim_lp_encode.argtypes = [p, p, Shape, i32, p, p, p, i32, p, p, p, p, i64, p]
     L.ccwsim_lp_train_step.restype = ctypes.c_int
-    L.ccwsim_lp_train_step.argtypes = [p, p, p, i32, ctypes.c_float, p, Shape, i32, p, p, p, p, i32, p, p, p, i64,
-                                       p]
+    L.ccwsim_lp_train_step.argtypes = [p, p, p, i32, ctypes.c_float, p, Shape, i32, p, p, p, p, i32, i32, p, p, p,
+                                       i64, p]
+    L.ccwsim_lp_labels.restype = ctypes.c_int
+    L.ccwsim_lp_labels.argtypes = [p, i32, i64, i32, p, p]
     L.ccwsim_lp_shortlist.restype = ctypes.c_int
     L.ccwsim_lp_shortlist.argtypes = [p, i32, i64, i32, p, p]
     L.ccwsim_select.restype = ctypes.c_int
@@ -149,7 +151,8 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_set_selection", "ccwsim_stats_workspace_size", "ccwsim_stats_histogram", "ccwsim_stats_variogram",
            "ccwsim_stats_connectivity", "ccwsim_cache_counts",
            "ccwsim_simulate_events", "ccwsim_simulate_match_errors", "ccwsim_lp_index_size", "ccwsim_lp_build_index",
-           "ccwsim_lp_propose_workspace_size", "ccwsim_lp_propose", "ccwsim_set_proposer_skew")
+           "ccwsim_lp_propose_workspace_size", "ccwsim_lp_propose", "ccwsim_set_proposer_skew",
+           "ccwsim_lp_labels")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
@@ -369,16 +372,19 @@ def lp_encode(w, approx, ws: LpWorkspace, or_n=None, or_m=None, want_keys=True, 
 
 def lp_train_step(w, m, v, step, lr, approx, ws: LpWorkspace, or_n, or_m, labels, want_grad=False):
     """One Adam step on a batch of data events (or_n / or_m int32 [B, T_c
-    cells]) and their labels; returns the per-example losses (and the
-    gradient before the update when asked)."""
+    cells]) and their labels (int32 [B] or [B, L]: distinct positive
+    candidates per event); returns the per-example losses (and the gradient
+    before the update when asked)."""
     ext, level, tmpl, batch = ws.args
     B = or_n.shape[0]
+    n_pos = 1 if labels.dim() == 1 else int(labels.shape[1])
     assert B == batch
     loss = torch.empty(B, dtype=torch.float32, device=approx.device)
     g = torch.empty_like(w) if want_grad else None
     _check("ccwsim_lp_train_step", load().ccwsim_lp_train_step(_ptr(w), _ptr(m), _ptr(v), step, lr, _ptr(approx),
                                                                shape_of(ext), level, _i3(tmpl, 1), _ptr(or_n),
-                                                               _ptr(or_m), _ptr(labels), B, _ptr(loss), _ptr(g), _ptr(ws.ws),
+                                                               _ptr(or_m), _ptr(labels), n_pos, B, _ptr(loss), _ptr(g),
+                                                               _ptr(ws.ws),
                                                                ws.nbytes, _stream()))
     return loss, g
 
@@ -387,6 +393,15 @@ def lp_shortlist(scores, k):
     B, n = scores.shape
     idx = torch.empty((B, k), dtype=torch.int32, device=scores.device)
     _check("ccwsim_lp_shortlist", load().ccwsim_lp_shortlist(_ptr(scores), B, n, k, _ptr(idx), _stream()))
+    return idx
+
+
+def lp_labels(scores, k):
+    """The k smallest exact scores' candidate indices per row (int32 [B, k],
+    ties to the smaller index, order not significant)."""
+    B, n = scores.shape
+    idx = torch.empty((B, k), dtype=torch.int32, device=scores.device)
+    _check("ccwsim_lp_labels", load().ccwsim_lp_labels(_ptr(scores), B, n, k, _ptr(idx), _stream()))
     return idx
 
 

@@ -1078,14 +1078,16 @@ extern "C" int ccwsim_lp_encode(const float* weights, const int32_t* approx, ccw
 
 extern "C" int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr,
                                     const int32_t* approx, ccwsim_shape ti, int32_t level, const int32_t tmpl[3],
-                                    const int32_t* or_n, const int32_t* or_m, const int32_t* labels, int32_t batch,
-                                    float* loss,
+                                    const int32_t* or_n, const int32_t* or_m, const int32_t* labels, int32_t n_pos,
+                                    int32_t batch, float* loss,
                                     float* grad_out, void* workspace, int64_t workspace_bytes, void* stream) {
   LpPlan L;
   CCW_TRY(lp_plan(ti, level, tmpl, batch, L));
   if (!weights || !adam_m || !adam_v || !approx || !or_n || !or_m || !labels || !loss)
     return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
   if (batch < 1) return fail(CCWSIM_ERR_INVALID_ARG, "batch must be >= 1");
+  if (n_pos < 1 || n_pos > kLpPosMax || n_pos > L.g.ncand)
+    return fail(CCWSIM_ERR_INVALID_ARG, "n_pos must be in [1, min(%d, candidates)]", kLpPosMax);
   if (step < 1) return fail(CCWSIM_ERR_INVALID_ARG, "Adam steps count from 1");
   if (!workspace || workspace_bytes < L.total) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", L.total);
   if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -1094,7 +1096,7 @@ extern "C" int ccwsim_lp_train_step(float* weights, float* adam_m, float* adam_v
   const Geom& g = L.g;
   lp_forward(L, weights, approx, or_n, or_m, ws, true, st);
   float* S = (float*)(ws + L.o_S);
-  k_lp_ce<<<(unsigned)batch, kThreads, 0, st>>>(S, labels, g.ncand, batch, loss);   // S becomes dS
+  k_lp_ce<<<(unsigned)batch, kThreads, 0, st>>>(S, labels, n_pos, g.ncand, batch, loss);   // S becomes dS
   float* gW = (float*)(ws + L.o_gW);
   float* dq = (float*)(ws + L.o_dq);
   float* dkmap = (float*)(ws + L.o_dkmap);
@@ -1122,7 +1124,18 @@ extern "C" int ccwsim_lp_shortlist(const float* scores, int32_t batch, int64_t n
   if (batch < 0 || n_cand < 1 || n_cand > (1 << 20)) return fail(CCWSIM_ERR_INVALID_ARG, "sizes");
   if (k < 1 || k > 256 || k > n_cand) return fail(CCWSIM_ERR_INVALID_ARG, "k must be in [1, min(256, n_cand)]");
   if (batch == 0) return CCWSIM_OK;
-  k_lp_topk<<<(unsigned)batch, kThreads, 0, as_stream(stream)>>>(scores, n_cand, k, idx_out);
+  k_lp_topk<float><<<(unsigned)batch, kThreads, 0, as_stream(stream)>>>(scores, n_cand, k, idx_out);
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+extern "C" int ccwsim_lp_labels(const int32_t* scores, int32_t batch, int64_t n_cand, int32_t k, int32_t* idx_out,
+                                void* stream) {
+  if (!scores || !idx_out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (batch < 0 || n_cand < 1 || n_cand > (1 << 20)) return fail(CCWSIM_ERR_INVALID_ARG, "sizes");
+  if (k < 1 || k > 256 || k > n_cand) return fail(CCWSIM_ERR_INVALID_ARG, "k must be in [1, min(256, n_cand)]");
+  if (batch == 0) return CCWSIM_OK;
+  k_lp_topk<int32_t><<<(unsigned)batch, kThreads, 0, as_stream(stream)>>>(scores, n_cand, k, idx_out);
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }

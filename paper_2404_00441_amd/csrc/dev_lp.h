@@ -206,12 +206,16 @@ __global__ void k_lp_scores(const float* __restrict__ qv, const float* __restric
   S[id] = s;
 }
 
-// Cross-entropy of the softmax over candidates against the best position,
-// per example; dS = (softmax - onehot) / B in place of S.  One workgroup
-// per example, fixed-order reductions.
+// Cross-entropy of the softmax over candidates against a set T of L
+// positions (distinct; L = 1: the best position), per example:
+// loss = log sum_c exp S_c - log sum_{c in T} exp S_c, and in place of S
+// its gradient for the batch mean, dS_c = (p_c - [c in T] exp S_c / sum_T exp S) / B.
+// One workgroup per example, fixed-order reductions.
+constexpr int kLpPosMax = 32;
 __global__ __launch_bounds__(kThreads) void k_lp_ce(float* __restrict__ S, const int32_t* __restrict__ label,
-                                                    long long ncand, int B, float* __restrict__ loss) {
+                                                    int L, long long ncand, int B, float* __restrict__ loss) {
   __shared__ float red[kThreads];
+  __shared__ float s_lv[kLpPosMax];
   const int b = blockIdx.x;
   float* s = S + (long long)b * ncand;
   float m = -3.4e38f;
@@ -233,13 +237,16 @@ __global__ __launch_bounds__(kThreads) void k_lp_ce(float* __restrict__ S, const
     __syncthreads();
   }
   z = red[0];
-  const int lb = label[b];
-  const float sl = s[lb];
+  const int32_t* lb = label + (long long)b * L;
+  if ((int)threadIdx.x < L) s_lv[threadIdx.x] = expf(s[lb[threadIdx.x]] - m);
   __syncthreads();
-  if (threadIdx.x == 0) loss[b] = logf(z) + m - sl;
+  float zt = 0.f;
+  for (int j = 0; j < L; ++j) zt += s_lv[j];
+  if (threadIdx.x == 0) loss[b] = logf(z) - logf(zt);
   const float inv = 1.f / (z * (float)B);
-  for (long long c = threadIdx.x; c < ncand; c += kThreads)
-    s[c] = expf(s[c] - m) * inv - (c == lb ? 1.f / (float)B : 0.f);
+  for (long long c = threadIdx.x; c < ncand; c += kThreads) s[c] = expf(s[c] - m) * inv;
+  __syncthreads();
+  if ((int)threadIdx.x < L) s[lb[threadIdx.x]] -= s_lv[threadIdx.x] / (zt * (float)B);
 }
 
 // dq[b][d] = sum_c dS[b][c] k_c[d]; one workgroup per example, 4 threads
@@ -351,11 +358,14 @@ __device__ __forceinline__ uint32_t lp_desc_key(float f) {
   const uint32_t asc = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending with f
   return ~asc;                                                          // ascending with -f
 }
-__global__ __launch_bounds__(kThreads) void k_lp_topk(const float* __restrict__ S, long long ncand, int k,
+// The same order for exact integer scores: the k smallest first.
+__device__ __forceinline__ uint32_t lp_desc_key(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_lp_topk(const T* __restrict__ S, long long ncand, int k,
                                                       int32_t* __restrict__ out) {
   __shared__ unsigned hist[2048];
   __shared__ unsigned s_pref, s_need, s_cnt, s_tie[kThreads + 1];
-  const float* s = S + (long long)blockIdx.x * ncand;
+  const T* s = S + (long long)blockIdx.x * ncand;
   const int tid = threadIdx.x;
   uint32_t prefix = 0, need = (uint32_t)k;
   const int shifts[3] = {21, 10, 0}, bits[3] = {11, 11, 10};

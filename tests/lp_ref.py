@@ -106,14 +106,19 @@ def forward(w, K, beta, events, cand, tc):
 
 
 def loss_and_grad(w, K, beta, events, labels, cand, tc):
+    """labels: [B] (the best candidate) or [B, L] (a set of distinct
+    positives): loss = -log of the softmax mass on the set."""
     keys, q, S, (kin, kacts, kmap, ev, qacts, qmap) = forward(w, K, beta, events, cand, tc)
     B = S.shape[0]
+    lab = np.asarray(labels).reshape(B, -1)
     m = S.max(axis=1, keepdims=True)
     e = np.exp(S - m)
     z = e.sum(axis=1, keepdims=True)
-    loss = (np.log(z) + m)[:, 0] - S[np.arange(B), labels]
+    rows = np.arange(B)[:, None]
+    zt = e[rows, lab].sum(axis=1)
+    loss = np.log(z[:, 0]) - np.log(zt)
     dS = e / z / B
-    dS[np.arange(B), labels] -= 1.0 / B
+    dS[rows, lab] -= e[rows, lab] / zt[:, None] / B
     dq = dS @ keys
     dkeys = dS.T @ q
     kenc, qenc = unpack(w)

@@ -251,14 +251,18 @@ def test_training_pairs_spot_checked_by_the_oracle(cc, orc, setup):
     from paper_2404_00441_amd import learn
     p, ti, tig, approx, w, index, K = setup
     _say("training pairs vs oracle")
-    on, om, lab, sbest, nk = learn.training_pairs(p, tig, [11, 12])
+    on, om, lab, best, sbest, nk = learn.training_pairs(p, tig, [11, 12])
     geo = orc.geometry(_sp(p, orc))
     tc = geo["tc"][:2][::-1]
     b = geo["beta_cells"]
-    onn, omn, labn, sbn = on.cpu().numpy(), om.cpu().numpy(), lab.cpu().numpy(), sbest.cpu().numpy()
+    onn, omn, labn, bestn, sbn = (x.cpu().numpy() for x in (on, om, lab, best, sbest))
     assert (nk.cpu().numpy() > 0).all()
+    assert labn.shape[1] == p["top_k"]
     rng = np.random.default_rng(3)
     n = max(25, len(onn) // 100)
     for i in rng.choice(len(onn), size=n, replace=False):
         S = orc.scores(K, geo["cand"][:2], onn[i].reshape(tc), omn[i].reshape(tc), b).ravel()
-        assert S[labn[i]] == S.min() == sbn[i], i
+        assert S[bestn[i]] == S.min() == sbn[i], i
+        # the label set: the K smallest scores (ties to the smaller index)
+        want = np.sort(np.argsort(S, kind="stable")[: p["top_k"]])
+        assert np.array_equal(np.sort(labn[i]), want), i

@@ -102,14 +102,20 @@ def test_init_is_he_uniform_and_seeded(cc):
     assert o == w1.size
 
 
-@pytest.mark.parametrize("geom", GEOMS[:2], ids=[f"{g[0][0]}x{g[0][1]}_J{g[1]}" for g in GEOMS[:2]])
-def test_train_step_matches_reference(cc, geom):
+TRAIN_CASES = [(GEOMS[0], 1), (GEOMS[1], 1), (GEOMS[0], 4), (GEOMS[1], 10)]
+
+
+@pytest.mark.parametrize("geom,n_pos", TRAIN_CASES, ids=[f"{g[0][0]}x{g[0][1]}_J{g[1]}_L{L}" for g, L in TRAIN_CASES])
+def test_train_step_matches_reference(cc, geom, n_pos):
     import torch
     ti, level, tmpl, B = geom
-    _say("lp train step", geom)
+    _say("lp train step", geom, n_pos)
     K, (on, om), ev, cand, tc = _inputs(ti, level, tmpl, B, 5)
     rng = np.random.default_rng(9)
-    labels = rng.integers(0, cand[0] * cand[1], size=B)
+    if n_pos == 1:
+        labels = rng.integers(0, cand[0] * cand[1], size=B)
+    else:
+        labels = np.stack([rng.choice(cand[0] * cand[1], size=n_pos, replace=False) for _ in range(B)])
     w = cc.lp_init(11)
     w0 = w.cpu().numpy().astype(np.float64)
     m = torch.zeros_like(w)
@@ -158,6 +164,19 @@ def test_shortlist_matches_a_sort(cc, B, n, k):
         # patterns: take the order of the kernel's key, 0.0 above -0.0)
         key = S[b].astype(np.float64) + np.where(np.signbit(S[b]) & (S[b] == 0), -1e-300, 0.0)
         want = np.sort(np.argsort(-key, kind="stable")[:k])
+        assert np.array_equal(np.sort(idx[b]), want), b
+
+
+@pytest.mark.parametrize("B,n,k", [(3, 1000, 10), (2, 57121, 10), (1, 300, 256)])
+def test_labels_match_a_sort(cc, B, n, k):
+    # the k smallest exact scores, ties to the smaller index
+    rng = np.random.default_rng(n)
+    S = rng.integers(-5000, 5000, size=(B, n)).astype(np.int32)
+    S[0, ::3] = S[0, 0]
+    S[-1, :20] = np.iinfo(np.int32).min
+    idx = cc.lp_labels(_t(S, np.int32), k).cpu().numpy()
+    for b in range(B):
+        want = np.sort(np.argsort(S[b].astype(np.int64), kind="stable")[:k])
         assert np.array_equal(np.sort(idx[b]), want), b
 
 

@@ -46,3 +46,24 @@ def test_reference_receptive_field_covers_the_window():
         K2[y, x] = 5.0
         k1, _, _, _ = lp_ref.forward(w, K2, 16, ev, cand, tc)
         assert not np.allclose(k1[0], k0[0])   # candidate (0, 0)
+
+
+def test_reference_set_loss_gradient_and_special_case():
+    # several positives: finite differences again; one positive: the
+    # single-label loss, log(sum exp S) - S_label
+    w, K, ev, labels, cand, tc = _setup(3)
+    rng = np.random.default_rng(4)
+    sets = np.stack([rng.choice(cand[0] * cand[1], size=3, replace=False) for _ in range(3)])
+    loss, g = lp_ref.loss_and_grad(w, K, 4, ev, sets, cand, tc)
+    f = lambda ww: lp_ref.loss_and_grad(ww, K, 4, ev, sets, cand, tc)[0].mean()
+    for i in rng.choice(w.size, size=30, replace=False):
+        h = 1e-5
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        num = (f(wp) - f(wm)) / (2 * h)
+        assert abs(num - g[i]) <= 1e-6 + 1e-4 * abs(num), (i, num, g[i])
+    l1, _ = lp_ref.loss_and_grad(w, K, 4, ev, labels, cand, tc)
+    _, _, S, _ = lp_ref.forward(w, K, 4, ev, cand, tc)
+    direct = np.log(np.exp(S).sum(axis=1)) - S[np.arange(3), labels]
+    assert np.allclose(l1, direct, rtol=1e-12, atol=1e-12)
