@@ -1497,7 +1497,7 @@ struct Plan {
   const void* lp_checked = nullptr;   // the index whose header was last read back
   long long ws_lp_grid = 0, ws_lp_sel = 0, ws_lp_ok = 0, ws_lp_map = 0, ws_lp_dtiles = 0, ws_lp_drecs = 0,
             ws_lp_dcount = 0;
-  long long ws_err = 0;               // match error of every patch's choice
+  long long ws_err = 0;               // every patch's drawn candidate (for the match errors)
   int scan_g = 1;                     // tiles per scan workgroup (tuned)
   bool rows_ok = false;               // the row-minima selection fits this plan
   bool ev_delta = false;              // additive Haar data events (see k_event_init)
@@ -2503,7 +2503,7 @@ struct FinArgs {
   const int32_t* rowcnt;          // fused selection: keys at the start of each row's segment, else null
   const int32_t* lp_map;          // learned proposer: [slot] packed scan slot, or -1 (proposal stands)
   const uint64_t* lp_sel;         // learned proposer: [slot][top_k] the proposal's K best keys
-  float* err_log;                 // [patch] match error of the chosen candidate (-1: no overlap)
+  int32_t* drawn;                 // [patch] the drawn candidate
   const int32_t* Ki;
   const int32_t* det;
   const int32_t* tree;  // block-subtree coefficients (tree path)
@@ -3086,38 +3086,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a) {
   int idx = (int)tie_perm_inv((uint32_t)(s_fin[jpick] & kMask20), tkey);
   idx = min(max(idx, 0), g.ncand - 1);  // always in range for keys written by the scan
   if (tid == 0 && a.chosen_log) a.chosen_log[(long long)f.r * a.nsteps + f.step] = idx;
-  if (a.err_log) {
-    // match error of the choice: its score completed to the squared
-    // difference, sum n (K - |beta| m / n)^2 = S + sum |beta|^2 m^2 / n,
-    // over |beta|^2 times the known cells (orthonormal coefficients per
-    // known cell)
-    __shared__ double s_et[kThreads / 64], s_en[kThreads / 64];
-    const double B = (double)(1 << (g.shift - 1));
-    double t = 0.0, nn = 0.0;
-    if (tid < a.kpad && my_beta >= 0 && f.bandmask) {
-      const double m = (double)a.mbuf[(long long)(a.fbegin + slot) * kKMax + tid];
-      const int n = a.nbt[(long long)f.shape * g.tcells + my_beta];
-      if (n > 0) {
-        t = B * B * m * m / (double)n;
-        nn = (double)n;
-      }
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      t += __shfl_xor(t, m, 64);
-      nn += __shfl_xor(nn, m, 64);
-    }
-    if ((tid & 63) == 0) {
-      s_et[tid >> 6] = t;
-      s_en[tid >> 6] = nn;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const double ts = s_et[0] + s_et[1] + s_et[2] + s_et[3], ns = s_en[0] + s_en[1] + s_en[2] + s_en[3];
-      const int32_t S = (int32_t)((uint32_t)((s_fin[jpick] >> 20) & 0xFFFFFFFFull) ^ 0x80000000u);
-      a.err_log[a.fbegin + slot] = ns > 0.0 ? (float)(((double)S + ts) / (B * B * ns)) : -1.f;
-    }
-  }
+  if (tid == 0) a.drawn[a.fbegin + slot] = idx;
   const int cx = idx % g.cand[0], cy = (idx / g.cand[0]) % g.cand[1], cz = idx / (g.cand[0] * g.cand[1]);
 
   if (win_defer) {
@@ -3575,7 +3544,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   uint64_t* keys = (uint64_t*)(ws + P->ws_keys);
   uint64_t* rowmin = (uint64_t*)(ws + P->ws_rowmin);
   int32_t* rowcnt = (int32_t*)(ws + P->ws_rowcnt);
-  float* err_log = (float*)(ws + P->ws_err);
+  int32_t* drawn = (int32_t*)(ws + P->ws_err);
   // the learned proposer's patches that fall back are scanned with the fused selection
   const bool fused = P->lp || sel_fused_of(P);
   const bool sel_rows = !fused && sel_rows_of(P);
@@ -3683,7 +3652,6 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
       k_scatter_hd<<<nblocks(n_hd), kThreads, 0, st>>>(sg, hdmap, g, p->n_real, n_hd, hd_real, hd_pos, hd_val);
     k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>(predcnt, P->nfilters, 0);
     k_fill_i32<<<1, kThreads, 0, st>>>((int32_t*)report, 32, 0);
-    k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>((int32_t*)err_log, P->nfilters, (int32_t)0xBF800000u);
     if (P->ev_delta)
       k_event_init<<<(unsigned)P->nfilters, kThreads, (size_t)g.tcells * 4, st>>>(g, filters, kbeta, sg, mbuf,
                                                                                    P->kpad);
@@ -3766,7 +3734,7 @@ int enqueue_simulate(const Plan* P, const ccwsim_params* p, const int8_t* ti, in
   fa.dp_batch = P->dp_batch;
   fa.learn = P->learn;
   fa.rescore_rows = P->learn || sel_rows;
-  fa.err_log = p->score_mode == 0 ? err_log : nullptr;
+  fa.drawn = drawn;
   fa.rows_exact = !P->learn;
   fa.hdm = n_hd > 0 ? hdmask : nullptr;
   fa.hd_bits = hd_bits;
@@ -4355,6 +4323,58 @@ extern "C" int ccwsim_simulate_events(const ccwsim_params* p, const void* worksp
   return CCWSIM_OK;
 }
 
+namespace {
+// Match error of each patch's drawn candidate c, from the data event the
+// call left in the workspace and the level-J grid:
+// (S + sum |beta|^2 m^2 / n) / (|beta|^2 sum n) with S = sum n K^2 - 2^s sum m K.
+__global__ __launch_bounds__(kThreads) void k_match_errors(Geom g, const FilterDev* __restrict__ filters,
+                                                           const int32_t* __restrict__ kbeta,
+                                                           const int32_t* __restrict__ nbt,
+                                                           const int32_t* __restrict__ mbuf,
+                                                           const int32_t* __restrict__ drawn,
+                                                           const int32_t* __restrict__ Ki, int kpad, float* __restrict__ out) {
+  __shared__ double s_r[4][kThreads / 64];
+  const int pi = blockIdx.x, tid = threadIdx.x;
+  const FilterDev f = filters[pi];
+  const int c = min(max(drawn[pi], 0), (int)g.ncand - 1);
+  int cx, cy, cz;
+  split3(c, g.cand[0], g.cand[1], cx, cy, cz);
+  double t = 0.0, nn = 0.0, E = 0.0, C = 0.0;
+  if (tid < kpad && f.bandmask) {
+    const int beta = kbeta[f.orient * kKMax + tid];
+    if (beta >= 0) {
+      const int n = nbt[(long long)f.shape * g.tcells + beta];
+      if (n > 0) {
+        const double B = (double)(1 << (g.shift - 1));
+        const double m = (double)mbuf[(long long)pi * kKMax + tid];
+        int bx, by, bz;
+        split3(beta, g.tc[0], g.tc[1], bx, by, bz);
+        const double k = (double)Ki[idx3i(cx + bx, cy + by, cz + bz, g.G)];
+        t = B * B * m * m / (double)n;
+        nn = (double)n;
+        E = (double)n * k * k;
+        C = m * k;
+      }
+    }
+  }
+  double v[4] = {t, nn, E, C};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if ((tid & 63) == 0) s_r[q][tid >> 6] = v[q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double r[4];
+    for (int q = 0; q < 4; ++q) r[q] = s_r[q][0] + s_r[q][1] + s_r[q][2] + s_r[q][3];
+    const double B = (double)(1 << (g.shift - 1));
+    const double S = r[2] - (double)(1 << g.shift) * r[3];
+    out[pi] = r[1] > 0.0 ? (float)((S + r[0]) / (B * B * r[1])) : -1.f;
+  }
+}
+}  // namespace
+
 extern "C" int ccwsim_simulate_match_errors(const ccwsim_params* p, const void* workspace, int64_t workspace_bytes,
                                             float* out, void* stream) {
   if (!p || !workspace || !out) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
@@ -4362,8 +4382,18 @@ extern "C" int ccwsim_simulate_match_errors(const ccwsim_params* p, const void* 
   CCW_TRY(get_plan(*p, &Ph));
   Plan* P = Ph.get();
   if (workspace_bytes < P->ws_total) return fail(CCWSIM_ERR_WORKSPACE, "workspace too small");
-  HIP_TRY(hipMemcpyAsync(out, (const unsigned char*)workspace + P->ws_err, (size_t)P->nfilters * 4,
-                         hipMemcpyDeviceToDevice, as_stream(stream)));
+  hipStream_t st = as_stream(stream);
+  if (p->score_mode != 0) {
+    k_fill_i32<<<nblocks(P->nfilters), kThreads, 0, st>>>((int32_t*)out, P->nfilters, (int32_t)0xBF800000u);
+  } else {
+    const unsigned char* ws = (const unsigned char*)workspace;
+    const unsigned char* tbl = ws + P->ws_tbl;
+    k_match_errors<<<(unsigned)P->nfilters, kThreads, 0, st>>>(
+        P->g, (const FilterDev*)(tbl + P->off_filters), (const int32_t*)(tbl + P->off_kbeta),
+        (const int32_t*)(tbl + P->off_nbt), (const int32_t*)(ws + P->ws_mbuf), (const int32_t*)(ws + P->ws_err),
+        (const int32_t*)(ws + P->ws_ki), P->kpad, out);
+  }
+  HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }
 

@@ -440,6 +440,16 @@ __device__ __forceinline__ uint64_t wave_sort_asc(uint64_t v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS only: the fences cover the local
+// address space, so outstanding global loads (prefetches) and stores are
+// not waited for, as __syncthreads would.  For kernels whose workgroups
+// share data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {

@@ -915,7 +915,7 @@ void k_scan_sel(ScanArgs a) {
       s_seg[((sg & 1) * 2 + jp) * (kSegMax / 2) + (sg >> 1)] = p * cs + 2 * (so + jp - p);
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (!a.standalone) {
     // events to their taps, 8 taps of one filter per thread and step (the
     // tap entries were loaded before the barrier)
@@ -930,7 +930,7 @@ void k_scan_sel(ScanArgs a) {
       for (int e = 0; e < 8; ++e) v[e] = kq[e] >= 0 ? s_mst[jj * kl + kq[e]] : (OT)0.0f;
       *(vec8*)(s_B + jj * bstride + tp) = v;
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   const bool fvalid = rec.gidx >= 0;
@@ -1095,7 +1095,7 @@ void k_scan_sel(ScanArgs a) {
     for (int v = 0; v < 16; ++v)
       if (v < NG) gm[v] = vmin[v];
   }
-  __syncthreads();
+  lds_barrier();
   // tau of each patch: the ksel-th smallest of its group minima (ties by
   // position)
   for (int pi = tid; pi < kFiltersPerTile * G8; pi += kThreads) {
@@ -1109,7 +1109,7 @@ void k_scan_sel(ScanArgs a) {
     }
     if (rank == a.ksel - 1) s_tau[jj] = x;
   }
-  __syncthreads();
+  lds_barrier();
 
   // pass 2: survivors, their keys
   const qt tau = s_tau[j];
@@ -1163,7 +1163,7 @@ void k_scan_sel(ScanArgs a) {
     }
   }
   flush();
-  __syncthreads();
+  lds_barrier();
   if (tid < t.count && s_rec[tid].gidx >= 0) {
     const long long o2 = (long long)(t.first + tid) * (g.cand[1] * g.cand[2]) + row;
     a.rowcnt[o2] = (int32_t)s_cnt[tid];
