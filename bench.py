@@ -289,7 +289,7 @@ LP_TRAIN_SEEDS = (1001, 1002, 1003, 1004)   # plain simulations whose data event
 LP_HELDOUT_SEED = 2001
 LP_EPOCHS, LP_BATCH, LP_LR = 6, 512, 2e-3
 LP_LISTS, LP_PROBE = 512, 8
-LP_GATES = (None, 0.2, 0.15, 0.12, 0.1)     # None: every proposal stands
+LP_GATES = (None, 0.2, 0.15, 0.12)           # None: every proposal stands
 
 
 def measure_learned(cc, wl, dev, reps=3):

@@ -295,11 +295,11 @@ int ccwsim_lp_labels(const int32_t* scores, int32_t batch, int64_t n_cand, int32
  *     ccwsim_ccf_scan), the query (the query encoder's output at the
  *     window's centre block), the `probe` lists whose centroids have the
  *     largest inner product with it (ties to the smaller list), and their
- *     members in that order, up to 1024 (the first list alone may be cut),
+ *     members in that order, up to 1792 (the first list alone may be cut),
  *     each scored exactly in integers, S = sum n K^2 - 2 |beta| sum m K.
  *     Outputs: topk_keys uint64 [n_filters][top_k] the min(top_k, n_cand)
  *     best keys (S + 2^31, pi(index)) of ccwsim_select (all ones when fewer
- *     members were scored); members int32 [n_filters][1024] and n_members
+ *     members were scored); members int32 [n_filters][1792] and n_members
  *     int32 [n_filters], queries float32 [n_filters][64] and best_error
  *     float32 [n_filters] (the best key's match error, see
  *     ccwsim_simulate_match_errors; -1 when fewer than top_k members),

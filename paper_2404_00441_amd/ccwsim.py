@@ -424,13 +424,13 @@ def lp_build_index(w, approx, ti_extent, level, tmpl, n_lists, iters=10):
     return ix
 
 
-LP_CAND_MAX = 1024
+LP_CAND_MAX = 1792
 
 
 def lp_propose(index, approx, ti_extent, level, max_code, tmpl, or_n, or_m, probe, top_k, seed=0, realization=None,
                step=None):
     """The proposal for each data event: (keys int64 [F, k], members int32
-    [F, 1024], n_members int32 [F], queries float32 [F, 64], best match
+    [F, 1792], n_members int32 [F], queries float32 [F, 64], best match
     error float32 [F])."""
     F = or_n.shape[0]
     dev = approx.device

@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_lp_topk(const T* __restrict__ S, l
 constexpr int32_t kLpMagic = 0x4C504958;
 constexpr int kLpListsMax = 1024;   // lists of an index
 constexpr int kLpProbeMax = 16;     // lists probed per data event
-constexpr int kLpCandMax = 1024;    // candidates scored exactly per data event
+constexpr int kLpCandMax = 1792;    // candidates scored exactly per data event
 
 struct LpIndexHeader {
   int32_t magic, n_lists, level, ndim;
@@ -838,7 +838,7 @@ __host__ __device__ inline long long lp_prop_grid_bytes(const Geom& g, int kt_by
 }
 __host__ __device__ inline long long lp_prop_alias_bytes(const Geom& g, int cap) {
   long long v = (2ll * (g.tc[0] + 2) * (g.tc[1] + 2) + 49 * kLpC + 9 * kLpC + kLpC) * 4;   // encoder scratch
-  const long long ck = (((long long)cap * 4 + 15) & ~15ll) + (long long)cap * 8;         // members, keys
+  const long long ck = (((long long)cap * 4 + 15) & ~15ll) + (long long)cap * 4;         // members, scores
   if (ck > v) v = ck;
   if (4ll * kLpListsMax > v) v = 4ll * kLpListsMax;                                       // list scores
   return (v + 15) & ~15ll;
@@ -865,7 +865,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   KT* s_K = (KT*)smem;
   unsigned char* alias = smem + lp_prop_grid_bytes(g, (int)sizeof(KT));
   int* s_cand = (int*)alias;   // members, after the list scores
-  uint64_t* s_keys = (uint64_t*)(alias + (((long long)a.cap * 4 + 15) & ~15ll));
+  int32_t* s_sc = (int32_t*)(alias + (((long long)a.cap * 4 + 15) & ~15ll));   // exact scores of the members
   float* s_a0 = (float*)alias;
   float* s_a1 = s_a0 + 49 * kLpC;
   float* s_a2 = s_a1 + 9 * kLpC;
@@ -1069,10 +1069,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (i0 + u * kThreads < M) s_keys[i0 + u * kThreads] = make_key(0u, E[u] - (C[u] << shift), tie_perm((uint32_t)cc[u], tkey));
+        if (i0 + u * kThreads < M) s_sc[i0 + u * kThreads] = E[u] - (C[u] << shift);
     }
     __syncthreads();
-    if (M >= k) block_topk(M, k, [&](long long i) { return s_keys[i]; }, sh);
+    // keys rebuilt from (score, member) where they are compared
+    if (M >= k)
+      block_topk(M, k, [&](long long i) {
+        const int c = min(max(s_cand[i], 0), (int)g.ncand - 1);
+        return make_key(0u, s_sc[i], tie_perm((uint32_t)c, tkey));
+      }, sh);
   }
   if (tid == 0) {
     double err = -1.0;

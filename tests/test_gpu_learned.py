@@ -145,7 +145,7 @@ def test_proposal_matches_oracle(cc, orc, setup):
             assert cs[probed].min() >= cs[rest].max() - 1e-4 * np.abs(cs).max()
         # members are whole lists (the last one may be cut only when alone)
         tot = sum(loff[j + 1] - loff[j] for j in probed)
-        assert n == tot or (len(probed) == 1 and n == 1024)
+        assert n == tot or (len(probed) == 1 and n == cc.LP_CAND_MAX)
         # keys: the K best oracle keys over the members
         S = orc.scores(K, cand, onn[i].reshape(tc), omn[i].reshape(tc), b).ravel()
         Sm = np.full_like(S, 2 ** 31 - 1)
