@@ -620,12 +620,12 @@ __device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, in
       if (py >= 0 && py < tc1 && px >= 0 && px < tc0) {
         // the 3 x 3 neighbourhood lies in the bordered canvas
         const float* e0 = ev + py * ew + px;
-        s = b0;
+        float sc[2] = {b0, 0.f};   // one chain per input channel
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-          for (int t = 0; t < 9; ++t) s += w0[ci * 9 + t] * e0[ci * eh * ew + (t / 3) * ew + (t % 3)];
-        s = fmaxf(s, 0.f);
+          for (int t = 0; t < 9; ++t) sc[ci] += w0[ci * 9 + t] * e0[ci * eh * ew + (t / 3) * ew + (t % 3)];
+        s = fmaxf(sc[0] + sc[1], 0.f);
       }
       a0[pos * kLpC + co] = s;
     }
@@ -634,19 +634,23 @@ __device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, in
   // layer 1: 32 -> 32, dilation 2, at the 9 points h + 4 d.  Thread
   // (co, part) sums its 4 input channels (one 16-byte LDS read per tap) for
   // all 9 points; the 8 parts of an output are added with lane shuffles.
-#pragma unroll 1
+#pragma unroll 3
   for (int pos = 0; pos < 9; ++pos) {
     const int dy = pos / 3 - 1, dx = pos % 3 - 1;
     const int py = h1 + 4 * dy, px = h0 + 4 * dx;
     const bool in = py >= 0 && py < tc1 && px >= 0 && px < tc0;   // uniform
-    float s = 0.f;
+    float sc[4] = {0.f, 0.f, 0.f, 0.f};   // one chain per input channel
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       // layer-0 lattice point h + 4 d + 2 e with e = tap offset
       const int ly = 2 * (dy + 1) + (t / 3), lx = 2 * (dx + 1) + (t % 3);
       const float4 x = *(const float4*)(a0 + (ly * 7 + lx) * kLpC + p1 * 4);
-      s += w1[t] * x.x + w1[9 + t] * x.y + w1[18 + t] * x.z + w1[27 + t] * x.w;
+      sc[0] += w1[t] * x.x;
+      sc[1] += w1[9 + t] * x.y;
+      sc[2] += w1[18 + t] * x.z;
+      sc[3] += w1[27 + t] * x.w;
     }
+    float s = (sc[0] + sc[1]) + (sc[2] + sc[3]);
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
@@ -655,12 +659,16 @@ __device__ void lp_query_sparse(const float* __restrict__ W, const float* ev, in
   __syncthreads();
   // layer 2: 32 -> 32, dilation 4, at h only; 8 lanes per output
   {
-    float s = 0.f;
+    float sc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const float4 x = *(const float4*)(a1 + t * kLpC + p1 * 4);
-      s += w2[t] * x.x + w2[9 + t] * x.y + w2[18 + t] * x.z + w2[27 + t] * x.w;
+      sc[0] += w2[t] * x.x;
+      sc[1] += w2[9 + t] * x.y;
+      sc[2] += w2[18 + t] * x.z;
+      sc[3] += w2[27 + t] * x.w;
     }
+    float s = (sc[0] + sc[1]) + (sc[2] + sc[3]);
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
