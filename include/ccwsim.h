@@ -260,8 +260,8 @@ int ccwsim_ccf_scan_noalloc(ccwsim_shape ti, int32_t level, int32_t wavelet, int
  *                     (float32 [batch]) and, when grad_out is not NULL, the
  *                     gradient before the update;
  *   ccwsim_lp_shortlist: the k (<= 256) highest scores' candidate indices
- *                     per row of scores (ties to the smaller index; the
- *                     order within a row is not significant);
+ *                     per row of scores (ties to the smaller index), in
+ *                     ascending index order;
  *   ccwsim_lp_labels: the same for exact int32 scores (Sec. 4.3 S), the k
  *                     smallest: the training labels.
  * Every pointer is a device pointer owned by the caller; workspaces are

@@ -398,7 +398,7 @@ def lp_shortlist(scores, k):
 
 def lp_labels(scores, k):
     """The k smallest exact scores' candidate indices per row (int32 [B, k],
-    ties to the smaller index, order not significant)."""
+    ties to the smaller index, ascending)."""
     B, n = scores.shape
     idx = torch.empty((B, k), dtype=torch.int32, device=scores.device)
     _check("ccwsim_lp_labels", load().ccwsim_lp_labels(_ptr(scores), B, n, k, _ptr(idx), _stream()))

@@ -352,7 +352,7 @@ __global__ void k_lp_kin(const int32_t* __restrict__ K, long long n, float inv_b
 // (three passes of 11, 11 and 10 bits with LDS histograms), then every
 // candidate strictly above the threshold and, in index order, as many
 // candidates at the threshold as the k still need.  One workgroup per
-// example; the output order is not significant.
+// example; the k indices come out in ascending order.
 __device__ __forceinline__ uint32_t lp_desc_key(float f) {
   const uint32_t u = __float_as_uint(f);
   const uint32_t asc = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending with f
@@ -365,6 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_lp_topk(const T* __restrict__ S, l
                                                       int32_t* __restrict__ out) {
   __shared__ unsigned hist[2048];
   __shared__ unsigned s_pref, s_need, s_cnt, s_tie[kThreads + 1];
+  __shared__ int32_t s_out[256];
   const T* s = S + (long long)blockIdx.x * ncand;
   const int tid = threadIdx.x;
   uint32_t prefix = 0, need = (uint32_t)k;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_lp_topk(const T* __restrict__ S, l
   unsigned ties = 0;
   for (long long c = c0; c < c1; ++c) {
     const uint32_t key = lp_desc_key(s[c]);
-    if (key < prefix) out[(long long)blockIdx.x * k + atomicAdd(&s_cnt, 1u)] = (int32_t)c;
+    if (key < prefix) s_out[atomicAdd(&s_cnt, 1u)] = (int32_t)c;
     else if (key == prefix) ++ties;
   }
   s_tie[tid] = ties;
@@ -422,9 +423,18 @@ __global__ __launch_bounds__(kThreads) void k_lp_topk(const T* __restrict__ S, l
   __syncthreads();
   for (long long c = c0; c < c1 && before < need; ++c) {
     if (lp_desc_key(s[c]) == prefix) {
-      out[(long long)blockIdx.x * k + base + before] = (int32_t)c;
+      s_out[base + before] = (int32_t)c;
       ++before;
     }
+  }
+  __syncthreads();
+  // in ascending index order (distinct indices: the rank is the position),
+  // so the output does not depend on the order of the atomics above
+  for (int i = tid; i < k; i += kThreads) {
+    const int32_t v = s_out[i];
+    int r = 0;
+    for (int j = 0; j < k; ++j) r += s_out[j] < v ? 1 : 0;
+    out[(long long)blockIdx.x * k + r] = v;
   }
 }
 
