@@ -266,3 +266,83 @@ def test_training_pairs_spot_checked_by_the_oracle(cc, orc, setup):
         # the label set: the K smallest scores (ties to the smaller index)
         want = np.sort(np.argsort(S, kind="stable")[: p["top_k"]])
         assert np.array_equal(np.sort(labn[i]), want), i
+
+
+EDGE_CASES = [
+    # (lists, probe): one list holding every candidate (cut at the member
+    # cap); more lists probed than exist; the most lists (one or two candidates each)
+    (1, 4), (3, 16), (1024, 16),
+]
+
+
+@pytest.mark.parametrize("n_lists,probe", EDGE_CASES, ids=[f"L{a}_P{b}" for a, b in EDGE_CASES])
+def test_proposal_edge_cases_match_oracle(cc, orc, setup, n_lists, probe):
+    import torch
+    p, ti, tig, approx, w, index, K = setup
+    _say("proposal edge case", n_lists, probe)
+    geo = orc.geometry(_sp(p, orc))
+    tc = geo["tc"][:2][::-1]
+    cand = geo["cand"][:2]
+    b = geo["beta_cells"]
+    ncand = int(np.prod(cand))
+    n_lists = min(n_lists, ncand)
+    ix = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], n_lists, iters=3)
+    sim, out, on, om, rr, ss = _events(cc, p, tig)
+    # events with an overlap, one without (every score 0), one with a single
+    # known block
+    sel = np.nonzero(on.sum(dim=1).cpu().numpy() > 0)[0][:6]
+    on_s, om_s = on[sel].clone(), om[sel].clone()
+    on_s[0] = 0
+    om_s[0] = 0
+    on_s[1] = 0
+    om_s[1] = 0
+    on_s[1, 5] = b
+    om_s[1, 5] = b
+    rr_s, ss_s = rr[sel].contiguous(), ss[sel].to(torch.int64).contiguous()
+    keys, mem, nmem, _, _ = cc.lp_propose(ix, approx, p["ti"], p["level"], p["n_facies"] - 1, p["tmpl"],
+                                          on_s.contiguous(), om_s.contiguous(), probe, p["top_k"], seed=p["seed"],
+                                          realization=rr_s, step=ss_s)
+    keys = keys.cpu().numpy().view(np.uint64)
+    mem, nmem = mem.cpu().numpy(), nmem.cpu().numpy()
+    onn, omn, rrn, ssn = on_s.cpu().numpy(), om_s.cpu().numpy(), rr_s.cpu().numpy(), ss_s.cpu().numpy()
+    for i in range(len(sel)):
+        n = int(nmem[i])
+        assert 1 <= n <= min(ncand, cc.LP_CAND_MAX)
+        members = mem[i, :n]
+        assert len(np.unique(members)) == n and members.min() >= 0 and members.max() < ncand
+        if n_lists == 1:
+            assert n == min(ncand, cc.LP_CAND_MAX) and np.array_equal(members, np.arange(n))
+        S = orc.scores(K, cand, onn[i].reshape(tc), omn[i].reshape(tc), b).ravel()
+        Sm = np.full_like(S, 2 ** 31 - 1)
+        Sm[members] = S[members]
+        if n >= p["top_k"]:
+            _, kref = orc.select(Sm, None, p["top_k"], p["seed"], int(rrn[i]), int(ssn[i]))
+            assert np.array_equal(keys[i], kref), i
+        else:
+            assert np.all(keys[i] == np.uint64(2 ** 64 - 1))
+
+
+def test_learned_simulation_with_hard_data_falls_back_there(cc, orc):
+    # patches with hard data in their virtual template go to the scan, so a
+    # conditional run honours every datum; with the gate closed the
+    # realizations are the oracle's
+    p, ti, hd = wl.make("c2_scale2d", scale=0.3)
+    _say("learned with hard data", p["ti"], p["grid"], len(hd[0]))
+    tig = _t(ti)
+    approx, _ = cc.dwt(tig, p["level"])
+    w = cc.lp_init(9)
+    ix = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], 16, iters=3)
+    nd = len(p["ti"])
+    hdd = cc.hd_to_device(hd, nd)
+    q = dict(p, proposer_dim=64, proposer=ix, lp_probe=4, lp_gate=1e30)
+    sim = cc.Simulator(q)
+    out = sim.run(tig, hdd).cpu().numpy()
+    for r, pos, v in zip(*hd):
+        assert out[(r,) + tuple(pos[::-1])] == v
+    rep = sim.report()
+    assert rep["proposer_fallbacks"] > 0 and rep["proposer_patches"] > 0
+    q = dict(q, lp_gate=-1.0)
+    sim2 = cc.Simulator(q)
+    out2 = sim2.run(tig, hdd).cpu().numpy()
+    ref, _ = orc.simulate(_sp(p, orc), ti, hd)
+    assert np.array_equal(out2, ref)
