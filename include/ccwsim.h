@@ -210,6 +210,63 @@ int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max
                     const int32_t* realization, const int64_t* step, uint64_t* topk_keys, void* workspace,
                     int64_t workspace_bytes, void* stream);
 
+/* ---- CDF 9/7 wavelet in floating point (Sec. 4.2: the mother wavelet is a
+ * choice; Sec. 4.3 scores over the approximation) ----
+ * The Cohen-Daubechies-Feauveau 9/7 biorthogonal wavelet in the lifting
+ * factorisation of Daubechies and Sweldens: per line of even length,
+ * d += alpha (s + s'), s += beta (d' + d), d += gamma (s + s'),
+ * s += delta (d' + d) on the even (s) and odd (d) samples (primes are the
+ * right / left neighbours), then s *= zeta, d /= zeta, with alpha =
+ * -1.586134342059924, beta = -0.052980118572961, gamma = 0.882911075530934,
+ * delta = 0.443506852043971, zeta = 1.149604398860241 (low-pass gain sqrt 2
+ * at DC); whole-sample symmetric extension; x then y then z per level; the
+ * TI edge-replicated to Np = ceil(n / 2^J) * 2^J per used axis.  fp32
+ * arithmetic throughout.
+ *   ccwsim_dwt97: approx float32 [G cells] and details float32 in the layout
+ *     of ccwsim_dwt (counts from ccwsim_dwt_sizes with any wavelet).
+ *   ccwsim_idwt97: the inverse, image float32 [Np cells] (the edge-replicated
+ *     TI, up to rounding).
+ *   workspace: ccwsim_dwt97_workspace_size bytes (-1 on a bad shape),
+ *     256-byte aligned, caller-owned.
+ * ccwsim_ccf_scan97 scores every candidate (coarse-aligned as for
+ * ccwsim_ccf_scan) against n_filters data events, each a known-block mask
+ * or_n (int32 0/1 [n_filters][T_c cells]: the blocks holding a known cell)
+ * and the event's own level-J approximation or_m (float32, same shape; read
+ * where or_n is 1):  S(c) = sum over blocks b with or_n = 1 of
+ * (approx[c + b] - or_m[b])^2, evaluated in fp32 in block order (x fastest).
+ *   scores:    float32 [n_filters][C cells], the whole map, or NULL.
+ *   topk_keys: uint64 [n_filters][top_k] ascending, or NULL: key =
+ *              (bits of the fp32 S) << 20 | pi(index), pi keyed by seed,
+ *              realization[f], step[f] as in ccwsim_select; 1 <= top_k <= 16,
+ *              top_k <= C cells.
+ *   shortlist: 0 or R >= C cells: every candidate's fp32 S decides the keys.
+ *              top_k <= R < C cells (R <= 256): precision split.  A bulk pass
+ *              ranks every candidate by sum n (A K - K^2 / 2) with MFMA
+ *              operands in fp16 (precision 0; K^2 scaled by a power of two
+ *              fitting the largest |approx|, values clamped to the fp16
+ *              range) or bf16 (precision 1), fp32 accumulation; the R
+ *              candidates with the largest bulk value (ties to the smaller
+ *              index) are rescored in fp32 and the keys come from them.
+ *   shortlist_out: int32 [n_filters][R] ascending candidate indices of the
+ *              shortlist, or NULL (only with a shortlist smaller than C).
+ * The fp32 S of a candidate is the same value in the map and in its key.
+ * workspace: ccwsim_ccf_scan97_workspace_size(...) bytes (want_scores /
+ * want_keys say which outputs will be non-NULL), 256-byte aligned,
+ * caller-owned; -1 on invalid arguments.  T_c cells <= 256. */
+int64_t ccwsim_dwt97_workspace_size(ccwsim_shape s, int32_t level);
+int ccwsim_dwt97(const int8_t* x, ccwsim_shape s, int32_t level, float* approx, float* details, void* workspace,
+                 int64_t workspace_bytes, void* stream);
+int ccwsim_idwt97(const float* approx, const float* details, ccwsim_shape ti, int32_t level, float* image,
+                  void* workspace, int64_t workspace_bytes, void* stream);
+int64_t ccwsim_ccf_scan97_workspace_size(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tmpl[3],
+                                         int32_t n_filters, int32_t top_k, int32_t shortlist, int32_t want_scores,
+                                         int32_t want_keys);
+int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precision, const float* approx, const int32_t tmpl[3],
+                      const int32_t* or_n, const float* or_m, int32_t n_filters, float* scores, int32_t top_k,
+                      int32_t shortlist, uint64_t seed, const int32_t* realization, const int64_t* step,
+                      uint64_t* topk_keys, int32_t* shortlist_out, void* workspace, int64_t workspace_bytes,
+                      void* stream);
+
 /* ---- the scan without a workspace -----------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation).

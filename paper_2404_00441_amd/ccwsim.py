@@ -138,6 +138,16 @@ def load():
     L.ccwsim_stats_variogram.argtypes = [p, Shape, i32, i32, i32, i32, p, p, i64, p]
     L.ccwsim_stats_connectivity.restype = ctypes.c_int
     L.ccwsim_stats_connectivity.argtypes = [p, Shape, i32, i32, i32, i32, p, p, p, i64, p]
+    L.ccwsim_dwt97_workspace_size.restype = i64
+    L.ccwsim_dwt97_workspace_size.argtypes = [Shape, i32]
+    L.ccwsim_dwt97.restype = ctypes.c_int
+    L.ccwsim_dwt97.argtypes = [p, Shape, i32, p, p, p, i64, p]
+    L.ccwsim_idwt97.restype = ctypes.c_int
+    L.ccwsim_idwt97.argtypes = [p, p, Shape, i32, p, p, i64, p]
+    L.ccwsim_ccf_scan97_workspace_size.restype = i64
+    L.ccwsim_ccf_scan97_workspace_size.argtypes = [Shape, i32, i32, p, i32, i32, i32, i32, i32]
+    L.ccwsim_ccf_scan97.restype = ctypes.c_int
+    L.ccwsim_ccf_scan97.argtypes = [Shape, i32, i32, p, p, p, p, i32, p, i32, i32, u64, p, p, p, p, p, i64, p]
     _lib = L
     return L
 
@@ -152,7 +162,8 @@ EXPORTS = ("ccwsim_status_string", "ccwsim_last_error", "ccwsim_dwt_sizes", "ccw
            "ccwsim_stats_connectivity", "ccwsim_cache_counts",
            "ccwsim_simulate_events", "ccwsim_simulate_match_errors", "ccwsim_lp_index_size", "ccwsim_lp_build_index",
            "ccwsim_lp_propose_workspace_size", "ccwsim_lp_propose", "ccwsim_set_proposer_skew",
-           "ccwsim_lp_labels")
+           "ccwsim_lp_labels", "ccwsim_dwt97_workspace_size", "ccwsim_dwt97", "ccwsim_idwt97",
+           "ccwsim_ccf_scan97_workspace_size", "ccwsim_ccf_scan97")
 
 KINDS = ("dwt", "energy", "init", "prepare", "scan", "finalize", "crop", "learn")
 
@@ -296,6 +307,75 @@ def ccf_scan(ti_extent, level, max_code, approx, tmpl, or_n, or_m, score_mode=0,
     if not fused:
         return scores
     return scores, keys
+
+
+def dwt97(x: torch.Tensor, level: int):
+    """CDF 9/7 DWT in fp32.  x: int8 GPU tensor in numpy order.  Returns
+    (approx float32 [grid], details float32 flat, in the layout of dwt)."""
+    extent = tuple(x.shape[::-1])
+    _, nd, _ = dwt_sizes(extent, level, 0)
+    nw = int(load().ccwsim_dwt97_workspace_size(shape_of(extent), level))
+    if nw < 0:
+        raise CcwsimError("ccwsim_dwt97_workspace_size", 1, load().ccwsim_last_error().decode())
+    b = 2 ** level
+    grid = tuple(-(-n // b) for n in x.shape)
+    approx = torch.empty(grid, dtype=torch.float32, device=x.device)
+    details = torch.empty(max(nd, 1), dtype=torch.float32, device=x.device)
+    _, ws = _aligned_workspace(nw, x.device)
+    _check("ccwsim_dwt97", load().ccwsim_dwt97(_ptr(x), shape_of(extent), level, _ptr(approx), _ptr(details),
+                                               _ptr(ws), nw, _stream()))
+    return approx, details[:nd]
+
+
+def idwt97(approx: torch.Tensor, details: torch.Tensor, ti_extent, level: int):
+    """Inverse of dwt97: the edge-replicated image, float32 in numpy order."""
+    nw = int(load().ccwsim_dwt97_workspace_size(shape_of(ti_extent), level))
+    if nw < 0:
+        raise CcwsimError("ccwsim_dwt97_workspace_size", 1, load().ccwsim_last_error().decode())
+    b = 2 ** level
+    np_ = tuple(-(-n // b) * b for n in ti_extent)[::-1]
+    img = torch.empty(np_, dtype=torch.float32, device=approx.device)
+    _, ws = _aligned_workspace(nw, approx.device)
+    _check("ccwsim_idwt97", load().ccwsim_idwt97(_ptr(approx), _ptr(details) if details.numel() else None,
+                                                 shape_of(ti_extent), level, _ptr(img), _ptr(ws), nw, _stream()))
+    return img
+
+
+def ccf_scan97(ti_extent, level, approx, tmpl, or_n, or_m, top_k=None, shortlist=0, precision=0, seed=0,
+               realization=None, step=None, want_scores=None, want_shortlist=False):
+    """CDF 9/7 scores.  approx float32 [grid]; or_n int32 (0/1) and or_m
+    float32 [n_filters, T_c cells].  Without top_k: float32 scores
+    [n_filters, n_cand].  With top_k: (scores or None, keys int64 [n_filters,
+    top_k], shortlist int32 [n_filters, R] or None); shortlist 0 rescores
+    every candidate in fp32, R < n_cand ranks them first with the fp16 /
+    bf16 bulk (precision 0 / 1)."""
+    nf = or_m.shape[0]
+    b = 2 ** level
+    cand = [(ti_extent[a] - tmpl[a]) // b + 1 for a in range(len(ti_extent))]
+    ncand = 1
+    for c in cand:
+        ncand *= c
+    fused = top_k is not None
+    if want_scores is None:
+        want_scores = not fused
+    dev = approx.device
+    scores = torch.empty((nf, ncand), dtype=torch.float32, device=dev) if want_scores else None
+    keys = torch.empty((nf, top_k), dtype=torch.int64, device=dev) if fused else None
+    R = min(shortlist, ncand) if shortlist else ncand
+    sl = torch.empty((nf, R), dtype=torch.int32, device=dev) if (want_shortlist and fused and R < ncand) else None
+    t3 = _i3(tmpl, 1)
+    ws_bytes = int(load().ccwsim_ccf_scan97_workspace_size(shape_of(ti_extent), level, precision, t3, nf,
+                                                            top_k or 0, shortlist, int(want_scores), int(fused)))
+    if ws_bytes < 0:
+        raise CcwsimError("ccwsim_ccf_scan97_workspace_size", 1, load().ccwsim_last_error().decode())
+    _, ws = _aligned_workspace(ws_bytes, dev)
+    _check("ccwsim_ccf_scan97", load().ccwsim_ccf_scan97(shape_of(ti_extent), level, precision, _ptr(approx), t3,
+                                                         _ptr(or_n), _ptr(or_m), nf, _ptr(scores), top_k or 0,
+                                                         shortlist, seed, _ptr(realization), _ptr(step), _ptr(keys),
+                                                         _ptr(sl), _ptr(ws), ws_bytes, _stream()))
+    if not fused:
+        return scores
+    return scores, keys, sl
 
 
 def select(scores, mismatch, top_k, seed, realization, step, want_keys=False):

@@ -20,6 +20,7 @@
 #include "dev_learn.h"
 #include "dev_lp.h"
 #include "dev_stats.h"
+#include "dev_cdf97.h"
 
 using namespace ccw;
 
@@ -4543,6 +4544,226 @@ extern "C" int ccwsim_stats_connectivity(const int8_t* codes, ccwsim_shape shape
       k_st_conn<<<dim3(stat_blocks(s.cells, n_img), (unsigned)n_img), kThreads, (size_t)max_lag * 8, st>>>(
           L, s, axis, max_lag, ob + (long long)f * max_lag, oc + (long long)f * max_lag,
           (long long)n_facies * max_lag);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+// ===========================================================================
+// CDF 9/7 in floating point (Sec. 4.2: the mother wavelet is a choice)
+// ===========================================================================
+namespace {
+
+// Workspace of the 9/7 transforms: three float buffers of the padded TI.
+long long c97_ws_bytes(const Geom& g) { return 3 * align256((long long)g.np[0] * g.np[1] * g.np[2] * 4); }
+
+// Level-J 9/7 DWT of the TI into approx and the detail layout of the other
+// wavelets (band-stacked passes, as for 5/3).
+int launch_dwt97(const Geom& g, const int8_t* x, float* approx, float* details, unsigned char* ws, hipStream_t st) {
+  const long long npc = (long long)g.np[0] * g.np[1] * g.np[2];
+  float* C = (float*)ws;
+  float* A = (float*)(ws + align256(npc * 4));
+  float* B = (float*)(ws + 2 * align256(npc * 4));
+  k_c97_pad<<<nblocks(npc), kThreads, 0, st>>>(x, g.level == 0 ? approx : C, g);
+  int e[3] = {g.np[0], g.np[1], g.np[2]};
+  for (int j = 1; j <= g.level; ++j) {
+    const float* src = C;
+    float* bufs[2] = {A, B};
+    float* dst = nullptr;
+    for (int a = 0; a < g.ndim; ++a) {
+      dst = bufs[a & 1];
+      const long long outc = (long long)e[0] * e[1] * e[2] / 2 * (1 << a);
+      k_c97_fwd<<<nblocks(outc), kThreads, 0, st>>>(src, dst, e[0], e[1], e[2], a, 1 << a);
+      e[a] >>= 1;
+      src = dst;
+    }
+    const long long band = (long long)e[0] * e[1] * e[2];
+    HIP_TRY(hipMemcpyAsync(details + g.det_off[j], dst + band, band * ((1 << g.ndim) - 1) * 4,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(j == g.level ? approx : C, dst, band * 4, hipMemcpyDeviceToDevice, st));
+  }
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+// Inverse from approx and details into `image` (the padded extent).
+int launch_idwt97(const Geom& g, const float* approx, const float* details, float* image, unsigned char* ws,
+                  hipStream_t st) {
+  const long long npc = (long long)g.np[0] * g.np[1] * g.np[2];
+  float* C = (float*)ws;
+  float* A = (float*)(ws + align256(npc * 4));
+  float* B = (float*)(ws + 2 * align256(npc * 4));
+  const int nd = g.ndim;
+  int e[3] = {g.G[0], g.G[1], g.G[2]};
+  if (g.level == 0) {
+    HIP_TRY(hipMemcpyAsync(image, approx, npc * 4, hipMemcpyDeviceToDevice, st));
+    return CCWSIM_OK;
+  }
+  const float* cur = approx;
+  for (int j = g.level; j >= 1; --j) {
+    const long long band = (long long)e[0] * e[1] * e[2];
+    float* bufs[2] = {A, B};
+    HIP_TRY(hipMemcpyAsync(A, cur, band * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(A + band, details + g.det_off[j], band * ((1 << nd) - 1) * 4, hipMemcpyDeviceToDevice, st));
+    const float* src = A;
+    float* dst = nullptr;
+    for (int a = nd - 1, i = 1; a >= 0; --a, ++i) {
+      dst = a > 0 ? bufs[i & 1] : (j == 1 ? image : C);
+      e[a] <<= 1;
+      const long long pairs = (long long)e[0] * e[1] * e[2] / 2 * (1 << a);
+      k_c97_inv<<<nblocks(pairs), kThreads, 0, st>>>(src, dst, e[0], e[1], e[2], a, 1 << a);
+      src = dst;
+    }
+    cur = C;
+  }
+  HIP_TRY(hipGetLastError());
+  return CCWSIM_OK;
+}
+
+struct C97Plan {
+  Geom g;
+  int kpad = 0, W = 0, R = 0;
+  bool exact = true, want_scores = false, want_keys = false;
+  size_t lds = 0;
+  long long ws_cnt = 0, ws_off = 0, ws_val = 0, ws_kmax = 0, ws_map = -1, ws_bulk = -1, ws_short = -1, ws_total = 0;
+};
+
+int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tmpl[3], int32_t n_filters,
+             int32_t top_k, int32_t shortlist, bool want_scores, bool want_keys, bool scores_given, C97Plan& p) {
+  Geom& g = p.g;
+  CCW_TRY(geom_ti(g, ti, level));
+  if (!tmpl) return fail(CCWSIM_ERR_INVALID_ARG, "null template");
+  CCW_TRY(geom_tmpl(g, tmpl));
+  if (n_filters < 1) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters must be >= 1");
+  if (precision != 0 && precision != 1) return fail(CCWSIM_ERR_INVALID_ARG, "precision must be 0 (fp16) or 1 (bf16)");
+  if (!want_scores && !want_keys) return fail(CCWSIM_ERR_INVALID_ARG, "neither scores nor top-K keys requested");
+  if (g.tcells > kC97BlocksMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kC97BlocksMax);
+  p.want_scores = want_scores;
+  p.want_keys = want_keys;
+  if (want_keys) {
+    if (top_k < 1 || top_k > kTopMax) return fail(CCWSIM_ERR_UNSUPPORTED, "top_k must be in [1, %d]", kTopMax);
+    if (top_k > g.ncand) return fail(CCWSIM_ERR_INVALID_ARG, "top_k exceeds the %d candidates", g.ncand);
+    if (shortlist != 0 && (shortlist < top_k || shortlist > kC97ShortMax))
+      return fail(CCWSIM_ERR_INVALID_ARG, "shortlist must be 0 (every candidate rescored) or in [top_k, %d]",
+                  kC97ShortMax);
+    p.R = shortlist == 0 ? g.ncand : std::min(shortlist, g.ncand);
+    p.exact = p.R == g.ncand;
+  }
+  const long long nf = n_filters;
+  long long o = 0;
+  p.ws_cnt = o;   o += align256(nf * 4);
+  p.ws_off = o;   o += align256(nf * kC97BlocksMax * 4);
+  p.ws_val = o;   o += align256(nf * kC97BlocksMax * 4);
+  if (want_keys && p.exact && !scores_given) {
+    p.ws_map = o; o += align256(nf * g.ncand * 4);
+  }
+  if (want_keys && !p.exact) {
+    const int nrows = g.tc[1] * g.tc[2];
+    p.kpad = (int)((2 * g.tcells + 15) / 16 * 16);
+    p.W = kC97Seg + g.tc[0] - 1;
+    p.lds = c97_bulk_lds(nrows, p.W, p.kpad);
+    if (p.lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "bulk scan needs %zu bytes of LDS", p.lds);
+    p.ws_kmax = o;  o += 256;
+    p.ws_bulk = o;  o += align256(nf * g.ncand * 4);
+    p.ws_short = o; o += align256(nf * p.R * 4);
+  }
+  p.ws_total = o;
+  return CCWSIM_OK;
+}
+
+}  // namespace
+
+extern "C" int64_t ccwsim_dwt97_workspace_size(ccwsim_shape s, int32_t level) {
+  Geom g;
+  if (geom_ti(g, s, level)) return -1;
+  return c97_ws_bytes(g);
+}
+
+extern "C" int ccwsim_dwt97(const int8_t* x, ccwsim_shape s, int32_t level, float* approx, float* details,
+                            void* workspace, int64_t workspace_bytes, void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, s, level));
+  if (!x || !approx || (level > 0 && !details)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  const long long need = c97_ws_bytes(g);
+  if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return launch_dwt97(g, x, approx, details, (unsigned char*)workspace, as_stream(stream));
+}
+
+extern "C" int ccwsim_idwt97(const float* approx, const float* details, ccwsim_shape ti, int32_t level, float* image,
+                             void* workspace, int64_t workspace_bytes, void* stream) {
+  Geom g;
+  CCW_TRY(geom_ti(g, ti, level));
+  if (!approx || !image || (level > 0 && !details)) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  const long long need = c97_ws_bytes(g);
+  if (!workspace || workspace_bytes < need) return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return launch_idwt97(g, approx, details, image, (unsigned char*)workspace, as_stream(stream));
+}
+
+extern "C" int64_t ccwsim_ccf_scan97_workspace_size(ccwsim_shape ti, int32_t level, int32_t precision,
+                                                    const int32_t tmpl[3], int32_t n_filters, int32_t top_k,
+                                                    int32_t shortlist, int32_t want_scores, int32_t want_keys) {
+  C97Plan p;
+  if (c97_plan(ti, level, precision, tmpl, n_filters, top_k, shortlist, want_scores != 0, want_keys != 0,
+               want_scores != 0, p))
+    return -1;
+  return p.ws_total;
+}
+
+extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precision, const float* approx,
+                                 const int32_t tmpl[3], const int32_t* or_n, const float* or_m, int32_t n_filters,
+                                 float* scores, int32_t top_k, int32_t shortlist, uint64_t seed,
+                                 const int32_t* realization, const int64_t* step, uint64_t* topk_keys,
+                                 int32_t* shortlist_out, void* workspace, int64_t workspace_bytes, void* stream) {
+  C97Plan p;
+  CCW_TRY(c97_plan(ti, level, precision, tmpl, n_filters, top_k, shortlist, scores != nullptr, topk_keys != nullptr,
+                   scores != nullptr, p));
+  if (!approx || !or_n || !or_m) return fail(CCWSIM_ERR_INVALID_ARG, "null pointer");
+  if (topk_keys && (!realization || !step)) return fail(CCWSIM_ERR_INVALID_ARG, "top-K keys need realization and step");
+  if (shortlist_out && (!topk_keys || p.exact))
+    return fail(CCWSIM_ERR_INVALID_ARG, "shortlist_out needs top-K keys and a shortlist smaller than the candidates");
+  if (!workspace || workspace_bytes < p.ws_total)
+    return fail(CCWSIM_ERR_WORKSPACE, "workspace of %lld bytes needed", p.ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(CCWSIM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const Geom& g = p.g;
+  hipStream_t st = as_stream(stream);
+  unsigned char* ws = (unsigned char*)workspace;
+  int32_t* cnt = (int32_t*)(ws + p.ws_cnt);
+  int32_t* off = (int32_t*)(ws + p.ws_off);
+  float* val = (float*)(ws + p.ws_val);
+  k_c97_pack<<<nblocks(n_filters), kThreads, 0, st>>>(or_n, or_m, n_filters, g, cnt, off, val);
+  const dim3 mgrid((unsigned)((g.ncand + kThreads - 1) / kThreads), (unsigned)n_filters);
+  if (scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, scores);
+  if (topk_keys) {
+    if (p.exact) {
+      float* map = scores ? scores : (float*)(ws + p.ws_map);
+      if (!scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, map);
+      k_c97_topk_all<<<(unsigned)n_filters, kThreads, 0, st>>>(map, g, top_k, seed, realization, step, topk_keys);
+    } else {
+      float* kmax = (float*)(ws + p.ws_kmax);
+      float* bulk = (float*)(ws + p.ws_bulk);
+      int32_t* sl = shortlist_out ? shortlist_out : (int32_t*)(ws + p.ws_short);
+      const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
+      k_c97_absmax<<<1, kThreads, 0, st>>>(approx, gcells, kmax);
+      C97BulkArgs a = {};
+      a.g = g;
+      a.K = approx;
+      a.or_n = or_n;
+      a.or_m = or_m;
+      a.kmax = kmax;
+      a.n_filters = n_filters;
+      a.kpad = p.kpad;
+      a.W = p.W;
+      a.bulk = bulk;
+      const dim3 bgrid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + 31) / 32),
+                       (unsigned)((g.cand[0] + kC97Seg - 1) / kC97Seg));
+      if (precision == 1) k_c97_bulk<__bf16><<<bgrid, kThreads, p.lds, st>>>(a);
+      else k_c97_bulk<_Float16><<<bgrid, kThreads, p.lds, st>>>(a);
+      k_lp_topk<float><<<(unsigned)n_filters, kThreads, 0, st>>>(bulk, g.ncand, p.R, sl);
+      k_c97_rescore<<<(unsigned)n_filters, kThreads, 0, st>>>(approx, g, cnt, off, val, sl, p.R, top_k, seed,
+                                                             realization, step, topk_keys);
     }
   }
   HIP_TRY(hipGetLastError());

@@ -220,3 +220,23 @@ def test_proposer_skew_validation(lib):
     assert lib.ccwsim_set_proposer_skew(ctypes.c_float(-1.0)) == 1
     assert lib.ccwsim_set_proposer_skew(ctypes.c_float(float("nan"))) == 1
     assert lib.ccwsim_set_proposer_skew(ctypes.c_float(0.0)) == 0
+
+
+def test_cdf97_sizes_and_validation(lib):
+    from paper_2404_00441_amd import ccwsim
+    sh = ccwsim.shape_of((120, 100))
+    assert lib.ccwsim_dwt97_workspace_size(sh, 2) == 3 * (-(-120 * 100 * 4 // 256) * 256)   # three 256-aligned buffers
+    assert lib.ccwsim_dwt97_workspace_size(ccwsim.shape_of((0, 100)), 2) == -1
+    t = ccwsim._i3((24, 24), 1)
+    ws = lib.ccwsim_ccf_scan97_workspace_size
+    assert ws(sh, 2, 0, t, 8, 10, 0, 1, 1) > 0          # exact keys and the map
+    assert ws(sh, 2, 0, t, 8, 10, 64, 0, 1) > 0         # bulk shortlist
+    assert ws(sh, 2, 1, t, 8, 10, 64, 0, 1) > 0
+    assert ws(sh, 2, 2, t, 8, 10, 64, 0, 1) == -1       # precision
+    assert ws(sh, 2, 0, t, 8, 10, 4, 0, 1) == -1        # shortlist below top_k
+    assert ws(sh, 2, 0, t, 8, 10, 257, 0, 1) == -1      # shortlist above 256
+    assert ws(sh, 2, 0, t, 8, 17, 0, 0, 1) == -1        # top_k above 16
+    assert ws(sh, 2, 0, t, 0, 10, 0, 0, 1) == -1        # no events
+    assert ws(sh, 2, 0, t, 8, 10, 0, 0, 0) == -1        # no output
+    big = ccwsim._i3((68, 68), 1)                       # 17 x 17 blocks > 256
+    assert ws(sh, 2, 0, big, 8, 10, 0, 1, 0) == -1

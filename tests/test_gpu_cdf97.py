@@ -1,0 +1,296 @@
+"""GPU parity of the CDF 9/7 path (ccwsim_dwt97, ccwsim_idwt97,
+ccwsim_ccf_scan97) against the float64 oracle in oracle/cdf97.py.
+
+Tolerances, derived from the arithmetic:
+- transform: fp32 lifting, about a dozen roundings per output and pass,
+  amplified by the lifting gains; every coefficient within 1e-5 of the
+  largest magnitude of its band (typical errors are ~1e-7 of it).
+- scores: the kernel sums nk squared differences of the same fp32 inputs
+  the oracle reads, one rounding for the difference and one fused
+  multiply-add per term, so |S32 - S64| <= (nk + 2) 2^-24 S64; with at most
+  144 known blocks that is below 8.7e-6, and the tests assert the 1e-5
+  relative tolerance.
+- selection: keys carry the fp32 score, so which of two candidates within
+  the fp32 error of each other comes first is not unique; the tests compare
+  the sorted scores and check that every chosen candidate lies within the
+  tolerance of the K-th best.
+- bulk ranking (shortlist): the fp16 / bf16 operands are off by a relative
+  2^-11 / 2^-8 each, so the bulk value of a candidate is off by at most
+  eta(c), computed below from |A||K| and K^2 sums; a shortlist is valid when
+  no left-out candidate beats a kept one by more than the two bounds.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cdf97 as c97
+from oracle import oracle as orc
+from paper_2404_00441_amd import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_00441_amd import ccwsim
+    ccwsim.load()
+    return ccwsim
+
+
+def _img(shape, seed, nfac=3):
+    if len(shape) == 2 and min(shape) >= 40:
+        return syn.channel_image_2d(shape[1], shape[0], 5, nfac, seed=seed).astype(np.int8)
+    return np.random.default_rng(seed).integers(0, nfac, size=shape).astype(np.int8)
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).cuda()
+
+
+DWT_CASES = [((56, 64), 1), ((70, 90), 2), ((50, 37), 3), ((12, 18, 20), 2), ((8, 8), 2), ((128, 128), 2)]
+
+
+@pytest.mark.parametrize("shape,level", DWT_CASES, ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in DWT_CASES])
+def test_dwt97_matches_oracle(cc, shape, level):
+    _say("dwt97", shape, level)
+    x = _img(shape, 3)
+    a_ref, d_ref = c97.dwt97(x, level)
+    a, d = cc.dwt97(_dev(x, np.int8), level)
+    a = a.cpu().numpy().astype(np.float64)
+    d = d.cpu().numpy().astype(np.float64)
+    assert a.shape == a_ref.shape
+    assert np.abs(a - a_ref).max() <= 1e-5 * np.abs(a_ref).max()
+    off = 0
+    for dj in d_ref:
+        got = d[off: off + dj.size].reshape(dj.shape)
+        off += dj.size
+        for q in range(dj.shape[0]):
+            scale = max(np.abs(dj[q]).max(), np.abs(a_ref).max() * 1e-3)
+            assert np.abs(got[q] - dj[q]).max() <= 1e-5 * scale, q
+    assert off == d.size
+
+
+@pytest.mark.parametrize("shape,level", DWT_CASES[:4], ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in DWT_CASES[:4]])
+def test_idwt97_reconstructs(cc, shape, level):
+    _say("idwt97", shape, level)
+    x = _img(shape, 4)
+    xd = _dev(x, np.int8)
+    a, d = cc.dwt97(xd, level)
+    img = cc.idwt97(a, d, tuple(shape[::-1]), level).cpu().numpy().astype(np.float64)
+    pad = c97.pad_edge(x, level)
+    assert img.shape == pad.shape
+    assert np.abs(img - pad).max() < 1e-4
+    assert np.array_equal(np.rint(img).astype(np.int64), pad.astype(np.int64))
+    # the inverse of the oracle's (fp32-rounded) coefficients against the
+    # oracle's inverse of the same values
+    a_ref, d_ref = c97.dwt97(x, level)
+    a32 = a_ref.astype(np.float32)
+    d32 = [dj.astype(np.float32) for dj in d_ref]
+    flat = np.concatenate([dj.ravel() for dj in d32]) if d32 else np.zeros(0, np.float32)
+    img2 = cc.idwt97(_dev(a32, np.float32), _dev(flat, np.float32), tuple(shape[::-1]), level)
+    want = c97.idwt97(a32.astype(np.float64), [dj.astype(np.float64) for dj in d32])
+    assert np.abs(img2.cpu().numpy() - want).max() <= 1e-5 * np.abs(want).max()
+
+
+def _events(K, tc, n_ev, ov, seed):
+    """Data events: crops of the level-J approximation K_ref of a second
+    seeded image at random block positions, kept on an L-shaped band of ov
+    blocks (top rows and left columns), zero elsewhere."""
+    rng = np.random.default_rng(seed)
+    nd = K.ndim
+    n = np.zeros((n_ev,) + tc, np.int32)
+    A = np.zeros((n_ev,) + tc, np.float64)
+    for e in range(n_ev):
+        p = [rng.integers(0, K.shape[i] - tc[i] + 1) for i in range(nd)]
+        win = K[tuple(slice(p[i], p[i] + tc[i]) for i in range(nd))]
+        mask = np.zeros(tc, bool)
+        w = rng.integers(1, ov + 1)
+        if nd == 2:
+            mask[:w, :] = True
+            mask[:, :w] = True
+        else:
+            mask[:, :w, :] = True
+            mask[:, :, :w] = True
+        if e % 5 == 4:
+            mask[:] = False
+            mask[(0,) * nd] = True    # a single known block
+        n[e][mask] = 1
+        A[e][mask] = win[mask] + rng.normal(scale=0.05, size=mask.sum())
+    return n, A
+
+
+def _setup(ti_shape, ref_shape, level, T, n_ev, seed=11):
+    ti = _img(ti_shape, seed)
+    ref = _img(ref_shape, seed + 1)
+    K = c97.dwt97(ti, level)[0].astype(np.float32)
+    Kr = c97.dwt97(ref, level)[0]
+    b = 2 ** level
+    tc = tuple(-(-t // b) for t in T)
+    n, A = _events(Kr, tc, n_ev, max(1, tc[-1] // 4), seed + 2)
+    A = A.astype(np.float32)
+    ext = tuple(ti_shape[::-1])
+    cand = tuple((ti_shape[i] - T[i]) // b + 1 for i in range(len(T)))
+    return ti, K, n, A, ext, cand, tc
+
+
+def _oracle_scores(K, cand, n, A):
+    return np.stack([c97.scores97(K.astype(np.float64), cand, n[e], A[e].astype(np.float64)).ravel()
+                     for e in range(n.shape[0])])
+
+
+SCAN_CASES = [((100, 120), (90, 90), 2, (24, 24), 37),
+              ((64, 80), (64, 64), 1, (16, 16), 33),
+              ((120, 128), (100, 100), 2, (48, 48), 40),
+              ((20, 36, 40), (20, 30, 30), 2, (8, 12, 12), 9)]
+SCAN_IDS = [f"{'x'.join(map(str, c[0]))}_J{c[2]}_T{c[3][-1]}" for c in SCAN_CASES]
+
+
+@pytest.mark.parametrize("case", SCAN_CASES, ids=SCAN_IDS)
+def test_scan97_map_matches_oracle(cc, case):
+    ti_shape, ref_shape, level, T, n_ev = case
+    _say("scan97 map", case)
+    ti, K, n, A, ext, cand, tc = _setup(ti_shape, ref_shape, level, T, n_ev)
+    S = cc.ccf_scan97(ext, level, _dev(K, np.float32), T[::-1], _dev(n.reshape(n_ev, -1), np.int32),
+                      _dev(A.reshape(n_ev, -1), np.float32)).cpu().numpy().astype(np.float64)
+    want = _oracle_scores(K, cand, n, A)
+    assert S.shape == want.shape
+    err = np.abs(S - want)
+    assert np.all(err <= 1e-5 * want + 1e-30), float((err / np.maximum(want, 1e-30)).max())
+
+
+def _perm_table(ncand, seed, r, step):
+    key = orc.rng(seed, orc.STREAM_TIEBREAK, r, step)
+    return {orc.perm20(c, key): c for c in range(ncand)}
+
+
+def _decode(keys, table):
+    k = keys.astype(np.uint64)
+    S = (k >> np.uint64(20)).astype(np.uint32).view(np.float32).astype(np.float64)
+    idx = np.array([table[int(v)] for v in (k & np.uint64(0xFFFFF))])
+    return S, idx
+
+
+def _check_topk(S_got, idx, S64, k, allowed=None):
+    """Keys ascending; scores within the tolerance of the oracle's; the k
+    chosen are the k best of `allowed` (all candidates by default) up to
+    candidates within the fp32 error of the k-th."""
+    assert len(set(idx.tolist())) == k
+    assert np.all(np.diff(S_got) >= 0)
+    assert np.all(np.abs(S_got - S64[idx]) <= 1e-5 * S64[idx] + 1e-30)
+    pool = np.arange(S64.size) if allowed is None else np.asarray(allowed)
+    best = np.sort(S64[pool])[:k]
+    assert np.all(np.abs(np.sort(S64[idx]) - best) <= 2e-5 * best + 1e-30)
+    if allowed is not None:
+        assert set(idx.tolist()) <= set(pool.tolist())
+
+
+@pytest.mark.parametrize("case", SCAN_CASES, ids=SCAN_IDS)
+def test_scan97_exact_keys(cc, case):
+    import torch
+    ti_shape, ref_shape, level, T, n_ev = case
+    _say("scan97 exact keys", case)
+    ti, K, n, A, ext, cand, tc = _setup(ti_shape, ref_shape, level, T, n_ev)
+    k, seed = 10, 5
+    real = torch.arange(n_ev, dtype=torch.int32, device="cuda")
+    step = torch.full((n_ev,), 3, dtype=torch.int64, device="cuda")
+    S, keys, sl = cc.ccf_scan97(ext, level, _dev(K, np.float32), T[::-1], _dev(n.reshape(n_ev, -1), np.int32),
+                                _dev(A.reshape(n_ev, -1), np.float32), top_k=k, shortlist=0, seed=seed,
+                                realization=real, step=step, want_scores=True)
+    assert sl is None
+    S = S.cpu().numpy()
+    keys = keys.cpu().numpy()
+    want = _oracle_scores(K, cand, n, A)
+    ncand = want.shape[1]
+    for e in range(n_ev):
+        tab = _perm_table(ncand, seed, e, 3)
+        S_got, idx = _decode(keys[e], tab)
+        _check_topk(S_got, idx, want[e], k)
+        # the key's score is the map's value, bit for bit
+        assert np.array_equal(S_got.astype(np.float32), S[e][idx])
+    # keys alone (no map requested) are the same
+    _, keys2, _ = cc.ccf_scan97(ext, level, _dev(K, np.float32), T[::-1], _dev(n.reshape(n_ev, -1), np.int32),
+                                _dev(A.reshape(n_ev, -1), np.float32), top_k=k, shortlist=0, seed=seed,
+                                realization=real, step=step)
+    assert np.array_equal(keys2.cpu().numpy(), keys)
+
+
+def _bulk_bound(K, cand, n, A, precision):
+    """Bound eta(c) on |bulk - exact| of the ranking value sum n (A K - K^2/2)."""
+    u = 2.0 ** -11 if precision == 0 else 2.0 ** -8
+    sub = 2.0 ** -25 if precision == 0 else 0.0
+    kmax = float(np.abs(K).max())
+    q = max(0, int(np.floor(np.log2(kmax * kmax))) - 14) + 1 if kmax * kmax >= 1 and precision == 0 else 1
+    Kd = K.astype(np.float64)
+    out = []
+    for e in range(n.shape[0]):
+        nk = int(n[e].sum())
+        k2 = c97.scores97(Kd, cand, n[e], np.zeros(n[e].shape))   # sum n K^2
+        # sum n |A| |K| and sum n (|A| + |K|), by the same block loop
+        absA = np.abs(A[e].astype(np.float64))
+        aK = np.zeros(cand, np.float64)
+        apk = np.zeros(cand, np.float64)
+        for b in zip(*np.nonzero(n[e])):
+            win = np.abs(Kd[tuple(slice(b[i], b[i] + cand[i]) for i in range(Kd.ndim))])
+            aK += absA[b] * win
+            apk += absA[b] + win
+        eta = (aK * (2 * u + u * u) + apk * sub * (1 + u) + 0.5 * k2 * (u + U32 + u * U32)
+               + nk * 2.0 ** (q - 1) * sub + 2 * nk * U32 * 1.01 * (aK + 0.5 * k2) * 1.01)
+        out.append(1.5 * eta.ravel() + 1e-30)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp16", "bf16"])
+@pytest.mark.parametrize("case", SCAN_CASES, ids=SCAN_IDS)
+def test_scan97_bulk_shortlist(cc, case, precision):
+    import torch
+    ti_shape, ref_shape, level, T, n_ev = case
+    _say("scan97 bulk", case, precision)
+    ti, K, n, A, ext, cand, tc = _setup(ti_shape, ref_shape, level, T, n_ev)
+    k, R, seed = 10, 64, 9
+    real = torch.arange(n_ev, dtype=torch.int32, device="cuda")
+    step = torch.zeros((n_ev,), dtype=torch.int64, device="cuda")
+    _, keys, sl = cc.ccf_scan97(ext, level, _dev(K, np.float32), T[::-1], _dev(n.reshape(n_ev, -1), np.int32),
+                                _dev(A.reshape(n_ev, -1), np.float32), top_k=k, shortlist=R, precision=precision,
+                                seed=seed, realization=real, step=step, want_shortlist=True)
+    keys = keys.cpu().numpy()
+    sl = sl.cpu().numpy()
+    want = _oracle_scores(K, cand, n, A)
+    eta = _bulk_bound(K, cand, n, A, precision)
+    ncand = want.shape[1]
+    agree = []
+    for e in range(n_ev):
+        s = sl[e]
+        assert np.all(np.diff(s) > 0) and s[0] >= 0 and s[-1] < ncand
+        out = np.setdiff1d(np.arange(ncand), s)
+        # no left-out candidate beats a kept one by more than both bounds
+        assert (want[e][out] + 2 * eta[e][out]).min() >= (want[e][s] - 2 * eta[e][s]).max()
+        tab = _perm_table(ncand, seed, e, 0)
+        S_got, idx = _decode(keys[e], tab)
+        _check_topk(S_got, idx, want[e], k, allowed=s)
+        agree.append(len(set(idx.tolist()) & set(c97.topk97(want[e], k).tolist())) / k)
+    _say(f"  top-{k} agreement with the float64 oracle: mean {np.mean(agree):.3f}, min {np.min(agree):.2f}")
+
+
+def test_scan97_validation(cc):
+    import torch
+    K = torch.zeros((30, 30), dtype=torch.float32, device="cuda")
+    n = torch.ones((2, 36), dtype=torch.int32, device="cuda")
+    A = torch.zeros((2, 36), dtype=torch.float32, device="cuda")
+    real = torch.zeros(2, dtype=torch.int32, device="cuda")
+    step = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with pytest.raises(cc.CcwsimError):   # shortlist below top_k
+        cc.ccf_scan97((120, 120), 2, K, (24, 24), n, A, top_k=8, shortlist=4, realization=real, step=step)
+    with pytest.raises(cc.CcwsimError):   # top_k above 16
+        cc.ccf_scan97((120, 120), 2, K, (24, 24), n, A, top_k=17, realization=real, step=step)
+    with pytest.raises(cc.CcwsimError):   # shortlist above 256
+        cc.ccf_scan97((120, 120), 2, K, (24, 24), n, A, top_k=8, shortlist=300, realization=real, step=step)
