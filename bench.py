@@ -54,6 +54,8 @@ def parse():
                     help="skip dense conditioning, the level x grid-size sweep and the ensemble statistics")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
+    ap.add_argument("--cdf97-only", action="store_true",
+                    help="print only the CDF 9/7 measurements (transform, exact and split selection)")
     ap.add_argument("--learned-only", action="store_true",
                     help="only the learned proposer's measurement (training, offline metrics, gate sweep)")
     ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
@@ -412,7 +414,85 @@ def measure_next(cc, wl, dev):
             out["level_grid"].append(dict(_time_case(cc, p, ti, hd, dev), level=level, grid=n))
         p, ti, hd = wl.level_grid_case(level, 512, hd_per_512=2000)
         out["level_grid"].append(dict(_time_case(cc, p, ti, hd, dev), level=level, grid=512))
+    out["cdf97"] = measure_cdf97(cc, wl, dev)
     return out
+
+
+def measure_cdf97(cc, wl, dev, n_events=448, k=10, reps=10):
+    """The CDF 9/7 path at the 2000^2 x 16 workload's scan shape (1000^2
+    three-facies training image, J = 2, T = 48, 448 data events: 28 patches
+    in flight x 16 realizations): the transform, the exact fp32 selection
+    (every candidate rescored) and the precision split (fp16 / bf16 MFMA bulk,
+    fp32 rescoring of a 64 or 128 shortlist), with the share of the exact
+    path's 10 best that each split keeps.  Events are crops of the level-2
+    approximation of a second seeded channel image at random block
+    positions, known on an L-shaped band of 3 blocks."""
+    import numpy as np
+    import torch
+    from paper_2404_00441_amd import synthetic as syn
+    p, ti, _ = wl.make("c5_learned", n_real=1)
+    level, T = p["level"], p["tmpl"]
+    b = 2 ** level
+    tc = [-(-t // b) for t in T]
+    ti_d = torch.from_numpy(np.ascontiguousarray(ti)).to(dev)
+    ref = syn.channel_image_2d(p["grid"][0] // 2, p["grid"][1] // 2, 50, p["n_facies"], seed=4242)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_dwt = timed(lambda: cc.dwt97(ti_d, level))
+    K, _ = cc.dwt97(ti_d, level)
+    Kr, _ = cc.dwt97(torch.from_numpy(np.ascontiguousarray(ref)).to(dev), level)
+    Kr = Kr.cpu().numpy()
+    rng = np.random.default_rng(17)
+    ov = 3
+    mask = np.zeros((tc[1], tc[0]), bool)
+    mask[:ov, :] = True
+    mask[:, :ov] = True
+    n = np.broadcast_to(mask, (n_events,) + mask.shape).astype(np.int32).copy()
+    A = np.zeros(n.shape, np.float32)
+    for e in range(n_events):
+        y, x = rng.integers(0, Kr.shape[0] - tc[1] + 1), rng.integers(0, Kr.shape[1] - tc[0] + 1)
+        A[e][mask] = Kr[y: y + tc[1], x: x + tc[0]][mask]
+    n_d = torch.from_numpy(n.reshape(n_events, -1)).to(dev)
+    A_d = torch.from_numpy(A.reshape(n_events, -1)).to(dev)
+    real = torch.arange(n_events, dtype=torch.int32, device=dev) % 16
+    step = torch.arange(n_events, dtype=torch.int64, device=dev)
+    cand = [(p["ti"][a] - T[a]) // b + 1 for a in range(2)]
+    ncand = cand[0] * cand[1]
+    nk = int(mask.sum())
+
+    def run(shortlist, precision=0):
+        return cc.ccf_scan97(p["ti"], level, K, T, n_d, A_d, top_k=k, shortlist=shortlist, precision=precision,
+                             seed=1, realization=real, step=step)[1]
+
+    exact = run(0).cpu()
+    ex_idx = [set((exact[e] & 0xFFFFF).tolist()) for e in range(n_events)]
+    ms_exact = timed(lambda: run(0))
+    res = {"workload": f"1000^2 TI, J={level}, T={T[0]}, {n_events} events x {ncand} candidates, "
+                       f"{nk} known blocks per event, K={k}",
+           "dwt97_ms": ms_dwt,
+           "exact_fp32": {"ms_per_call": ms_exact,
+                          "gflops_fp32": 3.0 * nk * ncand * n_events / (ms_exact * 1e-3) / 1e9},
+           "split": []}
+    for prec, name in ((0, "fp16"), (1, "bf16")):
+        for R in (64, 128):
+            keys = run(R, prec).cpu()
+            same = np.mean([len(ex_idx[e] & set((keys[e] & 0xFFFFF).tolist())) / k for e in range(n_events)])
+            ms = timed(lambda: run(R, prec))
+            res["split"].append({"bulk": name, "shortlist": R, "ms_per_call": ms,
+                                 "speedup_vs_exact": ms_exact / ms,
+                                 "top10_same_as_exact": float(same),
+                                 "bulk_tflops_algorithmic": 2.0 * 2 * nk * ncand * n_events / (ms * 1e-3) / 1e12})
+    return res
 
 
 def measure_stats(cc, wl, dev, n_real=100, max_lag=200):
@@ -563,6 +643,9 @@ def main():
 
     if a.learned_only:
         print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"))}), flush=True)
+        return
+    if a.cdf97_only:
+        print(json.dumps({"cdf97": measure_cdf97(cc, wl, torch.device("cuda:0"))}), flush=True)
         return
     p, ti, hd = wl.make(a.workload, n_real=a.n_real)
     nd = len(p["ti"])

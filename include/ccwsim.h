@@ -240,7 +240,7 @@ int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max
  *              realization[f], step[f] as in ccwsim_select; 1 <= top_k <= 16,
  *              top_k <= C cells.
  *   shortlist: 0 or R >= C cells: every candidate's fp32 S decides the keys.
- *              top_k <= R < C cells (R <= 256): precision split.  A bulk pass
+ *              top_k <= R < C cells (R <= 128): precision split.  A bulk pass
  *              ranks every candidate by sum n (A K - K^2 / 2) with MFMA
  *              operands in fp16 (precision 0; K^2 scaled by a power of two
  *              fitting the largest |approx|, values clamped to the fp16

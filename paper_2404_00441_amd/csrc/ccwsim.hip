@@ -4626,7 +4626,8 @@ struct C97Plan {
   int kpad = 0, W = 0, R = 0;
   bool exact = true, want_scores = false, want_keys = false;
   size_t lds = 0;
-  long long ws_cnt = 0, ws_off = 0, ws_val = 0, ws_kmax = 0, ws_map = -1, ws_bulk = -1, ws_short = -1, ws_total = 0;
+  long long ws_cnt = 0, ws_off = 0, ws_val = 0, ws_kmax = 0, ws_map = -1, ws_bulk = -1, ws_short = -1, ws_cext = -1,
+            ws_total = 0;
 };
 
 int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tmpl[3], int32_t n_filters,
@@ -4655,8 +4656,12 @@ int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tm
   p.ws_cnt = o;   o += align256(nf * 4);
   p.ws_off = o;   o += align256(nf * kC97BlocksMax * 4);
   p.ws_val = o;   o += align256(nf * kC97BlocksMax * 4);
+  const long long nchk = (long long)g.cand[1] * g.cand[2] * ((g.cand[0] + 31) / 32);
   if (want_keys && p.exact && !scores_given) {
     p.ws_map = o; o += align256(nf * g.ncand * 4);
+  }
+  if (want_keys) {
+    p.ws_cext = o; o += align256(nf * nchk * 4);
   }
   if (want_keys && !p.exact) {
     const int nrows = g.tc[1] * g.tc[2];
@@ -4664,7 +4669,7 @@ int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tm
     p.W = kC97Seg + g.tc[0] - 1;
     p.lds = c97_bulk_lds(nrows, p.W, p.kpad);
     if (p.lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "bulk scan needs %zu bytes of LDS", p.lds);
-    p.ws_kmax = o;  o += 256;
+    p.ws_kmax = o;  o += align256(kC97MaxParts * 4);
     p.ws_bulk = o;  o += align256(nf * g.ncand * 4);
     p.ws_short = o; o += align256(nf * p.R * 4);
   }
@@ -4733,20 +4738,23 @@ extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precisi
   int32_t* cnt = (int32_t*)(ws + p.ws_cnt);
   int32_t* off = (int32_t*)(ws + p.ws_off);
   float* val = (float*)(ws + p.ws_val);
-  k_c97_pack<<<nblocks(n_filters), kThreads, 0, st>>>(or_n, or_m, n_filters, g, cnt, off, val);
-  const dim3 mgrid((unsigned)((g.ncand + kThreads - 1) / kThreads), (unsigned)n_filters);
-  if (scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, scores);
+  k_c97_pack<<<(unsigned)((n_filters + kThreads / 64 - 1) / (kThreads / 64)), kThreads, 0, st>>>(
+      or_n, or_m, n_filters, g, cnt, off, val);
+  const unsigned nseg = (unsigned)((g.cand[0] + kThreads - 1) / kThreads);
+  const dim3 mgrid(nseg * (unsigned)(g.cand[1] * g.cand[2]), (unsigned)n_filters);
+  float* cext = topk_keys ? (float*)(ws + p.ws_cext) : nullptr;
+  if (scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, scores, p.exact ? cext : nullptr);
   if (topk_keys) {
     if (p.exact) {
       float* map = scores ? scores : (float*)(ws + p.ws_map);
-      if (!scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, map);
-      k_c97_topk_all<<<(unsigned)n_filters, kThreads, 0, st>>>(map, g, top_k, seed, realization, step, topk_keys);
+      if (!scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, map, cext);
+      k_c97_best<<<(unsigned)n_filters, kThreads, 0, st>>>(map, cext, g, top_k, seed, realization, step, topk_keys);
     } else {
       float* kmax = (float*)(ws + p.ws_kmax);
       float* bulk = (float*)(ws + p.ws_bulk);
       int32_t* sl = shortlist_out ? shortlist_out : (int32_t*)(ws + p.ws_short);
       const long long gcells = (long long)g.G[0] * g.G[1] * g.G[2];
-      k_c97_absmax<<<1, kThreads, 0, st>>>(approx, gcells, kmax);
+      k_c97_absmax<<<kC97MaxParts, kThreads, 0, st>>>(approx, gcells, kmax);
       C97BulkArgs a = {};
       a.g = g;
       a.K = approx;
@@ -4757,11 +4765,12 @@ extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precisi
       a.kpad = p.kpad;
       a.W = p.W;
       a.bulk = bulk;
+      a.cmax = cext;
       const dim3 bgrid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + 31) / 32),
                        (unsigned)((g.cand[0] + kC97Seg - 1) / kC97Seg));
       if (precision == 1) k_c97_bulk<__bf16><<<bgrid, kThreads, p.lds, st>>>(a);
       else k_c97_bulk<_Float16><<<bgrid, kThreads, p.lds, st>>>(a);
-      k_lp_topk<float><<<(unsigned)n_filters, kThreads, 0, st>>>(bulk, g.ncand, p.R, sl);
+      k_c97_short<<<(unsigned)n_filters, kThreads, 0, st>>>(bulk, cext, g, p.R, sl);
       k_c97_rescore<<<(unsigned)n_filters, kThreads, 0, st>>>(approx, g, cnt, off, val, sl, p.R, top_k, seed,
                                                              realization, step, topk_keys);
     }

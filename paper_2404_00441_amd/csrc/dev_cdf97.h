@@ -26,7 +26,7 @@ constexpr float kC97Gamma = 0.882911075530934f;
 constexpr float kC97Delta = 0.443506852043971f;
 constexpr float kC97Zeta = 1.149604398860241f;
 constexpr int kC97BlocksMax = 256;    // template blocks of a 9/7 event
-constexpr int kC97ShortMax = 256;     // candidates rescored per event
+constexpr int kC97ShortMax = 128;     // candidates rescored per event
 constexpr int kC97Seg = 256;          // candidates of a row per bulk workgroup
 
 // Index i of a line of n samples under whole-sample symmetric extension
@@ -127,20 +127,28 @@ __global__ __launch_bounds__(kThreads) void k_c97_inv(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 
 // Per event: its known blocks in template order as (offset of block b from a
-// candidate's base cell in the K grid, A_b), and their count.
-__global__ void k_c97_pack(const int32_t* __restrict__ or_n, const float* __restrict__ or_m, int n_filters, Geom g,
-                           int32_t* __restrict__ cnt, int32_t* __restrict__ off, float* __restrict__ val) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// candidate's base cell in the K grid, A_b), and their count.  One
+// wavefront per event; blocks are compacted 64 at a time by ballot.
+__global__ __launch_bounds__(kThreads) void k_c97_pack(const int32_t* __restrict__ or_n, const float* __restrict__ or_m,
+                                                       int n_filters, Geom g, int32_t* __restrict__ cnt,
+                                                       int32_t* __restrict__ off, float* __restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  const int f = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (f >= n_filters) return;
   int c = 0;
-  for (int b = 0; b < (int)g.tcells; ++b) {
-    if (or_n[(long long)f * g.tcells + b] == 0) continue;
-    const int bx = b % g.tc[0], by = (b / g.tc[0]) % g.tc[1], bz = b / (g.tc[0] * g.tc[1]);
-    off[(long long)f * kC97BlocksMax + c] = idx3i(bx, by, bz, g.G);
-    val[(long long)f * kC97BlocksMax + c] = or_m[(long long)f * g.tcells + b];
-    ++c;
+  for (int b0 = 0; b0 < (int)g.tcells; b0 += 64) {
+    const int b = b0 + lane;
+    const bool known = b < (int)g.tcells && or_n[(long long)f * g.tcells + b] != 0;
+    const uint64_t m = __ballot(known);
+    if (known) {
+      const int pos = c + __popcll(m & ((1ull << lane) - 1ull));
+      const int bx = b % g.tc[0], by = (b / g.tc[0]) % g.tc[1], bz = b / (g.tc[0] * g.tc[1]);
+      off[(long long)f * kC97BlocksMax + pos] = idx3i(bx, by, bz, g.G);
+      val[(long long)f * kC97BlocksMax + pos] = or_m[(long long)f * g.tcells + b];
+    }
+    c += __popcll(m);
   }
-  cnt[f] = c;
+  if (lane == 0) cnt[f] = c;
 }
 
 // Cell of candidate c in the K grid.
@@ -168,43 +176,58 @@ __device__ __forceinline__ uint64_t c97_key(float S, int c, uint64_t tkey) {
   return ((uint64_t)__float_as_uint(S) << 20) | tie_perm((uint32_t)c, tkey);
 }
 
-// The score map: grid (candidate blocks of 256, events).
+// Order-preserving 32-bit key of a float: ascending with the value.
+__device__ __forceinline__ uint32_t c97_asc(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Candidates are taken in chunks of 32 consecutive x positions of one
+// candidate row: chunk q = row * nchr + x / 32, nchr = ceil(C_x / 32), so the
+// chunks ascend with the candidate index.  The score map and the bulk pass
+// leave each chunk's best value (smallest score, largest bulk value) for
+// the selections below.
+
+// The score map: grid (candidate rows x row segments of 256 candidates,
+// events).  Optionally the smallest score of each chunk.
 __global__ __launch_bounds__(kThreads) void k_c97_map(const float* __restrict__ K, Geom g, const int32_t* __restrict__ cnt,
                                                       const int32_t* __restrict__ off, const float* __restrict__ val,
-                                                      float* __restrict__ out) {
+                                                      float* __restrict__ out, float* __restrict__ cmin) {
   __shared__ int s_off[kC97BlocksMax];
   __shared__ float s_val[kC97BlocksMax];
-  const int f = blockIdx.y, tid = threadIdx.x;
+  const int nseg = (g.cand[0] + kThreads - 1) / kThreads;
+  const int f = blockIdx.y, row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg, tid = threadIdx.x;
   const int nk = cnt[f];
   for (int i = tid; i < nk; i += kThreads) {
     s_off[i] = off[(long long)f * kC97BlocksMax + i];
     s_val[i] = val[(long long)f * kC97BlocksMax + i];
   }
   __syncthreads();
-  const int c = blockIdx.x * kThreads + tid;
-  if (c >= g.ncand) return;
-  out[(long long)f * g.ncand + c] = c97_score(K, c97_base(c, g), s_off, s_val, nk);
+  const int x = seg * kThreads + tid;
+  const bool ok = x < g.cand[0];
+  const int c = row * g.cand[0] + x;
+  float S = INFINITY;
+  if (ok) {
+    S = c97_score(K, c97_base(c, g), s_off, s_val, nk);
+    out[(long long)f * g.ncand + c] = S;
+  }
+  if (cmin) {
+    float m = S;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) m = fminf(m, __shfl_xor(m, o));
+    const int nchr = (g.cand[0] + 31) / 32;
+    if ((tid & 31) == 0 && x < g.cand[0])
+      cmin[(long long)f * g.cand[1] * g.cand[2] * nchr + (long long)row * nchr + x / 32] = m;
+  }
 }
 
-// The K best of every candidate (from the score map): one workgroup per
-// event, keys ascending.
-__global__ __launch_bounds__(kThreads) void k_c97_topk_all(const float* __restrict__ map, Geom g, int k, uint64_t seed,
-                                                           const int32_t* __restrict__ real,
-                                                           const int64_t* __restrict__ steps, uint64_t* __restrict__ out) {
-  __shared__ TopkShared sh;
-  const int f = blockIdx.x;
-  const uint64_t tkey = draw64(seed, kStreamTiebreak, (uint64_t)real[f], (uint64_t)steps[f]);
-  const float* m = map + (long long)f * g.ncand;
-  block_topk(g.ncand, k, [&](long long c) { return c97_key(m[c], (int)c, tkey); }, sh);
-  if ((int)threadIdx.x < k) out[(long long)f * k + threadIdx.x] = sh.top[threadIdx.x];
-}
-
-// Largest |K| over the grid (one workgroup); it sets the fp16 operands'
-// power-of-two scaling of K^2.
-__global__ __launch_bounds__(kThreads) void k_c97_absmax(const float* __restrict__ K, long long n, float* __restrict__ out) {
+// Largest |K| over the grid: one partial maximum per workgroup (64 of them).
+constexpr int kC97MaxParts = 64;
+__global__ __launch_bounds__(kThreads) void k_c97_absmax(const float* __restrict__ K, long long n, float* __restrict__ part) {
   __shared__ float s_m[kThreads / 64];
   float m = 0.f;
-  for (long long i = threadIdx.x; i < n; i += kThreads) m = fmaxf(m, fabsf(K[i]));
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    m = fmaxf(m, fabsf(K[i]));
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
@@ -212,8 +235,198 @@ __global__ __launch_bounds__(kThreads) void k_c97_absmax(const float* __restrict
   if (threadIdx.x == 0) {
     float r = s_m[0];
     for (int w = 1; w < kThreads / 64; ++w) r = fmaxf(r, s_m[w]);
-    *out = r;
+    part[blockIdx.x] = r;
   }
+}
+
+// Workgroup-wide inclusive prefix sum of one value per thread (threads in
+// order); s_w holds kThreads / 64 + 1 entries.  Every thread must call it.
+__device__ __forceinline__ unsigned c97_incl_scan(unsigned v, unsigned* s_w, unsigned& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) s_w[wave] = v;
+  __syncthreads();
+  unsigned base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    base += w < wave ? s_w[w] : 0u;
+    tot += s_w[w];
+  }
+  __syncthreads();
+  total = tot;
+  return base + v;
+}
+
+struct C97Sel {
+  unsigned hist[2048];
+  unsigned w[kThreads / 64 + 1];
+  uint32_t key, need;
+};
+
+// The k-th smallest of n 32-bit keys key_at(i) (1 <= k <= n): its value,
+// and how many keys equal to it the k smallest take.  Three histogram
+// passes of 11, 11 and 10 bits; each pass finds its bin with a prefix sum
+// over the workgroup (thread t owns bins 8t .. 8t + 7).
+template <class KeyFn>
+__device__ void c97_kth_smallest(int n, int k, KeyFn key_at, C97Sel& sh) {
+  const int tid = threadIdx.x;
+  uint32_t prefix = 0, need = (uint32_t)k;
+  const int shifts[3] = {21, 10, 0}, bits[3] = {11, 11, 10};
+  for (int pass = 0; pass < 3; ++pass) {
+    for (int i = tid; i < 2048; i += kThreads) sh.hist[i] = 0;
+    __syncthreads();
+    const int shf = shifts[pass];
+    const uint32_t hmask = pass == 0 ? 0u : ~((1u << (shf + bits[pass])) - 1u);
+    const uint32_t dmask = (1u << bits[pass]) - 1u;
+    for (int i = tid; i < n; i += kThreads) {
+      const uint32_t key = key_at(i);
+      if ((key & hmask) == (prefix & hmask)) atomicAdd(&sh.hist[(key >> shf) & dmask], 1u);
+    }
+    __syncthreads();
+    unsigned loc[8], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      loc[j] = sh.hist[8 * tid + j];
+      sum += loc[j];
+    }
+    unsigned total;
+    const unsigned incl = c97_incl_scan(sum, sh.w, total);
+    unsigned acc = incl - sum;
+    if (acc < need && incl >= need) {
+      int j = 0;
+      while (acc + loc[j] < need) acc += loc[j++];
+      sh.key = prefix | ((uint32_t)(8 * tid + j) << shf);
+      sh.need = need - acc;
+    }
+    __syncthreads();
+    prefix = sh.key;
+    need = sh.need;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sh.key = prefix;
+    sh.need = need;
+  }
+  __syncthreads();
+}
+
+constexpr int kC97ListMax = 256;   // chunks a selection gathers into LDS
+
+// Shortlist of the bulk pass: the R largest bulk values of an event (ties
+// to the smaller index), R <= 128, as ascending candidate indices.  The
+// R-th largest chunk maximum tau bounds the R-th largest value from below,
+// so every member lies in a chunk whose maximum is >= tau: all chunks above
+// tau (fewer than R) and, in index order, at most R chunks at tau (they hold
+// the smallest-index candidates at tau).  Those chunks (< 2R) go to LDS and
+// the selection finishes there.  One workgroup per event.
+__global__ __launch_bounds__(kThreads) void k_c97_short(const float* __restrict__ bulk, const float* __restrict__ cmax,
+                                                        Geom g, int R, int32_t* __restrict__ out) {
+  __shared__ C97Sel sh;
+  __shared__ int s_list[kC97ListMax];
+  __shared__ float s_v[kC97ListMax * 32];
+  __shared__ unsigned s_n;
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int nchr = (g.cand[0] + 31) / 32;
+  const int nchk = g.cand[1] * g.cand[2] * nchr;
+  const float* cm = cmax + (long long)f * nchk;
+  const float* bv = bulk + (long long)f * g.ncand;
+  // tau as a descending key: the R-th smallest of ~asc(max)
+  uint32_t tk = 0xFFFFFFFFu;
+  if (nchk > R) {
+    c97_kth_smallest(nchk, R, [&](int i) { return ~c97_asc(cm[i]); }, sh);
+    tk = sh.key;
+  }
+  // ordered compaction of the chunks above tau and the first R at tau
+  unsigned base = 0, eq_base = 0;
+  for (int q0 = 0; q0 < nchk; q0 += kThreads) {
+    const int q = q0 + tid;
+    const uint32_t key = q < nchk ? ~c97_asc(cm[q]) : 0xFFFFFFFFu;
+    const bool above = q < nchk && key < tk, at = q < nchk && key == tk;
+    unsigned eq_tot;
+    const unsigned eq_rank = eq_base + c97_incl_scan(at ? 1u : 0u, sh.w, eq_tot) - (at ? 1u : 0u);
+    const bool take = above || (at && eq_rank < (unsigned)R) || (q < nchk && nchk <= R);
+    unsigned tot;
+    const unsigned pos = base + c97_incl_scan(take ? 1u : 0u, sh.w, tot) - (take ? 1u : 0u);
+    if (take && pos < kC97ListMax) s_list[pos] = q;
+    base += tot;
+    eq_base += eq_tot;
+  }
+  const int nl = (int)min(base, (unsigned)kC97ListMax);
+  for (int i = tid; i < nl * 32; i += kThreads) {
+    const int q = s_list[i >> 5], x = (q % nchr) * 32 + (i & 31);
+    s_v[i] = x < g.cand[0] ? bv[(long long)(q / nchr) * g.cand[0] + x] : -INFINITY;
+  }
+  __syncthreads();
+  c97_kth_smallest(nl * 32, R, [&](int i) { return ~c97_asc(s_v[i]); }, sh);
+  const uint32_t pk = sh.key, pneed = sh.need;
+  // every value above the R-th and, in index order, pneed of those equal
+  unsigned eqb = 0, ob = 0;
+  for (int i0 = 0; i0 < nl * 32; i0 += kThreads) {
+    const int i = i0 + tid;
+    const uint32_t key = i < nl * 32 ? ~c97_asc(s_v[i]) : 0xFFFFFFFFu;
+    const bool at = i < nl * 32 && key == pk;
+    unsigned eq_tot;
+    const unsigned er = eqb + c97_incl_scan(at ? 1u : 0u, sh.w, eq_tot) - (at ? 1u : 0u);
+    const bool take = i < nl * 32 && (key < pk || (at && er < pneed));
+    unsigned tot;
+    const unsigned pos = ob + c97_incl_scan(take ? 1u : 0u, sh.w, tot) - (take ? 1u : 0u);
+    if (take && pos < (unsigned)R) {
+      const int q = s_list[i >> 5];
+      out[(long long)f * R + pos] = (q / nchr) * g.cand[0] + (q % nchr) * 32 + (i & 31);
+    }
+    ob += tot;
+    eqb += eq_tot;
+  }
+  (void)s_n;
+}
+
+// The K best keys of every candidate from the score map and its chunk
+// minima: tau = the K-th smallest chunk minimum bounds the K-th smallest
+// score from above, so the K best lie in chunks whose minimum is <= tau.
+// Their keys go to LDS when they fit (at most kC97ListMax chunks), else the
+// whole row of the map is searched.  One workgroup per event; keys ascending.
+__global__ __launch_bounds__(kThreads) void k_c97_best(const float* __restrict__ map, const float* __restrict__ cmin,
+                                                       Geom g, int k, uint64_t seed, const int32_t* __restrict__ real,
+                                                       const int64_t* __restrict__ steps, uint64_t* __restrict__ out) {
+  __shared__ C97Sel sh;
+  __shared__ TopkShared tsh;
+  __shared__ int s_list[kC97ListMax];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const uint64_t tkey = draw64(seed, kStreamTiebreak, (uint64_t)real[f], (uint64_t)steps[f]);
+  const int nchr = (g.cand[0] + 31) / 32;
+  const int nchk = g.cand[1] * g.cand[2] * nchr;
+  const float* cm = cmin + (long long)f * nchk;
+  const float* m = map + (long long)f * g.ncand;
+  uint32_t tk = 0xFFFFFFFFu;
+  if (nchk > k) {
+    c97_kth_smallest(nchk, k, [&](int i) { return c97_asc(cm[i]); }, sh);
+    tk = sh.key;
+  }
+  unsigned base = 0;
+  for (int q0 = 0; q0 < nchk; q0 += kThreads) {
+    const int q = q0 + tid;
+    const bool take = q < nchk && c97_asc(cm[q]) <= tk;
+    unsigned tot;
+    const unsigned pos = base + c97_incl_scan(take ? 1u : 0u, sh.w, tot) - (take ? 1u : 0u);
+    if (take && pos < kC97ListMax) s_list[pos] = q;
+    base += tot;
+  }
+  if (base <= (unsigned)kC97ListMax) {
+    const int n = (int)base * 32;
+    block_topk(n, k, [&](long long i) {
+      const int q = s_list[i >> 5], x = (q % nchr) * 32 + (int)(i & 31);
+      const int c = (q / nchr) * g.cand[0] + x;
+      // past the row's end: a key above every real one
+      return x < g.cand[0] ? c97_key(m[c], c, tkey) : (~0ull - (uint64_t)i);
+    }, tsh);
+  } else {
+    block_topk(g.ncand, k, [&](long long c) { return c97_key(m[c], (int)c, tkey); }, tsh);
+  }
+  if (tid < k) out[(long long)f * k + tid] = tsh.top[tid];
 }
 
 template <typename OT>
@@ -251,11 +464,12 @@ struct C97BulkArgs {
   const float* K;            // level-J grid
   const int32_t* or_n;       // [event][T_c cells]
   const float* or_m;         // [event][T_c cells]
-  const float* kmax;         // largest |K| (device)
+  const float* kmax;         // kC97MaxParts partial maxima of |K| (device)
   int n_filters;
   int kpad;                  // 2 T_c cells, padded to 16
   int W;                     // strip width: kC97Seg + T_c,x - 1
   float* bulk;               // [event][candidates]: sum n A K - n K^2 / 2
+  float* cmax;               // [event][chunks]: largest bulk value of each chunk
 };
 
 // LDS of a bulk workgroup: both strips (16-byte aligned end), the block
@@ -285,7 +499,9 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
   const int W = a.W, kpad = a.kpad;
   const int nrows = g.tc[1] * g.tc[2];
   const int tcells = (int)g.tcells;
-  const int q = C97Op<OT>::q_of(*a.kmax);
+  float kmax = 0.f;
+  for (int i = 0; i < kC97MaxParts; ++i) kmax = fmaxf(kmax, a.kmax[i]);
+  const int q = C97Op<OT>::q_of(kmax);
   const float down = ldexpf(1.f, -q), tap = -0.5f * ldexpf(1.f, q);
   OT* s_k = (OT*)smem;                       // [nrows][W] K, then [nrows][W] K^2 2^-q
   int* s_off = (int*)(smem + c97_strip_bytes(nrows, W));
@@ -332,12 +548,25 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
       for (int e = 0; e < 8; ++e) kv[e] = s_k[s_off[kc + g8 + e] + cb];
       acc = C97Op<OT>::mma(*(const vec8*)(erow + kc), kv, acc);
     }
-    if (x0 + cb < g.cand[0]) {
+    const bool ok = x0 + cb < g.cand[0];
+    if (ok) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int f = f0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         if (f < a.n_filters) a.bulk[(long long)f * g.ncand + rowbase + cb] = acc[v];
       }
+    }
+    // each event's largest value over the chunk's 32 candidates (the lanes
+    // of a half wavefront)
+    const int nchr = (g.cand[0] + 31) / 32;
+    const long long nchk = (long long)g.cand[1] * g.cand[2] * nchr;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float m = ok ? acc[v] : -INFINITY;
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+      const int f = f0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if (j == 0 && f < a.n_filters) a.cmax[f * nchk + (long long)row * nchr + (x0 >> 5) + ch] = m;
     }
   }
 }

@@ -234,7 +234,7 @@ def test_cdf97_sizes_and_validation(lib):
     assert ws(sh, 2, 1, t, 8, 10, 64, 0, 1) > 0
     assert ws(sh, 2, 2, t, 8, 10, 64, 0, 1) == -1       # precision
     assert ws(sh, 2, 0, t, 8, 10, 4, 0, 1) == -1        # shortlist below top_k
-    assert ws(sh, 2, 0, t, 8, 10, 257, 0, 1) == -1      # shortlist above 256
+    assert ws(sh, 2, 0, t, 8, 10, 129, 0, 1) == -1      # shortlist above 128
     assert ws(sh, 2, 0, t, 8, 17, 0, 0, 1) == -1        # top_k above 16
     assert ws(sh, 2, 0, t, 0, 10, 0, 0, 1) == -1        # no events
     assert ws(sh, 2, 0, t, 8, 10, 0, 0, 0) == -1        # no output
