@@ -4626,7 +4626,7 @@ struct C97Plan {
   int kpad = 0, W = 0, R = 0;
   bool exact = true, want_scores = false, want_keys = false;
   size_t lds = 0;
-  long long ws_cnt = 0, ws_off = 0, ws_val = 0, ws_kmax = 0, ws_map = -1, ws_bulk = -1, ws_short = -1, ws_cext = -1,
+  long long ws_cnt = 0, ws_off = 0, ws_soff = 0, ws_val = 0, ws_kmax = 0, ws_map = -1, ws_bulk = -1, ws_short = -1, ws_cext = -1,
             ws_total = 0;
 };
 
@@ -4636,7 +4636,7 @@ int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tm
   CCW_TRY(geom_ti(g, ti, level));
   if (!tmpl) return fail(CCWSIM_ERR_INVALID_ARG, "null template");
   CCW_TRY(geom_tmpl(g, tmpl));
-  if (n_filters < 1) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters must be >= 1");
+  if (n_filters < 1 || n_filters > (1 << 19)) return fail(CCWSIM_ERR_INVALID_ARG, "n_filters must be in [1, 2^19]");
   if (precision != 0 && precision != 1) return fail(CCWSIM_ERR_INVALID_ARG, "precision must be 0 (fp16) or 1 (bf16)");
   if (!want_scores && !want_keys) return fail(CCWSIM_ERR_INVALID_ARG, "neither scores nor top-K keys requested");
   if (g.tcells > kC97BlocksMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kC97BlocksMax);
@@ -4655,6 +4655,7 @@ int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tm
   long long o = 0;
   p.ws_cnt = o;   o += align256(nf * 4);
   p.ws_off = o;   o += align256(nf * kC97BlocksMax * 4);
+  p.ws_soff = o;  o += align256(nf * kC97BlocksMax * 4);
   p.ws_val = o;   o += align256(nf * kC97BlocksMax * 4);
   const long long nchk = (long long)g.cand[1] * g.cand[2] * ((g.cand[0] + 31) / 32);
   if (want_keys && p.exact && !scores_given) {
@@ -4738,16 +4739,18 @@ extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precisi
   int32_t* cnt = (int32_t*)(ws + p.ws_cnt);
   int32_t* off = (int32_t*)(ws + p.ws_off);
   float* val = (float*)(ws + p.ws_val);
+  const int sw = c97_map_width(g);
+  int32_t* soff = (int32_t*)(ws + p.ws_soff);
   k_c97_pack<<<(unsigned)((n_filters + kThreads / 64 - 1) / (kThreads / 64)), kThreads, 0, st>>>(
-      or_n, or_m, n_filters, g, cnt, off, val);
-  const unsigned nseg = (unsigned)((g.cand[0] + kThreads - 1) / kThreads);
-  const dim3 mgrid(nseg * (unsigned)(g.cand[1] * g.cand[2]), (unsigned)n_filters);
+      or_n, or_m, n_filters, g, sw + g.tc[0] - 1, cnt, off, soff, val);
+  const unsigned nseg = (unsigned)((g.cand[0] + sw - 1) / sw);
+  const dim3 mgrid(nseg * (unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + kC97MapEvents - 1) / kC97MapEvents));
   float* cext = topk_keys ? (float*)(ws + p.ws_cext) : nullptr;
-  if (scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, scores, p.exact ? cext : nullptr);
+  if (scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, sw, cnt, soff, val, n_filters, scores, p.exact ? cext : nullptr);
   if (topk_keys) {
     if (p.exact) {
       float* map = scores ? scores : (float*)(ws + p.ws_map);
-      if (!scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, cnt, off, val, map, cext);
+      if (!scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, sw, cnt, soff, val, n_filters, map, cext);
       k_c97_best<<<(unsigned)n_filters, kThreads, 0, st>>>(map, cext, g, top_k, seed, realization, step, topk_keys);
     } else {
       float* kmax = (float*)(ws + p.ws_kmax);
@@ -4758,8 +4761,9 @@ extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precisi
       C97BulkArgs a = {};
       a.g = g;
       a.K = approx;
-      a.or_n = or_n;
-      a.or_m = or_m;
+      a.cnt = cnt;
+      a.blk = off;
+      a.val = val;
       a.kmax = kmax;
       a.n_filters = n_filters;
       a.kpad = p.kpad;

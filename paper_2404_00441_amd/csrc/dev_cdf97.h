@@ -126,12 +126,21 @@ __global__ __launch_bounds__(kThreads) void k_c97_inv(const float* __restrict__ 
 // Scores
 // ---------------------------------------------------------------------------
 
-// Per event: its known blocks in template order as (offset of block b from a
-// candidate's base cell in the K grid, A_b), and their count.  One
-// wavefront per event; blocks are compacted 64 at a time by ballot.
+// Offset of template block b from a candidate's base cell in a box of
+// row length e0 and e1 rows per plane.
+__device__ __forceinline__ int c97_block_off(int b, const Geom& g, int e0, int e1) {
+  const int bx = b % g.tc[0], by = (b / g.tc[0]) % g.tc[1], bz = b / (g.tc[0] * g.tc[1]);
+  return bx + e0 * (by + e1 * bz);
+}
+
+// Per event: its known blocks in template order as (block index b, offset
+// of the block in the score map's LDS strip of row length wmap, A_b), and
+// their count.  One wavefront per event; blocks are compacted 64 at a
+// time by ballot.
 __global__ __launch_bounds__(kThreads) void k_c97_pack(const int32_t* __restrict__ or_n, const float* __restrict__ or_m,
-                                                       int n_filters, Geom g, int32_t* __restrict__ cnt,
-                                                       int32_t* __restrict__ off, float* __restrict__ val) {
+                                                       int n_filters, Geom g, int wmap, int32_t* __restrict__ cnt,
+                                                       int32_t* __restrict__ off, int32_t* __restrict__ soff,
+                                                       float* __restrict__ val) {
   const int lane = threadIdx.x & 63;
   const int f = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (f >= n_filters) return;
@@ -142,8 +151,8 @@ __global__ __launch_bounds__(kThreads) void k_c97_pack(const int32_t* __restrict
     const uint64_t m = __ballot(known);
     if (known) {
       const int pos = c + __popcll(m & ((1ull << lane) - 1ull));
-      const int bx = b % g.tc[0], by = (b / g.tc[0]) % g.tc[1], bz = b / (g.tc[0] * g.tc[1]);
-      off[(long long)f * kC97BlocksMax + pos] = idx3i(bx, by, bz, g.G);
+      off[(long long)f * kC97BlocksMax + pos] = b;
+      soff[(long long)f * kC97BlocksMax + pos] = c97_block_off(b, g, wmap, g.tc[1]);
       val[(long long)f * kC97BlocksMax + pos] = or_m[(long long)f * g.tcells + b];
     }
     c += __popcll(m);
@@ -158,9 +167,10 @@ __device__ __forceinline__ int c97_base(int c, const Geom& g) {
 }
 
 // S(c) in fp32, in the event's block order: the one routine behind the score
-// map and the rescoring, so both give the same value for a candidate.
-__device__ __forceinline__ float c97_score(const float* __restrict__ K, int base, const int* off, const float* A,
-                                           int nk) {
+// map and the rescoring, so both give the same value for a candidate (K
+// read from the grid or from an LDS copy of it).
+template <typename OffP, typename ValP>
+__device__ __forceinline__ float c97_score(const float* K, int base, OffP off, ValP A, int nk) {
   float s = 0.f;
   for (int i = 0; i < nk; ++i) {
     const float d = K[base + off[i]] - A[i];
@@ -188,36 +198,78 @@ __device__ __forceinline__ uint32_t c97_asc(float f) {
 // leave each chunk's best value (smallest score, largest bulk value) for
 // the selections below.
 
-// The score map: grid (candidate rows x row segments of 256 candidates,
-// events).  Optionally the smallest score of each chunk.
-__global__ __launch_bounds__(kThreads) void k_c97_map(const float* __restrict__ K, Geom g, const int32_t* __restrict__ cnt,
-                                                      const int32_t* __restrict__ off, const float* __restrict__ val,
-                                                      float* __restrict__ out, float* __restrict__ cmin) {
-  __shared__ int s_off[kC97BlocksMax];
-  __shared__ float s_val[kC97BlocksMax];
-  const int nseg = (g.cand[0] + kThreads - 1) / kThreads;
-  const int f = blockIdx.y, row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg, tid = threadIdx.x;
-  const int nk = cnt[f];
-  for (int i = tid; i < nk; i += kThreads) {
-    s_off[i] = off[(long long)f * kC97BlocksMax + i];
-    s_val[i] = val[(long long)f * kC97BlocksMax + i];
-  }
-  __syncthreads();
-  const int x = seg * kThreads + tid;
-  const bool ok = x < g.cand[0];
-  const int c = row * g.cand[0] + x;
-  float S = INFINITY;
-  if (ok) {
-    S = c97_score(K, c97_base(c, g), s_off, s_val, nk);
-    out[(long long)f * g.ncand + c] = S;
-  }
-  if (cmin) {
-    float m = S;
+// Stage the K values a candidate row segment reaches: strip entry i =
+// (x, r) of W x (T_c,y T_c,z) holds K[x0 + x, cy + by, cz + bz] with r = by
+// + T_c,y bz (0 past the grid's x end), passed to store(i, value).  Every
+// load of a thread goes out before its stores.
+template <class Store>
+__device__ __forceinline__ void c97_stage(const float* __restrict__ K, const Geom& g, int x0, int cy, int cz, int W,
+                                          Store store) {
+  constexpr int U = 8;
+  const int n = g.tc[1] * g.tc[2] * W;
+  BoxWalk w(threadIdx.x, kThreads, W, g.tc[1]);
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * kThreads) {
+    float v[U];
 #pragma unroll
-    for (int o = 1; o < 32; o <<= 1) m = fminf(m, __shfl_xor(m, o));
-    const int nchr = (g.cand[0] + 31) / 32;
-    if ((tid & 31) == 0 && x < g.cand[0])
-      cmin[(long long)f * g.cand[1] * g.cand[2] * nchr + (long long)row * nchr + x / 32] = m;
+    for (int u = 0; u < U; ++u) {
+      // positions past the strip read a clamped cell and are not stored
+      const int x = x0 + w.x;
+      const int y = min(cy + w.y, g.G[1] - 1), z = min(cz + w.z, g.G[2] - 1);
+      v[u] = K[idx3i(min(x, g.G[0] - 1), y, z, g.G)];
+      v[u] = x < g.G[0] ? v[u] : 0.f;
+      w.next();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * kThreads < n) store(i0 + u * kThreads, v[u]);
+  }
+}
+
+// The score map.  Workgroup: one segment of sw candidates of a candidate
+// row (grid x = row * segments + segment) against up to kC97MapEvents
+// events (grid y); the K values the segment reaches (T_c,y x T_c,z grid rows
+// of sw + T_c,x - 1 cells) are staged once in LDS and serve every event.
+// Optionally the smallest score of each chunk.
+constexpr int kC97MapEvents = 8;
+constexpr int kC97MapLds = 32 * 1024;
+// Segment width: a multiple of 32 (<= 256) whose strip fits kC97MapLds.
+inline int c97_map_width(const Geom& g) {
+  const int nrows = g.tc[1] * g.tc[2];
+  int sw = (kC97MapLds / (4 * nrows) - (g.tc[0] - 1)) / 32 * 32;
+  return sw < 32 ? 32 : sw > 256 ? 256 : sw;
+}
+__global__ __launch_bounds__(kThreads) void k_c97_map(const float* __restrict__ K, Geom g, int sw,
+                                                      const int32_t* __restrict__ cnt, const int32_t* __restrict__ soff,
+                                                      const float* __restrict__ val, int n_filters,
+                                                      float* __restrict__ out, float* __restrict__ cmin) {
+  __shared__ float s_k[kC97MapLds / 4];
+  const int nseg = (g.cand[0] + sw - 1) / sw;
+  const int row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg, tid = threadIdx.x;
+  const int cy = row % g.cand[1], cz = row / g.cand[1];
+  const int W = sw + g.tc[0] - 1, nrows = g.tc[1] * g.tc[2];
+  const int x0 = seg * sw;
+  c97_stage(K, g, x0, cy, cz, W, [&](int i, float v) { s_k[i] = v; });
+  __syncthreads();
+  const int x = x0 + tid;
+  const bool ok = tid < sw && x < g.cand[0];
+  const int c = row * g.cand[0] + x;
+  const int nchr = (g.cand[0] + 31) / 32;
+  const long long nchk = (long long)g.cand[1] * g.cand[2] * nchr;
+  const int f1 = min(n_filters, (int)(blockIdx.y + 1) * kC97MapEvents);
+  for (int f = blockIdx.y * kC97MapEvents; f < f1; ++f) {
+    // the event's list is the same for every lane: scalar loads
+    const int nk = cnt[f];
+    float S = INFINITY;
+    if (ok) {
+      S = c97_score(s_k, tid, soff + (long long)f * kC97BlocksMax, val + (long long)f * kC97BlocksMax, nk);
+      out[(long long)f * g.ncand + c] = S;
+    }
+    if (cmin) {
+      float m = S;
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) m = fminf(m, __shfl_xor(m, o));
+      if ((tid & 31) == 0 && ok) cmin[f * nchk + (long long)row * nchr + x / 32] = m;
+    }
   }
 }
 
@@ -462,8 +514,9 @@ __device__ __forceinline__ OT c97_op(float v) {
 struct C97BulkArgs {
   Geom g;
   const float* K;            // level-J grid
-  const int32_t* or_n;       // [event][T_c cells]
-  const float* or_m;         // [event][T_c cells]
+  const int32_t* cnt;        // [event] known blocks
+  const int32_t* blk;        // [event][kC97BlocksMax] their template block indices
+  const float* val;          // [event][kC97BlocksMax] their A values
   const float* kmax;         // kC97MaxParts partial maxima of |K| (device)
   int n_filters;
   int kpad;                  // 2 T_c cells, padded to 16
@@ -507,32 +560,92 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
   int* s_off = (int*)(smem + c97_strip_bytes(nrows, W));
   OT* s_b = (OT*)(smem + c97_strip_bytes(nrows, W) + (size_t)kpad * 4);
   const int bstride = kpad + 8;
-  for (int i = tid; i < nrows * W; i += kThreads) {
-    const int x = x0 + i % W, r = i / W;
-    const int by = r % g.tc[1], bz = r / g.tc[1];
-    float v = 0.f;
-    if (x < g.G[0]) v = a.K[idx3i(x, cy + by, cz + bz, g.G)];
+  c97_stage(a.K, g, x0, cy, cz, W, [&](int i, float v) {
     s_k[i] = c97_op<OT>(v);
     s_k[nrows * W + i] = c97_op<OT>(v * v * down);
+  });
+  // the blocks known to any of the tile's events, ascending: the
+  // contraction runs over those only (2 nu taps, padded to 16)
+  __shared__ int s_u[kC97BlocksMax], s_bl[kC97BlocksMax], s_cnt[32];
+  __shared__ int s_nu, s_mc;
+  for (int b = tid; b < tcells; b += kThreads) s_u[b] = 0;
+  if (tid < 64) {
+    const int c = tid < 32 && f0 + tid < a.n_filters ? a.cnt[f0 + tid] : 0;
+    if (tid < 32) s_cnt[tid] = c;
+    int m = c;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) m = max(m, __shfl_xor(m, o));
+    if (tid == 0) s_mc = m;
   }
-  for (int k = tid; k < kpad; k += kThreads) {
-    const int b = k < tcells ? k : k - tcells;
+  __syncthreads();
+  // slots (event jf, list entry e) of the tile, e < the tile's longest list
+  const int fl = a.n_filters - 1, mc = max(s_mc, 1), nslot = 32 * mc;
+  constexpr int U = 8;
+  for (int i0 = tid; i0 < nslot; i0 += U * kThreads) {
+    int bb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(i0 + u * kThreads, nslot - 1), jf = i / mc;
+      bb[u] = a.blk[(long long)min(f0 + jf, fl) * kC97BlocksMax + (i - jf * mc)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kThreads, jf = i / mc;
+      if (i < nslot && i - jf * mc < s_cnt[jf]) s_u[bb[u]] = 1;
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    int c = 0;
+    for (int b0 = 0; b0 < tcells; b0 += 64) {
+      const int b = b0 + lane;
+      const bool u = b < tcells && s_u[b] != 0;
+      const uint64_t m = __ballot(u);
+      if (u) {
+        const int pos = c + __popcll(m & ((1ull << lane) - 1ull));
+        s_bl[pos] = b;
+        s_u[b] = pos;   // from here on: the block's position in the list
+      }
+      c += __popcll(m);
+    }
+    if (lane == 0) s_nu = c;
+  }
+  __syncthreads();
+  const int nu = s_nu, kp = (2 * nu + 15) / 16 * 16;
+  for (int k = tid; k < kp; k += kThreads) {
     int o = 0;
-    if (k < 2 * tcells) {
+    if (k < 2 * nu) {
+      const int b = s_bl[k < nu ? k : k - nu];
       const int bx = b % g.tc[0], by = (b / g.tc[0]) % g.tc[1], bz = b / (g.tc[0] * g.tc[1]);
-      o = (bz * g.tc[1] + by) * W + bx + (k < tcells ? 0 : nrows * W);
+      o = (bz * g.tc[1] + by) * W + bx + (k < nu ? 0 : nrows * W);
     }
     s_off[k] = o;
   }
-  for (int i = tid; i < 32 * kpad; i += kThreads) {
-    const int jf = i / kpad, k = i - jf * kpad, f = f0 + jf;
-    float v = 0.f;
-    if (f < a.n_filters && k < 2 * tcells) {
-      const int b = k < tcells ? k : k - tcells;
-      const bool known = a.or_n[(long long)f * tcells + b] != 0;
-      v = !known ? 0.f : k < tcells ? a.or_m[(long long)f * tcells + b] : tap;
+  for (int i = tid; i < 32 * kp; i += kThreads) {
+    const int jf = i / kp;
+    s_b[jf * bstride + (i - jf * kp)] = (OT)0.0f;
+  }
+  __syncthreads();
+  const OT tap_op = c97_op<OT>(tap);
+  for (int i0 = tid; i0 < nslot; i0 += U * kThreads) {
+    int bb[U];
+    float vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(i0 + u * kThreads, nslot - 1), jf = i / mc;
+      const long long o = (long long)min(f0 + jf, fl) * kC97BlocksMax + (i - jf * mc);
+      bb[u] = a.blk[o];
+      vv[u] = a.val[o];
     }
-    s_b[jf * bstride + k] = c97_op<OT>(v);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kThreads, jf = i / mc;
+      if (i < nslot && i - jf * mc < s_cnt[jf]) {
+        const int pos = s_u[bb[u]];
+        s_b[jf * bstride + pos] = c97_op<OT>(vv[u]);
+        s_b[jf * bstride + nu + pos] = tap_op;
+      }
+    }
   }
   __syncthreads();
   const int nchunks = min(kC97Seg, g.cand[0] - x0 + 31) / 32;
@@ -542,7 +655,7 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
   for (int ch = wave; ch < nchunks; ch += kThreads / 64) {
     const int cb = ch * 32 + j;
     float16_t acc = {};
-    for (int kc = 0; kc < kpad; kc += 16) {
+    for (int kc = 0; kc < kp; kc += 16) {
       vec8 kv;
 #pragma unroll
       for (int e = 0; e < 8; ++e) kv[e] = s_k[s_off[kc + g8 + e] + cb];
@@ -587,7 +700,7 @@ __global__ __launch_bounds__(kThreads) void k_c97_rescore(const float* __restric
   const int f = blockIdx.x, tid = threadIdx.x;
   const int nk = cnt[f];
   for (int i = tid; i < nk; i += kThreads) {
-    s_off[i] = off[(long long)f * kC97BlocksMax + i];
+    s_off[i] = c97_block_off(off[(long long)f * kC97BlocksMax + i], g, g.G[0], g.G[1]);
     s_val[i] = val[(long long)f * kC97BlocksMax + i];
   }
   __syncthreads();

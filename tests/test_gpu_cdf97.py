@@ -262,9 +262,10 @@ def test_scan97_bulk_shortlist(cc, case, precision):
     k, R, seed = 10, 64, 9
     real = torch.arange(n_ev, dtype=torch.int32, device="cuda")
     step = torch.zeros((n_ev,), dtype=torch.int64, device="cuda")
-    _, keys, sl = cc.ccf_scan97(ext, level, _dev(K, np.float32), T[::-1], _dev(n.reshape(n_ev, -1), np.int32),
+    S, keys, sl = cc.ccf_scan97(ext, level, _dev(K, np.float32), T[::-1], _dev(n.reshape(n_ev, -1), np.int32),
                                 _dev(A.reshape(n_ev, -1), np.float32), top_k=k, shortlist=R, precision=precision,
-                                seed=seed, realization=real, step=step, want_shortlist=True)
+                                seed=seed, realization=real, step=step, want_shortlist=True, want_scores=True)
+    S = S.cpu().numpy()
     keys = keys.cpu().numpy()
     sl = sl.cpu().numpy()
     want = _oracle_scores(K, cand, n, A)
@@ -280,6 +281,8 @@ def test_scan97_bulk_shortlist(cc, case, precision):
         tab = _perm_table(ncand, seed, e, 0)
         S_got, idx = _decode(keys[e], tab)
         _check_topk(S_got, idx, want[e], k, allowed=s)
+        # the rescored fp32 score is the map's value, bit for bit
+        assert np.array_equal(S_got.astype(np.float32), S[e][idx])
         agree.append(len(set(idx.tolist()) & set(c97.topk97(want[e], k).tolist())) / k)
     _say(f"  top-{k} agreement with the float64 oracle: mean {np.mean(agree):.3f}, min {np.min(agree):.2f}")
 
