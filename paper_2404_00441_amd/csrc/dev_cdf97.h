@@ -366,6 +366,47 @@ __device__ void c97_kth_smallest(int n, int k, KeyFn key_at, C97Sel& sh) {
   __syncthreads();
 }
 
+// Ordered compaction: of n items with 32-bit keys keyf(i), every key below
+// tk and, in index order, the first lim keys equal to tk; emit(i, pos) for
+// each in index order (pos = 0, 1, ...).  Rounds of 8 consecutive items per
+// thread, two workgroup prefix sums per round.  Returns how many were taken.
+// Every thread must call it; LDS that emit writes is visible to the whole
+// workgroup on return (closing barrier).
+template <class KeyF, class Emit>
+__device__ unsigned c97_take_ordered(int n, uint32_t tk, unsigned lim, KeyF keyf, Emit emit, unsigned* s_w) {
+  unsigned base = 0, eqb = 0;
+  for (int r0 = 0; r0 < n; r0 += 8 * kThreads) {
+    const int i0 = r0 + 8 * (int)threadIdx.x;
+    uint32_t key[8];
+    unsigned neq = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      key[e] = i0 + e < n ? keyf(i0 + e) : 0u;
+      neq += (i0 + e < n && key[e] == tk) ? 1u : 0u;
+    }
+    unsigned eq_tot;
+    unsigned er = eqb + c97_incl_scan(neq, s_w, eq_tot) - neq;
+    bool take[8];
+    unsigned nt = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool in = i0 + e < n, at = in && key[e] == tk;
+      take[e] = in && (key[e] < tk || (at && er < lim));
+      er += at ? 1u : 0u;
+      nt += take[e] ? 1u : 0u;
+    }
+    unsigned tot;
+    unsigned pos = base + c97_incl_scan(nt, s_w, tot) - nt;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (take[e]) emit(i0 + e, pos++);
+    base += tot;
+    eqb += eq_tot;
+  }
+  __syncthreads();
+  return base;
+}
+
 constexpr int kC97ListMax = 256;   // chunks a selection gathers into LDS
 
 // Shortlist of the bulk pass: the R largest bulk values of an event (ties
@@ -380,7 +421,6 @@ __global__ __launch_bounds__(kThreads) void k_c97_short(const float* __restrict_
   __shared__ C97Sel sh;
   __shared__ int s_list[kC97ListMax];
   __shared__ float s_v[kC97ListMax * 32];
-  __shared__ unsigned s_n;
   const int f = blockIdx.x, tid = threadIdx.x;
   const int nchr = (g.cand[0] + 31) / 32;
   const int nchk = g.cand[1] * g.cand[2] * nchr;
@@ -392,21 +432,13 @@ __global__ __launch_bounds__(kThreads) void k_c97_short(const float* __restrict_
     c97_kth_smallest(nchk, R, [&](int i) { return ~c97_asc(cm[i]); }, sh);
     tk = sh.key;
   }
-  // ordered compaction of the chunks above tau and the first R at tau
-  unsigned base = 0, eq_base = 0;
-  for (int q0 = 0; q0 < nchk; q0 += kThreads) {
-    const int q = q0 + tid;
-    const uint32_t key = q < nchk ? ~c97_asc(cm[q]) : 0xFFFFFFFFu;
-    const bool above = q < nchk && key < tk, at = q < nchk && key == tk;
-    unsigned eq_tot;
-    const unsigned eq_rank = eq_base + c97_incl_scan(at ? 1u : 0u, sh.w, eq_tot) - (at ? 1u : 0u);
-    const bool take = above || (at && eq_rank < (unsigned)R) || (q < nchk && nchk <= R);
-    unsigned tot;
-    const unsigned pos = base + c97_incl_scan(take ? 1u : 0u, sh.w, tot) - (take ? 1u : 0u);
-    if (take && pos < kC97ListMax) s_list[pos] = q;
-    base += tot;
-    eq_base += eq_tot;
-  }
+  // ordered compaction of the chunks above tau and the first R at tau (all
+  // of them when there are no more than R)
+  const unsigned base = c97_take_ordered(nchk, tk, (unsigned)R, [&](int q) { return ~c97_asc(cm[q]); },
+                                         [&](int q, unsigned pos) {
+                                           if (pos < kC97ListMax) s_list[pos] = q;
+                                         },
+                                         sh.w);
   const int nl = (int)min(base, (unsigned)kC97ListMax);
   for (int i = tid; i < nl * 32; i += kThreads) {
     const int q = s_list[i >> 5], x = (q % nchr) * 32 + (i & 31);
@@ -416,24 +448,14 @@ __global__ __launch_bounds__(kThreads) void k_c97_short(const float* __restrict_
   c97_kth_smallest(nl * 32, R, [&](int i) { return ~c97_asc(s_v[i]); }, sh);
   const uint32_t pk = sh.key, pneed = sh.need;
   // every value above the R-th and, in index order, pneed of those equal
-  unsigned eqb = 0, ob = 0;
-  for (int i0 = 0; i0 < nl * 32; i0 += kThreads) {
-    const int i = i0 + tid;
-    const uint32_t key = i < nl * 32 ? ~c97_asc(s_v[i]) : 0xFFFFFFFFu;
-    const bool at = i < nl * 32 && key == pk;
-    unsigned eq_tot;
-    const unsigned er = eqb + c97_incl_scan(at ? 1u : 0u, sh.w, eq_tot) - (at ? 1u : 0u);
-    const bool take = i < nl * 32 && (key < pk || (at && er < pneed));
-    unsigned tot;
-    const unsigned pos = ob + c97_incl_scan(take ? 1u : 0u, sh.w, tot) - (take ? 1u : 0u);
-    if (take && pos < (unsigned)R) {
-      const int q = s_list[i >> 5];
-      out[(long long)f * R + pos] = (q / nchr) * g.cand[0] + (q % nchr) * 32 + (i & 31);
-    }
-    ob += tot;
-    eqb += eq_tot;
-  }
-  (void)s_n;
+  c97_take_ordered(nl * 32, pk, pneed, [&](int i) { return ~c97_asc(s_v[i]); },
+                   [&](int i, unsigned pos) {
+                     if (pos < (unsigned)R) {
+                       const int q = s_list[i >> 5];
+                       out[(long long)f * R + pos] = (q / nchr) * g.cand[0] + (q % nchr) * 32 + (i & 31);
+                     }
+                   },
+                   sh.w);
 }
 
 // The K best keys of every candidate from the score map and its chunk
@@ -458,15 +480,11 @@ __global__ __launch_bounds__(kThreads) void k_c97_best(const float* __restrict__
     c97_kth_smallest(nchk, k, [&](int i) { return c97_asc(cm[i]); }, sh);
     tk = sh.key;
   }
-  unsigned base = 0;
-  for (int q0 = 0; q0 < nchk; q0 += kThreads) {
-    const int q = q0 + tid;
-    const bool take = q < nchk && c97_asc(cm[q]) <= tk;
-    unsigned tot;
-    const unsigned pos = base + c97_incl_scan(take ? 1u : 0u, sh.w, tot) - (take ? 1u : 0u);
-    if (take && pos < kC97ListMax) s_list[pos] = q;
-    base += tot;
-  }
+  const unsigned base = c97_take_ordered(nchk, tk, 0xFFFFFFFFu, [&](int q) { return c97_asc(cm[q]); },
+                                         [&](int q, unsigned pos) {
+                                           if (pos < kC97ListMax) s_list[pos] = q;
+                                         },
+                                         sh.w);
   if (base <= (unsigned)kC97ListMax) {
     const int n = (int)base * 32;
     block_topk(n, k, [&](long long i) {
