@@ -292,7 +292,7 @@ LP_HELDOUT_SEED = 2001
 LP_EPOCHS, LP_BATCH, LP_LR = 6, 512, 2e-3
 LP_LISTS = 512
 # (lists probed, gate): None lets every proposal stand
-LP_POINTS = ((8, None), (12, None), (16, None), (8, 0.2), (8, 0.15), (8, 0.12))
+LP_POINTS = ((8, None), (10, None), (12, None), (16, None), (8, 0.2), (8, 0.15), (8, 0.12))
 LP_EVAL_SEEDS = (1, 2, 3)                    # each form simulated with each seed; errors pooled
 
 
