@@ -57,7 +57,8 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).cuda()
 
 
-DWT_CASES = [((56, 64), 1), ((70, 90), 2), ((50, 37), 3), ((12, 18, 20), 2), ((8, 8), 2), ((128, 128), 2)]
+DWT_CASES = [((56, 64), 1), ((70, 90), 2), ((50, 37), 3), ((12, 18, 20), 2), ((8, 8), 2), ((128, 128), 2),
+             ((9, 11), 0)]
 
 
 @pytest.mark.parametrize("shape,level", DWT_CASES, ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in DWT_CASES])
@@ -81,7 +82,10 @@ def test_dwt97_matches_oracle(cc, shape, level):
     assert off == d.size
 
 
-@pytest.mark.parametrize("shape,level", DWT_CASES[:4], ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in DWT_CASES[:4]])
+IDWT_CASES = DWT_CASES[:4] + [DWT_CASES[-1]]
+
+
+@pytest.mark.parametrize("shape,level", IDWT_CASES, ids=[f"{'x'.join(map(str, s))}_J{j}" for s, j in IDWT_CASES])
 def test_idwt97_reconstructs(cc, shape, level):
     _say("idwt97", shape, level)
     x = _img(shape, 4)
@@ -152,7 +156,8 @@ def _oracle_scores(K, cand, n, A):
 SCAN_CASES = [((100, 120), (90, 90), 2, (24, 24), 37),
               ((64, 80), (64, 64), 1, (16, 16), 33),
               ((120, 128), (100, 100), 2, (48, 48), 40),
-              ((20, 36, 40), (20, 30, 30), 2, (8, 12, 12), 9)]
+              ((20, 36, 40), (20, 30, 30), 2, (8, 12, 12), 9),
+              ((30, 41), (30, 30), 0, (6, 8), 35)]
 SCAN_IDS = [f"{'x'.join(map(str, c[0]))}_J{c[2]}_T{c[3][-1]}" for c in SCAN_CASES]
 
 
