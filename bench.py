@@ -56,6 +56,8 @@ def parse():
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     ap.add_argument("--cdf97-only", action="store_true",
                     help="print only the CDF 9/7 measurements (transform, exact and split selection)")
+    ap.add_argument("--lp-epochs", type=int, default=None,
+                    help="training epochs of the learned proposer (default: the built-in schedule)")
     ap.add_argument("--learned-only", action="store_true",
                     help="only the learned proposer's measurement (training, offline metrics, gate sweep)")
     ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
@@ -296,7 +298,7 @@ LP_POINTS = ((8, None), (10, None), (12, None), (16, None), (8, 0.2), (8, 0.15),
 LP_EVAL_SEEDS = (1, 2, 3)                    # each form simulated with each seed; errors pooled
 
 
-def measure_learned(cc, wl, dev, reps=3):
+def measure_learned(cc, wl, dev, reps=3, epochs=None):
     """C5 with the learned convolutional proposer against the plain form on
     the same GPU.  Training pairs: the data events of plain simulations of
     the C5 workload with other seeds and their exact-best candidates; a
@@ -322,7 +324,8 @@ def measure_learned(cc, wl, dev, reps=3):
     t_pairs = time.perf_counter() - t0
     von, vom, vlab, vbest, vsb, vnk = learn.training_pairs(dict(p, n_real=2), ti_d, [LP_HELDOUT_SEED])
     t0 = time.perf_counter()
-    w, hist = learn.train(p, approx, on, om, lab, epochs=LP_EPOCHS, batch=LP_BATCH, lr=LP_LR, seed=7)
+    epochs = epochs or LP_EPOCHS
+    w, hist = learn.train(p, approx, on, om, lab, epochs=epochs, batch=LP_BATCH, lr=LP_LR, seed=7)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     ev = learn.evaluate(p, w, approx, von, vom, vlab, vbest, vsb, vnk)
@@ -354,7 +357,7 @@ def measure_learned(cc, wl, dev, reps=3):
     res = {"workload": wl.describe(p), "training": {
         "pairs": int(on.shape[0]), "pair_seeds": list(LP_TRAIN_SEEDS), "pairs_s": t_pairs,
         "labels_per_pair": int(lab.shape[1]),
-        "epochs": LP_EPOCHS, "batch": LP_BATCH, "lr": LP_LR, "train_s": t_train,
+        "epochs": epochs, "batch": LP_BATCH, "lr": LP_LR, "train_s": t_train,
         "loss_per_epoch": hist, "index_lists": LP_LISTS, "index_s": t_index},
         "heldout": dict(ev, seed=LP_HELDOUT_SEED),
         "eval_seeds": list(LP_EVAL_SEEDS),
@@ -642,7 +645,7 @@ def main():
     from paper_2404_00441_amd import workloads as wl
 
     if a.learned_only:
-        print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"))}), flush=True)
+        print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"), epochs=a.lp_epochs)}), flush=True)
         return
     if a.cdf97_only:
         print(json.dumps({"cdf97": measure_cdf97(cc, wl, torch.device("cuda:0"))}), flush=True)
