@@ -4623,7 +4623,7 @@ int launch_idwt97(const Geom& g, const float* approx, const float* details, floa
 
 struct C97Plan {
   Geom g;
-  int kpad = 0, W = 0, R = 0;
+  int kpad = 0, W = 0, R = 0, seg = kC97Seg;
   bool exact = true, want_scores = false, want_keys = false;
   size_t lds = 0;
   long long ws_cnt = 0, ws_off = 0, ws_soff = 0, ws_val = 0, ws_kmax = 0, ws_map = -1, ws_bulk = -1, ws_short = -1, ws_cext = -1,
@@ -4640,6 +4640,9 @@ int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tm
   if (precision != 0 && precision != 1) return fail(CCWSIM_ERR_INVALID_ARG, "precision must be 0 (fp16) or 1 (bf16)");
   if (!want_scores && !want_keys) return fail(CCWSIM_ERR_INVALID_ARG, "neither scores nor top-K keys requested");
   if (g.tcells > kC97BlocksMax) return fail(CCWSIM_ERR_UNSUPPORTED, "template has %lld blocks (> %d)", g.tcells, kC97BlocksMax);
+  if (c97_map_width(g) == 0)
+    return fail(CCWSIM_ERR_UNSUPPORTED, "template of %d block rows of %d blocks is too tall for the score map's strip",
+                g.tc[1] * g.tc[2], g.tc[0]);
   p.want_scores = want_scores;
   p.want_keys = want_keys;
   if (want_keys) {
@@ -4667,7 +4670,9 @@ int c97_plan(ccwsim_shape ti, int32_t level, int32_t precision, const int32_t tm
   if (want_keys && !p.exact) {
     const int nrows = g.tc[1] * g.tc[2];
     p.kpad = (int)((2 * g.tcells + 15) / 16 * 16);
-    p.W = kC97Seg + g.tc[0] - 1;
+    // the widest row segment whose strips fit the LDS
+    for (p.seg = kC97Seg; p.seg > 32 && c97_bulk_lds(nrows, p.seg + g.tc[0] - 1, p.kpad) > 64 * 1024; p.seg -= 32) {}
+    p.W = p.seg + g.tc[0] - 1;
     p.lds = c97_bulk_lds(nrows, p.W, p.kpad);
     if (p.lds > 64 * 1024) return fail(CCWSIM_ERR_UNSUPPORTED, "bulk scan needs %zu bytes of LDS", p.lds);
     p.ws_kmax = o;  o += align256(kC97MaxParts * 4);
@@ -4740,17 +4745,18 @@ extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precisi
   int32_t* off = (int32_t*)(ws + p.ws_off);
   float* val = (float*)(ws + p.ws_val);
   const int sw = c97_map_width(g);
+  const size_t mlds = c97_map_lds(sw, g);
   int32_t* soff = (int32_t*)(ws + p.ws_soff);
   k_c97_pack<<<(unsigned)((n_filters + kThreads / 64 - 1) / (kThreads / 64)), kThreads, 0, st>>>(
-      or_n, or_m, n_filters, g, sw + g.tc[0] - 1, cnt, off, soff, val);
+      or_n, or_m, n_filters, g, c97_map_wc(sw, g), cnt, off, soff, val);
   const unsigned nseg = (unsigned)((g.cand[0] + sw - 1) / sw);
   const dim3 mgrid(nseg * (unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + kC97MapEvents - 1) / kC97MapEvents));
   float* cext = topk_keys ? (float*)(ws + p.ws_cext) : nullptr;
-  if (scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, sw, cnt, soff, val, n_filters, scores, p.exact ? cext : nullptr);
+  if (scores) k_c97_map<<<mgrid, kThreads, mlds, st>>>(approx, g, sw, cnt, soff, val, n_filters, scores, p.exact ? cext : nullptr);
   if (topk_keys) {
     if (p.exact) {
       float* map = scores ? scores : (float*)(ws + p.ws_map);
-      if (!scores) k_c97_map<<<mgrid, kThreads, 0, st>>>(approx, g, sw, cnt, soff, val, n_filters, map, cext);
+      if (!scores) k_c97_map<<<mgrid, kThreads, mlds, st>>>(approx, g, sw, cnt, soff, val, n_filters, map, cext);
       k_c97_best<<<(unsigned)n_filters, kThreads, 0, st>>>(map, cext, g, top_k, seed, realization, step, topk_keys);
     } else {
       float* kmax = (float*)(ws + p.ws_kmax);
@@ -4767,11 +4773,12 @@ extern "C" int ccwsim_ccf_scan97(ccwsim_shape ti, int32_t level, int32_t precisi
       a.kmax = kmax;
       a.n_filters = n_filters;
       a.kpad = p.kpad;
+      a.seg = p.seg;
       a.W = p.W;
       a.bulk = bulk;
       a.cmax = cext;
       const dim3 bgrid((unsigned)(g.cand[1] * g.cand[2]), (unsigned)((n_filters + 31) / 32),
-                       (unsigned)((g.cand[0] + kC97Seg - 1) / kC97Seg));
+                       (unsigned)((g.cand[0] + p.seg - 1) / p.seg));
       if (precision == 1) k_c97_bulk<__bf16><<<bgrid, kThreads, p.lds, st>>>(a);
       else k_c97_bulk<_Float16><<<bgrid, kThreads, p.lds, st>>>(a);
       k_c97_short<<<(unsigned)n_filters, kThreads, 0, st>>>(bulk, cext, g, p.R, sl);

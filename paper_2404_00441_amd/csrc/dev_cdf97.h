@@ -27,7 +27,7 @@ constexpr float kC97Delta = 0.443506852043971f;
 constexpr float kC97Zeta = 1.149604398860241f;
 constexpr int kC97BlocksMax = 256;    // template blocks of a 9/7 event
 constexpr int kC97ShortMax = 128;     // candidates rescored per event
-constexpr int kC97Seg = 256;          // candidates of a row per bulk workgroup
+constexpr int kC97Seg = 256;          // candidates of a row per bulk workgroup, at most
 
 // Index i of a line of n samples under whole-sample symmetric extension
 // (period 2(n - 1); parity is kept).
@@ -200,8 +200,8 @@ __device__ __forceinline__ uint32_t c97_asc(float f) {
 
 // Stage the K values a candidate row segment reaches: strip entry i =
 // (x, r) of W x (T_c,y T_c,z) holds K[x0 + x, cy + by, cz + bz] with r = by
-// + T_c,y bz (0 past the grid's x end), passed to store(i, value).  Every
-// load of a thread goes out before its stores.
+// + T_c,y bz (0 past the grid's x end), passed to store(i, x, value).
+// Every load of a thread goes out before its stores.
 template <class Store>
 __device__ __forceinline__ void c97_stage(const float* __restrict__ K, const Geom& g, int x0, int cy, int cz, int W,
                                           Store store) {
@@ -210,6 +210,7 @@ __device__ __forceinline__ void c97_stage(const float* __restrict__ K, const Geo
   BoxWalk w(threadIdx.x, kThreads, W, g.tc[1]);
   for (int i0 = threadIdx.x; i0 < n; i0 += U * kThreads) {
     float v[U];
+    int xs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       // positions past the strip read a clamped cell and are not stored
@@ -217,58 +218,81 @@ __device__ __forceinline__ void c97_stage(const float* __restrict__ K, const Geo
       const int y = min(cy + w.y, g.G[1] - 1), z = min(cz + w.z, g.G[2] - 1);
       v[u] = K[idx3i(min(x, g.G[0] - 1), y, z, g.G)];
       v[u] = x < g.G[0] ? v[u] : 0.f;
+      xs[u] = w.x;
       w.next();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (i0 + u * kThreads < n) store(i0 + u * kThreads, v[u]);
+      if (i0 + u * kThreads < n) store(i0 + u * kThreads, xs[u], v[u]);
   }
 }
 
 // The score map.  Workgroup: one segment of sw candidates of a candidate
 // row (grid x = row * segments + segment) against up to kC97MapEvents
-// events (grid y); the K values the segment reaches (T_c,y x T_c,z grid rows
-// of sw + T_c,x - 1 cells) are staged once in LDS and serve every event.
-// Optionally the smallest score of each chunk.
+// events (grid y).  The K values the segment reaches (T_c,y x T_c,z grid
+// rows of Wc = sw + T_c,x cells, rounded up to even) are staged once in LDS
+// in two copies, K[x] and K[x + 1], so that a thread reads the values of
+// its two adjacent candidates for a block with one aligned 8-byte load
+// (copy 0 for an even block offset, copy 1 for an odd one).  The two halves
+// of the workgroup take alternate events; the event lists are read with
+// scalar loads.  Optionally the smallest score of each chunk.
 constexpr int kC97MapEvents = 8;
-constexpr int kC97MapLds = 32 * 1024;
-// Segment width: a multiple of 32 (<= 256) whose strip fits kC97MapLds.
+constexpr int kC97MapLds = 64 * 1024;
+__host__ __device__ inline int c97_map_wc(int sw, const Geom& g) { return (sw + g.tc[0] + 1) & ~1; }
+inline size_t c97_map_lds(int sw, const Geom& g) { return (size_t)8 * g.tc[1] * g.tc[2] * c97_map_wc(sw, g); }
+// Segment width: the widest multiple of 32 (<= 256) whose strips fit
+// kC97MapLds; 0 when not even 32 does (very tall, narrow templates).
 inline int c97_map_width(const Geom& g) {
-  const int nrows = g.tc[1] * g.tc[2];
-  int sw = (kC97MapLds / (4 * nrows) - (g.tc[0] - 1)) / 32 * 32;
-  return sw < 32 ? 32 : sw > 256 ? 256 : sw;
+  for (int sw = 256; sw >= 32; sw -= 32)
+    if (c97_map_lds(sw, g) <= kC97MapLds) return sw;
+  return 0;
 }
 __global__ __launch_bounds__(kThreads) void k_c97_map(const float* __restrict__ K, Geom g, int sw,
                                                       const int32_t* __restrict__ cnt, const int32_t* __restrict__ soff,
                                                       const float* __restrict__ val, int n_filters,
                                                       float* __restrict__ out, float* __restrict__ cmin) {
-  __shared__ float s_k[kC97MapLds / 4];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int nseg = (g.cand[0] + sw - 1) / sw;
   const int row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg, tid = threadIdx.x;
   const int cy = row % g.cand[1], cz = row / g.cand[1];
-  const int W = sw + g.tc[0] - 1, nrows = g.tc[1] * g.tc[2];
+  const int Wc = c97_map_wc(sw, g), nrows = g.tc[1] * g.tc[2];
+  float* k0 = (float*)smem;          // K[x0 + i]
+  float* k1 = k0 + nrows * Wc;       // K[x0 + i + 1]
   const int x0 = seg * sw;
-  c97_stage(K, g, x0, cy, cz, W, [&](int i, float v) { s_k[i] = v; });
+  c97_stage(K, g, x0, cy, cz, Wc, [&](int i, int xi, float v) {
+    k0[i] = v;
+    if (xi > 0) k1[i - 1] = v;
+  });
   __syncthreads();
-  const int x = x0 + tid;
-  const bool ok = tid < sw && x < g.cand[0];
-  const int c = row * g.cand[0] + x;
+  const int half = tid >> 7, tl = tid & 127;
+  const int xa = x0 + 2 * tl;                     // this thread's candidates xa, xa + 1
+  const bool ok0 = 2 * tl < sw && xa < g.cand[0], ok1 = 2 * tl + 1 < sw && xa + 1 < g.cand[0];
+  const int ca = row * g.cand[0] + xa;
   const int nchr = (g.cand[0] + 31) / 32;
   const long long nchk = (long long)g.cand[1] * g.cand[2] * nchr;
   const int f1 = min(n_filters, (int)(blockIdx.y + 1) * kC97MapEvents);
-  for (int f = blockIdx.y * kC97MapEvents; f < f1; ++f) {
-    // the event's list is the same for every lane: scalar loads
-    const int nk = cnt[f];
-    float S = INFINITY;
-    if (ok) {
-      S = c97_score(s_k, tid, soff + (long long)f * kC97BlocksMax, val + (long long)f * kC97BlocksMax, nk);
-      out[(long long)f * g.ncand + c] = S;
+  for (int f = (int)blockIdx.y * kC97MapEvents + half; f < f1; f += 2) {
+    const int fu = __builtin_amdgcn_readfirstlane(f);   // one event per wavefront
+    const int nk = cnt[fu];
+    const int32_t* so = soff + (long long)fu * kC97BlocksMax;
+    const float* av = val + (long long)fu * kC97BlocksMax;
+    // per candidate the same operations in the same order as c97_score
+    float s0 = 0.f, s1 = 0.f;
+    for (int i = 0; i < (2 * tl < sw ? nk : 0); ++i) {   // threads past the segment read nothing
+      const int o = so[i];
+      const float a = av[i];
+      const float2 kv = *(const float2*)(((o & 1) ? k1 + (o - 1) : k0 + o) + 2 * tl);
+      const float d0 = kv.x - a, d1 = kv.y - a;
+      s0 = fmaf(d0, d0, s0);
+      s1 = fmaf(d1, d1, s1);
     }
+    if (ok0) out[(long long)fu * g.ncand + ca] = s0;
+    if (ok1) out[(long long)fu * g.ncand + ca + 1] = s1;
     if (cmin) {
-      float m = S;
+      float m = fminf(ok0 ? s0 : INFINITY, ok1 ? s1 : INFINITY);
 #pragma unroll
-      for (int o = 1; o < 32; o <<= 1) m = fminf(m, __shfl_xor(m, o));
-      if ((tid & 31) == 0 && ok) cmin[f * nchk + (long long)row * nchr + x / 32] = m;
+      for (int o = 1; o < 16; o <<= 1) m = fminf(m, __shfl_xor(m, o));
+      if ((tl & 15) == 0 && ok0) cmin[fu * nchk + (long long)row * nchr + (xa >> 5)] = m;
     }
   }
 }
@@ -538,7 +562,8 @@ struct C97BulkArgs {
   const float* kmax;         // kC97MaxParts partial maxima of |K| (device)
   int n_filters;
   int kpad;                  // 2 T_c cells, padded to 16
-  int W;                     // strip width: kC97Seg + T_c,x - 1
+  int seg;                   // candidates of a row per workgroup (a multiple of 32, <= kC97Seg)
+  int W;                     // strip width: seg + T_c,x - 1
   float* bulk;               // [event][candidates]: sum n A K - n K^2 / 2
   float* cmax;               // [event][chunks]: largest bulk value of each chunk
 };
@@ -555,7 +580,7 @@ inline size_t c97_bulk_lds(int nrows, int W, int kpad) {
 // candidates have the largest B.  One contraction over 2 T_c cells per
 // candidate: the first half pairs n A with K, the second -n 2^q / 2 with
 // K^2 2^-q, operands in OT (fp16 / bf16), fp32 accumulation.  Workgroup:
-// kC97Seg candidates of one row (grid z) against 32 events (grid y); each
+// seg candidates of one row (grid z) against 32 events (grid y); each
 // wavefront takes 32-candidate chunks.  The MFMA takes the events as A and the K strip as B, so lane l
 // holds candidate l % 32 of 16 events and the stores are contiguous runs.
 template <typename OT>
@@ -566,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row = blockIdx.x;
   const int cy = row % g.cand[1], cz = row / g.cand[1];
-  const int f0 = blockIdx.y * 32, x0 = blockIdx.z * kC97Seg;
+  const int f0 = blockIdx.y * 32, x0 = blockIdx.z * a.seg;
   const int W = a.W, kpad = a.kpad;
   const int nrows = g.tc[1] * g.tc[2];
   const int tcells = (int)g.tcells;
@@ -578,7 +603,7 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
   int* s_off = (int*)(smem + c97_strip_bytes(nrows, W));
   OT* s_b = (OT*)(smem + c97_strip_bytes(nrows, W) + (size_t)kpad * 4);
   const int bstride = kpad + 8;
-  c97_stage(a.K, g, x0, cy, cz, W, [&](int i, float v) {
+  c97_stage(a.K, g, x0, cy, cz, W, [&](int i, int, float v) {
     s_k[i] = c97_op<OT>(v);
     s_k[nrows * W + i] = c97_op<OT>(v * v * down);
   });
@@ -666,7 +691,7 @@ __global__ __launch_bounds__(kThreads) void k_c97_bulk(C97BulkArgs a) {
     }
   }
   __syncthreads();
-  const int nchunks = min(kC97Seg, g.cand[0] - x0 + 31) / 32;
+  const int nchunks = min(a.seg, g.cand[0] - x0 + 31) / 32;
   const int j = lane & 31, g8 = (lane >> 5) * 8;
   const OT* erow = s_b + j * bstride + g8;
   const long long rowbase = (long long)g.cand[0] * row + x0;

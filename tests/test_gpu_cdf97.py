@@ -157,7 +157,8 @@ SCAN_CASES = [((100, 120), (90, 90), 2, (24, 24), 37),
               ((64, 80), (64, 64), 1, (16, 16), 33),
               ((120, 128), (100, 100), 2, (48, 48), 40),
               ((20, 36, 40), (20, 30, 30), 2, (8, 12, 12), 9),
-              ((30, 41), (30, 30), 0, (6, 8), 35)]
+              ((30, 41), (30, 30), 0, (6, 8), 35),
+              ((80, 70), (80, 80), 0, (64, 1), 12)]
 SCAN_IDS = [f"{'x'.join(map(str, c[0]))}_J{c[2]}_T{c[3][-1]}" for c in SCAN_CASES]
 
 
