@@ -56,6 +56,10 @@ def parse():
                     help="HBM bytes per launch measured with rocprofv3 counters (optional)")
     ap.add_argument("--cdf97-only", action="store_true",
                     help="print only the CDF 9/7 measurements (transform, exact and split selection)")
+    ap.add_argument("--lp-lists", type=int, default=None, help="inverted lists of the learned proposer's index")
+    ap.add_argument("--lp-eval-seeds", type=int, default=None, help="evaluation seeds 1..N of the learned sweep")
+    ap.add_argument("--lp-points", default=None,
+                    help="(lists probed[:gate]) points of the learned sweep, comma-separated, e.g. 8,12,8:0.2")
     ap.add_argument("--lp-epochs", type=int, default=None,
                     help="training epochs of the learned proposer (default: the built-in schedule)")
     ap.add_argument("--learned-only", action="store_true",
@@ -294,11 +298,11 @@ LP_HELDOUT_SEED = 2001
 LP_EPOCHS, LP_BATCH, LP_LR = 6, 512, 2e-3
 LP_LISTS = 512
 # (lists probed, gate): None lets every proposal stand
-LP_POINTS = ((8, None), (10, None), (12, None), (16, None), (8, 0.2), (8, 0.15), (8, 0.12))
-LP_EVAL_SEEDS = (1, 2, 3)                    # each form simulated with each seed; errors pooled
+LP_POINTS = ((4, None), (8, None), (12, None), (16, None), (8, 0.2), (8, 0.15))
+LP_EVAL_SEEDS = (1, 2, 3, 4, 5, 6, 7, 8)     # each form simulated with each seed; errors pooled
 
 
-def measure_learned(cc, wl, dev, reps=3, epochs=None):
+def measure_learned(cc, wl, dev, reps=3, epochs=None, lists=None, points=None, eval_seeds=None):
     """C5 with the learned convolutional proposer against the plain form on
     the same GPU.  Training pairs: the data events of plain simulations of
     the C5 workload with other seeds and their exact-best candidates; a
@@ -330,7 +334,9 @@ def measure_learned(cc, wl, dev, reps=3, epochs=None):
     t_train = time.perf_counter() - t0
     ev = learn.evaluate(p, w, approx, von, vom, vlab, vbest, vsb, vnk)
     t0 = time.perf_counter()
-    index = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], LP_LISTS, iters=10)
+    lists = lists or LP_LISTS
+    eval_seeds = eval_seeds or LP_EVAL_SEEDS
+    index = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], lists, iters=10)
     torch.cuda.synchronize()
     t_index = time.perf_counter() - t0
 
@@ -338,7 +344,7 @@ def measure_learned(cc, wl, dev, reps=3, epochs=None):
         # every evaluation seed: time per call and the drawn candidates'
         # match errors, pooled over the seeds
         ts, errs, fbs, acc, scored, n = [], [], 0, 0, 0, 0
-        for sd in LP_EVAL_SEEDS:
+        for sd in eval_seeds:
             sim = cc.Simulator(dict(q, seed=sd), device=dev)
             ts.append(_time_runs(lambda: sim.run(ti_d), reps))
             e = sim.match_errors()
@@ -358,22 +364,69 @@ def measure_learned(cc, wl, dev, reps=3, epochs=None):
         "pairs": int(on.shape[0]), "pair_seeds": list(LP_TRAIN_SEEDS), "pairs_s": t_pairs,
         "labels_per_pair": int(lab.shape[1]),
         "epochs": epochs, "batch": LP_BATCH, "lr": LP_LR, "train_s": t_train,
-        "loss_per_epoch": hist, "index_lists": LP_LISTS, "index_s": t_index},
+        "loss_per_epoch": hist, "index_lists": lists, "index_s": t_index},
         "heldout": dict(ev, seed=LP_HELDOUT_SEED),
-        "eval_seeds": list(LP_EVAL_SEEDS),
+        "eval_seeds": list(eval_seeds),
         "plain": {"ms": t_plain * 1e3, "cells_per_s": cells / t_plain, "match_error_mean": e_plain,
                   "match_error_p95": e95_plain},
         "by_gate": []}
-    for probe, gate in LP_POINTS:
+    for probe, gate in (points or LP_POINTS):
         q = dict(p, proposer_dim=64, proposer=index, lp_probe=probe, lp_gate=1e30 if gate is None else gate)
         t, em, e95, fbr, spp = run(q)
         res["by_gate"].append({
             "gate": gate, "probe": probe, "ms": t * 1e3, "cells_per_s": cells / t, "speedup": t_plain / t,
             "match_error_mean": em, "match_error_p95": e95, "match_error_vs_plain": em / e_plain,
             "fallback_rate": fbr, "members_scored_per_patch": spp})
-    ok = [r for r in res["by_gate"] if r["match_error_vs_plain"] <= 1.01]
+    # equal match error: within 1 % of plain's mean, either way
+    ok = [r for r in res["by_gate"] if abs(r["match_error_vs_plain"] - 1.0) <= 0.01]
     res["equal_error"] = max(ok, key=lambda r: r["speedup"]) if ok else None
+    # realization statistics beside the TI's (the first evaluation seed):
+    # the match error depends on the realizations themselves, so the forms'
+    # realizations are compared directly
+    forms = [("plain", p)] + [(f"probe {r['probe']}" + ("" if r["gate"] is None else f" gate {r['gate']}"),
+                               dict(p, proposer_dim=64, proposer=index, lp_probe=r["probe"],
+                                    lp_gate=1e30 if r["gate"] is None else r["gate"]))
+                              for r in res["by_gate"] if r["gate"] is None]
+    res["realization_stats"] = _realization_stats(cc, p, ti_d, forms, eval_seeds[0])
     return res
+
+
+def _realization_stats(cc, p, ti_d, forms, seed, lags=(1, 5, 10, 20, 50, 100)):
+    """Per form: facies proportions, indicator variograms of facies 1 along x
+    and y and its probability of connection along x at a few lags, for the
+    realizations of one call, with the TI's; and the mean absolute
+    difference of the two variograms from the TI's over those lags."""
+    import numpy as np
+    import torch
+    nf, max_lag = p["n_facies"], max(lags)
+    g, t_ext = p["grid"], p["ti"]
+    lag_i = [h - 1 for h in lags]
+
+    def stats(imgs, ext):
+        n = imgs.shape[0]
+        cells = n * int(np.prod(ext))
+        pi, _ = cc.stats_histogram(imgs, nf, per_cell=False)
+        vx, vy = cc.stats_variogram(imgs, nf, 0, max_lag), cc.stats_variogram(imgs, nf, 1, max_lag)
+        bx, cx = cc.stats_connectivity(imgs, nf, 0, max_lag)
+        gam = {}
+        for name, v, a in (("x", vx, 0), ("y", vy, 1)):
+            pairs = np.array([cc.pair_count(ext, a, h) for h in lags], dtype=np.float64)
+            gam[name] = v.cpu().numpy().sum(axis=0)[1, lag_i] / (2.0 * pairs * n)
+        b, c = bx.cpu().numpy().sum(axis=0)[1, lag_i], cx.cpu().numpy().sum(axis=0)[1, lag_i]
+        return {"proportions": (pi.cpu().numpy().sum(axis=0) / cells).round(4).tolist(),
+                "variogram_x": gam["x"].round(4).tolist(), "variogram_y": gam["y"].round(4).tolist(),
+                "connection_x": np.where(b > 0, c / np.maximum(b, 1), np.nan).round(4).tolist()}
+
+    out = {"lags": list(lags), "facies": 1, "seed": seed, "ti": stats(ti_d.view(1, *ti_d.shape), t_ext)}
+    tv = np.array(out["ti"]["variogram_x"] + out["ti"]["variogram_y"])
+    for name, q in forms:
+        sim = cc.Simulator(dict(q, seed=seed), device=ti_d.device)
+        real = sim.run(ti_d).view(torch.int8)
+        st = stats(real, g)
+        st["variogram_mad_vs_ti"] = float(np.abs(np.array(st["variogram_x"] + st["variogram_y"]) - tv).mean())
+        out[name] = st
+        del sim, real
+    return out
 
 
 def _time_case(cc, p, ti, hd, dev, reps=3):
@@ -645,7 +698,11 @@ def main():
     from paper_2404_00441_amd import workloads as wl
 
     if a.learned_only:
-        print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"), epochs=a.lp_epochs)}), flush=True)
+        pts = tuple((int(v.split(":")[0]), float(v.split(":")[1]) if ":" in v else None)
+                    for v in a.lp_points.split(",")) if a.lp_points else None
+        seeds = tuple(range(1, a.lp_eval_seeds + 1)) if a.lp_eval_seeds else None
+        print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"), epochs=a.lp_epochs,
+                                                     lists=a.lp_lists, points=pts, eval_seeds=seeds)}), flush=True)
         return
     if a.cdf97_only:
         print(json.dumps({"cdf97": measure_cdf97(cc, wl, torch.device("cuda:0"))}), flush=True)
