@@ -252,7 +252,9 @@ int ccwsim_ccf_scan(ccwsim_shape ti, int32_t level, int32_t wavelet, int32_t max
  * The fp32 S of a candidate is the same value in the map and in its key.
  * workspace: ccwsim_ccf_scan97_workspace_size(...) bytes (want_scores /
  * want_keys say which outputs will be non-NULL), 256-byte aligned,
- * caller-owned; -1 on invalid arguments.  T_c cells <= 256. */
+ * caller-owned; -1 on invalid arguments.  T_c cells <= 256; a template of
+ * more than about 240 block rows of one block (too tall for the map's LDS
+ * strip) is refused with CCWSIM_ERR_UNSUPPORTED. */
 int64_t ccwsim_dwt97_workspace_size(ccwsim_shape s, int32_t level);
 int ccwsim_dwt97(const int8_t* x, ccwsim_shape s, int32_t level, float* approx, float* details, void* workspace,
                  int64_t workspace_bytes, void* stream);

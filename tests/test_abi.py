@@ -240,3 +240,6 @@ def test_cdf97_sizes_and_validation(lib):
     assert ws(sh, 2, 0, t, 8, 10, 0, 0, 0) == -1        # no output
     big = ccwsim._i3((68, 68), 1)                       # 17 x 17 blocks > 256
     assert ws(sh, 2, 0, big, 8, 10, 0, 1, 0) == -1
+    tall = ccwsim.shape_of((4, 1000))                   # 250 block rows of one block at J = 0
+    assert ws(tall, 0, 0, ccwsim._i3((1, 250), 1), 8, 10, 0, 1, 0) == -1
+    assert ws(tall, 0, 0, ccwsim._i3((1, 200), 1), 8, 10, 0, 1, 0) > 0
