@@ -168,3 +168,18 @@ def test_band_layout_separable_image():
     assert np.abs(approx - SQ2 * s[None, :]).max() < 1e-11
     assert np.abs(det[0][0] - SQ2 * d[None, :]).max() < 1e-11
     assert np.abs(det[0][1:]).max() < 1e-11
+
+
+def test_band_layout_separable_volume():
+    # a volume varying along z only: the x and y passes multiply by sqrt 2
+    # (low) or give zero (high), so only band 4 (z high, x and y low) of the
+    # details is non-zero, equal to 2 times the line's detail, and the
+    # approximation is 2 times the line's low band
+    f = np.random.default_rng(4).normal(size=16)
+    vol = np.broadcast_to(f[:, None, None], (16, 6, 8)).copy()   # [z][y][x]
+    approx, det = c97.dwt97(vol, 1)
+    s, d = c97.lift97_forward(f)
+    assert np.abs(approx - 2.0 * s[:, None, None]).max() < 1e-11
+    for q in range(1, 8):
+        want = 2.0 * d[:, None, None] if q == 4 else 0.0
+        assert np.abs(det[0][q - 1] - want).max() < 1e-11, q
