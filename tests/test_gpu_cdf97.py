@@ -371,7 +371,16 @@ def test_scan97_at_the_c5_scan_shape(cc):
     _say("scan97 at the C5 scan shape")
     p, ti, _ = wl.make("c5_learned", n_real=1)
     level, T = p["level"], tuple(p["tmpl"])
-    K = c97.dwt97(ti, level)[0].astype(np.float32)
+    a_ref, d_ref = c97.dwt97(ti, level)
+    K = a_ref.astype(np.float32)
+    # the transform of the full training image and its inverse
+    ti_d = _dev(ti, np.int8)
+    a_gpu, d_gpu = cc.dwt97(ti_d, level)
+    assert np.abs(a_gpu.cpu().numpy() - a_ref).max() <= 1e-5 * np.abs(a_ref).max()
+    flat = np.concatenate([dj.ravel() for dj in d_ref])
+    assert np.abs(d_gpu.cpu().numpy() - flat).max() <= 1e-5 * np.abs(a_ref).max()
+    img = cc.idwt97(a_gpu, d_gpu, tuple(p["ti"]), level).cpu().numpy()
+    assert np.array_equal(np.rint(img).astype(np.int64), ti.astype(np.int64))
     ref = syn.channel_image_2d(500, 500, 20, 3, seed=4242)
     Kr = c97.dwt97(ref, level)[0]
     tc = (12, 12)
