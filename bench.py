@@ -298,7 +298,7 @@ LP_HELDOUT_SEED = 2001
 LP_EPOCHS, LP_BATCH, LP_LR = 6, 512, 2e-3
 LP_LISTS = 512
 # (lists probed, gate): None lets every proposal stand
-LP_POINTS = ((4, None), (8, None), (12, None), (16, None), (8, 0.2), (8, 0.15))
+LP_POINTS = ((4, None), (5, None), (6, None), (8, None), (12, None), (16, None), (8, 0.2), (8, 0.15))
 LP_EVAL_SEEDS = (1, 2, 3, 4, 5, 6, 7, 8)     # each form simulated with each seed; errors pooled
 
 
