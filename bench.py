@@ -58,6 +58,7 @@ def parse():
                     help="print only the CDF 9/7 measurements (transform, exact and split selection)")
     ap.add_argument("--lp-lists", type=int, default=None, help="inverted lists of the learned proposer's index")
     ap.add_argument("--lp-eval-seeds", type=int, default=None, help="evaluation seeds 1..N of the learned sweep")
+    ap.add_argument("--lp-kmeans-iters", type=int, default=None, help="k-means rounds of the learned index")
     ap.add_argument("--lp-points", default=None,
                     help="(lists probed[:gate]) points of the learned sweep, comma-separated, e.g. 8,12,8:0.2")
     ap.add_argument("--lp-epochs", type=int, default=None,
@@ -297,12 +298,13 @@ LP_TRAIN_SEEDS = (1001, 1002, 1003, 1004)   # plain simulations whose data event
 LP_HELDOUT_SEED = 2001
 LP_EPOCHS, LP_BATCH, LP_LR = 6, 512, 2e-3
 LP_LISTS = 512
+LP_KMEANS_ITERS = 10
 # (lists probed, gate): None lets every proposal stand
 LP_POINTS = ((4, None), (5, None), (6, None), (8, None), (12, None), (16, None), (8, 0.2), (8, 0.15))
 LP_EVAL_SEEDS = (1, 2, 3, 4, 5, 6, 7, 8)     # each form simulated with each seed; errors pooled
 
 
-def measure_learned(cc, wl, dev, reps=3, epochs=None, lists=None, points=None, eval_seeds=None):
+def measure_learned(cc, wl, dev, reps=3, epochs=None, lists=None, points=None, eval_seeds=None, kmeans_iters=None):
     """C5 with the learned convolutional proposer against the plain form on
     the same GPU.  Training pairs: the data events of plain simulations of
     the C5 workload with other seeds and their exact-best candidates; a
@@ -336,7 +338,8 @@ def measure_learned(cc, wl, dev, reps=3, epochs=None, lists=None, points=None, e
     t0 = time.perf_counter()
     lists = lists or LP_LISTS
     eval_seeds = eval_seeds or LP_EVAL_SEEDS
-    index = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], lists, iters=10)
+    kmeans_iters = kmeans_iters or LP_KMEANS_ITERS
+    index = cc.lp_build_index(w, approx, p["ti"], p["level"], p["tmpl"], lists, iters=kmeans_iters)
     torch.cuda.synchronize()
     t_index = time.perf_counter() - t0
 
@@ -364,7 +367,7 @@ def measure_learned(cc, wl, dev, reps=3, epochs=None, lists=None, points=None, e
         "pairs": int(on.shape[0]), "pair_seeds": list(LP_TRAIN_SEEDS), "pairs_s": t_pairs,
         "labels_per_pair": int(lab.shape[1]),
         "epochs": epochs, "batch": LP_BATCH, "lr": LP_LR, "train_s": t_train,
-        "loss_per_epoch": hist, "index_lists": lists, "index_s": t_index},
+        "loss_per_epoch": hist, "index_lists": lists, "kmeans_iters": kmeans_iters, "index_s": t_index},
         "heldout": dict(ev, seed=LP_HELDOUT_SEED),
         "eval_seeds": list(eval_seeds),
         "plain": {"ms": t_plain * 1e3, "cells_per_s": cells / t_plain, "match_error_mean": e_plain,
@@ -702,7 +705,8 @@ def main():
                     for v in a.lp_points.split(",")) if a.lp_points else None
         seeds = tuple(range(1, a.lp_eval_seeds + 1)) if a.lp_eval_seeds else None
         print(json.dumps({"learned": measure_learned(cc, wl, torch.device("cuda:0"), epochs=a.lp_epochs,
-                                                     lists=a.lp_lists, points=pts, eval_seeds=seeds)}), flush=True)
+                                                     lists=a.lp_lists, points=pts, eval_seeds=seeds,
+                                                     kmeans_iters=a.lp_kmeans_iters)}), flush=True)
         return
     if a.cdf97_only:
         print(json.dumps({"cdf97": measure_cdf97(cc, wl, torch.device("cuda:0"))}), flush=True)
