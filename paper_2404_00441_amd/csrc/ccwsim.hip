@@ -1166,7 +1166,7 @@ int lp_index_layout(const LpPlan& L, int n_lists, LpIndexHeader& h) {
   h.off_w = o;
   o += align256(lp_query_floats() * 4);
   h.off_cent = o;
-  o += align256((long long)n_lists * kLpD * 4);
+  o += 2 * lp_cent_bytes(n_lists);   // [n_lists][64], then [16][n_lists][4]
   h.off_list = o;
   o += align256((long long)(n_lists + 1) * 4);
   h.off_mem = o;
@@ -1252,6 +1252,8 @@ extern "C" int ccwsim_lp_build_index(const float* weights, const int32_t* approx
     k_km_lists<<<(unsigned)n_lists, kThreads, 0, st>>>(assign, g.ncand, off, mem);
     k_km_update<<<(unsigned)n_lists, kThreads, 0, st>>>(keys, off, mem, cent);
   }
+  k_km_transpose<<<nblocks((long long)n_lists * (kLpD / 4)), kThreads, 0, st>>>(
+      cent, n_lists, (float*)(ix + h.off_cent + lp_cent_bytes(n_lists)));
   HIP_TRY(hipGetLastError());
   return CCWSIM_OK;
 }

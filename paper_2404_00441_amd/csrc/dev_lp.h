@@ -454,12 +454,25 @@ struct LpIndexHeader {
   int32_t G[3], cand[3], tc[3], pad0;
   int64_t ncand;
   int64_t off_w;      // bytes from the index base: the query encoder's weights (float)
-  int64_t off_cent;   // centroids [n_lists][64] (float)
+  int64_t off_cent;   // centroids [n_lists][64] (float), then the same values as
+                      // [16][n_lists][4] at off_cent + lp_cent_bytes(n_lists), so
+                      // that a thread per list reads its 16-byte words coalesced
   int64_t off_list;   // list offsets [n_lists + 1] (int32)
   int64_t off_mem;    // members [ncand] (int32), by list, ascending within a list
   int64_t bytes;
 };
 __host__ __device__ inline long long lp_query_floats() { return lp_weights_total() - lp_offset(1, 0); }
+__host__ __device__ inline long long lp_cent_bytes(int n_lists) {
+  return ((long long)n_lists * kLpD * 4 + 255) & ~255ll;
+}
+
+// The centroids' second copy: word d4 (4 floats) of list j at d4 * n_lists + j.
+__global__ void k_km_transpose(const float* __restrict__ cent, int nl, float* __restrict__ ct) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nl * (kLpD / 4)) return;
+  const int j = id % nl, d4 = id / nl;
+  ((float4*)ct)[id] = ((const float4*)cent)[(long long)j * (kLpD / 4) + d4];
+}
 
 // Starting centroids: keys at evenly spaced candidate indices.
 __global__ void k_km_init(const float* __restrict__ keys, long long ncand, int nl, float* __restrict__ cent) {
@@ -991,14 +1004,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   lp_query_sparse((const float*)(a.index + H->off_w), s_ev, g.tc[0], g.tc[1], s_a0, s_a1, s_a2, s_q);
   if (a.q_out && tid < kLpD) a.q_out[(long long)slot * kLpD + tid] = s_q[tid];
   // the lists by the inner product of the query with their centroid
-  const float* cent = (const float*)(a.index + H->off_cent);
   const int nl = hdr_ok ? H->n_lists : 1;
+  const float4* ct = (const float4*)(a.index + H->off_cent + lp_cent_bytes(nl));
   for (int j = tid; j < nl; j += kThreads) {
-    const float4* c4 = (const float4*)(cent + (long long)j * kLpD);
     float s = 0.f;
 #pragma unroll
     for (int d = 0; d < kLpD / 4; ++d) {
-      const float4 c = c4[d];
+      const float4 c = ct[(long long)d * nl + j];   // coalesced across the lists
       s += s_q[4 * d] * c.x + s_q[4 * d + 1] * c.y + s_q[4 * d + 2] * c.z + s_q[4 * d + 3] * c.w;
     }
     s_cs[j] = s == s ? s : -INFINITY;   // a total order for the ranks below
